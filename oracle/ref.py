@@ -1,0 +1,301 @@
+"""ctypes wrapper of the FP64 CPU oracle (oracle/pmdg_ref.c).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
+baseline leg use this module; the product package never imports it.  It takes
+plain dictionaries and NumPy arrays (the seeded workload description) and
+shares no code with the HIP library.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+_dp = ctypes.POINTER(ctypes.c_double)
+_lp = ctypes.POINTER(ctypes.c_long)
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.LIB
+        src = os.path.join(_build.HERE, "pmdg_ref.c")
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(src):
+            _build.build()
+        L = ctypes.CDLL(path)
+        vp = ctypes.c_void_p
+        L.pmdg_ref_create.restype = vp
+        L.pmdg_ref_create.argtypes = [ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double]
+        L.pmdg_ref_destroy.argtypes = [vp]
+        L.pmdg_ref_num_nodes.restype = ctypes.c_long
+        L.pmdg_ref_num_nodes.argtypes = [vp]
+        L.pmdg_ref_dom_nodes.restype = ctypes.c_long
+        L.pmdg_ref_dom_nodes.argtypes = [vp, ctypes.c_int]
+        L.pmdg_ref_gamma.restype = ctypes.c_double
+        L.pmdg_ref_gamma.argtypes = [vp]
+        L.pmdg_ref_set_literal.argtypes = [vp, ctypes.c_int]
+        L.pmdg_ref_set_sample_gain.argtypes = [vp, ctypes.c_double]
+        L.pmdg_ref_set_dt.argtypes = [vp, ctypes.c_double]
+        L.pmdg_ref_cfl_dt.restype = ctypes.c_double
+        L.pmdg_ref_cfl_dt.argtypes = [vp, ctypes.c_double]
+        L.pmdg_ref_coords.argtypes = [vp, _dp]
+        L.pmdg_ref_mass.argtypes = [vp, _dp]
+        L.pmdg_ref_apply_K.argtypes = [vp, _dp, _dp, ctypes.c_int]
+        L.pmdg_ref_lambda_max.restype = ctypes.c_double
+        L.pmdg_ref_lambda_max.argtypes = [vp, ctypes.c_int, ctypes.c_uint]
+        L.pmdg_ref_set_pmuts.restype = ctypes.c_int
+        L.pmdg_ref_set_pmuts.argtypes = [vp, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp, _dp, _dp]
+        L.pmdg_ref_pmut_nodes.restype = ctypes.c_int
+        L.pmdg_ref_pmut_nodes.argtypes = [vp, ctypes.c_int, _dp]
+        L.pmdg_ref_set_shape.restype = ctypes.c_int
+        L.pmdg_ref_set_shape.argtypes = [vp, ctypes.c_int, _dp]
+        L.pmdg_ref_coupling.restype = ctypes.c_int
+        L.pmdg_ref_coupling.argtypes = [vp, ctypes.c_int, ctypes.c_int, _lp, _dp]
+        L.pmdg_ref_set_drive.argtypes = [vp, _dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int]
+        L.pmdg_ref_set_rx.argtypes = [vp, ctypes.c_double, ctypes.c_double]
+        L.pmdg_ref_window.restype = ctypes.c_double
+        L.pmdg_ref_window.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.pmdg_ref_drive.restype = ctypes.c_double
+        L.pmdg_ref_drive.argtypes = [ctypes.c_double] * 4 + [ctypes.c_int, ctypes.c_double]
+        L.pmdg_ref_set_receivers.restype = ctypes.c_int
+        L.pmdg_ref_set_receivers.argtypes = [vp, ctypes.c_int, _dp]
+        L.pmdg_ref_sample_receivers.argtypes = [vp, _dp, _dp]
+        L.pmdg_ref_set_state.argtypes = [vp, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_long]
+        L.pmdg_ref_get_state.argtypes = [vp, _dp, _dp, _dp, _dp, _dp, _dp, _lp]
+        L.pmdg_ref_step.argtypes = [vp, ctypes.c_int, _dp]
+        L.pmdg_ref_gll.restype = ctypes.c_int
+        L.pmdg_ref_gll.argtypes = [ctypes.c_int, _dp, _dp]
+        L.pmdg_ref_gl.restype = ctypes.c_int
+        L.pmdg_ref_gl.argtypes = [ctypes.c_int, _dp, _dp]
+        L.pmdg_ref_dmat.restype = ctypes.c_int
+        L.pmdg_ref_dmat.argtypes = [ctypes.c_int, _dp]
+        L.pmdg_ref_lagrange.argtypes = [ctypes.c_int, _dp, ctypes.c_double, _dp, _dp]
+        L.pmdg_ref_element_apply.argtypes = [ctypes.c_int, _dp, ctypes.c_double, _dp, _dp]
+        L.pmdg_ref_num_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+# ---------------------------------------------------------------- helpers
+
+def gll(N):
+    x = np.zeros(N + 1); w = np.zeros(N + 1)
+    if lib().pmdg_ref_gll(N, _d(x), _d(w)):
+        raise ValueError("order out of range")
+    return x, w
+
+
+def gl(n):
+    x = np.zeros(n); w = np.zeros(n)
+    if lib().pmdg_ref_gl(n, _d(x), _d(w)):
+        raise ValueError("point count out of range")
+    return x, w
+
+
+def dmat(N):
+    D = np.zeros((N + 1, N + 1))
+    lib().pmdg_ref_dmat(N, _d(D))
+    return D
+
+
+def lagrange(nodes, t):
+    nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+    n = len(nodes) - 1
+    v = np.zeros(n + 1); d = np.zeros(n + 1)
+    lib().pmdg_ref_lagrange(n, _d(nodes), float(t), _d(v), _d(d))
+    return v, d
+
+
+def element_apply(N, h, c, u):
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1)
+    r = np.zeros_like(u)
+    lib().pmdg_ref_element_apply(N, _d(h), float(c), _d(u), _d(r))
+    return r
+
+
+def window(t, Td):
+    return lib().pmdg_ref_window(float(t), float(Td))
+
+
+def drive(A, theta, f, ncyc, envelope, t):
+    return lib().pmdg_ref_drive(float(A), float(theta), float(f), float(ncyc), int(envelope), float(t))
+
+
+def num_threads():
+    return lib().pmdg_ref_num_threads()
+
+
+def dom_params(dom):
+    """12 doubles {x0[3], h[3], ne[3], N, c, rho} from a brick description."""
+    x0 = np.asarray(dom["x0"], dtype=np.float64)
+    x1 = np.asarray(dom["x1"], dtype=np.float64)
+    ne = np.asarray(dom["ne"], dtype=np.float64)
+    h = (x1 - x0) / ne
+    return np.concatenate([x0, h, ne, [dom["N"], dom["c"], dom["rho"]]])
+
+
+class RefSolver:
+    """One scenario of the coupled problem on the CPU, FP64."""
+
+    def __init__(self, domains, alpha=2.0, cfl=0.3, dt=None):
+        prm = np.ascontiguousarray(np.concatenate([dom_params(d) for d in domains]))
+        self.L = lib()
+        self.h = self.L.pmdg_ref_create(len(domains), _d(prm), 1.0, float(alpha))
+        if not self.h:
+            raise ValueError("oracle: invalid mesh description")
+        self.ndom = len(domains)
+        self.n = self.L.pmdg_ref_num_nodes(self.h)
+        self.dt = float(dt) if dt is not None else self.L.pmdg_ref_cfl_dt(self.h, float(cfl))
+        self.L.pmdg_ref_set_dt(self.h, self.dt)
+        self.Np = 0
+        self.Nm = 0
+        self.R = 0
+
+    def __del__(self):
+        try:
+            if self.h:
+                self.L.pmdg_ref_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    # ---- mesh / operators
+    def dom_nodes(self, d):
+        return self.L.pmdg_ref_dom_nodes(self.h, d)
+
+    def coords(self):
+        x = np.zeros((self.n, 3))
+        self.L.pmdg_ref_coords(self.h, _d(x))
+        return x
+
+    def mass(self):
+        m = np.zeros(self.n)
+        self.L.pmdg_ref_mass(self.h, _d(m))
+        return m
+
+    def apply_K(self, p, which=3):
+        p = np.ascontiguousarray(p, dtype=np.float64)
+        out = np.zeros(self.n)
+        self.L.pmdg_ref_apply_K(self.h, _d(p), _d(out), which)
+        return out
+
+    def dense_K(self, which=3):
+        K = np.zeros((self.n, self.n))
+        e = np.zeros(self.n)
+        for j in range(self.n):
+            e[:] = 0.0
+            e[j] = 1.0
+            K[:, j] = self.apply_K(e, which)
+        return K
+
+    def gamma(self):
+        return self.L.pmdg_ref_gamma(self.h)
+
+    def lambda_max(self, iters=200, seed=1):
+        return self.L.pmdg_ref_lambda_max(self.h, iters, seed)
+
+    def set_literal(self, on):
+        self.L.pmdg_ref_set_literal(self.h, 1 if on else 0)
+
+    def set_sample_gain(self, g):
+        self.L.pmdg_ref_set_sample_gain(self.h, float(g))
+
+    # ---- PMUTs
+    def set_pmuts(self, centers, radius, omega, zeta, eta):
+        centers = np.ascontiguousarray(centers, dtype=np.float64).reshape(-1, 2)
+        radius = np.ascontiguousarray(radius, dtype=np.float64).reshape(-1)
+        omega = np.ascontiguousarray(omega, dtype=np.float64)
+        self.Np, self.Nm = omega.shape
+        zeta = np.ascontiguousarray(zeta, dtype=np.float64).reshape(self.Np, self.Nm)
+        eta = np.ascontiguousarray(eta, dtype=np.float64).reshape(self.Np, self.Nm)
+        self.L.pmdg_ref_set_pmuts(self.h, self.Np, _d(centers), _d(radius), self.Nm,
+                                  _d(omega), _d(zeta), _d(eta))
+
+    def pmut_nodes(self, k):
+        n = self.L.pmdg_ref_pmut_nodes(self.h, k, _dp())
+        xyz = np.zeros((max(n, 1), 3))
+        self.L.pmdg_ref_pmut_nodes(self.h, k, _d(xyz))
+        return xyz[:n]
+
+    def set_shape(self, k, shape):
+        shape = np.ascontiguousarray(shape, dtype=np.float64)
+        self.L.pmdg_ref_set_shape(self.h, k, _d(shape))
+
+    def coupling(self, k, m):
+        n = self.L.pmdg_ref_pmut_nodes(self.h, k, _dp())
+        node = np.zeros(max(n, 1), dtype=np.int64); val = np.zeros(max(n, 1))
+        self.L.pmdg_ref_coupling(self.h, k, m, node.ctypes.data_as(_lp), _d(val))
+        return node[:n], val[:n]
+
+    def set_drive(self, amp, phase, freq, ncyc, envelope=0):
+        amp = np.ascontiguousarray(amp, dtype=np.float64).reshape(-1)
+        phase = np.ascontiguousarray(phase, dtype=np.float64).reshape(-1)
+        self.L.pmdg_ref_set_drive(self.h, _d(amp), _d(phase), float(freq), float(ncyc), int(envelope))
+
+    def set_rx(self, t_switch, cap):
+        self.L.pmdg_ref_set_rx(self.h, float(t_switch), float(cap))
+
+    # ---- receivers
+    def set_receivers(self, xyz):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+        self.R = xyz.shape[0]
+        if self.L.pmdg_ref_set_receivers(self.h, self.R, _d(xyz)):
+            raise ValueError("oracle: receiver outside the mesh")
+
+    def sample(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float64)
+        out = np.zeros(self.R)
+        self.L.pmdg_ref_sample_receivers(self.h, _d(p), _d(out))
+        return out
+
+    # ---- state and stepping
+    def set_state(self, p=None, pd=None, pdd=None, q=None, qd=None, qdd=None, nstep=0):
+        def arr(a):
+            return _dp() if a is None else _d(np.ascontiguousarray(a, dtype=np.float64))
+        keep = [np.ascontiguousarray(a, dtype=np.float64) if a is not None else None
+                for a in (p, pd, pdd, q, qd, qdd)]
+        ptrs = [_dp() if a is None else _d(a) for a in keep]
+        self.L.pmdg_ref_set_state(self.h, *ptrs, int(nstep))
+        del arr
+
+    def get_state(self):
+        nm = max(self.Np * self.Nm, 1)
+        p, pd, pdd = np.zeros(self.n), np.zeros(self.n), np.zeros(self.n)
+        q, qd, qdd = np.zeros(nm), np.zeros(nm), np.zeros(nm)
+        ns = ctypes.c_long(0)
+        self.L.pmdg_ref_get_state(self.h, _d(p), _d(pd), _d(pdd), _d(q), _d(qd), _d(qdd), ctypes.byref(ns))
+        k = self.Np * self.Nm
+        return dict(p=p, pd=pd, pdd=pdd, q=q[:k], qd=qd[:k], qdd=qdd[:k], nstep=ns.value)
+
+    def step(self, nsteps):
+        tr = np.zeros((max(self.R, 1), nsteps))
+        self.L.pmdg_ref_step(self.h, int(nsteps), _d(tr))
+        return tr[: self.R]
+
+
+def from_workload(wl, scenario=0, shape_fn=None):
+    """Builds an oracle solver for one scenario of a workload description.
+
+    shape_fn(k, xyz) -> [Nm x n] mode-shape samples at the given face nodes
+    (the workload's own mode-shape generator)."""
+    s = RefSolver(wl["domains"], alpha=wl.get("alpha", 2.0), cfl=wl.get("cfl", 0.3))
+    pm = wl.get("pmuts")
+    if pm is not None and len(pm["radius"]):
+        s.set_pmuts(pm["centers"], pm["radius"], pm["omega"], pm["zeta"], pm["eta"])
+        for k in range(s.Np):
+            xyz = s.pmut_nodes(k)
+            s.set_shape(k, shape_fn(k, xyz))
+        dr = wl["drive"]
+        s.set_drive(np.asarray(dr["amp"])[scenario], np.asarray(dr["phase"])[scenario],
+                    np.asarray(dr["freq"]).reshape(-1)[scenario], dr["ncyc"], dr.get("envelope", 0))
+        if "rx" in wl:
+            s.set_rx(wl["rx"]["t_switch"], wl["rx"]["cap"])
+    s.set_receivers(wl["receivers"])
+    return s

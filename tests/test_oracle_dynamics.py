@@ -1,0 +1,306 @@
+"""Pins of the oracle's time stepping (Sec. 3.1, Algorithm 1: Newmark
+beta = 0, gamma = 1/2) and of the PMUT modal ODE coupling (Sec. 2, eq.
+pmut_problem; Sec. 3.1, eqs. f_i and g_m)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import ref
+from tests._indep import sem_1d
+
+from paper_2603_06267_amd import workloads as W
+
+
+def _cube(N, ne, L=1.0, c=1.5):
+    return W.brick([0, 0, 0], [L, L, L], [ne, ne, ne], N, c=c)
+
+
+def _eigvec_1d(N, ne, h, mode):
+    K, M = sem_1d(N, ne, h)
+    Mi = 1 / np.sqrt(M)
+    lam, V = np.linalg.eigh(Mi[:, None] * K * Mi[None, :])
+    return lam[mode], Mi * V[:, mode]
+
+
+def test_standing_wave_discrete_closed_form():
+    """Rigid cube, p^0 = separable discrete eigenvector (tensor product of
+    independently built 1D generalised eigenvectors), zero velocity,
+    consistent acceleration: Newmark/leapfrog gives p^n = p^0 cos(n theta),
+    cos theta = 1 - dt^2 omega_h^2 / 2 with omega_h^2 = c^2 (l_x + l_y + l_z)."""
+    N, ne, c = 4, 3, 1.5
+    h = 1.0 / ne
+    lx, vx = _eigvec_1d(N, ne, h, 1)
+    ly, vy = _eigvec_1d(N, ne, h, 2)
+    lz, vz = _eigvec_1d(N, ne, h, 1)
+    v = np.kron(vz, np.kron(vy, vx))
+    lam = c * c * (lx + ly + lz)
+    s = ref.RefSolver([_cube(N, ne, c=c)])
+    s.set_state(p=v, pd=np.zeros_like(v), pdd=-lam * v)
+    theta = math.acos(1 - 0.5 * s.dt ** 2 * lam)
+    for n in (1, 7, 50, 400):
+        s2 = ref.RefSolver([_cube(N, ne, c=c)])
+        s2.set_state(p=v, pd=np.zeros_like(v), pdd=-lam * v)
+        s2.step(n)
+        p = s2.get_state()["p"]
+        assert np.abs(p - v * math.cos(n * theta)).max() < 1e-12 * np.abs(v).max() * max(1, n / 50)
+
+
+@pytest.mark.parametrize("N,expected", [(2, 1.35e-4), (3, 3.9e-7), (4, 7.1e-10)])
+def test_p_convergence_of_mode_111(N, expected):
+    """Mode (1,1,1) of a rigid cube of side L on 4^3 elements: the oracle's
+    operator has the tensor eigenvector with omega_h^2 = 3 c^2 lambda_1D, and
+    its relative error against c pi sqrt(3) / L decays spectrally (the 1D
+    rates of a 4-element line)."""
+    L, ne, c = 1.0, 4, 1.5
+    l1, v1 = _eigvec_1d(N, ne, L / ne, 1)
+    v = np.kron(v1, np.kron(v1, v1))
+    s = ref.RefSolver([_cube(N, ne, L, c)], dt=1.0)
+    Kv = s.apply_K(v)
+    lam = 3 * c * c * l1
+    assert np.abs(Kv - lam * s.mass() * v).max() < 1e-10 * np.abs(Kv).max()
+    err = abs(math.sqrt(lam) - c * math.pi * math.sqrt(3) / L) / (c * math.pi * math.sqrt(3) / L)
+    assert 0.8 * expected < err < 1.25 * expected
+
+
+def test_leapfrog_energy_conserved_two_domain():
+    """Without PMUT coupling the two-level discrete energy
+    E = 1/2 d^T M d + 1/2 (p^{n+1})^T K p^n, d = (p^{n+1} - p^n)/dt,
+    is an exact invariant of the leapfrog scheme for symmetric K."""
+    wl = W.small_two_domain(True)
+    prim, sec = wl["domains"]
+    prim = dict(prim, ne=[4, 2, 1], x1=[1.0, 0.5, 0.25])
+    sec = dict(sec, ne=[2, 1, 2], x0=[0, 0, 0.25], x1=[1.0, 0.5, 1.25])
+    s = ref.RefSolver([prim, sec])
+    rng = np.random.default_rng(3)
+    p0 = rng.standard_normal(s.n)
+    s.set_state(p=p0, pd=np.zeros(s.n), pdd=-s.apply_K(p0) / s.mass())
+    M = s.mass()
+    E = []
+    prev = p0.copy()
+    for n in range(300):
+        s.step(1)
+        p = s.get_state()["p"]
+        d = (p - prev) / s.dt
+        E.append(0.5 * d @ (M * d) + 0.5 * p @ s.apply_K(prev))
+        prev = p
+    E = np.array(E)
+    assert np.abs(E - E[0]).max() < 1e-11 * abs(E[0])
+
+
+def _single_pmut(omega, zeta=0.0, eta=1.0, Nm=1, dt=None):
+    dom = W.brick([0, 0, 0], [1, 1, 1], [2, 2, 2], 2)
+    s = ref.RefSolver([dom], dt=dt)
+    s.set_pmuts([[0.5, 0.5]], [0.3], np.full((1, Nm), omega), np.full((1, Nm), zeta), np.full((1, Nm), eta))
+    xyz = s.pmut_nodes(0)
+    s.set_shape(0, np.ones((Nm, len(xyz))))
+    s.set_receivers([[0.5, 0.5, 0.5]])
+    return s
+
+
+def test_modal_ode_free_oscillation():
+    """Sampling removed (test hook), no drive: q^n = q^0 cos(n theta),
+    cos theta = 1 - omega^2 dt^2 / 2."""
+    om = 13.0
+    s = _single_pmut(om, dt=0.01)
+    s.set_sample_gain(0.0)
+    s.set_drive([0.0], [0.0], 1.0, 3.0, 0)
+    s.set_state(q=[1.0], qd=[0.0], qdd=[-om * om])
+    theta = math.acos(1 - 0.5 * (om * 0.01) ** 2)
+    for n in range(1, 200):
+        s.step(1)
+        q = s.get_state()["q"][0]
+        assert abs(q - math.cos(n * theta)) < 1e-12
+
+
+def test_modal_ode_rect_drive_discrete_green():
+    """Sampling removed, RECT sine drive from rest: q^n equals the discrete
+    convolution sum_{m=1}^{n-1} G^{n-m} eta phi(t^m),
+    G^j = dt^2 sin(j theta) / sin(theta), and the continuous solution
+    eta A/(w^2 - W^2) (sin W t - (W/w) sin w t) within O(dt^2)."""
+    om, f, A, eta = 11.0, 1.3, 0.7, 1.9
+    dt = 0.004
+    s = _single_pmut(om, eta=eta, dt=dt)
+    s.set_sample_gain(0.0)
+    s.set_drive([A], [0.0], f, 1000.0, 2)
+    nst = 1500
+    qs = []
+    for n in range(nst):
+        s.step(1)
+        qs.append(s.get_state()["q"][0])
+    qs = np.array(qs)  # qs[n-1] = q^n
+    theta = math.acos(1 - 0.5 * (om * dt) ** 2)
+    Wf = 2 * math.pi * f
+    phi = A * np.sin(Wf * dt * np.arange(nst + 1))
+    G = dt * dt * np.sin(np.arange(nst + 1) * theta) / math.sin(theta)
+    for n in (2, 10, 333, 1500):
+        conv = sum(G[n - m] * eta * phi[m] for m in range(1, n))
+        assert abs(qs[n - 1] - conv) < 1e-12 * max(1.0, abs(conv))
+    t = dt * np.arange(1, nst + 1)
+    cont = eta * A / (om ** 2 - Wf ** 2) * (np.sin(Wf * t) - (Wf / om) * np.sin(om * t))
+    err = np.abs(qs - cont).max() / np.abs(cont).max()
+    assert err < 5e-3  # O(dt^2 omega^2 t) phase error of the continuous reference
+    s2 = _single_pmut(om, eta=eta, dt=dt / 2)
+    s2.set_sample_gain(0.0)
+    s2.set_drive([A], [0.0], f, 1000.0, 2)
+    q2 = []
+    for n in range(2 * nst):
+        s2.step(1)
+        q2.append(s2.get_state()["q"][0])
+    err2 = np.abs(np.array(q2)[1::2] - cont).max() / np.abs(cont).max()
+    assert 3.0 < err / err2 < 5.0  # second order
+
+
+def test_modal_ode_damped_duhamel():
+    """zeta > 0: the damping acts on the predicted velocity (as the absorbing
+    term of Algorithm 1 acts on the predicted pressure rate), which is
+    consistent but only first order in zeta*omega*dt; the result converges to
+    the continuous Duhamel integral of the damped oscillator."""
+    om, zeta, f, A = 9.0, 0.05, 1.1, 1.0
+    T = 4.0
+    wd = om * math.sqrt(1 - zeta ** 2)
+    Wf = 2 * math.pi * f
+    tt = np.linspace(0, T, 200001)
+    force = A * np.sin(Wf * tt)
+
+    def duhamel(t):
+        m = tt <= t
+        tau = tt[m]
+        g = np.exp(-zeta * om * (t - tau)) * np.sin(wd * (t - tau)) / wd
+        return np.trapezoid(g * force[m], tau)
+
+    errs = []
+    for dt in (0.01, 0.005):
+        s = _single_pmut(om, zeta=zeta, dt=dt)
+        s.set_sample_gain(0.0)
+        s.set_drive([A], [0.0], f, 1000.0, 2)
+        n = int(round(T / dt))
+        s.step(n)
+        errs.append(abs(s.get_state()["q"][0] - duhamel(n * dt)))
+    assert errs[1] < 1e-4 and 1.8 < errs[0] / errs[1] < 4.5
+
+
+def test_rx_switch_softens_mode():
+    """After the TX->RX switch the voltage is (1/C) sum eta q, so a single
+    mode obeys qdd = -(omega^2 - eta^2/C) q (Sec. 2, eq. ode)."""
+    om, eta, C = 10.0, 3.0, 0.5
+    dt = 0.002
+    s = _single_pmut(om, eta=eta, dt=dt)
+    s.set_sample_gain(0.0)
+    s.set_drive([0.0], [0.0], 1.0, 3.0, 0)
+    s.set_rx(-1.0, C)
+    s.set_state(q=[1.0], qd=[0.0], qdd=[-(om ** 2 - eta ** 2 / C)])
+    qs = []
+    for n in range(3000):
+        s.step(1)
+        qs.append(s.get_state()["q"][0])
+    w2 = om ** 2 - eta ** 2 / C
+    theta = math.acos(1 - 0.5 * w2 * dt * dt)
+    assert np.abs(np.array(qs) - np.cos(theta * np.arange(1, 3001))).max() < 1e-10
+
+
+def _two_pmut_solver():
+    prim = W.brick([0, 0, 0], [2, 1, 0.5], [8, 4, 2], 3)
+    s = ref.RefSolver([prim])
+    om = np.array([[8.0, 15.0], [8.0, 15.0]])
+    s.set_pmuts([[0.6, 0.5], [1.45, 0.4]], [0.35, 0.35], om, np.full((2, 2), 0.02), np.full((2, 2), 1.0))
+    for k in range(2):
+        xyz = s.pmut_nodes(k)
+        r = np.hypot(xyz[:, 0] - [0.6, 1.45][k], xyz[:, 1] - [0.5, 0.4][k])
+        s.set_shape(k, np.stack([6 * (1 - (r / 0.35) ** 2), 6 * (1 - (r / 0.35) ** 2) * (1 - 2 * (r / 0.35) ** 2)]))
+    s.set_receivers([[1.0, 0.5, 0.3], [0.2, 0.8, 0.45]])
+    return s
+
+
+def test_reciprocity():
+    """Two PMUTs with identical modal data: the charge sum_m eta q of PMUT k
+    driven through PMUT j equals that of j driven through k.  Eliminating p
+    leaves [diag + kappa B^T G B] qdd = E phi with G symmetric (Sec. 3.1, eqs.
+    semi_SEM / semi_PMUT), so the transfer is symmetric; with several modes
+    only the eta-weighted sum is reciprocal, not each mode on its own."""
+    out = {}
+    for drv in (0, 1):
+        s = _two_pmut_solver()
+        amp = [1.0 if k == drv else 0.0 for k in range(2)]
+        s.set_drive(amp, [0.0, 0.0], 2.0, 3.0, 0)
+        qs = []
+        for n in range(600):
+            s.step(1)
+            qs.append(s.get_state()["q"].copy())
+        out[drv] = np.array(qs)
+    a = out[0][:, 2:4].sum(axis=1)  # charge of PMUT 1 driven by 0 (eta = 1)
+    b = out[1][:, 0:2].sum(axis=1)  # charge of PMUT 0 driven by 1
+    assert np.abs(a).max() > 1e-6
+    assert np.abs(a - b).max() < 1e-11 * np.abs(a).max()
+
+
+def test_linearity_superposition():
+    """trace(A, theta) = A sum_k [cos theta_k Y_k^s - sin theta_k Y_k^c], with
+    Y^s / Y^c the single-PMUT responses to the sin / cos carrier."""
+    theta = np.array([0.7, 2.9])
+    A = 1.7
+
+    def run(amp, ph):
+        s = _two_pmut_solver()
+        s.set_drive(amp, ph, 2.0, 3.0, 0)
+        return s.step(400)
+    full = run([A, A], theta)
+    comb = 0
+    for k in range(2):
+        e = [1.0 if j == k else 0.0 for j in range(2)]
+        Ys = run(e, [0.0, 0.0])
+        Yc = run(e, [-math.pi / 2, -math.pi / 2])
+        comb = comb + A * (math.cos(theta[k]) * Ys - math.sin(theta[k]) * Yc)
+    assert np.abs(full - comb).max() < 1e-12 * np.abs(full).max()
+
+
+def test_coupling_order_literal_unstable_synced_bounded():
+    """The printed ordering samples p^n (one step stale): with coupling it
+    amplifies every step; the synchronised ordering stays bounded."""
+    res = {}
+    for lit in (False, True):
+        s = _two_pmut_solver()
+        s.set_literal(lit)
+        rng = np.random.default_rng(0)
+        p0 = rng.standard_normal(s.n) * 1e-3
+        s.set_state(p=p0, pd=np.zeros(s.n), pdd=-s.apply_K(p0) / s.mass())
+        s.set_drive([0.0, 0.0], [0.0, 0.0], 2.0, 3.0, 0)
+        s.step(3000)
+        res[lit] = np.abs(s.get_state()["p"]).max()
+    assert res[False] < 1e-2
+    assert res[True] > 10 * res[False]
+
+
+def test_receivers_interpolate_polynomials_exactly():
+    wl = W.small_two_domain(False)
+    s = ref.RefSolver(wl["domains"], dt=1.0)
+    s.set_receivers(wl["receivers"])
+    X = s.coords()
+    f = lambda x: 0.3 + x[:, 0] ** 3 - 2 * x[:, 1] * x[:, 2] + 0.5 * x[:, 2] ** 2 * x[:, 0]
+    assert np.abs(s.sample(f(X)) - f(np.asarray(wl["receivers"]))).max() < 1e-12
+
+
+def test_face_weights_sum_to_face_area():
+    """U = 1 over a disc covering the whole bottom face: sum_i B_i = area."""
+    dom = W.brick([0, 0, 0], [1.5, 1, 1], [3, 2, 2], 4)
+    s = ref.RefSolver([dom], dt=1.0)
+    s.set_pmuts([[0.75, 0.5]], [10.0], [[5.0]], [[0.0]], [[1.0]])
+    n = len(s.pmut_nodes(0))
+    assert n == 13 * 9
+    s.set_shape(0, np.ones((1, n)))
+    _, v = s.coupling(0, 0)
+    assert abs(v.sum() - 1.5) < 1e-14
+
+
+def test_window_values():
+    """g(t) of Sec. 6.1 (eq. voltage) with n = 10: zero at both ends, one at
+    T_d/2, symmetric; g(0.05 T_d) = exp(1 - (1 - 2 b^21/(1+b^20))^-2) with
+    b = 0.9, i.e. 0.58066, and 0.96320 at b = 0.8 (t = 0.1 T_d)."""
+    Td = 1.7
+    assert ref.window(0.0, Td) == 0.0 and ref.window(Td, Td) == 0.0
+    assert abs(ref.window(Td / 2, Td) - 1.0) < 1e-15
+    for t in np.linspace(0, Td, 37):
+        assert abs(ref.window(t, Td) - ref.window(Td - t, Td)) < 1e-14
+    assert abs(ref.window(0.05 * Td, Td) - 0.5806560846) < 1e-9
+    assert abs(ref.window(0.1 * Td, Td) - 0.9631987356) < 1e-9
+    assert ref.window(-0.1, Td) == 0.0 and ref.window(Td * 1.01, Td) == 0.0
