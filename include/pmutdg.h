@@ -1,0 +1,188 @@
+/*
+ * pmutdg.h -- C ABI of the MI355X (gfx950) time stepper for PMUT arrays
+ * coupled to a DG spectral-element acoustic model (arXiv 2603.06267).
+ *
+ * One step advances, on the GPU:
+ *   - the matrix-free stiffness action of the continuous GLL spectral
+ *     elements inside each of (up to) two axis-aligned bricks (Sec. 3,
+ *     bilinear form a, eq. Wf_2, volume sum),
+ *   - the symmetric interior-penalty terms across the non-conforming,
+ *     mixed-order interface Gamma_I between the bricks (eq. Wf_2, interface
+ *     sums; penalty gamma_F; interface quadrature on the finer face, Sec. 5),
+ *   - the lumped-mass explicit Newmark (beta = 0, gamma = 1/2) update
+ *     (Sec. 3.1, eq. semi_SEM, Algorithm 1),
+ *   - each PMUT's reduced modal ODE, driven by the applied voltage and by the
+ *     pressure it samples on its face, and the face force it returns
+ *     (Sec. 2, eq. pmut_problem; Sec. 3.1, eqs. f_i, g_m, semi_PMUT),
+ *   - pressure traces at receiver points.
+ *
+ * Conventions
+ *   - Every call returns a pmdg_status (0 = OK, negative = error).  No
+ *     exception crosses the ABI.  pmdg_last_error() returns a thread-local,
+ *     library-owned string describing the last error on the calling thread.
+ *   - Host arrays are plain C arrays owned by the caller; the library copies
+ *     what it keeps.  Device memory is owned by the caller: the library asks
+ *     for one workspace size and sub-allocates inside the buffer passed to
+ *     pmdg_bind; it never allocates device memory itself.
+ *   - Streams are hipStream_t passed as void*; NULL means the default stream.
+ *   - Units are the caller's, but must be consistent (the Python layer uses
+ *     mm, us, MHz).
+ *   - Layout of the primary brick: PMUT discs sit on its bottom face
+ *     z = x0[2]; the secondary brick (if any) sits on top of it and shares the
+ *     primary's top face as Gamma_I (the primary is the "+" / fine side).
+ *   - All boundaries other than PMUT discs are rigid (homogeneous Neumann).
+ */
+#ifndef PMUTDG_H
+#define PMUTDG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int pmdg_status;
+#define PMDG_OK 0
+#define PMDG_EINVAL (-1)    /* bad argument (size, pointer, geometry) */
+#define PMDG_ENOMEM (-2)    /* host allocation failed / workspace too small */
+#define PMDG_EHIP (-3)      /* a HIP runtime call failed */
+#define PMDG_EUNSTABLE (-4) /* time step or PMUT coupling outside the stable range */
+#define PMDG_ESTATE (-5)    /* call not allowed in the solver's current state */
+
+typedef struct pmdg_solver pmdg_solver;
+
+/* One axis-aligned brick of ne[0] x ne[1] x ne[2] equal hexahedra carrying a
+ * continuous Q_order space on GLL nodes (Sec. 3, spaces V_a^{r_a}). */
+typedef struct {
+  double x0[3], x1[3]; /* opposite corners, x1 > x0 componentwise */
+  int ne[3];           /* elements per axis, >= 1 */
+  int order;           /* polynomial order N, 1..8 */
+  double c;            /* sound speed (> 0) */
+  double rho;          /* density; kappa = rho c^2 of the primary (Sec. 2) */
+} pmdg_brick;
+
+typedef struct {
+  int ndom;            /* 1 or 2 */
+  pmdg_brick dom[2];   /* dom[0] primary (fine); dom[1] secondary (coarse) */
+  double cfl;          /* dt = cfl * min_dom(h_min * min GLL gap / 2 / c) if dt <= 0 */
+  double dt;           /* explicit time step if > 0 */
+  double penalty_alpha;/* SIPG constant alpha in gamma_F (Sec. 3); > 0 */
+  int precision;       /* 32: FP32 field state/operators, FP64 ODE+traces; 64: all FP64 */
+  int n_scenarios;     /* S >= 1 drive scenarios sharing mesh and PMUT modal data */
+  int trace_capacity;  /* receiver samples kept per receiver and scenario (>= 1) */
+} pmdg_problem;
+
+/* Creates a solver: builds GLL / Gauss-Legendre rules, the assembled 1D
+ * operators, the interface quadrature-point list (fine-face Gauss points
+ * mapped into the coarse elements, Sec. 5) and dt.  Rejects geometry where
+ * the secondary's bottom face is not the primary's top face (EINVAL) and a
+ * dt beyond the explicit stability bound of the volume operator
+ * (EUNSTABLE).  *out receives the handle (NULL on error). */
+pmdg_status pmdg_create(const pmdg_problem* pr, pmdg_solver** out);
+
+/* PMUTs on the primary's bottom face (Sec. 2, eq. pmut_problem): Np discs
+ * with centres ctr[2*Np] (x, y) and radii radius[Np]; per disc Nm modes with
+ * angular frequency omega, damping ratio zeta (acting on the predicted modal
+ * velocity) and coupling eta, each [Np*Nm] row-major.  Must precede
+ * pmdg_bind.  Face nodes inside a disc belong to that PMUT (discs must not
+ * overlap: EINVAL). */
+pmdg_status pmdg_set_pmuts(pmdg_solver* h, int Np, const double* ctr, const double* radius, int Nm,
+                           const double* omega, const double* zeta, const double* eta);
+
+/* Number of face nodes of PMUT k and, if xyz != NULL, their coordinates
+ * (xyz[3*n]); the order is the order expected by pmdg_set_pmut_shape. */
+pmdg_status pmdg_pmut_face_nodes(pmdg_solver* h, int k, int* n, double* xyz);
+
+/* Mode-shape samples U_{k,m}.n at PMUT k's face nodes, shape[Nm * n]
+ * (mode-major).  With the face quadrature weights this defines the coupling
+ * matrix B of eqs. f_i and g_m.  Must precede pmdg_bind. */
+pmdg_status pmdg_set_pmut_shape(pmdg_solver* h, int k, const double* shape);
+
+/* Drive phi_{k,0}(t) = amp sin(2 pi freq t - phase) * envelope(t), with
+ * T_d = ncyc / freq.  amp, phase: [S*Np]; freq: [S].  envelope 0 = smooth
+ * window g of Sec. 6.1 (eq. voltage), 1 = rectangular on [0, T_d],
+ * 2 = rectangular, never switched off.  May be called before or after bind
+ * (after bind it uploads synchronously). */
+pmdg_status pmdg_set_drive(pmdg_solver* h, const double* amp, const double* phase, const double* freq,
+                           double ncyc, int envelope);
+
+/* TX -> RX switch (Sec. 2, eq. ode): for t > t_switch the voltage is
+ * (1/cap) sum_m eta q.  Default t_switch = +infinity (TX only). */
+pmdg_status pmdg_set_rx(pmdg_solver* h, double t_switch, double cap);
+
+/* Receiver points xyz[3*R]; each is located in the lowest-index element
+ * containing it (primary first) and sampled by tensor Lagrange
+ * interpolation, accumulated in FP64.  A point outside both bricks gives
+ * EINVAL.  Must precede pmdg_bind. */
+pmdg_status pmdg_set_receivers(pmdg_solver* h, int R, const double* xyz);
+
+/* Device bytes needed by pmdg_bind (depends on everything set so far). */
+pmdg_status pmdg_workspace_size(pmdg_solver* h, size_t* bytes);
+
+/* Binds caller-owned device memory (>= pmdg_workspace_size bytes, 256-byte
+ * aligned) and uploads all tables; the state starts at rest.  The caller
+ * keeps the memory alive until pmdg_destroy.  Binding twice: ESTATE. */
+pmdg_status pmdg_bind(pmdg_solver* h, void* dev_ptr, size_t bytes, void* stream);
+
+/* The time step in use. */
+pmdg_status pmdg_get_dt(pmdg_solver* h, double* dt);
+
+/* Enqueues n time steps on stream and returns without waiting.  Steps run
+ * as captured hipGraphs (replayed in chunks) unless graphs are disabled with
+ * pmdg_set_option.  Exceeding trace_capacity gives ESTATE before anything is
+ * enqueued.  One solver must not be stepped on two streams at once. */
+pmdg_status pmdg_step(pmdg_solver* h, int n, void* stream);
+
+/* Steps completed so far. */
+pmdg_status pmdg_steps_done(pmdg_solver* h, long* nsteps);
+
+/* Waits for stream, then copies the FP64 traces [S][R][steps_done] into the
+ * host array out (column j holds the pressure at time (j+1) dt). */
+pmdg_status pmdg_read_traces(pmdg_solver* h, double* out, void* stream);
+
+/* Modal state of scenario s after the last step: q, qdot, qddot [Np*Nm]
+ * (host arrays; NULL entries skipped). */
+pmdg_status pmdg_read_modal(pmdg_solver* h, int s, double* q, double* qd, double* qdd, void* stream);
+
+/* Field state of scenario s: pressure at the current and the previous time
+ * level, [n_nodes] each, nodes of the primary then of the secondary, x
+ * fastest.  set_state also sets the modal state (NULL: zero) and the step
+ * counter, and recomputes the face force and interface terms. */
+pmdg_status pmdg_num_nodes(pmdg_solver* h, long* n);
+pmdg_status pmdg_get_state(pmdg_solver* h, int s, double* p, double* p_prev, void* stream);
+pmdg_status pmdg_set_state(pmdg_solver* h, int s, const double* p, const double* p_prev, const double* q,
+                           const double* qd, const double* qdd, long nstep, void* stream);
+
+/* Node coordinates [n_nodes * 3] in the state's order. */
+pmdg_status pmdg_node_coords(pmdg_solver* h, double* xyz);
+
+/* Non-finite watchdog: *nonfinite != 0 once any updated pressure was NaN or
+ * infinite. */
+pmdg_status pmdg_status_flags(pmdg_solver* h, int* nonfinite, void* stream);
+
+/* Options: PMDG_OPT_GRAPH (1 = replay hipGraphs, 0 = direct launches),
+ * PMDG_OPT_TILE_ROWS (rows per wave of the stiffness tile: 1, 2, 4 or 8),
+ * PMDG_OPT_TILE_ZCHUNK (planes per block along z, 0 = whole brick),
+ * PMDG_OPT_GRAPH_CHUNK (steps per captured graph). */
+#define PMDG_OPT_GRAPH 1
+#define PMDG_OPT_TILE_ROWS 2
+#define PMDG_OPT_TILE_ZCHUNK 3
+#define PMDG_OPT_GRAPH_CHUNK 4
+pmdg_status pmdg_set_option(pmdg_solver* h, int option, long value);
+
+/* Average duration (ms) of each kernel class over the last timed
+ * pmdg_step call made with PMDG_OPT_TIMING set: [0] stiffness, [1] face,
+ * [2] flux.  Timing uses HIP events on the stepping stream. */
+#define PMDG_OPT_TIMING 5
+pmdg_status pmdg_kernel_times(pmdg_solver* h, double* ms3);
+
+/* Frees host resources (device memory is the caller's).  NULL is a no-op. */
+void pmdg_destroy(pmdg_solver* h);
+
+const char* pmdg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PMUTDG_H */

@@ -1,0 +1,1199 @@
+// libpmutdg: host side of the C ABI (include/pmutdg.h).
+//
+// Builds the operator tables of the explicit step on the host once (long
+// double), uploads them into a caller-owned device workspace and enqueues
+// the per-step kernels of pmutdg_kernels.hip, optionally as hipGraphs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "pmutdg_internal.h"
+#include "pmutdg.h"
+
+using namespace pmdg;
+typedef long double ld;
+
+static thread_local std::string g_err;
+
+static pmdg_status fail(pmdg_status s, const std::string& m) {
+  g_err = m;
+  return s;
+}
+
+#define HIPCHK(call)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) return fail(PMDG_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// ------------------------------------------------------------------------
+// 1D spectral-element rules (Sec. 3: Lagrange basis on GLL nodes, reduced
+// integration of the mass form; Sec. 5: Gauss-Legendre points on the finer
+// interface face).
+// ------------------------------------------------------------------------
+static void leg(int n, ld t, ld& P, ld& Pm1, ld& dP) {
+  // P_n, P_{n-1} and P_n' by the Bonnet recurrence
+  ld a = 1, b = t;
+  if (n == 0) { P = 1; Pm1 = 0; dP = 0; return; }
+  for (int k = 2; k <= n; ++k) {
+    ld c = ((2 * k - 1) * t * b - (k - 1) * a) / k;
+    a = b;
+    b = c;
+  }
+  P = b;
+  Pm1 = a;
+  dP = (std::fabs(t) < 1) ? n * (a - t * b) / (1 - t * t) : (t > 0 ? 1 : (n % 2 ? 1 : -1)) * 0.5L * n * (n + 1);
+}
+
+struct Rule1D {
+  int N = 0;
+  std::vector<ld> x, w, lam;  // nodes, weights, barycentric weights
+  std::vector<ld> D;          // D[i*(N+1)+j] = l_j'(x_i)
+};
+
+// GLL: interior nodes are the zeros of P_{N-1}(t) - t P_N(t), which is
+// proportional to (1 - t^2) P_N'(t).
+static Rule1D gll_rule(int N) {
+  Rule1D r;
+  r.N = N;
+  r.x.assign(N + 1, 0);
+  r.w.assign(N + 1, 0);
+  r.x[0] = -1;
+  r.x[N] = 1;
+  for (int j = 1; j < N; ++j) {
+    ld t = -std::cos(M_PI * (ld)j / N);
+    for (int it = 0; it < 200; ++it) {
+      ld P, Pm1, dP, Q, Qm1, dQ;
+      leg(N, t, P, Pm1, dP);
+      leg(N - 1, t, Q, Qm1, dQ);
+      const ld f = Q - t * P, df = dQ - P - t * dP;
+      const ld step = f / df;
+      t -= step;
+      if (std::fabs(step) < 1e-19L) break;
+    }
+    r.x[j] = t;
+  }
+  std::sort(r.x.begin(), r.x.end());
+  std::vector<ld> PN(N + 1);
+  for (int j = 0; j <= N; ++j) {
+    ld P, Pm1, dP;
+    leg(N, r.x[j], P, Pm1, dP);
+    PN[j] = P;
+    r.w[j] = 2.0L / (N * (N + 1.0L) * P * P);
+  }
+  r.lam.assign(N + 1, 1);
+  for (int j = 0; j <= N; ++j)
+    for (int m = 0; m <= N; ++m)
+      if (m != j) r.lam[j] /= (r.x[j] - r.x[m]);
+  r.D.assign((N + 1) * (N + 1), 0);
+  for (int i = 0; i <= N; ++i)
+    for (int j = 0; j <= N; ++j)
+      if (i != j) r.D[i * (N + 1) + j] = PN[i] / (PN[j] * (r.x[i] - r.x[j]));
+  r.D[0] = -0.25L * N * (N + 1);
+  r.D[N * (N + 1) + N] = 0.25L * N * (N + 1);
+  return r;
+}
+
+static void gl_rule(int n, std::vector<ld>& x, std::vector<ld>& w) {
+  x.assign(n, 0);
+  w.assign(n, 0);
+  for (int j = 0; j < n; ++j) {
+    ld t = -std::cos(M_PI * (4.0L * j + 3.0L) / (4.0L * n + 2.0L));
+    ld P, Pm1, dP;
+    for (int it = 0; it < 200; ++it) {
+      leg(n, t, P, Pm1, dP);
+      const ld step = P / dP;
+      t -= step;
+      if (std::fabs(step) < 1e-19L) break;
+    }
+    leg(n, t, P, Pm1, dP);
+    x[j] = t;
+    w[j] = 2.0L / ((1 - t * t) * dP * dP);
+  }
+}
+
+// Lagrange basis values at t by the barycentric formula.
+static void bary_eval(const Rule1D& r, ld t, ld* v) {
+  const int n = r.N + 1;
+  for (int j = 0; j < n; ++j)
+    if (std::fabs(t - r.x[j]) < 1e-16L) {
+      for (int k = 0; k < n; ++k) v[k] = (k == j);
+      return;
+    }
+  ld den = 0;
+  for (int j = 0; j < n; ++j) den += r.lam[j] / (t - r.x[j]);
+  for (int j = 0; j < n; ++j) v[j] = r.lam[j] / (t - r.x[j]) / den;
+}
+
+// ------------------------------------------------------------------------
+// Solver object
+// ------------------------------------------------------------------------
+struct Brick {
+  double x0[3], h[3];
+  int ne[3], N, nn[3];
+  long plane, nnodes;
+  double c, rho;
+  Rule1D rule;
+  std::vector<double> tap[3];   // [nn][2N]
+  std::vector<double> minv[3];  // [nn]
+  std::vector<double> mass1[3]; // [nn] assembled 1D lumped mass
+  double lam1[3];               // largest eigenvalue of M_d^{-1} K_d
+  double coord(int axis, int i) const {
+    const int e = i / N, a = i % N;
+    return x0[axis] + h[axis] * (e + 0.5 * ((double)rule.x[a] + 1.0));
+  }
+};
+
+struct Seg {
+  size_t off = 0, bytes = 0;
+};
+
+struct pmdg_solver {
+  pmdg_problem pr;
+  int ndom = 1, S = 1, prec = 32;
+  long cap = 1;
+  double dt = 0;
+  Brick b[2];
+  // interface
+  int Nq = 0;
+  std::vector<double> Lq, wJ, xw, yw;
+  std::vector<int> xcx, ycx, xl_off, xl, yl_off, yl;
+  double gamma = 0, dz0[kMaxOrder + 1] = {0}, dz1[kMaxOrder + 1] = {0};
+  // PMUTs
+  int Np = 0, Nm = 0;
+  std::vector<double> ctr, rad, omega, zeta, eta;
+  std::vector<int> pm_off, pm_node;
+  std::vector<double> pm_wf, pm_B;
+  std::vector<char> shape_set;
+  // drive
+  std::vector<double> amp, phase, freq;
+  double ncyc = 3, t_switch = INFINITY, rx_cap = 1;
+  int envelope = 0;
+  // receivers
+  int R = 0;
+  std::vector<int> r_dom;
+  std::vector<long> r_base;
+  std::vector<double> r_w;
+  // device
+  bool bound = false;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  std::map<std::string, Seg> seg;
+  long steps_done = 0;
+  // options
+  int use_graph = 1, rows = 2, zchunk = 0, graph_chunk = 64, timing = 0;
+  std::map<int, hipGraphExec_t> graphs;
+  hipStream_t cap_stream = nullptr;
+  double ktimes[3] = {0, 0, 0};
+};
+
+static int nfine(const pmdg_solver* s) { return s->b[0].ne[0] * s->b[0].ne[1]; }
+static int ncoarse(const pmdg_solver* s) { return s->ndom > 1 ? s->b[1].ne[0] * s->b[1].ne[1] : 0; }
+static long face0(const pmdg_solver* s) { return (long)s->b[0].nn[0] * s->b[0].nn[1]; }
+static long face1(const pmdg_solver* s) { return s->ndom > 1 ? (long)s->b[1].nn[0] * s->b[1].nn[1] : 0; }
+
+static int setup_brick(Brick& B, const pmdg_brick& d, std::string& err) {
+  B.N = d.order;
+  if (B.N < 1 || B.N > kMaxOrder) { err = "order must be in 1..8"; return -1; }
+  if (!(d.c > 0) || !(d.rho > 0)) { err = "c and rho must be positive"; return -1; }
+  B.c = d.c;
+  B.rho = d.rho;
+  for (int a = 0; a < 3; ++a) {
+    if (d.ne[a] < 1 || !(d.x1[a] > d.x0[a])) { err = "bad brick extent or element count"; return -1; }
+    B.x0[a] = d.x0[a];
+    B.ne[a] = d.ne[a];
+    B.h[a] = (d.x1[a] - d.x0[a]) / d.ne[a];
+    B.nn[a] = B.N * B.ne[a] + 1;
+  }
+  B.plane = (long)B.nn[0] * B.nn[1];
+  B.nnodes = B.plane * B.nn[2];
+  if (B.nnodes > (1L << 31)) { err = "brick too large"; return -1; }
+  B.rule = gll_rule(B.N);
+  const int N = B.N, n1 = N + 1, NT = 2 * N;
+  for (int a = 0; a < 3; ++a) {
+    const int n = B.nn[a];
+    const ld h = B.h[a];
+    // local 1D stiffness (2/h) D^T W D and assembled operator M^{-1} K
+    std::vector<ld> kl(n1 * n1, 0);
+    for (int i = 0; i < n1; ++i)
+      for (int j = 0; j < n1; ++j) {
+        ld sacc = 0;
+        for (int q = 0; q < n1; ++q) sacc += B.rule.w[q] * B.rule.D[q * n1 + i] * B.rule.D[q * n1 + j];
+        kl[i * n1 + j] = 2.0L / h * sacc;
+      }
+    std::vector<ld> M(n, 0);
+    std::vector<ld> K((size_t)n * (NT + 1), 0);  // band storage K[i][t + N]
+    for (int e = 0; e < B.ne[a]; ++e)
+      for (int i = 0; i < n1; ++i) {
+        M[N * e + i] += 0.5L * h * B.rule.w[i];
+        for (int j = 0; j < n1; ++j) K[(size_t)(N * e + i) * (NT + 1) + (j - i + N)] += kl[i * n1 + j];
+      }
+    B.tap[a].assign((size_t)n * NT, 0);
+    B.minv[a].assign(n, 0);
+    B.mass1[a].assign(n, 0);
+    for (int i = 0; i < n; ++i) {
+      B.minv[a][i] = (double)(1.0L / M[i]);
+      B.mass1[a][i] = (double)M[i];
+      for (int t = -N; t <= N; ++t) {
+        if (t == 0) continue;
+        const int slot = t < 0 ? (t + N) : (N + t - 1);
+        const bool ok = i + t >= 0 && i + t < n;
+        B.tap[a][(size_t)i * NT + slot] = ok ? (double)(K[(size_t)i * (NT + 1) + (t + N)] / M[i]) : 0.0;
+      }
+    }
+    // largest eigenvalue of M^{-1} K (similar to M^{-1/2} K M^{-1/2}) by power iteration
+    std::vector<ld> v(n), wv(n);
+    for (int i = 0; i < n; ++i) v[i] = 1.0L + 0.37L * std::sin(1.3L * i) * ((i % 2) ? 1 : -1);
+    ld lam = 0;
+    for (int it = 0; it < 4000; ++it) {
+      ld nrm = 0;
+      for (int i = 0; i < n; ++i) {
+        ld acc = 0;
+        for (int t = -N; t <= N; ++t)
+          if (i + t >= 0 && i + t < n) acc += K[(size_t)i * (NT + 1) + (t + N)] / std::sqrt(M[i] * M[i + t]) * v[i + t];
+        wv[i] = acc;
+        nrm += acc * acc;
+      }
+      nrm = std::sqrt(nrm);
+      ld vv = 0, vw = 0;
+      for (int i = 0; i < n; ++i) { vv += v[i] * v[i]; vw += v[i] * wv[i]; }
+      lam = vw / vv;
+      for (int i = 0; i < n; ++i) v[i] = wv[i] / nrm;
+    }
+    B.lam1[a] = (double)lam;
+  }
+  return 0;
+}
+
+// Interface quadrature-point list (Sec. 5): Gauss-Legendre points of every
+// fine face (the primary's top element faces) pushed forward with the fine
+// map and pulled back into the lowest-index coarse element containing them.
+// On bricks both maps are affine and separable, so the list factors into an
+// x table and a y table.
+static int setup_interface(pmdg_solver* s, std::string& err) {
+  Brick &F = s->b[0], &C = s->b[1];
+  const double ztop = F.x0[2] + F.ne[2] * F.h[2];
+  const double tolz = 1e-9 * std::min(F.h[2], C.h[2]);
+  if (std::fabs(ztop - C.x0[2]) > tolz) { err = "secondary bottom face must be the primary top face"; return -1; }
+  for (int a = 0; a < 2; ++a) {
+    const double l0 = F.ne[a] * F.h[a], l1 = C.ne[a] * C.h[a];
+    if (std::fabs(F.x0[a] - C.x0[a]) > 1e-9 * l0 || std::fabs(l0 - l1) > 1e-9 * l0) {
+      err = "primary and secondary must share the same lateral extent";
+      return -1;
+    }
+  }
+  const int N0 = F.N, N1 = C.N, n0 = N0 + 1, n1 = N1 + 1;
+  if (std::max(N0, N1) > kMaxOrder - 1) { err = "orders of two coupled bricks must be <= 7"; return -1; }
+  s->Nq = std::max(N0, N1) + 1;
+  const int Nq = s->Nq;
+  std::vector<ld> gx, gw;
+  gl_rule(Nq, gx, gw);
+  s->Lq.assign(Nq * n0, 0);
+  for (int q = 0; q < Nq; ++q) {
+    ld v[kMaxOrder + 1];
+    bary_eval(F.rule, gx[q], v);
+    for (int a = 0; a < n0; ++a) s->Lq[q * n0 + a] = (double)v[a];
+  }
+  s->wJ.assign(Nq * Nq, 0);
+  for (int qb = 0; qb < Nq; ++qb)
+    for (int qa = 0; qa < Nq; ++qa) s->wJ[qb * Nq + qa] = (double)(gw[qa] * gw[qb]) * 0.25 * F.h[0] * F.h[1];
+  for (int axis = 0; axis < 2; ++axis) {
+    std::vector<int>& cx = axis == 0 ? s->xcx : s->ycx;
+    std::vector<double>& cw = axis == 0 ? s->xw : s->yw;
+    std::vector<int>& off = axis == 0 ? s->xl_off : s->yl_off;
+    std::vector<int>& lst = axis == 0 ? s->xl : s->yl;
+    const int nef = F.ne[axis], nec = C.ne[axis];
+    cx.assign(nef * Nq, 0);
+    cw.assign((size_t)nef * Nq * n1, 0);
+    std::vector<std::vector<int>> buckets(nec);
+    for (int e = 0; e < nef; ++e)
+      for (int q = 0; q < Nq; ++q) {
+        const ld xq = F.x0[axis] + F.h[axis] * (e + 0.5L * (gx[q] + 1));
+        int found = -1;
+        ld xi = 0;
+        for (int k = 0; k < nec; ++k) {
+          const ld r = 2 * (xq - (C.x0[axis] + k * (ld)C.h[axis])) / C.h[axis] - 1;
+          if (r >= -1 - 1e-12L && r <= 1 + 1e-12L) { found = k; xi = r; break; }
+        }
+        if (found < 0) { err = "interface point outside the coarse face"; return -1; }
+        cx[e * Nq + q] = found;
+        ld v[kMaxOrder + 1];
+        bary_eval(C.rule, xi, v);
+        for (int a = 0; a < n1; ++a) cw[(size_t)(e * Nq + q) * n1 + a] = (double)v[a];
+        buckets[found].push_back(e * Nq + q);
+      }
+    off.assign(nec + 1, 0);
+    lst.clear();
+    for (int k = 0; k < nec; ++k) {
+      off[k] = (int)lst.size();
+      lst.insert(lst.end(), buckets[k].begin(), buckets[k].end());
+    }
+    off[nec] = (int)lst.size();
+  }
+  const double cbar = 2.0 * F.c * C.c / (F.c + C.c);
+  const int nmax = std::max(N0, N1);
+  s->gamma = s->pr.penalty_alpha * cbar * cbar * nmax * nmax / std::min(F.h[2], C.h[2]);
+  for (int c = 0; c < n0; ++c) s->dz0[c] = (double)(2.0L / F.h[2] * F.rule.D[N0 * n0 + c]);
+  for (int c = 0; c < n1; ++c) s->dz1[c] = (double)(2.0L / C.h[2] * C.rule.D[0 * n1 + c]);
+  return 0;
+}
+
+// ------------------------------------------------------------------------
+// Workspace layout
+// ------------------------------------------------------------------------
+static size_t rbytes(const pmdg_solver* s) { return s->prec == 64 ? 8 : 4; }
+
+static size_t layout(pmdg_solver* s) {
+  s->seg.clear();
+  size_t off = 0;
+  auto add = [&](const std::string& name, size_t bytes) {
+    Seg g;
+    g.off = off;
+    g.bytes = bytes;
+    s->seg[name] = g;
+    off += (bytes + 255) / 256 * 256;
+  };
+  const size_t rb = rbytes(s);
+  const long S = s->S;
+  add("ctl", 256);
+  for (int d = 0; d < s->ndom; ++d) {
+    const Brick& B = s->b[d];
+    const std::string p = "d" + std::to_string(d) + ".";
+    add(p + "P0", rb * S * B.nnodes);
+    add(p + "P1", rb * S * B.nnodes);
+    if (s->prec == 32) add(p + "X", rb * S * B.nnodes);
+    for (int a = 0; a < 3; ++a) {
+      add(p + "tap" + std::to_string(a), rb * B.nn[a] * 2 * B.N);
+      add(p + "minv" + std::to_string(a), rb * B.nn[a]);
+    }
+  }
+  if (s->Np > 0) {
+    add("force", rb * S * face0(s));
+    add("pm_off", sizeof(int) * (s->Np + 1));
+    add("pm_node", sizeof(int) * std::max<size_t>(1, s->pm_node.size()));
+    add("pm_B", sizeof(double) * std::max<size_t>(1, s->pm_B.size()));
+    add("omega", sizeof(double) * s->Np * s->Nm);
+    add("zeta", sizeof(double) * s->Np * s->Nm);
+    add("eta", sizeof(double) * s->Np * s->Nm);
+    add("amp", sizeof(double) * S * s->Np);
+    add("phase", sizeof(double) * S * s->Np);
+    add("freq", sizeof(double) * S);
+    add("q", sizeof(double) * S * s->Np * s->Nm);
+    add("qd", sizeof(double) * S * s->Np * s->Nm);
+    add("qdd", sizeof(double) * S * s->Np * s->Nm);
+  }
+  if (s->ndom > 1) {
+    const int n0 = s->b[0].N + 1, n1 = s->b[1].N + 1;
+    add("tr0", rb * S * face0(s) * 2);
+    add("tr1", rb * S * face1(s) * 2);
+    add("R0", rb * S * nfine(s) * n0 * n0 * 2);
+    add("R1", rb * S * ncoarse(s) * n1 * n1 * 2);
+    add("Lq", rb * s->Lq.size());
+    add("wJ", rb * s->wJ.size());
+    add("xw", rb * s->xw.size());
+    add("yw", rb * s->yw.size());
+    add("xcx", sizeof(int) * s->xcx.size());
+    add("ycx", sizeof(int) * s->ycx.size());
+    add("xl_off", sizeof(int) * s->xl_off.size());
+    add("xl", sizeof(int) * s->xl.size());
+    add("yl_off", sizeof(int) * s->yl_off.size());
+    add("yl", sizeof(int) * s->yl.size());
+  }
+  if (s->R > 0) {
+    add("r_dom", sizeof(int) * s->R);
+    add("r_base", sizeof(long) * s->R);
+    add("r_w", sizeof(double) * s->r_w.size());
+    add("traces", sizeof(double) * S * s->R * s->cap);
+  }
+  return off;
+}
+
+template <typename T>
+static T* dptr(pmdg_solver* s, const std::string& name) {
+  auto it = s->seg.find(name);
+  if (it == s->seg.end() || !s->ws) return nullptr;
+  return (T*)(s->ws + it->second.off);
+}
+
+template <typename Real>
+static std::vector<Real> conv(const std::vector<double>& v) {
+  return std::vector<Real>(v.begin(), v.end());
+}
+
+static pmdg_status upload_bytes(pmdg_solver* s, const std::string& name, const void* src, size_t bytes,
+                                hipStream_t st) {
+  auto it = s->seg.find(name);
+  if (it == s->seg.end()) return fail(PMDG_EINVAL, "internal: unknown segment " + name);
+  if (bytes > it->second.bytes) return fail(PMDG_EINVAL, "internal: segment overflow " + name);
+  if (bytes == 0) return PMDG_OK;
+  HIPCHK(hipMemcpyAsync(s->ws + it->second.off, src, bytes, hipMemcpyHostToDevice, st));
+  return PMDG_OK;
+}
+
+template <typename Real>
+static pmdg_status upload_real(pmdg_solver* s, const std::string& name, const std::vector<double>& v,
+                               hipStream_t st) {
+  std::vector<Real> t = conv<Real>(v);
+  pmdg_status r = upload_bytes(s, name, t.data(), t.size() * sizeof(Real), st);
+  if (r) return r;
+  HIPCHK(hipStreamSynchronize(st));
+  return PMDG_OK;
+}
+
+template <typename T>
+static pmdg_status upload_vec(pmdg_solver* s, const std::string& name, const std::vector<T>& v, hipStream_t st) {
+  pmdg_status r = upload_bytes(s, name, v.data(), v.size() * sizeof(T), st);
+  if (r) return r;
+  HIPCHK(hipStreamSynchronize(st));
+  return PMDG_OK;
+}
+
+// ------------------------------------------------------------------------
+// Kernel argument assembly
+// ------------------------------------------------------------------------
+template <typename Real>
+static DomView<Real> view(pmdg_solver* s, int d) {
+  DomView<Real> v;
+  const Brick& B = s->b[d];
+  for (int a = 0; a < 3; ++a) v.nn[a] = B.nn[a];
+  v.N = B.N;
+  v.plane = B.plane;
+  v.nnodes = B.nnodes;
+  const std::string p = "d" + std::to_string(d) + ".";
+  v.P[0] = dptr<Real>(s, p + "P0");
+  v.P[1] = dptr<Real>(s, p + "P1");
+  v.X = s->prec == 32 ? dptr<Real>(s, p + "X") : nullptr;
+  for (int a = 0; a < 3; ++a) {
+    v.tap[a] = dptr<Real>(s, p + "tap" + std::to_string(a));
+    v.minv[a] = dptr<Real>(s, p + "minv" + std::to_string(a));
+  }
+  return v;
+}
+
+template <typename Real>
+static StiffArgs<Real> stiff_args(pmdg_solver* s, int d) {
+  StiffArgs<Real> a;
+  memset(&a, 0, sizeof(a));
+  a.d = view<Real>(s, d);
+  a.S = s->S;
+  a.dt2 = (Real)(s->dt * s->dt);
+  a.counter = dptr<long>(s, "ctl");
+  a.nonfinite = (int*)(dptr<char>(s, "ctl") + 16);
+  a.force = (d == 0 && s->Np > 0) ? dptr<Real>(s, "force") : nullptr;
+  if (s->ndom > 1) {
+    const Brick& B = s->b[d];
+    a.iface = dptr<Real>(s, d == 0 ? "R0" : "R1");
+    a.iface_side = d == 0 ? 1 : -1;
+    a.iface_nex = B.ne[0];
+    a.iface_ney = B.ne[1];
+    const double c2 = B.c * B.c;
+    for (int c = 0; c <= B.N; ++c) a.iface_d[c] = (Real)(c2 * (d == 0 ? s->dz0[c] : s->dz1[c]));
+  }
+  const int TY = kWaves * s->rows;
+  const Brick& B = s->b[d];
+  a.nbx = (B.nn[0] + kTileX - 1) / kTileX;
+  a.nby = (B.nn[1] + TY - 1) / TY;
+  a.zchunk = (s->zchunk > 0) ? std::min(s->zchunk, B.nn[2]) : B.nn[2];
+  a.nbz = (B.nn[2] + a.zchunk - 1) / a.zchunk;
+  a.nblocks = a.nbx * a.nby * a.nbz * s->S;
+  return a;
+}
+
+template <typename Real>
+static FaceArgs<Real> face_args(pmdg_solver* s, int prime) {
+  FaceArgs<Real> a;
+  memset(&a, 0, sizeof(a));
+  a.counter = dptr<long>(s, "ctl");
+  a.done = (unsigned*)(dptr<char>(s, "ctl") + 8);
+  a.prime = prime;
+  a.S = s->S;
+  a.dt = s->dt;
+  a.ndom = s->ndom;
+  a.d0 = view<Real>(s, 0);
+  if (s->ndom > 1) a.d1 = view<Real>(s, 1);
+  if (s->ndom > 1) {
+    a.tr0 = dptr<Real>(s, "tr0");
+    a.tr1 = dptr<Real>(s, "tr1");
+    for (int c = 0; c <= s->b[0].N; ++c) a.dz0[c] = (Real)s->dz0[c];
+    for (int c = 0; c <= s->b[1].N; ++c) a.dz1[c] = (Real)s->dz1[c];
+    a.nb_tr0 = (int)((s->S * face0(s) + 255) / 256);
+    a.nb_tr1 = (int)((s->S * face1(s) + 255) / 256);
+  }
+  if (s->Np > 0) {
+    a.Np = s->Np;
+    a.Nm = s->Nm;
+    a.pm_off = dptr<int>(s, "pm_off");
+    a.pm_node = dptr<int>(s, "pm_node");
+    a.pm_B = dptr<double>(s, "pm_B");
+    a.omega = dptr<double>(s, "omega");
+    a.zeta = dptr<double>(s, "zeta");
+    a.eta = dptr<double>(s, "eta");
+    a.kappa = s->b[0].rho * s->b[0].c * s->b[0].c;
+    a.amp = dptr<double>(s, "amp");
+    a.phase = dptr<double>(s, "phase");
+    a.freq = dptr<double>(s, "freq");
+    a.ncyc = s->ncyc;
+    a.envelope = s->envelope;
+    a.t_switch = s->t_switch;
+    a.cap = s->rx_cap;
+    a.q = dptr<double>(s, "q");
+    a.qd = dptr<double>(s, "qd");
+    a.qdd = dptr<double>(s, "qdd");
+    a.force = dptr<Real>(s, "force");
+    a.nb_pm = s->S * s->Np;
+  }
+  if (s->R > 0 && !prime) {
+    a.R = s->R;
+    a.r_dom = dptr<int>(s, "r_dom");
+    a.r_base = dptr<long>(s, "r_base");
+    a.r_w = dptr<double>(s, "r_w");
+    a.traces = dptr<double>(s, "traces");
+    a.tcap = s->cap;
+    a.nb_rc = (s->S * s->R + kWaves - 1) / kWaves;
+  }
+  a.nblocks = a.nb_tr0 + a.nb_tr1 + a.nb_pm + a.nb_rc;
+  if (a.nblocks == 0) a.nblocks = 1;
+  return a;
+}
+
+template <typename Real>
+static FluxArgs<Real> flux_args(pmdg_solver* s) {
+  FluxArgs<Real> a;
+  memset(&a, 0, sizeof(a));
+  if (s->ndom < 2) return a;
+  a.S = s->S;
+  a.N0 = s->b[0].N;
+  a.N1 = s->b[1].N;
+  a.Nq = s->Nq;
+  a.nn0x = s->b[0].nn[0];
+  a.nn1x = s->b[1].nn[0];
+  a.nex0 = s->b[0].ne[0];
+  a.ney0 = s->b[0].ne[1];
+  a.nex1 = s->b[1].ne[0];
+  a.ney1 = s->b[1].ne[1];
+  a.tr0 = dptr<Real>(s, "tr0");
+  a.tr1 = dptr<Real>(s, "tr1");
+  a.Lq = dptr<Real>(s, "Lq");
+  a.wJ = dptr<Real>(s, "wJ");
+  a.xcx = dptr<int>(s, "xcx");
+  a.ycx = dptr<int>(s, "ycx");
+  a.xw = dptr<Real>(s, "xw");
+  a.yw = dptr<Real>(s, "yw");
+  a.xl_off = dptr<int>(s, "xl_off");
+  a.xl = dptr<int>(s, "xl");
+  a.yl_off = dptr<int>(s, "yl_off");
+  a.yl = dptr<int>(s, "yl");
+  a.gamma = (Real)s->gamma;
+  a.cf2 = (Real)(s->b[0].c * s->b[0].c);
+  a.cc2 = (Real)(s->b[1].c * s->b[1].c);
+  a.R0 = dptr<Real>(s, "R0");
+  a.R1 = dptr<Real>(s, "R1");
+  a.nb_fine = (s->S * nfine(s) + kWaves - 1) / kWaves;
+  a.nb_coarse = (s->S * ncoarse(s) + kWaves - 1) / kWaves;
+  return a;
+}
+
+template <typename Real>
+static pmdg_status enqueue_step(pmdg_solver* s, hipStream_t st, hipEvent_t* ev) {
+  const bool incr = s->prec == 32;
+  int e = 0;
+  for (int d = 0; d < s->ndom; ++d) {
+    StiffArgs<Real> a = stiff_args<Real>(s, d);
+    if (ev) HIPCHK(hipEventRecord(ev[e++], st));
+    HIPCHK(launch_stiff<Real>(a, s->rows, incr, st));
+    if (ev) HIPCHK(hipEventRecord(ev[e++], st));
+  }
+  {
+    FaceArgs<Real> a = face_args<Real>(s, 0);
+    if (ev) HIPCHK(hipEventRecord(ev[e++], st));
+    HIPCHK(launch_face<Real>(a, st));
+    if (ev) HIPCHK(hipEventRecord(ev[e++], st));
+  }
+  if (s->ndom > 1) {
+    FluxArgs<Real> a = flux_args<Real>(s);
+    if (ev) HIPCHK(hipEventRecord(ev[e++], st));
+    HIPCHK(launch_flux<Real>(a, st));
+    if (ev) HIPCHK(hipEventRecord(ev[e++], st));
+  }
+  return PMDG_OK;
+}
+
+template <typename Real>
+static pmdg_status prime(pmdg_solver* s, hipStream_t st) {
+  FaceArgs<Real> a = face_args<Real>(s, 1);
+  HIPCHK(launch_face<Real>(a, st));
+  if (s->ndom > 1) {
+    FluxArgs<Real> f = flux_args<Real>(s);
+    HIPCHK(launch_flux<Real>(f, st));
+  }
+  return PMDG_OK;
+}
+
+static pmdg_status enqueue(pmdg_solver* s, hipStream_t st, hipEvent_t* ev) {
+  return s->prec == 64 ? enqueue_step<double>(s, st, ev) : enqueue_step<float>(s, st, ev);
+}
+
+static void drop_graphs(pmdg_solver* s) {
+  for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+  s->graphs.clear();
+}
+
+template <typename Real>
+static pmdg_status bind_tables(pmdg_solver* s, hipStream_t st) {
+  pmdg_status r;
+  for (int d = 0; d < s->ndom; ++d) {
+    const std::string p = "d" + std::to_string(d) + ".";
+    for (int a = 0; a < 3; ++a) {
+      if ((r = upload_real<Real>(s, p + "tap" + std::to_string(a), [&] {
+             std::vector<double> t(s->b[d].tap[a]);
+             for (auto& v : t) v *= -s->dt * s->dt * s->b[d].c * s->b[d].c;
+             return t;
+           }(), st)))
+        return r;
+      if ((r = upload_real<Real>(s, p + "minv" + std::to_string(a), s->b[d].minv[a], st))) return r;
+    }
+  }
+  if (s->ndom > 1) {
+    if ((r = upload_real<Real>(s, "Lq", s->Lq, st))) return r;
+    if ((r = upload_real<Real>(s, "wJ", s->wJ, st))) return r;
+    if ((r = upload_real<Real>(s, "xw", s->xw, st))) return r;
+    if ((r = upload_real<Real>(s, "yw", s->yw, st))) return r;
+    if ((r = upload_vec(s, "xcx", s->xcx, st))) return r;
+    if ((r = upload_vec(s, "ycx", s->ycx, st))) return r;
+    if ((r = upload_vec(s, "xl_off", s->xl_off, st))) return r;
+    if ((r = upload_vec(s, "xl", s->xl, st))) return r;
+    if ((r = upload_vec(s, "yl_off", s->yl_off, st))) return r;
+    if ((r = upload_vec(s, "yl", s->yl, st))) return r;
+  }
+  return PMDG_OK;
+}
+
+template <typename Real>
+static pmdg_status get_state_t(pmdg_solver* s, int sc, double* p, double* pp, hipStream_t st) {
+  HIPCHK(hipStreamSynchronize(st));
+  long cnt = 0;
+  HIPCHK(hipMemcpy(&cnt, dptr<long>(s, "ctl"), sizeof(long), hipMemcpyDeviceToHost));
+  const int cur = (int)(cnt & 1);
+  long o = 0;
+  for (int d = 0; d < s->ndom; ++d) {
+    const Brick& B = s->b[d];
+    const std::string pf = "d" + std::to_string(d) + ".";
+    std::vector<Real> a(B.nnodes), b(B.nnodes);
+    HIPCHK(hipMemcpy(a.data(), dptr<Real>(s, pf + (cur ? "P1" : "P0")) + (size_t)sc * B.nnodes,
+                     B.nnodes * sizeof(Real), hipMemcpyDeviceToHost));
+    if (s->prec == 32)
+      HIPCHK(hipMemcpy(b.data(), dptr<Real>(s, pf + "X") + (size_t)sc * B.nnodes, B.nnodes * sizeof(Real),
+                       hipMemcpyDeviceToHost));
+    else
+      HIPCHK(hipMemcpy(b.data(), dptr<Real>(s, pf + (cur ? "P0" : "P1")) + (size_t)sc * B.nnodes,
+                       B.nnodes * sizeof(Real), hipMemcpyDeviceToHost));
+    for (long i = 0; i < B.nnodes; ++i) {
+      if (p) p[o + i] = (double)a[i];
+      if (pp) pp[o + i] = s->prec == 32 ? (double)a[i] - (double)b[i] : (double)b[i];
+    }
+    o += B.nnodes;
+  }
+  return PMDG_OK;
+}
+
+template <typename Real>
+static pmdg_status set_state_t(pmdg_solver* s, int sc, const double* p, const double* pp, const double* q,
+                               const double* qd, const double* qdd, long nstep, hipStream_t st) {
+  HIPCHK(hipStreamSynchronize(st));
+  const int cur = (int)(nstep & 1);
+  long o = 0;
+  for (int d = 0; d < s->ndom; ++d) {
+    const Brick& B = s->b[d];
+    const std::string pf = "d" + std::to_string(d) + ".";
+    std::vector<Real> a(B.nnodes), b(B.nnodes);
+    for (long i = 0; i < B.nnodes; ++i) {
+      const double pv = p ? p[o + i] : 0.0, pq = pp ? pp[o + i] : 0.0;
+      a[i] = (Real)pv;
+      b[i] = s->prec == 32 ? (Real)(pv - pq) : (Real)pq;
+    }
+    HIPCHK(hipMemcpy(dptr<Real>(s, pf + (cur ? "P1" : "P0")) + (size_t)sc * B.nnodes, a.data(),
+                     B.nnodes * sizeof(Real), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dptr<Real>(s, pf + (s->prec == 32 ? "X" : (cur ? "P0" : "P1"))) + (size_t)sc * B.nnodes,
+                     b.data(), B.nnodes * sizeof(Real), hipMemcpyHostToDevice));
+    o += B.nnodes;
+  }
+  if (s->Np > 0) {
+    const size_t nm = (size_t)s->Np * s->Nm, off = nm * sc;
+    std::vector<double> z(nm, 0.0);
+    HIPCHK(hipMemcpy(dptr<double>(s, "q") + off, q ? q : z.data(), nm * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dptr<double>(s, "qd") + off, qd ? qd : z.data(), nm * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dptr<double>(s, "qdd") + off, qdd ? qdd : z.data(), nm * 8, hipMemcpyHostToDevice));
+  }
+  HIPCHK(hipMemcpy(dptr<long>(s, "ctl"), &nstep, sizeof(long), hipMemcpyHostToDevice));
+  pmdg_status r = prime<Real>(s, st);
+  if (r) return r;
+  HIPCHK(hipStreamSynchronize(st));
+  s->steps_done = nstep;
+  return PMDG_OK;
+}
+
+// ------------------------------------------------------------------------
+// ABI
+// ------------------------------------------------------------------------
+extern "C" {
+
+const char* pmdg_last_error(void) { return g_err.c_str(); }
+
+pmdg_status pmdg_create(const pmdg_problem* pr, pmdg_solver** out) {
+  if (!out) return fail(PMDG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!pr) return fail(PMDG_EINVAL, "problem is NULL");
+  if (pr->ndom < 1 || pr->ndom > 2) return fail(PMDG_EINVAL, "ndom must be 1 or 2");
+  if (pr->precision != 32 && pr->precision != 64) return fail(PMDG_EINVAL, "precision must be 32 or 64");
+  if (pr->n_scenarios < 1) return fail(PMDG_EINVAL, "n_scenarios must be >= 1");
+  if (pr->trace_capacity < 1) return fail(PMDG_EINVAL, "trace_capacity must be >= 1");
+  if (pr->ndom == 2 && !(pr->penalty_alpha > 0)) return fail(PMDG_EINVAL, "penalty_alpha must be > 0");
+  pmdg_solver* s = new (std::nothrow) pmdg_solver();
+  if (!s) return fail(PMDG_ENOMEM, "out of host memory");
+  s->pr = *pr;
+  s->ndom = pr->ndom;
+  s->S = pr->n_scenarios;
+  s->prec = pr->precision;
+  s->cap = pr->trace_capacity;
+  std::string err;
+  for (int d = 0; d < s->ndom; ++d)
+    if (setup_brick(s->b[d], pr->dom[d], err)) {
+      delete s;
+      return fail(PMDG_EINVAL, "brick " + std::to_string(d) + ": " + err);
+    }
+  if (s->ndom == 2 && setup_interface(s, err)) {
+    delete s;
+    return fail(PMDG_EINVAL, err);
+  }
+  // time step: dt = cfl * h_min * (min GLL gap) / 2 / c over both bricks
+  if (pr->dt > 0) {
+    s->dt = pr->dt;
+  } else {
+    if (!(pr->cfl > 0)) { delete s; return fail(PMDG_EINVAL, "cfl must be > 0 when dt <= 0"); }
+    double best = INFINITY;
+    for (int d = 0; d < s->ndom; ++d) {
+      const Brick& B = s->b[d];
+      double gap = INFINITY, hm = INFINITY;
+      for (int i = 0; i < B.N; ++i) gap = std::min(gap, (double)(B.rule.x[i + 1] - B.rule.x[i]));
+      for (int a = 0; a < 3; ++a) hm = std::min(hm, B.h[a]);
+      best = std::min(best, pr->cfl * hm * gap * 0.5 / B.c);
+    }
+    s->dt = best;
+  }
+  // explicit stability of the volume operator: dt^2 lambda_max < 4
+  for (int d = 0; d < s->ndom; ++d) {
+    const Brick& B = s->b[d];
+    const double lam = B.c * B.c * (B.lam1[0] + B.lam1[1] + B.lam1[2]);
+    if (s->dt * s->dt * lam >= 4.0) {
+      delete s;
+      return fail(PMDG_EUNSTABLE, "dt exceeds the explicit stability bound of brick " + std::to_string(d));
+    }
+  }
+  s->amp.assign(s->S, 0.0);
+  s->phase.assign(s->S, 0.0);
+  s->freq.assign(s->S, 1.0);
+  *out = s;
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_set_pmuts(pmdg_solver* s, int Np, const double* ctr, const double* radius, int Nm,
+                           const double* omega, const double* zeta, const double* eta) {
+  if (!s) return fail(PMDG_EINVAL, "NULL solver");
+  if (s->bound) return fail(PMDG_ESTATE, "set_pmuts must precede bind");
+  if (Np < 0 || Nm < 1 || Nm > kMaxModes || (Np > 0 && (!ctr || !radius || !omega || !zeta || !eta)))
+    return fail(PMDG_EINVAL, "bad PMUT arguments (1 <= Nm <= 16)");
+  s->Np = Np;
+  s->Nm = Nm;
+  s->ctr.assign(ctr, ctr + 2 * Np);
+  s->rad.assign(radius, radius + Np);
+  s->omega.assign(omega, omega + (size_t)Np * Nm);
+  s->zeta.assign(zeta, zeta + (size_t)Np * Nm);
+  s->eta.assign(eta, eta + (size_t)Np * Nm);
+  const Brick& B = s->b[0];
+  std::vector<int> owner(face0(s), -1);
+  s->pm_off.assign(Np + 1, 0);
+  s->pm_node.clear();
+  s->pm_wf.clear();
+  for (int k = 0; k < Np; ++k) {
+    s->pm_off[k] = (int)s->pm_node.size();
+    for (int j = 0; j < B.nn[1]; ++j)
+      for (int i = 0; i < B.nn[0]; ++i) {
+        const double dx = B.coord(0, i) - ctr[2 * k], dy = B.coord(1, j) - ctr[2 * k + 1];
+        if (std::sqrt(dx * dx + dy * dy) <= radius[k]) {
+          const long f = i + (long)B.nn[0] * j;
+          if (owner[f] >= 0) return fail(PMDG_EINVAL, "PMUT discs overlap");
+          owner[f] = k;
+          s->pm_node.push_back((int)f);
+          // face quadrature weight: product of the assembled 1D lumped masses
+          s->pm_wf.push_back(B.mass1[0][i] * B.mass1[1][j]);
+        }
+      }
+  }
+  s->pm_off[Np] = (int)s->pm_node.size();
+  s->pm_B.assign(s->pm_node.size() * Nm, 0.0);
+  s->shape_set.assign(Np, 0);
+  s->amp.assign((size_t)s->S * Np, 0.0);
+  s->phase.assign((size_t)s->S * Np, 0.0);
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_pmut_face_nodes(pmdg_solver* s, int k, int* n, double* xyz) {
+  if (!s || !n) return fail(PMDG_EINVAL, "NULL argument");
+  if (k < 0 || k >= s->Np) return fail(PMDG_EINVAL, "PMUT index out of range");
+  const int o = s->pm_off[k], cnt = s->pm_off[k + 1] - o;
+  *n = cnt;
+  if (xyz) {
+    const Brick& B = s->b[0];
+    for (int m = 0; m < cnt; ++m) {
+      const int f = s->pm_node[o + m];
+      xyz[3 * m] = B.coord(0, f % B.nn[0]);
+      xyz[3 * m + 1] = B.coord(1, f / B.nn[0]);
+      xyz[3 * m + 2] = B.x0[2];
+    }
+  }
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_set_pmut_shape(pmdg_solver* s, int k, const double* shape) {
+  if (!s || !shape) return fail(PMDG_EINVAL, "NULL argument");
+  if (s->bound) return fail(PMDG_ESTATE, "set_pmut_shape must precede bind");
+  if (k < 0 || k >= s->Np) return fail(PMDG_EINVAL, "PMUT index out of range");
+  const int o = s->pm_off[k], cnt = s->pm_off[k + 1] - o, Nm = s->Nm;
+  const Brick& B = s->b[0];
+  const double kappa = B.rho * B.c * B.c;
+  for (int m = 0; m < Nm; ++m) {
+    double X = 0;
+    for (int n = 0; n < cnt; ++n) {
+      const double bv = s->pm_wf[o + n] * shape[(size_t)m * cnt + n];
+      s->pm_B[(size_t)(o + n) * Nm + m] = bv;
+      const int f = s->pm_node[o + n];
+      const double M = B.mass1[0][f % B.nn[0]] * B.mass1[1][f / B.nn[0]] * B.mass1[2][0];
+      X += bv * bv / M;
+    }
+    X *= kappa * s->dt * s->dt;
+    if (X > 2.0)
+      return fail(PMDG_EUNSTABLE, "PMUT coupling strength kappa dt^2 b^T M^-1 b = " + std::to_string(X) +
+                                      " exceeds 2 (synchronised explicit coupling unstable)");
+  }
+  s->shape_set[k] = 1;
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_set_drive(pmdg_solver* s, const double* amp, const double* phase, const double* freq, double ncyc,
+                           int envelope) {
+  if (!s || (s->Np > 0 && (!amp || !phase)) || !freq) return fail(PMDG_EINVAL, "NULL argument");
+  if (envelope < 0 || envelope > 2 || !(ncyc > 0)) return fail(PMDG_EINVAL, "bad envelope or ncyc");
+  for (int i = 0; i < s->S; ++i)
+    if (!(freq[i] > 0)) return fail(PMDG_EINVAL, "freq must be > 0");
+  const size_t n = (size_t)s->S * s->Np;
+  s->amp.assign(amp, amp + n);
+  s->phase.assign(phase, phase + n);
+  s->freq.assign(freq, freq + s->S);
+  s->ncyc = ncyc;
+  s->envelope = envelope;
+  drop_graphs(s);
+  if (s->bound && s->Np > 0) {
+    hipStream_t st = nullptr;
+    pmdg_status r;
+    if ((r = upload_vec(s, "amp", s->amp, st))) return r;
+    if ((r = upload_vec(s, "phase", s->phase, st))) return r;
+    if ((r = upload_vec(s, "freq", s->freq, st))) return r;
+  }
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_set_rx(pmdg_solver* s, double t_switch, double cap) {
+  if (!s) return fail(PMDG_EINVAL, "NULL solver");
+  if (!(cap != 0)) return fail(PMDG_EINVAL, "capacitance must be non-zero");
+  s->t_switch = t_switch;
+  s->rx_cap = cap;
+  drop_graphs(s);
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_set_receivers(pmdg_solver* s, int R, const double* xyz) {
+  if (!s || R < 0 || (R > 0 && !xyz)) return fail(PMDG_EINVAL, "bad receiver arguments");
+  if (s->bound) return fail(PMDG_ESTATE, "set_receivers must precede bind");
+  s->R = R;
+  s->r_dom.assign(R, 0);
+  s->r_base.assign(R, 0);
+  s->r_w.assign((size_t)R * 3 * (kMaxOrder + 1), 0.0);
+  for (int r = 0; r < R; ++r) {
+    bool ok = false;
+    for (int d = 0; d < s->ndom && !ok; ++d) {
+      const Brick& B = s->b[d];
+      int e[3];
+      ld xi[3];
+      bool in = true;
+      for (int a = 0; a < 3 && in; ++a) {
+        int found = -1;
+        for (int k = 0; k < B.ne[a]; ++k) {
+          const ld t = 2 * (xyz[3 * r + a] - (B.x0[a] + k * (ld)B.h[a])) / B.h[a] - 1;
+          if (t >= -1 - 1e-12L && t <= 1 + 1e-12L) { found = k; xi[a] = t; break; }
+        }
+        if (found < 0) in = false;
+        else e[a] = found;
+      }
+      if (!in) continue;
+      ok = true;
+      s->r_dom[r] = d;
+      s->r_base[r] = (long)B.N * e[0] + (long)B.nn[0] * B.N * e[1] + B.plane * B.N * e[2];
+      for (int a = 0; a < 3; ++a) {
+        ld v[kMaxOrder + 1];
+        bary_eval(B.rule, xi[a], v);
+        for (int i = 0; i <= B.N; ++i) s->r_w[((size_t)r * 3 + a) * (kMaxOrder + 1) + i] = (double)v[i];
+      }
+    }
+    if (!ok) return fail(PMDG_EINVAL, "receiver " + std::to_string(r) + " lies outside the mesh");
+  }
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_workspace_size(pmdg_solver* s, size_t* bytes) {
+  if (!s || !bytes) return fail(PMDG_EINVAL, "NULL argument");
+  *bytes = layout(s);
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_bind(pmdg_solver* s, void* dev_ptr, size_t bytes, void* stream) {
+  if (!s) return fail(PMDG_EINVAL, "NULL solver");
+  if (s->bound) return fail(PMDG_ESTATE, "already bound");
+  if (!dev_ptr || ((uintptr_t)dev_ptr & 255)) return fail(PMDG_EINVAL, "workspace must be 256-byte aligned");
+  for (int k = 0; k < s->Np; ++k)
+    if (!s->shape_set[k]) return fail(PMDG_ESTATE, "mode shape of PMUT " + std::to_string(k) + " not set");
+  const size_t need = layout(s);
+  if (bytes < need) return fail(PMDG_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+  hipStream_t st = (hipStream_t)stream;
+  s->ws = (char*)dev_ptr;
+  s->ws_bytes = bytes;
+  // zero everything (fill kernel: safe under capture on any stream)
+  HIPCHK(launch_fill_bytes(s->ws, need / 4 * 4, st));
+  pmdg_status r = s->prec == 64 ? bind_tables<double>(s, st) : bind_tables<float>(s, st);
+  if (r) { s->ws = nullptr; return r; }
+  if (s->Np > 0) {
+    if ((r = upload_vec(s, "pm_off", s->pm_off, st))) return r;
+    if ((r = upload_vec(s, "pm_node", s->pm_node, st))) return r;
+    if ((r = upload_vec(s, "pm_B", s->pm_B, st))) return r;
+    if ((r = upload_vec(s, "omega", s->omega, st))) return r;
+    if ((r = upload_vec(s, "zeta", s->zeta, st))) return r;
+    if ((r = upload_vec(s, "eta", s->eta, st))) return r;
+    if ((r = upload_vec(s, "amp", s->amp, st))) return r;
+    if ((r = upload_vec(s, "phase", s->phase, st))) return r;
+    if ((r = upload_vec(s, "freq", s->freq, st))) return r;
+  }
+  if (s->R > 0) {
+    if ((r = upload_vec(s, "r_dom", s->r_dom, st))) return r;
+    if ((r = upload_vec(s, "r_base", s->r_base, st))) return r;
+    if ((r = upload_vec(s, "r_w", s->r_w, st))) return r;
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  s->bound = true;
+  s->steps_done = 0;
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_get_dt(pmdg_solver* s, double* dt) {
+  if (!s || !dt) return fail(PMDG_EINVAL, "NULL argument");
+  *dt = s->dt;
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_num_nodes(pmdg_solver* s, long* n) {
+  if (!s || !n) return fail(PMDG_EINVAL, "NULL argument");
+  *n = s->b[0].nnodes + (s->ndom > 1 ? s->b[1].nnodes : 0);
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_node_coords(pmdg_solver* s, double* xyz) {
+  if (!s || !xyz) return fail(PMDG_EINVAL, "NULL argument");
+  long o = 0;
+  for (int d = 0; d < s->ndom; ++d) {
+    const Brick& B = s->b[d];
+    for (int k = 0; k < B.nn[2]; ++k)
+      for (int j = 0; j < B.nn[1]; ++j)
+        for (int i = 0; i < B.nn[0]; ++i, ++o) {
+          xyz[3 * o] = B.coord(0, i);
+          xyz[3 * o + 1] = B.coord(1, j);
+          xyz[3 * o + 2] = B.coord(2, k);
+        }
+  }
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_set_option(pmdg_solver* s, int option, long value) {
+  if (!s) return fail(PMDG_EINVAL, "NULL solver");
+  switch (option) {
+    case PMDG_OPT_GRAPH: s->use_graph = value ? 1 : 0; break;
+    case PMDG_OPT_TILE_ROWS:
+      if (!(value == 1 || value == 2 || value == 4 || (value == 8 && s->prec == 32)))
+        return fail(PMDG_EINVAL, "tile rows must be 1, 2, 4 (or 8 in FP32)");
+      s->rows = (int)value;
+      break;
+    case PMDG_OPT_TILE_ZCHUNK:
+      if (value < 0) return fail(PMDG_EINVAL, "zchunk must be >= 0");
+      s->zchunk = (int)value;
+      break;
+    case PMDG_OPT_GRAPH_CHUNK:
+      if (value < 1) return fail(PMDG_EINVAL, "graph chunk must be >= 1");
+      s->graph_chunk = (int)value;
+      break;
+    case PMDG_OPT_TIMING: s->timing = value ? 1 : 0; break;
+    default: return fail(PMDG_EINVAL, "unknown option");
+  }
+  drop_graphs(s);
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_step(pmdg_solver* s, int n, void* stream) {
+  if (!s) return fail(PMDG_EINVAL, "NULL solver");
+  if (!s->bound) return fail(PMDG_ESTATE, "bind before stepping");
+  if (n < 0) return fail(PMDG_EINVAL, "n must be >= 0");
+  if (s->R > 0 && s->steps_done + n > s->cap) return fail(PMDG_ESTATE, "trace capacity exceeded");
+  if (n == 0) return PMDG_OK;
+  hipStream_t st = (hipStream_t)stream;
+  if (s->timing) {
+    const int per = 2 * (s->ndom + 1 + (s->ndom > 1 ? 1 : 0));
+    std::vector<hipEvent_t> ev((size_t)n * per);
+    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    for (int i = 0; i < n; ++i) {
+      pmdg_status r = enqueue(s, st, ev.data() + (size_t)i * per);
+      if (r) return r;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    double tot[3] = {0, 0, 0};
+    for (int i = 0; i < n; ++i) {
+      hipEvent_t* e = ev.data() + (size_t)i * per;
+      int k = 0;
+      for (int d = 0; d < s->ndom; ++d, k += 2) {
+        float ms;
+        HIPCHK(hipEventElapsedTime(&ms, e[k], e[k + 1]));
+        tot[0] += ms;
+      }
+      float ms;
+      HIPCHK(hipEventElapsedTime(&ms, e[k], e[k + 1]));
+      tot[1] += ms;
+      k += 2;
+      if (s->ndom > 1) {
+        HIPCHK(hipEventElapsedTime(&ms, e[k], e[k + 1]));
+        tot[2] += ms;
+      }
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    for (int c = 0; c < 3; ++c) s->ktimes[c] = tot[c] / n;
+    s->steps_done += n;
+    return PMDG_OK;
+  }
+  if (!s->use_graph) {
+    for (int i = 0; i < n; ++i) {
+      pmdg_status r = enqueue(s, st, nullptr);
+      if (r) return r;
+    }
+    s->steps_done += n;
+    return PMDG_OK;
+  }
+  // graph replay in chunks; capture happens on a private stream so that the
+  // caller's stream may be the legacy default stream
+  if (!s->cap_stream) HIPCHK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+  int left = n;
+  while (left > 0) {
+    const int len = std::min(left, s->graph_chunk);
+    auto it = s->graphs.find(len);
+    if (it == s->graphs.end()) {
+      hipGraph_t g;
+      HIPCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+      pmdg_status r = PMDG_OK;
+      for (int i = 0; i < len && !r; ++i) r = enqueue(s, s->cap_stream, nullptr);
+      hipError_t ec = hipStreamEndCapture(s->cap_stream, &g);
+      if (r) return r;
+      if (ec != hipSuccess) return fail(PMDG_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+      hipGraphExec_t ex;
+      ec = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      if (ec != hipSuccess) return fail(PMDG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ec));
+      it = s->graphs.emplace(len, ex).first;
+    }
+    HIPCHK(hipGraphLaunch(it->second, st));
+    left -= len;
+  }
+  s->steps_done += n;
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_steps_done(pmdg_solver* s, long* n) {
+  if (!s || !n) return fail(PMDG_EINVAL, "NULL argument");
+  *n = s->steps_done;
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_kernel_times(pmdg_solver* s, double* ms3) {
+  if (!s || !ms3) return fail(PMDG_EINVAL, "NULL argument");
+  for (int c = 0; c < 3; ++c) ms3[c] = s->ktimes[c];
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_read_traces(pmdg_solver* s, double* out, void* stream) {
+  if (!s || !out) return fail(PMDG_EINVAL, "NULL argument");
+  if (!s->bound) return fail(PMDG_ESTATE, "not bound");
+  if (s->R == 0) return PMDG_OK;
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  std::vector<double> all((size_t)s->S * s->R * s->cap);
+  HIPCHK(hipMemcpy(all.data(), dptr<double>(s, "traces"), all.size() * sizeof(double), hipMemcpyDeviceToHost));
+  const long n = std::min(s->steps_done, s->cap);
+  for (long sr = 0; sr < (long)s->S * s->R; ++sr)
+    memcpy(out + sr * n, all.data() + sr * s->cap, n * sizeof(double));
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_read_modal(pmdg_solver* s, int sc, double* q, double* qd, double* qdd, void* stream) {
+  if (!s) return fail(PMDG_EINVAL, "NULL solver");
+  if (!s->bound) return fail(PMDG_ESTATE, "not bound");
+  if (sc < 0 || sc >= s->S) return fail(PMDG_EINVAL, "scenario out of range");
+  if (s->Np == 0) return PMDG_OK;
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  const size_t nm = (size_t)s->Np * s->Nm, off = nm * sc;
+  if (q) HIPCHK(hipMemcpy(q, dptr<double>(s, "q") + off, nm * 8, hipMemcpyDeviceToHost));
+  if (qd) HIPCHK(hipMemcpy(qd, dptr<double>(s, "qd") + off, nm * 8, hipMemcpyDeviceToHost));
+  if (qdd) HIPCHK(hipMemcpy(qdd, dptr<double>(s, "qdd") + off, nm * 8, hipMemcpyDeviceToHost));
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_get_state(pmdg_solver* s, int sc, double* p, double* p_prev, void* stream) {
+  if (!s) return fail(PMDG_EINVAL, "NULL solver");
+  if (!s->bound) return fail(PMDG_ESTATE, "not bound");
+  if (sc < 0 || sc >= s->S) return fail(PMDG_EINVAL, "scenario out of range");
+  return s->prec == 64 ? get_state_t<double>(s, sc, p, p_prev, (hipStream_t)stream)
+                       : get_state_t<float>(s, sc, p, p_prev, (hipStream_t)stream);
+}
+
+pmdg_status pmdg_set_state(pmdg_solver* s, int sc, const double* p, const double* p_prev, const double* q,
+                           const double* qd, const double* qdd, long nstep, void* stream) {
+  if (!s) return fail(PMDG_EINVAL, "NULL solver");
+  if (!s->bound) return fail(PMDG_ESTATE, "not bound");
+  if (sc < 0 || sc >= s->S) return fail(PMDG_EINVAL, "scenario out of range");
+  if (nstep < 0 || (s->R > 0 && nstep > s->cap)) return fail(PMDG_EINVAL, "nstep out of range");
+  return s->prec == 64 ? set_state_t<double>(s, sc, p, p_prev, q, qd, qdd, nstep, (hipStream_t)stream)
+                       : set_state_t<float>(s, sc, p, p_prev, q, qd, qdd, nstep, (hipStream_t)stream);
+}
+
+pmdg_status pmdg_status_flags(pmdg_solver* s, int* nonfinite, void* stream) {
+  if (!s || !nonfinite) return fail(PMDG_EINVAL, "NULL argument");
+  if (!s->bound) return fail(PMDG_ESTATE, "not bound");
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  HIPCHK(hipMemcpy(nonfinite, dptr<char>(s, "ctl") + 16, sizeof(int), hipMemcpyDeviceToHost));
+  return PMDG_OK;
+}
+
+void pmdg_destroy(pmdg_solver* s) {
+  if (!s) return;
+  drop_graphs(s);
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+  delete s;
+}
+
+}  // extern "C"

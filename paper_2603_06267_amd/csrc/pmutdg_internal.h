@@ -1,0 +1,134 @@
+// Internal declarations shared by the host side and the kernels of
+// libpmutdg.  Not part of the public ABI (see include/pmutdg.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace pmdg {
+
+constexpr int kMaxOrder = 8;                // polynomial order N <= 8
+constexpr int kMaxNq = kMaxOrder + 1;       // Gauss points per direction on Gamma_I
+constexpr int kMaxModes = 16;               // modes per PMUT
+constexpr int kTileX = 64;                  // stiffness tile width = one wavefront
+constexpr int kWaves = 4;                   // waves per stiffness workgroup
+
+// Field arrays and operator tables of one brick, as seen by the kernels.
+template <typename Real>
+struct DomView {
+  int nn[3];          // nodes per axis
+  int N;              // order
+  long plane;         // nn[0] * nn[1]
+  long nnodes;        // nn[0] * nn[1] * nn[2]
+  Real* P[2];         // [S][nnodes] pressure, double-buffered by step parity
+  Real* X;            // [S][nnodes] increment p^n - p^{n-1} (increment form only)
+  const Real* tap[3]; // [nn_axis][2N] off-centre taps of -dt^2 c^2 M_d^{-1} K_d
+  const Real* minv[3];// [nn_axis] inverse assembled 1D lumped mass
+};
+
+// Stiffness + update kernel arguments (one brick).
+template <typename Real>
+struct StiffArgs {
+  DomView<Real> d;
+  int S;
+  Real dt2;                 // dt^2
+  const long* counter;      // steps completed (read only here)
+  int* nonfinite;           // watchdog flag
+  // PMUT face force on the primary's bottom plane: [S][nn0*nn1], or null
+  const Real* force;
+  // interface residual per face of Gamma_I: [S][nface][(N+1)^2][2] or null
+  const Real* iface;
+  int iface_side;           // +1: top element layer (fine side); -1: bottom layer (coarse side)
+  int iface_nex, iface_ney; // faces per axis on Gamma_I for this brick
+  Real iface_d[kMaxOrder + 1]; // c^2 (2/h_z) l_c'(+-1)
+  // tiling
+  int nbx, nby, nbz, zchunk;
+  int nblocks;
+};
+
+// Face kernel: PMUT sampling + modal ODE + face force, receivers, and the
+// value / normal-derivative traces of both bricks on Gamma_I.
+template <typename Real>
+struct FaceArgs {
+  long* counter;
+  unsigned* done;
+  int nblocks;
+  int prime;                // 1: only traces and force from the stored qddot
+  int S;
+  double dt;
+  DomView<Real> d0, d1;
+  int ndom;
+  // interface traces
+  Real* tr0;                // [S][nn0x*nn0y][2] (value, d/dz) at the primary top plane
+  Real* tr1;                // [S][nn1x*nn1y][2] at the secondary bottom plane
+  Real dz0[kMaxOrder + 1];  // (2/h_z) l_c'(+1), primary
+  Real dz1[kMaxOrder + 1];  // (2/h_z) l_c'(-1), secondary
+  // PMUTs
+  int Np, Nm;
+  const int* pm_off;        // [Np+1]
+  const int* pm_node;       // flat bottom-face index i + nn0x*j
+  const double* pm_B;       // [nodes][Nm] face weight * mode shape
+  const double* omega;      // [Np*Nm]
+  const double* zeta;
+  const double* eta;
+  double kappa;
+  const double* amp;        // [S*Np]
+  const double* phase;      // [S*Np]
+  const double* freq;       // [S]
+  double ncyc;
+  int envelope;
+  double t_switch, cap;
+  double* q;                // [S*Np*Nm]
+  double* qd;
+  double* qdd;
+  Real* force;              // [S][nn0x*nn0y]
+  // receivers
+  int R;
+  const int* r_dom;         // [R]
+  const long* r_base;       // [R] node index of the element's first node
+  const double* r_w;        // [R][3][kMaxOrder+1]
+  double* traces;           // [S][R][cap]
+  long tcap;
+  // block-role ranges
+  int nb_tr0, nb_tr1, nb_pm, nb_rc;
+};
+
+// Interface flux kernel: SIPG terms per Gauss point of each fine face,
+// reduced onto the faces of both sides.
+template <typename Real>
+struct FluxArgs {
+  int S;
+  int N0, N1, Nq;
+  int nn0x, nn1x;           // face-grid widths (nodes) of both sides
+  int nex0, ney0, nex1, ney1;
+  const Real* tr0;
+  const Real* tr1;
+  const Real* Lq;           // [Nq][N0+1] fine basis at the Gauss points
+  const Real* wJ;           // [Nq*Nq] Gauss weight * fine face Jacobian
+  const int* xcx;           // [nex0*Nq] coarse element index along x of fine point (ex,qa)
+  const int* ycx;           // [ney0*Nq]
+  const Real* xw;           // [nex0*Nq][N1+1] coarse basis at the mapped point
+  const Real* yw;           // [ney0*Nq][N1+1]
+  const int* xl_off;        // [nex1+1] CSR: fine points (ex*Nq+qa) inside coarse element cx
+  const int* xl;            //
+  const int* yl_off;        // [ney1+1]
+  const int* yl;
+  Real gamma, cf2, cc2;
+  Real* R0;                 // [S][nex0*ney0][(N0+1)^2][2]
+  Real* R1;                 // [S][nex1*ney1][(N1+1)^2][2]
+  int nb_fine, nb_coarse;   // blocks (4 faces each)
+};
+
+// Launchers (defined in pmutdg_kernels.hip).
+template <typename Real>
+hipError_t launch_stiff(const StiffArgs<Real>& a, int rows_per_wave, bool incr, hipStream_t st);
+template <typename Real>
+hipError_t launch_face(const FaceArgs<Real>& a, hipStream_t st);
+template <typename Real>
+hipError_t launch_flux(const FluxArgs<Real>& a, hipStream_t st);
+template <typename Real>
+hipError_t launch_fill(Real* p, long n, Real v, hipStream_t st);
+hipError_t launch_fill_bytes(void* p, size_t n, hipStream_t st);
+
+}  // namespace pmdg

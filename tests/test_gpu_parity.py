@@ -1,0 +1,222 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle on
+the same seeded inputs.  Tolerances: relative L2 of all receiver traces
+<= 1e-5 for the FP32 solver (increment-form state, FP64 ODE and traces) and
+<= 1e-10 for the FP64 solver."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ref
+from paper_2603_06267_amd import solver, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {32: 1e-5, 64: 1e-10}
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def run_pair(wl, precision, steps=None, scen=0):
+    steps = steps or wl["steps"]
+    sf = W.shape_fn(wl)
+    o = ref.from_workload(wl, scenario=scen, shape_fn=sf)
+    to = o.step(steps)
+    g = solver.from_workload(wl, precision=precision, n_steps=steps, scenarios=[scen], shape_fn=sf)
+    g.step(steps)
+    tg = g.read_traces()[0]
+    assert not g.nonfinite()
+    return tg, to, g, o
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_config1_cube_single_pmut(precision):
+    _say(f"config1 precision={precision}")
+    wl = W.config1()
+    tg, to, g, o = run_pair(wl, precision)
+    assert abs(g.dt - o.dt) < 1e-15 * o.dt
+    assert np.abs(to).max() > 0
+    err = rel_l2(tg, to)
+    _say(f"  rel L2 {err:.3e}")
+    assert err <= TOL[precision]
+    # modal state agrees as well
+    q, qd, qdd = g.read_modal()
+    st = o.get_state()
+    assert rel_l2(q, st["q"]) <= 10 * TOL[precision]
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+@pytest.mark.parametrize("nested", [True, False])
+def test_small_two_domain(precision, nested):
+    """Several tiles in x and y with ragged tails, both interface kinds
+    (nested 2:1 and non-nested 4:3), receivers in both bricks."""
+    _say(f"small two-domain nested={nested} precision={precision}")
+    wl = W.small_two_domain(nested, steps=400)
+    tg, to, g, o = run_pair(wl, precision)
+    err = rel_l2(tg, to)
+    _say(f"  rel L2 {err:.3e}")
+    assert err <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_config2_two_domain_array(precision):
+    _say(f"config2 precision={precision} (2000 steps)")
+    wl = W.config2()
+    tg, to, g, o = run_pair(wl, precision)
+    err = rel_l2(tg, to)
+    _say(f"  rel L2 {err:.3e}")
+    assert err <= TOL[precision]
+
+
+def test_graph_replay_equals_direct_launches():
+    wl = W.small_two_domain(True, steps=150)
+    sf = W.shape_fn(wl)
+    out = []
+    for graph in (0, 1):
+        g = solver.from_workload(wl, precision=32, shape_fn=sf, bind=False)
+        g.set_option(1, graph)
+        g.set_option(4, 37)  # odd chunk length: replays cross step parity
+        g.bind()
+        g.step(150)
+        out.append(g.read_traces())
+    assert np.array_equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("rows,zchunk", [(1, 0), (4, 5), (8, 3)])
+def test_tilings_agree(rows, zchunk):
+    """Every tile shape gives the same arithmetic per node (bitwise)."""
+    wl = W.small_two_domain(False, steps=80)
+    sf = W.shape_fn(wl)
+    ref_tr = None
+    for r, z in ((2, 0), (rows, zchunk)):
+        g = solver.from_workload(wl, precision=32, shape_fn=sf, bind=False)
+        g.set_option(2, r)
+        g.set_option(3, z)
+        g.bind()
+        g.step(80)
+        tr = g.read_traces()
+        if ref_tr is None:
+            ref_tr = tr
+        else:
+            assert np.array_equal(tr, ref_tr)
+
+
+def test_scenarios_batch_equals_single():
+    """S scenarios in one launch == S separate single-scenario solvers."""
+    wl = W.config4()["scenarios"]
+    wl = dict(wl, steps=120)
+    sf = W.shape_fn(wl)
+    sc = [0, 5, 17]
+    gb = solver.from_workload(wl, precision=32, scenarios=sc, shape_fn=sf)
+    gb.step(120)
+    tb = gb.read_traces()
+    for i, s in enumerate(sc):
+        g1 = solver.from_workload(wl, precision=32, scenarios=[s], shape_fn=sf)
+        g1.step(120)
+        assert np.array_equal(g1.read_traces()[0], tb[i])
+    o = ref.from_workload(wl, scenario=17, shape_fn=sf)
+    assert rel_l2(tb[2], o.step(120)) <= 1e-5
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_checkpoint_resume(precision):
+    wl = W.small_two_domain(True, steps=200)
+    sf = W.shape_fn(wl)
+    g = solver.from_workload(wl, precision=precision, shape_fn=sf)
+    g.step(200)
+    full = g.read_traces()
+    h = solver.from_workload(wl, precision=precision, shape_fn=sf)
+    h.step(90)
+    p, pp = h.get_state(0)
+    q, qd, qdd = h.read_modal(0)
+    k = solver.from_workload(wl, precision=precision, shape_fn=sf)
+    k.set_state(0, p, pp, q, qd, qdd, nstep=90)
+    k.step(110)
+    tail = k.read_traces()[:, :, 90:]
+    if precision == 64:
+        assert np.array_equal(tail, full[:, :, 90:])
+    else:
+        # the increment is re-derived from p and p_prev in FP64 on the host
+        assert rel_l2(tail, full[:, :, 90:]) < 1e-6
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_standing_wave(precision):
+    """Rigid cube, separable discrete eigenvector as initial state:
+    p^n = v cos(n theta) (closed form of the discrete scheme)."""
+    from tests._indep import sem_1d
+    N, ne, c = 4, 3, 1.5
+    dom = W.brick([0, 0, 0], [1, 1, 1], [ne, ne, ne], N, c=c)
+    g = solver.Solver([dom], precision=precision, trace_capacity=400)
+    g.set_receivers([[0.3, 0.6, 0.2]])
+    g.bind()
+    K, M = sem_1d(N, ne, 1.0 / ne)
+    Mi = 1 / np.sqrt(M)
+    lam, V = np.linalg.eigh(Mi[:, None] * K * Mi[None, :])
+    v1, v2 = Mi * V[:, 1], Mi * V[:, 2]
+    v = np.kron(v1, np.kron(v2, v1))
+    lam3 = c * c * (2 * lam[1] + lam[2])
+    theta = math.acos(1 - 0.5 * g.dt ** 2 * lam3)
+    g.set_state(0, v, v * math.cos(theta))
+    g.step(400)
+    p, _ = g.get_state(0)
+    err = np.abs(p - v * math.cos(400 * theta)).max() / np.abs(v).max()
+    assert err < (2e-5 if precision == 32 else 1e-11)
+
+
+def _smooth_field(xyz, seed):
+    rng = np.random.default_rng(seed)
+    f = np.zeros(len(xyz))
+    for _ in range(4):
+        k = rng.uniform(0.5, 2.5, size=3)
+        ph = rng.uniform(0, 2 * np.pi, size=3)
+        f += np.prod(np.cos(k * xyz + ph), axis=1) * rng.uniform(0.5, 1.0)
+    return f
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_config3_full_size_one_step(precision):
+    """Full-size config 3 (32.8M nodes, 1024 PMUTs, 4:3 interface) in the
+    launch configuration the benchmark times: one step from a smooth state
+    with non-zero modal accelerations, against the oracle's explicit update
+    p^{n+1} = 2 p^n - p^{n-1} + dt^2 M^{-1} (f(qdd^n) - K p^n) at every node."""
+    _say(f"config3 one step precision={precision}")
+    wl = W.config3(steps=4)
+    sf = W.shape_fn(wl)
+    g = solver.from_workload(wl, precision=precision, n_steps=4, shape_fn=sf, bind=False)
+    g.set_option(2, 2)
+    g.bind()
+    xyz = g.node_coords()
+    p = _smooth_field(xyz, 1)
+    pp = p - 0.05 * _smooth_field(xyz, 2)
+    rng = np.random.default_rng(3)
+    nm = g.Np * g.Nm
+    qdd = rng.standard_normal(nm)
+    g.set_state(0, p, pp, np.zeros(nm), np.zeros(nm), qdd, nstep=0)
+    g.set_option(1, 0)
+    g.step(1)
+    pn, _ = g.get_state(0)
+    del xyz
+    o = ref.from_workload(wl, shape_fn=sf)
+    Kp = o.apply_K(p)
+    M = o.mass()
+    f = np.zeros(o.n)
+    kappa = wl["domains"][0]["rho"] * wl["domains"][0]["c"] ** 2
+    for k in range(o.Np):
+        for m in range(o.Nm):
+            nd, val = o.coupling(k, m)
+            f[nd] += -kappa * qdd[k * o.Nm + m] * val
+    expect = 2 * p - pp + o.dt ** 2 * (f - Kp) / M
+    d = pn - expect
+    scale = np.abs(expect - p).max()
+    err = np.abs(d).max() / scale
+    _say(f"  max |diff| / max |p^(n+1) - p^n| = {err:.3e}")
+    assert err < (2e-4 if precision == 32 else 1e-10)
