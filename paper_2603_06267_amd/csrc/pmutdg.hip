@@ -144,6 +144,8 @@ struct Brick {
   std::vector<double> minv[3];  // [nn]
   std::vector<double> mass1[3]; // [nn] assembled 1D lumped mass
   double lam1[3];               // largest eigenvalue of M_d^{-1} K_d
+  std::vector<double> ctap[3];  // [N+2][2N] rows by node class (see StiffArgs)
+  std::vector<double> cmin[3];  // [N+2]
   double coord(int axis, int i) const {
     const int e = i / N, a = i % N;
     return x0[axis] + h[axis] * (e + 0.5 * ((double)rule.x[a] + 1.0));
@@ -187,7 +189,7 @@ struct pmdg_solver {
   std::map<std::string, Seg> seg;
   long steps_done = 0;
   // options
-  int use_graph = 1, rows = 2, zchunk = 0, graph_chunk = 64, timing = 0;
+  int use_graph = 1, rows = 2, waves = 4, zchunk = 9, graph_chunk = 64, timing = 0;
   std::map<int, hipGraphExec_t> graphs;
   hipStream_t cap_stream = nullptr;
   double ktimes[3] = {0, 0, 0};
@@ -267,6 +269,30 @@ static int setup_brick(Brick& B, const pmdg_brick& d, std::string& err) {
       for (int i = 0; i < n; ++i) v[i] = wv[i] / nrm;
     }
     B.lam1[a] = (double)lam;
+    // rows by node class: interior i mod N, first node, last node
+    B.ctap[a].assign((size_t)(N + 2) * NT, 0.0);
+    B.cmin[a].assign(N + 2, 0.0);
+    auto rep = [&](int cls) -> int {
+      if (cls == N) return 0;
+      if (cls == N + 1) return n - 1;
+      if (cls == 0) return n > N + 1 ? N : -1;
+      return cls;
+    };
+    for (int cls = 0; cls < N + 2; ++cls) {
+      const int i = rep(cls);
+      if (i < 0) continue;
+      for (int t = 0; t < NT; ++t) B.ctap[a][(size_t)cls * NT + t] = B.tap[a][(size_t)i * NT + t];
+      B.cmin[a][cls] = B.minv[a][i];
+    }
+    for (int i = 0; i < n; ++i) {
+      const int cls = i == 0 ? N : (i == n - 1 ? N + 1 : i % N);
+      for (int t = 0; t < NT; ++t)
+        if (std::fabs(B.ctap[a][(size_t)cls * NT + t] - B.tap[a][(size_t)i * NT + t]) >
+            1e-12 * std::fabs(B.tap[a][(size_t)i * NT + t]) + 1e-300) {
+          err = "internal: 1D operator rows are not periodic by node class";
+          return -1;
+        }
+    }
   }
   return 0;
 }
@@ -372,6 +398,8 @@ static size_t layout(pmdg_solver* s) {
       add(p + "tap" + std::to_string(a), rb * B.nn[a] * 2 * B.N);
       add(p + "minv" + std::to_string(a), rb * B.nn[a]);
     }
+    add(p + "xtapc", rb * (B.N + 2) * 2 * B.N);
+    add(p + "xminc", rb * (B.N + 2));
   }
   if (s->Np > 0) {
     add("force", rb * S * face0(s));
@@ -484,7 +512,6 @@ static StiffArgs<Real> stiff_args(pmdg_solver* s, int d) {
   a.S = s->S;
   a.dt2 = (Real)(s->dt * s->dt);
   a.counter = dptr<long>(s, "ctl");
-  a.nonfinite = (int*)(dptr<char>(s, "ctl") + 16);
   a.force = (d == 0 && s->Np > 0) ? dptr<Real>(s, "force") : nullptr;
   if (s->ndom > 1) {
     const Brick& B = s->b[d];
@@ -495,7 +522,25 @@ static StiffArgs<Real> stiff_args(pmdg_solver* s, int d) {
     const double c2 = B.c * B.c;
     for (int c = 0; c <= B.N; ++c) a.iface_d[c] = (Real)(c2 * (d == 0 ? s->dz0[c] : s->dz1[c]));
   }
-  const int TY = kWaves * s->rows;
+  {
+    const Brick& Bd = s->b[d];
+    const std::string p = "d" + std::to_string(d) + ".";
+    a.xtap = dptr<Real>(s, p + "xtapc");
+    a.xmin = dptr<Real>(s, p + "xminc");
+    const double sc = -s->dt * s->dt * Bd.c * Bd.c;
+    const int NT = 2 * Bd.N;
+    for (int cls = 0; cls < Bd.N + 2; ++cls) {
+      for (int t = 0; t < NT; ++t) {
+        a.ytap[cls][t] = (Real)(sc * Bd.ctap[1][(size_t)cls * NT + t]);
+        a.ztap[cls][t] = (Real)(sc * Bd.ctap[2][(size_t)cls * NT + t]);
+      }
+      a.ymin[cls] = (Real)Bd.cmin[1][cls];
+      a.zmin[cls] = (Real)Bd.cmin[2][cls];
+    }
+    for (int t = 0; t < NT; ++t) a.ytap[Bd.N + 2][t] = 0;  // rows outside the brick
+    a.ymin[Bd.N + 2] = 0;
+  }
+  const int TY = s->waves * s->rows;
   const Brick& B = s->b[d];
   a.nbx = (B.nn[0] + kTileX - 1) / kTileX;
   a.nby = (B.nn[1] + TY - 1) / TY;
@@ -511,6 +556,7 @@ static FaceArgs<Real> face_args(pmdg_solver* s, int prime) {
   memset(&a, 0, sizeof(a));
   a.counter = dptr<long>(s, "ctl");
   a.done = (unsigned*)(dptr<char>(s, "ctl") + 8);
+  a.nonfinite = (int*)(dptr<char>(s, "ctl") + 16);
   a.prime = prime;
   a.S = s->S;
   a.dt = s->dt;
@@ -606,7 +652,7 @@ static pmdg_status enqueue_step(pmdg_solver* s, hipStream_t st, hipEvent_t* ev) 
   for (int d = 0; d < s->ndom; ++d) {
     StiffArgs<Real> a = stiff_args<Real>(s, d);
     if (ev) HIPCHK(hipEventRecord(ev[e++], st));
-    HIPCHK(launch_stiff<Real>(a, s->rows, incr, st));
+    HIPCHK(launch_stiff<Real>(a, s->rows, s->waves, incr, st));
     if (ev) HIPCHK(hipEventRecord(ev[e++], st));
   }
   {
@@ -657,6 +703,12 @@ static pmdg_status bind_tables(pmdg_solver* s, hipStream_t st) {
            }(), st)))
         return r;
       if ((r = upload_real<Real>(s, p + "minv" + std::to_string(a), s->b[d].minv[a], st))) return r;
+    }
+    {
+      std::vector<double> t(s->b[d].ctap[0]);
+      for (auto& v : t) v *= -s->dt * s->dt * s->b[d].c * s->b[d].c;
+      if ((r = upload_real<Real>(s, p + "xtapc", t, st))) return r;
+      if ((r = upload_real<Real>(s, p + "xminc", s->b[d].cmin[0], st))) return r;
     }
   }
   if (s->ndom > 1) {
@@ -1031,8 +1083,9 @@ pmdg_status pmdg_set_option(pmdg_solver* s, int option, long value) {
   switch (option) {
     case PMDG_OPT_GRAPH: s->use_graph = value ? 1 : 0; break;
     case PMDG_OPT_TILE_ROWS:
-      if (!(value == 1 || value == 2 || value == 4 || (value == 8 && s->prec == 32)))
-        return fail(PMDG_EINVAL, "tile rows must be 1, 2, 4 (or 8 in FP32)");
+      if (!(value == 1 || value == 2 || value == 4))
+        return fail(PMDG_EINVAL, "tile rows must be 1, 2 or 4");
+      if (value == 4 && s->waves == 8 && s->prec == 64) return fail(PMDG_EINVAL, "8 waves x 4 rows is FP32 only");
       s->rows = (int)value;
       break;
     case PMDG_OPT_TILE_ZCHUNK:
@@ -1044,6 +1097,11 @@ pmdg_status pmdg_set_option(pmdg_solver* s, int option, long value) {
       s->graph_chunk = (int)value;
       break;
     case PMDG_OPT_TIMING: s->timing = value ? 1 : 0; break;
+    case PMDG_OPT_TILE_WAVES:
+      if (!(value == 4 || value == 8)) return fail(PMDG_EINVAL, "waves per stiffness workgroup must be 4 or 8");
+      if (value == 8 && s->rows == 4 && s->prec == 64) return fail(PMDG_EINVAL, "8 waves x 4 rows is FP32 only");
+      s->waves = (int)value;
+      break;
     default: return fail(PMDG_EINVAL, "unknown option");
   }
   drop_graphs(s);

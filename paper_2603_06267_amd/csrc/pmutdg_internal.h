@@ -34,7 +34,6 @@ struct StiffArgs {
   int S;
   Real dt2;                 // dt^2
   const long* counter;      // steps completed (read only here)
-  int* nonfinite;           // watchdog flag
   // PMUT face force on the primary's bottom plane: [S][nn0*nn1], or null
   const Real* force;
   // interface residual per face of Gamma_I: [S][nface][(N+1)^2][2] or null
@@ -42,6 +41,14 @@ struct StiffArgs {
   int iface_side;           // +1: top element layer (fine side); -1: bottom layer (coarse side)
   int iface_nex, iface_ney; // faces per axis on Gamma_I for this brick
   Real iface_d[kMaxOrder + 1]; // c^2 (2/h_z) l_c'(+-1)
+  // operator rows by node class along each axis: class a < N is an
+  // interior node with i mod N = a, class N the first and N+1 the last node
+  // of the line.  y and z rows live in the kernel arguments (scalar loads).
+  const Real* xtap;                           // [N+2][2N]
+  const Real* xmin;                           // [N+2]
+  Real ytap[kMaxOrder + 3][2 * kMaxOrder];   // class N+2: zero row (outside the brick)
+  Real ztap[kMaxOrder + 2][2 * kMaxOrder];
+  Real ymin[kMaxOrder + 3], zmin[kMaxOrder + 2];
   // tiling
   int nbx, nby, nbz, zchunk;
   int nblocks;
@@ -53,6 +60,7 @@ template <typename Real>
 struct FaceArgs {
   long* counter;
   unsigned* done;
+  int* nonfinite;           // watchdog: set when a sampled pressure is not finite
   int nblocks;
   int prime;                // 1: only traces and force from the stored qddot
   int S;
@@ -122,7 +130,7 @@ struct FluxArgs {
 
 // Launchers (defined in pmutdg_kernels.hip).
 template <typename Real>
-hipError_t launch_stiff(const StiffArgs<Real>& a, int rows_per_wave, bool incr, hipStream_t st);
+hipError_t launch_stiff(const StiffArgs<Real>& a, int rows_per_wave, int waves, bool incr, hipStream_t st);
 template <typename Real>
 hipError_t launch_face(const FaceArgs<Real>& a, hipStream_t st);
 template <typename Real>

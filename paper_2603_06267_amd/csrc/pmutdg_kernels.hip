@@ -21,190 +21,13 @@
 // off-centre taps of its three grid lines; the kernel applies them in
 // difference form sum_t a_t (p_{i+t} - p_i), which keeps the zero row sum of
 // A_d exact in finite precision.
+#include <utility>
+
 #include "pmutdg_internal.h"
+#include "stiff_kernel.h"
 
 namespace pmdg {
 
-// Workgroups are dispatched round-robin over the 8 XCDs; remap so that each
-// XCD works on a contiguous range of tiles (neighbouring tiles share halo
-// planes through that XCD's L2).
-__device__ __forceinline__ int xcd_remap(int b, int nblk) {
-  const int q = nblk >> 3, r = nblk & 7;
-  const int xcd = b & 7, slot = b >> 3;
-  return xcd * q + min(xcd, r) + slot;
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// ------------------------------------------------------------------------
-// Stiffness + update: 2.5D tiles (64 x TY nodes in x-y) marching along z.
-// The z line lives in a register queue of 2N+1 planes per owned node; the
-// x and y lines are read from an LDS copy of the current plane with an
-// N-node halo.  Increment form (FP32): X holds p^n - p^{n-1},
-// X += a, p^{n+1} = p^n + X.  Two-level form (FP64):
-// p^{n+1} = p^n + (p^n - p^{n-1}) + a, written over p^{n-1}.
-// ------------------------------------------------------------------------
-template <typename Real, int N, bool INCR, int RY>
-__global__ void __launch_bounds__(256) k_stiff(const StiffArgs<Real> a) {
-  constexpr int TX = kTileX, TY = kWaves * RY, W = TX + 2 * N, H = TY + 2 * N, NT = 2 * N;
-  __shared__ Real tile[H * W];
-
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  int t = xcd_remap(blockIdx.x, a.nblocks);
-  const int bx = t % a.nbx; t /= a.nbx;
-  const int by = t % a.nby; t /= a.nby;
-  const int bz = t % a.nbz; t /= a.nbz;
-  const int s = t;
-
-  const int nx = a.d.nn[0], ny = a.d.nn[1], nz = a.d.nn[2];
-  const long plane = a.d.plane;
-  const long cnt = *a.counter;
-  const int cur = (int)(cnt & 1);
-  const Real* __restrict__ P = a.d.P[cur] + (long)s * a.d.nnodes;
-  Real* __restrict__ Pn = a.d.P[cur ^ 1] + (long)s * a.d.nnodes;
-  Real* __restrict__ X = INCR ? a.d.X + (long)s * a.d.nnodes : nullptr;
-
-  const int x = bx * TX + lane;
-  const bool xin = x < nx;
-  const int ybase = by * TY + wave * RY;
-
-  Real tx[NT];
-#pragma unroll
-  for (int i = 0; i < NT; ++i) tx[i] = xin ? a.d.tap[0][(long)x * NT + i] : Real(0);
-  Real ty[RY][NT];
-  Real my[RY];
-#pragma unroll
-  for (int r = 0; r < RY; ++r) {
-    const int y = ybase + r;
-#pragma unroll
-    for (int i = 0; i < NT; ++i) ty[r][i] = (y < ny) ? a.d.tap[1][(long)y * NT + i] : Real(0);
-    my[r] = (y < ny) ? a.d.minv[1][y] : Real(0);
-  }
-  const Real mx = xin ? a.d.minv[0][x] : Real(0);
-
-  const int k0 = bz * a.zchunk;
-  const int k1 = min(nz, k0 + a.zchunk);
-
-  Real q[RY][NT + 1];
-#pragma unroll
-  for (int r = 0; r < RY; ++r) {
-    const int y = ybase + r;
-    const bool in = xin && y < ny;
-    const long base = x + (long)nx * y;
-#pragma unroll
-    for (int i = 0; i < NT; ++i) {
-      const int kk = k0 - N + i;
-      q[r][i + 1] = (in && kk >= 0 && kk < nz) ? P[base + kk * plane] : Real(0);
-    }
-  }
-
-  // interface layer of this brick
-  int lay0 = 1 << 30, lay1 = -1;
-  if (a.iface) {
-    if (a.iface_side > 0) { lay0 = nz - 1 - N; lay1 = nz - 1; }
-    else { lay0 = 0; lay1 = N; }
-  }
-  constexpr int n1 = N + 1;
-  bool bad = false;
-
-  for (int k = k0; k < k1; ++k) {
-#pragma unroll
-    for (int r = 0; r < RY; ++r) {
-      const int y = ybase + r;
-      const bool in = xin && y < ny;
-#pragma unroll
-      for (int i = 0; i < NT; ++i) q[r][i] = q[r][i + 1];
-      const int kk = k + N;
-      q[r][NT] = (in && kk < nz) ? P[x + (long)nx * y + kk * plane] : Real(0);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < RY; ++r) tile[(N + wave * RY + r) * W + N + lane] = q[r][N];
-    if (lane < NT) {
-      const int hx = lane < N ? (bx * TX - N + lane) : (bx * TX + TX + lane - N);
-      const int col = lane < N ? lane : (TX + lane);
-      const bool okx = hx >= 0 && hx < nx;
-#pragma unroll
-      for (int r = 0; r < RY; ++r) {
-        const int y = ybase + r;
-        tile[(N + wave * RY + r) * W + col] = (okx && y < ny) ? P[hx + (long)nx * y + k * plane] : Real(0);
-      }
-    }
-    for (int hr = wave; hr < NT; hr += kWaves) {
-      const int trow = hr < N ? hr : (TY + hr);
-      const int y = by * TY - N + trow;
-      tile[trow * W + N + lane] = (xin && y >= 0 && y < ny) ? P[x + (long)nx * y + k * plane] : Real(0);
-    }
-    __syncthreads();
-
-    const Real* __restrict__ tz = a.d.tap[2] + (long)k * NT;
-    const Real mz = a.d.minv[2][k];
-    const bool in_layer = (k >= lay0 && k <= lay1);
-    const int cl = k - lay0;
-
-#pragma unroll
-    for (int r = 0; r < RY; ++r) {
-      const int y = ybase + r;
-      const int row = N + wave * RY + r;
-      const Real p0 = q[r][N];
-      Real acc = 0;
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        acc += tx[i] * (tile[row * W + lane + i] - p0);
-        acc += tx[N + i] * (tile[row * W + N + lane + 1 + i] - p0);
-        acc += ty[r][i] * (tile[(row - N + i) * W + N + lane] - p0);
-        acc += ty[r][N + i] * (tile[(row + 1 + i) * W + N + lane] - p0);
-        acc += tz[i] * (q[r][i] - p0);
-        acc += tz[N + i] * (q[r][N + 1 + i] - p0);
-      }
-      if (!(xin && y < ny)) continue;
-      const Real minv = mx * my[r] * mz;
-      if (a.force && k == 0) acc += a.dt2 * minv * a.force[(long)s * plane + x + (long)nx * y];
-      if (in_layer) {
-        // gather the residual of the (up to 4) interface faces sharing (x, y)
-        Real RA = 0, RB = 0;
-        const int ex1 = min(x / N, a.iface_nex - 1), ey1 = min(y / N, a.iface_ney - 1);
-        const int ax1 = x - N * ex1, by1 = y - N * ey1;
-        const long fbase = (long)s * a.iface_nex * a.iface_ney;
-#pragma unroll
-        for (int jy = 0; jy < 2; ++jy) {
-          const int ey = ey1 - jy, bb = jy ? N : by1;
-          if (jy && !(by1 == 0 && ey1 > 0)) continue;
-#pragma unroll
-          for (int jx = 0; jx < 2; ++jx) {
-            const int ex = ex1 - jx, aa = jx ? N : ax1;
-            if (jx && !(ax1 == 0 && ex1 > 0)) continue;
-            const Real* R = a.iface + ((fbase + ex + (long)a.iface_nex * ey) * (n1 * n1) + aa + n1 * bb) * 2;
-            RA += R[0];
-            RB += R[1];
-          }
-        }
-        Real rif = RB * a.iface_d[cl];
-        if (a.iface_side > 0) { if (cl == N) rif += RA; }
-        else { if (cl == 0) rif -= RA; }
-        acc -= a.dt2 * minv * rif;
-      }
-      const long idx = x + (long)nx * y + k * plane;
-      Real pn;
-      if (INCR) {
-        const Real xv = X[idx] + acc;
-        pn = p0 + xv;
-        X[idx] = xv;
-      } else {
-        pn = p0 + (p0 - Pn[idx]) + acc;
-      }
-      Pn[idx] = pn;
-      bad |= !__builtin_isfinite(pn);
-    }
-  }
-  if (bad) atomicOr(a.nonfinite, 1);
-}
 
 // ------------------------------------------------------------------------
 // Face kernel.
@@ -284,13 +107,16 @@ __global__ void __launch_bounds__(256) k_face(const FaceArgs<Real> a) {
 #pragma unroll
       for (int m = 0; m < kMaxModes; ++m) acc[m] = 0.0;
       const Real* P0 = a.d0.P[buf] + (long)s * a.d0.nnodes;
+      bool bad = false;
       for (int n = n0 + tid; n < n1; n += 256) {
         const double p = (double)P0[a.pm_node[n]];
+        bad |= !__builtin_isfinite(p);
         const double* B = a.pm_B + (long)n * Nm;
 #pragma unroll
         for (int m = 0; m < kMaxModes; ++m)
           if (m < Nm) acc[m] += B[m] * p;
       }
+      if (bad) atomicOr(a.nonfinite, 1);
 #pragma unroll
       for (int m = 0; m < kMaxModes; ++m) {
         if (m < Nm) {
@@ -352,6 +178,7 @@ __global__ void __launch_bounds__(256) k_face(const FaceArgs<Real> a) {
       }
       acc = wave_sum(acc);
       if (lane == 0 && cnt < a.tcap) a.traces[((long)s * a.R + r) * a.tcap + cnt] = acc;
+      if (lane == 0 && !__builtin_isfinite(acc)) atomicOr(a.nonfinite, 1);
     }
   }
 
@@ -486,46 +313,16 @@ __global__ void k_fill(Real* p, long n, Real v) {
 // ------------------------------------------------------------------------
 // Launchers
 // ------------------------------------------------------------------------
-template <typename Real, int N, bool INCR>
-static hipError_t stiff_rows(const StiffArgs<Real>& a, int ry, hipStream_t st) {
-  dim3 g(a.nblocks), blk(256);
-  switch (ry) {
-    case 1: hipLaunchKernelGGL((k_stiff<Real, N, INCR, 1>), g, blk, 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_stiff<Real, N, INCR, 2>), g, blk, 0, st, a); break;
-    case 4: hipLaunchKernelGGL((k_stiff<Real, N, INCR, 4>), g, blk, 0, st, a); break;
-    case 8:
-      if constexpr (sizeof(Real) == 4) { hipLaunchKernelGGL((k_stiff<Real, N, INCR, 8>), g, blk, 0, st, a); break; }
-      else return hipErrorInvalidValue;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-template <typename Real, bool INCR>
-static hipError_t stiff_order(const StiffArgs<Real>& a, int ry, hipStream_t st) {
-  switch (a.d.N) {
-    case 1: return stiff_rows<Real, 1, INCR>(a, ry, st);
-    case 2: return stiff_rows<Real, 2, INCR>(a, ry, st);
-    case 3: return stiff_rows<Real, 3, INCR>(a, ry, st);
-    case 4: return stiff_rows<Real, 4, INCR>(a, ry, st);
-    case 5: return stiff_rows<Real, 5, INCR>(a, ry, st);
-    case 6: return stiff_rows<Real, 6, INCR>(a, ry, st);
-    case 7: return stiff_rows<Real, 7, INCR>(a, ry, st);
-    case 8: return stiff_rows<Real, 8, INCR>(a, ry, st);
-    default: return hipErrorInvalidValue;
-  }
-}
-
 template <>
-hipError_t launch_stiff<float>(const StiffArgs<float>& a, int ry, bool incr, hipStream_t st) {
+hipError_t launch_stiff<float>(const StiffArgs<float>& a, int ry, int wv, bool incr, hipStream_t st) {
   if (!incr) return hipErrorInvalidValue;  // FP32 state always uses the increment form
-  return stiff_order<float, true>(a, ry, st);
+  return a.d.N <= 4 ? launch_stiff_f32_lo(a, ry, wv, st) : launch_stiff_f32_hi(a, ry, wv, st);
 }
 
 template <>
-hipError_t launch_stiff<double>(const StiffArgs<double>& a, int ry, bool incr, hipStream_t st) {
+hipError_t launch_stiff<double>(const StiffArgs<double>& a, int ry, int wv, bool incr, hipStream_t st) {
   if (incr) return hipErrorInvalidValue;  // FP64 state uses the two-level form
-  return stiff_order<double, false>(a, ry, st);
+  return a.d.N <= 4 ? launch_stiff_f64_lo(a, ry, wv, st) : launch_stiff_f64_hi(a, ry, wv, st);
 }
 
 template <typename Real>

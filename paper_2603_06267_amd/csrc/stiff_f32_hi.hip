@@ -1,0 +1,16 @@
+// Stiffness kernel instantiations: float, orders 5..8.
+#include "stiff_kernel.h"
+
+namespace pmdg {
+
+hipError_t launch_stiff_f32_hi(const StiffArgs<float>& a, int ry, int wv, hipStream_t st) {
+  switch (a.d.N) {
+    case 5: return stiff_waves<float, 5, true>(a, ry, wv, st);
+    case 6: return stiff_waves<float, 6, true>(a, ry, wv, st);
+    case 7: return stiff_waves<float, 7, true>(a, ry, wv, st);
+    case 8: return stiff_waves<float, 8, true>(a, ry, wv, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace pmdg

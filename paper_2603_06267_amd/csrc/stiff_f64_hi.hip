@@ -1,0 +1,16 @@
+// Stiffness kernel instantiations: double, orders 5..8.
+#include "stiff_kernel.h"
+
+namespace pmdg {
+
+hipError_t launch_stiff_f64_hi(const StiffArgs<double>& a, int ry, int wv, hipStream_t st) {
+  switch (a.d.N) {
+    case 5: return stiff_waves<double, 5, false>(a, ry, wv, st);
+    case 6: return stiff_waves<double, 6, false>(a, ry, wv, st);
+    case 7: return stiff_waves<double, 7, false>(a, ry, wv, st);
+    case 8: return stiff_waves<double, 8, false>(a, ry, wv, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace pmdg

@@ -1,0 +1,317 @@
+// Stiffness + update kernel of libpmutdg (CDNA4 / gfx950), included by the
+// per-precision compilation units stiff_f32_*.hip and stiff_f64_*.hip.
+//
+// The volume operator of a uniform brick with GLL collocation is the
+// Kronecker sum c^2 (A_x (x) I (x) I + I (x) A_y (x) I + I (x) I (x) A_z),
+// A_d = M_d^{-1} K_d the assembled 1D operator (an exact identity of the
+// tensor-product spectral element, equivalent to element-wise sum
+// factorisation followed by assembly).  Each node therefore needs the 2N
+// off-centre taps of its three grid lines; the kernel applies them in
+// difference form sum_t a_t (p_{i+t} - p_i), which keeps the zero row sum of
+// A_d exact in finite precision.
+#pragma once
+
+#include <utility>
+
+#include "pmutdg_internal.h"
+
+namespace pmdg {
+
+// Compile-time loop: f(std::integral_constant<int, 0>{}) ... f(<N-1>).
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs; remap so that each
+// XCD works on a contiguous range of tiles (neighbouring tiles share halo
+// planes through that XCD's L2).
+__device__ __forceinline__ int xcd_remap(int b, int nblk) {
+  const int q = nblk >> 3, r = nblk & 7;
+  const int xcd = b & 7, slot = b >> 3;
+  return xcd * q + min(xcd, r) + slot;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ------------------------------------------------------------------------
+// Stiffness + update: 2.5D tiles (64 x TY nodes in x-y) marching along z.
+// The z line lives in a register queue of 2N+1 planes per owned node (its
+// rotation is unrolled so that no register moves are needed); the x and y
+// lines are read from a double-buffered LDS copy of the current plane with an
+// N-node halo.  Everything the next plane needs (lead plane, halos, the
+// increment or previous level) is fetched one plane ahead so that memory
+// latency overlaps the arithmetic, with one barrier per plane.
+// Increment form (FP32): X holds p^n - p^{n-1}, X += a, p^{n+1} = p^n + X.
+// Two-level form (FP64): p^{n+1} = p^n + (p^n - p^{n-1}) + a over p^{n-1}.
+// ------------------------------------------------------------------------
+template <int N>
+__device__ __forceinline__ int node_class(int i, int n) {
+  return i == 0 ? N : (i == n - 1 ? N + 1 : i % N);
+}
+
+template <typename Real, int N, bool INCR, int RY, int WV>
+__global__ void __launch_bounds__(64 * WV) k_stiff(const StiffArgs<Real> a) {
+  constexpr int TX = kTileX, TY = WV * RY, W = TX + 2 * N, H = TY + 2 * N, NT = 2 * N, NQ = NT + 1;
+  constexpr int HYR = (NT + WV - 1) / WV;              // y-halo rows per wave
+  constexpr int NXH = (TY * NT + 64 * WV - 1) / (64 * WV);  // x-halo loads per thread
+  __shared__ Real tile[2][H * W];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  int t = xcd_remap(blockIdx.x, a.nblocks);
+  const int bx = t % a.nbx; t /= a.nbx;
+  const int by = t % a.nby; t /= a.nby;
+  const int bz = t % a.nbz; t /= a.nbz;
+  const int s = t;
+
+  const int nx = a.d.nn[0], ny = a.d.nn[1], nz = a.d.nn[2];
+  const unsigned plane = (unsigned)a.d.plane;
+  const long cnt = *a.counter;
+  const int cur = (int)(cnt & 1);
+  const Real* __restrict__ P = a.d.P[cur] + (long)s * a.d.nnodes;
+  Real* __restrict__ Pn = a.d.P[cur ^ 1] + (long)s * a.d.nnodes;
+  Real* __restrict__ X = INCR ? a.d.X + (long)s * a.d.nnodes : Pn;  // increment, or p^{n-1}
+
+  // Every load below is unconditional on a clamped address and masked
+  // afterwards, so no load needs its own branch.
+  const int x = bx * TX + lane;
+  const bool xin = x < nx;
+  const int xc_ = min(x, nx - 1);
+  const int ybase = by * TY + wave * RY;
+
+  Real tx[NT];
+  const int cxl = node_class<N>(xc_, nx);
+#pragma unroll
+  for (int i = 0; i < NT; ++i) {
+    const Real v = a.xtap[cxl * NT + i];
+    tx[i] = xin ? v : Real(0);
+  }
+  const Real mx = a.xmin[cxl];
+  int cyr[RY];
+  bool in[RY];
+  unsigned roff[RY];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    const int y = ybase + r;
+    cyr[r] = y < ny ? node_class<N>(y, ny) : N + 2;  // class N+2: all-zero row
+    in[r] = xin && y < ny;
+    roff[r] = (unsigned)xc_ + (unsigned)nx * (unsigned)min(y, ny - 1);
+  }
+  // x-halo slots of this thread: (row, column) pairs of the 2N x TY halo
+  unsigned xh_off[NXH];
+  int xh_dst[NXH];
+  bool xh_ok[NXH];
+#pragma unroll
+  for (int j = 0; j < NXH; ++j) {
+    const int e = tid + j * 64 * WV;
+    const int hrow = e / NT, hc = e % NT;
+    const int hx = hc < N ? (bx * TX - N + hc) : (bx * TX + TX + hc - N);
+    const int y = by * TY + hrow;
+    xh_ok[j] = e < TY * NT && hx >= 0 && hx < nx && y < ny;
+    xh_off[j] = (unsigned)min(max(hx, 0), nx - 1) + (unsigned)nx * (unsigned)min(y, ny - 1);
+    xh_dst[j] = e < TY * NT ? ((N + hrow) * W + (hc < N ? hc : TX + hc)) : -1;
+  }
+  // y-halo rows of this wave
+  unsigned yh_off[HYR];
+  int yh_dst[HYR];
+  bool yh_ok[HYR];
+#pragma unroll
+  for (int j = 0; j < HYR; ++j) {
+    const int hr = wave + j * WV;
+    const int trow = hr < N ? hr : (TY + hr);
+    const int y = by * TY - N + trow;
+    yh_ok[j] = hr < NT && xin && y >= 0 && y < ny;
+    yh_off[j] = (unsigned)xc_ + (unsigned)nx * (unsigned)min(max(y, 0), ny - 1);
+    yh_dst[j] = hr < NT ? trow * W + N + lane : -1;
+  }
+
+  const int k0 = bz * a.zchunk;
+  const int k1 = min(nz, k0 + a.zchunk);
+
+  Real q[RY][NQ];
+  Real xc[RY];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      const int kk = k0 - N + i;
+      const Real v = P[roff[r] + (unsigned)min(max(kk, 0), nz - 1) * plane];
+      q[r][i] = (in[r] && kk >= 0 && kk < nz) ? v : Real(0);
+    }
+    const Real v = X[roff[r] + (unsigned)k0 * plane];
+    xc[r] = in[r] ? v : Real(0);
+  }
+  {
+    Real* T = tile[0];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) T[(N + wave * RY + r) * W + N + lane] = q[r][N];
+#pragma unroll
+    for (int j = 0; j < NXH; ++j) {
+      const Real v = P[xh_off[j] + (unsigned)k0 * plane];
+      if (xh_dst[j] >= 0) T[xh_dst[j]] = xh_ok[j] ? v : Real(0);
+    }
+#pragma unroll
+    for (int j = 0; j < HYR; ++j) {
+      const Real v = P[yh_off[j] + (unsigned)k0 * plane];
+      if (yh_dst[j] >= 0) T[yh_dst[j]] = yh_ok[j] ? v : Real(0);
+    }
+  }
+
+  int lay0 = 1 << 30, lay1 = -1;
+  if (a.iface) {
+    if (a.iface_side > 0) { lay0 = nz - 1 - N; lay1 = nz - 1; }
+    else { lay0 = 0; lay1 = N; }
+  }
+  constexpr int n1 = N + 1;
+
+  for (int kb = k0; kb < k1; kb += NQ) {
+    static_for<NQ>([&](auto uc) {
+      constexpr int u = decltype(uc)::value;
+      const int k = kb + u;
+      if (k >= k1) return;
+      const int b = (k - k0) & 1;
+      const int kn = k + 1;
+      const bool more = kn < k1;
+      // (1) fetch for the next plane
+      Real nq[RY], xn[RY], hxv[NXH], hyv[HYR];
+      const int kl = k + N + 1;
+      const unsigned kl_off = (unsigned)min(kl, nz - 1) * plane;
+      const unsigned kn_off = (unsigned)min(kn, nz - 1) * plane;
+#pragma unroll
+      for (int r = 0; r < RY; ++r) {
+        nq[r] = P[roff[r] + kl_off];
+        xn[r] = X[roff[r] + kn_off];
+      }
+#pragma unroll
+      for (int j = 0; j < NXH; ++j) hxv[j] = P[xh_off[j] + kn_off];
+#pragma unroll
+      for (int j = 0; j < HYR; ++j) hyv[j] = P[yh_off[j] + kn_off];
+      // (2) plane k is complete in buffer b
+      __syncthreads();
+      const Real* T = tile[b];
+      Real col[RY + NT];
+#pragma unroll
+      for (int j = 0; j < RY + NT; ++j) col[j] = T[(wave * RY + j) * W + N + lane];
+      const int cz = node_class<N>(k, nz);
+      const Real mz = a.zmin[cz];
+      const bool in_layer = (k >= lay0 && k <= lay1);
+      const int cl = k - lay0;
+      // (3) update the nodes of plane k
+#pragma unroll
+      for (int r = 0; r < RY; ++r) {
+        const int row = N + wave * RY + r;
+        const Real p0 = q[r][(u + N) % NQ];
+        const Real* ty = a.ytap[cyr[r]];
+        const Real* tz = a.ztap[cz];
+        Real acc = 0;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          acc += tx[i] * (T[row * W + lane + i] - p0);
+          acc += tx[N + i] * (T[row * W + N + lane + 1 + i] - p0);
+          acc += ty[i] * (col[r + i] - p0);
+          acc += ty[N + i] * (col[r + N + 1 + i] - p0);
+          acc += tz[i] * (q[r][(u + i) % NQ] - p0);
+          acc += tz[N + i] * (q[r][(u + N + 1 + i) % NQ] - p0);
+        }
+        if (in[r]) {
+          const Real minv = mx * a.ymin[cyr[r]] * mz;
+          if (a.force && k == 0) acc += a.dt2 * minv * a.force[(long)s * plane + roff[r]];
+          if (in_layer) {
+            // residual of the (up to 4) interface faces sharing (x, y)
+            const int y = ybase + r;
+            Real RA = 0, RB = 0;
+            const int ex1 = min(x / N, a.iface_nex - 1), ey1 = min(y / N, a.iface_ney - 1);
+            const int ax1 = x - N * ex1, by1 = y - N * ey1;
+            const long fbase = (long)s * a.iface_nex * a.iface_ney;
+#pragma unroll
+            for (int jy = 0; jy < 2; ++jy) {
+              const int ey = ey1 - jy, bb = jy ? N : by1;
+              if (jy && !(by1 == 0 && ey1 > 0)) continue;
+#pragma unroll
+              for (int jx = 0; jx < 2; ++jx) {
+                const int ex = ex1 - jx, aa = jx ? N : ax1;
+                if (jx && !(ax1 == 0 && ex1 > 0)) continue;
+                const Real* R = a.iface + ((fbase + ex + (long)a.iface_nex * ey) * (n1 * n1) + aa + n1 * bb) * 2;
+                RA += R[0];
+                RB += R[1];
+              }
+            }
+            Real rif = RB * a.iface_d[cl];
+            if (a.iface_side > 0) { if (cl == N) rif += RA; }
+            else { if (cl == 0) rif -= RA; }
+            acc -= a.dt2 * minv * rif;
+          }
+          const unsigned idx = roff[r] + (unsigned)k * plane;
+          Real pn;
+          if (INCR) {
+            const Real xv = xc[r] + acc;
+            pn = p0 + xv;
+            X[idx] = xv;
+          } else {
+            pn = p0 + (p0 - xc[r]) + acc;
+          }
+          Pn[idx] = pn;
+        }
+      }
+      // (4) plane k+1 into the other buffer
+      if (more) {
+        Real* Tn = tile[b ^ 1];
+#pragma unroll
+        for (int r = 0; r < RY; ++r) Tn[(N + wave * RY + r) * W + N + lane] = q[r][(u + N + 1) % NQ];
+#pragma unroll
+        for (int j = 0; j < NXH; ++j)
+          if (xh_dst[j] >= 0) Tn[xh_dst[j]] = xh_ok[j] ? hxv[j] : Real(0);
+#pragma unroll
+        for (int j = 0; j < HYR; ++j)
+          if (yh_dst[j] >= 0) Tn[yh_dst[j]] = yh_ok[j] ? hyv[j] : Real(0);
+      }
+      // (5) rotate the queue
+#pragma unroll
+      for (int r = 0; r < RY; ++r) {
+        q[r][u % NQ] = (in[r] && kl < nz) ? nq[r] : Real(0);
+        xc[r] = (in[r] && more) ? xn[r] : Real(0);
+      }
+    });
+  }
+}
+
+
+template <typename Real, int N, bool INCR, int WV>
+static hipError_t stiff_rows(const StiffArgs<Real>& a, int ry, hipStream_t st) {
+  dim3 g(a.nblocks), blk(64 * WV);
+  switch (ry) {
+    case 1: hipLaunchKernelGGL((k_stiff<Real, N, INCR, 1, WV>), g, blk, 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_stiff<Real, N, INCR, 2, WV>), g, blk, 0, st, a); break;
+    case 4:
+      if constexpr (WV == 4 || sizeof(Real) == 4) { hipLaunchKernelGGL((k_stiff<Real, N, INCR, 4, WV>), g, blk, 0, st, a); break; }
+      else return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename Real, int N, bool INCR>
+static hipError_t stiff_waves(const StiffArgs<Real>& a, int ry, int wv, hipStream_t st) {
+  if (wv == 4) return stiff_rows<Real, N, INCR, 4>(a, ry, st);
+  if (wv == 8) return stiff_rows<Real, N, INCR, 8>(a, ry, st);
+  return hipErrorInvalidValue;
+}
+
+// Launchers for one precision and a range of orders (one per unit).
+hipError_t launch_stiff_f32_lo(const StiffArgs<float>& a, int ry, int wv, hipStream_t st);
+hipError_t launch_stiff_f32_hi(const StiffArgs<float>& a, int ry, int wv, hipStream_t st);
+hipError_t launch_stiff_f64_lo(const StiffArgs<double>& a, int ry, int wv, hipStream_t st);
+hipError_t launch_stiff_f64_hi(const StiffArgs<double>& a, int ry, int wv, hipStream_t st);
+
+}  // namespace pmdg
