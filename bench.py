@@ -85,7 +85,7 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--rows", type=int, default=2)
-    ap.add_argument("--zchunk", type=int, default=0)
+    ap.add_argument("--zchunk", type=int, default=33)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--fp64", action="store_true", help="also time the FP64 instantiation")

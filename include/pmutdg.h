@@ -162,15 +162,14 @@ pmdg_status pmdg_node_coords(pmdg_solver* h, double* xyz);
 pmdg_status pmdg_status_flags(pmdg_solver* h, int* nonfinite, void* stream);
 
 /* Options: PMDG_OPT_GRAPH (1 = replay hipGraphs, 0 = direct launches),
- * PMDG_OPT_TILE_ROWS (rows per wave of the stiffness tile: 1, 2 or 4),
- * PMDG_OPT_TILE_ZCHUNK (planes per block along z, 0 = whole brick),
- * PMDG_OPT_GRAPH_CHUNK (steps per captured graph),
- * PMDG_OPT_TILE_WAVES (waves per stiffness workgroup: 4 or 8). */
+ * PMDG_OPT_TILE_ROWS (rows per wave of the stiffness tile: 1, 2 or 4; a
+ * workgroup covers 64 x (4 rows) nodes per plane),
+ * PMDG_OPT_TILE_ZCHUNK (planes per workgroup along z, 0 = whole brick),
+ * PMDG_OPT_GRAPH_CHUNK (steps per captured graph). */
 #define PMDG_OPT_GRAPH 1
 #define PMDG_OPT_TILE_ROWS 2
 #define PMDG_OPT_TILE_ZCHUNK 3
 #define PMDG_OPT_GRAPH_CHUNK 4
-#define PMDG_OPT_TILE_WAVES 6
 pmdg_status pmdg_set_option(pmdg_solver* h, int option, long value);
 
 /* Average duration (ms) of each kernel class over the last timed

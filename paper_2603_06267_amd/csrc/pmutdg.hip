@@ -137,7 +137,9 @@ static void bary_eval(const Rule1D& r, ld t, ld* v) {
 struct Brick {
   double x0[3], h[3];
   int ne[3], N, nn[3];
-  long plane, nnodes;
+  long plane, nnodes;   // compact (host / ABI) layout
+  int px;               // device row pitch: nn[0] rounded up to a multiple of 64 nodes
+  long pplane, pnodes;  // device plane stride and nodes per scenario
   double c, rho;
   Rule1D rule;
   std::vector<double> tap[3];   // [nn][2N]
@@ -189,7 +191,7 @@ struct pmdg_solver {
   std::map<std::string, Seg> seg;
   long steps_done = 0;
   // options
-  int use_graph = 1, rows = 2, waves = 4, zchunk = 9, graph_chunk = 64, timing = 0;
+  int use_graph = 1, rows = 2, zchunk = 33, graph_chunk = 64, timing = 0;
   std::map<int, hipGraphExec_t> graphs;
   hipStream_t cap_stream = nullptr;
   double ktimes[3] = {0, 0, 0};
@@ -215,7 +217,10 @@ static int setup_brick(Brick& B, const pmdg_brick& d, std::string& err) {
   }
   B.plane = (long)B.nn[0] * B.nn[1];
   B.nnodes = B.plane * B.nn[2];
-  if (B.nnodes > (1L << 31)) { err = "brick too large"; return -1; }
+  B.px = (B.nn[0] + 63) / 64 * 64;
+  B.pplane = (long)B.px * B.nn[1];
+  B.pnodes = B.pplane * B.nn[2];
+  if (B.pnodes > (1L << 31) - 1024) { err = "brick too large"; return -1; }
   B.rule = gll_rule(B.N);
   const int N = B.N, n1 = N + 1, NT = 2 * N;
   for (int a = 0; a < 3; ++a) {
@@ -316,6 +321,8 @@ static int setup_interface(pmdg_solver* s, std::string& err) {
   }
   const int N0 = F.N, N1 = C.N, n0 = N0 + 1, n1 = N1 + 1;
   if (std::max(N0, N1) > kMaxOrder - 1) { err = "orders of two coupled bricks must be <= 7"; return -1; }
+  for (int a = 0; a < 2; ++a)
+    if (F.h[a] > C.h[a] * (1 + 1e-12)) { err = "the primary (fine) brick's faces must not be larger than the secondary's"; return -1; }
   s->Nq = std::max(N0, N1) + 1;
   const int Nq = s->Nq;
   std::vector<ld> gx, gw;
@@ -361,6 +368,8 @@ static int setup_interface(pmdg_solver* s, std::string& err) {
       lst.insert(lst.end(), buckets[k].begin(), buckets[k].end());
     }
     off[nec] = (int)lst.size();
+    for (int k = 0; k < nec; ++k)
+      if (off[k + 1] - off[k] > 64) { err = "more than 64 fine Gauss points per coarse element along an axis"; return -1; }
   }
   const double cbar = 2.0 * F.c * C.c / (F.c + C.c);
   const int nmax = std::max(N0, N1);
@@ -368,6 +377,42 @@ static int setup_interface(pmdg_solver* s, std::string& err) {
   for (int c = 0; c < n0; ++c) s->dz0[c] = (double)(2.0L / F.h[2] * F.rule.D[N0 * n0 + c]);
   for (int c = 0; c < n1; ++c) s->dz1[c] = (double)(2.0L / C.h[2] * C.rule.D[0 * n1 + c]);
   return 0;
+}
+
+// ------------------------------------------------------------------------
+// Drive tables (Sec. 6.1, eq. voltage): the applied voltage of PMUT k is
+// A_k g(t) sin(2 pi f t - theta_k) = (A_k cos theta_k) C_s(t) - (A_k sin theta_k) C_c(t)
+// with C_s = g(t) sin(2 pi f t), C_c = g(t) cos(2 pi f t) sampled at t_n = n dt.
+// ------------------------------------------------------------------------
+static double drive_window(double t, double Td, int envelope) {
+  if (envelope == 2) return t >= 0 ? 1.0 : 0.0;
+  if (t < 0 || t > Td) return 0.0;
+  if (envelope == 1) return 1.0;
+  // smooth window with n = 10 in the symmetric variable b = |2t/T_d - 1|
+  const double b = std::fabs(2.0 * t / Td - 1.0);
+  const double b20 = std::pow(b, 20.0);
+  const double base = 1.0 - 2.0 * b20 * b / (1.0 + b20);
+  if (base <= 0.0) return 0.0;
+  return std::exp(1.0 - 1.0 / (base * base));
+}
+
+static void drive_tables(const pmdg_solver* s, std::vector<double>& dA, std::vector<double>& car) {
+  dA.assign((size_t)s->S * s->Np * 2, 0.0);
+  car.assign((size_t)s->S * (s->cap + 1) * 2, 0.0);
+  for (int sc = 0; sc < s->S; ++sc) {
+    for (int k = 0; k < s->Np; ++k) {
+      const size_t i = (size_t)sc * s->Np + k;
+      dA[2 * i] = s->amp[i] * std::cos(s->phase[i]);
+      dA[2 * i + 1] = s->amp[i] * std::sin(s->phase[i]);
+    }
+    const double f = s->freq[sc], Td = s->ncyc / f;
+    for (long n = 0; n <= s->cap; ++n) {
+      const double t = n * s->dt;
+      const double g = drive_window(t, Td, s->envelope);
+      car[((size_t)sc * (s->cap + 1) + n) * 2] = g * std::sin(2.0 * M_PI * f * t);
+      car[((size_t)sc * (s->cap + 1) + n) * 2 + 1] = g * std::cos(2.0 * M_PI * f * t);
+    }
+  }
 }
 
 // ------------------------------------------------------------------------
@@ -391,27 +436,22 @@ static size_t layout(pmdg_solver* s) {
   for (int d = 0; d < s->ndom; ++d) {
     const Brick& B = s->b[d];
     const std::string p = "d" + std::to_string(d) + ".";
-    add(p + "P0", rb * S * B.nnodes);
-    add(p + "P1", rb * S * B.nnodes);
-    if (s->prec == 32) add(p + "X", rb * S * B.nnodes);
-    for (int a = 0; a < 3; ++a) {
-      add(p + "tap" + std::to_string(a), rb * B.nn[a] * 2 * B.N);
-      add(p + "minv" + std::to_string(a), rb * B.nn[a]);
-    }
-    add(p + "xtapc", rb * (B.N + 2) * 2 * B.N);
-    add(p + "xminc", rb * (B.N + 2));
+    add(p + "P0", rb * S * B.pnodes);
+    add(p + "P1", rb * S * B.pnodes);
+    if (s->prec == 32) add(p + "X", rb * S * B.pnodes);
+    add(p + "taps", rb * 3 * (B.N + 3) * 2 * B.N);
+    add(p + "mins", rb * 3 * (B.N + 3));
   }
   if (s->Np > 0) {
-    add("force", rb * S * face0(s));
+    add("force", rb * S * s->b[0].pplane);
     add("pm_off", sizeof(int) * (s->Np + 1));
     add("pm_node", sizeof(int) * std::max<size_t>(1, s->pm_node.size()));
     add("pm_B", sizeof(double) * std::max<size_t>(1, s->pm_B.size()));
     add("omega", sizeof(double) * s->Np * s->Nm);
     add("zeta", sizeof(double) * s->Np * s->Nm);
     add("eta", sizeof(double) * s->Np * s->Nm);
-    add("amp", sizeof(double) * S * s->Np);
-    add("phase", sizeof(double) * S * s->Np);
-    add("freq", sizeof(double) * S);
+    add("dA", sizeof(double) * S * s->Np * 2);
+    add("car", sizeof(double) * S * (s->cap + 1) * 2);
     add("q", sizeof(double) * S * s->Np * s->Nm);
     add("qd", sizeof(double) * S * s->Np * s->Nm);
     add("qdd", sizeof(double) * S * s->Np * s->Nm);
@@ -422,6 +462,7 @@ static size_t layout(pmdg_solver* s) {
     add("tr1", rb * S * face1(s) * 2);
     add("R0", rb * S * nfine(s) * n0 * n0 * 2);
     add("R1", rb * S * ncoarse(s) * n1 * n1 * 2);
+    add("Aq", rb * S * nfine(s) * s->Nq * s->Nq * 2);
     add("Lq", rb * s->Lq.size());
     add("wJ", rb * s->wJ.size());
     add("xw", rb * s->xw.size());
@@ -491,16 +532,13 @@ static DomView<Real> view(pmdg_solver* s, int d) {
   const Brick& B = s->b[d];
   for (int a = 0; a < 3; ++a) v.nn[a] = B.nn[a];
   v.N = B.N;
-  v.plane = B.plane;
-  v.nnodes = B.nnodes;
+  v.px = B.px;
+  v.plane = B.pplane;
+  v.nnodes = B.pnodes;
   const std::string p = "d" + std::to_string(d) + ".";
   v.P[0] = dptr<Real>(s, p + "P0");
   v.P[1] = dptr<Real>(s, p + "P1");
   v.X = s->prec == 32 ? dptr<Real>(s, p + "X") : nullptr;
-  for (int a = 0; a < 3; ++a) {
-    v.tap[a] = dptr<Real>(s, p + "tap" + std::to_string(a));
-    v.minv[a] = dptr<Real>(s, p + "minv" + std::to_string(a));
-  }
   return v;
 }
 
@@ -523,26 +561,14 @@ static StiffArgs<Real> stiff_args(pmdg_solver* s, int d) {
     for (int c = 0; c <= B.N; ++c) a.iface_d[c] = (Real)(c2 * (d == 0 ? s->dz0[c] : s->dz1[c]));
   }
   {
-    const Brick& Bd = s->b[d];
     const std::string p = "d" + std::to_string(d) + ".";
-    a.xtap = dptr<Real>(s, p + "xtapc");
-    a.xmin = dptr<Real>(s, p + "xminc");
-    const double sc = -s->dt * s->dt * Bd.c * Bd.c;
-    const int NT = 2 * Bd.N;
-    for (int cls = 0; cls < Bd.N + 2; ++cls) {
-      for (int t = 0; t < NT; ++t) {
-        a.ytap[cls][t] = (Real)(sc * Bd.ctap[1][(size_t)cls * NT + t]);
-        a.ztap[cls][t] = (Real)(sc * Bd.ctap[2][(size_t)cls * NT + t]);
-      }
-      a.ymin[cls] = (Real)Bd.cmin[1][cls];
-      a.zmin[cls] = (Real)Bd.cmin[2][cls];
-    }
-    for (int t = 0; t < NT; ++t) a.ytap[Bd.N + 2][t] = 0;  // rows outside the brick
-    a.ymin[Bd.N + 2] = 0;
+    a.taps = dptr<Real>(s, p + "taps");
+    a.mins = dptr<Real>(s, p + "mins");
   }
-  const int TY = s->waves * s->rows;
   const Brick& B = s->b[d];
-  a.nbx = (B.nn[0] + kTileX - 1) / kTileX;
+  a.rows = s->rows;
+  a.nbx = B.px / 64;
+  const int TY = kWaves * s->rows;
   a.nby = (B.nn[1] + TY - 1) / TY;
   a.zchunk = (s->zchunk > 0) ? std::min(s->zchunk, B.nn[2]) : B.nn[2];
   a.nbz = (B.nn[2] + a.zchunk - 1) / a.zchunk;
@@ -555,7 +581,6 @@ static FaceArgs<Real> face_args(pmdg_solver* s, int prime) {
   FaceArgs<Real> a;
   memset(&a, 0, sizeof(a));
   a.counter = dptr<long>(s, "ctl");
-  a.done = (unsigned*)(dptr<char>(s, "ctl") + 8);
   a.nonfinite = (int*)(dptr<char>(s, "ctl") + 16);
   a.prime = prime;
   a.S = s->S;
@@ -581,11 +606,9 @@ static FaceArgs<Real> face_args(pmdg_solver* s, int prime) {
     a.zeta = dptr<double>(s, "zeta");
     a.eta = dptr<double>(s, "eta");
     a.kappa = s->b[0].rho * s->b[0].c * s->b[0].c;
-    a.amp = dptr<double>(s, "amp");
-    a.phase = dptr<double>(s, "phase");
-    a.freq = dptr<double>(s, "freq");
-    a.ncyc = s->ncyc;
-    a.envelope = s->envelope;
+    a.dA = dptr<double>(s, "dA");
+    a.car = dptr<double>(s, "car");
+    a.ncar = s->cap + 1;
     a.t_switch = s->t_switch;
     a.cap = s->rx_cap;
     a.q = dptr<double>(s, "q");
@@ -609,7 +632,7 @@ static FaceArgs<Real> face_args(pmdg_solver* s, int prime) {
 }
 
 template <typename Real>
-static FluxArgs<Real> flux_args(pmdg_solver* s) {
+static FluxArgs<Real> flux_args(pmdg_solver* s, int tick) {
   FluxArgs<Real> a;
   memset(&a, 0, sizeof(a));
   if (s->ndom < 2) return a;
@@ -640,6 +663,9 @@ static FluxArgs<Real> flux_args(pmdg_solver* s) {
   a.cc2 = (Real)(s->b[1].c * s->b[1].c);
   a.R0 = dptr<Real>(s, "R0");
   a.R1 = dptr<Real>(s, "R1");
+  a.Aq = dptr<Real>(s, "Aq");
+  a.counter = dptr<long>(s, "ctl");
+  a.tick = tick;
   a.nb_fine = (s->S * nfine(s) + kWaves - 1) / kWaves;
   a.nb_coarse = (s->S * ncoarse(s) + kWaves - 1) / kWaves;
   return a;
@@ -652,7 +678,7 @@ static pmdg_status enqueue_step(pmdg_solver* s, hipStream_t st, hipEvent_t* ev) 
   for (int d = 0; d < s->ndom; ++d) {
     StiffArgs<Real> a = stiff_args<Real>(s, d);
     if (ev) HIPCHK(hipEventRecord(ev[e++], st));
-    HIPCHK(launch_stiff<Real>(a, s->rows, s->waves, incr, st));
+    HIPCHK(launch_stiff<Real>(a, incr, st));
     if (ev) HIPCHK(hipEventRecord(ev[e++], st));
   }
   {
@@ -661,12 +687,14 @@ static pmdg_status enqueue_step(pmdg_solver* s, hipStream_t st, hipEvent_t* ev) 
     HIPCHK(launch_face<Real>(a, st));
     if (ev) HIPCHK(hipEventRecord(ev[e++], st));
   }
+  if (ev) HIPCHK(hipEventRecord(ev[e++], st));
   if (s->ndom > 1) {
-    FluxArgs<Real> a = flux_args<Real>(s);
-    if (ev) HIPCHK(hipEventRecord(ev[e++], st));
+    FluxArgs<Real> a = flux_args<Real>(s, 1);
     HIPCHK(launch_flux<Real>(a, st));
-    if (ev) HIPCHK(hipEventRecord(ev[e++], st));
+  } else {
+    HIPCHK(launch_tick(dptr<long>(s, "ctl"), st));
   }
+  if (ev) HIPCHK(hipEventRecord(ev[e++], st));
   return PMDG_OK;
 }
 
@@ -675,7 +703,7 @@ static pmdg_status prime(pmdg_solver* s, hipStream_t st) {
   FaceArgs<Real> a = face_args<Real>(s, 1);
   HIPCHK(launch_face<Real>(a, st));
   if (s->ndom > 1) {
-    FluxArgs<Real> f = flux_args<Real>(s);
+    FluxArgs<Real> f = flux_args<Real>(s, 0);
     HIPCHK(launch_flux<Real>(f, st));
   }
   return PMDG_OK;
@@ -695,21 +723,17 @@ static pmdg_status bind_tables(pmdg_solver* s, hipStream_t st) {
   pmdg_status r;
   for (int d = 0; d < s->ndom; ++d) {
     const std::string p = "d" + std::to_string(d) + ".";
-    for (int a = 0; a < 3; ++a) {
-      if ((r = upload_real<Real>(s, p + "tap" + std::to_string(a), [&] {
-             std::vector<double> t(s->b[d].tap[a]);
-             for (auto& v : t) v *= -s->dt * s->dt * s->b[d].c * s->b[d].c;
-             return t;
-           }(), st)))
-        return r;
-      if ((r = upload_real<Real>(s, p + "minv" + std::to_string(a), s->b[d].minv[a], st))) return r;
-    }
-    {
-      std::vector<double> t(s->b[d].ctap[0]);
-      for (auto& v : t) v *= -s->dt * s->dt * s->b[d].c * s->b[d].c;
-      if ((r = upload_real<Real>(s, p + "xtapc", t, st))) return r;
-      if ((r = upload_real<Real>(s, p + "xminc", s->b[d].cmin[0], st))) return r;
-    }
+    const Brick& B = s->b[d];
+    const int NT = 2 * B.N, NC = B.N + 3;
+    std::vector<double> taps((size_t)3 * NC * NT, 0.0), mins((size_t)3 * NC, 0.0);
+    const double sc = -s->dt * s->dt * B.c * B.c;
+    for (int ax = 0; ax < 3; ++ax)
+      for (int cls = 0; cls < B.N + 2; ++cls) {
+        for (int t = 0; t < NT; ++t) taps[((size_t)ax * NC + cls) * NT + t] = sc * B.ctap[ax][(size_t)cls * NT + t];
+        mins[(size_t)ax * NC + cls] = B.cmin[ax][cls];
+      }
+    if ((r = upload_real<Real>(s, p + "taps", taps, st))) return r;
+    if ((r = upload_real<Real>(s, p + "mins", mins, st))) return r;
   }
   if (s->ndom > 1) {
     if ((r = upload_real<Real>(s, "Lq", s->Lq, st))) return r;
@@ -726,6 +750,12 @@ static pmdg_status bind_tables(pmdg_solver* s, hipStream_t st) {
   return PMDG_OK;
 }
 
+// compact (i + nn0 (j + nn1 k)) <-> device (i + px (j + nn1 k)) node index
+static inline long dev_index(const Brick& B, long i) {
+  const long row = i / B.nn[0];
+  return row * B.px + (i - row * B.nn[0]);
+}
+
 template <typename Real>
 static pmdg_status get_state_t(pmdg_solver* s, int sc, double* p, double* pp, hipStream_t st) {
   HIPCHK(hipStreamSynchronize(st));
@@ -736,18 +766,19 @@ static pmdg_status get_state_t(pmdg_solver* s, int sc, double* p, double* pp, hi
   for (int d = 0; d < s->ndom; ++d) {
     const Brick& B = s->b[d];
     const std::string pf = "d" + std::to_string(d) + ".";
-    std::vector<Real> a(B.nnodes), b(B.nnodes);
-    HIPCHK(hipMemcpy(a.data(), dptr<Real>(s, pf + (cur ? "P1" : "P0")) + (size_t)sc * B.nnodes,
-                     B.nnodes * sizeof(Real), hipMemcpyDeviceToHost));
+    std::vector<Real> a(B.pnodes), b(B.pnodes);
+    HIPCHK(hipMemcpy(a.data(), dptr<Real>(s, pf + (cur ? "P1" : "P0")) + (size_t)sc * B.pnodes,
+                     B.pnodes * sizeof(Real), hipMemcpyDeviceToHost));
     if (s->prec == 32)
-      HIPCHK(hipMemcpy(b.data(), dptr<Real>(s, pf + "X") + (size_t)sc * B.nnodes, B.nnodes * sizeof(Real),
+      HIPCHK(hipMemcpy(b.data(), dptr<Real>(s, pf + "X") + (size_t)sc * B.pnodes, B.pnodes * sizeof(Real),
                        hipMemcpyDeviceToHost));
     else
-      HIPCHK(hipMemcpy(b.data(), dptr<Real>(s, pf + (cur ? "P0" : "P1")) + (size_t)sc * B.nnodes,
-                       B.nnodes * sizeof(Real), hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(b.data(), dptr<Real>(s, pf + (cur ? "P0" : "P1")) + (size_t)sc * B.pnodes,
+                       B.pnodes * sizeof(Real), hipMemcpyDeviceToHost));
     for (long i = 0; i < B.nnodes; ++i) {
-      if (p) p[o + i] = (double)a[i];
-      if (pp) pp[o + i] = s->prec == 32 ? (double)a[i] - (double)b[i] : (double)b[i];
+      const long di = dev_index(B, i);
+      if (p) p[o + i] = (double)a[di];
+      if (pp) pp[o + i] = s->prec == 32 ? (double)a[di] - (double)b[di] : (double)b[di];
     }
     o += B.nnodes;
   }
@@ -763,16 +794,17 @@ static pmdg_status set_state_t(pmdg_solver* s, int sc, const double* p, const do
   for (int d = 0; d < s->ndom; ++d) {
     const Brick& B = s->b[d];
     const std::string pf = "d" + std::to_string(d) + ".";
-    std::vector<Real> a(B.nnodes), b(B.nnodes);
+    std::vector<Real> a(B.pnodes, Real(0)), b(B.pnodes, Real(0));
     for (long i = 0; i < B.nnodes; ++i) {
       const double pv = p ? p[o + i] : 0.0, pq = pp ? pp[o + i] : 0.0;
-      a[i] = (Real)pv;
-      b[i] = s->prec == 32 ? (Real)(pv - pq) : (Real)pq;
+      const long di = dev_index(B, i);
+      a[di] = (Real)pv;
+      b[di] = s->prec == 32 ? (Real)(pv - pq) : (Real)pq;
     }
-    HIPCHK(hipMemcpy(dptr<Real>(s, pf + (cur ? "P1" : "P0")) + (size_t)sc * B.nnodes, a.data(),
-                     B.nnodes * sizeof(Real), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(dptr<Real>(s, pf + (s->prec == 32 ? "X" : (cur ? "P0" : "P1"))) + (size_t)sc * B.nnodes,
-                     b.data(), B.nnodes * sizeof(Real), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dptr<Real>(s, pf + (cur ? "P1" : "P0")) + (size_t)sc * B.pnodes, a.data(),
+                     B.pnodes * sizeof(Real), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dptr<Real>(s, pf + (s->prec == 32 ? "X" : (cur ? "P0" : "P1"))) + (size_t)sc * B.pnodes,
+                     b.data(), B.pnodes * sizeof(Real), hipMemcpyHostToDevice));
     o += B.nnodes;
   }
   if (s->Np > 0) {
@@ -881,7 +913,7 @@ pmdg_status pmdg_set_pmuts(pmdg_solver* s, int Np, const double* ctr, const doub
           const long f = i + (long)B.nn[0] * j;
           if (owner[f] >= 0) return fail(PMDG_EINVAL, "PMUT discs overlap");
           owner[f] = k;
-          s->pm_node.push_back((int)f);
+          s->pm_node.push_back(i + B.px * j);  // device (padded) face index
           // face quadrature weight: product of the assembled 1D lumped masses
           s->pm_wf.push_back(B.mass1[0][i] * B.mass1[1][j]);
         }
@@ -904,8 +936,8 @@ pmdg_status pmdg_pmut_face_nodes(pmdg_solver* s, int k, int* n, double* xyz) {
     const Brick& B = s->b[0];
     for (int m = 0; m < cnt; ++m) {
       const int f = s->pm_node[o + m];
-      xyz[3 * m] = B.coord(0, f % B.nn[0]);
-      xyz[3 * m + 1] = B.coord(1, f / B.nn[0]);
+      xyz[3 * m] = B.coord(0, f % B.px);
+      xyz[3 * m + 1] = B.coord(1, f / B.px);
       xyz[3 * m + 2] = B.x0[2];
     }
   }
@@ -925,7 +957,7 @@ pmdg_status pmdg_set_pmut_shape(pmdg_solver* s, int k, const double* shape) {
       const double bv = s->pm_wf[o + n] * shape[(size_t)m * cnt + n];
       s->pm_B[(size_t)(o + n) * Nm + m] = bv;
       const int f = s->pm_node[o + n];
-      const double M = B.mass1[0][f % B.nn[0]] * B.mass1[1][f / B.nn[0]] * B.mass1[2][0];
+      const double M = B.mass1[0][f % B.px] * B.mass1[1][f / B.px] * B.mass1[2][0];
       X += bv * bv / M;
     }
     X *= kappa * s->dt * s->dt;
@@ -953,9 +985,10 @@ pmdg_status pmdg_set_drive(pmdg_solver* s, const double* amp, const double* phas
   if (s->bound && s->Np > 0) {
     hipStream_t st = nullptr;
     pmdg_status r;
-    if ((r = upload_vec(s, "amp", s->amp, st))) return r;
-    if ((r = upload_vec(s, "phase", s->phase, st))) return r;
-    if ((r = upload_vec(s, "freq", s->freq, st))) return r;
+    std::vector<double> dA, car;
+    drive_tables(s, dA, car);
+    if ((r = upload_vec(s, "dA", dA, st))) return r;
+    if ((r = upload_vec(s, "car", car, st))) return r;
   }
   return PMDG_OK;
 }
@@ -995,7 +1028,7 @@ pmdg_status pmdg_set_receivers(pmdg_solver* s, int R, const double* xyz) {
       if (!in) continue;
       ok = true;
       s->r_dom[r] = d;
-      s->r_base[r] = (long)B.N * e[0] + (long)B.nn[0] * B.N * e[1] + B.plane * B.N * e[2];
+      s->r_base[r] = (long)B.N * e[0] + (long)B.px * B.N * e[1] + B.pplane * B.N * e[2];
       for (int a = 0; a < 3; ++a) {
         ld v[kMaxOrder + 1];
         bary_eval(B.rule, xi[a], v);
@@ -1035,9 +1068,10 @@ pmdg_status pmdg_bind(pmdg_solver* s, void* dev_ptr, size_t bytes, void* stream)
     if ((r = upload_vec(s, "omega", s->omega, st))) return r;
     if ((r = upload_vec(s, "zeta", s->zeta, st))) return r;
     if ((r = upload_vec(s, "eta", s->eta, st))) return r;
-    if ((r = upload_vec(s, "amp", s->amp, st))) return r;
-    if ((r = upload_vec(s, "phase", s->phase, st))) return r;
-    if ((r = upload_vec(s, "freq", s->freq, st))) return r;
+    std::vector<double> dA, car;
+    drive_tables(s, dA, car);
+    if ((r = upload_vec(s, "dA", dA, st))) return r;
+    if ((r = upload_vec(s, "car", car, st))) return r;
   }
   if (s->R > 0) {
     if ((r = upload_vec(s, "r_dom", s->r_dom, st))) return r;
@@ -1083,9 +1117,7 @@ pmdg_status pmdg_set_option(pmdg_solver* s, int option, long value) {
   switch (option) {
     case PMDG_OPT_GRAPH: s->use_graph = value ? 1 : 0; break;
     case PMDG_OPT_TILE_ROWS:
-      if (!(value == 1 || value == 2 || value == 4))
-        return fail(PMDG_EINVAL, "tile rows must be 1, 2 or 4");
-      if (value == 4 && s->waves == 8 && s->prec == 64) return fail(PMDG_EINVAL, "8 waves x 4 rows is FP32 only");
+      if (!(value == 1 || value == 2 || value == 4)) return fail(PMDG_EINVAL, "tile rows per wave must be 1, 2 or 4");
       s->rows = (int)value;
       break;
     case PMDG_OPT_TILE_ZCHUNK:
@@ -1097,11 +1129,6 @@ pmdg_status pmdg_set_option(pmdg_solver* s, int option, long value) {
       s->graph_chunk = (int)value;
       break;
     case PMDG_OPT_TIMING: s->timing = value ? 1 : 0; break;
-    case PMDG_OPT_TILE_WAVES:
-      if (!(value == 4 || value == 8)) return fail(PMDG_EINVAL, "waves per stiffness workgroup must be 4 or 8");
-      if (value == 8 && s->rows == 4 && s->prec == 64) return fail(PMDG_EINVAL, "8 waves x 4 rows is FP32 only");
-      s->waves = (int)value;
-      break;
     default: return fail(PMDG_EINVAL, "unknown option");
   }
   drop_graphs(s);
@@ -1112,11 +1139,11 @@ pmdg_status pmdg_step(pmdg_solver* s, int n, void* stream) {
   if (!s) return fail(PMDG_EINVAL, "NULL solver");
   if (!s->bound) return fail(PMDG_ESTATE, "bind before stepping");
   if (n < 0) return fail(PMDG_EINVAL, "n must be >= 0");
-  if (s->R > 0 && s->steps_done + n > s->cap) return fail(PMDG_ESTATE, "trace capacity exceeded");
+  if (s->steps_done + n > s->cap) return fail(PMDG_ESTATE, "trace capacity (maximum step count) exceeded");
   if (n == 0) return PMDG_OK;
   hipStream_t st = (hipStream_t)stream;
   if (s->timing) {
-    const int per = 2 * (s->ndom + 1 + (s->ndom > 1 ? 1 : 0));
+    const int per = 2 * (s->ndom + 2);
     std::vector<hipEvent_t> ev((size_t)n * per);
     for (auto& e : ev) HIPCHK(hipEventCreate(&e));
     for (int i = 0; i < n; ++i) {
@@ -1137,10 +1164,8 @@ pmdg_status pmdg_step(pmdg_solver* s, int n, void* stream) {
       HIPCHK(hipEventElapsedTime(&ms, e[k], e[k + 1]));
       tot[1] += ms;
       k += 2;
-      if (s->ndom > 1) {
-        HIPCHK(hipEventElapsedTime(&ms, e[k], e[k + 1]));
-        tot[2] += ms;
-      }
+      HIPCHK(hipEventElapsedTime(&ms, e[k], e[k + 1]));
+      tot[2] += ms;
     }
     for (auto& e : ev) (void)hipEventDestroy(e);
     for (int c = 0; c < 3; ++c) s->ktimes[c] = tot[c] / n;

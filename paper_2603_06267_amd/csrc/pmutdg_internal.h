@@ -11,20 +11,18 @@ namespace pmdg {
 constexpr int kMaxOrder = 8;                // polynomial order N <= 8
 constexpr int kMaxNq = kMaxOrder + 1;       // Gauss points per direction on Gamma_I
 constexpr int kMaxModes = 16;               // modes per PMUT
-constexpr int kTileX = 64;                  // stiffness tile width = one wavefront
-constexpr int kWaves = 4;                   // waves per stiffness workgroup
+constexpr int kWaves = 4;                   // waves per workgroup
 
 // Field arrays and operator tables of one brick, as seen by the kernels.
 template <typename Real>
 struct DomView {
   int nn[3];          // nodes per axis
   int N;              // order
-  long plane;         // nn[0] * nn[1]
-  long nnodes;        // nn[0] * nn[1] * nn[2]
+  int px;             // padded row pitch (nn[0] rounded up to a multiple of 64)
+  long plane;         // px * nn[1]  (device plane stride)
+  long nnodes;        // plane * nn[2] (device nodes per scenario)
   Real* P[2];         // [S][nnodes] pressure, double-buffered by step parity
   Real* X;            // [S][nnodes] increment p^n - p^{n-1} (increment form only)
-  const Real* tap[3]; // [nn_axis][2N] off-centre taps of -dt^2 c^2 M_d^{-1} K_d
-  const Real* minv[3];// [nn_axis] inverse assembled 1D lumped mass
 };
 
 // Stiffness + update kernel arguments (one brick).
@@ -43,14 +41,11 @@ struct StiffArgs {
   Real iface_d[kMaxOrder + 1]; // c^2 (2/h_z) l_c'(+-1)
   // operator rows by node class along each axis: class a < N is an
   // interior node with i mod N = a, class N the first and N+1 the last node
-  // of the line.  y and z rows live in the kernel arguments (scalar loads).
-  const Real* xtap;                           // [N+2][2N]
-  const Real* xmin;                           // [N+2]
-  Real ytap[kMaxOrder + 3][2 * kMaxOrder];   // class N+2: zero row (outside the brick)
-  Real ztap[kMaxOrder + 2][2 * kMaxOrder];
-  Real ymin[kMaxOrder + 3], zmin[kMaxOrder + 2];
+  // of the line, class N+2 an all-zero row (outside the brick).
+  const Real* taps;         // [3][N+3][2N]: -dt^2 c^2 (M_d^{-1} K_d) off-centre entries
+  const Real* mins;         // [3][N+3]: inverse assembled 1D lumped mass
   // tiling
-  int nbx, nby, nbz, zchunk;
+  int nbx, nby, nbz, zchunk, rows;
   int nblocks;
 };
 
@@ -58,8 +53,7 @@ struct StiffArgs {
 // value / normal-derivative traces of both bricks on Gamma_I.
 template <typename Real>
 struct FaceArgs {
-  long* counter;
-  unsigned* done;
+  const long* counter;
   int* nonfinite;           // watchdog: set when a sampled pressure is not finite
   int nblocks;
   int prime;                // 1: only traces and force from the stored qddot
@@ -81,11 +75,9 @@ struct FaceArgs {
   const double* zeta;
   const double* eta;
   double kappa;
-  const double* amp;        // [S*Np]
-  const double* phase;      // [S*Np]
-  const double* freq;       // [S]
-  double ncyc;
-  int envelope;
+  const double* dA;         // [S*Np][2]: A cos(theta), A sin(theta)
+  const double* car;        // [S][ncar][2]: g(t_n) sin(2 pi f t_n), g(t_n) cos(2 pi f t_n)
+  long ncar;
   double t_switch, cap;
   double* q;                // [S*Np*Nm]
   double* qd;
@@ -125,12 +117,15 @@ struct FluxArgs {
   Real gamma, cf2, cc2;
   Real* R0;                 // [S][nex0*ney0][(N0+1)^2][2]
   Real* R1;                 // [S][nex1*ney1][(N1+1)^2][2]
+  Real* Aq;                 // [S][nex0*ney0][Nq*Nq][2] SIPG terms per fine Gauss point
+  long* counter;            // advanced by the coarse pass when tick != 0
+  int tick;
   int nb_fine, nb_coarse;   // blocks (4 faces each)
 };
 
 // Launchers (defined in pmutdg_kernels.hip).
 template <typename Real>
-hipError_t launch_stiff(const StiffArgs<Real>& a, int rows_per_wave, int waves, bool incr, hipStream_t st);
+hipError_t launch_stiff(const StiffArgs<Real>& a, bool incr, hipStream_t st);
 template <typename Real>
 hipError_t launch_face(const FaceArgs<Real>& a, hipStream_t st);
 template <typename Real>
@@ -138,5 +133,6 @@ hipError_t launch_flux(const FluxArgs<Real>& a, hipStream_t st);
 template <typename Real>
 hipError_t launch_fill(Real* p, long n, Real v, hipStream_t st);
 hipError_t launch_fill_bytes(void* p, size_t n, hipStream_t st);
+hipError_t launch_tick(long* counter, hipStream_t st);
 
 }  // namespace pmdg

@@ -32,45 +32,28 @@ namespace pmdg {
 // ------------------------------------------------------------------------
 // Face kernel.
 // ------------------------------------------------------------------------
-__device__ __forceinline__ double window_g(double t, double Td) {
-  // smooth window of Sec. 6.1 (eq. voltage), exponent n = 10, written in the
-  // symmetric variable b = |2t/T_d - 1|
-  if (t < 0.0 || t > Td) return 0.0;
-  const double b = fabs(2.0 * t / Td - 1.0);
-  const double b2 = b * b, b4 = b2 * b2, b5 = b4 * b, b10 = b5 * b5, b20 = b10 * b10;
-  const double base = 1.0 - 2.0 * b20 * b / (1.0 + b20);
-  if (base <= 0.0) return 0.0;
-  return exp(1.0 - 1.0 / (base * base));
-}
-
-__device__ __forceinline__ double drive_phi(double A, double th, double f, double ncyc, int env, double t) {
-  const double Td = ncyc / f;
-  double e;
-  if (env == 0) e = window_g(t, Td);
-  else if (env == 1) e = (t >= 0.0 && t <= Td) ? 1.0 : 0.0;
-  else e = (t >= 0.0) ? 1.0 : 0.0;
-  return A * sin(2.0 * M_PI * f * t - th) * e;
-}
-
 template <typename Real>
 __device__ void face_traces(const FaceArgs<Real>& a, int side, int item, int buf) {
+  // item runs over the compact face grid nn[0] x nn[1] of every scenario
   const DomView<Real>& D = side == 0 ? a.d0 : a.d1;
-  const long nf = D.plane;
+  const long nf = (long)D.nn[0] * D.nn[1];
   if (item >= (long)a.S * nf) return;
   const int s = item / nf;
   const long f = item - (long)s * nf;
+  const long j = f / D.nn[0], i = f - j * D.nn[0];
+  const long g = i + (long)D.px * j;  // device index within a plane
   const Real* P = D.P[buf] + (long)s * D.nnodes;
   const int N = D.N;
   Real val, der = 0;
   if (side == 0) {
     const int top = D.nn[2] - 1;
-    val = P[f + D.plane * top];
-    for (int c = 0; c <= N; ++c) der += a.dz0[c] * P[f + D.plane * (top - N + c)];
+    val = P[g + D.plane * top];
+    for (int c = 0; c <= N; ++c) der += a.dz0[c] * P[g + D.plane * (top - N + c)];
     a.tr0[((long)s * nf + f) * 2] = val;
     a.tr0[((long)s * nf + f) * 2 + 1] = der;
   } else {
-    val = P[f];
-    for (int c = 0; c <= N; ++c) der += a.dz1[c] * P[f + D.plane * c];
+    val = P[g];
+    for (int c = 0; c <= N; ++c) der += a.dz1[c] * P[g + D.plane * c];
     a.tr1[((long)s * nf + f) * 2] = val;
     a.tr1[((long)s * nf + f) * 2 + 1] = der;
   }
@@ -133,8 +116,10 @@ __global__ void __launch_bounds__(256) k_face(const FaceArgs<Real> a) {
           for (int m = 0; m < Nm; ++m) phi += a.eta[(long)k * Nm + m] * qp_s[m];
           phi /= a.cap;
         } else {
-          phi = drive_phi(a.amp[(long)s * a.Np + k], a.phase[(long)s * a.Np + k], a.freq[s], a.ncyc,
-                          a.envelope, t);
+          // A g(t) sin(2 pi f t - theta) = (A cos theta) g sin(2 pi f t) - (A sin theta) g cos(2 pi f t)
+          const double* c2 = a.car + ((long)s * a.ncar + min(lev, a.ncar - 1)) * 2;
+          const double* d2 = a.dA + ((long)s * a.Np + k) * 2;
+          phi = d2[0] * c2[0] - d2[1] * c2[1];
         }
         phi_s = phi;
       }
@@ -153,7 +138,7 @@ __global__ void __launch_bounds__(256) k_face(const FaceArgs<Real> a) {
       if (tid < Nm) qdd_s[tid] = a.qdd[qo + tid];
     }
     __syncthreads();
-    Real* F = a.force + (long)s * a.d0.plane;
+    Real* F = a.force + (long)s * a.d0.plane;  // padded bottom plane
     for (int n = n0 + tid; n < n1; n += 256) {
       const double* B = a.pm_B + (long)n * Nm;
       double f = 0.0;
@@ -174,7 +159,7 @@ __global__ void __launch_bounds__(256) k_face(const FaceArgs<Real> a) {
       for (int idx = lane; idx < n1 * n1 * n1; idx += 64) {
         const int i = idx % n1, j = (idx / n1) % n1, c = idx / (n1 * n1);
         acc += w[i] * w[kMaxOrder + 1 + j] * w[2 * (kMaxOrder + 1) + c] *
-               (double)Pd[base + i + (long)D.nn[0] * j + D.plane * c];
+               (double)Pd[base + i + (long)D.px * j + D.plane * c];
       }
       acc = wave_sum(acc);
       if (lane == 0 && cnt < a.tcap) a.traces[((long)s * a.R + r) * a.tcap + cnt] = acc;
@@ -182,127 +167,188 @@ __global__ void __launch_bounds__(256) k_face(const FaceArgs<Real> a) {
     }
   }
 
-  if (!a.prime) {
-    __syncthreads();
-    if (tid == 0) {
-      __threadfence();
-      const unsigned prev = atomicAdd(a.done, 1u);
-      if (prev == (unsigned)a.nblocks - 1u) {
-        // every block has read the counter: advance the step
-        atomicExch(a.done, 0u);
-        atomicAdd((unsigned long long*)a.counter, 1ull);
-        __threadfence();
-      }
-    }
-  }
+
 }
 
 // ------------------------------------------------------------------------
-// Interface flux.
+// Interface flux, in two passes over Gamma_I.
+//   k_flux_fine: one wave per fine face.  The face's value / normal-derivative
+//     traces are staged in LDS and interpolated to its Nq x Nq Gauss points by
+//     two 1D contractions; the coarse traces are interpolated the same way
+//     (x first, over the at most 2 N1 + 1 coarse node rows the face touches,
+//     then y).  At each point the SIPG integrand gives
+//       A_q = w J (gamma [p] - {c^2 d_n p}),  B_q = -w J [p] / 2,
+//     stored for the coarse pass and reduced onto the fine face's nodes.
+//   k_flux_coarse: one wave per coarse face: reduces the A_q, B_q of the
+//     points mapped into it onto its nodes (two 1D contractions), and, in the
+//     last launch of a step, advances the step counter.
 // ------------------------------------------------------------------------
 template <typename Real>
-__device__ __forceinline__ void flux_point(const FluxArgs<Real>& a, int s, int ex, int ey, int qa, int qb,
-                                           Real& A, Real& B) {
-  const int N0 = a.N0, N1 = a.N1, n0 = N0 + 1, n1 = N1 + 1, Nq = a.Nq;
+__global__ void __launch_bounds__(256) k_flux_fine(const FluxArgs<Real> a) {
+  constexpr int MQ = kMaxNq - 1;  // Nq <= 8 on Gamma_I (orders <= 7)
+  __shared__ Real sT[kWaves][2][64];
+  __shared__ Real sR[kWaves][2][MQ * 8];
+  __shared__ Real sC[kWaves][2][MQ * 16];
+  __shared__ Real sA[kWaves][2][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int Nq = a.Nq, N0 = a.N0, N1 = a.N1, n0 = N0 + 1, n1 = N1 + 1;
+  const int nfine = a.nex0 * a.ney0;
+  const int item = blockIdx.x * kWaves + w;
+  const bool valid = item < a.S * nfine;
+  const int s = valid ? item / nfine : 0, f = valid ? item - s * nfine : 0;
+  const int ex = f % a.nex0, ey = f / a.nex0;
   const long nf0 = (long)a.nn0x * (a.ney0 * N0 + 1), nf1 = (long)a.nn1x * (a.ney1 * N1 + 1);
   const Real* T0 = a.tr0 + (long)s * nf0 * 2;
   const Real* T1 = a.tr1 + (long)s * nf1 * 2;
-  Real pP = 0, dP = 0, pM = 0, dM = 0;
-  for (int bb = 0; bb < n0; ++bb) {
-    const Real lb = a.Lq[qb * n0 + bb];
-    const long row = (long)a.nn0x * (N0 * ey + bb) + N0 * ex;
+  // coarse node rows touched by this face
+  int cy_lo = 1 << 30, cy_hi = -1;
+  for (int qb = 0; qb < Nq; ++qb) {
+    const int c = a.ycx[ey * Nq + qb];
+    cy_lo = min(cy_lo, c);
+    cy_hi = max(cy_hi, c);
+  }
+  const int ry0 = N1 * cy_lo, nrow = N1 * (cy_hi - cy_lo) + n1;
+  // (1) fine traces into LDS; coarse traces contracted along x
+  if (valid && lane < n0 * n0) {
+    const long node = (long)(N0 * ex + lane % n0) + (long)a.nn0x * (N0 * ey + lane / n0);
+    sT[w][0][lane] = T0[node * 2];
+    sT[w][1][lane] = T0[node * 2 + 1];
+  }
+  for (int l = lane; l < Nq * nrow; l += 64) {
+    const int qa = l % Nq, row = ry0 + l / Nq;
+    const int cx = a.xcx[ex * Nq + qa];
+    const Real* wx = a.xw + (long)(ex * Nq + qa) * n1;
+    Real cv = 0, cd = 0;
+    if (valid)
+      for (int aa = 0; aa < n1; ++aa) {
+        const long node = (long)(N1 * cx + aa) + (long)a.nn1x * row;
+        cv += wx[aa] * T1[node * 2];
+        cd += wx[aa] * T1[node * 2 + 1];
+      }
+    sC[w][0][l] = cv;
+    sC[w][1][l] = cd;
+  }
+  __syncthreads();
+  // (2) fine traces contracted along x: sR[qa + Nq b]
+  if (lane < Nq * n0) {
+    const int qa = lane % Nq, b = lane / Nq;
+    Real rv = 0, rd = 0;
     for (int aa = 0; aa < n0; ++aa) {
-      const Real w = a.Lq[qa * n0 + aa] * lb;
-      pP += w * T0[(row + aa) * 2];
-      dP += w * T0[(row + aa) * 2 + 1];
+      const Real l = a.Lq[qa * n0 + aa];
+      rv += l * sT[w][0][aa + n0 * b];
+      rd += l * sT[w][1][aa + n0 * b];
+    }
+    sR[w][0][lane] = rv;
+    sR[w][1][lane] = rd;
+  }
+  __syncthreads();
+  // (3) SIPG integrand at the Gauss points
+  if (lane < Nq * Nq) {
+    const int qa = lane % Nq, qb = lane / Nq;
+    Real pP = 0, dP = 0, pM = 0, dM = 0;
+    for (int b = 0; b < n0; ++b) {
+      const Real l = a.Lq[qb * n0 + b];
+      pP += l * sR[w][0][qa + Nq * b];
+      dP += l * sR[w][1][qa + Nq * b];
+    }
+    const int cy = a.ycx[ey * Nq + qb];
+    const Real* wy = a.yw + (long)(ey * Nq + qb) * n1;
+    for (int b = 0; b < n1; ++b) {
+      const int li = qa + Nq * (N1 * cy + b - ry0);
+      pM += wy[b] * sC[w][0][li];
+      dM += wy[b] * sC[w][1][li];
+    }
+    const Real jump = pP - pM;
+    const Real avg = Real(0.5) * (a.cf2 * dP + a.cc2 * dM);
+    const Real wj = a.wJ[qb * Nq + qa];
+    const Real A = wj * (a.gamma * jump - avg), B = Real(-0.5) * wj * jump;
+    sA[w][0][lane] = A;
+    sA[w][1][lane] = B;
+    if (valid) {
+      Real* o = a.Aq + (((long)s * nfine + f) * Nq * Nq + lane) * 2;
+      o[0] = A;
+      o[1] = B;
     }
   }
-  const int cx = a.xcx[ex * Nq + qa], cy = a.ycx[ey * Nq + qb];
-  const Real* wx = a.xw + (long)(ex * Nq + qa) * n1;
-  const Real* wy = a.yw + (long)(ey * Nq + qb) * n1;
-  for (int bb = 0; bb < n1; ++bb) {
-    const long row = (long)a.nn1x * (N1 * cy + bb) + N1 * cx;
-    for (int aa = 0; aa < n1; ++aa) {
-      const Real w = wx[aa] * wy[bb];
-      pM += w * T1[(row + aa) * 2];
-      dM += w * T1[(row + aa) * 2 + 1];
+  __syncthreads();
+  // (4) reduce onto the fine nodes: contract along qb, then along qa
+  if (lane < Nq * n0) {
+    const int qa = lane % Nq, b = lane / Nq;
+    Real ta = 0, tb = 0;
+    for (int qb = 0; qb < Nq; ++qb) {
+      const Real l = a.Lq[qb * n0 + b];
+      ta += l * sA[w][0][qa + Nq * qb];
+      tb += l * sA[w][1][qa + Nq * qb];
     }
+    sR[w][0][lane] = ta;
+    sR[w][1][lane] = tb;
   }
-  const Real jump = pP - pM;
-  const Real avg = Real(0.5) * (a.cf2 * dP + a.cc2 * dM);
-  const Real wj = a.wJ[qb * Nq + qa];
-  A = wj * (a.gamma * jump - avg);
-  B = Real(-0.5) * wj * jump;
+  __syncthreads();
+  if (valid && lane < n0 * n0) {
+    const int aa = lane % n0, b = lane / n0;
+    Real RA = 0, RB = 0;
+    for (int qa = 0; qa < Nq; ++qa) {
+      const Real l = a.Lq[qa * n0 + aa];
+      RA += l * sR[w][0][qa + Nq * b];
+      RB += l * sR[w][1][qa + Nq * b];
+    }
+    Real* R = a.R0 + (((long)s * nfine + f) * n0 * n0 + lane) * 2;
+    R[0] = RA;
+    R[1] = RB;
+  }
 }
 
 template <typename Real>
-__global__ void __launch_bounds__(256) k_flux(const FluxArgs<Real> a) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int Nq = a.Nq;
-  int b = blockIdx.x;
-  if (b < a.nb_fine) {
-    const int nfine = a.nex0 * a.ney0;
-    const int item = b * kWaves + wave;
-    if (item >= a.S * nfine) return;
-    const int s = item / nfine, f = item - s * nfine;
-    const int ex = f % a.nex0, ey = f / a.nex0;
-    Real A = 0, B = 0;
-    if (lane < Nq * Nq) flux_point(a, s, ex, ey, lane % Nq, lane / Nq, A, B);
-    const int n0 = a.N0 + 1;
-    Real RA = 0, RB = 0;
-    const int aa = lane % n0, bb = lane / n0;
-    for (int qq = 0; qq < Nq * Nq; ++qq) {
-      const Real Aq = __shfl(A, qq, 64), Bq = __shfl(B, qq, 64);
-      if (lane < n0 * n0) {
-        const Real w = a.Lq[(qq % Nq) * n0 + aa] * a.Lq[(qq / Nq) * n0 + bb];
-        RA += w * Aq;
-        RB += w * Bq;
+__global__ void __launch_bounds__(256) k_flux_coarse(const FluxArgs<Real> a) {
+  constexpr int ML = 64;  // fine Gauss points per coarse element along one axis
+  __shared__ Real sT[kWaves][2][ML * 8];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int Nq = a.Nq, N1 = a.N1, n1 = N1 + 1;
+  const int nfine = a.nex0 * a.ney0, ncoarse = a.nex1 * a.ney1;
+  const int item = blockIdx.x * kWaves + w;
+  const bool valid = item < a.S * ncoarse;
+  const int s = valid ? item / ncoarse : 0, f = valid ? item - s * ncoarse : 0;
+  const int cx = f % a.nex1, cy = f / a.nex1;
+  const int xo0 = a.xl_off[cx], nxl = a.xl_off[cx + 1] - xo0;
+  const int yo0 = a.yl_off[cy], nyl = a.yl_off[cy + 1] - yo0;
+  // (1) contract along y: sT[ix + ML b] = sum_iy wy(iy)[b] A(ix, iy)
+  for (int l = lane; l < nxl * n1; l += 64) {
+    const int ix = l % nxl, b = l / nxl;
+    const int ex_qa = a.xl[xo0 + ix];
+    const int ex = ex_qa / Nq, qa = ex_qa % Nq;
+    Real ta = 0, tb = 0;
+    if (valid)
+      for (int iy = 0; iy < nyl; ++iy) {
+        const int ey_qb = a.yl[yo0 + iy];
+        const int ey = ey_qb / Nq, qb = ey_qb % Nq;
+        const Real wy = a.yw[(long)ey_qb * n1 + b];
+        const Real* A = a.Aq + (((long)s * nfine + ex + (long)a.nex0 * ey) * Nq * Nq + qa + Nq * qb) * 2;
+        ta += wy * A[0];
+        tb += wy * A[1];
       }
-    }
-    if (lane < n0 * n0) {
-      Real* R = a.R0 + (((long)s * nfine + f) * n0 * n0 + lane) * 2;
-      R[0] = RA;
-      R[1] = RB;
-    }
-  } else {
-    b -= a.nb_fine;
-    const int ncoarse = a.nex1 * a.ney1;
-    const int item = b * kWaves + wave;
-    if (item >= a.S * ncoarse) return;
-    const int s = item / ncoarse, f = item - s * ncoarse;
-    const int cx = f % a.nex1, cy = f / a.nex1;
-    const int xo0 = a.xl_off[cx], nxl = a.xl_off[cx + 1] - xo0;
-    const int yo0 = a.yl_off[cy], nyl = a.yl_off[cy + 1] - yo0;
-    const int nqc = nxl * nyl;
-    const int n1 = a.N1 + 1;
-    const int aa = lane % n1, bb = lane / n1;
-    Real RA = 0, RB = 0;
-    for (int base = 0; base < nqc; base += 64) {
-      Real A = 0, B = 0;
-      int px = 0, py = 0;
-      const int qi = base + lane;
-      if (qi < nqc) {
-        px = a.xl[xo0 + qi % nxl];
-        py = a.yl[yo0 + qi / nxl];
-        flux_point(a, s, px / Nq, py / Nq, px % Nq, py % Nq, A, B);
-      }
-      const int cntq = min(64, nqc - base);
-      for (int qq = 0; qq < cntq; ++qq) {
-        const Real Aq = __shfl(A, qq, 64), Bq = __shfl(B, qq, 64);
-        const int pxq = __shfl(px, qq, 64), pyq = __shfl(py, qq, 64);
-        if (lane < n1 * n1) {
-          const Real w = a.xw[(long)pxq * n1 + aa] * a.yw[(long)pyq * n1 + bb];
-          RA += w * Aq;
-          RB += w * Bq;
-        }
-      }
-    }
-    if (lane < n1 * n1) {
-      Real* R = a.R1 + (((long)s * ncoarse + f) * n1 * n1 + lane) * 2;
-      R[0] = RA;  // the stiffness kernel applies the coarse side's minus sign
-      R[1] = RB;
-    }
+    sT[w][0][ix + ML * b] = ta;
+    sT[w][1][ix + ML * b] = tb;
   }
+  __syncthreads();
+  // (2) contract along x onto the coarse face's nodes
+  if (valid && lane < n1 * n1) {
+    const int aa = lane % n1, b = lane / n1;
+    Real RA = 0, RB = 0;
+    for (int ix = 0; ix < nxl; ++ix) {
+      const Real wx = a.xw[(long)a.xl[xo0 + ix] * n1 + aa];
+      RA += wx * sT[w][0][ix + ML * b];
+      RB += wx * sT[w][1][ix + ML * b];
+    }
+    Real* R = a.R1 + (((long)s * ncoarse + f) * n1 * n1 + lane) * 2;
+    R[0] = RA;  // the stiffness kernel applies the coarse side's minus sign
+    R[1] = RB;
+  }
+  if (a.tick && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd((unsigned long long*)a.counter, 1ull);
+}
+
+// Advances the step counter when no interface pass ends the step.
+__global__ void k_tick(long* counter) {
+  if (threadIdx.x == 0) atomicAdd((unsigned long long*)counter, 1ull);
 }
 
 template <typename Real>
@@ -314,15 +360,15 @@ __global__ void k_fill(Real* p, long n, Real v) {
 // Launchers
 // ------------------------------------------------------------------------
 template <>
-hipError_t launch_stiff<float>(const StiffArgs<float>& a, int ry, int wv, bool incr, hipStream_t st) {
+hipError_t launch_stiff<float>(const StiffArgs<float>& a, bool incr, hipStream_t st) {
   if (!incr) return hipErrorInvalidValue;  // FP32 state always uses the increment form
-  return a.d.N <= 4 ? launch_stiff_f32_lo(a, ry, wv, st) : launch_stiff_f32_hi(a, ry, wv, st);
+  return a.d.N <= 4 ? launch_stiff_f32_lo(a, st) : launch_stiff_f32_hi(a, st);
 }
 
 template <>
-hipError_t launch_stiff<double>(const StiffArgs<double>& a, int ry, int wv, bool incr, hipStream_t st) {
+hipError_t launch_stiff<double>(const StiffArgs<double>& a, bool incr, hipStream_t st) {
   if (incr) return hipErrorInvalidValue;  // FP64 state uses the two-level form
-  return a.d.N <= 4 ? launch_stiff_f64_lo(a, ry, wv, st) : launch_stiff_f64_hi(a, ry, wv, st);
+  return a.d.N <= 4 ? launch_stiff_f64_lo(a, st) : launch_stiff_f64_hi(a, st);
 }
 
 template <typename Real>
@@ -333,9 +379,16 @@ hipError_t launch_face(const FaceArgs<Real>& a, hipStream_t st) {
 
 template <typename Real>
 hipError_t launch_flux(const FluxArgs<Real>& a, hipStream_t st) {
-  const int nb = a.nb_fine + a.nb_coarse;
-  if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_flux<Real>, dim3(nb), dim3(256), 0, st, a);
+  if (a.nb_fine == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_flux_fine<Real>, dim3(a.nb_fine), dim3(256), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_flux_coarse<Real>, dim3(a.nb_coarse), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_tick(long* counter, hipStream_t st) {
+  hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, st, counter);
   return hipGetLastError();
 }
 

@@ -3,12 +3,12 @@
 
 namespace pmdg {
 
-hipError_t launch_stiff_f32_hi(const StiffArgs<float>& a, int ry, int wv, hipStream_t st) {
+hipError_t launch_stiff_f32_hi(const StiffArgs<float>& a, hipStream_t st) {
   switch (a.d.N) {
-    case 5: return stiff_waves<float, 5, true>(a, ry, wv, st);
-    case 6: return stiff_waves<float, 6, true>(a, ry, wv, st);
-    case 7: return stiff_waves<float, 7, true>(a, ry, wv, st);
-    case 8: return stiff_waves<float, 8, true>(a, ry, wv, st);
+    case 5: return stiff_rows<float, 5, true>(a, st);
+    case 6: return stiff_rows<float, 6, true>(a, st);
+    case 7: return stiff_rows<float, 7, true>(a, st);
+    case 8: return stiff_rows<float, 8, true>(a, st);
     default: return hipErrorInvalidValue;
   }
 }

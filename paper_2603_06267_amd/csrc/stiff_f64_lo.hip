@@ -3,12 +3,12 @@
 
 namespace pmdg {
 
-hipError_t launch_stiff_f64_lo(const StiffArgs<double>& a, int ry, int wv, hipStream_t st) {
+hipError_t launch_stiff_f64_lo(const StiffArgs<double>& a, hipStream_t st) {
   switch (a.d.N) {
-    case 1: return stiff_waves<double, 1, false>(a, ry, wv, st);
-    case 2: return stiff_waves<double, 2, false>(a, ry, wv, st);
-    case 3: return stiff_waves<double, 3, false>(a, ry, wv, st);
-    case 4: return stiff_waves<double, 4, false>(a, ry, wv, st);
+    case 1: return stiff_rows<double, 1, false>(a, st);
+    case 2: return stiff_rows<double, 2, false>(a, st);
+    case 3: return stiff_rows<double, 3, false>(a, st);
+    case 4: return stiff_rows<double, 4, false>(a, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -45,12 +45,15 @@ __device__ __forceinline__ T wave_sum(T v) {
 
 // ------------------------------------------------------------------------
 // Stiffness + update: 2.5D tiles (64 x TY nodes in x-y) marching along z.
-// The z line lives in a register queue of 2N+1 planes per owned node (its
-// rotation is unrolled so that no register moves are needed); the x and y
-// lines are read from a double-buffered LDS copy of the current plane with an
-// N-node halo.  Everything the next plane needs (lead plane, halos, the
-// increment or previous level) is fetched one plane ahead so that memory
-// latency overlaps the arithmetic, with one barrier per plane.
+// Rows are padded to a multiple of 64 nodes, so each wave's row segment is a
+// cache-line aligned 64-lane access.  The z line lives in a register queue
+// of 2N+1 planes per owned node (its rotation is unrolled so that no register
+// moves are needed); the x and y lines are read from a double-buffered LDS
+// copy of the current plane with an N-node halo.  Everything the next plane
+// needs (lead plane, halos, the increment or previous level) is fetched one
+// plane ahead so that memory latency overlaps the arithmetic, with one
+// barrier per plane.  Operator rows come by node class (x per lane, y per
+// wave row, z per plane, all uniform where the class is).
 // Increment form (FP32): X holds p^n - p^{n-1}, X += a, p^{n+1} = p^n + X.
 // Two-level form (FP64): p^{n+1} = p^n + (p^n - p^{n-1}) + a over p^{n-1}.
 // ------------------------------------------------------------------------
@@ -61,7 +64,7 @@ __device__ __forceinline__ int node_class(int i, int n) {
 
 template <typename Real, int N, bool INCR, int RY, int WV>
 __global__ void __launch_bounds__(64 * WV) k_stiff(const StiffArgs<Real> a) {
-  constexpr int TX = kTileX, TY = WV * RY, W = TX + 2 * N, H = TY + 2 * N, NT = 2 * N, NQ = NT + 1;
+  constexpr int TX = 64, TY = WV * RY, W = TX + 2 * N, H = TY + 2 * N, NT = 2 * N, NQ = NT + 1;
   constexpr int HYR = (NT + WV - 1) / WV;              // y-halo rows per wave
   constexpr int NXH = (TY * NT + 64 * WV - 1) / (64 * WV);  // x-halo loads per thread
   __shared__ Real tile[2][H * W];
@@ -85,28 +88,39 @@ __global__ void __launch_bounds__(64 * WV) k_stiff(const StiffArgs<Real> a) {
 
   // Every load below is unconditional on a clamped address and masked
   // afterwards, so no load needs its own branch.
+  constexpr int NC = N + 3;
+  const Real* __restrict__ TP = a.taps;
+  const Real* __restrict__ MI = a.mins;
+  const unsigned px = (unsigned)a.d.px;
+  // rows are padded to a multiple of 64 nodes: every lane's x is inside the row
   const int x = bx * TX + lane;
   const bool xin = x < nx;
-  const int xc_ = min(x, nx - 1);
   const int ybase = by * TY + wave * RY;
 
   Real tx[NT];
-  const int cxl = node_class<N>(xc_, nx);
+  const int cxl = xin ? node_class<N>(x, nx) : N + 2;  // class N+2: all-zero row
 #pragma unroll
-  for (int i = 0; i < NT; ++i) {
-    const Real v = a.xtap[cxl * NT + i];
-    tx[i] = xin ? v : Real(0);
-  }
-  const Real mx = a.xmin[cxl];
+  for (int i = 0; i < NT; ++i) tx[i] = TP[cxl * NT + i];
+  const Real mx = MI[cxl];
   int cyr[RY];
   bool in[RY];
   unsigned roff[RY];
+  Real ty[RY][NT], my[RY];
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
     const int y = ybase + r;
-    cyr[r] = y < ny ? node_class<N>(y, ny) : N + 2;  // class N+2: all-zero row
+    cyr[r] = y < ny ? node_class<N>(y, ny) : N + 2;
     in[r] = xin && y < ny;
-    roff[r] = (unsigned)xc_ + (unsigned)nx * (unsigned)min(y, ny - 1);
+    roff[r] = (unsigned)x + px * (unsigned)min(y, ny - 1);
+#pragma unroll
+    for (int i = 0; i < NT; ++i) ty[r][i] = TP[(NC + cyr[r]) * NT + i];
+    my[r] = MI[NC + cyr[r]];
+  }
+  // z operator rows by class, staged in LDS (read with uniform addresses)
+  __shared__ Real ztab[(N + 2) * (NT + 1)];
+  for (int i = tid; i < (N + 2) * (NT + 1); i += 64 * WV) {
+    const int cls = i / (NT + 1), j = i % (NT + 1);
+    ztab[i] = j < NT ? TP[(2 * NC + cls) * NT + j] : MI[2 * NC + cls];
   }
   // x-halo slots of this thread: (row, column) pairs of the 2N x TY halo
   unsigned xh_off[NXH];
@@ -119,7 +133,7 @@ __global__ void __launch_bounds__(64 * WV) k_stiff(const StiffArgs<Real> a) {
     const int hx = hc < N ? (bx * TX - N + hc) : (bx * TX + TX + hc - N);
     const int y = by * TY + hrow;
     xh_ok[j] = e < TY * NT && hx >= 0 && hx < nx && y < ny;
-    xh_off[j] = (unsigned)min(max(hx, 0), nx - 1) + (unsigned)nx * (unsigned)min(y, ny - 1);
+    xh_off[j] = (unsigned)min(max(hx, 0), nx - 1) + px * (unsigned)min(y, ny - 1);
     xh_dst[j] = e < TY * NT ? ((N + hrow) * W + (hc < N ? hc : TX + hc)) : -1;
   }
   // y-halo rows of this wave
@@ -132,7 +146,7 @@ __global__ void __launch_bounds__(64 * WV) k_stiff(const StiffArgs<Real> a) {
     const int trow = hr < N ? hr : (TY + hr);
     const int y = by * TY - N + trow;
     yh_ok[j] = hr < NT && xin && y >= 0 && y < ny;
-    yh_off[j] = (unsigned)xc_ + (unsigned)nx * (unsigned)min(max(y, 0), ny - 1);
+    yh_off[j] = (unsigned)x + px * (unsigned)min(max(y, 0), ny - 1);
     yh_dst[j] = hr < NT ? trow * W + N + lane : -1;
   }
 
@@ -204,7 +218,8 @@ __global__ void __launch_bounds__(64 * WV) k_stiff(const StiffArgs<Real> a) {
 #pragma unroll
       for (int j = 0; j < RY + NT; ++j) col[j] = T[(wave * RY + j) * W + N + lane];
       const int cz = node_class<N>(k, nz);
-      const Real mz = a.zmin[cz];
+      const Real* tz = ztab + cz * (NT + 1);
+      const Real mz = tz[NT];
       const bool in_layer = (k >= lay0 && k <= lay1);
       const int cl = k - lay0;
       // (3) update the nodes of plane k
@@ -212,20 +227,19 @@ __global__ void __launch_bounds__(64 * WV) k_stiff(const StiffArgs<Real> a) {
       for (int r = 0; r < RY; ++r) {
         const int row = N + wave * RY + r;
         const Real p0 = q[r][(u + N) % NQ];
-        const Real* ty = a.ytap[cyr[r]];
-        const Real* tz = a.ztap[cz];
+
         Real acc = 0;
 #pragma unroll
         for (int i = 0; i < N; ++i) {
           acc += tx[i] * (T[row * W + lane + i] - p0);
           acc += tx[N + i] * (T[row * W + N + lane + 1 + i] - p0);
-          acc += ty[i] * (col[r + i] - p0);
-          acc += ty[N + i] * (col[r + N + 1 + i] - p0);
+          acc += ty[r][i] * (col[r + i] - p0);
+          acc += ty[r][N + i] * (col[r + N + 1 + i] - p0);
           acc += tz[i] * (q[r][(u + i) % NQ] - p0);
           acc += tz[N + i] * (q[r][(u + N + 1 + i) % NQ] - p0);
         }
         if (in[r]) {
-          const Real minv = mx * a.ymin[cyr[r]] * mz;
+          const Real minv = mx * my[r] * mz;
           if (a.force && k == 0) acc += a.dt2 * minv * a.force[(long)s * plane + roff[r]];
           if (in_layer) {
             // residual of the (up to 4) interface faces sharing (x, y)
@@ -287,31 +301,22 @@ __global__ void __launch_bounds__(64 * WV) k_stiff(const StiffArgs<Real> a) {
 }
 
 
-template <typename Real, int N, bool INCR, int WV>
-static hipError_t stiff_rows(const StiffArgs<Real>& a, int ry, hipStream_t st) {
-  dim3 g(a.nblocks), blk(64 * WV);
-  switch (ry) {
-    case 1: hipLaunchKernelGGL((k_stiff<Real, N, INCR, 1, WV>), g, blk, 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_stiff<Real, N, INCR, 2, WV>), g, blk, 0, st, a); break;
-    case 4:
-      if constexpr (WV == 4 || sizeof(Real) == 4) { hipLaunchKernelGGL((k_stiff<Real, N, INCR, 4, WV>), g, blk, 0, st, a); break; }
-      else return hipErrorInvalidValue;
+template <typename Real, int N, bool INCR>
+static hipError_t stiff_rows(const StiffArgs<Real>& a, hipStream_t st) {
+  dim3 g(a.nblocks), blk(64 * kWaves);
+  switch (a.rows) {
+    case 1: hipLaunchKernelGGL((k_stiff<Real, N, INCR, 1, kWaves>), g, blk, 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_stiff<Real, N, INCR, 2, kWaves>), g, blk, 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_stiff<Real, N, INCR, 4, kWaves>), g, blk, 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-template <typename Real, int N, bool INCR>
-static hipError_t stiff_waves(const StiffArgs<Real>& a, int ry, int wv, hipStream_t st) {
-  if (wv == 4) return stiff_rows<Real, N, INCR, 4>(a, ry, st);
-  if (wv == 8) return stiff_rows<Real, N, INCR, 8>(a, ry, st);
-  return hipErrorInvalidValue;
-}
-
 // Launchers for one precision and a range of orders (one per unit).
-hipError_t launch_stiff_f32_lo(const StiffArgs<float>& a, int ry, int wv, hipStream_t st);
-hipError_t launch_stiff_f32_hi(const StiffArgs<float>& a, int ry, int wv, hipStream_t st);
-hipError_t launch_stiff_f64_lo(const StiffArgs<double>& a, int ry, int wv, hipStream_t st);
-hipError_t launch_stiff_f64_hi(const StiffArgs<double>& a, int ry, int wv, hipStream_t st);
+hipError_t launch_stiff_f32_lo(const StiffArgs<float>& a, hipStream_t st);
+hipError_t launch_stiff_f32_hi(const StiffArgs<float>& a, hipStream_t st);
+hipError_t launch_stiff_f64_lo(const StiffArgs<double>& a, hipStream_t st);
+hipError_t launch_stiff_f64_hi(const StiffArgs<double>& a, hipStream_t st);
 
 }  // namespace pmdg

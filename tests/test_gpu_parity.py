@@ -90,15 +90,14 @@ def test_graph_replay_equals_direct_launches():
     assert np.array_equal(out[0], out[1])
 
 
-@pytest.mark.parametrize("rows,zchunk,waves", [(1, 0, 4), (4, 5, 4), (2, 3, 8), (4, 11, 8)])
-def test_tilings_agree(rows, zchunk, waves):
+@pytest.mark.parametrize("rows,zchunk", [(1, 0), (2, 5), (4, 3), (1, 11)])
+def test_tilings_agree(rows, zchunk):
     """Every tile shape gives the same arithmetic per node (bitwise)."""
     wl = W.small_two_domain(False, steps=80)
     sf = W.shape_fn(wl)
     ref_tr = None
-    for r, z, wv in ((2, 0, 4), (rows, zchunk, waves)):
+    for r, z in ((1, 17), (rows, zchunk)):
         g = solver.from_workload(wl, precision=32, shape_fn=sf, bind=False)
-        g.set_option(6, wv)
         g.set_option(2, r)
         g.set_option(3, z)
         g.bind()
