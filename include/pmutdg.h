@@ -181,6 +181,31 @@ pmdg_status pmdg_kernel_times(pmdg_solver* h, double* ms3);
 /* Frees host resources (device memory is the caller's).  NULL is a no-op. */
 void pmdg_destroy(pmdg_solver* h);
 
+/* ---- Batched form --------------------------------------------------------
+ * Several bound single-brick FP32 solvers (uneven meshes and orders, each
+ * with its own drive scenarios) stepped together: per time step one
+ * persistent stiffness launch over a device work list of (solver, tile)
+ * items, one persistent face launch (PMUT sampling / modal ODE / face force,
+ * receivers) and one launch advancing every solver's step counter, replayed
+ * as hipGraphs.  Each solver keeps its own state, traces and tile options
+ * (set them before pmdg_batch_create); read results through the solvers. */
+typedef struct pmdg_batch pmdg_batch;
+
+/* solvers[n]: bound, ndom == 1, precision 32, tile rows 1 or 2; the batch
+ * does not own them and they must outlive it.  EINVAL / ESTATE otherwise. */
+pmdg_status pmdg_batch_create(int n, pmdg_solver* const* solvers, pmdg_batch** out);
+/* Device bytes for the work lists and argument blocks. */
+pmdg_status pmdg_batch_workspace_size(pmdg_batch* b, size_t* bytes);
+/* Binds caller-owned device memory (256-byte aligned) and uploads the lists. */
+pmdg_status pmdg_batch_bind(pmdg_batch* b, void* dev_ptr, size_t bytes, void* stream);
+/* PMDG_OPT_GRAPH and PMDG_OPT_GRAPH_CHUNK as for a solver. */
+pmdg_status pmdg_batch_set_option(pmdg_batch* b, int option, long value);
+/* Enqueues n steps of every solver of the batch on stream (ESTATE if any
+ * solver's trace capacity would be exceeded). */
+pmdg_status pmdg_batch_step(pmdg_batch* b, int n, void* stream);
+/* NULL is a no-op. */
+void pmdg_batch_destroy(pmdg_batch* b);
+
 const char* pmdg_last_error(void);
 
 #ifdef __cplusplus

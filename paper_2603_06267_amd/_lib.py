@@ -111,4 +111,5 @@ def check(code):
 
 
 def declared_symbols():
-    return list(_SIGS) + ["pmdg_destroy", "pmdg_last_error"]
+    from . import _lib_ext
+    return list(_SIGS) + ["pmdg_destroy", "pmdg_last_error"] + _lib_ext.symbols()

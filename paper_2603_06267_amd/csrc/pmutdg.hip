@@ -1280,3 +1280,167 @@ void pmdg_destroy(pmdg_solver* s) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------------
+// Batched form: several bound single-brick solvers stepped together by
+// persistent launches over device work lists.
+// ------------------------------------------------------------------------
+struct pmdg_batch {
+  std::vector<pmdg_solver*> sv;
+  int nmax = 1;
+  size_t lds = 0;
+  int n_stiff = 0, n_face = 0, grid_stiff = 1, grid_face = 1;
+  char* ws = nullptr;
+  size_t off_sargs = 0, off_fargs = 0, off_sitems = 0, off_fitems = 0, off_ctr = 0, bytes = 0;
+  bool bound = false;
+  int use_graph = 1, graph_chunk = 64;
+  std::map<int, hipGraphExec_t> graphs;
+  hipStream_t cap_stream = nullptr;
+};
+
+static size_t al256(size_t x) { return (x + 255) / 256 * 256; }
+
+static void batch_layout(pmdg_batch* b) {
+  const size_t n = b->sv.size();
+  size_t o = 0;
+  b->off_sargs = o; o = al256(o + n * sizeof(StiffArgs<float>));
+  b->off_fargs = o; o = al256(o + n * sizeof(FaceArgs<float>));
+  b->off_sitems = o; o = al256(o + (size_t)b->n_stiff * sizeof(int2));
+  b->off_fitems = o; o = al256(o + (size_t)b->n_face * sizeof(int2));
+  b->off_ctr = o; o = al256(o + n * sizeof(long*));
+  b->bytes = o;
+}
+
+static pmdg_status batch_enqueue(pmdg_batch* b, hipStream_t st) {
+  HIPCHK(launch_stiff_batch((const StiffArgs<float>*)(b->ws + b->off_sargs), (const int2*)(b->ws + b->off_sitems),
+                            b->n_stiff, b->nmax, b->grid_stiff, b->lds, st));
+  HIPCHK(launch_face_batch((const FaceArgs<float>*)(b->ws + b->off_fargs), (const int2*)(b->ws + b->off_fitems),
+                           b->n_face, b->grid_face, st));
+  HIPCHK(launch_tick_batch((long* const*)(b->ws + b->off_ctr), (int)b->sv.size(), st));
+  return PMDG_OK;
+}
+
+extern "C" {
+
+pmdg_status pmdg_batch_create(int n, pmdg_solver* const* solvers, pmdg_batch** out) {
+  if (!out) return fail(PMDG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n < 1 || !solvers) return fail(PMDG_EINVAL, "need at least one solver");
+  pmdg_batch* b = new (std::nothrow) pmdg_batch();
+  if (!b) return fail(PMDG_ENOMEM, "out of host memory");
+  for (int i = 0; i < n; ++i) {
+    pmdg_solver* s = solvers[i];
+    if (!s || !s->bound) { delete b; return fail(PMDG_ESTATE, "every solver must be bound"); }
+    if (s->ndom != 1 || s->prec != 32) { delete b; return fail(PMDG_EINVAL, "batches take single-brick FP32 solvers"); }
+    if (s->rows != 1 && s->rows != 2) { delete b; return fail(PMDG_EINVAL, "batched tiles use 1 or 2 rows per wave"); }
+    b->sv.push_back(s);
+    b->nmax = std::max(b->nmax, s->b[0].N);
+    b->lds = std::max(b->lds, batch_lds_bytes(s->b[0].N, s->rows));
+    b->n_stiff += stiff_args<float>(s, 0).nblocks;
+    b->n_face += face_args<float>(s, 0).nblocks;
+  }
+  batch_layout(b);
+  *out = b;
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_batch_workspace_size(pmdg_batch* b, size_t* bytes) {
+  if (!b || !bytes) return fail(PMDG_EINVAL, "NULL argument");
+  *bytes = b->bytes;
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_batch_bind(pmdg_batch* b, void* dev_ptr, size_t bytes, void* stream) {
+  if (!b) return fail(PMDG_EINVAL, "NULL batch");
+  if (b->bound) return fail(PMDG_ESTATE, "already bound");
+  if (!dev_ptr || ((uintptr_t)dev_ptr & 255)) return fail(PMDG_EINVAL, "workspace must be 256-byte aligned");
+  if (bytes < b->bytes) return fail(PMDG_ENOMEM, "batch workspace too small: need " + std::to_string(b->bytes));
+  hipStream_t st = (hipStream_t)stream;
+  b->ws = (char*)dev_ptr;
+  std::vector<StiffArgs<float>> sa;
+  std::vector<FaceArgs<float>> fa;
+  std::vector<int2> si, fi;
+  std::vector<long*> ctr;
+  for (size_t p = 0; p < b->sv.size(); ++p) {
+    pmdg_solver* s = b->sv[p];
+    sa.push_back(stiff_args<float>(s, 0));
+    fa.push_back(face_args<float>(s, 0));
+    for (int t = 0; t < sa.back().nblocks; ++t) si.push_back(make_int2((int)p, t));
+    for (int t = 0; t < fa.back().nblocks; ++t) fi.push_back(make_int2((int)p, t));
+    ctr.push_back(dptr<long>(s, "ctl"));
+  }
+  HIPCHK(hipMemcpyAsync(b->ws + b->off_sargs, sa.data(), sa.size() * sizeof(sa[0]), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(b->ws + b->off_fargs, fa.data(), fa.size() * sizeof(fa[0]), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(b->ws + b->off_sitems, si.data(), si.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(b->ws + b->off_fitems, fi.data(), fi.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(b->ws + b->off_ctr, ctr.data(), ctr.size() * sizeof(long*), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  int dev = 0, cus = 256, occ = 1;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  HIPCHK(batch_occupancy(b->nmax, b->lds, &occ));
+  b->grid_stiff = std::max(1, std::min(b->n_stiff, cus * std::max(occ, 1)));
+  b->grid_face = std::max(1, std::min(b->n_face, cus * 4));
+  b->bound = true;
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_batch_set_option(pmdg_batch* b, int option, long value) {
+  if (!b) return fail(PMDG_EINVAL, "NULL batch");
+  if (option == PMDG_OPT_GRAPH) b->use_graph = value ? 1 : 0;
+  else if (option == PMDG_OPT_GRAPH_CHUNK && value >= 1) b->graph_chunk = (int)value;
+  else return fail(PMDG_EINVAL, "unsupported batch option");
+  for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+  b->graphs.clear();
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_batch_step(pmdg_batch* b, int n, void* stream) {
+  if (!b) return fail(PMDG_EINVAL, "NULL batch");
+  if (!b->bound) return fail(PMDG_ESTATE, "bind the batch before stepping");
+  if (n < 0) return fail(PMDG_EINVAL, "n must be >= 0");
+  for (auto* s : b->sv)
+    if (s->steps_done + n > s->cap) return fail(PMDG_ESTATE, "a solver's trace capacity would be exceeded");
+  if (n == 0) return PMDG_OK;
+  hipStream_t st = (hipStream_t)stream;
+  if (!b->use_graph) {
+    for (int i = 0; i < n; ++i) {
+      pmdg_status r = batch_enqueue(b, st);
+      if (r) return r;
+    }
+  } else {
+    if (!b->cap_stream) HIPCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    int left = n;
+    while (left > 0) {
+      const int len = std::min(left, b->graph_chunk);
+      auto it = b->graphs.find(len);
+      if (it == b->graphs.end()) {
+        hipGraph_t g;
+        HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+        pmdg_status r = PMDG_OK;
+        for (int i = 0; i < len && !r; ++i) r = batch_enqueue(b, b->cap_stream);
+        hipError_t ec = hipStreamEndCapture(b->cap_stream, &g);
+        if (r) return r;
+        if (ec != hipSuccess) return fail(PMDG_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+        hipGraphExec_t ex;
+        ec = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ec != hipSuccess) return fail(PMDG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ec));
+        it = b->graphs.emplace(len, ex).first;
+      }
+      HIPCHK(hipGraphLaunch(it->second, st));
+      left -= len;
+    }
+  }
+  for (auto* s : b->sv) s->steps_done += n;
+  return PMDG_OK;
+}
+
+void pmdg_batch_destroy(pmdg_batch* b) {
+  if (!b) return;
+  for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  delete b;
+}
+
+}  // extern "C"

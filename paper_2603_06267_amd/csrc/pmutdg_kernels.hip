@@ -59,8 +59,9 @@ __device__ void face_traces(const FaceArgs<Real>& a, int side, int item, int buf
   }
 }
 
+// One workgroup-sized unit b of the face work of one problem.
 template <typename Real>
-__global__ void __launch_bounds__(256) k_face(const FaceArgs<Real> a) {
+__device__ void face_block(const FaceArgs<Real>& a, int b) {
   __shared__ double red[kWaves][kMaxModes];
   __shared__ double qp_s[kMaxModes], qds_s[kMaxModes], qdd_s[kMaxModes];
   __shared__ double phi_s;
@@ -68,7 +69,6 @@ __global__ void __launch_bounds__(256) k_face(const FaceArgs<Real> a) {
   const long cnt = *a.counter;
   const long lev = a.prime ? cnt : cnt + 1;  // time level of the pressure to sample
   const int buf = (int)(lev & 1);
-  int b = blockIdx.x;
 
   if (b < a.nb_tr0) {
     face_traces(a, 0, b * 256 + tid, buf);
@@ -168,6 +168,28 @@ __global__ void __launch_bounds__(256) k_face(const FaceArgs<Real> a) {
   }
 
 
+}
+
+template <typename Real>
+__global__ void __launch_bounds__(256) k_face(const FaceArgs<Real> a) {
+  face_block(a, blockIdx.x);
+}
+
+// Persistent face kernel over the (problem, unit) work list of a batch.
+template <typename Real>
+__global__ void __launch_bounds__(256) k_face_batch(const FaceArgs<Real>* __restrict__ probs,
+                                                    const int2* __restrict__ items, int nitems) {
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int2 w = items[it];
+    __syncthreads();
+    face_block(probs[w.x], w.y);
+  }
+}
+
+// Advances the step counters of all problems of a batch.
+__global__ void k_tick_batch(long* const* __restrict__ counters, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) atomicAdd((unsigned long long*)counters[i], 1ull);
 }
 
 // ------------------------------------------------------------------------
@@ -384,6 +406,18 @@ hipError_t launch_flux(const FluxArgs<Real>& a, hipStream_t st) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_flux_coarse<Real>, dim3(a.nb_coarse), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_face_batch(const FaceArgs<float>* probs, const int2* items, int nitems, int grid,
+                             hipStream_t st) {
+  if (nitems == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_face_batch<float>, dim3(grid), dim3(256), 0, st, probs, items, nitems);
+  return hipGetLastError();
+}
+
+hipError_t launch_tick_batch(long* const* counters, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_tick_batch, dim3((n + 63) / 64), dim3(64), 0, st, counters, n);
   return hipGetLastError();
 }
 

@@ -62,17 +62,26 @@ __device__ __forceinline__ int node_class(int i, int n) {
   return i == 0 ? N : (i == n - 1 ? N + 1 : i % N);
 }
 
+// LDS (in Real elements) of one stiffness workgroup: two plane buffers and
+// the z operator rows
+template <int N, int RY, int WV>
+__host__ __device__ constexpr int stiff_lds_elems() {
+  return 2 * (64 + 2 * N) * (WV * RY + 2 * N) + (N + 2) * (2 * N + 1);
+}
+
+// One tile of the stiffness update (tile = linear tile index of the brick
+// and scenario); lds holds stiff_lds_elems<N, RY, WV>() elements.
 template <typename Real, int N, bool INCR, int RY, int WV>
-__global__ void __launch_bounds__(64 * WV) k_stiff(const StiffArgs<Real> a) {
+__device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id, Real* __restrict__ lds) {
   constexpr int TX = 64, TY = WV * RY, W = TX + 2 * N, H = TY + 2 * N, NT = 2 * N, NQ = NT + 1;
   constexpr int HYR = (NT + WV - 1) / WV;              // y-halo rows per wave
   constexpr int NXH = (TY * NT + 64 * WV - 1) / (64 * WV);  // x-halo loads per thread
-  __shared__ Real tile[2][H * W];
+  Real (*tile)[H * W] = reinterpret_cast<Real (*)[H * W]>(lds);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  int t = xcd_remap(blockIdx.x, a.nblocks);
+  int t = tile_id;
   const int bx = t % a.nbx; t /= a.nbx;
   const int by = t % a.nby; t /= a.nby;
   const int bz = t % a.nbz; t /= a.nbz;
@@ -117,7 +126,7 @@ __global__ void __launch_bounds__(64 * WV) k_stiff(const StiffArgs<Real> a) {
     my[r] = MI[NC + cyr[r]];
   }
   // z operator rows by class, staged in LDS (read with uniform addresses)
-  __shared__ Real ztab[(N + 2) * (NT + 1)];
+  Real* ztab = lds + 2 * H * W;
   for (int i = tid; i < (N + 2) * (NT + 1); i += 64 * WV) {
     const int cls = i / (NT + 1), j = i % (NT + 1);
     ztab[i] = j < NT ? TP[(2 * NC + cls) * NT + j] : MI[2 * NC + cls];
@@ -300,6 +309,12 @@ __global__ void __launch_bounds__(64 * WV) k_stiff(const StiffArgs<Real> a) {
   }
 }
 
+
+template <typename Real, int N, bool INCR, int RY, int WV>
+__global__ void __launch_bounds__(64 * WV) k_stiff(const StiffArgs<Real> a) {
+  __shared__ Real lds[stiff_lds_elems<N, RY, WV>()];
+  stiff_tile<Real, N, INCR, RY, WV>(a, xcd_remap(blockIdx.x, a.nblocks), lds);
+}
 
 template <typename Real, int N, bool INCR>
 static hipError_t stiff_rows(const StiffArgs<Real>& a, hipStream_t st) {

@@ -1,0 +1,56 @@
+"""Batched form on the GPU: persistent launches over many problems give the
+same results as stepping each problem on its own (bitwise), match the FP64
+oracle, and the tile autotuner returns a valid, cached choice."""
+import numpy as np
+import pytest
+
+from oracle import ref
+from paper_2603_06267_amd import batch as B, solver, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _workloads(steps, nscen=8, mesh_ids=(0, 5, 10, 15)):
+    c4 = W.config4()
+    base = dict(c4["scenarios"], steps=steps)
+    dr = base["drive"]
+    base["drive"] = {k: (v[:nscen] if hasattr(v, "__len__") and not isinstance(v, float) else v)
+                     for k, v in dr.items()}
+    meshes = [dict(c4["meshes"][i], steps=steps) for i in mesh_ids]
+    return [base] + meshes
+
+
+def test_batch_equals_individual_solvers():
+    steps = 100
+    wls = _workloads(steps)
+    sfs = [W.shape_fn(w) for w in wls]
+    b = B.build_batch(wls, shape_fns=sfs, n_steps=steps)
+    b.step(steps)
+    for wl, sf, sb in zip(wls, sfs, b.solvers):
+        s1 = solver.from_workload(wl, precision=32, n_steps=steps, shape_fn=sf)
+        s1.step(steps)
+        np.testing.assert_array_equal(sb.read_traces(), s1.read_traces())
+
+
+def test_batch_vs_oracle_highest_order_mesh():
+    steps = 150
+    wls = _workloads(steps, nscen=4, mesh_ids=(3, 15))
+    sfs = [W.shape_fn(w) for w in wls]
+    b = B.build_batch(wls, shape_fns=sfs, n_steps=steps)
+    b.set_option(4, 29)
+    b.step(steps)
+    for i, sc in ((0, 3), (2, 0)):
+        o = ref.from_workload(wls[i], scenario=sc, shape_fn=sfs[i])
+        to = o.step(steps)
+        tg = b.solvers[i].read_traces()[sc]
+        err = np.linalg.norm(tg - to) / np.linalg.norm(to)
+        assert err <= 1e-5, (i, sc, err)
+
+
+def test_tuner_choice_valid_and_cached(tmp_path):
+    t = B.TileTuner(path=str(tmp_path / "tiles.json"), candidates=[(1, 9), (2, 17)], steps=3)
+    dom = W.config4()["meshes"][6]["domains"]
+    best = t.tune(dom, S=1)
+    assert best in [(1, 9), (2, 17)]
+    t2 = B.TileTuner(path=str(tmp_path / "tiles.json"))
+    assert t2.tune(dom, S=1) == best
