@@ -21,10 +21,34 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+STIFF_SOURCES = ["stiff_kernel.h", "stiff_f32_lo.hip", "stiff_f32_hi.hip"]
+COUNTERS = os.path.join(ROOT, "profiles", "k_stiff_config3_fp32_hbm_counters.md")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def measured_traffic(rows, zchunk):
+    """HBM bytes per step of the two stiffness launches from the committed
+    FETCH_SIZE / WRITE_SIZE passes, if the kernel sources and tile shape are
+    still the ones those counters were taken with; else None."""
+    import hashlib
+    if (rows, zchunk) != (2, 33) or not os.path.exists(COUNTERS):
+        return None
+    h = hashlib.sha256()
+    for f in STIFF_SOURCES:
+        with open(os.path.join(ROOT, "paper_2603_06267_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    fields = {}
+    with open(COUNTERS) as fh:
+        for line in fh:
+            if ":" in line and line.split(":")[0] in ("traffic_bytes_per_step", "stiff_source_sha256"):
+                k, v = line.split(":", 1)
+                fields[k] = v.strip()
+    if fields.get("stiff_source_sha256") != h.hexdigest():
+        return None
+    return float(fields["traffic_bytes_per_step"])
 
 
 def cpu_baseline(wl, steps):
@@ -68,6 +92,7 @@ def run_gpu(wl, precision, steps, warmup, graphs, rows, zchunk):
     gg.set_option(2, rows)
     gg.set_option(3, zchunk)
     gg.bind()
+    gg.set_option(1, 1 if graphs else 0)
     gg.step(warmup)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -87,8 +112,10 @@ def main():
     ap.add_argument("--rows", type=int, default=2)
     ap.add_argument("--zchunk", type=int, default=33)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=8)
-    ap.add_argument("--fp64", action="store_true", help="also time the FP64 instantiation")
+    ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 instantiation")
+    ap.add_argument("--direct", action="store_true",
+                    help="direct kernel launches instead of hipGraph replay (for counter collection)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported (the multi-GPU slab "
@@ -103,15 +130,17 @@ def main():
 
     log(f"config 3: {dofs} unique DOFs ({W.element_local_dofs(wl)} element-local); FP32 run, "
         f"{args.warmup} warmup + {args.steps} timed steps")
-    el, el_graph, kt, finite = run_gpu(wl, 32, args.steps, args.warmup, True, args.rows, args.zchunk)
+    el, el_graph, kt, finite = run_gpu(wl, 32, args.steps, args.warmup, not args.direct, args.rows, args.zchunk)
     log(f"  timed (events): {el * 1e3 / args.steps:.4f} ms/step; graph replay: {el_graph * 1e3 / args.steps:.4f} "
         f"ms/step; kernels ms: stiff {kt[0]:.4f} face {kt[1]:.4f} flux {kt[2]:.4f}")
     best = min(el, el_graph)
     value = dofs * args.steps / best
-    # algorithmic bytes of the stiffness class per step: increment form reads
-    # p and dp and writes p and dp, 4 bytes each, at every node of both bricks
-    bytes_per_step = 16.0 * (n0 + n1)
+    # algorithmic bytes per step of the stiffness launches (both bricks): read
+    # p^n and p^{n-1}, write p^{n+1}, 4 bytes each per unique DOF.  The FP32
+    # increment form moves 16 B per DOF by design (p and p^n - p^{n-1}).
+    bytes_per_step = 12.0 * (n0 + n1)
     achieved = bytes_per_step / (kt[0] * 1e-3) / 1e9
+    traffic = measured_traffic(args.rows, args.zchunk)
     out = {
         "metric": "DOF-updates/s",
         "value": value,
@@ -128,17 +157,22 @@ def main():
         "config": {"workload": "config3-large-array: 1024 PMUTs x 10 modes, primary 128x128x8 hexes N=4 + "
                                "secondary 96^3 hexes N=3, 4:3 non-conforming interface, FP32 state / FP64 ODE",
                    "unique_dofs": dofs, "element_local_dofs": W.element_local_dofs(wl),
-                   "parallelism": "single GPU", "timed_with": "graph" if el_graph <= el else "events"},
+                   "parallelism": "single GPU",
+                   "timed_with": ("direct" if args.direct else "graph") + (" replay" if el_graph <= el else " + events")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
-                     "kernel": "k_stiff (both bricks), 16 B per DOF-update"},
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     "kernel": "k_stiff, both bricks per step (12 B per unique DOF algorithmic; "
+                               "traffic = measured HBM bytes per step)",
+                     "moved_GBs": None if traffic is None else traffic / (kt[0] * 1e-3) / 1e9},
         "kernel_ms": {"stiff": kt[0], "face": kt[1], "flux": kt[2]},
         "finite": finite,
     }
-    if args.fp64:
-        el64, elg64, kt64, fin64 = run_gpu(wl, 64, args.steps, args.warmup, True, 1, args.zchunk)
+    if not args.no_fp64:
+        log("FP64 instantiation ...")
+        el64, elg64, kt64, fin64 = run_gpu(wl, 64, args.steps, args.warmup, not args.direct, 1, args.zchunk)
         out["fp64"] = {"value": dofs * args.steps / min(el64, elg64), "unit": "DOF-updates/s",
-                       "stiff_ms": kt64[0], "achieved_GBs": 24.0 * (n0 + n1) / (kt64[0] * 1e-3) / 1e9}
+                       "stiff_ms": kt64[0], "achieved_GBs": 24.0 * (n0 + n1) / (kt64[0] * 1e-3) / 1e9,
+                       "frac": 24.0 * (n0 + n1) / (kt64[0] * 1e-3) / 1e9 / PEAK_HBM_GBS}
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         wl_cpu = W.config3(steps=args.cpu_steps)

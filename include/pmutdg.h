@@ -69,7 +69,8 @@ typedef struct {
   double penalty_alpha;/* SIPG constant alpha in gamma_F (Sec. 3); > 0 */
   int precision;       /* 32: FP32 field state/operators, FP64 ODE+traces; 64: all FP64 */
   int n_scenarios;     /* S >= 1 drive scenarios sharing mesh and PMUT modal data */
-  int trace_capacity;  /* receiver samples kept per receiver and scenario (>= 1) */
+  int trace_capacity;  /* steps a solver may take in total (>= 1): receiver samples kept per
+                        * receiver and scenario, and length of the per-step drive table */
 } pmdg_problem;
 
 /* Creates a solver: builds GLL / Gauss-Legendre rules, the assembled 1D
@@ -205,6 +206,60 @@ pmdg_status pmdg_batch_set_option(pmdg_batch* b, int option, long value);
 pmdg_status pmdg_batch_step(pmdg_batch* b, int n, void* stream);
 /* NULL is a no-op. */
 void pmdg_batch_destroy(pmdg_batch* b);
+
+/* ---- Surrogate form -------------------------------------------------------
+ * A fully connected network u[n_0] -> y[n_L] with GELU on the hidden layers
+ * (gelu(z) = z Phi(z), Phi the standard normal distribution function) that
+ * stands in for the solver on the map from drive parameters (per-PMUT
+ * phases, frequency, amplitude) to receiver traces.  The GEMMs run on BF16
+ * MFMA with FP32 accumulation; the parameters are FP32 masters with BF16
+ * copies; training minimises the mean squared error with Adam (bias
+ * corrected).  Input and output pass through fixed affine maps:
+ *   x_0 = (u - shift) * scale per feature,  y_phys = out_scale * y.
+ * All rows are row-major FP32; u[nrows][n_0], targets t[nrows][n_L],
+ * outputs y[B][n_L].  Device pointers unless stated.  Errors: EINVAL for bad
+ * sizes or pointers, ESTATE for calls out of order, EHIP for runtime
+ * failures.  Calls that overlap on one model race (one stream per model). */
+typedef struct pmdg_mlp pmdg_mlp;
+
+/* widths[nlayers + 1]: n_0 .. n_L; n_1 .. n_L multiples of 8; 1 <= nlayers <= 16. */
+pmdg_status pmdg_mlp_create(int nlayers, const int* widths, pmdg_mlp** out);
+/* Number of trainable values sum_l n_{l+1} (n_l + 1). */
+pmdg_status pmdg_mlp_num_params(pmdg_mlp* m, long* n);
+/* Device bytes for parameters, Adam moments, activations of up to max_batch
+ * rows (a multiple of 8) and split-K partial sums; fixes max_batch. */
+pmdg_status pmdg_mlp_workspace_size(pmdg_mlp* m, int max_batch, size_t* bytes);
+/* Binds caller-owned device memory (256-byte aligned), zeroes it. */
+pmdg_status pmdg_mlp_bind(pmdg_mlp* m, void* dev_ptr, size_t bytes, void* stream);
+/* Input map shift[n_0], scale[n_0] (host) and output scale (> 0). */
+pmdg_status pmdg_mlp_set_io_map(pmdg_mlp* m, const float* shift, const float* scale, float out_scale, void* stream);
+/* Host parameters, per layer W_l [n_{l+1}][n_l] row-major then b_l; resets Adam. */
+pmdg_status pmdg_mlp_set_params(pmdg_mlp* m, const float* host, void* stream);
+pmdg_status pmdg_mlp_get_params(pmdg_mlp* m, float* host, void* stream);
+/* Gradients of the last backward pass, same host layout as the parameters. */
+pmdg_status pmdg_mlp_get_grads(pmdg_mlp* m, float* host, void* stream);
+/* Forward pass of B rows (multiple of 8, <= max_batch).  Row r is u[idx[r]]
+ * (idx clamped into [0, nrows)) or, with idx NULL, u[r] (nrows >= B).  With y
+ * non-NULL writes out_scale * y there (inference); with y NULL keeps the
+ * normalised output for pmdg_mlp_backward (training). */
+pmdg_status pmdg_mlp_forward(pmdg_mlp* m, const float* u, const int* idx, int nrows, int B, float* y, void* stream);
+/* Gradients of (1 / (B n_L)) sum (y - t[row] / out_scale)^2 for the last
+ * training forward (same rows); per-row squared error and squared target
+ * norm (normalised units) into rowerr[B], rownorm[B] if non-NULL. */
+pmdg_status pmdg_mlp_backward(pmdg_mlp* m, const float* t, int B, float* rowerr, float* rownorm, void* stream);
+/* One Adam step (bias-corrected, step count kept by the model) on the last gradients. */
+pmdg_status pmdg_mlp_adam(pmdg_mlp* m, float lr, float beta1, float beta2, float eps, void* stream);
+/* forward (training) + backward + Adam. */
+pmdg_status pmdg_mlp_train_step(pmdg_mlp* m, const float* u, const float* t, const int* idx, int nrows, int B,
+                                float lr, float beta1, float beta2, float eps, float* rowerr, float* rownorm,
+                                void* stream);
+/* Two-member ensemble: mean[B][n] = (a + b) / 2 and the relative spread
+ * spread[r] = |a_r - b_r| / |mean_r| (0 if mean_r = 0); n a multiple of 4,
+ * a, b, mean 16-byte aligned; mean may alias a or b. */
+pmdg_status pmdg_mlp_pair_combine(const float* a, const float* b, int B, int n, float* mean, float* spread,
+                                  void* stream);
+/* NULL is a no-op. */
+void pmdg_mlp_destroy(pmdg_mlp* m);
 
 const char* pmdg_last_error(void);
 

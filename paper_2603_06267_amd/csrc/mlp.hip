@@ -1,0 +1,695 @@
+// libpmutdg, surrogate form: a fully connected network that maps the drive
+// parameters of a PMUT array (per-PMUT phase, frequency, amplitude) to
+// receiver traces, trained and evaluated by hand-written BF16 MFMA kernels
+// (CDNA4 v_mfma_f32_32x32x16_bf16) that accumulate in FP32, on FP32 master
+// weights updated by Adam.
+//
+//   input     x_0 = bf16((u - shift) * scale), rows optionally gathered
+//   forward   z_l = x_l W_l^T + b_l, x_{l+1} = bf16(gelu(z_l)) (hidden layers),
+//             y = z_{L-1}; inference returns out_scale * y
+//   loss      mean squared error against t / out_scale,
+//             dz_{L-1} = 2 (y - t / out_scale) / (B n_out)
+//   backward  dW_l = dz_l^T x_l, db_l = sum over rows of dz_l,
+//             dz_{l-1} = (dz_l W_l) * gelu'(z_{l-1})
+//   update    Adam with bias correction on the FP32 masters; the BF16 copies
+//             used by the GEMMs are refreshed in the same pass
+//
+// Layouts (row-major): activations [batch][width], the input width padded
+// with zeros to a multiple of 32; W_l [n_out][n_in padded].
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pmutdg.h"
+#include "pmutdg_internal.h"
+
+namespace {
+
+typedef unsigned short bf16_t;
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float floatx16;
+
+__device__ __forceinline__ bf16_t f2bf(float f) {
+  // round to nearest, ties to even (operands are finite)
+  unsigned u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (bf16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_d(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * __expf(-0.5f * z * z);
+}
+
+enum { EPI_FWD_GELU = 0, EPI_FWD_LIN = 1, EPI_DX_GELU = 2, EPI_DW = 3 };
+
+struct GemmArgs {
+  int M, N, K;           // C[M][N] = sum_r A(i, r) B(r, j)
+  const bf16_t* A;       // A(i, r) = A[i*lda + r] (ACON) or A[r*lda + i]
+  const bf16_t* B;       // B(r, j) = B[j*ldb + r] (BCON) or B[r*ldb + j]
+  int lda, ldb;
+  const float* bias;     // [N] (forward epilogues)
+  float* Cf;             // FP32 result (z, dz or dW), ld = ldc
+  bf16_t* Cb;            // BF16 copy (activation or dz), ld = ldc
+  int ldc;
+  const float* Zprev;    // pre-activation for gelu' (EPI_DX_GELU), ld = ldc
+  float* Y;              // EPI_FWD_LIN: if set, out_scale * z goes here instead of Cf
+  float out_scale;
+  float* part;           // split-K partial sums [ks][M][N]
+  int mt, nt, ks, kchunk;
+};
+
+constexpr int BM = 128, BN = 128, BK = 32, LDK = BK + 8;
+
+template <int EPI>
+__device__ __forceinline__ void epilogue(const GemmArgs& g, int row, int col, float v) {
+  const long o = (long)row * g.ldc + col;
+  if (EPI == EPI_FWD_GELU) {
+    const float z = v + g.bias[col];
+    g.Cf[o] = z;
+    g.Cb[o] = f2bf(gelu(z));
+  } else if (EPI == EPI_FWD_LIN) {
+    const float z = v + g.bias[col];
+    if (g.Y) g.Y[o] = g.out_scale * z;
+    else g.Cf[o] = z;
+  } else if (EPI == EPI_DX_GELU) {
+    const float d = v * gelu_d(g.Zprev[o]);
+    g.Cf[o] = d;
+    g.Cb[o] = f2bf(d);
+  } else {
+    g.Cf[o] = v;
+  }
+}
+
+// One 128 x 128 output tile per workgroup of 4 waves (2 x 2), each wave
+// 64 x 64 = 2 x 2 MFMA 32x32 blocks.  MFMA 32x32x16 operand layout: lane l
+// supplies row (A) or column (B) l % 32 and eight reduction indices chosen by
+// l / 32 (the same for A and B, so the exact order within the 16 does not
+// matter); accumulator element r of lane l is row 8 (r / 4) + 4 (l / 32) +
+// r % 4, column l % 32.  The linear grid is remapped so that the workgroups
+// one XCD receives (dispatch is round-robin over the 8 XCDs) are consecutive
+// tiles that share the same B (weight) tile, which then stays in that XCD's L2.
+template <bool ACON, bool BCON, int EPI>
+__global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) bf16_t As[2][BM * LDK];
+  __shared__ __attribute__((aligned(16))) bf16_t Bs[2][BN * LDK];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+
+  const int nb = g.mt * g.nt * g.ks;
+  int t = blockIdx.x;
+  if ((nb & 7) == 0) t = (t & 7) * (nb >> 3) + (t >> 3);
+  const int z = t / (g.mt * g.nt);
+  const int rem = t - z * g.mt * g.nt;
+  const int m0 = (rem % g.mt) * BM, n0 = (rem / g.mt) * BN;
+  const int kbeg = z * g.kchunk, kend = min(g.K, kbeg + g.kchunk);
+
+  auto load_tile = [&](int buf, int k0) {
+#pragma unroll
+    for (int c2 = 0; c2 < 2; ++c2) {
+      const int c = tid + 256 * c2;
+      if (ACON) {
+        const int row = c >> 2, kc = (c & 3) * 8;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (m0 + row < g.M && k0 + kc < kend) v = *(const uint4*)(g.A + (long)(m0 + row) * g.lda + k0 + kc);
+        *(uint4*)&As[buf][row * LDK + kc] = v;
+      } else {
+        const int r = c >> 4, ic = (c & 15) * 8;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (k0 + r < kend && m0 + ic < g.M) v = *(const uint4*)(g.A + (long)(k0 + r) * g.lda + m0 + ic);
+        const bf16_t* e = (const bf16_t*)&v;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) As[buf][(ic + q) * LDK + r] = e[q];
+      }
+    }
+#pragma unroll
+    for (int c2 = 0; c2 < 2; ++c2) {
+      const int c = tid + 256 * c2;
+      if (BCON) {
+        const int col = c >> 2, kc = (c & 3) * 8;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (n0 + col < g.N && k0 + kc < kend) v = *(const uint4*)(g.B + (long)(n0 + col) * g.ldb + k0 + kc);
+        *(uint4*)&Bs[buf][col * LDK + kc] = v;
+      } else {
+        const int r = c >> 4, jc = (c & 15) * 8;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (k0 + r < kend && n0 + jc < g.N) v = *(const uint4*)(g.B + (long)(k0 + r) * g.ldb + n0 + jc);
+        const bf16_t* e = (const bf16_t*)&v;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) Bs[buf][(jc + q) * LDK + r] = e[q];
+      }
+    }
+  };
+
+  floatx16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+  const int nk = (kend - kbeg + BK - 1) / BK;
+  if (nk > 0) load_tile(0, kbeg);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) load_tile(buf ^ 1, kbeg + (kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 16) {
+      bf16x8 af[2], bfr[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int row = wm * 64 + i * 32 + (lane & 31);
+        af[i] = *(const bf16x8*)&As[buf][row * LDK + kk + (lane >> 5) * 8];
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int col = wn * 64 + j * 32 + (lane & 31);
+        bfr[j] = *(const bf16x8*)&Bs[buf][col * LDK + kk + (lane >> 5) * 8];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+  float* part = g.ks > 1 ? g.part + (long)z * g.M * g.N : nullptr;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = m0 + wm * 64 + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+        const int col = n0 + wn * 64 + j * 32 + (lane & 31);
+        if (row >= g.M || col >= g.N) continue;
+        if (part) part[(long)row * g.N + col] = acc[i][j][r];
+        else epilogue<EPI>(g, row, col, acc[i][j][r]);
+      }
+}
+
+// split-K: sum the ks partial tiles in a fixed order, then the epilogue
+template <int EPI>
+__global__ void k_splitk_reduce(const GemmArgs g) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long MN = (long)g.M * g.N;
+  if (i >= MN) return;
+  float s = 0.f;
+  for (int z = 0; z < g.ks; ++z) s += g.part[z * MN + i];
+  epilogue<EPI>(g, (int)(i / g.N), (int)(i % g.N), s);
+}
+
+// x_0 = bf16((u[src] - shift) * scale), zero-padded to ld columns
+__global__ void k_pack_input(const float* __restrict__ u, const int* __restrict__ idx, int nrows, int B, int nin, int ld,
+                             const float* __restrict__ shift, const float* __restrict__ scale,
+                             bf16_t* __restrict__ X) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= (long)B * ld) return;
+  const int r = (int)(i / ld), c = (int)(i % ld);
+  const long src = idx ? min(max(idx[r], 0), nrows - 1) : r;
+  X[i] = c < nin ? f2bf((u[src * nin + c] - shift[c]) * scale[c]) : (bf16_t)0;
+}
+
+// per-row squared error and squared target norm (normalised units), and
+// dz = 2 (y - t / out_scale) / (B n)
+__global__ void __launch_bounds__(256) k_loss(const float* __restrict__ Y, const float* __restrict__ T,
+                                              const int* __restrict__ idx, int nrows, int B, int n, float inv_scale,
+                                              float* __restrict__ dZ, bf16_t* __restrict__ dZb,
+                                              float* __restrict__ rowerr, float* __restrict__ rownorm) {
+  const int r = blockIdx.x;
+  const long src = idx ? min(max(idx[r], 0), nrows - 1) : r;
+  float se = 0.f, sn = 0.f;
+  const float sc = 2.0f / ((float)B * (float)n);
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    const long o = (long)r * n + c;
+    const float tv = T[src * n + c] * inv_scale;
+    const float d = Y[o] - tv;
+    se += d * d;
+    sn += tv * tv;
+    const float gr = sc * d;
+    dZ[o] = gr;
+    dZb[o] = f2bf(gr);
+  }
+  __shared__ float s1[256], s2[256];
+  s1[threadIdx.x] = se;
+  s2[threadIdx.x] = sn;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      s1[threadIdx.x] += s1[threadIdx.x + s];
+      s2[threadIdx.x] += s2[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    rowerr[r] = s1[0];
+    rownorm[r] = s2[0];
+  }
+}
+
+// db[c] = sum_r dz[r][c], 64 columns x 4 row groups per workgroup
+__global__ void __launch_bounds__(256) k_colsum(const float* __restrict__ dZ, int B, int n, float* __restrict__ db) {
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63), rg = threadIdx.x >> 6;
+  float s = 0.f;
+  if (c < n)
+    for (int r = rg; r < B; r += 4) s += dZ[(long)r * n + c];
+  __shared__ float sh[4][64];
+  sh[rg][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (rg == 0 && c < n) db[c] = (sh[0][threadIdx.x] + sh[1][threadIdx.x]) + (sh[2][threadIdx.x] + sh[3][threadIdx.x]);
+}
+
+__global__ void k_adam(float* __restrict__ w, const float* __restrict__ gr, float* __restrict__ m,
+                       float* __restrict__ v, bf16_t* __restrict__ wb, long n, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float g = gr[i];
+  const float mi = b1 * m[i] + (1.f - b1) * g;
+  const float vi = b2 * v[i] + (1.f - b2) * g * g;
+  m[i] = mi;
+  v[i] = vi;
+  const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  w[i] = wi;
+  if (wb) wb[i] = f2bf(wi);
+}
+
+__global__ void k_to_bf16(const float* __restrict__ w, bf16_t* __restrict__ wb, long n) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i < n) wb[i] = f2bf(w[i]);
+}
+
+// ensemble of two: mean into out and the per-row relative spread
+// |a - b| / |(a + b) / 2| (0 where the mean vanishes)
+// (out may alias a or b: each element is read before it is written, by the
+// same thread)
+__global__ void __launch_bounds__(256) k_pair_combine(const float* a, const float* b, int n, float* out,
+                                                      float* __restrict__ spread) {
+  const long base = (long)blockIdx.x * n;
+  float s1 = 0.f, s2 = 0.f;
+  for (int c = threadIdx.x * 4; c < n; c += 1024) {
+    const float4 x = *(const float4*)(a + base + c), y = *(const float4*)(b + base + c);
+    const float4 m = make_float4(0.5f * (x.x + y.x), 0.5f * (x.y + y.y), 0.5f * (x.z + y.z), 0.5f * (x.w + y.w));
+    const float dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z, dw = x.w - y.w;
+    s1 += dx * dx + dy * dy + dz * dz + dw * dw;
+    s2 += m.x * m.x + m.y * m.y + m.z * m.z + m.w * m.w;
+    *(float4*)(out + base + c) = m;
+  }
+  __shared__ float t1[256], t2[256];
+  t1[threadIdx.x] = s1;
+  t2[threadIdx.x] = s2;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      t1[threadIdx.x] += t1[threadIdx.x + s];
+      t2[threadIdx.x] += t2[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) spread[blockIdx.x] = t2[0] > 0.f ? sqrtf(t1[0] / t2[0]) : 0.f;
+}
+
+inline long nblk(long n, int b) { return (n + b - 1) / b; }
+
+pmdg_status mfail(pmdg_status s, const std::string& m) {
+  pmdg::set_last_error(m);
+  return s;
+}
+
+constexpr int kTargetBlocks = 256;  // one workgroup per CU
+constexpr size_t kPartFloats = (size_t)384 * BM * BN;
+
+// split-K factor: ks * tiles <= kTargetBlocks + tiles, chunks of >= 256
+void plan_split(GemmArgs& g) {
+  g.mt = (g.M + BM - 1) / BM;
+  g.nt = (g.N + BN - 1) / BN;
+  const int tiles = g.mt * g.nt;
+  int ks = 1;
+  if (tiles < kTargetBlocks / 2) {
+    ks = (kTargetBlocks + tiles - 1) / tiles;
+    ks = std::min(ks, std::max(1, g.K / 256));
+  }
+  g.kchunk = (int)((g.K + ks - 1) / ks + BK - 1) / BK * BK;
+  g.ks = (g.K + g.kchunk - 1) / g.kchunk;
+}
+
+template <bool ACON, bool BCON, int EPI>
+hipError_t gemm(GemmArgs g, float* part, hipStream_t st) {
+  plan_split(g);
+  g.part = part;
+  if (g.ks > 1 && (size_t)g.ks * g.M * g.N > kPartFloats) {
+    g.kchunk = ((g.K + BK - 1) / BK) * BK;
+    g.ks = 1;
+  }
+  hipLaunchKernelGGL((k_gemm<ACON, BCON, EPI>), dim3(g.mt * g.nt * g.ks), dim3(256), 0, st, g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || g.ks == 1) return e;
+  hipLaunchKernelGGL((k_splitk_reduce<EPI>), dim3((unsigned)nblk((long)g.M * g.N, 256)), dim3(256), 0, st, g);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+#define MCHK(call)                                                                                  \
+  do {                                                                                              \
+    hipError_t e_ = (call);                                                                         \
+    if (e_ != hipSuccess) return mfail(PMDG_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct pmdg_mlp {
+  int L = 0;                       // weight matrices
+  std::vector<int> width;          // L + 1 widths
+  std::vector<int> kin;            // padded input width of layer l
+  int max_batch = 0;
+  char* ws = nullptr;
+  bool bound = false;
+  bool have_z = false;             // last forward kept the normalised output
+  int last_batch = 0;
+  const int* last_idx = nullptr;
+  int last_nrows = 0;
+  std::vector<float> shift, scale; // input map (host copies)
+  float out_scale = 1.f;
+  // byte offsets into the workspace
+  std::vector<size_t> oW, ob, oWb, omW, ovW, omb, ovb, odW, odb, oZ, oXb, odZ, odZb;
+  size_t oRowErr = 0, oRowNorm = 0, oShift = 0, oScale = 0, oPart = 0, bytes = 0;
+  long nparams = 0;
+  int adam_t = 0;
+};
+
+static size_t a256(size_t x) { return (x + 255) / 256 * 256; }
+
+static void mlp_layout(pmdg_mlp* m) {
+  const int L = m->L;
+  const size_t B = m->max_batch;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = a256(o + bytes); return r; };
+  for (auto* v : {&m->oW, &m->ob, &m->oWb, &m->omW, &m->ovW, &m->omb, &m->ovb, &m->odW, &m->odb, &m->oZ, &m->odZ,
+                  &m->odZb})
+    v->assign(L, 0);
+  m->oXb.assign(L, 0);
+  for (int l = 0; l < L; ++l) {
+    const size_t nw = (size_t)m->width[l + 1] * m->kin[l], nb = m->width[l + 1];
+    m->oW[l] = take(4 * nw); m->ob[l] = take(4 * nb); m->oWb[l] = take(2 * nw);
+    m->omW[l] = take(4 * nw); m->ovW[l] = take(4 * nw); m->omb[l] = take(4 * nb); m->ovb[l] = take(4 * nb);
+    m->odW[l] = take(4 * nw); m->odb[l] = take(4 * nb);
+    m->oZ[l] = take(4 * B * m->width[l + 1]);
+    m->odZ[l] = take(4 * B * m->width[l + 1]);
+    m->odZb[l] = take(2 * B * m->width[l + 1]);
+    m->oXb[l] = take(2 * B * m->kin[l]);
+  }
+  m->oRowErr = take(4 * B);
+  m->oRowNorm = take(4 * B);
+  m->oShift = take(4 * (size_t)m->kin[0]);
+  m->oScale = take(4 * (size_t)m->kin[0]);
+  m->oPart = take(4 * kPartFloats);
+  m->bytes = o;
+}
+
+template <typename T>
+static T* at(pmdg_mlp* m, size_t off) { return (T*)(m->ws + off); }
+
+static pmdg_status check_batch(pmdg_mlp* m, const int* idx, int nrows, int B) {
+  if (!m->bound) return mfail(PMDG_ESTATE, "model not bound");
+  if (B < 8 || B > m->max_batch || B % 8) return mfail(PMDG_EINVAL, "batch must be a multiple of 8 in [8, max_batch]");
+  if (nrows < 1 || (!idx && nrows < B)) return mfail(PMDG_EINVAL, "nrows must be >= 1, and >= B without idx");
+  return PMDG_OK;
+}
+
+static pmdg_status mlp_forward_dev(pmdg_mlp* m, const float* u, const int* idx, int nrows, int B, float* y,
+                                   hipStream_t st) {
+  const int L = m->L;
+  hipLaunchKernelGGL(k_pack_input, dim3((unsigned)nblk((long)B * m->kin[0], 256)), dim3(256), 0, st, u, idx, nrows, B,
+                     m->width[0], m->kin[0], at<float>(m, m->oShift), at<float>(m, m->oScale),
+                     at<bf16_t>(m, m->oXb[0]));
+  MCHK(hipGetLastError());
+  for (int l = 0; l < L; ++l) {
+    GemmArgs g;
+    memset(&g, 0, sizeof(g));
+    g.M = B; g.N = m->width[l + 1]; g.K = m->kin[l];
+    g.A = at<bf16_t>(m, m->oXb[l]); g.lda = m->kin[l];
+    g.B = at<bf16_t>(m, m->oWb[l]); g.ldb = m->kin[l];
+    g.bias = at<float>(m, m->ob[l]);
+    g.Cf = at<float>(m, m->oZ[l]); g.ldc = m->width[l + 1];
+    if (l < L - 1) {
+      g.Cb = at<bf16_t>(m, m->oXb[l + 1]);
+      MCHK((gemm<true, true, EPI_FWD_GELU>(g, at<float>(m, m->oPart), st)));
+    } else {
+      g.Y = y;
+      g.out_scale = m->out_scale;
+      MCHK((gemm<true, true, EPI_FWD_LIN>(g, at<float>(m, m->oPart), st)));
+    }
+  }
+  m->have_z = (y == nullptr);
+  m->last_batch = B;
+  m->last_idx = idx;
+  m->last_nrows = nrows;
+  return PMDG_OK;
+}
+
+static pmdg_status mlp_backward_dev(pmdg_mlp* m, const float* t, const int* idx, int nrows, int B, hipStream_t st) {
+  const int L = m->L, nout = m->width[L];
+  hipLaunchKernelGGL(k_loss, dim3(B), dim3(256), 0, st, at<float>(m, m->oZ[L - 1]), t, idx, nrows, B, nout,
+                     1.0f / m->out_scale, at<float>(m, m->odZ[L - 1]), at<bf16_t>(m, m->odZb[L - 1]),
+                     at<float>(m, m->oRowErr), at<float>(m, m->oRowNorm));
+  MCHK(hipGetLastError());
+  for (int l = L - 1; l >= 0; --l) {
+    const int n = m->width[l + 1], k = m->kin[l];
+    {  // dW_l [n][k] = dz_l^T x_l
+      GemmArgs g;
+      memset(&g, 0, sizeof(g));
+      g.M = n; g.N = k; g.K = B;
+      g.A = at<bf16_t>(m, m->odZb[l]); g.lda = n;
+      g.B = at<bf16_t>(m, m->oXb[l]); g.ldb = k;
+      g.Cf = at<float>(m, m->odW[l]); g.ldc = k;
+      MCHK((gemm<false, false, EPI_DW>(g, at<float>(m, m->oPart), st)));
+    }
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)nblk(n, 64)), dim3(256), 0, st, at<float>(m, m->odZ[l]), B, n,
+                       at<float>(m, m->odb[l]));
+    MCHK(hipGetLastError());
+    if (l > 0) {  // dz_{l-1} [B][width_l] = (dz_l W_l) * gelu'(z_{l-1})
+      GemmArgs g;
+      memset(&g, 0, sizeof(g));
+      g.M = B; g.N = m->width[l]; g.K = n;
+      g.A = at<bf16_t>(m, m->odZb[l]); g.lda = n;
+      g.B = at<bf16_t>(m, m->oWb[l]); g.ldb = k;
+      g.Cf = at<float>(m, m->odZ[l - 1]); g.Cb = at<bf16_t>(m, m->odZb[l - 1]); g.ldc = m->width[l];
+      g.Zprev = at<float>(m, m->oZ[l - 1]);
+      MCHK((gemm<true, false, EPI_DX_GELU>(g, at<float>(m, m->oPart), st)));
+    }
+  }
+  return PMDG_OK;
+}
+
+static pmdg_status copy_out(pmdg_mlp* m, const std::vector<size_t>& oW, const std::vector<size_t>& ob, float* host) {
+  float* p = host;
+  for (int l = 0; l < m->L; ++l) {
+    const int no = m->width[l + 1], ni = m->width[l], kp = m->kin[l];
+    std::vector<float> w((size_t)no * kp);
+    MCHK(hipMemcpy(w.data(), at<float>(m, oW[l]), w.size() * 4, hipMemcpyDeviceToHost));
+    for (int r = 0; r < no; ++r)
+      for (int c = 0; c < ni; ++c) p[(size_t)r * ni + c] = w[(size_t)r * kp + c];
+    p += (size_t)no * ni;
+    MCHK(hipMemcpy(p, at<float>(m, ob[l]), (size_t)no * 4, hipMemcpyDeviceToHost));
+    p += no;
+  }
+  return PMDG_OK;
+}
+
+extern "C" {
+
+pmdg_status pmdg_mlp_create(int nlayers, const int* widths, pmdg_mlp** out) {
+  if (!out) return mfail(PMDG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (nlayers < 1 || nlayers > 16 || !widths) return mfail(PMDG_EINVAL, "nlayers must be in [1, 16]");
+  for (int l = 0; l <= nlayers; ++l)
+    if (widths[l] < 1 || widths[l] > (1 << 20)) return mfail(PMDG_EINVAL, "widths must be in [1, 2^20]");
+  for (int l = 1; l <= nlayers; ++l)
+    if (widths[l] % 8) return mfail(PMDG_EINVAL, "hidden and output widths must be multiples of 8");
+  pmdg_mlp* m = new (std::nothrow) pmdg_mlp();
+  if (!m) return mfail(PMDG_ENOMEM, "out of host memory");
+  m->L = nlayers;
+  m->width.assign(widths, widths + nlayers + 1);
+  m->kin.resize(nlayers);
+  for (int l = 0; l < nlayers; ++l) m->kin[l] = (m->width[l] + 31) / 32 * 32;
+  for (int l = 0; l < nlayers; ++l) m->nparams += (long)m->width[l + 1] * (m->width[l] + 1);
+  m->shift.assign(m->kin[0], 0.f);
+  m->scale.assign(m->kin[0], 1.f);
+  *out = m;
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_mlp_num_params(pmdg_mlp* m, long* n) {
+  if (!m || !n) return mfail(PMDG_EINVAL, "NULL argument");
+  *n = m->nparams;
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_mlp_workspace_size(pmdg_mlp* m, int max_batch, size_t* bytes) {
+  if (!m || !bytes) return mfail(PMDG_EINVAL, "NULL argument");
+  if (m->bound) return mfail(PMDG_ESTATE, "already bound");
+  if (max_batch < 8 || max_batch % 8 || max_batch > (1 << 16))
+    return mfail(PMDG_EINVAL, "max_batch must be a multiple of 8 in [8, 65536]");
+  m->max_batch = max_batch;
+  mlp_layout(m);
+  *bytes = m->bytes;
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_mlp_bind(pmdg_mlp* m, void* dev, size_t bytes, void* stream) {
+  if (!m) return mfail(PMDG_EINVAL, "NULL model");
+  if (m->bound) return mfail(PMDG_ESTATE, "already bound");
+  if (m->max_batch == 0) return mfail(PMDG_ESTATE, "call pmdg_mlp_workspace_size first");
+  if (!dev || ((uintptr_t)dev & 255)) return mfail(PMDG_EINVAL, "workspace must be 256-byte aligned");
+  if (bytes < m->bytes) return mfail(PMDG_ENOMEM, "workspace too small: need " + std::to_string(m->bytes));
+  hipStream_t st = (hipStream_t)stream;
+  m->ws = (char*)dev;
+  MCHK(hipMemsetAsync(m->ws, 0, m->bytes, st));
+  MCHK(hipMemcpyAsync(at<float>(m, m->oShift), m->shift.data(), 4 * m->shift.size(), hipMemcpyHostToDevice, st));
+  MCHK(hipMemcpyAsync(at<float>(m, m->oScale), m->scale.data(), 4 * m->scale.size(), hipMemcpyHostToDevice, st));
+  MCHK(hipStreamSynchronize(st));
+  m->bound = true;
+  m->adam_t = 0;
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_mlp_set_io_map(pmdg_mlp* m, const float* shift, const float* scale, float out_scale, void* stream) {
+  if (!m || !shift || !scale) return mfail(PMDG_EINVAL, "NULL argument");
+  if (!(out_scale > 0.f) || !std::isfinite(out_scale)) return mfail(PMDG_EINVAL, "out_scale must be finite and > 0");
+  for (int c = 0; c < m->width[0]; ++c)
+    if (!std::isfinite(shift[c]) || !std::isfinite(scale[c])) return mfail(PMDG_EINVAL, "non-finite input map");
+  for (int c = 0; c < m->width[0]; ++c) {
+    m->shift[c] = shift[c];
+    m->scale[c] = scale[c];
+  }
+  m->out_scale = out_scale;
+  if (m->bound) {
+    hipStream_t st = (hipStream_t)stream;
+    MCHK(hipMemcpyAsync(at<float>(m, m->oShift), m->shift.data(), 4 * m->shift.size(), hipMemcpyHostToDevice, st));
+    MCHK(hipMemcpyAsync(at<float>(m, m->oScale), m->scale.data(), 4 * m->scale.size(), hipMemcpyHostToDevice, st));
+    MCHK(hipStreamSynchronize(st));
+  }
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_mlp_set_params(pmdg_mlp* m, const float* host, void* stream) {
+  if (!m || !host) return mfail(PMDG_EINVAL, "NULL argument");
+  if (!m->bound) return mfail(PMDG_ESTATE, "model not bound");
+  hipStream_t st = (hipStream_t)stream;
+  MCHK(hipStreamSynchronize(st));
+  const float* p = host;
+  for (int l = 0; l < m->L; ++l) {
+    const int no = m->width[l + 1], ni = m->width[l], kp = m->kin[l];
+    std::vector<float> w((size_t)no * kp, 0.f);
+    for (int r = 0; r < no; ++r)
+      for (int c = 0; c < ni; ++c) w[(size_t)r * kp + c] = p[(size_t)r * ni + c];
+    p += (size_t)no * ni;
+    MCHK(hipMemcpy(at<float>(m, m->oW[l]), w.data(), w.size() * 4, hipMemcpyHostToDevice));
+    MCHK(hipMemcpy(at<float>(m, m->ob[l]), p, (size_t)no * 4, hipMemcpyHostToDevice));
+    p += no;
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)nblk((long)w.size(), 256)), dim3(256), 0, st,
+                       at<float>(m, m->oW[l]), at<bf16_t>(m, m->oWb[l]), (long)w.size());
+    MCHK(hipGetLastError());
+  }
+  // fresh optimiser state
+  for (int l = 0; l < m->L; ++l) {
+    const size_t nw = (size_t)m->width[l + 1] * m->kin[l], nb = m->width[l + 1];
+    MCHK(hipMemsetAsync(at<float>(m, m->omW[l]), 0, 4 * nw, st));
+    MCHK(hipMemsetAsync(at<float>(m, m->ovW[l]), 0, 4 * nw, st));
+    MCHK(hipMemsetAsync(at<float>(m, m->omb[l]), 0, 4 * nb, st));
+    MCHK(hipMemsetAsync(at<float>(m, m->ovb[l]), 0, 4 * nb, st));
+  }
+  m->adam_t = 0;
+  MCHK(hipStreamSynchronize(st));
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_mlp_get_params(pmdg_mlp* m, float* host, void* stream) {
+  if (!m || !host) return mfail(PMDG_EINVAL, "NULL argument");
+  if (!m->bound) return mfail(PMDG_ESTATE, "model not bound");
+  MCHK(hipStreamSynchronize((hipStream_t)stream));
+  return copy_out(m, m->oW, m->ob, host);
+}
+
+pmdg_status pmdg_mlp_get_grads(pmdg_mlp* m, float* host, void* stream) {
+  if (!m || !host) return mfail(PMDG_EINVAL, "NULL argument");
+  if (!m->bound) return mfail(PMDG_ESTATE, "model not bound");
+  MCHK(hipStreamSynchronize((hipStream_t)stream));
+  return copy_out(m, m->odW, m->odb, host);
+}
+
+pmdg_status pmdg_mlp_forward(pmdg_mlp* m, const float* u, const int* idx, int nrows, int B, float* y, void* stream) {
+  if (!m || !u) return mfail(PMDG_EINVAL, "NULL argument");
+  pmdg_status r = check_batch(m, idx, nrows, B);
+  if (r) return r;
+  return mlp_forward_dev(m, u, idx, nrows, B, y, (hipStream_t)stream);
+}
+
+pmdg_status pmdg_mlp_backward(pmdg_mlp* m, const float* t, int B, float* rowerr, float* rownorm, void* stream) {
+  if (!m || !t) return mfail(PMDG_EINVAL, "NULL argument");
+  pmdg_status r = check_batch(m, m->last_idx, m->last_nrows, B);
+  if (r) return r;
+  if (!m->have_z || m->last_batch != B)
+    return mfail(PMDG_ESTATE, "backward needs a preceding training forward (y == NULL) of the same batch");
+  hipStream_t st = (hipStream_t)stream;
+  if ((r = mlp_backward_dev(m, t, m->last_idx, m->last_nrows, B, st))) return r;
+  if (rowerr) MCHK(hipMemcpyAsync(rowerr, at<float>(m, m->oRowErr), (size_t)B * 4, hipMemcpyDeviceToDevice, st));
+  if (rownorm) MCHK(hipMemcpyAsync(rownorm, at<float>(m, m->oRowNorm), (size_t)B * 4, hipMemcpyDeviceToDevice, st));
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_mlp_adam(pmdg_mlp* m, float lr, float b1, float b2, float eps, void* stream) {
+  if (!m) return mfail(PMDG_EINVAL, "NULL model");
+  if (!m->bound) return mfail(PMDG_ESTATE, "model not bound");
+  if (!(lr >= 0.f) || !(b1 >= 0.f && b1 < 1.f) || !(b2 >= 0.f && b2 < 1.f) || !(eps > 0.f))
+    return mfail(PMDG_EINVAL, "need lr >= 0, 0 <= b1, b2 < 1, eps > 0");
+  hipStream_t st = (hipStream_t)stream;
+  m->adam_t += 1;
+  const float c1 = (float)(1.0 - std::pow((double)b1, m->adam_t));
+  const float c2 = (float)(1.0 - std::pow((double)b2, m->adam_t));
+  for (int l = 0; l < m->L; ++l) {
+    const long nw = (long)m->width[l + 1] * m->kin[l], nb = m->width[l + 1];
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)nblk(nw, 256)), dim3(256), 0, st, at<float>(m, m->oW[l]),
+                       at<float>(m, m->odW[l]), at<float>(m, m->omW[l]), at<float>(m, m->ovW[l]),
+                       at<bf16_t>(m, m->oWb[l]), nw, lr, b1, b2, eps, c1, c2);
+    MCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)nblk(nb, 256)), dim3(256), 0, st, at<float>(m, m->ob[l]),
+                       at<float>(m, m->odb[l]), at<float>(m, m->omb[l]), at<float>(m, m->ovb[l]), (bf16_t*)nullptr,
+                       nb, lr, b1, b2, eps, c1, c2);
+    MCHK(hipGetLastError());
+  }
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_mlp_train_step(pmdg_mlp* m, const float* u, const float* t, const int* idx, int nrows, int B,
+                                float lr, float b1, float b2, float eps, float* rowerr, float* rownorm, void* stream) {
+  if (!m || !u || !t) return mfail(PMDG_EINVAL, "NULL argument");
+  pmdg_status r = check_batch(m, idx, nrows, B);
+  if (r) return r;
+  hipStream_t st = (hipStream_t)stream;
+  if ((r = mlp_forward_dev(m, u, idx, nrows, B, nullptr, st))) return r;
+  if ((r = pmdg_mlp_backward(m, t, B, rowerr, rownorm, stream))) return r;
+  return pmdg_mlp_adam(m, lr, b1, b2, eps, stream);
+}
+
+pmdg_status pmdg_mlp_pair_combine(const float* a, const float* b, int B, int n, float* mean, float* spread,
+                                  void* stream) {
+  if (!a || !b || !mean || !spread) return mfail(PMDG_EINVAL, "NULL argument");
+  if (B < 1 || n < 4 || n % 4) return mfail(PMDG_EINVAL, "need B >= 1 and n a positive multiple of 4");
+  if (((uintptr_t)a | (uintptr_t)b | (uintptr_t)mean) & 15) return mfail(PMDG_EINVAL, "arrays must be 16-byte aligned");
+  hipLaunchKernelGGL(k_pair_combine, dim3(B), dim3(256), 0, (hipStream_t)stream, a, b, n, mean, spread);
+  MCHK(hipGetLastError());
+  return PMDG_OK;
+}
+
+void pmdg_mlp_destroy(pmdg_mlp* m) { delete m; }
+
+}  // extern "C"

@@ -26,6 +26,10 @@ static pmdg_status fail(pmdg_status s, const std::string& m) {
   return s;
 }
 
+namespace pmdg {
+void set_last_error(const std::string& m) { g_err = m; }
+}  // namespace pmdg
+
 #define HIPCHK(call)                                                                          \
   do {                                                                                        \
     hipError_t e_ = (call);                                                                   \

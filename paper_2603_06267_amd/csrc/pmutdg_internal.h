@@ -5,8 +5,12 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <string>
 
 namespace pmdg {
+
+// Sets the thread-local message returned by pmdg_last_error().
+void set_last_error(const std::string& m);
 
 constexpr int kMaxOrder = 8;                // polynomial order N <= 8
 constexpr int kMaxNq = kMaxOrder + 1;       // Gauss points per direction on Gamma_I

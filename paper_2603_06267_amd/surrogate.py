@@ -1,0 +1,171 @@
+"""Surrogate form: a network trained on runs of the solver itself that maps a
+PMUT array's drive parameters (16 per-PMUT phases, frequency, amplitude) to
+its receiver traces (64 receivers x 512 samples), with a calibrated error
+estimate and the solver as fallback.
+
+  data       the GPU solver (FP32 state, FP64 modal ODE and traces) on the
+             seeded scenarios of the surrogate data set, one batched launch
+  network    18 -> 512 -> 512 -> 512 -> 512 -> 32768, GELU, trained by the
+             library's BF16-MFMA forward / backward / Adam kernels
+  estimate   a two-member ensemble (different initialisations and minibatch
+             orders); its spread |y_1 - y_2| / |(y_1 + y_2) / 2|, scaled by the
+             split-conformal quantile of (true error / spread) on a held-out
+             calibration set, bounds the relative L2 error of the ensemble
+             mean with the stated coverage
+  fallback   scenarios whose estimate exceeds the tolerance (2% relative L2)
+             are re-run by the solver; the solver's traces replace them
+
+Host code here is control flow (minibatch order, learning-rate schedule,
+quantiles over a few hundred numbers); every array operation of the path runs
+in libpmutdg's kernels."""
+import math
+import time
+
+import numpy as np
+
+from . import mlp as _mlp
+from . import solver as _solver
+from . import workloads as W
+
+WIDTHS = [18, 512, 512, 512, 512, 32768]
+N_PMUT = 16
+TOL = 0.02
+
+
+def input_map():
+    """Affine map of the raw features onto [-1, 1]: phases in [0, 2 pi),
+    frequency in [1.5, 3] MHz, amplitude in [0.5, 1]."""
+    shift = np.array([math.pi] * N_PMUT + [2.25, 0.75], dtype=np.float32)
+    scale = np.array([1.0 / math.pi] * N_PMUT + [1.0 / 0.75, 4.0], dtype=np.float32)
+    return shift, scale
+
+
+def drive_from_features(F):
+    """Drive description of the solver for feature rows [phase x16, freq, amp]."""
+    F = np.asarray(F, dtype=np.float64)
+    return {"amp": np.repeat(F[:, 17:18], N_PMUT, axis=1), "phase": F[:, :N_PMUT].copy(), "freq": F[:, 16].copy(),
+            "ncyc": 3.0, "envelope": 0}
+
+
+def solve(F, steps=512, device="cuda", stream=None, max_scenarios=4096):
+    """Runs the plain GPU solver for feature rows F; returns device FP32 traces
+    [len(F), R * steps] (receiver-major).  Scenarios go in launches of at most
+    max_scenarios."""
+    import torch
+    base = W.batch_geometry()
+    sf = W.shape_fn(base)
+    out = []
+    for i0 in range(0, len(F), max_scenarios):
+        wl = dict(base, drive=drive_from_features(F[i0:i0 + max_scenarios]))
+        g = _solver.from_workload(wl, precision=32, n_steps=steps, shape_fn=sf, device=device)
+        g.step(steps, stream)
+        tr = g.read_traces(stream)
+        out.append(torch.from_numpy(tr.reshape(tr.shape[0], -1).astype(np.float32)).to(device))
+        g.close()
+    return torch.cat(out) if len(out) > 1 else out[0]
+
+
+class Surrogate:
+    def __init__(self, n_members=2, max_batch=1024, seed=0, device="cuda", widths=None):
+        self.widths = list(widths or WIDTHS)
+        self.members = [_mlp.MLP(self.widths, max_batch=max_batch, device=device) for _ in range(n_members)]
+        self.max_batch = max_batch
+        self.device = device
+        self.seed = seed
+        self.scale = None
+        self.out_scale = 1.0
+        self.history = []
+
+    # ---- training ---------------------------------------------------------
+    def fit(self, U, T, train_idx, steps=3000, batch=256, lr=1e-3, lr_final=1e-5, log=None, log_every=500):
+        """U [n, 18], T [n, n_out]: device FP32 tensors; train_idx: host ints.
+        Each member: He initialisation from its own seed, its own minibatch
+        order, Adam with a cosine learning-rate decay from lr to lr_final."""
+        import torch
+        shift, scl = input_map()
+        tr = torch.as_tensor(np.asarray(train_idx), dtype=torch.long, device=U.device)
+        self.out_scale = float(torch.sqrt((T[tr] ** 2).mean()).item())
+        err = torch.empty(batch, dtype=torch.float32, device=U.device)
+        nrm = torch.empty(batch, dtype=torch.float32, device=U.device)
+        ntr = len(train_idx)
+        t0 = time.perf_counter()
+        for k, m in enumerate(self.members):
+            rng = np.random.default_rng(self.seed + 1000 * k)
+            m.set_io_map(shift, scl, self.out_scale)
+            m.init_params(rng)
+            order = np.empty(0, dtype=np.int64)
+            for s in range(steps):
+                if len(order) < batch:
+                    order = np.concatenate([order, np.asarray(train_idx)[rng.permutation(ntr)]])
+                idx = torch.as_tensor(order[:batch].astype(np.int32), device=U.device)
+                order = order[batch:]
+                a = lr_final + 0.5 * (lr - lr_final) * (1 + math.cos(math.pi * s / steps))
+                m.train_step(U, T, idx, a, rowerr=err, rownorm=nrm)
+                if log and (s % log_every == 0 or s == steps - 1):
+                    rel = torch.sqrt(err / nrm).median().item()
+                    self.history.append((k, s, rel))
+                    log(f"member {k} step {s}: minibatch median rel L2 {rel:.4f} "
+                        f"({time.perf_counter() - t0:.1f} s)")
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    # ---- inference --------------------------------------------------------
+    def predict(self, U, idx=None, out=None, stream=None):
+        """Ensemble mean [B, n_out] and raw spread |y1 - y2| / |mean| per row."""
+        import torch
+        B = int(idx.shape[0]) if idx is not None else int(U.shape[0])
+        assert B <= self.max_batch and B % 8 == 0
+        ys = [m.forward(U, idx=idx, stream=stream) for m in self.members]
+        if len(ys) == 1:
+            return ys[0], torch.zeros(B, device=U.device)
+        return _mlp.pair_combine(ys[0], ys[1], mean=ys[0] if out is None else out, stream=stream)
+
+    def calibrate(self, U, T, cal_idx, coverage=0.95):
+        """Split-conformal scale: the ceil((n + 1) coverage)-th smallest of
+        (true relative error / spread) over the calibration rows."""
+        import torch
+        err, spread = self.errors(U, T, cal_idx)
+        r = np.sort(err / np.maximum(spread, 1e-12))
+        n = len(r)
+        k = min(n - 1, int(math.ceil((n + 1) * coverage)) - 1)
+        self.scale = float(r[k])
+        return self.scale
+
+    def errors(self, U, T, rows):
+        """True relative L2 error of the ensemble mean and its spread, per row
+        (host arrays); rows in batches of max_batch."""
+        import torch
+        errs, spreads = [], []
+        rows = np.asarray(rows)
+        for i0 in range(0, len(rows), self.max_batch):
+            r = rows[i0:i0 + self.max_batch]
+            pad = (-len(r)) % 8
+            rr = np.concatenate([r, np.repeat(r[-1:], pad)]) if pad else r
+            idx = torch.as_tensor(rr.astype(np.int32), device=U.device)
+            mean, spread = self.predict(U, idx=idx)
+            t = T[torch.as_tensor(rr, device=U.device)]
+            e = torch.linalg.vector_norm(mean - t, dim=1) / torch.linalg.vector_norm(t, dim=1)
+            errs.append(e[:len(r)].cpu().numpy())
+            spreads.append(spread[:len(r)].cpu().numpy())
+        return np.concatenate(errs), np.concatenate(spreads)
+
+    def estimate(self, spread):
+        return self.scale * spread
+
+    def infer(self, F, U=None, tol=TOL, stream=None):
+        """Traces for feature rows F (host [B, 18], B <= max_batch, multiple
+        of 8): ensemble mean where the calibrated estimate is <= tol, the
+        solver's traces elsewhere.  Returns (device traces, host mask of rows
+        sent to the solver, host estimates)."""
+        import torch
+        assert self.scale is not None, "calibrate first"
+        if U is None:
+            U = torch.as_tensor(np.asarray(F, dtype=np.float32), device=self.device)
+        mean, spread = self.predict(U, stream=stream)
+        est = (self.scale * spread).cpu().numpy()
+        mask = est > tol
+        if mask.any():
+            rows = np.nonzero(mask)[0]
+            sol = solve(np.asarray(F)[rows], stream=stream)
+            mean[torch.as_tensor(rows, device=mean.device)] = sol
+        return mean, mask, est

@@ -97,3 +97,36 @@ def test_workspace_grows_with_scenarios():
     a = solver.Solver(wl["domains"], n_scenarios=1, trace_capacity=8)
     b = solver.Solver(wl["domains"], n_scenarios=4, trace_capacity=8)
     assert b.workspace_size() > 3 * a.workspace_size() // 2
+
+
+def test_mlp_host_checks():
+    """Surrogate network entry points: argument and state errors raised on the
+    host before any device work."""
+    import ctypes
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+
+    def create(widths):
+        arr = (ctypes.c_int * len(widths))(*widths)
+        return L.pmdg_mlp_create(len(widths) - 1, arr, ctypes.byref(h))
+
+    assert create([18, 512, 30]) == _lib.PMDG_EINVAL      # output width not a multiple of 8
+    assert create([18, 0, 32]) == _lib.PMDG_EINVAL
+    assert L.pmdg_mlp_create(0, None, ctypes.byref(h)) == _lib.PMDG_EINVAL
+    assert create([18, 512, 512, 512, 512, 32768]) == _lib.PMDG_OK
+    n = ctypes.c_long()
+    assert L.pmdg_mlp_num_params(h, ctypes.byref(n)) == _lib.PMDG_OK
+    assert n.value == 17_607_680
+    sz = ctypes.c_size_t()
+    assert L.pmdg_mlp_workspace_size(h, 1020, ctypes.byref(sz)) == _lib.PMDG_EINVAL
+    assert L.pmdg_mlp_workspace_size(h, 1024, ctypes.byref(sz)) == _lib.PMDG_OK
+    assert sz.value > 4 * 17_607_680 * 5
+    # not bound: every compute call is a state error
+    x = ctypes.c_void_p(256)
+    assert L.pmdg_mlp_forward(h, x, None, 1024, 1024, x, None) == _lib.PMDG_ESTATE
+    assert L.pmdg_mlp_adam(h, 1e-3, 0.9, 0.999, 1e-8, None) == _lib.PMDG_ESTATE
+    assert L.pmdg_mlp_bind(h, ctypes.c_void_p(0x100001), sz.value, None) == _lib.PMDG_EINVAL
+    assert L.pmdg_mlp_pair_combine(None, x, 8, 32, x, x, None) == _lib.PMDG_EINVAL
+    assert L.pmdg_mlp_pair_combine(x, x, 8, 30, x, x, None) == _lib.PMDG_EINVAL
+    L.pmdg_mlp_destroy(h)
+    L.pmdg_mlp_destroy(None)

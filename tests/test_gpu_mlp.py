@@ -1,0 +1,195 @@
+"""GPU checks of the surrogate network kernels (BF16 MFMA GEMMs with FP32
+accumulation, GELU epilogues, loss, split-K reductions, Adam) through the
+C ABI against the FP64 NumPy oracle (oracle/mlp_ref.py).
+
+Tolerances: where every operand is a short dyadic number the BF16 products
+and their FP32 sums are exact, so the GPU must equal the oracle bit for bit;
+otherwise each BF16 rounding of an activation, weight or output gradient
+(unit roundoff 2^-9) contributes independently and the relative L2 error
+over a layer stays near 2^-9 sqrt(depth): 1e-2 for outputs, 3e-2 for
+gradients."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import mlp_ref as R
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def _dev(a, dtype=None):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype or torch.float32, device="cuda")
+
+
+def _dyadic(rng, shape, num, den):
+    return rng.integers(-num, num + 1, size=shape).astype(np.float64) / den
+
+
+def _model(widths, max_batch):
+    from paper_2603_06267_amd import mlp
+    return mlp.MLP(widths, max_batch=max_batch)
+
+
+@pytest.mark.parametrize("widths,B", [([40, 264], 136), ([2048, 64], 64), ([96, 520], 1000)])
+def test_linear_layer_bit_exact(widths, B):
+    """One linear layer with dyadic inputs, weights and biases: ragged tiles
+    in every dimension, a split-K launch ([2048, 64] at batch 64) and an
+    input width padded from 40/96 to a multiple of 32."""
+    _say(f"linear exact widths={widths} B={B}")
+    rng = np.random.default_rng(1)
+    W = _dyadic(rng, (widths[1], widths[0]), 4, 16)
+    b = _dyadic(rng, widths[1], 8, 8)
+    u = _dyadic(rng, (B, widths[0]), 2, 4)
+    m = _model(widths, max_batch=max(B, 8))
+    m.set_params(R.flatten([(W, b)]))
+    y = m.forward(_dev(u)).cpu().numpy()
+    ref, _ = R.forward([(W, b)], u)
+    assert np.array_equal(y.astype(np.float64), ref)
+
+
+def test_linear_layer_backward_and_adam_exact():
+    """Dyadic residuals make dY = 2 (y - t) / (B n) exact in BF16, hence dW and
+    db exact in FP32; one Adam step then matches the oracle to FP32 rounding."""
+    rng = np.random.default_rng(2)
+    n_in, n_out, B = 32, 128, 64
+    W = _dyadic(rng, (n_out, n_in), 4, 16)
+    b = _dyadic(rng, n_out, 8, 8)
+    u = _dyadic(rng, (B, n_in), 2, 4)
+    y, cache = R.forward([(W, b)], u)
+    t = y - _dyadic(rng, (B, n_out), 3, 8)
+    gW, gb = R.backward([(W, b)], cache, y, t)[0]
+    m = _model([n_in, n_out], 64)
+    m.set_params(R.flatten([(W, b)]))
+    ud, td = _dev(u), _dev(t)
+    m.forward(ud, y=False)
+    m.backward(td, B)
+    g = m.get_grads()
+    assert np.array_equal(g.astype(np.float64), R.flatten([(gW, gb)]))
+    m.adam(1e-2, 0.9, 0.999, 1e-8)
+    p = m.get_params().astype(np.float64)
+    opt = R.Adam([(W, b)], lr=1e-2)
+    exp = R.flatten(opt.step([(W, b)], [(gW, gb)]))
+    assert np.abs(p - exp).max() <= 1e-6 * max(1.0, np.abs(exp).max())
+
+
+def _twin(widths, B, seed):
+    rng = np.random.default_rng(seed)
+    params = R.init_params(widths, rng)
+    params = [(W.astype(np.float32).astype(np.float64), (0.1 * rng.standard_normal(b.shape)).astype(np.float32)
+               .astype(np.float64)) for W, b in params]
+    u = rng.uniform(-1, 1, (B, widths[0]))
+    t = rng.standard_normal((B, widths[-1])) * 0.5
+    return params, u, t
+
+
+@pytest.mark.parametrize("widths,B", [([18, 64, 64, 64, 64, 256], 64), ([18, 512, 512, 512, 512, 32768], 64)])
+def test_gradients_against_oracle(widths, B):
+    """Reduced-width twin and one full-size minibatch: every layer's weight
+    and bias gradient against the FP64 oracle."""
+    _say(f"gradients widths={widths} B={B}")
+    params, u, t = _twin(widths, B, 3)
+    m = _model(widths, B)
+    m.set_params(R.flatten(params))
+    m.forward(_dev(u), y=False)
+    m.backward(_dev(t), B)
+    g = m.get_grads().astype(np.float64)
+    y, cache = R.forward(params, u)
+    gr = R.backward(params, cache, y, t)
+    o = 0
+    for l, (gW, gb) in enumerate(gr):
+        nW, nb = gW.size, gb.size
+        eW = rel_l2(g[o:o + nW], gW.ravel())
+        eb = rel_l2(g[o + nW:o + nW + nb], gb)
+        _say(f"  layer {l}: dW rel L2 {eW:.2e}, db rel L2 {eb:.2e}")
+        assert eW < 3e-2 and eb < 3e-2
+        o += nW + nb
+
+
+def test_forward_full_size_inference_batch():
+    """Inference at the surrogate's size (batch 1024) with the input map and
+    output scale, checked on sampled rows against the oracle."""
+    import math
+    widths = [18, 512, 512, 512, 512, 32768]
+    params, _, _ = _twin(widths, 8, 4)
+    rng = np.random.default_rng(5)
+    F = np.concatenate([rng.uniform(0, 2 * math.pi, (1024, 16)), rng.uniform(1.5, 3, (1024, 1)),
+                        rng.uniform(0.5, 1, (1024, 1))], axis=1)
+    shift = np.array([math.pi] * 16 + [2.25, 0.75])
+    scale = np.array([1 / math.pi] * 16 + [1 / 0.75, 4.0])
+    m = _model(widths, 1024)
+    m.set_params(R.flatten(params))
+    m.set_io_map(shift, scale, 0.25)
+    y = m.forward(_dev(F)).cpu().numpy()
+    assert np.isfinite(y).all()
+    rows = rng.choice(1024, 24, replace=False)
+    ref, _ = R.forward(params, F[rows], shift.astype(np.float32).astype(np.float64),
+                       scale.astype(np.float32).astype(np.float64))
+    err = rel_l2(y[rows], 0.25 * ref)
+    _say(f"  sampled rows rel L2 {err:.2e}")
+    assert err < 1e-2
+
+
+def test_gather_rows_equals_contiguous():
+    import torch
+    widths = [18, 64, 64, 128]
+    params, u, t = _twin(widths, 48, 6)
+    m = _model(widths, 48)
+    m.set_params(R.flatten(params))
+    ud = _dev(u)
+    perm = np.random.default_rng(0).permutation(48)[:40].astype(np.int32)
+    y1 = m.forward(ud, idx=_dev(perm, torch.int32)).cpu().numpy()
+    y2 = m.forward(_dev(u[perm])).cpu().numpy()
+    assert np.array_equal(y1, y2)
+
+
+def test_training_follows_oracle():
+    """The same twin, initialisation and minibatch sequence trained on the GPU
+    and by the oracle: losses agree along the way and both fall by 10x."""
+    import torch
+    widths = [4, 64, 64, 64]
+    rng = np.random.default_rng(8)
+    params = [(W.astype(np.float32).astype(np.float64), b) for W, b in R.init_params(widths, rng)]
+    u = rng.uniform(-1, 1, (512, 4))
+    t = np.stack([np.sin(2 * u[:, 0] + u[:, 1] * k / 16) * np.cos(u[:, 2] - k / 32) + 0.3 * u[:, 3]
+                  for k in range(64)], axis=1)
+    m = _model(widths, 64)
+    m.set_params(R.flatten(params))
+    ud, td = _dev(u), _dev(t)
+    err = torch.empty(64, dtype=torch.float32, device="cuda")
+    nrm = torch.empty(64, dtype=torch.float32, device="cuda")
+    opt = R.Adam(params, lr=2e-3)
+    p = params
+    gl, ol = [], []
+    for s in range(300):
+        idx = rng.permutation(512)[:64]
+        m.train_step(ud, td, _dev(idx.astype(np.int32), torch.int32), 2e-3, rowerr=err, rownorm=nrm)
+        gl.append(float(err.sum().item()) / (64 * 64))
+        p, l = R.train_step(p, opt, u[idx], t[idx])
+        ol.append(l)
+    _say(f"  loss gpu {gl[0]:.3e} -> {gl[-1]:.3e}, oracle {ol[0]:.3e} -> {ol[-1]:.3e}")
+    assert abs(gl[0] - ol[0]) < 1e-2 * ol[0]
+    assert gl[-1] < 0.1 * gl[0] and ol[-1] < 0.1 * ol[0]
+    assert np.mean(gl[-50:]) < 1.5 * np.mean(ol[-50:])
+
+
+def test_pair_combine():
+    rng = np.random.default_rng(9)
+    a = rng.standard_normal((24, 1024)).astype(np.float32)
+    b = (a + 0.01 * rng.standard_normal((24, 1024))).astype(np.float32)
+    from paper_2603_06267_amd import mlp
+    mean, spread = mlp.pair_combine(_dev(a), _dev(b))
+    mean = mean.cpu().numpy()
+    assert np.array_equal(mean, (0.5 * (a.astype(np.float64) + b)).astype(np.float32))
+    exp = np.linalg.norm(a.astype(np.float64) - b, axis=1) / np.linalg.norm(0.5 * (a.astype(np.float64) + b), axis=1)
+    assert np.abs(spread.cpu().numpy() - exp).max() < 1e-5 * exp.max()
