@@ -34,7 +34,7 @@ def measured_traffic(rows, zchunk):
     FETCH_SIZE / WRITE_SIZE passes, if the kernel sources and tile shape are
     still the ones those counters were taken with; else None."""
     import hashlib
-    if (rows, zchunk) != (2, 33) or not os.path.exists(COUNTERS):
+    if (rows, zchunk) != (2, 73) or not os.path.exists(COUNTERS):
         return None
     h = hashlib.sha256()
     for f in STIFF_SOURCES:
@@ -104,16 +104,133 @@ def run_gpu(wl, precision, steps, warmup, graphs, rows, zchunk):
     return el, el_graph, kt, finite
 
 
+def batched_leg(steps=512):
+    """Batched form on the batch workload (64 drive scenarios of the cube with
+    a 4x4 PMUT array + 16 uneven single-brick meshes, orders 3..6): one
+    persistent launch sequence per step for all of them, against the same 80
+    runs stepped one solver at a time (both as hipGraph replays, steps only)."""
+    import torch
+    from paper_2603_06267_amd import batch as B, solver, workloads as W
+    c4 = W.config4()
+    wls = [c4["scenarios"]] + c4["meshes"]
+    sfs = [W.shape_fn(w) for w in wls]
+    tuner = B.TileTuner(candidates=[(1, 17), (2, 17), (2, 33), (1, 0), (2, 0)])
+    t0 = time.perf_counter()
+    b = B.build_batch(wls, shape_fns=sfs, tuner=tuner, n_steps=steps)
+    setup = time.perf_counter() - t0
+    b.step(8)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    b.step(steps - 8)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    nsc = sum(len(w["drive"]["amp"]) for w in wls)
+    singles = []
+    for w, sf in zip(wls, sfs):
+        for sc in range(len(w["drive"]["amp"])):
+            singles.append(solver.from_workload(w, precision=32, n_steps=steps, scenarios=[sc], shape_fn=sf))
+    for s1 in singles:
+        s1.step(8)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for s1 in singles:
+        s1.step(steps - 8)
+    torch.cuda.synchronize()
+    el2 = time.perf_counter() - t
+    frac = (steps - 8) / steps
+    return {"workload": "64 scenarios (cube, 4x4 PMUTs, 3 modes) + 16 meshes 8x8x4..24x24x8 N=3..6, 512 steps",
+            "scenarios": nsc, "batched_scenarios_per_s": nsc * frac / el, "loop_scenarios_per_s": nsc * frac / el2,
+            "speedup": el2 / el, "setup_and_tuning_s": setup, "tiles": {k: v["best"] for k, v in tuner.cache.items()}}
+
+
+def surrogate_leg(runs, steps, log):
+    """Surrogate form: data from the GPU solver, two members trained by the
+    library's BF16-MFMA kernels, split-conformal calibration, then inference
+    with solver fallback at 2% relative L2 on the held-out test scenarios and
+    a 1024-scenario batch, against the plain solver."""
+    import torch
+    from paper_2603_06267_amd import surrogate as S, workloads as W
+    c5 = W.config5()
+    F = c5["features"]
+    if runs > len(F):
+        rng = np.random.default_rng(W.SEED0 + 55)
+        ph, fr, am = W.scenario_params(rng, runs - len(F))
+        F = np.concatenate([F, np.concatenate([ph, fr[:, None], am[:, None]], 1)])
+    t0 = time.perf_counter()
+    T = S.solve(F)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    U = torch.as_tensor(F.astype(np.float32), device="cuda")
+    train = np.concatenate([np.arange(3584), np.arange(4096, len(F))])
+    cal, test = np.arange(3584, 3840), np.arange(3840, 4096)
+    sur = S.Surrogate(n_members=2, n_fourier=8)
+    t_train = sur.fit(U, T, train, steps=steps, log=log, log_every=max(1, steps // 4))
+    scale = sur.calibrate(U, T, cal)
+    err, spread = sur.errors(U, T, test)
+    est = sur.estimate(spread)
+    # inference with fallback on the 256 test scenarios, at the 2% tolerance
+    # and, for context, at looser ones
+    tt = T[torch.as_tensor(test, device="cuda")]
+    by_tol = {}
+    for tol in (S.TOL, 0.05, 0.1, 0.2):
+        sur.infer(F[test[:8]], tol=tol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out, mask, _ = sur.infer(F[test], tol=tol)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        d = (torch.linalg.vector_norm(out - tt, dim=1) / torch.linalg.vector_norm(tt, dim=1)).cpu().numpy()
+        by_tol[f"{tol:g}"] = {"routed_to_solver": float(mask.mean()), "scenarios_per_s": len(test) / el,
+                              "delivered_share_above_tol": float(np.mean(d > tol))}
+        if tol == S.TOL:
+            t_inf, derr, mask2 = el, d, mask
+    # network alone, batch 1024
+    y = torch.empty((1024, T.shape[1]), device="cuda")
+    for _ in range(3):
+        sur.members[0].forward(U[:1024], y=y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        sur.predict(U[:1024])
+    torch.cuda.synchronize()
+    t_net = (time.perf_counter() - t0) / 10
+    # the plain solver: one scenario at a time (8 timed) and 1024 in one batched launch
+    t0 = time.perf_counter()
+    for r in range(8):
+        S.solve(F[r:r + 1])
+    torch.cuda.synchronize()
+    single = 8 / (time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    S.solve(F[:1024])
+    torch.cuda.synchronize()
+    batched = 1024 / (time.perf_counter() - t0)
+    pipeline = len(test) / t_inf
+    return {"workload": f"cube with 4x4 PMUTs, 64 receivers x 512 samples; {len(F)} solver runs "
+                        f"({len(train)} train, 256 calibration, 256 test)",
+            "data_s": t_data, "train_s": t_train, "train_steps_per_member": steps,
+            "test_rel_l2_median": float(np.median(err)), "test_rel_l2_p90": float(np.quantile(err, 0.9)),
+            "calibration_scale": scale, "coverage": float(np.mean(err <= est)),
+            "routed_to_solver": float(mask2.mean()), "delivered_rel_l2_median": float(np.median(derr)),
+            "delivered_share_above_2pct": float(np.mean(derr > S.TOL)),
+            "pipeline_scenarios_per_s": pipeline, "network_scenarios_per_s": 1024 / t_net,
+            "solver_single_scenarios_per_s": single, "solver_batched_scenarios_per_s": batched,
+            "gain_vs_single": pipeline / single, "gain_vs_batched": pipeline / batched, "by_tolerance": by_tol}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--rows", type=int, default=2)
-    ap.add_argument("--zchunk", type=int, default=33)
+    ap.add_argument("--zchunk", type=int, default=73)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 instantiation")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-form leg")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-form leg")
+    ap.add_argument("--surrogate-runs", type=int, default=4096)
+    ap.add_argument("--surrogate-steps", type=int, default=3000)
     ap.add_argument("--direct", action="store_true",
                     help="direct kernel launches instead of hipGraph replay (for counter collection)")
     args = ap.parse_args()
@@ -173,6 +290,12 @@ def main():
         out["fp64"] = {"value": dofs * args.steps / min(el64, elg64), "unit": "DOF-updates/s",
                        "stiff_ms": kt64[0], "achieved_GBs": 24.0 * (n0 + n1) / (kt64[0] * 1e-3) / 1e9,
                        "frac": 24.0 * (n0 + n1) / (kt64[0] * 1e-3) / 1e9 / PEAK_HBM_GBS}
+    if not args.no_batched:
+        log("batched form ...")
+        out["batched"] = batched_leg()
+    if not args.no_surrogate:
+        log("surrogate form ...")
+        out["surrogate"] = surrogate_leg(args.surrogate_runs, args.surrogate_steps, log)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         wl_cpu = W.config3(steps=args.cpu_steps)

@@ -177,6 +177,10 @@ pmdg_status pmdg_set_option(pmdg_solver* h, int option, long value);
  * pmdg_step call made with PMDG_OPT_TIMING set: [0] stiffness, [1] face,
  * [2] flux.  Timing uses HIP events on the stepping stream. */
 #define PMDG_OPT_TIMING 5
+/* Tile of the secondary brick alone: rows per wave (0 = as PMDG_OPT_TILE_ROWS)
+ * and planes per workgroup (-1 = as PMDG_OPT_TILE_ZCHUNK, 0 = whole brick). */
+#define PMDG_OPT_TILE_ROWS_SECONDARY 6
+#define PMDG_OPT_TILE_ZCHUNK_SECONDARY 7
 pmdg_status pmdg_kernel_times(pmdg_solver* h, double* ms3);
 
 /* Frees host resources (device memory is the caller's).  NULL is a no-op. */
@@ -208,18 +212,22 @@ pmdg_status pmdg_batch_step(pmdg_batch* b, int n, void* stream);
 void pmdg_batch_destroy(pmdg_batch* b);
 
 /* ---- Surrogate form -------------------------------------------------------
- * A fully connected network u[n_0] -> y[n_L] with GELU on the hidden layers
- * (gelu(z) = z Phi(z), Phi the standard normal distribution function) that
- * stands in for the solver on the map from drive parameters (per-PMUT
- * phases, frequency, amplitude) to receiver traces.  The GEMMs run on BF16
- * MFMA with FP32 accumulation; the parameters are FP32 masters with BF16
- * copies; training minimises the mean squared error with Adam (bias
- * corrected).  Input and output pass through fixed affine maps:
- *   x_0 = (u - shift) * scale per feature,  y_phys = out_scale * y.
- * All rows are row-major FP32; u[nrows][n_0], targets t[nrows][n_L],
- * outputs y[B][n_L].  Device pointers unless stated.  Errors: EINVAL for bad
- * sizes or pointers, ESTATE for calls out of order, EHIP for runtime
- * failures.  Calls that overlap on one model race (one stream per model). */
+ * A fully connected network with GELU on the hidden layers (gelu(z) =
+ * z Phi(z), Phi the standard normal distribution function) that stands in for
+ * the solver on the map from drive parameters (per-PMUT phases, frequency,
+ * amplitude) to receiver traces.  The GEMMs run on BF16 MFMA with FP32
+ * accumulation; the parameters are FP32 masters with BF16 copies; training
+ * minimises the mean squared error with Adam (bias corrected).
+ * Raw input rows u[n_u] pass through a fixed embedding into the n_0 network
+ * inputs: column c takes feature u[src[c]] either affinely, (u - shift) *
+ * scale, or as cos / sin (scale u + shift) (angles, Fourier features).  The
+ * physical output is out_scale * a * y, with a = 1 or a = u[amp_col] for an
+ * output known to be proportional to one
+ * feature.  All rows are row-major FP32; u[nrows][n_u], targets
+ * t[nrows][n_L], outputs y[B][n_L].  Device pointers unless stated.  Errors:
+ * EINVAL for bad sizes or pointers, ESTATE for calls out of order, EHIP for
+ * runtime failures.  Calls that overlap on one model race (one stream per
+ * model). */
 typedef struct pmdg_mlp pmdg_mlp;
 
 /* widths[nlayers + 1]: n_0 .. n_L; n_1 .. n_L multiples of 8; 1 <= nlayers <= 16. */
@@ -231,8 +239,12 @@ pmdg_status pmdg_mlp_num_params(pmdg_mlp* m, long* n);
 pmdg_status pmdg_mlp_workspace_size(pmdg_mlp* m, int max_batch, size_t* bytes);
 /* Binds caller-owned device memory (256-byte aligned), zeroes it. */
 pmdg_status pmdg_mlp_bind(pmdg_mlp* m, void* dev_ptr, size_t bytes, void* stream);
-/* Input map shift[n_0], scale[n_0] (host) and output scale (> 0). */
-pmdg_status pmdg_mlp_set_io_map(pmdg_mlp* m, const float* shift, const float* scale, float out_scale, void* stream);
+/* Input embedding (host arrays of ncols = n_0): src[c] in [0, n_u), op[c]
+ * 0 = (u - shift) * scale, 1 = cos(scale u + shift), 2 = sin(scale u +
+ * shift).  amp_col = -1 or the feature a; out_scale > 0.  Default: n_u =
+ * n_0, identity, amp_col = -1, out_scale = 1. */
+pmdg_status pmdg_mlp_set_io_map(pmdg_mlp* m, int n_u, int ncols, const int* src, const int* op, const float* shift,
+                                const float* scale, int amp_col, float out_scale, void* stream);
 /* Host parameters, per layer W_l [n_{l+1}][n_l] row-major then b_l; resets Adam. */
 pmdg_status pmdg_mlp_set_params(pmdg_mlp* m, const float* host, void* stream);
 pmdg_status pmdg_mlp_get_params(pmdg_mlp* m, float* host, void* stream);
@@ -240,10 +252,10 @@ pmdg_status pmdg_mlp_get_params(pmdg_mlp* m, float* host, void* stream);
 pmdg_status pmdg_mlp_get_grads(pmdg_mlp* m, float* host, void* stream);
 /* Forward pass of B rows (multiple of 8, <= max_batch).  Row r is u[idx[r]]
  * (idx clamped into [0, nrows)) or, with idx NULL, u[r] (nrows >= B).  With y
- * non-NULL writes out_scale * y there (inference); with y NULL keeps the
+ * non-NULL writes out_scale * a * y there (inference); with y NULL keeps the
  * normalised output for pmdg_mlp_backward (training). */
 pmdg_status pmdg_mlp_forward(pmdg_mlp* m, const float* u, const int* idx, int nrows, int B, float* y, void* stream);
-/* Gradients of (1 / (B n_L)) sum (y - t[row] / out_scale)^2 for the last
+/* Gradients of (1 / (B n_L)) sum (y - t[row] / (out_scale a))^2 for the last
  * training forward (same rows); per-row squared error and squared target
  * norm (normalised units) into rowerr[B], rownorm[B] if non-NULL. */
 pmdg_status pmdg_mlp_backward(pmdg_mlp* m, const float* t, int B, float* rowerr, float* rownorm, void* stream);

@@ -10,9 +10,11 @@ Gauss error linear unit on the hidden layers:
     gelu(z) = z Phi(z) = z (1 + erf(z / sqrt 2)) / 2,
 trained on the mean squared error (1 / (B n)) sum (y - t)^2 by Adam
 (Kingma and Ba, 2015, Algorithm 1: bias-corrected first and second moments).
-Inputs and outputs pass through fixed affine maps,
-    x_0 = (u - shift) * scale   (per feature),   physical output = out_scale * y,
-and the loss compares y with t / out_scale.
+Raw input features u pass through a fixed embedding (each network input is
+one raw feature mapped affinely, (u - shift) * scale, or through cos or sin of
+scale u + shift); the physical output is out_scale * a * y with a either 1 or
+one raw feature the output is proportional to, and the loss compares y with
+t / (out_scale * a).
 
 Parameters are a list of (W, b) pairs with W of shape [n_out, n_in].
 """
@@ -57,12 +59,29 @@ def unflatten(vec, widths):
     return params
 
 
-def forward(params, u, shift=None, scale=None):
-    """Returns (y, cache) with y the normalised output and cache the per-layer
-    inputs x_l and pre-activations z_l."""
-    x = np.asarray(u, dtype=np.float64)
-    if shift is not None:
-        x = (x - shift) * scale
+def embed(u, columns=None):
+    """Network input x_0 from raw features u [B, n_u]; columns: one (src, op,
+    shift, scale) per input, op 0 = (u_src - shift) * scale, 1 = cos(scale
+    u_src + shift), 2 = sin(scale u_src + shift).  None: u itself."""
+    u = np.asarray(u, dtype=np.float64)
+    if columns is None:
+        return u.copy()
+    cols = []
+    for src, op, shift, scale in columns:
+        v = u[:, src]
+        if op == 0:
+            cols.append((v - shift) * scale)
+        elif op == 1:
+            cols.append(np.cos(scale * v + shift))
+        else:
+            cols.append(np.sin(scale * v + shift))
+    return np.stack(cols, axis=1)
+
+
+def forward(params, x):
+    """Returns (y, cache) with y the normalised output of network input x and
+    cache the per-layer inputs x_l and pre-activations z_l."""
+    x = np.asarray(x, dtype=np.float64)
     xs, zs = [], []
     L = len(params)
     for l, (W, b) in enumerate(params):
@@ -118,9 +137,10 @@ class Adam:
         return out
 
 
-def train_step(params, opt, u, t, shift=None, scale=None, out_scale=1.0, lr=None):
-    """One minibatch step; returns (new params, loss before the step)."""
-    y, cache = forward(params, u, shift, scale)
+def train_step(params, opt, x, t, out_scale=1.0, lr=None):
+    """One minibatch step on network inputs x and physical targets t (out_scale
+    may be a per-row column); returns (new params, loss before the step)."""
+    y, cache = forward(params, x)
     tn = np.asarray(t, dtype=np.float64) / out_scale
     g = backward(params, cache, y, tn)
     return opt.step(params, g, lr), loss(y, tn)

@@ -4,11 +4,15 @@
 // (CDNA4 v_mfma_f32_32x32x16_bf16) that accumulate in FP32, on FP32 master
 // weights updated by Adam.
 //
-//   input     x_0 = bf16((u - shift) * scale), rows optionally gathered
+//   input     x_0 = bf16(embed(u)), rows optionally gathered: each network
+//             input column takes one raw feature u_c, either affinely,
+//             (u_c - shift) * scale, or through cos / sin (scale u_c + shift)
+//             (angles, and Fourier features of a scalar)
 //   forward   z_l = x_l W_l^T + b_l, x_{l+1} = bf16(gelu(z_l)) (hidden layers),
-//             y = z_{L-1}; inference returns out_scale * y
-//   loss      mean squared error against t / out_scale,
-//             dz_{L-1} = 2 (y - t / out_scale) / (B n_out)
+//             y = z_{L-1}; inference returns out_scale * a * y, where a is one
+//             raw feature the output is proportional to (or 1)
+//   loss      mean squared error against t / (out_scale a),
+//             dz_{L-1} = 2 (y - t / (out_scale a)) / (B n_out)
 //   backward  dW_l = dz_l^T x_l, db_l = sum over rows of dz_l,
 //             dz_{l-1} = (dz_l W_l) * gelu'(z_{l-1})
 //   update    Adam with bias correction on the FP32 masters; the BF16 copies
@@ -58,8 +62,9 @@ struct GemmArgs {
   bf16_t* Cb;            // BF16 copy (activation or dz), ld = ldc
   int ldc;
   const float* Zprev;    // pre-activation for gelu' (EPI_DX_GELU), ld = ldc
-  float* Y;              // EPI_FWD_LIN: if set, out_scale * z goes here instead of Cf
+  float* Y;              // EPI_FWD_LIN: if set, out_scale * rowscale[row] * z goes here instead of Cf
   float out_scale;
+  const float* rowscale; // [M] per-row output factor
   float* part;           // split-K partial sums [ks][M][N]
   int mt, nt, ks, kchunk;
 };
@@ -75,7 +80,7 @@ __device__ __forceinline__ void epilogue(const GemmArgs& g, int row, int col, fl
     g.Cb[o] = f2bf(gelu(z));
   } else if (EPI == EPI_FWD_LIN) {
     const float z = v + g.bias[col];
-    if (g.Y) g.Y[o] = g.out_scale * z;
+    if (g.Y) g.Y[o] = g.out_scale * g.rowscale[row] * z;
     else g.Cf[o] = z;
   } else if (EPI == EPI_DX_GELU) {
     const float d = v * gelu_d(g.Zprev[o]);
@@ -208,30 +213,47 @@ __global__ void k_splitk_reduce(const GemmArgs g) {
   epilogue<EPI>(g, (int)(i / g.N), (int)(i % g.N), s);
 }
 
-// x_0 = bf16((u[src] - shift) * scale), zero-padded to ld columns
-__global__ void k_pack_input(const float* __restrict__ u, const int* __restrict__ idx, int nrows, int B, int nin, int ld,
-                             const float* __restrict__ shift, const float* __restrict__ scale,
-                             bf16_t* __restrict__ X) {
+// One network input column: raw feature src (-1: zero padding) and how it
+// enters (0: (u - shift) * scale, 1: cos(scale u + shift), 2: sin(scale u + shift)).
+struct EmbCol {
+  int src, op;
+  float shift, scale;
+};
+
+// x_0[r][c] = bf16(embed column c of u[row r]), rowscale[r] = u[row r][amp]
+__global__ void k_pack_input(const float* __restrict__ u, const int* __restrict__ idx, int nrows, int B, int nu, int ld,
+                             const EmbCol* __restrict__ emb, int amp, bf16_t* __restrict__ X,
+                             float* __restrict__ rowscale) {
   const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (i >= (long)B * ld) return;
   const int r = (int)(i / ld), c = (int)(i % ld);
   const long src = idx ? min(max(idx[r], 0), nrows - 1) : r;
-  X[i] = c < nin ? f2bf((u[src * nin + c] - shift[c]) * scale[c]) : (bf16_t)0;
+  const EmbCol e = emb[c];
+  float v = 0.f;
+  if (e.src >= 0) {
+    const float x = u[src * nu + e.src];
+    v = e.op == 0 ? (x - e.shift) * e.scale : (e.op == 1 ? cosf(e.scale * x + e.shift) : sinf(e.scale * x + e.shift));
+  }
+  X[i] = f2bf(v);
+  if (c == 0) rowscale[r] = amp >= 0 ? u[src * nu + amp] : 1.0f;
 }
 
 // per-row squared error and squared target norm (normalised units), and
 // dz = 2 (y - t / out_scale) / (B n)
 __global__ void __launch_bounds__(256) k_loss(const float* __restrict__ Y, const float* __restrict__ T,
                                               const int* __restrict__ idx, int nrows, int B, int n, float inv_scale,
+                                              const float* __restrict__ rowscale,
                                               float* __restrict__ dZ, bf16_t* __restrict__ dZb,
                                               float* __restrict__ rowerr, float* __restrict__ rownorm) {
   const int r = blockIdx.x;
   const long src = idx ? min(max(idx[r], 0), nrows - 1) : r;
   float se = 0.f, sn = 0.f;
   const float sc = 2.0f / ((float)B * (float)n);
+  const float rs = rowscale[r];
+  const float inv = rs != 0.f ? inv_scale / rs : 0.f;
   for (int c = threadIdx.x; c < n; c += blockDim.x) {
     const long o = (long)r * n + c;
-    const float tv = T[src * n + c] * inv_scale;
+    const float tv = T[src * n + c] * inv;
     const float d = Y[o] - tv;
     se += d * d;
     sn += tv * tv;
@@ -376,11 +398,13 @@ struct pmdg_mlp {
   int last_batch = 0;
   const int* last_idx = nullptr;
   int last_nrows = 0;
-  std::vector<float> shift, scale; // input map (host copies)
+  int n_u = 0;                     // raw features per input row
+  int amp_col = -1;                // raw feature the output is proportional to
+  std::vector<EmbCol> emb;         // input map per network input column (kin[0])
   float out_scale = 1.f;
   // byte offsets into the workspace
   std::vector<size_t> oW, ob, oWb, omW, ovW, omb, ovb, odW, odb, oZ, oXb, odZ, odZb;
-  size_t oRowErr = 0, oRowNorm = 0, oShift = 0, oScale = 0, oPart = 0, bytes = 0;
+  size_t oRowErr = 0, oRowNorm = 0, oEmb = 0, oRowScale = 0, oPart = 0, bytes = 0;
   long nparams = 0;
   int adam_t = 0;
 };
@@ -408,8 +432,8 @@ static void mlp_layout(pmdg_mlp* m) {
   }
   m->oRowErr = take(4 * B);
   m->oRowNorm = take(4 * B);
-  m->oShift = take(4 * (size_t)m->kin[0]);
-  m->oScale = take(4 * (size_t)m->kin[0]);
+  m->oEmb = take(sizeof(EmbCol) * (size_t)m->kin[0]);
+  m->oRowScale = take(4 * B);
   m->oPart = take(4 * kPartFloats);
   m->bytes = o;
 }
@@ -428,8 +452,8 @@ static pmdg_status mlp_forward_dev(pmdg_mlp* m, const float* u, const int* idx, 
                                    hipStream_t st) {
   const int L = m->L;
   hipLaunchKernelGGL(k_pack_input, dim3((unsigned)nblk((long)B * m->kin[0], 256)), dim3(256), 0, st, u, idx, nrows, B,
-                     m->width[0], m->kin[0], at<float>(m, m->oShift), at<float>(m, m->oScale),
-                     at<bf16_t>(m, m->oXb[0]));
+                     m->n_u, m->kin[0], at<EmbCol>(m, m->oEmb), m->amp_col, at<bf16_t>(m, m->oXb[0]),
+                     at<float>(m, m->oRowScale));
   MCHK(hipGetLastError());
   for (int l = 0; l < L; ++l) {
     GemmArgs g;
@@ -445,6 +469,7 @@ static pmdg_status mlp_forward_dev(pmdg_mlp* m, const float* u, const int* idx, 
     } else {
       g.Y = y;
       g.out_scale = m->out_scale;
+      g.rowscale = at<float>(m, m->oRowScale);
       MCHK((gemm<true, true, EPI_FWD_LIN>(g, at<float>(m, m->oPart), st)));
     }
   }
@@ -458,7 +483,8 @@ static pmdg_status mlp_forward_dev(pmdg_mlp* m, const float* u, const int* idx, 
 static pmdg_status mlp_backward_dev(pmdg_mlp* m, const float* t, const int* idx, int nrows, int B, hipStream_t st) {
   const int L = m->L, nout = m->width[L];
   hipLaunchKernelGGL(k_loss, dim3(B), dim3(256), 0, st, at<float>(m, m->oZ[L - 1]), t, idx, nrows, B, nout,
-                     1.0f / m->out_scale, at<float>(m, m->odZ[L - 1]), at<bf16_t>(m, m->odZb[L - 1]),
+                     1.0f / m->out_scale, at<float>(m, m->oRowScale), at<float>(m, m->odZ[L - 1]),
+                     at<bf16_t>(m, m->odZb[L - 1]),
                      at<float>(m, m->oRowErr), at<float>(m, m->oRowNorm));
   MCHK(hipGetLastError());
   for (int l = L - 1; l >= 0; --l) {
@@ -521,8 +547,9 @@ pmdg_status pmdg_mlp_create(int nlayers, const int* widths, pmdg_mlp** out) {
   m->kin.resize(nlayers);
   for (int l = 0; l < nlayers; ++l) m->kin[l] = (m->width[l] + 31) / 32 * 32;
   for (int l = 0; l < nlayers; ++l) m->nparams += (long)m->width[l + 1] * (m->width[l] + 1);
-  m->shift.assign(m->kin[0], 0.f);
-  m->scale.assign(m->kin[0], 1.f);
+  m->n_u = m->width[0];
+  m->emb.assign(m->kin[0], EmbCol{-1, 0, 0.f, 1.f});
+  for (int c = 0; c < m->width[0]; ++c) m->emb[c].src = c;
   *out = m;
   return PMDG_OK;
 }
@@ -553,28 +580,36 @@ pmdg_status pmdg_mlp_bind(pmdg_mlp* m, void* dev, size_t bytes, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   m->ws = (char*)dev;
   MCHK(hipMemsetAsync(m->ws, 0, m->bytes, st));
-  MCHK(hipMemcpyAsync(at<float>(m, m->oShift), m->shift.data(), 4 * m->shift.size(), hipMemcpyHostToDevice, st));
-  MCHK(hipMemcpyAsync(at<float>(m, m->oScale), m->scale.data(), 4 * m->scale.size(), hipMemcpyHostToDevice, st));
+  MCHK(hipMemcpyAsync(at<EmbCol>(m, m->oEmb), m->emb.data(), sizeof(EmbCol) * m->emb.size(), hipMemcpyHostToDevice,
+                      st));
   MCHK(hipStreamSynchronize(st));
   m->bound = true;
   m->adam_t = 0;
   return PMDG_OK;
 }
 
-pmdg_status pmdg_mlp_set_io_map(pmdg_mlp* m, const float* shift, const float* scale, float out_scale, void* stream) {
-  if (!m || !shift || !scale) return mfail(PMDG_EINVAL, "NULL argument");
+pmdg_status pmdg_mlp_set_io_map(pmdg_mlp* m, int n_u, int ncols, const int* src, const int* op, const float* shift,
+                                const float* scale, int amp_col, float out_scale, void* stream) {
+  if (!m || !src || !op || !shift || !scale) return mfail(PMDG_EINVAL, "NULL argument");
+  if (n_u < 1 || n_u > (1 << 20)) return mfail(PMDG_EINVAL, "n_u out of range");
+  if (ncols != m->width[0]) return mfail(PMDG_EINVAL, "ncols must equal widths[0] = " + std::to_string(m->width[0]));
   if (!(out_scale > 0.f) || !std::isfinite(out_scale)) return mfail(PMDG_EINVAL, "out_scale must be finite and > 0");
-  for (int c = 0; c < m->width[0]; ++c)
+  if (amp_col < -1 || amp_col >= n_u) return mfail(PMDG_EINVAL, "amp_col must be -1 or a feature index");
+  std::vector<EmbCol> emb(m->kin[0], EmbCol{-1, 0, 0.f, 1.f});
+  for (int c = 0; c < ncols; ++c) {
+    if (src[c] < 0 || src[c] >= n_u) return mfail(PMDG_EINVAL, "src must index a raw feature");
+    if (op[c] < 0 || op[c] > 2) return mfail(PMDG_EINVAL, "op must be 0 (affine), 1 (cos) or 2 (sin)");
     if (!std::isfinite(shift[c]) || !std::isfinite(scale[c])) return mfail(PMDG_EINVAL, "non-finite input map");
-  for (int c = 0; c < m->width[0]; ++c) {
-    m->shift[c] = shift[c];
-    m->scale[c] = scale[c];
+    emb[c] = EmbCol{src[c], op[c], shift[c], scale[c]};
   }
+  m->emb = emb;
+  m->n_u = n_u;
+  m->amp_col = amp_col;
   m->out_scale = out_scale;
   if (m->bound) {
     hipStream_t st = (hipStream_t)stream;
-    MCHK(hipMemcpyAsync(at<float>(m, m->oShift), m->shift.data(), 4 * m->shift.size(), hipMemcpyHostToDevice, st));
-    MCHK(hipMemcpyAsync(at<float>(m, m->oScale), m->scale.data(), 4 * m->scale.size(), hipMemcpyHostToDevice, st));
+    MCHK(hipMemcpyAsync(at<EmbCol>(m, m->oEmb), m->emb.data(), sizeof(EmbCol) * m->emb.size(),
+                        hipMemcpyHostToDevice, st));
     MCHK(hipStreamSynchronize(st));
   }
   return PMDG_OK;

@@ -195,7 +195,8 @@ struct pmdg_solver {
   std::map<std::string, Seg> seg;
   long steps_done = 0;
   // options
-  int use_graph = 1, rows = 2, zchunk = 33, graph_chunk = 64, timing = 0;
+  int use_graph = 1, rows = 2, zchunk = 73, graph_chunk = 64, timing = 0;
+  int rows1 = 0, zchunk1 = -1;  // secondary brick's tile (0 / -1: as the primary's)
   std::map<int, hipGraphExec_t> graphs;
   hipStream_t cap_stream = nullptr;
   double ktimes[3] = {0, 0, 0};
@@ -570,11 +571,12 @@ static StiffArgs<Real> stiff_args(pmdg_solver* s, int d) {
     a.mins = dptr<Real>(s, p + "mins");
   }
   const Brick& B = s->b[d];
-  a.rows = s->rows;
+  a.rows = (d == 1 && s->rows1 > 0) ? s->rows1 : s->rows;
+  const int zc = (d == 1 && s->zchunk1 >= 0) ? s->zchunk1 : s->zchunk;
   a.nbx = B.px / 64;
-  const int TY = kWaves * s->rows;
+  const int TY = kWaves * a.rows;
   a.nby = (B.nn[1] + TY - 1) / TY;
-  a.zchunk = (s->zchunk > 0) ? std::min(s->zchunk, B.nn[2]) : B.nn[2];
+  a.zchunk = (zc > 0) ? std::min(zc, B.nn[2]) : B.nn[2];
   a.nbz = (B.nn[2] + a.zchunk - 1) / a.zchunk;
   a.nblocks = a.nbx * a.nby * a.nbz * s->S;
   return a;
@@ -1127,6 +1129,15 @@ pmdg_status pmdg_set_option(pmdg_solver* s, int option, long value) {
     case PMDG_OPT_TILE_ZCHUNK:
       if (value < 0) return fail(PMDG_EINVAL, "zchunk must be >= 0");
       s->zchunk = (int)value;
+      break;
+    case PMDG_OPT_TILE_ROWS_SECONDARY:
+      if (!(value == 0 || value == 1 || value == 2 || value == 4))
+        return fail(PMDG_EINVAL, "tile rows per wave must be 0 (as the primary), 1, 2 or 4");
+      s->rows1 = (int)value;
+      break;
+    case PMDG_OPT_TILE_ZCHUNK_SECONDARY:
+      if (value < -1) return fail(PMDG_EINVAL, "zchunk must be >= -1");
+      s->zchunk1 = (int)value;
       break;
     case PMDG_OPT_GRAPH_CHUNK:
       if (value < 1) return fail(PMDG_EINVAL, "graph chunk must be >= 1");

@@ -49,10 +49,10 @@ __device__ __forceinline__ T wave_sum(T v) {
 // cache-line aligned 64-lane access.  The z line lives in a register queue
 // of 2N+1 planes per owned node (its rotation is unrolled so that no register
 // moves are needed); the x and y lines are read from a double-buffered LDS
-// copy of the current plane with an N-node halo.  Everything the next plane
-// needs (lead plane, halos, the increment or previous level) is fetched one
-// plane ahead so that memory latency overlaps the arithmetic, with one
-// barrier per plane.  Operator rows come by node class (x per lane, y per
+// copy of the current plane with an N-node halo.  Everything a plane needs
+// (lead plane, halos, the increment or previous level) is fetched two planes
+// ahead so that memory latency overlaps the arithmetic of two planes, with
+// one barrier per plane.  Operator rows come by node class (x per lane, y per
 // wave row, z per plane, all uniform where the class is).
 // Increment form (FP32): X holds p^n - p^{n-1}, X += a, p^{n+1} = p^n + X.
 // Two-level form (FP64): p^{n+1} = p^n + (p^n - p^{n-1}) + a over p^{n-1}.
@@ -197,29 +197,80 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
     else { lay0 = 0; lay1 = N; }
   }
   constexpr int n1 = N + 1;
+  // The PMUT force (plane 0) and the interface residual of a node's column
+  // do not change along z: gather them once per tile, so that the plane loop
+  // issues no loads but the streaming ones.
+  Real fr[RY], RA[RY], RB[RY];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) fr[r] = RA[r] = RB[r] = Real(0);
+  if (a.force && k0 == 0) {
+#pragma unroll
+    for (int r = 0; r < RY; ++r)
+      if (in[r]) fr[r] = a.force[(long)s * plane + roff[r]];
+  }
+  if (a.iface && k1 > lay0 && k0 <= lay1) {
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      if (!in[r]) continue;
+      // residual of the (up to 4) interface faces sharing (x, y)
+      const int y = ybase + r;
+      const int ex1 = min(x / N, a.iface_nex - 1), ey1 = min(y / N, a.iface_ney - 1);
+      const int ax1 = x - N * ex1, by1 = y - N * ey1;
+      const long fbase = (long)s * a.iface_nex * a.iface_ney;
+#pragma unroll
+      for (int jy = 0; jy < 2; ++jy) {
+        const int ey = ey1 - jy, bb = jy ? N : by1;
+        if (jy && !(by1 == 0 && ey1 > 0)) continue;
+#pragma unroll
+        for (int jx = 0; jx < 2; ++jx) {
+          const int ex = ex1 - jx, aa = jx ? N : ax1;
+          if (jx && !(ax1 == 0 && ex1 > 0)) continue;
+          const Real* R = a.iface + ((fbase + ex + (long)a.iface_nex * ey) * (n1 * n1) + aa + n1 * bb) * 2;
+          RA[r] += R[0];
+          RB[r] += R[1];
+        }
+      }
+    }
+  }
 
-  for (int kb = k0; kb < k1; kb += NQ) {
-    static_for<NQ>([&](auto uc) {
+  // Prefetch two planes ahead: iteration k consumes the loads for plane k+1
+  // (issued at iteration k-1) and issues those for plane k+2, so each load
+  // has two plane updates of work to hide behind.  Slot j & 1 holds the
+  // data for plane j: the queue's lead plane j+N, the increment (or p^{n-1})
+  // of plane j and the x/y halos of plane j.
+  Real fq[2][RY], fx[2][RY], fhx[2][NXH], fhy[2][HYR];
+  auto fetch = [&](int slot, int j) {
+    const unsigned kl_off = (unsigned)min(j + N, nz - 1) * plane;
+    const unsigned kn_off = (unsigned)min(j, nz - 1) * plane;
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      fq[slot][r] = P[roff[r] + kl_off];
+      fx[slot][r] = X[roff[r] + kn_off];
+    }
+#pragma unroll
+    for (int jj = 0; jj < NXH; ++jj) fhx[slot][jj] = P[xh_off[jj] + kn_off];
+#pragma unroll
+    for (int jj = 0; jj < HYR; ++jj) fhy[slot][jj] = P[yh_off[jj] + kn_off];
+  };
+  fetch(1, k0 + 1);
+
+  // the unrolled body covers 2 NQ planes so that both the queue position
+  // (mod NQ) and the prefetch slot (mod 2) are compile-time constants
+  for (int kb = k0; kb < k1; kb += 2 * NQ) {
+    static_for<2 * NQ>([&](auto uc) {
       constexpr int u = decltype(uc)::value;
+      constexpr int uq = u % NQ;
+      constexpr int cs = (u + 1) & 1;  // slot of plane k+1 (k - k0 = kb - k0 + u, kb - k0 even)
+      constexpr int ns = u & 1;        // slot of plane k+2
       const int k = kb + u;
       if (k >= k1) return;
       const int b = (k - k0) & 1;
       const int kn = k + 1;
       const bool more = kn < k1;
-      // (1) fetch for the next plane
-      Real nq[RY], xn[RY], hxv[NXH], hyv[HYR];
-      const int kl = k + N + 1;
-      const unsigned kl_off = (unsigned)min(kl, nz - 1) * plane;
-      const unsigned kn_off = (unsigned)min(kn, nz - 1) * plane;
-#pragma unroll
-      for (int r = 0; r < RY; ++r) {
-        nq[r] = P[roff[r] + kl_off];
-        xn[r] = X[roff[r] + kn_off];
-      }
-#pragma unroll
-      for (int j = 0; j < NXH; ++j) hxv[j] = P[xh_off[j] + kn_off];
-#pragma unroll
-      for (int j = 0; j < HYR; ++j) hyv[j] = P[yh_off[j] + kn_off];
+      // (1) fetch for plane k+2 (unconditional on clamped addresses: a
+      // conditional load would make its registers a join that the compiler
+      // settles with copies, i.e. an early wait for the load)
+      fetch(ns, k + 2);
       // (2) plane k is complete in buffer b
       __syncthreads();
       const Real* T = tile[b];
@@ -235,7 +286,7 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
         const int row = N + wave * RY + r;
-        const Real p0 = q[r][(u + N) % NQ];
+        const Real p0 = q[r][(uq + N) % NQ];
 
         Real acc = 0;
 #pragma unroll
@@ -244,35 +295,16 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
           acc += tx[N + i] * (T[row * W + N + lane + 1 + i] - p0);
           acc += ty[r][i] * (col[r + i] - p0);
           acc += ty[r][N + i] * (col[r + N + 1 + i] - p0);
-          acc += tz[i] * (q[r][(u + i) % NQ] - p0);
-          acc += tz[N + i] * (q[r][(u + N + 1 + i) % NQ] - p0);
+          acc += tz[i] * (q[r][(uq + i) % NQ] - p0);
+          acc += tz[N + i] * (q[r][(uq + N + 1 + i) % NQ] - p0);
         }
         if (in[r]) {
           const Real minv = mx * my[r] * mz;
-          if (a.force && k == 0) acc += a.dt2 * minv * a.force[(long)s * plane + roff[r]];
+          if (k == 0) acc += a.dt2 * minv * fr[r];
           if (in_layer) {
-            // residual of the (up to 4) interface faces sharing (x, y)
-            const int y = ybase + r;
-            Real RA = 0, RB = 0;
-            const int ex1 = min(x / N, a.iface_nex - 1), ey1 = min(y / N, a.iface_ney - 1);
-            const int ax1 = x - N * ex1, by1 = y - N * ey1;
-            const long fbase = (long)s * a.iface_nex * a.iface_ney;
-#pragma unroll
-            for (int jy = 0; jy < 2; ++jy) {
-              const int ey = ey1 - jy, bb = jy ? N : by1;
-              if (jy && !(by1 == 0 && ey1 > 0)) continue;
-#pragma unroll
-              for (int jx = 0; jx < 2; ++jx) {
-                const int ex = ex1 - jx, aa = jx ? N : ax1;
-                if (jx && !(ax1 == 0 && ex1 > 0)) continue;
-                const Real* R = a.iface + ((fbase + ex + (long)a.iface_nex * ey) * (n1 * n1) + aa + n1 * bb) * 2;
-                RA += R[0];
-                RB += R[1];
-              }
-            }
-            Real rif = RB * a.iface_d[cl];
-            if (a.iface_side > 0) { if (cl == N) rif += RA; }
-            else { if (cl == 0) rif -= RA; }
+            Real rif = RB[r] * a.iface_d[cl];
+            if (a.iface_side > 0) { if (cl == N) rif += RA[r]; }
+            else { if (cl == 0) rif -= RA[r]; }
             acc -= a.dt2 * minv * rif;
           }
           const unsigned idx = roff[r] + (unsigned)k * plane;
@@ -291,19 +323,20 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
       if (more) {
         Real* Tn = tile[b ^ 1];
 #pragma unroll
-        for (int r = 0; r < RY; ++r) Tn[(N + wave * RY + r) * W + N + lane] = q[r][(u + N + 1) % NQ];
+        for (int r = 0; r < RY; ++r) Tn[(N + wave * RY + r) * W + N + lane] = q[r][(uq + N + 1) % NQ];
 #pragma unroll
         for (int j = 0; j < NXH; ++j)
-          if (xh_dst[j] >= 0) Tn[xh_dst[j]] = xh_ok[j] ? hxv[j] : Real(0);
+          if (xh_dst[j] >= 0) Tn[xh_dst[j]] = xh_ok[j] ? fhx[cs][j] : Real(0);
 #pragma unroll
         for (int j = 0; j < HYR; ++j)
-          if (yh_dst[j] >= 0) Tn[yh_dst[j]] = yh_ok[j] ? hyv[j] : Real(0);
+          if (yh_dst[j] >= 0) Tn[yh_dst[j]] = yh_ok[j] ? fhy[cs][j] : Real(0);
       }
-      // (5) rotate the queue
+      // (5) rotate the queue: plane k+N+1 replaces plane k-N
+      const int kl = k + N + 1;
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
-        q[r][u % NQ] = (in[r] && kl < nz) ? nq[r] : Real(0);
-        xc[r] = (in[r] && more) ? xn[r] : Real(0);
+        q[r][uq] = (in[r] && kl < nz) ? fq[cs][r] : Real(0);
+        xc[r] = (in[r] && more) ? fx[cs][r] : Real(0);
       }
     });
   }

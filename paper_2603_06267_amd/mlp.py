@@ -64,13 +64,19 @@ class MLP:
                                         _stream_ptr(stream)))
         return v
 
-    def set_io_map(self, shift, scale, out_scale, stream=None):
-        sh = np.ascontiguousarray(shift, dtype=np.float32)
-        sc = np.ascontiguousarray(scale, dtype=np.float32)
-        assert sh.size == self.widths[0] and sc.size == self.widths[0]
-        fp = ctypes.POINTER(ctypes.c_float)
-        check(self.L.pmdg_mlp_set_io_map(self.h, sh.ctypes.data_as(fp), sc.ctypes.data_as(fp),
+    def set_io_map(self, n_u, columns, out_scale=1.0, amp_col=-1, stream=None):
+        """columns: one (src, op, shift, scale) per network input, op 0 affine
+        ((u - shift) * scale), 1 cos(scale u + shift), 2 sin(scale u + shift)."""
+        cols = list(columns)
+        src = np.ascontiguousarray([c[0] for c in cols], dtype=np.int32)
+        op = np.ascontiguousarray([c[1] for c in cols], dtype=np.int32)
+        sh = np.ascontiguousarray([c[2] for c in cols], dtype=np.float32)
+        sc = np.ascontiguousarray([c[3] for c in cols], dtype=np.float32)
+        ip, fp = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_float)
+        check(self.L.pmdg_mlp_set_io_map(self.h, int(n_u), len(cols), src.ctypes.data_as(ip), op.ctypes.data_as(ip),
+                                         sh.ctypes.data_as(fp), sc.ctypes.data_as(fp), int(amp_col),
                                          float(out_scale), _stream_ptr(stream)))
+        self.n_u = int(n_u)
 
     # ---- compute ----------------------------------------------------------
     def forward(self, u, y=None, idx=None, B=None, stream=None):
@@ -117,3 +123,14 @@ def pair_combine(a, b, mean=None, spread=None, stream=None):
     check(lib().pmdg_mlp_pair_combine(_ptr(a), _ptr(b), int(B), int(n), _ptr(mean), _ptr(spread),
                                       _stream_ptr(stream)))
     return mean, spread
+
+
+def columns_from_kinds(kind, shift, scale):
+    """Embedding columns for per-feature kinds: 0 affine, 1 angle (cos, sin)."""
+    cols = []
+    for c, k in enumerate(kind):
+        if k == 0:
+            cols.append((c, 0, float(shift[c]), float(scale[c])))
+        else:
+            cols += [(c, 1, 0.0, 1.0), (c, 2, 0.0, 1.0)]
+    return cols

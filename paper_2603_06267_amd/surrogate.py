@@ -5,8 +5,12 @@ estimate and the solver as fallback.
 
   data       the GPU solver (FP32 state, FP64 modal ODE and traces) on the
              seeded scenarios of the surrogate data set, one batched launch
-  network    18 -> 512 -> 512 -> 512 -> 512 -> 32768, GELU, trained by the
-             library's BF16-MFMA forward / backward / Adam kernels
+  network    18 drive parameters -> 512 -> 512 -> 512 -> 512 -> 32768, GELU,
+             trained by the library's BF16-MFMA forward / backward / Adam
+             kernels.  Each phase enters as the pair (cos, sin) (phases are
+             angles, 34 network inputs in all), frequency and amplitude
+             affinely; the output is scaled by the amplitude, since the
+             solver's traces are exactly proportional to it
   estimate   a two-member ensemble (different initialisations and minibatch
              orders); its spread |y_1 - y_2| / |(y_1 + y_2) / 2|, scaled by the
              split-conformal quantile of (true error / spread) on a held-out
@@ -27,17 +31,34 @@ from . import mlp as _mlp
 from . import solver as _solver
 from . import workloads as W
 
-WIDTHS = [18, 512, 512, 512, 512, 32768]
+HIDDEN = [512, 512, 512, 512]
+N_OUT = 64 * 512
 N_PMUT = 16
 TOL = 0.02
 
 
-def input_map():
-    """Affine map of the raw features onto [-1, 1]: phases in [0, 2 pi),
-    frequency in [1.5, 3] MHz, amplitude in [0.5, 1]."""
-    shift = np.array([math.pi] * N_PMUT + [2.25, 0.75], dtype=np.float32)
-    scale = np.array([1.0 / math.pi] * N_PMUT + [1.0 / 0.75, 4.0], dtype=np.float32)
-    return shift, scale
+AMP_COL = N_PMUT + 1
+FREQ_COL = N_PMUT
+# sampled trace length (512 steps of the cube's dt = 8.634 ns), for the
+# frequency's Fourier columns
+T_TRACE_US = 4.42
+
+
+def input_columns(n_fourier=0):
+    """Embedding of the raw features [phase x16, frequency (MHz), amplitude]:
+    each phase as (cos, sin) (phases are angles), frequency in [1.5, 3] and
+    amplitude in [0.5, 1] mapped affinely onto [-1, 1], and optionally
+    n_fourier pairs cos / sin(2 pi tau_j f), tau_j = j T / n_fourier, which give
+    the network the oscillation of the traces with frequency at the sampled
+    times."""
+    cols = []
+    for k in range(N_PMUT):
+        cols += [(k, 1, 0.0, 1.0), (k, 2, 0.0, 1.0)]
+    cols += [(FREQ_COL, 0, 2.25, 1.0 / 0.75), (AMP_COL, 0, 0.75, 4.0)]
+    for j in range(1, n_fourier + 1):
+        w = 2.0 * math.pi * j * T_TRACE_US / n_fourier
+        cols += [(FREQ_COL, 1, 0.0, w), (FREQ_COL, 2, 0.0, w)]
+    return cols
 
 
 def drive_from_features(F):
@@ -66,8 +87,9 @@ def solve(F, steps=512, device="cuda", stream=None, max_scenarios=4096):
 
 
 class Surrogate:
-    def __init__(self, n_members=2, max_batch=1024, seed=0, device="cuda", widths=None):
-        self.widths = list(widths or WIDTHS)
+    def __init__(self, n_members=2, max_batch=1024, seed=0, device="cuda", n_fourier=0, hidden=None, n_out=N_OUT):
+        self.columns = input_columns(n_fourier)
+        self.widths = [len(self.columns)] + list(hidden or HIDDEN) + [n_out]
         self.members = [_mlp.MLP(self.widths, max_batch=max_batch, device=device) for _ in range(n_members)]
         self.max_batch = max_batch
         self.device = device
@@ -82,23 +104,27 @@ class Surrogate:
         Each member: He initialisation from its own seed, its own minibatch
         order, Adam with a cosine learning-rate decay from lr to lr_final."""
         import torch
-        shift, scl = input_map()
         tr = torch.as_tensor(np.asarray(train_idx), dtype=torch.long, device=U.device)
-        self.out_scale = float(torch.sqrt((T[tr] ** 2).mean()).item())
+        # RMS of the amplitude-normalised training traces
+        amp = U[tr, AMP_COL:AMP_COL + 1]
+        self.out_scale = float(torch.sqrt(((T[tr] / amp) ** 2).mean()).item())
         err = torch.empty(batch, dtype=torch.float32, device=U.device)
         nrm = torch.empty(batch, dtype=torch.float32, device=U.device)
         ntr = len(train_idx)
         t0 = time.perf_counter()
         for k, m in enumerate(self.members):
             rng = np.random.default_rng(self.seed + 1000 * k)
-            m.set_io_map(shift, scl, self.out_scale)
+            m.set_io_map(N_PMUT + 2, self.columns, out_scale=self.out_scale, amp_col=AMP_COL)
             m.init_params(rng)
-            order = np.empty(0, dtype=np.int64)
+            per_epoch = ntr // batch
+            perm = None
             for s in range(steps):
-                if len(order) < batch:
-                    order = np.concatenate([order, np.asarray(train_idx)[rng.permutation(ntr)]])
-                idx = torch.as_tensor(order[:batch].astype(np.int32), device=U.device)
-                order = order[batch:]
+                if s % per_epoch == 0:
+                    # one upload per epoch: the minibatches are views of it
+                    order = np.asarray(train_idx)[rng.permutation(ntr)][:per_epoch * batch]
+                    perm = torch.as_tensor(order.astype(np.int32), device=U.device)
+                j = s % per_epoch
+                idx = perm[j * batch:(j + 1) * batch]
                 a = lr_final + 0.5 * (lr - lr_final) * (1 + math.cos(math.pi * s / steps))
                 m.train_step(U, T, idx, a, rowerr=err, rownorm=nrm)
                 if log and (s % log_every == 0 or s == steps - 1):

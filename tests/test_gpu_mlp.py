@@ -117,27 +117,59 @@ def test_gradients_against_oracle(widths, B):
 
 
 def test_forward_full_size_inference_batch():
-    """Inference at the surrogate's size (batch 1024) with the input map and
-    output scale, checked on sampled rows against the oracle."""
+    """Inference at the surrogate's size (batch 1024) through the input
+    embedding (16 angles -> cos/sin, affine frequency and amplitude) and the
+    output factor out_scale * amplitude, on sampled rows against the oracle."""
     import math
-    widths = [18, 512, 512, 512, 512, 32768]
+    widths = [34, 512, 512, 512, 512, 32768]
     params, _, _ = _twin(widths, 8, 4)
     rng = np.random.default_rng(5)
     F = np.concatenate([rng.uniform(0, 2 * math.pi, (1024, 16)), rng.uniform(1.5, 3, (1024, 1)),
-                        rng.uniform(0.5, 1, (1024, 1))], axis=1)
-    shift = np.array([math.pi] * 16 + [2.25, 0.75])
-    scale = np.array([1 / math.pi] * 16 + [1 / 0.75, 4.0])
+                        rng.uniform(0.5, 1, (1024, 1))], axis=1).astype(np.float32)
+    from paper_2603_06267_amd import mlp
+    cols = mlp.columns_from_kinds([1] * 16 + [0, 0], [0.0] * 16 + [2.25, 0.75], [1.0] * 16 + [1 / 0.75, 4.0])
     m = _model(widths, 1024)
     m.set_params(R.flatten(params))
-    m.set_io_map(shift, scale, 0.25)
+    m.set_io_map(18, cols, out_scale=0.25, amp_col=17)
     y = m.forward(_dev(F)).cpu().numpy()
     assert np.isfinite(y).all()
     rows = rng.choice(1024, 24, replace=False)
-    ref, _ = R.forward(params, F[rows], shift.astype(np.float32).astype(np.float64),
-                       scale.astype(np.float32).astype(np.float64))
-    err = rel_l2(y[rows], 0.25 * ref)
+    cols32 = [(a, b, float(np.float32(c)), float(np.float32(d))) for a, b, c, d in cols]
+    x = R.embed(F[rows].astype(np.float64), cols32)
+    ref, _ = R.forward(params, x)
+    ref *= 0.25 * F[rows, 17:18].astype(np.float64)
+    err = rel_l2(y[rows], ref)
     _say(f"  sampled rows rel L2 {err:.2e}")
     assert err < 1e-2
+
+
+def test_amplitude_factor_in_training_loss():
+    """With amp_col set, the loss compares y with t / (out_scale a): targets
+    that are exactly out_scale * a * y(params) give zero loss and gradient."""
+    import math
+    import torch
+    widths = [7, 64, 64]
+    params, _, _ = _twin(widths, 8, 10)
+    rng = np.random.default_rng(11)
+    F = np.concatenate([rng.uniform(0, 2 * math.pi, (64, 2)), rng.uniform(0.5, 1, (64, 2))], axis=1)
+    from paper_2603_06267_amd import mlp
+    cols = mlp.columns_from_kinds([1, 1, 0, 0], [0, 0, 0.75, 0.75], [1, 1, 4.0, 4.0]) + [(2, 1, 0.25, 3.0)]
+    m = _model(widths, 64)
+    m.set_params(R.flatten(params))
+    m.set_io_map(4, cols, out_scale=2.0, amp_col=3)
+    Fd = _dev(F)
+    y = m.forward(Fd)
+    err = torch.empty(64, device="cuda")
+    nrm = torch.empty(64, device="cuda")
+    m.forward(Fd, y=False)
+    m.backward(y, 64, rowerr=err, rownorm=nrm)
+    rel = float(torch.sqrt(err.sum() / nrm.sum()).item())
+    _say(f"  self-consistent targets: rel loss {rel:.2e}")
+    assert rel < 1e-6
+    # and the oracle's normalised output agrees with y / (2 a)
+    x = R.embed(F.astype(np.float32).astype(np.float64), cols)
+    ref, _ = R.forward(params, x)
+    assert rel_l2(y.cpu().numpy() / (2.0 * F[:, 3:4].astype(np.float32)), ref) < 1e-2
 
 
 def test_gather_rows_equals_contiguous():

@@ -1,0 +1,107 @@
+"""Surrogate form end to end on the GPU: training data from the GPU solver
+(checked against the oracle), two-member BF16-MFMA training, split-conformal
+calibration of the error estimate, inference with solver fallback at the 2%
+relative-L2 tolerance, and the throughput of that pipeline against the plain
+solver.
+
+The data set is the surrogate workload (4096 seeded scenarios of the cube with
+a 4x4 PMUT array; 3584 train, 256 calibration, 256 test)."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from oracle import ref
+from paper_2603_06267_amd import surrogate as S, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TRAIN = np.arange(3584)
+CAL = np.arange(3584, 3840)
+TEST = np.arange(3840, 4096)
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def data():
+    import torch
+    c5 = W.config5()
+    F = c5["features"]
+    t0 = time.perf_counter()
+    T = S.solve(F)
+    torch.cuda.synchronize()
+    _say(f"surrogate data: {T.shape[0]} solver runs in {time.perf_counter() - t0:.2f} s")
+    U = torch.as_tensor(F.astype(np.float32), device="cuda")
+    return F, U, T
+
+
+@pytest.fixture(scope="module")
+def trained(data):
+    F, U, T = data
+    sur = S.Surrogate(n_members=2, seed=3)
+    el = sur.fit(U, T, TRAIN, steps=3000, log=_say, log_every=1000)
+    _say(f"trained 2 members x 3000 steps in {el:.1f} s")
+    scale = sur.calibrate(U, T, CAL)
+    _say(f"calibration scale (95% split-conformal) {scale:.3f}")
+    return sur
+
+
+def test_training_data_matches_oracle(data):
+    """The solver runs the network learns from are the solver's to 1e-5."""
+    F, U, T = data
+    c5 = W.config5()
+    sf = W.shape_fn(c5["scenarios"])
+    for s in (0, 2047, 4095):
+        o = ref.from_workload(c5["scenarios"], scenario=s, shape_fn=sf)
+        to = o.step(512).reshape(-1)
+        tg = T[s].double().cpu().numpy()
+        err = np.linalg.norm(tg - to) / np.linalg.norm(to)
+        _say(f"  scenario {s}: GPU solver vs oracle rel L2 {err:.2e}")
+        assert err < 1e-5
+
+
+def test_calibrated_estimate_covers(data, trained):
+    """On held-out test rows the calibrated estimate bounds the true error of
+    the ensemble mean for about 95% of them (split-conformal; 256 rows)."""
+    F, U, T = data
+    err, spread = trained.errors(U, T, TEST)
+    est = trained.estimate(spread)
+    cover = float(np.mean(err <= est))
+    _say(f"  test rows: network rel L2 median {np.median(err):.4f}, p90 {np.quantile(err, 0.9):.4f}; "
+         f"coverage {cover:.3f}")
+    assert cover >= 0.88
+
+
+def test_fallback_delivers_tolerance_and_gain(data, trained):
+    """Inference with fallback on the 256 test scenarios: rows whose estimate
+    exceeds 2% carry the solver's traces, bitwise; the delivered traces meet
+    2% except for the estimate's non-covered share; the pipeline's
+    scenarios/s is above the plain single-scenario solver's."""
+    import torch
+    F, U, T = data
+    rows = TEST
+    t0 = time.perf_counter()
+    out, mask, est = trained.infer(F[rows])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    t = T[torch.as_tensor(rows, device="cuda")]
+    err = (torch.linalg.vector_norm(out - t, dim=1) / torch.linalg.vector_norm(t, dim=1)).cpu().numpy()
+    _say(f"  routed to the solver: {mask.mean():.3f}; delivered rel L2 median {np.median(err):.2e}, "
+         f"share above 2%: {(err > S.TOL).mean():.3f}; {len(rows) / el:.0f} scenarios/s")
+    if mask.any():
+        assert torch.equal(out[torch.as_tensor(np.nonzero(mask)[0], device="cuda")],
+                           t[torch.as_tensor(np.nonzero(mask)[0], device="cuda")])
+    assert (err > S.TOL).mean() <= 0.12
+    # the plain solver one scenario at a time (8 of them, timed)
+    t0 = time.perf_counter()
+    for r in rows[:8]:
+        S.solve(F[r:r + 1])
+    torch.cuda.synchronize()
+    single = 8 / (time.perf_counter() - t0)
+    _say(f"  plain single-scenario solver: {single:.1f} scenarios/s; pipeline gain {len(rows) / el / single:.1f}x")
+    assert len(rows) / el > single

@@ -71,15 +71,24 @@ def test_linear_layer_gradient_vanishes_at_least_squares():
     assert np.abs(M.backward(params, cache, y, t)[0][0]).max() > 1e-3
 
 
-def test_input_affine_map():
+def test_embedding():
+    """Affine columns map their feature; cos / sin columns of an angle lie on
+    the unit circle, recover the angle and are 2 pi periodic in it; a Fourier
+    column of a scalar equals cos(scale u + shift)."""
     rng = np.random.default_rng(5)
-    params = M.init_params([3, 4, 2], rng)
-    u = rng.uniform(0, 2 * math.pi, (6, 3))
-    shift = np.array([math.pi, 1.0, 0.0])
-    scale = np.array([1 / math.pi, 2.0, 1.0])
-    y1, _ = M.forward(params, u, shift, scale)
-    y2, _ = M.forward(params, (u - shift) * scale)
-    assert np.array_equal(y1, y2)
+    u = np.concatenate([rng.uniform(0, 2 * math.pi, (6, 2)), rng.uniform(1.5, 3, (6, 1))], axis=1)
+    cols = [(0, 1, 0.0, 1.0), (0, 2, 0.0, 1.0), (1, 1, 0.0, 1.0), (1, 2, 0.0, 1.0), (2, 0, 2.25, 1 / 0.75),
+            (2, 1, 0.5, 3.0)]
+    x = M.embed(u, cols)
+    assert x.shape == (6, 6)
+    assert np.allclose(x[:, 0] ** 2 + x[:, 1] ** 2, 1.0, atol=1e-15)
+    assert np.allclose(np.arctan2(x[:, 1], x[:, 0]) % (2 * math.pi), u[:, 0], atol=1e-13)
+    assert np.allclose(x[:, 4], (u[:, 2] - 2.25) / 0.75, atol=0)
+    assert np.allclose(x[:, 5], [math.cos(3.0 * v + 0.5) for v in u[:, 2]], atol=1e-15)
+    u2 = u.copy()
+    u2[:, :2] += 2 * math.pi
+    assert np.allclose(M.embed(u2, cols)[:, :4], x[:, :4], atol=1e-13)
+    assert np.array_equal(M.embed(u), u)
 
 
 def test_adam_constant_gradient_closed_form():
