@@ -65,13 +65,14 @@ def cpu_baseline(wl, steps):
             "sample": f"{steps} steps of the same config-3 workload (FP64 oracle, {dt:.1f} s)"}
 
 
-def run_gpu(wl, precision, steps, warmup, graphs, rows, zchunk):
+def run_gpu(wl, precision, steps, warmup, graphs, rows, zchunk, tblock=1):
     import torch
     from paper_2603_06267_amd import solver, workloads as W
     g = solver.from_workload(wl, precision=precision, n_steps=steps + warmup, shape_fn=W.shape_fn(wl),
                              device="cuda:0", bind=False)
     g.set_option(2, rows)
     g.set_option(3, zchunk)
+    g.set_option(9, tblock)
     g.bind()
     stream = torch.cuda.current_stream()
     g.set_option(1, 1 if graphs else 0)
@@ -91,6 +92,7 @@ def run_gpu(wl, precision, steps, warmup, graphs, rows, zchunk):
                               device="cuda:0", bind=False)
     gg.set_option(2, rows)
     gg.set_option(3, zchunk)
+    gg.set_option(9, tblock)
     gg.bind()
     gg.set_option(1, 1 if graphs else 0)
     gg.step(warmup)
@@ -143,7 +145,7 @@ def batched_leg(steps=512):
             "speedup": el2 / el, "setup_and_tuning_s": setup, "tiles": {k: v["best"] for k, v in tuner.cache.items()}}
 
 
-def surrogate_leg(runs, steps, log):
+def surrogate_leg(runs, steps, log, batch=256, lr=1e-3):
     """Surrogate form: data from the GPU solver, two members trained by the
     library's BF16-MFMA kernels, split-conformal calibration, then inference
     with solver fallback at 2% relative L2 on the held-out test scenarios and
@@ -164,7 +166,7 @@ def surrogate_leg(runs, steps, log):
     train = np.concatenate([np.arange(3584), np.arange(4096, len(F))])
     cal, test = np.arange(3584, 3840), np.arange(3840, 4096)
     sur = S.Surrogate(n_members=2, n_fourier=8)
-    t_train = sur.fit(U, T, train, steps=steps, log=log, log_every=max(1, steps // 4))
+    t_train = sur.fit(U, T, train, steps=steps, batch=batch, lr=lr, log=log, log_every=max(1, steps // 4))
     scale = sur.calibrate(U, T, cal)
     err, spread = sur.errors(U, T, test)
     est = sur.estimate(spread)
@@ -207,7 +209,7 @@ def surrogate_leg(runs, steps, log):
     pipeline = len(test) / t_inf
     return {"workload": f"cube with 4x4 PMUTs, 64 receivers x 512 samples; {len(F)} solver runs "
                         f"({len(train)} train, 256 calibration, 256 test)",
-            "data_s": t_data, "train_s": t_train, "train_steps_per_member": steps,
+            "data_s": t_data, "train_s": t_train, "train_steps_per_member": steps, "minibatch": batch, "lr": lr,
             "test_rel_l2_median": float(np.median(err)), "test_rel_l2_p90": float(np.quantile(err, 0.9)),
             "calibration_scale": scale, "coverage": float(np.mean(err <= est)),
             "routed_to_solver": float(mask2.mean()), "delivered_rel_l2_median": float(np.median(derr)),
@@ -231,6 +233,10 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-form leg")
     ap.add_argument("--surrogate-runs", type=int, default=4096)
     ap.add_argument("--surrogate-steps", type=int, default=3000)
+    ap.add_argument("--no-surrogate-extended", action="store_true",
+                    help="skip the surrogate trained on the larger solver-generated data set")
+    ap.add_argument("--surrogate-extended-runs", type=int, default=65536)
+    ap.add_argument("--surrogate-extended-steps", type=int, default=60000)
     ap.add_argument("--direct", action="store_true",
                     help="direct kernel launches instead of hipGraph replay (for counter collection)")
     args = ap.parse_args()
@@ -296,6 +302,10 @@ def main():
     if not args.no_surrogate:
         log("surrogate form ...")
         out["surrogate"] = surrogate_leg(args.surrogate_runs, args.surrogate_steps, log)
+        if not args.no_surrogate_extended:
+            log("surrogate form, larger data set ...")
+            out["surrogate_extended"] = surrogate_leg(args.surrogate_extended_runs, args.surrogate_extended_steps, log,
+                                                      batch=512, lr=2e-3)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         wl_cpu = W.config3(steps=args.cpu_steps)

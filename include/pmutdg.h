@@ -181,6 +181,13 @@ pmdg_status pmdg_set_option(pmdg_solver* h, int option, long value);
  * and planes per workgroup (-1 = as PMDG_OPT_TILE_ZCHUNK, 0 = whole brick). */
 #define PMDG_OPT_TILE_ROWS_SECONDARY 6
 #define PMDG_OPT_TILE_ZCHUNK_SECONDARY 7
+/* Waves per stiffness workgroup, 4 or 8 (rows per wave 1 or 2 with 8). */
+#define PMDG_OPT_TILE_WAVES 8
+/* Steps per pass of the stiffness update over memory: 1, or 2 (FP32 solvers
+ * with orders <= 5: the volume update of two steps is fused; the planes that
+ * carry the PMUT force or the interface residual get their second step
+ * after the coupling of the first).  Same arithmetic per node either way. */
+#define PMDG_OPT_TIME_BLOCK 9
 pmdg_status pmdg_kernel_times(pmdg_solver* h, double* ms3);
 
 /* Frees host resources (device memory is the caller's).  NULL is a no-op. */

@@ -23,6 +23,8 @@ OPT_GRAPH_CHUNK = 4
 OPT_TIMING = 5
 OPT_TILE_ROWS_SECONDARY = 6
 OPT_TILE_ZCHUNK_SECONDARY = 7
+OPT_TILE_WAVES = 8
+OPT_TIME_BLOCK = 9
 
 ERRNAMES = {PMDG_EINVAL: "EINVAL", PMDG_ENOMEM: "ENOMEM", PMDG_EHIP: "EHIP",
             PMDG_EUNSTABLE: "EUNSTABLE", PMDG_ESTATE: "ESTATE"}

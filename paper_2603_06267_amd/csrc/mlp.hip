@@ -239,27 +239,31 @@ __global__ void k_pack_input(const float* __restrict__ u, const int* __restrict_
 }
 
 // per-row squared error and squared target norm (normalised units), and
-// dz = 2 (y - t / out_scale) / (B n)
+// dz = 2 (y - t / (out_scale a)) / (B n); n a multiple of 4
 __global__ void __launch_bounds__(256) k_loss(const float* __restrict__ Y, const float* __restrict__ T,
                                               const int* __restrict__ idx, int nrows, int B, int n, float inv_scale,
-                                              const float* __restrict__ rowscale,
-                                              float* __restrict__ dZ, bf16_t* __restrict__ dZb,
-                                              float* __restrict__ rowerr, float* __restrict__ rownorm) {
+                                              const float* __restrict__ rowscale, float* __restrict__ dZ,
+                                              bf16_t* __restrict__ dZb, float* __restrict__ rowerr,
+                                              float* __restrict__ rownorm) {
   const int r = blockIdx.x;
   const long src = idx ? min(max(idx[r], 0), nrows - 1) : r;
   float se = 0.f, sn = 0.f;
   const float sc = 2.0f / ((float)B * (float)n);
   const float rs = rowscale[r];
   const float inv = rs != 0.f ? inv_scale / rs : 0.f;
-  for (int c = threadIdx.x; c < n; c += blockDim.x) {
-    const long o = (long)r * n + c;
-    const float tv = T[src * n + c] * inv;
-    const float d = Y[o] - tv;
-    se += d * d;
-    sn += tv * tv;
-    const float gr = sc * d;
-    dZ[o] = gr;
-    dZb[o] = f2bf(gr);
+  const float4* __restrict__ Y4 = (const float4*)(Y + (long)r * n);
+  const float4* __restrict__ T4 = (const float4*)(T + src * n);
+  float4* __restrict__ D4 = (float4*)(dZ + (long)r * n);
+  uint2* __restrict__ Db = (uint2*)(dZb + (long)r * n);
+  for (int c = threadIdx.x; c < n / 4; c += blockDim.x) {
+    const float4 yv = Y4[c], tv4 = T4[c];
+    const float t0 = tv4.x * inv, t1 = tv4.y * inv, t2 = tv4.z * inv, t3 = tv4.w * inv;
+    const float d0 = yv.x - t0, d1 = yv.y - t1, d2 = yv.z - t2, d3 = yv.w - t3;
+    se += (d0 * d0 + d1 * d1) + (d2 * d2 + d3 * d3);
+    sn += (t0 * t0 + t1 * t1) + (t2 * t2 + t3 * t3);
+    const float4 g = make_float4(sc * d0, sc * d1, sc * d2, sc * d3);
+    D4[c] = g;
+    Db[c] = make_uint2((unsigned)f2bf(g.x) | ((unsigned)f2bf(g.y) << 16), (unsigned)f2bf(g.z) | ((unsigned)f2bf(g.w) << 16));
   }
   __shared__ float s1[256], s2[256];
   s1[threadIdx.x] = se;
@@ -278,31 +282,53 @@ __global__ void __launch_bounds__(256) k_loss(const float* __restrict__ Y, const
   }
 }
 
-// db[c] = sum_r dz[r][c], 64 columns x 4 row groups per workgroup
-__global__ void __launch_bounds__(256) k_colsum(const float* __restrict__ dZ, int B, int n, float* __restrict__ db) {
+// db[c] = sum_r dz[r][c] in two passes: partial sums over chunks of 64
+// rows (64 columns x 4 row groups per workgroup), then over the chunks
+constexpr int kColChunk = 64;
+__global__ void __launch_bounds__(256) k_colsum_part(const float* __restrict__ dZ, int B, int n,
+                                                     float* __restrict__ part) {
   const int c = blockIdx.x * 64 + (threadIdx.x & 63), rg = threadIdx.x >> 6;
+  const int r0 = blockIdx.y * kColChunk, r1 = min(B, r0 + kColChunk);
   float s = 0.f;
   if (c < n)
-    for (int r = rg; r < B; r += 4) s += dZ[(long)r * n + c];
+    for (int r = r0 + rg; r < r1; r += 4) s += dZ[(long)r * n + c];
   __shared__ float sh[4][64];
   sh[rg][threadIdx.x & 63] = s;
   __syncthreads();
-  if (rg == 0 && c < n) db[c] = (sh[0][threadIdx.x] + sh[1][threadIdx.x]) + (sh[2][threadIdx.x] + sh[3][threadIdx.x]);
+  if (rg == 0 && c < n)
+    part[(long)blockIdx.y * n + c] = (sh[0][threadIdx.x] + sh[1][threadIdx.x]) + (sh[2][threadIdx.x] + sh[3][threadIdx.x]);
 }
 
+__global__ void k_colsum_fin(const float* __restrict__ part, int nchunk, int n, float* __restrict__ db) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  float s = 0.f;
+  for (int j = 0; j < nchunk; ++j) s += part[(long)j * n + c];
+  db[c] = s;
+}
+
+// Adam on 4 consecutive values per thread (n a multiple of 4)
 __global__ void k_adam(float* __restrict__ w, const float* __restrict__ gr, float* __restrict__ m,
                        float* __restrict__ v, bf16_t* __restrict__ wb, long n, float lr, float b1, float b2,
                        float eps, float c1, float c2) {
   const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float g = gr[i];
-  const float mi = b1 * m[i] + (1.f - b1) * g;
-  const float vi = b2 * v[i] + (1.f - b2) * g * g;
-  m[i] = mi;
-  v[i] = vi;
-  const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
-  w[i] = wi;
-  if (wb) wb[i] = f2bf(wi);
+  if (i >= n / 4) return;
+  const float4 g = ((const float4*)gr)[i];
+  float4 mi = ((float4*)m)[i], vi = ((float4*)v)[i], wi = ((float4*)w)[i];
+  const float ga[4] = {g.x, g.y, g.z, g.w};
+  float ma[4] = {mi.x, mi.y, mi.z, mi.w}, va[4] = {vi.x, vi.y, vi.z, vi.w}, wa[4] = {wi.x, wi.y, wi.z, wi.w};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    ma[j] = b1 * ma[j] + (1.f - b1) * ga[j];
+    va[j] = b2 * va[j] + (1.f - b2) * ga[j] * ga[j];
+    wa[j] = wa[j] - lr * (ma[j] / c1) / (sqrtf(va[j] / c2) + eps);
+  }
+  ((float4*)m)[i] = make_float4(ma[0], ma[1], ma[2], ma[3]);
+  ((float4*)v)[i] = make_float4(va[0], va[1], va[2], va[3]);
+  ((float4*)w)[i] = make_float4(wa[0], wa[1], wa[2], wa[3]);
+  if (wb)
+    ((uint2*)wb)[i] = make_uint2((unsigned)f2bf(wa[0]) | ((unsigned)f2bf(wa[1]) << 16),
+                                 (unsigned)f2bf(wa[2]) | ((unsigned)f2bf(wa[3]) << 16));
 }
 
 __global__ void k_to_bf16(const float* __restrict__ w, bf16_t* __restrict__ wb, long n) {
@@ -350,7 +376,7 @@ pmdg_status mfail(pmdg_status s, const std::string& m) {
 constexpr int kTargetBlocks = 256;  // one workgroup per CU
 constexpr size_t kPartFloats = (size_t)384 * BM * BN;
 
-// split-K factor: ks * tiles <= kTargetBlocks + tiles, chunks of >= 256
+// split-K factor: ks * tiles <= kTargetBlocks + tiles, chunks of >= 64
 void plan_split(GemmArgs& g) {
   g.mt = (g.M + BM - 1) / BM;
   g.nt = (g.N + BN - 1) / BN;
@@ -358,7 +384,7 @@ void plan_split(GemmArgs& g) {
   int ks = 1;
   if (tiles < kTargetBlocks / 2) {
     ks = (kTargetBlocks + tiles - 1) / tiles;
-    ks = std::min(ks, std::max(1, g.K / 256));
+    ks = std::min(ks, std::max(1, g.K / 64));
   }
   g.kchunk = (int)((g.K + ks - 1) / ks + BK - 1) / BK * BK;
   g.ks = (g.K + g.kchunk - 1) / g.kchunk;
@@ -434,7 +460,11 @@ static void mlp_layout(pmdg_mlp* m) {
   m->oRowNorm = take(4 * B);
   m->oEmb = take(sizeof(EmbCol) * (size_t)m->kin[0]);
   m->oRowScale = take(4 * B);
-  m->oPart = take(4 * kPartFloats);
+  // split-K partial tiles, and the column-sum partials of the bias gradients
+  int wmax = 0;
+  for (int l = 1; l <= L; ++l) wmax = std::max(wmax, m->width[l]);
+  const size_t colpart = (size_t)((B + kColChunk - 1) / kColChunk) * wmax;
+  m->oPart = take(4 * std::max(kPartFloats, colpart));
   m->bytes = o;
 }
 
@@ -498,9 +528,15 @@ static pmdg_status mlp_backward_dev(pmdg_mlp* m, const float* t, const int* idx,
       g.Cf = at<float>(m, m->odW[l]); g.ldc = k;
       MCHK((gemm<false, false, EPI_DW>(g, at<float>(m, m->oPart), st)));
     }
-    hipLaunchKernelGGL(k_colsum, dim3((unsigned)nblk(n, 64)), dim3(256), 0, st, at<float>(m, m->odZ[l]), B, n,
-                       at<float>(m, m->odb[l]));
-    MCHK(hipGetLastError());
+    {
+      const int nchunk = (B + kColChunk - 1) / kColChunk;
+      hipLaunchKernelGGL(k_colsum_part, dim3((unsigned)nblk(n, 64), nchunk), dim3(256), 0, st,
+                         at<float>(m, m->odZ[l]), B, n, at<float>(m, m->oPart));
+      MCHK(hipGetLastError());
+      hipLaunchKernelGGL(k_colsum_fin, dim3((unsigned)nblk(n, 256)), dim3(256), 0, st, at<float>(m, m->oPart), nchunk,
+                         n, at<float>(m, m->odb[l]));
+      MCHK(hipGetLastError());
+    }
     if (l > 0) {  // dz_{l-1} [B][width_l] = (dz_l W_l) * gelu'(z_{l-1})
       GemmArgs g;
       memset(&g, 0, sizeof(g));
@@ -672,6 +708,7 @@ pmdg_status pmdg_mlp_backward(pmdg_mlp* m, const float* t, int B, float* rowerr,
   if (!m || !t) return mfail(PMDG_EINVAL, "NULL argument");
   pmdg_status r = check_batch(m, m->last_idx, m->last_nrows, B);
   if (r) return r;
+  if ((uintptr_t)t & 15) return mfail(PMDG_EINVAL, "targets must be 16-byte aligned");
   if (!m->have_z || m->last_batch != B)
     return mfail(PMDG_ESTATE, "backward needs a preceding training forward (y == NULL) of the same batch");
   hipStream_t st = (hipStream_t)stream;
@@ -692,11 +729,11 @@ pmdg_status pmdg_mlp_adam(pmdg_mlp* m, float lr, float b1, float b2, float eps, 
   const float c2 = (float)(1.0 - std::pow((double)b2, m->adam_t));
   for (int l = 0; l < m->L; ++l) {
     const long nw = (long)m->width[l + 1] * m->kin[l], nb = m->width[l + 1];
-    hipLaunchKernelGGL(k_adam, dim3((unsigned)nblk(nw, 256)), dim3(256), 0, st, at<float>(m, m->oW[l]),
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)nblk(nw / 4, 256)), dim3(256), 0, st, at<float>(m, m->oW[l]),
                        at<float>(m, m->odW[l]), at<float>(m, m->omW[l]), at<float>(m, m->ovW[l]),
                        at<bf16_t>(m, m->oWb[l]), nw, lr, b1, b2, eps, c1, c2);
     MCHK(hipGetLastError());
-    hipLaunchKernelGGL(k_adam, dim3((unsigned)nblk(nb, 256)), dim3(256), 0, st, at<float>(m, m->ob[l]),
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)nblk(nb / 4, 256)), dim3(256), 0, st, at<float>(m, m->ob[l]),
                        at<float>(m, m->odb[l]), at<float>(m, m->omb[l]), at<float>(m, m->ovb[l]), (bf16_t*)nullptr,
                        nb, lr, b1, b2, eps, c1, c2);
     MCHK(hipGetLastError());

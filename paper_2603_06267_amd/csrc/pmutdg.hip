@@ -197,6 +197,8 @@ struct pmdg_solver {
   // options
   int use_graph = 1, rows = 2, zchunk = 73, graph_chunk = 64, timing = 0;
   int rows1 = 0, zchunk1 = -1;  // secondary brick's tile (0 / -1: as the primary's)
+  int waves = 4;                // waves per stiffness workgroup
+  int tblock = 1;               // steps per stiffness pass (1, or 2 for FP32)
   std::map<int, hipGraphExec_t> graphs;
   hipStream_t cap_stream = nullptr;
   double ktimes[3] = {0, 0, 0};
@@ -443,7 +445,10 @@ static size_t layout(pmdg_solver* s) {
     const std::string p = "d" + std::to_string(d) + ".";
     add(p + "P0", rb * S * B.pnodes);
     add(p + "P1", rb * S * B.pnodes);
-    if (s->prec == 32) add(p + "X", rb * S * B.pnodes);
+    if (s->prec == 32) {
+      add(p + "P2", rb * S * B.pnodes);
+      add(p + "X", rb * 2 * S * B.pnodes);
+    }
     add(p + "taps", rb * 3 * (B.N + 3) * 2 * B.N);
     add(p + "mins", rb * 3 * (B.N + 3));
   }
@@ -543,7 +548,11 @@ static DomView<Real> view(pmdg_solver* s, int d) {
   const std::string p = "d" + std::to_string(d) + ".";
   v.P[0] = dptr<Real>(s, p + "P0");
   v.P[1] = dptr<Real>(s, p + "P1");
+  v.P[2] = s->prec == 32 ? dptr<Real>(s, p + "P2") : nullptr;
+  v.nbuf = s->prec == 32 ? 3 : 2;
   v.X = s->prec == 32 ? dptr<Real>(s, p + "X") : nullptr;
+  v.xstride = (long)s->S * B.pnodes;
+  v.xsel = (const int*)(dptr<char>(s, "ctl") + 8);
   return v;
 }
 
@@ -573,9 +582,12 @@ static StiffArgs<Real> stiff_args(pmdg_solver* s, int d) {
   const Brick& B = s->b[d];
   a.rows = (d == 1 && s->rows1 > 0) ? s->rows1 : s->rows;
   const int zc = (d == 1 && s->zchunk1 >= 0) ? s->zchunk1 : s->zchunk;
+  a.waves = s->waves;
   a.nbx = B.px / 64;
-  const int TY = kWaves * a.rows;
+  const int TY = a.waves * a.rows;
   a.nby = (B.nn[1] + TY - 1) / TY;
+  a.zlo = 0;
+  a.zhi = B.nn[2] - 1;
   a.zchunk = (zc > 0) ? std::min(zc, B.nn[2]) : B.nn[2];
   a.nbz = (B.nn[2] + a.zchunk - 1) / a.zchunk;
   a.nblocks = a.nbx * a.nby * a.nbz * s->S;
@@ -672,37 +684,145 @@ static FluxArgs<Real> flux_args(pmdg_solver* s, int tick) {
   a.Aq = dptr<Real>(s, "Aq");
   a.counter = dptr<long>(s, "ctl");
   a.tick = tick;
+  a.xsel = (int*)(dptr<char>(s, "ctl") + 8);
+  a.toggle = 0;
   a.nb_fine = (s->S * nfine(s) + kWaves - 1) / kWaves;
   a.nb_coarse = (s->S * ncoarse(s) + kWaves - 1) / kWaves;
   return a;
 }
 
-template <typename Real>
-static pmdg_status enqueue_step(pmdg_solver* s, hipStream_t st, hipEvent_t* ev) {
-  const bool incr = s->prec == 32;
-  int e = 0;
-  for (int d = 0; d < s->ndom; ++d) {
-    StiffArgs<Real> a = stiff_args<Real>(s, d);
-    if (ev) HIPCHK(hipEventRecord(ev[e++], st));
-    HIPCHK(launch_stiff<Real>(a, incr, st));
-    if (ev) HIPCHK(hipEventRecord(ev[e++], st));
+// Per-kernel-class HIP events (0 stiffness, 1 face, 2 interface + tick).
+struct Timer {
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev;
+  hipError_t begin(int cls, hipStream_t st) {
+    hipEvent_t a, b;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e != hipSuccess) return e;
+    ev.push_back({cls, {a, b}});
+    return hipEventRecord(a, st);
   }
+  hipError_t end(hipStream_t st) { return hipEventRecord(ev.back().second.second, st); }
+  void release() {
+    for (auto& e : ev) {
+      (void)hipEventDestroy(e.second.first);
+      (void)hipEventDestroy(e.second.second);
+    }
+    ev.clear();
+  }
+};
+
+#define TBEGIN(cls) \
+  if (tm) HIPCHK(tm->begin(cls, st))
+#define TEND() \
+  if (tm) HIPCHK(tm->end(st))
+
+template <typename Real>
+static pmdg_status enqueue_coupling(pmdg_solver* s, hipStream_t st, Timer* tm, int toggle) {
   {
     FaceArgs<Real> a = face_args<Real>(s, 0);
-    if (ev) HIPCHK(hipEventRecord(ev[e++], st));
+    TBEGIN(1);
     HIPCHK(launch_face<Real>(a, st));
-    if (ev) HIPCHK(hipEventRecord(ev[e++], st));
+    TEND();
   }
-  if (ev) HIPCHK(hipEventRecord(ev[e++], st));
+  TBEGIN(2);
   if (s->ndom > 1) {
     FluxArgs<Real> a = flux_args<Real>(s, 1);
+    a.toggle = toggle;
     HIPCHK(launch_flux<Real>(a, st));
   } else {
-    HIPCHK(launch_tick(dptr<long>(s, "ctl"), st));
+    HIPCHK(launch_tick(dptr<long>(s, "ctl"), (int*)(dptr<char>(s, "ctl") + 8), toggle, st));
   }
-  if (ev) HIPCHK(hipEventRecord(ev[e++], st));
+  TEND();
   return PMDG_OK;
 }
+
+template <typename Real>
+static pmdg_status enqueue_step(pmdg_solver* s, hipStream_t st, Timer* tm) {
+  const bool incr = s->prec == 32;
+  for (int d = 0; d < s->ndom; ++d) {
+    StiffArgs<Real> a = stiff_args<Real>(s, d);
+    TBEGIN(0);
+    HIPCHK(launch_stiff<Real>(a, incr, st));
+    TEND();
+  }
+  return enqueue_coupling<Real>(s, st, tm, 0);
+}
+
+// Planes of brick d whose second step of a two-step pass needs the coupling
+// terms of the first: the primary's PMUT plane and interface layers, the
+// secondary's interface layers.
+static void completion_ranges(const pmdg_solver* s, int d, int r[4]) {
+  const Brick& B = s->b[d];
+  r[0] = r[2] = 1;
+  r[1] = r[3] = 0;
+  if (d == 0) {
+    if (s->Np > 0) r[0] = r[1] = 0;
+    if (s->ndom > 1) { r[2] = B.nn[2] - 1 - B.N; r[3] = B.nn[2] - 1; }
+  } else {
+    r[0] = 0;
+    r[1] = B.N;
+  }
+}
+
+static bool two_step_ok(const pmdg_solver* s) {
+  if (s->prec != 32 || s->tblock != 2) return false;
+  for (int d = 0; d < s->ndom; ++d)
+    if (stiff2_tile_rows(s->b[d].N) <= 0) return false;
+  return true;
+}
+
+static StiffArgs<float> stiff2_args(pmdg_solver* s, int d) {
+  StiffArgs<float> a = stiff_args<float>(s, d);
+  const Brick& B = s->b[d];
+  const int TYO = stiff2_tile_rows(B.N), TXO = 64 - 2 * B.N;
+  const int zc = (d == 1 && s->zchunk1 >= 0) ? s->zchunk1 : s->zchunk;
+  a.nbx = (B.nn[0] + TXO - 1) / TXO;
+  a.nby = (B.nn[1] + TYO - 1) / TYO;
+  a.zlo = 0;
+  a.zhi = B.nn[2] - 1;
+  a.zchunk = (zc > 0) ? std::min(zc, B.nn[2]) : B.nn[2];
+  a.nbz = (B.nn[2] + a.zchunk - 1) / a.zchunk;
+  a.nblocks = a.nbx * a.nby * a.nbz * s->S;
+  int r[4];
+  completion_ranges(s, d, r);
+  a.cb0 = r[0]; a.ce0 = r[1]; a.cb1 = r[2]; a.ce1 = r[3];
+  return a;
+}
+
+// Steps n+1 and n+2: two-step stiffness passes, the coupling of step n+1
+// (whose tick also swaps the live copy of the increment), single-step
+// completion of the coupled planes, the coupling of step n+2.
+static pmdg_status enqueue_pair(pmdg_solver* s, hipStream_t st, Timer* tm) {
+  for (int d = 0; d < s->ndom; ++d) {
+    StiffArgs<float> a = stiff2_args(s, d);
+    TBEGIN(0);
+    HIPCHK(launch_stiff2(a, st));
+    TEND();
+  }
+  pmdg_status r = enqueue_coupling<float>(s, st, tm, 1);
+  if (r) return r;
+  for (int d = 0; d < s->ndom; ++d) {
+    int cr[4];
+    completion_ranges(s, d, cr);
+    for (int j = 0; j < 2; ++j) {
+      if (cr[2 * j] > cr[2 * j + 1]) continue;
+      StiffArgs<float> a = stiff_args<float>(s, d);
+      a.zlo = cr[2 * j];
+      a.zhi = cr[2 * j + 1];
+      a.zchunk = a.zhi - a.zlo + 1;
+      a.nbz = 1;
+      a.nblocks = a.nbx * a.nby * s->S;
+      TBEGIN(0);
+      HIPCHK(launch_stiff<float>(a, true, st));
+      TEND();
+    }
+  }
+  return enqueue_coupling<float>(s, st, tm, 0);
+}
+
+#undef TBEGIN
+#undef TEND
 
 template <typename Real>
 static pmdg_status prime(pmdg_solver* s, hipStream_t st) {
@@ -715,8 +835,14 @@ static pmdg_status prime(pmdg_solver* s, hipStream_t st) {
   return PMDG_OK;
 }
 
-static pmdg_status enqueue(pmdg_solver* s, hipStream_t st, hipEvent_t* ev) {
-  return s->prec == 64 ? enqueue_step<double>(s, st, ev) : enqueue_step<float>(s, st, ev);
+// n steps: pairs of two-step passes where enabled, single steps otherwise
+static pmdg_status enqueue(pmdg_solver* s, hipStream_t st, int n, Timer* tm) {
+  pmdg_status r = PMDG_OK;
+  int i = 0;
+  if (two_step_ok(s))
+    for (; i + 1 < n && !r; i += 2) r = enqueue_pair(s, st, tm);
+  for (; i < n && !r; ++i) r = s->prec == 64 ? enqueue_step<double>(s, st, tm) : enqueue_step<float>(s, st, tm);
+  return r;
 }
 
 static void drop_graphs(pmdg_solver* s) {
@@ -767,17 +893,20 @@ static pmdg_status get_state_t(pmdg_solver* s, int sc, double* p, double* pp, hi
   HIPCHK(hipStreamSynchronize(st));
   long cnt = 0;
   HIPCHK(hipMemcpy(&cnt, dptr<long>(s, "ctl"), sizeof(long), hipMemcpyDeviceToHost));
-  const int cur = (int)(cnt & 1);
+  int xsel = 0;
+  HIPCHK(hipMemcpy(&xsel, dptr<char>(s, "ctl") + 8, sizeof(int), hipMemcpyDeviceToHost));
+  const int nbuf = s->prec == 32 ? 3 : 2;
+  const int cur = (int)(cnt % nbuf);
   long o = 0;
   for (int d = 0; d < s->ndom; ++d) {
     const Brick& B = s->b[d];
     const std::string pf = "d" + std::to_string(d) + ".";
     std::vector<Real> a(B.pnodes), b(B.pnodes);
-    HIPCHK(hipMemcpy(a.data(), dptr<Real>(s, pf + (cur ? "P1" : "P0")) + (size_t)sc * B.pnodes,
+    HIPCHK(hipMemcpy(a.data(), dptr<Real>(s, pf + "P" + std::to_string(cur)) + (size_t)sc * B.pnodes,
                      B.pnodes * sizeof(Real), hipMemcpyDeviceToHost));
     if (s->prec == 32)
-      HIPCHK(hipMemcpy(b.data(), dptr<Real>(s, pf + "X") + (size_t)sc * B.pnodes, B.pnodes * sizeof(Real),
-                       hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(b.data(), dptr<Real>(s, pf + "X") + ((size_t)xsel * s->S + sc) * B.pnodes,
+                       B.pnodes * sizeof(Real), hipMemcpyDeviceToHost));
     else
       HIPCHK(hipMemcpy(b.data(), dptr<Real>(s, pf + (cur ? "P0" : "P1")) + (size_t)sc * B.pnodes,
                        B.pnodes * sizeof(Real), hipMemcpyDeviceToHost));
@@ -795,7 +924,10 @@ template <typename Real>
 static pmdg_status set_state_t(pmdg_solver* s, int sc, const double* p, const double* pp, const double* q,
                                const double* qd, const double* qdd, long nstep, hipStream_t st) {
   HIPCHK(hipStreamSynchronize(st));
-  const int cur = (int)(nstep & 1);
+  int xsel = 0;
+  HIPCHK(hipMemcpy(&xsel, dptr<char>(s, "ctl") + 8, sizeof(int), hipMemcpyDeviceToHost));
+  const int nbuf = s->prec == 32 ? 3 : 2;
+  const int cur = (int)(nstep % nbuf);
   long o = 0;
   for (int d = 0; d < s->ndom; ++d) {
     const Brick& B = s->b[d];
@@ -807,10 +939,14 @@ static pmdg_status set_state_t(pmdg_solver* s, int sc, const double* p, const do
       a[di] = (Real)pv;
       b[di] = s->prec == 32 ? (Real)(pv - pq) : (Real)pq;
     }
-    HIPCHK(hipMemcpy(dptr<Real>(s, pf + (cur ? "P1" : "P0")) + (size_t)sc * B.pnodes, a.data(),
+    HIPCHK(hipMemcpy(dptr<Real>(s, pf + "P" + std::to_string(cur)) + (size_t)sc * B.pnodes, a.data(),
                      B.pnodes * sizeof(Real), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(dptr<Real>(s, pf + (s->prec == 32 ? "X" : (cur ? "P0" : "P1"))) + (size_t)sc * B.pnodes,
-                     b.data(), B.pnodes * sizeof(Real), hipMemcpyHostToDevice));
+    if (s->prec == 32)
+      HIPCHK(hipMemcpy(dptr<Real>(s, pf + "X") + ((size_t)xsel * s->S + sc) * B.pnodes, b.data(),
+                       B.pnodes * sizeof(Real), hipMemcpyHostToDevice));
+    else
+      HIPCHK(hipMemcpy(dptr<Real>(s, pf + (cur ? "P0" : "P1")) + (size_t)sc * B.pnodes, b.data(),
+                       B.pnodes * sizeof(Real), hipMemcpyHostToDevice));
     o += B.nnodes;
   }
   if (s->Np > 0) {
@@ -1130,6 +1266,14 @@ pmdg_status pmdg_set_option(pmdg_solver* s, int option, long value) {
       if (value < 0) return fail(PMDG_EINVAL, "zchunk must be >= 0");
       s->zchunk = (int)value;
       break;
+    case PMDG_OPT_TIME_BLOCK:
+      if (!(value == 1 || value == 2)) return fail(PMDG_EINVAL, "steps per stiffness pass must be 1 or 2");
+      s->tblock = (int)value;
+      break;
+    case PMDG_OPT_TILE_WAVES:
+      if (!(value == 4 || value == 8)) return fail(PMDG_EINVAL, "waves per stiffness workgroup must be 4 or 8");
+      s->waves = (int)value;
+      break;
     case PMDG_OPT_TILE_ROWS_SECONDARY:
       if (!(value == 0 || value == 1 || value == 2 || value == 4))
         return fail(PMDG_EINVAL, "tile rows per wave must be 0 (as the primary), 1, 2 or 4");
@@ -1158,40 +1302,27 @@ pmdg_status pmdg_step(pmdg_solver* s, int n, void* stream) {
   if (n == 0) return PMDG_OK;
   hipStream_t st = (hipStream_t)stream;
   if (s->timing) {
-    const int per = 2 * (s->ndom + 2);
-    std::vector<hipEvent_t> ev((size_t)n * per);
-    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
-    for (int i = 0; i < n; ++i) {
-      pmdg_status r = enqueue(s, st, ev.data() + (size_t)i * per);
-      if (r) return r;
+    Timer tm;
+    pmdg_status r = enqueue(s, st, n, &tm);
+    if (r) {
+      tm.release();
+      return r;
     }
     HIPCHK(hipStreamSynchronize(st));
     double tot[3] = {0, 0, 0};
-    for (int i = 0; i < n; ++i) {
-      hipEvent_t* e = ev.data() + (size_t)i * per;
-      int k = 0;
-      for (int d = 0; d < s->ndom; ++d, k += 2) {
-        float ms;
-        HIPCHK(hipEventElapsedTime(&ms, e[k], e[k + 1]));
-        tot[0] += ms;
-      }
+    for (auto& e : tm.ev) {
       float ms;
-      HIPCHK(hipEventElapsedTime(&ms, e[k], e[k + 1]));
-      tot[1] += ms;
-      k += 2;
-      HIPCHK(hipEventElapsedTime(&ms, e[k], e[k + 1]));
-      tot[2] += ms;
+      HIPCHK(hipEventElapsedTime(&ms, e.second.first, e.second.second));
+      tot[e.first] += ms;
     }
-    for (auto& e : ev) (void)hipEventDestroy(e);
+    tm.release();
     for (int c = 0; c < 3; ++c) s->ktimes[c] = tot[c] / n;
     s->steps_done += n;
     return PMDG_OK;
   }
   if (!s->use_graph) {
-    for (int i = 0; i < n; ++i) {
-      pmdg_status r = enqueue(s, st, nullptr);
-      if (r) return r;
-    }
+    pmdg_status r = enqueue(s, st, n, nullptr);
+    if (r) return r;
     s->steps_done += n;
     return PMDG_OK;
   }
@@ -1206,7 +1337,7 @@ pmdg_status pmdg_step(pmdg_solver* s, int n, void* stream) {
       hipGraph_t g;
       HIPCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
       pmdg_status r = PMDG_OK;
-      for (int i = 0; i < len && !r; ++i) r = enqueue(s, s->cap_stream, nullptr);
+      r = enqueue(s, s->cap_stream, len, nullptr);
       hipError_t ec = hipStreamEndCapture(s->cap_stream, &g);
       if (r) return r;
       if (ec != hipSuccess) return fail(PMDG_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
@@ -1348,6 +1479,7 @@ pmdg_status pmdg_batch_create(int n, pmdg_solver* const* solvers, pmdg_batch** o
     if (!s || !s->bound) { delete b; return fail(PMDG_ESTATE, "every solver must be bound"); }
     if (s->ndom != 1 || s->prec != 32) { delete b; return fail(PMDG_EINVAL, "batches take single-brick FP32 solvers"); }
     if (s->rows != 1 && s->rows != 2) { delete b; return fail(PMDG_EINVAL, "batched tiles use 1 or 2 rows per wave"); }
+    if (s->waves != kWaves) { delete b; return fail(PMDG_EINVAL, "batched tiles use 4 waves per workgroup"); }
     b->sv.push_back(s);
     b->nmax = std::max(b->nmax, s->b[0].N);
     b->lds = std::max(b->lds, batch_lds_bytes(s->b[0].N, s->rows));

@@ -25,8 +25,11 @@ struct DomView {
   int px;             // padded row pitch (nn[0] rounded up to a multiple of 64)
   long plane;         // px * nn[1]  (device plane stride)
   long nnodes;        // plane * nn[2] (device nodes per scenario)
-  Real* P[2];         // [S][nnodes] pressure, double-buffered by step parity
-  Real* X;            // [S][nnodes] increment p^n - p^{n-1} (increment form only)
+  Real* P[3];         // [S][nnodes] pressure; p^n is P[n % nbuf]
+  int nbuf;           // 2 (FP64 two-level form, in place) or 3 (FP32 increment form)
+  Real* X;            // [2][S][nnodes] increment p^n - p^{n-1} (increment form only);
+  long xstride;       //   the live copy is X + (*xsel) * xstride (the two-step
+  const int* xsel;    //   update reads one copy and writes the other)
 };
 
 // Stiffness + update kernel arguments (one brick).
@@ -49,7 +52,12 @@ struct StiffArgs {
   const Real* taps;         // [3][N+3][2N]: -dt^2 c^2 (M_d^{-1} K_d) off-centre entries
   const Real* mins;         // [3][N+3]: inverse assembled 1D lumped mass
   // tiling
-  int nbx, nby, nbz, zchunk, rows;
+  int nbx, nby, nbz, zchunk, rows, waves;
+  int zlo, zhi;             // planes updated: [zlo, zhi] (all by default)
+  // two-step update: planes whose second step needs the coupling terms of
+  // the first ([cb0, ce0] and [cb1, ce1]; empty if cb > ce) keep p^{n+1} and
+  // the increment of step n+1 for a completion pass
+  int cb0, ce0, cb1, ce1;
   int nblocks;
 };
 
@@ -124,6 +132,8 @@ struct FluxArgs {
   Real* Aq;                 // [S][nex0*ney0][Nq*Nq][2] SIPG terms per fine Gauss point
   long* counter;            // advanced by the coarse pass when tick != 0
   int tick;
+  int* xsel;                // toggled with the tick when toggle != 0
+  int toggle;
   int nb_fine, nb_coarse;   // blocks (4 faces each)
 };
 
@@ -136,8 +146,13 @@ template <typename Real>
 hipError_t launch_flux(const FluxArgs<Real>& a, hipStream_t st);
 template <typename Real>
 hipError_t launch_fill(Real* p, long n, Real v, hipStream_t st);
+// two steps of the FP32 increment-form stiffness update in one pass
+hipError_t launch_stiff2(const StiffArgs<float>& a, hipStream_t st);
+int stiff2_tile_rows(int N);  // owned rows per two-step tile (0: order not supported)
+hipError_t launch_stiff2_lo(const StiffArgs<float>& a, hipStream_t st);
+hipError_t launch_stiff2_hi(const StiffArgs<float>& a, hipStream_t st);
 hipError_t launch_fill_bytes(void* p, size_t n, hipStream_t st);
-hipError_t launch_tick(long* counter, hipStream_t st);
+hipError_t launch_tick(long* counter, int* xsel, int toggle, hipStream_t st);
 // batched form
 size_t batch_lds_bytes(int N, int rows);
 hipError_t batch_occupancy(int nmax, size_t lds, int* blocks_per_cu);

@@ -68,7 +68,7 @@ __device__ void face_block(const FaceArgs<Real>& a, int b) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const long cnt = *a.counter;
   const long lev = a.prime ? cnt : cnt + 1;  // time level of the pressure to sample
-  const int buf = (int)(lev & 1);
+  const int buf = (int)(lev % a.d0.nbuf);
 
   if (b < a.nb_tr0) {
     face_traces(a, 0, b * 256 + tid, buf);
@@ -365,12 +365,18 @@ __global__ void __launch_bounds__(256) k_flux_coarse(const FluxArgs<Real> a) {
     R[0] = RA;  // the stiffness kernel applies the coarse side's minus sign
     R[1] = RB;
   }
-  if (a.tick && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd((unsigned long long*)a.counter, 1ull);
+  if (a.tick && blockIdx.x == 0 && threadIdx.x == 0) {
+    atomicAdd((unsigned long long*)a.counter, 1ull);
+    if (a.toggle) atomicXor(a.xsel, 1);
+  }
 }
 
 // Advances the step counter when no interface pass ends the step.
-__global__ void k_tick(long* counter) {
-  if (threadIdx.x == 0) atomicAdd((unsigned long long*)counter, 1ull);
+__global__ void k_tick(long* counter, int* xsel, int toggle) {
+  if (threadIdx.x == 0) {
+    atomicAdd((unsigned long long*)counter, 1ull);
+    if (toggle) atomicXor(xsel, 1);
+  }
 }
 
 template <typename Real>
@@ -392,6 +398,15 @@ hipError_t launch_stiff<double>(const StiffArgs<double>& a, bool incr, hipStream
   if (incr) return hipErrorInvalidValue;  // FP64 state uses the two-level form
   return a.d.N <= 4 ? launch_stiff_f64_lo(a, st) : launch_stiff_f64_hi(a, st);
 }
+
+hipError_t launch_stiff2(const StiffArgs<float>& a, hipStream_t st) {
+  if (stiff2_tile_rows(a.d.N) <= 0) return hipErrorInvalidValue;
+  return a.d.N <= 4 ? launch_stiff2_lo(a, st) : launch_stiff2_hi(a, st);
+}
+
+// owned rows of the two-step tile: 16 extended rows less an N-row halo on
+// each side (orders above 5 are not supported)
+int stiff2_tile_rows(int N) { return (N >= 1 && N <= 5) ? 16 - 2 * N : 0; }
 
 template <typename Real>
 hipError_t launch_face(const FaceArgs<Real>& a, hipStream_t st) {
@@ -421,8 +436,8 @@ hipError_t launch_tick_batch(long* const* counters, int n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_tick(long* counter, hipStream_t st) {
-  hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, st, counter);
+hipError_t launch_tick(long* counter, int* xsel, int toggle, hipStream_t st) {
+  hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, st, counter, xsel, toggle);
   return hipGetLastError();
 }
 

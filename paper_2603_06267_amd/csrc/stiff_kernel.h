@@ -90,10 +90,11 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
   const int nx = a.d.nn[0], ny = a.d.nn[1], nz = a.d.nn[2];
   const unsigned plane = (unsigned)a.d.plane;
   const long cnt = *a.counter;
-  const int cur = (int)(cnt & 1);
+  const int cur = (int)(cnt % a.d.nbuf), nxt = (int)((cnt + 1) % a.d.nbuf);
   const Real* __restrict__ P = a.d.P[cur] + (long)s * a.d.nnodes;
-  Real* __restrict__ Pn = a.d.P[cur ^ 1] + (long)s * a.d.nnodes;
-  Real* __restrict__ X = INCR ? a.d.X + (long)s * a.d.nnodes : Pn;  // increment, or p^{n-1}
+  Real* __restrict__ Pn = a.d.P[nxt] + (long)s * a.d.nnodes;
+  // increment (live copy), or p^{n-1}
+  Real* __restrict__ X = INCR ? a.d.X + (long)(*a.d.xsel) * a.d.xstride + (long)s * a.d.nnodes : Pn;
 
   // Every load below is unconditional on a clamped address and masked
   // afterwards, so no load needs its own branch.
@@ -159,8 +160,8 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
     yh_dst[j] = hr < NT ? trow * W + N + lane : -1;
   }
 
-  const int k0 = bz * a.zchunk;
-  const int k1 = min(nz, k0 + a.zchunk);
+  const int k0 = a.zlo + bz * a.zchunk;
+  const int k1 = min(a.zhi + 1, k0 + a.zchunk);
 
   Real q[RY][NQ];
   Real xc[RY];
@@ -351,11 +352,13 @@ __global__ void __launch_bounds__(64 * WV) k_stiff(const StiffArgs<Real> a) {
 
 template <typename Real, int N, bool INCR>
 static hipError_t stiff_rows(const StiffArgs<Real>& a, hipStream_t st) {
-  dim3 g(a.nblocks), blk(64 * kWaves);
-  switch (a.rows) {
-    case 1: hipLaunchKernelGGL((k_stiff<Real, N, INCR, 1, kWaves>), g, blk, 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_stiff<Real, N, INCR, 2, kWaves>), g, blk, 0, st, a); break;
-    case 4: hipLaunchKernelGGL((k_stiff<Real, N, INCR, 4, kWaves>), g, blk, 0, st, a); break;
+  dim3 g(a.nblocks);
+  switch (a.rows + 8 * a.waves) {
+    case 1 + 32: hipLaunchKernelGGL((k_stiff<Real, N, INCR, 1, 4>), g, dim3(256), 0, st, a); break;
+    case 2 + 32: hipLaunchKernelGGL((k_stiff<Real, N, INCR, 2, 4>), g, dim3(256), 0, st, a); break;
+    case 4 + 32: hipLaunchKernelGGL((k_stiff<Real, N, INCR, 4, 4>), g, dim3(256), 0, st, a); break;
+    case 1 + 64: hipLaunchKernelGGL((k_stiff<Real, N, INCR, 1, 8>), g, dim3(512), 0, st, a); break;
+    case 2 + 64: hipLaunchKernelGGL((k_stiff<Real, N, INCR, 2, 8>), g, dim3(512), 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

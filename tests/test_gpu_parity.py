@@ -220,3 +220,86 @@ def test_config3_full_size_one_step(precision):
     err = np.abs(d).max() / scale
     _say(f"  max |diff| / max |p^(n+1) - p^n| = {err:.3e}")
     assert err < (2e-4 if precision == 32 else 1e-10)
+
+
+@pytest.mark.parametrize("case", ["cube", "nested", "4to3"])
+def test_two_step_pass_matches_single_steps(case):
+    """Fusing the volume update of two steps (the coupled planes completed
+    after the coupling of the first) gives the single-step traces, and both
+    match the oracle; odd step counts end with a single step."""
+    _say(f"two-step pass: {case}")
+    if case == "cube":
+        wl, steps = W.config1(), 121
+    else:
+        wl, steps = W.small_two_domain(case == "nested", steps=121), 121
+    sf = W.shape_fn(wl)
+    out = {}
+    for tb in (1, 2):
+        for graph in (0, 1):
+            g = solver.from_workload(wl, precision=32, n_steps=steps, shape_fn=sf, bind=False)
+            g.set_option(9, tb)
+            g.set_option(1, graph)
+            g.set_option(4, 37)
+            g.bind()
+            g.step(steps)
+            assert not g.nonfinite()
+            out[(tb, graph)] = g.read_traces()
+    ref_tr = out[(1, 0)]
+    for k, tr in out.items():
+        d = rel_l2(tr, ref_tr)
+        _say(f"  tblock={k[0]} graph={k[1]}: rel diff to single steps {d:.2e}")
+        assert d < 1e-6
+    o = ref.from_workload(wl, shape_fn=sf)
+    err = rel_l2(out[(2, 1)][0], o.step(steps))
+    _say(f"  two-step vs oracle rel L2 {err:.2e}")
+    assert err <= TOL[32]
+
+
+def test_two_step_checkpoint_resume():
+    wl = W.small_two_domain(False, steps=100)
+    sf = W.shape_fn(wl)
+    g = solver.from_workload(wl, precision=32, shape_fn=sf, bind=False)
+    g.set_option(9, 2)
+    g.bind()
+    g.step(100)
+    full = g.read_traces()
+    h = solver.from_workload(wl, precision=32, shape_fn=sf, bind=False)
+    h.set_option(9, 2)
+    h.bind()
+    h.step(44)
+    p, pp = h.get_state(0)
+    q, qd, qdd = h.read_modal(0)
+    k = solver.from_workload(wl, precision=32, shape_fn=sf, bind=False)
+    k.set_option(9, 2)
+    k.bind()
+    k.set_state(0, p, pp, q, qd, qdd, nstep=44)
+    k.step(56)
+    assert rel_l2(k.read_traces()[:, :, 44:], full[:, :, 44:]) < 1e-6
+
+
+@pytest.mark.parametrize("precision", [32])
+def test_config3_two_step_pass_full_size(precision):
+    """Full-size config 3: four steps as two two-step passes against four
+    single steps from the same smooth state (every node)."""
+    _say("config3 two-step pass, 4 steps")
+    wl = W.config3(steps=6)
+    sf = W.shape_fn(wl)
+    res = []
+    for tb in (1, 2):
+        g = solver.from_workload(wl, precision=32, n_steps=6, shape_fn=sf, bind=False)
+        g.set_option(9, tb)
+        g.bind()
+        xyz = g.node_coords()
+        p = _smooth_field(xyz, 1)
+        pp = p - 0.05 * _smooth_field(xyz, 2)
+        del xyz
+        rng = np.random.default_rng(3)
+        nm = g.Np * g.Nm
+        g.set_state(0, p, pp, np.zeros(nm), np.zeros(nm), rng.standard_normal(nm), nstep=0)
+        g.step(4)
+        pn, _ = g.get_state(0)
+        res.append(pn)
+        del g
+    d = np.abs(res[1] - res[0]).max() / np.abs(res[0]).max()
+    _say(f"  max |two-step - single| / max |p| = {d:.2e}")
+    assert d < 1e-5
