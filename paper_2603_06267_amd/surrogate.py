@@ -195,3 +195,48 @@ class Surrogate:
             sol = solve(np.asarray(F)[rows], stream=stream)
             mean[torch.as_tensor(rows, device=mean.device)] = sol
         return mean, mask, est
+
+
+def bench_network(n_infer=20, n_train=50, batch_infer=1024, batch_train=256, n_fourier=8, seed=0):
+    """Times the network kernels alone on synthetic rows: inference passes of
+    batch_infer rows and training steps of batch_train rows (ms each)."""
+    import torch
+    from . import mlp as _m
+    cols = input_columns(n_fourier)
+    widths = [len(cols)] + HIDDEN + [N_OUT]
+    m = _m.MLP(widths, max_batch=max(batch_infer, batch_train))
+    m.set_io_map(N_PMUT + 2, cols, out_scale=0.3, amp_col=AMP_COL)
+    rng = np.random.default_rng(seed)
+    m.init_params(rng)
+    n = 4096
+    F = np.concatenate([rng.uniform(0, 2 * math.pi, (n, N_PMUT)), rng.uniform(1.5, 3, (n, 1)),
+                        rng.uniform(0.5, 1, (n, 1))], 1).astype(np.float32)
+    U = torch.as_tensor(F, device="cuda")
+    T = torch.as_tensor(rng.standard_normal((n, N_OUT), dtype=np.float32) * 0.3, device="cuda")
+    y = torch.empty((batch_infer, N_OUT), device="cuda")
+    for _ in range(3):
+        m.forward(U[:batch_infer], y=y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n_infer):
+        m.forward(U[:batch_infer], y=y)
+    torch.cuda.synchronize()
+    t_inf = (time.perf_counter() - t0) / n_infer
+    idx = torch.as_tensor(np.arange(batch_train, dtype=np.int32), device="cuda")
+    for _ in range(3):
+        m.train_step(U, T, idx, 1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n_train):
+        m.train_step(U, T, idx, 1e-4)
+    torch.cuda.synchronize()
+    t_tr = (time.perf_counter() - t0) / n_train
+    flop = 2.0 * sum(a * b for a, b in zip(widths[:-1], widths[1:]))
+    return {"widths": widths, "infer_ms": t_inf * 1e3, "infer_batch": batch_infer,
+            "infer_TFLOPs": flop * batch_infer / t_inf / 1e12, "train_step_ms": t_tr * 1e3,
+            "train_batch": batch_train, "train_TFLOPs": 3 * flop * batch_train / t_tr / 1e12}
+
+
+if __name__ == "__main__":
+    import json
+    print(json.dumps(bench_network()), flush=True)
