@@ -69,8 +69,6 @@ struct GemmArgs {
   int mt, nt, ks, kchunk;
 };
 
-constexpr int BM = 128, BN = 128, BK = 32, LDK = BK + 8;
-
 template <int EPI>
 __device__ __forceinline__ void epilogue(const GemmArgs& g, int row, int col, float v) {
   const long o = (long)row * g.ldc + col;
@@ -91,16 +89,28 @@ __device__ __forceinline__ void epilogue(const GemmArgs& g, int row, int col, fl
   }
 }
 
-// One 128 x 128 output tile per workgroup of 4 waves (2 x 2), each wave
-// 64 x 64 = 2 x 2 MFMA 32x32 blocks.  MFMA 32x32x16 operand layout: lane l
-// supplies row (A) or column (B) l % 32 and eight reduction indices chosen by
-// l / 32 (the same for A and B, so the exact order within the 16 does not
-// matter); accumulator element r of lane l is row 8 (r / 4) + 4 (l / 32) +
-// r % 4, column l % 32.  The linear grid is remapped so that the workgroups
-// one XCD receives (dispatch is round-robin over the 8 XCDs) are consecutive
-// tiles that share the same B (weight) tile, which then stays in that XCD's L2.
-template <bool ACON, bool BCON, int EPI>
+// Tile shape: 4 waves in 2 x 2, each wave TM x TN MFMA 32x32 blocks, so a
+// workgroup computes (64 TM) x (64 TN) outputs over BK-deep slices.
+template <int TM, int TN, int BK>
+struct Tile {
+  static constexpr int BM = 64 * TM, BN = 64 * TN, LDK = BK + 8;
+};
+
+// One output tile per workgroup of 4 waves.  MFMA 32x32x16 operand layout:
+// lane l supplies row (A) or column (B) l % 32 and eight reduction indices
+// chosen by l / 32 (the same for A and B, so the exact order within the 16
+// does not matter); accumulator element r of lane l is row 8 (r / 4) +
+// 4 (l / 32) + r % 4, column l % 32.  The linear grid is remapped so that the
+// workgroups one XCD receives (dispatch is round-robin over the 8 XCDs) are
+// consecutive tiles that share the same B (weight) tile, which then stays in
+// that XCD's L2.  Operand rows are staged in LDS padded by 8 elements, so
+// the 16-byte fragment reads of 32 consecutive rows hit distinct banks.
+template <bool ACON, bool BCON, int EPI, int TM, int TN, int BK>
 __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
+  using TL = Tile<TM, TN, BK>;
+  constexpr int BM = TL::BM, BN = TL::BN, LDK = TL::LDK;
+  constexpr int CA = BM * BK / 8 / 256, CB = BN * BK / 8 / 256;  // 8-element chunks per thread
+  static_assert(CA * 256 * 8 == BM * BK && CB * 256 * 8 == BN * BK, "tile must split into chunks");
   __shared__ __attribute__((aligned(16))) bf16_t As[2][BM * LDK];
   __shared__ __attribute__((aligned(16))) bf16_t Bs[2][BN * LDK];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -114,17 +124,19 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
   const int m0 = (rem % g.mt) * BM, n0 = (rem / g.mt) * BN;
   const int kbeg = z * g.kchunk, kend = min(g.K, kbeg + g.kchunk);
 
+  // contiguous operand: chunk c covers row c / (BK/8), reduction 8 (c % (BK/8));
+  // strided operand: chunk c covers reduction c / (B?/8), rows 8 (c % (B?/8))
   auto load_tile = [&](int buf, int k0) {
 #pragma unroll
-    for (int c2 = 0; c2 < 2; ++c2) {
+    for (int c2 = 0; c2 < CA; ++c2) {
       const int c = tid + 256 * c2;
       if (ACON) {
-        const int row = c >> 2, kc = (c & 3) * 8;
+        const int row = c / (BK / 8), kc = (c % (BK / 8)) * 8;
         uint4 v = make_uint4(0, 0, 0, 0);
         if (m0 + row < g.M && k0 + kc < kend) v = *(const uint4*)(g.A + (long)(m0 + row) * g.lda + k0 + kc);
         *(uint4*)&As[buf][row * LDK + kc] = v;
       } else {
-        const int r = c >> 4, ic = (c & 15) * 8;
+        const int r = c / (BM / 8), ic = (c % (BM / 8)) * 8;
         uint4 v = make_uint4(0, 0, 0, 0);
         if (k0 + r < kend && m0 + ic < g.M) v = *(const uint4*)(g.A + (long)(k0 + r) * g.lda + m0 + ic);
         const bf16_t* e = (const bf16_t*)&v;
@@ -133,15 +145,15 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
       }
     }
 #pragma unroll
-    for (int c2 = 0; c2 < 2; ++c2) {
+    for (int c2 = 0; c2 < CB; ++c2) {
       const int c = tid + 256 * c2;
       if (BCON) {
-        const int col = c >> 2, kc = (c & 3) * 8;
+        const int col = c / (BK / 8), kc = (c % (BK / 8)) * 8;
         uint4 v = make_uint4(0, 0, 0, 0);
         if (n0 + col < g.N && k0 + kc < kend) v = *(const uint4*)(g.B + (long)(n0 + col) * g.ldb + k0 + kc);
         *(uint4*)&Bs[buf][col * LDK + kc] = v;
       } else {
-        const int r = c >> 4, jc = (c & 15) * 8;
+        const int r = c / (BN / 8), jc = (c % (BN / 8)) * 8;
         uint4 v = make_uint4(0, 0, 0, 0);
         if (k0 + r < kend && n0 + jc < g.N) v = *(const uint4*)(g.B + (long)(k0 + r) * g.ldb + n0 + jc);
         const bf16_t* e = (const bf16_t*)&v;
@@ -151,11 +163,11 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
     }
   };
 
-  floatx16 acc[2][2];
+  floatx16 acc[TM][TN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < TN; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
@@ -167,21 +179,21 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
     if (kt + 1 < nk) load_tile(buf ^ 1, kbeg + (kt + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 16) {
-      bf16x8 af[2], bfr[2];
+      bf16x8 af[TM], bfr[TN];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int row = wm * 64 + i * 32 + (lane & 31);
+      for (int i = 0; i < TM; ++i) {
+        const int row = wm * 32 * TM + i * 32 + (lane & 31);
         af[i] = *(const bf16x8*)&As[buf][row * LDK + kk + (lane >> 5) * 8];
       }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int col = wn * 64 + j * 32 + (lane & 31);
+      for (int j = 0; j < TN; ++j) {
+        const int col = wn * 32 * TN + j * 32 + (lane & 31);
         bfr[j] = *(const bf16x8*)&Bs[buf][col * LDK + kk + (lane >> 5) * 8];
       }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < TN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
@@ -189,13 +201,13 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
 
   float* part = g.ks > 1 ? g.part + (long)z * g.M * g.N : nullptr;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < TN; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int row = m0 + wm * 64 + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-        const int col = n0 + wn * 64 + j * 32 + (lane & 31);
+        const int row = m0 + wm * 32 * TM + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+        const int col = n0 + wn * 32 * TN + j * 32 + (lane & 31);
         if (row >= g.M || col >= g.N) continue;
         if (part) part[(long)row * g.N + col] = acc[i][j][r];
         else epilogue<EPI>(g, row, col, acc[i][j][r]);
@@ -374,10 +386,10 @@ pmdg_status mfail(pmdg_status s, const std::string& m) {
 }
 
 constexpr int kTargetBlocks = 256;  // one workgroup per CU
-constexpr size_t kPartFloats = (size_t)384 * BM * BN;
+constexpr size_t kPartFloats = (size_t)384 * 128 * 128;
 
 // split-K factor: ks * tiles <= kTargetBlocks + tiles, chunks of >= 64
-void plan_split(GemmArgs& g) {
+void plan_split(GemmArgs& g, int BM, int BN) {
   g.mt = (g.M + BM - 1) / BM;
   g.nt = (g.N + BN - 1) / BN;
   const int tiles = g.mt * g.nt;
@@ -386,23 +398,35 @@ void plan_split(GemmArgs& g) {
     ks = (kTargetBlocks + tiles - 1) / tiles;
     ks = std::min(ks, std::max(1, g.K / 64));
   }
-  g.kchunk = (int)((g.K + ks - 1) / ks + BK - 1) / BK * BK;
+  g.kchunk = (int)((g.K + ks - 1) / ks + 31) / 32 * 32;
   g.ks = (g.K + g.kchunk - 1) / g.kchunk;
 }
 
-template <bool ACON, bool BCON, int EPI>
-hipError_t gemm(GemmArgs g, float* part, hipStream_t st) {
-  plan_split(g);
+template <bool ACON, bool BCON, int EPI, int TM, int TN, int BK>
+hipError_t gemm_t(GemmArgs g, float* part, hipStream_t st) {
+  using TL = Tile<TM, TN, BK>;
+  plan_split(g, TL::BM, TL::BN);
   g.part = part;
   if (g.ks > 1 && (size_t)g.ks * g.M * g.N > kPartFloats) {
-    g.kchunk = ((g.K + BK - 1) / BK) * BK;
+    g.kchunk = ((g.K + 31) / 32) * 32;
     g.ks = 1;
   }
-  hipLaunchKernelGGL((k_gemm<ACON, BCON, EPI>), dim3(g.mt * g.nt * g.ks), dim3(256), 0, st, g);
+  hipLaunchKernelGGL((k_gemm<ACON, BCON, EPI, TM, TN, BK>), dim3(g.mt * g.nt * g.ks), dim3(256), 0, st, g);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || g.ks == 1) return e;
   hipLaunchKernelGGL((k_splitk_reduce<EPI>), dim3((unsigned)nblk((long)g.M * g.N, 256)), dim3(256), 0, st, g);
   return hipGetLastError();
+}
+
+// Tile choice: 64 x 64 tiles where 128 x 128 tiles would leave most CUs
+// idle and the reduction is short (the hidden and first layers), else
+// 128 x 128 with split-K.  (Wider 2 x 4 blocks per wave measured slower: at
+// 268 registers one wave per SIMD cannot hide the LDS and memory latency.)
+template <bool ACON, bool BCON, int EPI>
+hipError_t gemm(GemmArgs g, float* part, hipStream_t st) {
+  const long mid = (long)((g.M + 127) / 128) * ((g.N + 127) / 128);
+  if (mid < kTargetBlocks / 4 && g.K <= 2048) return gemm_t<ACON, BCON, EPI, 1, 1, 32>(g, part, st);
+  return gemm_t<ACON, BCON, EPI, 2, 2, 32>(g, part, st);
 }
 
 }  // namespace

@@ -199,8 +199,13 @@ struct pmdg_solver {
   int rows1 = 0, zchunk1 = -1;  // secondary brick's tile (0 / -1: as the primary's)
   int waves = 4;                // waves per stiffness workgroup
   int tblock = 1;               // steps per stiffness pass (1, or 2 for FP32)
+  int overlap = 1;              // PMUT face work alongside the secondary's stiffness
   std::map<int, hipGraphExec_t> graphs;
   hipStream_t cap_stream = nullptr;
+  // side stream and events for running the PMUT part of the face kernel
+  // alongside the secondary brick's stiffness launch
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   double ktimes[3] = {0, 0, 0};
 };
 
@@ -737,8 +742,45 @@ static pmdg_status enqueue_coupling(pmdg_solver* s, hipStream_t st, Timer* tm, i
   return PMDG_OK;
 }
 
+// Two bricks, untimed: after the primary's stiffness launch, the face work
+// that needs only the primary (PMUT sampling, modal ODE and force, the
+// primary's interface traces) runs on a side stream while the secondary's
+// stiffness launch runs; the secondary's interface traces, the receivers and
+// the interface kernels follow the join.
+template <typename Real>
+static pmdg_status enqueue_step_split(pmdg_solver* s, hipStream_t st, int toggle) {
+  if (!s->side) {
+    HIPCHK(hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming));
+  }
+  const bool incr = s->prec == 32;
+  HIPCHK(launch_stiff<Real>(stiff_args<Real>(s, 0), incr, st));
+  HIPCHK(hipEventRecord(s->ev_fork, st));
+  HIPCHK(hipStreamWaitEvent(s->side, s->ev_fork, 0));
+  FaceArgs<Real> f = face_args<Real>(s, 0);
+  FaceArgs<Real> f1 = f, f2 = f;
+  f1.nb_tr1 = 0;
+  f1.nb_rc = 0;
+  f1.R = 0;
+  f1.nblocks = std::max(1, f1.nb_tr0 + f1.nb_pm);
+  f2.nb_tr0 = 0;
+  f2.nb_pm = 0;
+  f2.nblocks = std::max(1, f2.nb_tr1 + f2.nb_rc);
+  HIPCHK(launch_face<Real>(f1, s->side));
+  HIPCHK(hipEventRecord(s->ev_join, s->side));
+  HIPCHK(launch_stiff<Real>(stiff_args<Real>(s, 1), incr, st));
+  HIPCHK(hipStreamWaitEvent(st, s->ev_join, 0));
+  HIPCHK(launch_face<Real>(f2, st));
+  FluxArgs<Real> a = flux_args<Real>(s, 1);
+  a.toggle = toggle;
+  HIPCHK(launch_flux<Real>(a, st));
+  return PMDG_OK;
+}
+
 template <typename Real>
 static pmdg_status enqueue_step(pmdg_solver* s, hipStream_t st, Timer* tm) {
+  if (!tm && s->ndom == 2 && s->overlap) return enqueue_step_split<Real>(s, st, 0);
   const bool incr = s->prec == 32;
   for (int d = 0; d < s->ndom; ++d) {
     StiffArgs<Real> a = stiff_args<Real>(s, d);
@@ -1266,6 +1308,7 @@ pmdg_status pmdg_set_option(pmdg_solver* s, int option, long value) {
       if (value < 0) return fail(PMDG_EINVAL, "zchunk must be >= 0");
       s->zchunk = (int)value;
       break;
+    case PMDG_OPT_OVERLAP: s->overlap = value ? 1 : 0; break;
     case PMDG_OPT_TIME_BLOCK:
       if (!(value == 1 || value == 2)) return fail(PMDG_EINVAL, "steps per stiffness pass must be 1 or 2");
       s->tblock = (int)value;
@@ -1422,6 +1465,9 @@ void pmdg_destroy(pmdg_solver* s) {
   if (!s) return;
   drop_graphs(s);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+  if (s->side) (void)hipStreamDestroy(s->side);
+  if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
+  if (s->ev_join) (void)hipEventDestroy(s->ev_join);
   delete s;
 }
 

@@ -41,11 +41,14 @@ def _model(widths, max_batch):
     return mlp.MLP(widths, max_batch=max_batch)
 
 
-@pytest.mark.parametrize("widths,B", [([40, 264], 136), ([2048, 64], 64), ([96, 520], 1000)])
+@pytest.mark.parametrize("widths,B", [([40, 264], 136), ([2048, 64], 64), ([96, 520], 1000), ([64, 1032], 1024),
+                                      ([32, 8200], 1024)])
 def test_linear_layer_bit_exact(widths, B):
     """One linear layer with dyadic inputs, weights and biases: ragged tiles
-    in every dimension, a split-K launch ([2048, 64] at batch 64) and an
-    input width padded from 40/96 to a multiple of 32."""
+    in every dimension, a split-K launch ([2048, 64] at batch 64), an input
+    width padded from 40/96 to a multiple of 32, and both tile shapes: 64 x 64
+    (small grids) and 128 x 128 ([64, 1032], and [32, 8200] at batch 1024
+    with a ragged last column tile)."""
     _say(f"linear exact widths={widths} B={B}")
     rng = np.random.default_rng(1)
     W = _dyadic(rng, (widths[1], widths[0]), 4, 16)

@@ -303,3 +303,22 @@ def test_config3_two_step_pass_full_size(precision):
     d = np.abs(res[1] - res[0]).max() / np.abs(res[0]).max()
     _say(f"  max |two-step - single| / max |p| = {d:.2e}")
     assert d < 1e-5
+
+
+@pytest.mark.parametrize("graph", [0, 1])
+def test_overlapped_face_work_equals_sequential(graph):
+    """Running the PMUT face work on a side stream alongside the secondary's
+    stiffness launch gives bitwise the traces and modal state of running
+    every kernel in sequence."""
+    wl = W.small_two_domain(False, steps=90)
+    sf = W.shape_fn(wl)
+    res = []
+    for ov in (0, 1):
+        g = solver.from_workload(wl, precision=32, shape_fn=sf, bind=False)
+        g.set_option(10, ov)
+        g.set_option(1, graph)
+        g.bind()
+        g.step(90)
+        res.append((g.read_traces(), g.read_modal(0)[2]))
+    assert np.array_equal(res[0][0], res[1][0])
+    assert np.array_equal(res[0][1], res[1][1])
