@@ -188,10 +188,10 @@ pmdg_status pmdg_set_option(pmdg_solver* h, int option, long value);
  * carry the PMUT force or the interface residual get their second step
  * after the coupling of the first).  Same arithmetic per node either way. */
 #define PMDG_OPT_TIME_BLOCK 9
-/* Two bricks: 1 (default) runs the face work that needs only the primary
- * (PMUT sampling, modal ODE, force, primary interface traces) on a side
- * stream alongside the secondary's stiffness launch; 0 runs every kernel of
- * a step in sequence.  Same results either way. */
+/* Two bricks: 1 runs the face work that needs only the primary (PMUT
+ * sampling, modal ODE, force, primary interface traces) on a side stream
+ * alongside the secondary's stiffness launch; 0 (default) runs every kernel
+ * of a step in sequence.  Same results either way. */
 #define PMDG_OPT_OVERLAP 10
 pmdg_status pmdg_kernel_times(pmdg_solver* h, double* ms3);
 

@@ -199,7 +199,7 @@ struct pmdg_solver {
   int rows1 = 0, zchunk1 = -1;  // secondary brick's tile (0 / -1: as the primary's)
   int waves = 4;                // waves per stiffness workgroup
   int tblock = 1;               // steps per stiffness pass (1, or 2 for FP32)
-  int overlap = 1;              // PMUT face work alongside the secondary's stiffness
+  int overlap = 0;              // PMUT face work alongside the secondary's stiffness
   std::map<int, hipGraphExec_t> graphs;
   hipStream_t cap_stream = nullptr;
   // side stream and events for running the PMUT part of the face kernel
