@@ -226,6 +226,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--rows", type=int, default=2)
     ap.add_argument("--zchunk", type=int, default=73)
+    ap.add_argument("--tblock", type=int, default=1, choices=(1, 2),
+                    help="steps per stiffness pass (2: the fused two-step pass)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 instantiation")
@@ -253,7 +255,8 @@ def main():
 
     log(f"config 3: {dofs} unique DOFs ({W.element_local_dofs(wl)} element-local); FP32 run, "
         f"{args.warmup} warmup + {args.steps} timed steps")
-    el, el_graph, kt, finite = run_gpu(wl, 32, args.steps, args.warmup, not args.direct, args.rows, args.zchunk)
+    el, el_graph, kt, finite = run_gpu(wl, 32, args.steps, args.warmup, not args.direct, args.rows, args.zchunk,
+                                       args.tblock)
     log(f"  timed (events): {el * 1e3 / args.steps:.4f} ms/step; graph replay: {el_graph * 1e3 / args.steps:.4f} "
         f"ms/step; kernels ms: stiff {kt[0]:.4f} face {kt[1]:.4f} flux {kt[2]:.4f}")
     best = min(el, el_graph)
@@ -263,7 +266,7 @@ def main():
     # increment form moves 16 B per DOF by design (p and p^n - p^{n-1}).
     bytes_per_step = 12.0 * (n0 + n1)
     achieved = bytes_per_step / (kt[0] * 1e-3) / 1e9
-    traffic = measured_traffic(args.rows, args.zchunk)
+    traffic = measured_traffic(args.rows, args.zchunk) if args.tblock == 1 else None
     out = {
         "metric": "DOF-updates/s",
         "value": value,

@@ -184,7 +184,7 @@ pmdg_status pmdg_set_option(pmdg_solver* h, int option, long value);
 /* Waves per stiffness workgroup, 4 or 8 (rows per wave 1 or 2 with 8). */
 #define PMDG_OPT_TILE_WAVES 8
 /* Steps per pass of the stiffness update over memory: 1, or 2 (FP32 solvers
- * with orders <= 5: the volume update of two steps is fused; the planes that
+ * with orders <= 4: the volume update of two steps is fused; the planes that
  * carry the PMUT force or the interface residual get their second step
  * after the coupling of the first).  Same arithmetic per node either way. */
 #define PMDG_OPT_TIME_BLOCK 9
@@ -193,6 +193,8 @@ pmdg_status pmdg_set_option(pmdg_solver* h, int option, long value);
  * alongside the secondary's stiffness launch; 0 (default) runs every kernel
  * of a step in sequence.  Same results either way. */
 #define PMDG_OPT_OVERLAP 10
+/* PMDG_OPT_TIME_BLOCK for the secondary brick alone (0 = as the primary). */
+#define PMDG_OPT_TIME_BLOCK_SECONDARY 11
 pmdg_status pmdg_kernel_times(pmdg_solver* h, double* ms3);
 
 /* Frees host resources (device memory is the caller's).  NULL is a no-op. */

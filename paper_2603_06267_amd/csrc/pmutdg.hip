@@ -198,7 +198,8 @@ struct pmdg_solver {
   int use_graph = 1, rows = 2, zchunk = 73, graph_chunk = 64, timing = 0;
   int rows1 = 0, zchunk1 = -1;  // secondary brick's tile (0 / -1: as the primary's)
   int waves = 4;                // waves per stiffness workgroup
-  int tblock = 1;               // steps per stiffness pass (1, or 2 for FP32)
+  int tblock = 1;               // steps per stiffness pass of the primary (1, or 2 for FP32)
+  int tblock1 = 0;              // same for the secondary (0: as the primary)
   int overlap = 0;              // PMUT face work alongside the secondary's stiffness
   std::map<int, hipGraphExec_t> graphs;
   hipStream_t cap_stream = nullptr;
@@ -557,7 +558,7 @@ static DomView<Real> view(pmdg_solver* s, int d) {
   v.nbuf = s->prec == 32 ? 3 : 2;
   v.X = s->prec == 32 ? dptr<Real>(s, p + "X") : nullptr;
   v.xstride = (long)s->S * B.pnodes;
-  v.xsel = (const int*)(dptr<char>(s, "ctl") + 8);
+  v.xsel = (const int*)(dptr<char>(s, "ctl") + 8 + 4 * d);
   return v;
 }
 
@@ -690,7 +691,7 @@ static FluxArgs<Real> flux_args(pmdg_solver* s, int tick) {
   a.counter = dptr<long>(s, "ctl");
   a.tick = tick;
   a.xsel = (int*)(dptr<char>(s, "ctl") + 8);
-  a.toggle = 0;
+  a.toggle = 0;  // bit d: swap brick d's live increment copy
   a.nb_fine = (s->S * nfine(s) + kWaves - 1) / kWaves;
   a.nb_coarse = (s->S * ncoarse(s) + kWaves - 1) / kWaves;
   return a;
@@ -807,11 +808,17 @@ static void completion_ranges(const pmdg_solver* s, int d, int r[4]) {
   }
 }
 
-static bool two_step_ok(const pmdg_solver* s) {
-  if (s->prec != 32 || s->tblock != 2) return false;
+// brick d advances two steps per stiffness pass
+static bool two_step(const pmdg_solver* s, int d) {
+  if (s->prec != 32) return false;
+  const int tb = (d == 1 && s->tblock1 > 0) ? s->tblock1 : s->tblock;
+  return tb == 2 && stiff2_tile_rows(s->b[d].N) > 0;
+}
+
+static bool two_step_any(const pmdg_solver* s) {
   for (int d = 0; d < s->ndom; ++d)
-    if (stiff2_tile_rows(s->b[d].N) <= 0) return false;
-  return true;
+    if (two_step(s, d)) return true;
+  return false;
 }
 
 static StiffArgs<float> stiff2_args(pmdg_solver* s, int d) {
@@ -832,19 +839,31 @@ static StiffArgs<float> stiff2_args(pmdg_solver* s, int d) {
   return a;
 }
 
-// Steps n+1 and n+2: two-step stiffness passes, the coupling of step n+1
-// (whose tick also swaps the live copy of the increment), single-step
-// completion of the coupled planes, the coupling of step n+2.
+// Steps n+1 and n+2.  Bricks with two-step passes: the fused pass, then,
+// after the coupling of step n+1 (whose tick swaps their live increment
+// copies), a single-step completion of their coupled planes.  Other bricks:
+// a single step before and a single step after that coupling.
 static pmdg_status enqueue_pair(pmdg_solver* s, hipStream_t st, Timer* tm) {
+  int mask = 0;
   for (int d = 0; d < s->ndom; ++d) {
-    StiffArgs<float> a = stiff2_args(s, d);
     TBEGIN(0);
-    HIPCHK(launch_stiff2(a, st));
+    if (two_step(s, d)) {
+      HIPCHK(launch_stiff2(stiff2_args(s, d), st));
+      mask |= 1 << d;
+    } else {
+      HIPCHK(launch_stiff<float>(stiff_args<float>(s, d), true, st));
+    }
     TEND();
   }
-  pmdg_status r = enqueue_coupling<float>(s, st, tm, 1);
+  pmdg_status r = enqueue_coupling<float>(s, st, tm, mask);
   if (r) return r;
   for (int d = 0; d < s->ndom; ++d) {
+    if (!two_step(s, d)) {
+      TBEGIN(0);
+      HIPCHK(launch_stiff<float>(stiff_args<float>(s, d), true, st));
+      TEND();
+      continue;
+    }
     int cr[4];
     completion_ranges(s, d, cr);
     for (int j = 0; j < 2; ++j) {
@@ -881,7 +900,7 @@ static pmdg_status prime(pmdg_solver* s, hipStream_t st) {
 static pmdg_status enqueue(pmdg_solver* s, hipStream_t st, int n, Timer* tm) {
   pmdg_status r = PMDG_OK;
   int i = 0;
-  if (two_step_ok(s))
+  if (two_step_any(s))
     for (; i + 1 < n && !r; i += 2) r = enqueue_pair(s, st, tm);
   for (; i < n && !r; ++i) r = s->prec == 64 ? enqueue_step<double>(s, st, tm) : enqueue_step<float>(s, st, tm);
   return r;
@@ -935,8 +954,8 @@ static pmdg_status get_state_t(pmdg_solver* s, int sc, double* p, double* pp, hi
   HIPCHK(hipStreamSynchronize(st));
   long cnt = 0;
   HIPCHK(hipMemcpy(&cnt, dptr<long>(s, "ctl"), sizeof(long), hipMemcpyDeviceToHost));
-  int xsel = 0;
-  HIPCHK(hipMemcpy(&xsel, dptr<char>(s, "ctl") + 8, sizeof(int), hipMemcpyDeviceToHost));
+  int xsels[2] = {0, 0};
+  HIPCHK(hipMemcpy(xsels, dptr<char>(s, "ctl") + 8, sizeof(xsels), hipMemcpyDeviceToHost));
   const int nbuf = s->prec == 32 ? 3 : 2;
   const int cur = (int)(cnt % nbuf);
   long o = 0;
@@ -947,7 +966,7 @@ static pmdg_status get_state_t(pmdg_solver* s, int sc, double* p, double* pp, hi
     HIPCHK(hipMemcpy(a.data(), dptr<Real>(s, pf + "P" + std::to_string(cur)) + (size_t)sc * B.pnodes,
                      B.pnodes * sizeof(Real), hipMemcpyDeviceToHost));
     if (s->prec == 32)
-      HIPCHK(hipMemcpy(b.data(), dptr<Real>(s, pf + "X") + ((size_t)xsel * s->S + sc) * B.pnodes,
+      HIPCHK(hipMemcpy(b.data(), dptr<Real>(s, pf + "X") + ((size_t)xsels[d] * s->S + sc) * B.pnodes,
                        B.pnodes * sizeof(Real), hipMemcpyDeviceToHost));
     else
       HIPCHK(hipMemcpy(b.data(), dptr<Real>(s, pf + (cur ? "P0" : "P1")) + (size_t)sc * B.pnodes,
@@ -966,8 +985,8 @@ template <typename Real>
 static pmdg_status set_state_t(pmdg_solver* s, int sc, const double* p, const double* pp, const double* q,
                                const double* qd, const double* qdd, long nstep, hipStream_t st) {
   HIPCHK(hipStreamSynchronize(st));
-  int xsel = 0;
-  HIPCHK(hipMemcpy(&xsel, dptr<char>(s, "ctl") + 8, sizeof(int), hipMemcpyDeviceToHost));
+  int xsels[2] = {0, 0};
+  HIPCHK(hipMemcpy(xsels, dptr<char>(s, "ctl") + 8, sizeof(xsels), hipMemcpyDeviceToHost));
   const int nbuf = s->prec == 32 ? 3 : 2;
   const int cur = (int)(nstep % nbuf);
   long o = 0;
@@ -984,7 +1003,7 @@ static pmdg_status set_state_t(pmdg_solver* s, int sc, const double* p, const do
     HIPCHK(hipMemcpy(dptr<Real>(s, pf + "P" + std::to_string(cur)) + (size_t)sc * B.pnodes, a.data(),
                      B.pnodes * sizeof(Real), hipMemcpyHostToDevice));
     if (s->prec == 32)
-      HIPCHK(hipMemcpy(dptr<Real>(s, pf + "X") + ((size_t)xsel * s->S + sc) * B.pnodes, b.data(),
+      HIPCHK(hipMemcpy(dptr<Real>(s, pf + "X") + ((size_t)xsels[d] * s->S + sc) * B.pnodes, b.data(),
                        B.pnodes * sizeof(Real), hipMemcpyHostToDevice));
     else
       HIPCHK(hipMemcpy(dptr<Real>(s, pf + (cur ? "P0" : "P1")) + (size_t)sc * B.pnodes, b.data(),
@@ -1312,6 +1331,11 @@ pmdg_status pmdg_set_option(pmdg_solver* s, int option, long value) {
     case PMDG_OPT_TIME_BLOCK:
       if (!(value == 1 || value == 2)) return fail(PMDG_EINVAL, "steps per stiffness pass must be 1 or 2");
       s->tblock = (int)value;
+      break;
+    case PMDG_OPT_TIME_BLOCK_SECONDARY:
+      if (!(value == 0 || value == 1 || value == 2))
+        return fail(PMDG_EINVAL, "steps per stiffness pass must be 0 (as the primary), 1 or 2");
+      s->tblock1 = (int)value;
       break;
     case PMDG_OPT_TILE_WAVES:
       if (!(value == 4 || value == 8)) return fail(PMDG_EINVAL, "waves per stiffness workgroup must be 4 or 8");

@@ -132,8 +132,8 @@ struct FluxArgs {
   Real* Aq;                 // [S][nex0*ney0][Nq*Nq][2] SIPG terms per fine Gauss point
   long* counter;            // advanced by the coarse pass when tick != 0
   int tick;
-  int* xsel;                // toggled with the tick when toggle != 0
-  int toggle;
+  int* xsel;                // [2] live increment copy per brick; with the
+  int toggle;               // tick, bit d of toggle swaps brick d's
   int nb_fine, nb_coarse;   // blocks (4 faces each)
 };
 
@@ -150,7 +150,6 @@ hipError_t launch_fill(Real* p, long n, Real v, hipStream_t st);
 hipError_t launch_stiff2(const StiffArgs<float>& a, hipStream_t st);
 int stiff2_tile_rows(int N);  // owned rows per two-step tile (0: order not supported)
 hipError_t launch_stiff2_lo(const StiffArgs<float>& a, hipStream_t st);
-hipError_t launch_stiff2_hi(const StiffArgs<float>& a, hipStream_t st);
 hipError_t launch_fill_bytes(void* p, size_t n, hipStream_t st);
 hipError_t launch_tick(long* counter, int* xsel, int toggle, hipStream_t st);
 // batched form

@@ -367,7 +367,8 @@ __global__ void __launch_bounds__(256) k_flux_coarse(const FluxArgs<Real> a) {
   }
   if (a.tick && blockIdx.x == 0 && threadIdx.x == 0) {
     atomicAdd((unsigned long long*)a.counter, 1ull);
-    if (a.toggle) atomicXor(a.xsel, 1);
+    for (int d = 0; d < 2; ++d)
+      if (a.toggle & (1 << d)) atomicXor(a.xsel + d, 1);
   }
 }
 
@@ -375,7 +376,8 @@ __global__ void __launch_bounds__(256) k_flux_coarse(const FluxArgs<Real> a) {
 __global__ void k_tick(long* counter, int* xsel, int toggle) {
   if (threadIdx.x == 0) {
     atomicAdd((unsigned long long*)counter, 1ull);
-    if (toggle) atomicXor(xsel, 1);
+    for (int d = 0; d < 2; ++d)
+      if (toggle & (1 << d)) atomicXor(xsel + d, 1);
   }
 }
 
@@ -401,12 +403,12 @@ hipError_t launch_stiff<double>(const StiffArgs<double>& a, bool incr, hipStream
 
 hipError_t launch_stiff2(const StiffArgs<float>& a, hipStream_t st) {
   if (stiff2_tile_rows(a.d.N) <= 0) return hipErrorInvalidValue;
-  return a.d.N <= 4 ? launch_stiff2_lo(a, st) : launch_stiff2_hi(a, st);
+  return launch_stiff2_lo(a, st);
 }
 
 // owned rows of the two-step tile: 16 extended rows less an N-row halo on
-// each side (orders above 5 are not supported)
-int stiff2_tile_rows(int N) { return (N >= 1 && N <= 5) ? 16 - 2 * N : 0; }
+// each side (orders above 4 are not supported)
+int stiff2_tile_rows(int N) { return (N >= 1 && N <= 4) ? 16 - 2 * N : 0; }
 
 template <typename Real>
 hipError_t launch_face(const FaceArgs<Real>& a, hipStream_t st) {

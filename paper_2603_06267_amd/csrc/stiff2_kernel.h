@@ -1,15 +1,19 @@
 // Two steps of the FP32 increment-form stiffness update in one pass over
 // memory (temporal blocking of the explicit Newmark scheme), included by
-// stiff2_lo.hip / stiff2_hi.hip.
+// stiff2_lo.hip.
 //
 // A workgroup owns a (64 - 2N) x TY node tile of every plane of a z range and
 // computes, for the tile extended by N nodes on each side (64 lanes x
 // TY + 2N rows),
 //   stage 1   p^{n+1} = p^n + X^{n+1},  X^{n+1} = X^n + a(p^n)        (as the
 //             single-step kernel: register queue along z, LDS plane of p^n),
-//             kept in an LDS ring of the last 2N+1 planes,
+//             kept in an LDS ring of the last 2N+2 planes,
 //   stage 2   p^{n+2} = p^{n+1} + X^{n+2},  X^{n+2} = X^{n+1} + a(p^{n+1})
-//             on the owned nodes, N planes behind stage 1, from the ring.
+//             on the owned nodes, N+1 planes behind stage 1, from the ring.
+// With stage 2 one plane further behind than its stencil needs, it reads
+// only ring planes completed before the iteration's barrier and never the
+// slot stage 1 is writing, so one barrier per plane suffices and the two
+// stages of different waves overlap.
 // So p^n and X^n are read once and p^{n+1}, p^{n+2}, X^{n+2} written once
 // for two steps.  Stage 1 runs N planes beyond both ends of the z range so
 // that stage 2 has its z neighbours.  Planes whose second step needs the
@@ -28,19 +32,19 @@ namespace pmdg {
 // LDS (floats): two p^n plane buffers, the p^{n+1} ring, the z rows
 template <int N, int RY, int WV>
 __host__ __device__ constexpr int stiff2_lds_elems() {
-  return 2 * (64 + 2 * N) * (WV * RY + 2 * N) + (2 * N + 1) * (WV * RY) * 64 + (N + 2) * (2 * N + 1);
+  return 2 * (64 + 2 * N) * (WV * RY + 2 * N) + (2 * N + 2) * (WV * RY) * 64 + (N + 2) * (2 * N + 1);
 }
 
 template <int N, int RY, int WV>
 __device__ __forceinline__ void stiff2_tile(const StiffArgs<float>& a, int tile_id, float* __restrict__ lds) {
   constexpr int TYE = WV * RY, TXO = 64 - 2 * N, TYO = TYE - 2 * N;
-  constexpr int W = 64 + 2 * N, H = TYE + 2 * N, NT = 2 * N, NQ = NT + 1;
+  constexpr int W = 64 + 2 * N, H = TYE + 2 * N, NT = 2 * N, NQ = NT + 1, NR = NT + 2;
   constexpr int HYR = (NT + WV - 1) / WV;                     // y-halo rows per wave
   constexpr int NXH = (TYE * NT + 64 * WV - 1) / (64 * WV);  // x-halo loads per thread
   static_assert(TYO >= 1, "tile too small for this order");
   float (*tile)[H * W] = reinterpret_cast<float (*)[H * W]>(lds);
   float (*ring)[TYE * 64] = reinterpret_cast<float (*)[TYE * 64]>(lds + 2 * H * W);
-  float* ztab = lds + 2 * H * W + NQ * TYE * 64;
+  float* ztab = lds + 2 * H * W + NR * TYE * 64;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -126,10 +130,11 @@ __device__ __forceinline__ void stiff2_tile(const StiffArgs<float>& a, int tile_
     yh_dst[j] = hr < NT ? trow * W + N + lane : -1;
   }
 
-  // output planes [k0, k1); stage 1 runs over [k0 - N, k1 + N)
+  // output planes [k0, k1); stage 1 runs over [k0 - N, k1 + N], stage 2
+  // N+1 planes behind it
   const int k0 = a.zlo + bz * a.zchunk;
   const int k1 = min(a.zhi + 1, k0 + a.zchunk);
-  const int ks = k0 - N, ke = k1 + N;
+  const int ks = k0 - N, ke = k1 + N + 1;
   auto valid_plane = [&](int k) { return k >= 0 && k < nz; };
   auto completion = [&](int k) { return (k >= a.cb0 && k <= a.ce0) || (k >= a.cb1 && k <= a.ce1); };
 
@@ -221,13 +226,14 @@ __device__ __forceinline__ void stiff2_tile(const StiffArgs<float>& a, int tile_
   };
   fetch(1, ks + 1);
 
-  // X^{n+1} of the owned nodes of the last NQ planes (stage 2 uses plane k-N)
+  // X^{n+1} of the owned nodes of the last NQ planes (stage 2 uses plane k-N-1)
   float xq[RY][NQ];
 #pragma unroll
   for (int r = 0; r < RY; ++r)
 #pragma unroll
     for (int i = 0; i < NQ; ++i) xq[r][i] = 0.f;
 
+  int rslot = 0;  // ring slot of plane k: (k - ks) mod NR
   for (int kb = ks; kb < ke; kb += 2 * NQ) {
     static_for<2 * NQ>([&](auto uc) {
       constexpr int u = decltype(uc)::value;
@@ -240,8 +246,9 @@ __device__ __forceinline__ void stiff2_tile(const StiffArgs<float>& a, int tile_
       const bool vk = valid_plane(k);
       // (1) fetch for plane k+2
       fetch(ns, k + 2);
-      // (2) plane k of p^n complete in buffer b; stage 2 of the previous
-      // plane is done with the ring slot stage 1 overwrites now
+      // (2) plane k of p^n complete in buffer b, ring plane k-1 complete,
+      // and stage 2 of the previous iteration done with the slot stage 1
+      // overwrites now
       __syncthreads();
       const float* T = tile[b];
       float col[RY + NT];
@@ -281,7 +288,7 @@ __device__ __forceinline__ void stiff2_tile(const StiffArgs<float>& a, int tile_
           x1 = xc[r] + acc;
           p1 = p0 + x1;
         }
-        ring[uq][(wave * RY + r) * 64 + lane] = p1;
+        ring[rslot][(wave * RY + r) * 64 + lane] = p1;
         xq[r][uq] = x1;
         if (own[r] && emit) {
           const unsigned idx = roff[r] + (unsigned)k * plane;
@@ -309,19 +316,25 @@ __device__ __forceinline__ void stiff2_tile(const StiffArgs<float>& a, int tile_
         q[r][uq] = (in[r] && valid_plane(kl)) ? fq[cs][r] : 0.f;
         xc[r] = (in[r] && valid_plane(k + 1)) ? fx[cs][r] : 0.f;
       }
-      // (6) ring slot of plane k complete
-      __syncthreads();
-      // (7) stage 2: p^{n+2} of the owned nodes of plane m = k - N
-      const int m = k - N;
+      // (6) stage 2: p^{n+2} of the owned nodes of plane m = k - N - 1 from
+      // ring planes m-N .. m+N = k-2N-1 .. k-1
+      const int m = k - N - 1;
       if (m >= k0 && m < k1 && !completion(m)) {
-        constexpr int um = (u + NQ - N) % NQ;  // ring slot of plane m
+        constexpr int um = (u + 2 * NQ - N - 1) % NQ;  // xq slot of plane m
+        const int rm = (rslot + NR - N - 1) % NR;       // ring slot of plane m
+        int rz[NT];                                     // ring slots of m-N..m-1, m+1..m+N
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          rz[i] = (rm + NR - N + i) % NR;
+          rz[N + i] = (rm + 1 + i) % NR;
+        }
         const int czm = node_class<N>(m, nz);
         const float* tzm = ztab + czm * (NT + 1);
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
           if (!own[r]) continue;
           const int e = wave * RY + r;
-          const float* Rm = ring[um] + e * 64 + lane;
+          const float* Rm = ring[rm] + e * 64 + lane;
           const float c0 = Rm[0];
           float acc = 0.f;
 #pragma unroll
@@ -330,8 +343,8 @@ __device__ __forceinline__ void stiff2_tile(const StiffArgs<float>& a, int tile_
             acc += tx[N + i] * (Rm[1 + i] - c0);
             acc += ty[r][i] * (Rm[(i - N) * 64] - c0);
             acc += ty[r][N + i] * (Rm[(1 + i) * 64] - c0);
-            acc += tzm[i] * (ring[(um + NQ - N + i) % NQ][e * 64 + lane] - c0);
-            acc += tzm[N + i] * (ring[(um + 1 + i) % NQ][e * 64 + lane] - c0);
+            acc += tzm[i] * (ring[rz[i]][e * 64 + lane] - c0);
+            acc += tzm[N + i] * (ring[rz[N + i]][e * 64 + lane] - c0);
           }
           const float x2 = xq[r][um] + acc;
           const unsigned idx = roff[r] + (unsigned)m * plane;
@@ -339,6 +352,7 @@ __device__ __forceinline__ void stiff2_tile(const StiffArgs<float>& a, int tile_
           X1[idx] = x2;
         }
       }
+      rslot = rslot + 1 == NR ? 0 : rslot + 1;
     });
   }
 }
@@ -349,7 +363,8 @@ __global__ void __launch_bounds__(64 * WV) k_stiff2(const StiffArgs<float> a) {
   stiff2_tile<N, RY, WV>(a, xcd_remap(blockIdx.x, a.nblocks), lds);
 }
 
-// one tile shape per order: 8 waves x 2 rows (16 extended rows)
+// one tile shape per order: 8 waves x 2 rows (16 extended rows); orders up
+// to 4 (the LDS of order 5 would exceed 64 KB)
 template <int N>
 static hipError_t stiff2_launch(const StiffArgs<float>& a, hipStream_t st) {
   hipLaunchKernelGGL((k_stiff2<N, 2, 8>), dim3(a.nblocks), dim3(512), 0, st, a);
@@ -357,6 +372,5 @@ static hipError_t stiff2_launch(const StiffArgs<float>& a, hipStream_t st) {
 }
 
 hipError_t launch_stiff2_lo(const StiffArgs<float>& a, hipStream_t st);
-hipError_t launch_stiff2_hi(const StiffArgs<float>& a, hipStream_t st);
 
 }  // namespace pmdg

@@ -234,23 +234,27 @@ def test_two_step_pass_matches_single_steps(case):
         wl, steps = W.small_two_domain(case == "nested", steps=121), 121
     sf = W.shape_fn(wl)
     out = {}
-    for tb in (1, 2):
+    # (primary, secondary) steps per pass: both single, both two-step, and
+    # two-step passes for the secondary only
+    modes = [(1, 1), (2, 2)] + ([(1, 2)] if case != "cube" else [])
+    for tb in modes:
         for graph in (0, 1):
             g = solver.from_workload(wl, precision=32, n_steps=steps, shape_fn=sf, bind=False)
-            g.set_option(9, tb)
+            g.set_option(9, tb[0])
+            g.set_option(11, tb[1])
             g.set_option(1, graph)
             g.set_option(4, 37)
             g.bind()
             g.step(steps)
             assert not g.nonfinite()
             out[(tb, graph)] = g.read_traces()
-    ref_tr = out[(1, 0)]
+    ref_tr = out[((1, 1), 0)]
     for k, tr in out.items():
         d = rel_l2(tr, ref_tr)
-        _say(f"  tblock={k[0]} graph={k[1]}: rel diff to single steps {d:.2e}")
+        _say(f"  steps per pass={k[0]} graph={k[1]}: rel diff to single steps {d:.2e}")
         assert d < 1e-6
     o = ref.from_workload(wl, shape_fn=sf)
-    err = rel_l2(out[(2, 1)][0], o.step(steps))
+    err = rel_l2(out[((2, 2), 1)][0], o.step(steps))
     _say(f"  two-step vs oracle rel L2 {err:.2e}")
     assert err <= TOL[32]
 
