@@ -195,6 +195,10 @@ pmdg_status pmdg_set_option(pmdg_solver* h, int option, long value);
 #define PMDG_OPT_OVERLAP 10
 /* PMDG_OPT_TIME_BLOCK for the secondary brick alone (0 = as the primary). */
 #define PMDG_OPT_TIME_BLOCK_SECONDARY 11
+/* Prefetch distance of the single-step stiffness update in planes: 2
+ * (default), 3 or 4.  Distances above 2 apply to bricks of order <= 4 with
+ * 4-wave tiles of 1 or 2 rows; other bricks keep 2.  Same results. */
+#define PMDG_OPT_PREFETCH 12
 pmdg_status pmdg_kernel_times(pmdg_solver* h, double* ms3);
 
 /* Frees host resources (device memory is the caller's).  NULL is a no-op. */

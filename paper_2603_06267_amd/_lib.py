@@ -27,6 +27,7 @@ OPT_TILE_WAVES = 8
 OPT_TIME_BLOCK = 9
 OPT_OVERLAP = 10
 OPT_TIME_BLOCK_SECONDARY = 11
+OPT_PREFETCH = 12
 
 ERRNAMES = {PMDG_EINVAL: "EINVAL", PMDG_ENOMEM: "ENOMEM", PMDG_EHIP: "EHIP",
             PMDG_EUNSTABLE: "EUNSTABLE", PMDG_ESTATE: "ESTATE"}

@@ -198,6 +198,7 @@ struct pmdg_solver {
   int use_graph = 1, rows = 2, zchunk = 73, graph_chunk = 64, timing = 0;
   int rows1 = 0, zchunk1 = -1;  // secondary brick's tile (0 / -1: as the primary's)
   int waves = 4;                // waves per stiffness workgroup
+  int depth = 2;                // stiffness prefetch distance in planes
   int tblock = 1;               // steps per stiffness pass of the primary (1, or 2 for FP32)
   int tblock1 = 0;              // same for the secondary (0: as the primary)
   int overlap = 0;              // PMUT face work alongside the secondary's stiffness
@@ -234,6 +235,8 @@ static int setup_brick(Brick& B, const pmdg_brick& d, std::string& err) {
   B.pplane = (long)B.px * B.nn[1];
   B.pnodes = B.pplane * B.nn[2];
   if (B.pnodes > (1L << 31) - 1024) { err = "brick too large"; return -1; }
+  // the stiffness kernel stores relative to one plane with 32-bit byte offsets
+  if (B.pplane * (long)sizeof(double) >= (1L << 31)) { err = "brick plane too large"; return -1; }
   B.rule = gll_rule(B.N);
   const int N = B.N, n1 = N + 1, NT = 2 * N;
   for (int a = 0; a < 3; ++a) {
@@ -589,6 +592,7 @@ static StiffArgs<Real> stiff_args(pmdg_solver* s, int d) {
   a.rows = (d == 1 && s->rows1 > 0) ? s->rows1 : s->rows;
   const int zc = (d == 1 && s->zchunk1 >= 0) ? s->zchunk1 : s->zchunk;
   a.waves = s->waves;
+  a.depth = deep_prefetch_built(B.N, a.rows, a.waves) ? s->depth : 2;
   a.nbx = B.px / 64;
   const int TY = a.waves * a.rows;
   a.nby = (B.nn[1] + TY - 1) / TY;
@@ -1336,6 +1340,10 @@ pmdg_status pmdg_set_option(pmdg_solver* s, int option, long value) {
       if (!(value == 0 || value == 1 || value == 2))
         return fail(PMDG_EINVAL, "steps per stiffness pass must be 0 (as the primary), 1 or 2");
       s->tblock1 = (int)value;
+      break;
+    case PMDG_OPT_PREFETCH:
+      if (!(value >= 2 && value <= 4)) return fail(PMDG_EINVAL, "prefetch distance must be 2, 3 or 4 planes");
+      s->depth = (int)value;
       break;
     case PMDG_OPT_TILE_WAVES:
       if (!(value == 4 || value == 8)) return fail(PMDG_EINVAL, "waves per stiffness workgroup must be 4 or 8");

@@ -32,6 +32,12 @@ struct DomView {
   const int* xsel;    //   update reads one copy and writes the other)
 };
 
+// Prefetch distances beyond two planes are built for orders up to 4 and
+// 4-wave tiles of 1 or 2 rows per wave.
+__host__ __device__ constexpr bool deep_prefetch_built(int N, int rows, int waves) {
+  return N <= 4 && waves == 4 && (rows == 1 || rows == 2);
+}
+
 // Stiffness + update kernel arguments (one brick).
 template <typename Real>
 struct StiffArgs {
@@ -53,6 +59,7 @@ struct StiffArgs {
   const Real* mins;         // [3][N+3]: inverse assembled 1D lumped mass
   // tiling
   int nbx, nby, nbz, zchunk, rows, waves;
+  int depth;                // prefetch distance in planes (2, or 3 / 4 where built)
   int zlo, zhi;             // planes updated: [zlo, zhi] (all by default)
   // two-step update: planes whose second step needs the coupling terms of
   // the first ([cb0, ce0] and [cb1, ce1]; empty if cb > ce) keep p^{n+1} and

@@ -113,7 +113,8 @@ __device__ __forceinline__ void stiff2_tile(const StiffArgs<float>& a, int tile_
     const int hx = hc < N ? (bx * TXO - 2 * N + hc) : (bx * TXO - N + 64 + hc - N);
     const int y = by * TYO - N + hrow;
     xh_ok[j] = e < TYE * NT && hx >= 0 && hx < nx && y >= 0 && y < ny;
-    xh_off[j] = (unsigned)min(max(hx, 0), nx - 1) + px * (unsigned)min(max(y, 0), ny - 1);
+    // unused slots read the lane's own row segment (no extra cache lines)
+    xh_off[j] = xh_ok[j] ? (unsigned)hx + px * (unsigned)y : roff[0];
     xh_dst[j] = e < TYE * NT ? ((N + hrow) * W + (hc < N ? hc : 64 + hc)) : -1;
   }
   // y halo: N rows above and below the extended tile, 64 lanes each
@@ -126,7 +127,7 @@ __device__ __forceinline__ void stiff2_tile(const StiffArgs<float>& a, int tile_
     const int trow = hr < N ? hr : (TYE + hr);
     const int y = by * TYO - 2 * N + trow;
     yh_ok[j] = hr < NT && xin && y >= 0 && y < ny;
-    yh_off[j] = xc_ + px * (unsigned)min(max(y, 0), ny - 1);
+    yh_off[j] = yh_ok[j] ? xc_ + px * (unsigned)y : roff[0];
     yh_dst[j] = hr < NT ? trow * W + N + lane : -1;
   }
 

@@ -36,6 +36,24 @@ __device__ __forceinline__ int xcd_remap(int b, int nblk) {
   return xcd * q + min(xcd, r) + slot;
 }
 
+// Masked store without a branch: a raw buffer store relative to one plane,
+// where lanes outside the brick pass an offset beyond the plane's extent and
+// the hardware drops them.  (A global store under a divergent branch makes the
+// compiler's wait counting merge the taken and skipped paths conservatively:
+// a later wait for an earlier prefetch then also waits for loads issued after
+// the store.)  The plane must span fewer than 2^31 bytes.
+constexpr unsigned kDropOffset = 0x80000000u;
+template <typename Real>
+__device__ __forceinline__ void plane_store(Real* base, unsigned plane_bytes, unsigned off_bytes, Real v) {
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)plane_bytes, 0x00020000);
+  if constexpr (sizeof(Real) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rs, off_bytes, 0, 0);
+  } else {
+    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rs, off_bytes, 0, 0);
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
@@ -50,9 +68,9 @@ __device__ __forceinline__ T wave_sum(T v) {
 // of 2N+1 planes per owned node (its rotation is unrolled so that no register
 // moves are needed); the x and y lines are read from a double-buffered LDS
 // copy of the current plane with an N-node halo.  Everything a plane needs
-// (lead plane, halos, the increment or previous level) is fetched two planes
-// ahead so that memory latency overlaps the arithmetic of two planes, with
-// one barrier per plane.  Operator rows come by node class (x per lane, y per
+// (lead plane, halos, the increment or previous level) is fetched D planes
+// ahead (two by default) so that memory latency overlaps the arithmetic of
+// the planes in between, with one barrier per plane.  Operator rows come by node class (x per lane, y per
 // wave row, z per plane, all uniform where the class is).
 // Increment form (FP32): X holds p^n - p^{n-1}, X += a, p^{n+1} = p^n + X.
 // Two-level form (FP64): p^{n+1} = p^n + (p^n - p^{n-1}) + a over p^{n-1}.
@@ -69,11 +87,19 @@ __host__ __device__ constexpr int stiff_lds_elems() {
   return 2 * (64 + 2 * N) * (WV * RY + 2 * N) + (N + 2) * (2 * N + 1);
 }
 
+constexpr int ct_gcd(int a, int b) { return b == 0 ? a : ct_gcd(b, a % b); }
+
 // One tile of the stiffness update (tile = linear tile index of the brick
-// and scenario); lds holds stiff_lds_elems<N, RY, WV>() elements.
-template <typename Real, int N, bool INCR, int RY, int WV>
+// and scenario); lds holds stiff_lds_elems<N, RY, WV>() elements.  D is the
+// prefetch distance in planes (the loads for plane k + D are issued while
+// plane k is updated).
+template <typename Real, int N, bool INCR, int RY, int WV, int D = 2>
 __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id, Real* __restrict__ lds) {
   constexpr int TX = 64, TY = WV * RY, W = TX + 2 * N, H = TY + 2 * N, NT = 2 * N, NQ = NT + 1;
+  static_assert(D >= 2, "prefetch distance of at least two planes");
+  // unrolled planes per loop trip: queue position (mod NQ) and prefetch slot
+  // (mod D) are compile-time constants
+  constexpr int U = NQ / ct_gcd(NQ, D) * D;
   constexpr int HYR = (NT + WV - 1) / WV;              // y-halo rows per wave
   constexpr int NXH = (TY * NT + 64 * WV - 1) / (64 * WV);  // x-halo loads per thread
   Real (*tile)[H * W] = reinterpret_cast<Real (*)[H * W]>(lds);
@@ -89,6 +115,7 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
 
   const int nx = a.d.nn[0], ny = a.d.nn[1], nz = a.d.nn[2];
   const unsigned plane = (unsigned)a.d.plane;
+  const unsigned plane_bytes = plane * (unsigned)sizeof(Real);
   const long cnt = *a.counter;
   const int cur = (int)(cnt % a.d.nbuf), nxt = (int)((cnt + 1) % a.d.nbuf);
   const Real* __restrict__ P = a.d.P[cur] + (long)s * a.d.nnodes;
@@ -143,7 +170,10 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
     const int hx = hc < N ? (bx * TX - N + hc) : (bx * TX + TX + hc - N);
     const int y = by * TY + hrow;
     xh_ok[j] = e < TY * NT && hx >= 0 && hx < nx && y < ny;
-    xh_off[j] = (unsigned)min(max(hx, 0), nx - 1) + px * (unsigned)min(y, ny - 1);
+    // a slot that loads nothing useful reads the lane's own row segment, so
+    // that the wave's unused lanes share cache lines the wave loads anyway
+    // instead of touching a line each
+    xh_off[j] = xh_ok[j] ? (unsigned)hx + px * (unsigned)y : roff[0];
     xh_dst[j] = e < TY * NT ? ((N + hrow) * W + (hc < N ? hc : TX + hc)) : -1;
   }
   // y-halo rows of this wave
@@ -156,7 +186,7 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
     const int trow = hr < N ? hr : (TY + hr);
     const int y = by * TY - N + trow;
     yh_ok[j] = hr < NT && xin && y >= 0 && y < ny;
-    yh_off[j] = (unsigned)x + px * (unsigned)min(max(y, 0), ny - 1);
+    yh_off[j] = yh_ok[j] ? (unsigned)x + px * (unsigned)y : roff[0];
     yh_dst[j] = hr < NT ? trow * W + N + lane : -1;
   }
 
@@ -234,12 +264,12 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
     }
   }
 
-  // Prefetch two planes ahead: iteration k consumes the loads for plane k+1
-  // (issued at iteration k-1) and issues those for plane k+2, so each load
-  // has two plane updates of work to hide behind.  Slot j & 1 holds the
-  // data for plane j: the queue's lead plane j+N, the increment (or p^{n-1})
-  // of plane j and the x/y halos of plane j.
-  Real fq[2][RY], fx[2][RY], fhx[2][NXH], fhy[2][HYR];
+  // Prefetch D planes ahead: iteration k consumes the loads for plane k+1
+  // (issued at iteration k+1-D) and issues those for plane k+D, so each load
+  // has D-1 plane updates of work to hide behind.  Slot (j - k0) mod D holds
+  // the data for plane j: the queue's lead plane j+N, the increment (or
+  // p^{n-1}) of plane j and the x/y halos of plane j.
+  Real fq[D][RY], fx[D][RY], fhx[D][NXH], fhy[D][HYR];
   auto fetch = [&](int slot, int j) {
     const unsigned kl_off = (unsigned)min(j + N, nz - 1) * plane;
     const unsigned kn_off = (unsigned)min(j, nz - 1) * plane;
@@ -248,77 +278,92 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
       fq[slot][r] = P[roff[r] + kl_off];
       fx[slot][r] = X[roff[r] + kn_off];
     }
+    // unused halo slots read the lead-plane line of the lane's first row,
+    // which the fetch has just requested: no further L2 request
 #pragma unroll
-    for (int jj = 0; jj < NXH; ++jj) fhx[slot][jj] = P[xh_off[jj] + kn_off];
+    for (int jj = 0; jj < NXH; ++jj) fhx[slot][jj] = P[xh_off[jj] + (xh_ok[jj] ? kn_off : kl_off)];
 #pragma unroll
-    for (int jj = 0; jj < HYR; ++jj) fhy[slot][jj] = P[yh_off[jj] + kn_off];
+    for (int jj = 0; jj < HYR; ++jj) fhy[slot][jj] = P[yh_off[jj] + (yh_ok[jj] ? kn_off : kl_off)];
   };
-  fetch(1, k0 + 1);
+  static_for<D - 1>([&](auto ic) {
+    constexpr int i = decltype(ic)::value + 1;
+    fetch(i, k0 + i);
+  });
 
-  // the unrolled body covers 2 NQ planes so that both the queue position
-  // (mod NQ) and the prefetch slot (mod 2) are compile-time constants
-  for (int kb = k0; kb < k1; kb += 2 * NQ) {
-    static_for<2 * NQ>([&](auto uc) {
+  for (int kb = k0; kb < k1; kb += U) {
+    static_for<U>([&](auto uc) {
       constexpr int u = decltype(uc)::value;
       constexpr int uq = u % NQ;
-      constexpr int cs = (u + 1) & 1;  // slot of plane k+1 (k - k0 = kb - k0 + u, kb - k0 even)
-      constexpr int ns = u & 1;        // slot of plane k+2
+      constexpr int cs = (u + 1) % D;  // slot of plane k+1 (k - k0 = kb - k0 + u, U a multiple of D)
+      constexpr int ns = u % D;        // slot of plane k+D
       const int k = kb + u;
       if (k >= k1) return;
       const int b = (k - k0) & 1;
       const int kn = k + 1;
       const bool more = kn < k1;
-      // (1) fetch for plane k+2 (unconditional on clamped addresses: a
+      // (1) fetch for plane k+D (unconditional on clamped addresses: a
       // conditional load would make its registers a join that the compiler
       // settles with copies, i.e. an early wait for the load)
-      fetch(ns, k + 2);
+      fetch(ns, k + D);
       // (2) plane k is complete in buffer b
       __syncthreads();
+      // every LDS operand of the plane is read up front, so that the reads
+      // overlap one another rather than each being waited for at its use
       const Real* T = tile[b];
-      Real col[RY + NT];
+      Real col[RY + NT], xl[RY][NT], tz[NT + 1];
 #pragma unroll
       for (int j = 0; j < RY + NT; ++j) col[j] = T[(wave * RY + j) * W + N + lane];
+#pragma unroll
+      for (int r = 0; r < RY; ++r) {
+        const int row = N + wave * RY + r;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          xl[r][i] = T[row * W + lane + i];
+          xl[r][N + i] = T[row * W + N + lane + 1 + i];
+        }
+      }
       const int cz = node_class<N>(k, nz);
-      const Real* tz = ztab + cz * (NT + 1);
+#pragma unroll
+      for (int i = 0; i <= NT; ++i) tz[i] = ztab[cz * (NT + 1) + i];
+      __builtin_amdgcn_sched_barrier(0);
       const Real mz = tz[NT];
       const bool in_layer = (k >= lay0 && k <= lay1);
       const int cl = k - lay0;
       // (3) update the nodes of plane k
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
-        const int row = N + wave * RY + r;
         const Real p0 = q[r][(uq + N) % NQ];
 
         Real acc = 0;
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-          acc += tx[i] * (T[row * W + lane + i] - p0);
-          acc += tx[N + i] * (T[row * W + N + lane + 1 + i] - p0);
+          acc += tx[i] * (xl[r][i] - p0);
+          acc += tx[N + i] * (xl[r][N + i] - p0);
           acc += ty[r][i] * (col[r + i] - p0);
           acc += ty[r][N + i] * (col[r + N + 1 + i] - p0);
           acc += tz[i] * (q[r][(uq + i) % NQ] - p0);
           acc += tz[N + i] * (q[r][(uq + N + 1 + i) % NQ] - p0);
         }
-        if (in[r]) {
-          const Real minv = mx * my[r] * mz;
-          if (k == 0) acc += a.dt2 * minv * fr[r];
-          if (in_layer) {
-            Real rif = RB[r] * a.iface_d[cl];
-            if (a.iface_side > 0) { if (cl == N) rif += RA[r]; }
-            else { if (cl == 0) rif -= RA[r]; }
-            acc -= a.dt2 * minv * rif;
-          }
-          const unsigned idx = roff[r] + (unsigned)k * plane;
-          Real pn;
-          if (INCR) {
-            const Real xv = xc[r] + acc;
-            pn = p0 + xv;
-            X[idx] = xv;
-          } else {
-            pn = p0 + (p0 - xc[r]) + acc;
-          }
-          Pn[idx] = pn;
+        // lanes outside the brick compute on zeros and their stores are dropped
+        const Real minv = mx * my[r] * mz;
+        if (k == 0) acc += a.dt2 * minv * fr[r];
+        if (in_layer) {
+          Real rif = RB[r] * a.iface_d[cl];
+          if (a.iface_side > 0) { if (cl == N) rif += RA[r]; }
+          else { if (cl == 0) rif -= RA[r]; }
+          acc -= a.dt2 * minv * rif;
         }
+        const unsigned soff = in[r] ? roff[r] * (unsigned)sizeof(Real) : kDropOffset;
+        const long kp = (long)k * plane;
+        Real pn;
+        if (INCR) {
+          const Real xv = xc[r] + acc;
+          pn = p0 + xv;
+          plane_store(X + kp, plane_bytes, soff, xv);
+        } else {
+          pn = p0 + (p0 - xc[r]) + acc;
+        }
+        plane_store(Pn + kp, plane_bytes, soff, pn);
       }
       // (4) plane k+1 into the other buffer
       if (more) {
@@ -344,15 +389,27 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
 }
 
 
-template <typename Real, int N, bool INCR, int RY, int WV>
+template <typename Real, int N, bool INCR, int RY, int WV, int D = 2>
 __global__ void __launch_bounds__(64 * WV) k_stiff(const StiffArgs<Real> a) {
   __shared__ Real lds[stiff_lds_elems<N, RY, WV>()];
-  stiff_tile<Real, N, INCR, RY, WV>(a, xcd_remap(blockIdx.x, a.nblocks), lds);
+  stiff_tile<Real, N, INCR, RY, WV, D>(a, xcd_remap(blockIdx.x, a.nblocks), lds);
 }
 
 template <typename Real, int N, bool INCR>
 static hipError_t stiff_rows(const StiffArgs<Real>& a, hipStream_t st) {
   dim3 g(a.nblocks);
+  if constexpr (deep_prefetch_built(N, 1, 4)) {
+    if (a.depth > 2) {
+      switch (a.rows + 8 * a.depth) {
+        case 1 + 24: hipLaunchKernelGGL((k_stiff<Real, N, INCR, 1, 4, 3>), g, dim3(256), 0, st, a); break;
+        case 2 + 24: hipLaunchKernelGGL((k_stiff<Real, N, INCR, 2, 4, 3>), g, dim3(256), 0, st, a); break;
+        case 1 + 32: hipLaunchKernelGGL((k_stiff<Real, N, INCR, 1, 4, 4>), g, dim3(256), 0, st, a); break;
+        case 2 + 32: hipLaunchKernelGGL((k_stiff<Real, N, INCR, 2, 4, 4>), g, dim3(256), 0, st, a); break;
+        default: return hipErrorInvalidValue;
+      }
+      return hipGetLastError();
+    }
+  }
   switch (a.rows + 8 * a.waves) {
     case 1 + 32: hipLaunchKernelGGL((k_stiff<Real, N, INCR, 1, 4>), g, dim3(256), 0, st, a); break;
     case 2 + 32: hipLaunchKernelGGL((k_stiff<Real, N, INCR, 2, 4>), g, dim3(256), 0, st, a); break;

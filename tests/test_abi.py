@@ -74,6 +74,10 @@ def test_setup_errors_and_state_errors():
     assert _err(s.set_pmut_shape, 0, np.full(n, 1e3)) == _lib.PMDG_EUNSTABLE
     assert _err(s.step, 1, 0) == _lib.PMDG_ESTATE
     assert _err(s.set_option, 2, 3) == _lib.PMDG_EINVAL
+    assert _err(s.set_option, _lib.OPT_PREFETCH, 1) == _lib.PMDG_EINVAL
+    assert _err(s.set_option, _lib.OPT_PREFETCH, 5) == _lib.PMDG_EINVAL
+    s.set_option(_lib.OPT_PREFETCH, 4)
+    s.set_option(_lib.OPT_PREFETCH, 2)
     assert s.workspace_size() > 0
 
 

@@ -109,6 +109,28 @@ def test_tilings_agree(rows, zchunk):
             assert np.array_equal(tr, ref_tr)
 
 
+@pytest.mark.parametrize("precision", [32, 64])
+@pytest.mark.parametrize("depth,rows,zchunk", [(3, 2, 0), (4, 2, 5), (3, 1, 11), (4, 1, 0)])
+def test_prefetch_distances_agree(precision, depth, rows, zchunk):
+    """Prefetching 3 or 4 planes ahead changes only when loads are issued:
+    state and traces are bitwise those of the 2-plane default, with z chunks
+    shorter than, and not a multiple of, the unrolled loop."""
+    wl = W.small_two_domain(False, steps=90)
+    sf = W.shape_fn(wl)
+    out = []
+    for d in (2, depth):
+        g = solver.from_workload(wl, precision=precision, shape_fn=sf, bind=False)
+        g.set_option(2, rows)
+        g.set_option(3, zchunk)
+        g.set_option(12, d)
+        g.bind()
+        g.step(90)
+        out.append((g.read_traces(), *g.get_state(0)))
+        g.close()
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+
+
 def test_scenarios_batch_equals_single():
     """S scenarios in one launch == S separate single-scenario solvers."""
     wl = W.config4()["scenarios"]
