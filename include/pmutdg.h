@@ -190,8 +190,10 @@ pmdg_status pmdg_set_option(pmdg_solver* h, int option, long value);
 #define PMDG_OPT_TIME_BLOCK 9
 /* Two bricks: 1 runs the face work that needs only the primary (PMUT
  * sampling, modal ODE, force, primary interface traces) on a side stream
- * alongside the secondary's stiffness launch; 0 (default) runs every kernel
- * of a step in sequence.  Same results either way. */
+ * alongside the secondary's stiffness launch; 2 also runs the primary's
+ * stiffness launch on that side stream, concurrently with the secondary's;
+ * 0 (default) runs every kernel of a step in sequence.  Same results in
+ * every mode; other values are rejected (PMDG_EINVAL). */
 #define PMDG_OPT_OVERLAP 10
 /* PMDG_OPT_TIME_BLOCK for the secondary brick alone (0 = as the primary). */
 #define PMDG_OPT_TIME_BLOCK_SECONDARY 11

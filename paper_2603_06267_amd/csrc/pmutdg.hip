@@ -751,7 +751,9 @@ static pmdg_status enqueue_coupling(pmdg_solver* s, hipStream_t st, Timer* tm, i
 // that needs only the primary (PMUT sampling, modal ODE and force, the
 // primary's interface traces) runs on a side stream while the secondary's
 // stiffness launch runs; the secondary's interface traces, the receivers and
-// the interface kernels follow the join.
+// the interface kernels follow the join.  Mode 2 also moves the primary's
+// stiffness launch to the side stream, so that both bricks' stiffness
+// updates (independent of each other within a step) run together.
 template <typename Real>
 static pmdg_status enqueue_step_split(pmdg_solver* s, hipStream_t st, int toggle) {
   if (!s->side) {
@@ -760,9 +762,15 @@ static pmdg_status enqueue_step_split(pmdg_solver* s, hipStream_t st, int toggle
     HIPCHK(hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming));
   }
   const bool incr = s->prec == 32;
-  HIPCHK(launch_stiff<Real>(stiff_args<Real>(s, 0), incr, st));
-  HIPCHK(hipEventRecord(s->ev_fork, st));
-  HIPCHK(hipStreamWaitEvent(s->side, s->ev_fork, 0));
+  if (s->overlap == 2) {
+    HIPCHK(hipEventRecord(s->ev_fork, st));
+    HIPCHK(hipStreamWaitEvent(s->side, s->ev_fork, 0));
+    HIPCHK(launch_stiff<Real>(stiff_args<Real>(s, 0), incr, s->side));
+  } else {
+    HIPCHK(launch_stiff<Real>(stiff_args<Real>(s, 0), incr, st));
+    HIPCHK(hipEventRecord(s->ev_fork, st));
+    HIPCHK(hipStreamWaitEvent(s->side, s->ev_fork, 0));
+  }
   FaceArgs<Real> f = face_args<Real>(s, 0);
   FaceArgs<Real> f1 = f, f2 = f;
   f1.nb_tr1 = 0;
@@ -1331,7 +1339,10 @@ pmdg_status pmdg_set_option(pmdg_solver* s, int option, long value) {
       if (value < 0) return fail(PMDG_EINVAL, "zchunk must be >= 0");
       s->zchunk = (int)value;
       break;
-    case PMDG_OPT_OVERLAP: s->overlap = value ? 1 : 0; break;
+    case PMDG_OPT_OVERLAP:
+      if (!(value >= 0 && value <= 2)) return fail(PMDG_EINVAL, "overlap mode must be 0, 1 or 2");
+      s->overlap = (int)value;
+      break;
     case PMDG_OPT_TIME_BLOCK:
       if (!(value == 1 || value == 2)) return fail(PMDG_EINVAL, "steps per stiffness pass must be 1 or 2");
       s->tblock = (int)value;

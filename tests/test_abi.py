@@ -75,6 +75,7 @@ def test_setup_errors_and_state_errors():
     assert _err(s.step, 1, 0) == _lib.PMDG_ESTATE
     assert _err(s.set_option, 2, 3) == _lib.PMDG_EINVAL
     assert _err(s.set_option, _lib.OPT_PREFETCH, 1) == _lib.PMDG_EINVAL
+    assert _err(s.set_option, _lib.OPT_OVERLAP, 3) == _lib.PMDG_EINVAL
     assert _err(s.set_option, _lib.OPT_PREFETCH, 5) == _lib.PMDG_EINVAL
     s.set_option(_lib.OPT_PREFETCH, 4)
     s.set_option(_lib.OPT_PREFETCH, 2)
