@@ -293,8 +293,8 @@ __device__ __forceinline__ void stiff2_tile(const StiffArgs<float>& a, int tile_
         xq[r][uq] = x1;
         if (own[r] && emit) {
           const unsigned idx = roff[r] + (unsigned)k * plane;
-          P1[idx] = p1;
-          if (completion(k)) X1[idx] = x1;
+          __builtin_nontemporal_store(p1, &P1[idx]);
+          if (completion(k)) __builtin_nontemporal_store(x1, &X1[idx]);
         }
       }
       // (4) plane k+1 of p^n into the other buffer
@@ -349,8 +349,8 @@ __device__ __forceinline__ void stiff2_tile(const StiffArgs<float>& a, int tile_
           }
           const float x2 = xq[r][um] + acc;
           const unsigned idx = roff[r] + (unsigned)m * plane;
-          P2[idx] = c0 + x2;
-          X1[idx] = x2;
+          __builtin_nontemporal_store(c0 + x2, &P2[idx]);
+          __builtin_nontemporal_store(x2, &X1[idx]);
         }
       }
       rslot = rslot + 1 == NR ? 0 : rslot + 1;

@@ -41,16 +41,20 @@ __device__ __forceinline__ int xcd_remap(int b, int nblk) {
 // the hardware drops them.  (A global store under a divergent branch makes the
 // compiler's wait counting merge the taken and skipped paths conservatively:
 // a later wait for an earlier prefetch then also waits for loads issued after
-// the store.)  The plane must span fewer than 2^31 bytes.
+// the store.)  The plane must span fewer than 2^31 bytes.  The stores are
+// non-temporal: nothing reads the new level before the step's face kernel,
+// and keeping it out of the way in L2 leaves room for the halo rows of p
+// that neighbouring tiles re-read.
 constexpr unsigned kDropOffset = 0x80000000u;
+constexpr int kStoreNT = 2;  // cache-policy operand: non-temporal
 template <typename Real>
 __device__ __forceinline__ void plane_store(Real* base, unsigned plane_bytes, unsigned off_bytes, Real v) {
   const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)plane_bytes, 0x00020000);
   if constexpr (sizeof(Real) == 4) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rs, off_bytes, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rs, off_bytes, 0, kStoreNT);
   } else {
     typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rs, off_bytes, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rs, off_bytes, 0, kStoreNT);
   }
 }
 
