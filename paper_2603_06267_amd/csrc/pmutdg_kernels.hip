@@ -75,31 +75,61 @@ __device__ void face_block(const FaceArgs<Real>& a, int b) {
   } else if ((b -= a.nb_tr0) < a.nb_tr1) {
     face_traces(a, 1, b * 256 + tid, buf);
   } else if ((b -= a.nb_tr1) < a.nb_pm) {
+    // One PMUT.  Every load the update needs is issued up front (state,
+    // ODE coefficients and drive value by the first threads, the sampled
+    // pressures by all), so the block waits for memory once for the gather
+    // of the samples and once for the force scatter's operands.
     const int s = b / a.Np, k = b - s * a.Np;
     const int Nm = a.Nm;
     const long qo = ((long)s * a.Np + k) * Nm;
     const int n0 = a.pm_off[k], n1 = a.pm_off[k + 1];
     const double dt = a.dt;
     if (!a.prime) {
+      double q = 0, qd = 0, qdd = 0, w = 0, ze = 0, et = 0;
+      const long pi = (long)k * Nm + tid;
       if (tid < Nm) {
-        const double q = a.q[qo + tid], qd = a.qd[qo + tid], qdd = a.qdd[qo + tid];
-        qp_s[tid] = q + dt * qd + 0.5 * dt * dt * qdd;
-        qds_s[tid] = qd + 0.5 * dt * qdd;
+        q = a.q[qo + tid];
+        qd = a.qd[qo + tid];
+        qdd = a.qdd[qo + tid];
+        w = a.omega[pi];
+        ze = a.zeta[pi];
+        et = a.eta[pi];
+      }
+      const double t = lev * dt;
+      const bool driven = !(t > a.t_switch);
+      double c2x = 0, c2y = 0, d2x = 0, d2y = 0;
+      if (tid == 0 && driven) {
+        // A g(t) sin(2 pi f t - theta) = (A cos theta) g sin(2 pi f t) - (A sin theta) g cos(2 pi f t)
+        const double* c2 = a.car + ((long)s * a.ncar + min(lev, a.ncar - 1)) * 2;
+        const double* d2 = a.dA + ((long)s * a.Np + k) * 2;
+        c2x = c2[0];
+        c2y = c2[1];
+        d2x = d2[0];
+        d2y = d2[1];
       }
       double acc[kMaxModes];
 #pragma unroll
       for (int m = 0; m < kMaxModes; ++m) acc[m] = 0.0;
       const Real* P0 = a.d0.P[buf] + (long)s * a.d0.nnodes;
       bool bad = false;
+      // mode loops run over kMaxModes with clamped, unconditional loads: a
+      // load under a per-mode condition would be waited for one mode at a time
       for (int n = n0 + tid; n < n1; n += 256) {
         const double p = (double)P0[a.pm_node[n]];
         bad |= !__builtin_isfinite(p);
         const double* B = a.pm_B + (long)n * Nm;
+        double bm[kMaxModes];
+#pragma unroll
+        for (int m = 0; m < kMaxModes; ++m) bm[m] = B[min(m, Nm - 1)];
 #pragma unroll
         for (int m = 0; m < kMaxModes; ++m)
-          if (m < Nm) acc[m] += B[m] * p;
+          if (m < Nm) acc[m] += bm[m] * p;
       }
       if (bad) atomicOr(a.nonfinite, 1);
+      if (tid < Nm) {
+        qp_s[tid] = q + dt * qd + 0.5 * dt * dt * qdd;
+        qds_s[tid] = qd + 0.5 * dt * qdd;
+      }
 #pragma unroll
       for (int m = 0; m < kMaxModes; ++m) {
         if (m < Nm) {
@@ -109,30 +139,29 @@ __device__ void face_block(const FaceArgs<Real>& a, int b) {
       }
       __syncthreads();
       if (tid == 0) {
-        const double t = lev * dt;
         double phi;
-        if (t > a.t_switch) {
+        if (!driven) {
+          double em[kMaxModes];
+#pragma unroll
+          for (int m = 0; m < kMaxModes; ++m) em[m] = a.eta[(long)k * Nm + min(m, Nm - 1)];
           phi = 0.0;
-          for (int m = 0; m < Nm; ++m) phi += a.eta[(long)k * Nm + m] * qp_s[m];
+#pragma unroll
+          for (int m = 0; m < kMaxModes; ++m)
+            if (m < Nm) phi += em[m] * qp_s[m];
           phi /= a.cap;
         } else {
-          // A g(t) sin(2 pi f t - theta) = (A cos theta) g sin(2 pi f t) - (A sin theta) g cos(2 pi f t)
-          const double* c2 = a.car + ((long)s * a.ncar + min(lev, a.ncar - 1)) * 2;
-          const double* d2 = a.dA + ((long)s * a.Np + k) * 2;
-          phi = d2[0] * c2[0] - d2[1] * c2[1];
+          phi = d2x * c2x - d2y * c2y;
         }
         phi_s = phi;
       }
       __syncthreads();
       if (tid < Nm) {
         const double g = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
-        const long pi = (long)k * Nm + tid;
-        const double w = a.omega[pi];
-        const double qdd = -w * w * qp_s[tid] - 2.0 * a.zeta[pi] * w * qds_s[tid] + g + a.eta[pi] * phi_s;
+        const double qa = -w * w * qp_s[tid] - 2.0 * ze * w * qds_s[tid] + g + et * phi_s;
         a.q[qo + tid] = qp_s[tid];
-        a.qd[qo + tid] = qds_s[tid] + 0.5 * dt * qdd;
-        a.qdd[qo + tid] = qdd;
-        qdd_s[tid] = qdd;
+        a.qd[qo + tid] = qds_s[tid] + 0.5 * dt * qa;
+        a.qdd[qo + tid] = qa;
+        qdd_s[tid] = qa;
       }
     } else {
       if (tid < Nm) qdd_s[tid] = a.qdd[qo + tid];
@@ -141,8 +170,13 @@ __device__ void face_block(const FaceArgs<Real>& a, int b) {
     Real* F = a.force + (long)s * a.d0.plane;  // padded bottom plane
     for (int n = n0 + tid; n < n1; n += 256) {
       const double* B = a.pm_B + (long)n * Nm;
+      double bm[kMaxModes];
+#pragma unroll
+      for (int m = 0; m < kMaxModes; ++m) bm[m] = B[min(m, Nm - 1)];
       double f = 0.0;
-      for (int m = 0; m < Nm; ++m) f += qdd_s[m] * B[m];
+#pragma unroll
+      for (int m = 0; m < kMaxModes; ++m)
+        if (m < Nm) f += qdd_s[m] * bm[m];
       F[a.pm_node[n]] = (Real)(-a.kappa * f);
     }
   } else if (!a.prime) {
@@ -206,7 +240,7 @@ __global__ void k_tick_batch(long* const* __restrict__ counters, int n) {
 //     last launch of a step, advances the step counter.
 // ------------------------------------------------------------------------
 template <typename Real>
-__global__ void __launch_bounds__(256) k_flux_fine(const FluxArgs<Real> a) {
+__device__ __forceinline__ void flux_fine_block(const FluxArgs<Real>& a, int blk) {
   constexpr int MQ = kMaxNq - 1;  // Nq <= 8 on Gamma_I (orders <= 7)
   __shared__ Real sT[kWaves][2][64];
   __shared__ Real sR[kWaves][2][MQ * 8];
@@ -215,7 +249,7 @@ __global__ void __launch_bounds__(256) k_flux_fine(const FluxArgs<Real> a) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int Nq = a.Nq, N0 = a.N0, N1 = a.N1, n0 = N0 + 1, n1 = N1 + 1;
   const int nfine = a.nex0 * a.ney0;
-  const int item = blockIdx.x * kWaves + w;
+  const int item = blk * kWaves + w;
   const bool valid = item < a.S * nfine;
   const int s = valid ? item / nfine : 0, f = valid ? item - s * nfine : 0;
   const int ex = f % a.nex0, ey = f / a.nex0;
@@ -321,6 +355,11 @@ __global__ void __launch_bounds__(256) k_flux_fine(const FluxArgs<Real> a) {
 }
 
 template <typename Real>
+__global__ void __launch_bounds__(256) k_flux_fine(const FluxArgs<Real> a) {
+  flux_fine_block(a, blockIdx.x);
+}
+
+template <typename Real>
 __global__ void __launch_bounds__(256) k_flux_coarse(const FluxArgs<Real> a) {
   constexpr int ML = 64;  // fine Gauss points per coarse element along one axis
   __shared__ Real sT[kWaves][2][ML * 8];
@@ -339,7 +378,10 @@ __global__ void __launch_bounds__(256) k_flux_coarse(const FluxArgs<Real> a) {
     const int ex_qa = a.xl[xo0 + ix];
     const int ex = ex_qa / Nq, qa = ex_qa % Nq;
     Real ta = 0, tb = 0;
+    // unrolled so that the point-list loads of several rows are in flight
+    // together ahead of the loads they address
     if (valid)
+#pragma unroll 4
       for (int iy = 0; iy < nyl; ++iy) {
         const int ey_qb = a.yl[yo0 + iy];
         const int ey = ey_qb / Nq, qb = ey_qb % Nq;
