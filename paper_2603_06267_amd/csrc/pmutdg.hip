@@ -1523,6 +1523,7 @@ void pmdg_destroy(pmdg_solver* s) {
 struct pmdg_batch {
   std::vector<pmdg_solver*> sv;
   int nmax = 1;
+  int nm_max = 1;               // most modes per PMUT over the problems
   size_t lds = 0;
   int n_stiff = 0, n_face = 0, grid_stiff = 1, grid_face = 1;
   char* ws = nullptr;
@@ -1550,7 +1551,7 @@ static pmdg_status batch_enqueue(pmdg_batch* b, hipStream_t st) {
   HIPCHK(launch_stiff_batch((const StiffArgs<float>*)(b->ws + b->off_sargs), (const int2*)(b->ws + b->off_sitems),
                             b->n_stiff, b->nmax, b->grid_stiff, b->lds, st));
   HIPCHK(launch_face_batch((const FaceArgs<float>*)(b->ws + b->off_fargs), (const int2*)(b->ws + b->off_fitems),
-                           b->n_face, b->grid_face, st));
+                           b->n_face, b->grid_face, b->nm_max, st));
   HIPCHK(launch_tick_batch((long* const*)(b->ws + b->off_ctr), (int)b->sv.size(), st));
   return PMDG_OK;
 }
@@ -1571,6 +1572,7 @@ pmdg_status pmdg_batch_create(int n, pmdg_solver* const* solvers, pmdg_batch** o
     if (s->waves != kWaves) { delete b; return fail(PMDG_EINVAL, "batched tiles use 4 waves per workgroup"); }
     b->sv.push_back(s);
     b->nmax = std::max(b->nmax, s->b[0].N);
+    b->nm_max = std::max(b->nm_max, s->Nm);
     b->lds = std::max(b->lds, batch_lds_bytes(s->b[0].N, s->rows));
     b->n_stiff += stiff_args<float>(s, 0).nblocks;
     b->n_face += face_args<float>(s, 0).nblocks;

@@ -60,7 +60,8 @@ __device__ void face_traces(const FaceArgs<Real>& a, int side, int item, int buf
 }
 
 // One workgroup-sized unit b of the face work of one problem.
-template <typename Real>
+// MM bounds the mode loops (a multiple of 4, >= the problem's Nm).
+template <typename Real, int MM>
 __device__ void face_block(const FaceArgs<Real>& a, int b) {
   __shared__ double red[kWaves][kMaxModes];
   __shared__ double qp_s[kMaxModes], qds_s[kMaxModes], qdd_s[kMaxModes];
@@ -107,22 +108,22 @@ __device__ void face_block(const FaceArgs<Real>& a, int b) {
         d2x = d2[0];
         d2y = d2[1];
       }
-      double acc[kMaxModes];
+      double acc[MM];
 #pragma unroll
-      for (int m = 0; m < kMaxModes; ++m) acc[m] = 0.0;
+      for (int m = 0; m < MM; ++m) acc[m] = 0.0;
       const Real* P0 = a.d0.P[buf] + (long)s * a.d0.nnodes;
       bool bad = false;
-      // mode loops run over kMaxModes with clamped, unconditional loads: a
+      // mode loops run over MM with clamped, unconditional loads: a
       // load under a per-mode condition would be waited for one mode at a time
       for (int n = n0 + tid; n < n1; n += 256) {
         const double p = (double)P0[a.pm_node[n]];
         bad |= !__builtin_isfinite(p);
         const double* B = a.pm_B + (long)n * Nm;
-        double bm[kMaxModes];
+        double bm[MM];
 #pragma unroll
-        for (int m = 0; m < kMaxModes; ++m) bm[m] = B[min(m, Nm - 1)];
+        for (int m = 0; m < MM; ++m) bm[m] = B[min(m, Nm - 1)];
 #pragma unroll
-        for (int m = 0; m < kMaxModes; ++m)
+        for (int m = 0; m < MM; ++m)
           if (m < Nm) acc[m] += bm[m] * p;
       }
       if (bad) atomicOr(a.nonfinite, 1);
@@ -131,7 +132,7 @@ __device__ void face_block(const FaceArgs<Real>& a, int b) {
         qds_s[tid] = qd + 0.5 * dt * qdd;
       }
 #pragma unroll
-      for (int m = 0; m < kMaxModes; ++m) {
+      for (int m = 0; m < MM; ++m) {
         if (m < Nm) {
           const double v = wave_sum(acc[m]);
           if (lane == 0) red[wave][m] = v;
@@ -141,12 +142,12 @@ __device__ void face_block(const FaceArgs<Real>& a, int b) {
       if (tid == 0) {
         double phi;
         if (!driven) {
-          double em[kMaxModes];
+          double em[MM];
 #pragma unroll
-          for (int m = 0; m < kMaxModes; ++m) em[m] = a.eta[(long)k * Nm + min(m, Nm - 1)];
+          for (int m = 0; m < MM; ++m) em[m] = a.eta[(long)k * Nm + min(m, Nm - 1)];
           phi = 0.0;
 #pragma unroll
-          for (int m = 0; m < kMaxModes; ++m)
+          for (int m = 0; m < MM; ++m)
             if (m < Nm) phi += em[m] * qp_s[m];
           phi /= a.cap;
         } else {
@@ -170,12 +171,12 @@ __device__ void face_block(const FaceArgs<Real>& a, int b) {
     Real* F = a.force + (long)s * a.d0.plane;  // padded bottom plane
     for (int n = n0 + tid; n < n1; n += 256) {
       const double* B = a.pm_B + (long)n * Nm;
-      double bm[kMaxModes];
+      double bm[MM];
 #pragma unroll
-      for (int m = 0; m < kMaxModes; ++m) bm[m] = B[min(m, Nm - 1)];
+      for (int m = 0; m < MM; ++m) bm[m] = B[min(m, Nm - 1)];
       double f = 0.0;
 #pragma unroll
-      for (int m = 0; m < kMaxModes; ++m)
+      for (int m = 0; m < MM; ++m)
         if (m < Nm) f += qdd_s[m] * bm[m];
       F[a.pm_node[n]] = (Real)(-a.kappa * f);
     }
@@ -204,19 +205,19 @@ __device__ void face_block(const FaceArgs<Real>& a, int b) {
 
 }
 
-template <typename Real>
+template <typename Real, int MM>
 __global__ void __launch_bounds__(256) k_face(const FaceArgs<Real> a) {
-  face_block(a, blockIdx.x);
+  face_block<Real, MM>(a, blockIdx.x);
 }
 
 // Persistent face kernel over the (problem, unit) work list of a batch.
-template <typename Real>
+template <typename Real, int MM>
 __global__ void __launch_bounds__(256) k_face_batch(const FaceArgs<Real>* __restrict__ probs,
                                                     const int2* __restrict__ items, int nitems) {
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int2 w = items[it];
     __syncthreads();
-    face_block(probs[w.x], w.y);
+    face_block<Real, MM>(probs[w.x], w.y);
   }
 }
 
@@ -454,7 +455,12 @@ int stiff2_tile_rows(int N) { return (N >= 1 && N <= 4) ? 16 - 2 * N : 0; }
 
 template <typename Real>
 hipError_t launch_face(const FaceArgs<Real>& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_face<Real>, dim3(a.nblocks), dim3(256), 0, st, a);
+  if (a.Nm <= 4)
+    hipLaunchKernelGGL((k_face<Real, 4>), dim3(a.nblocks), dim3(256), 0, st, a);
+  else if (a.Nm <= 8)
+    hipLaunchKernelGGL((k_face<Real, 8>), dim3(a.nblocks), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_face<Real, kMaxModes>), dim3(a.nblocks), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
@@ -468,10 +474,15 @@ hipError_t launch_flux(const FluxArgs<Real>& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_face_batch(const FaceArgs<float>* probs, const int2* items, int nitems, int grid,
+hipError_t launch_face_batch(const FaceArgs<float>* probs, const int2* items, int nitems, int grid, int nm_max,
                              hipStream_t st) {
   if (nitems == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_face_batch<float>, dim3(grid), dim3(256), 0, st, probs, items, nitems);
+  if (nm_max <= 4)
+    hipLaunchKernelGGL((k_face_batch<float, 4>), dim3(grid), dim3(256), 0, st, probs, items, nitems);
+  else if (nm_max <= 8)
+    hipLaunchKernelGGL((k_face_batch<float, 8>), dim3(grid), dim3(256), 0, st, probs, items, nitems);
+  else
+    hipLaunchKernelGGL((k_face_batch<float, kMaxModes>), dim3(grid), dim3(256), 0, st, probs, items, nitems);
   return hipGetLastError();
 }
 

@@ -41,20 +41,21 @@ __device__ __forceinline__ int xcd_remap(int b, int nblk) {
 // the hardware drops them.  (A global store under a divergent branch makes the
 // compiler's wait counting merge the taken and skipped paths conservatively:
 // a later wait for an earlier prefetch then also waits for loads issued after
-// the store.)  The plane must span fewer than 2^31 bytes.  The stores are
-// non-temporal: nothing reads the new level before the step's face kernel,
-// and keeping it out of the way in L2 leaves room for the halo rows of p
-// that neighbouring tiles re-read.
+// the store.)  The plane must span fewer than 2^31 bytes.  NT selects
+// non-temporal stores, for bricks far larger than L2: nothing reads the new
+// level before the step's face kernel, and keeping it out of the way in L2
+// leaves room for the halo rows of p that neighbouring tiles re-read.  (The
+// batched form, whose meshes are small, keeps plain stores.)
 constexpr unsigned kDropOffset = 0x80000000u;
-constexpr int kStoreNT = 2;  // cache-policy operand: non-temporal
-template <typename Real>
+template <bool NT, typename Real>
 __device__ __forceinline__ void plane_store(Real* base, unsigned plane_bytes, unsigned off_bytes, Real v) {
+  constexpr int cpol = NT ? 2 : 0;  // cache-policy operand: 2 = non-temporal
   const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)plane_bytes, 0x00020000);
   if constexpr (sizeof(Real) == 4) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rs, off_bytes, 0, kStoreNT);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rs, off_bytes, 0, cpol);
   } else {
     typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rs, off_bytes, 0, kStoreNT);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rs, off_bytes, 0, cpol);
   }
 }
 
@@ -96,8 +97,8 @@ constexpr int ct_gcd(int a, int b) { return b == 0 ? a : ct_gcd(b, a % b); }
 // One tile of the stiffness update (tile = linear tile index of the brick
 // and scenario); lds holds stiff_lds_elems<N, RY, WV>() elements.  D is the
 // prefetch distance in planes (the loads for plane k + D are issued while
-// plane k is updated).
-template <typename Real, int N, bool INCR, int RY, int WV, int D = 2>
+// plane k is updated); NTS selects non-temporal stores.
+template <typename Real, int N, bool INCR, int RY, int WV, int D = 2, bool NTS = true>
 __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id, Real* __restrict__ lds) {
   constexpr int TX = 64, TY = WV * RY, W = TX + 2 * N, H = TY + 2 * N, NT = 2 * N, NQ = NT + 1;
   static_assert(D >= 2, "prefetch distance of at least two planes");
@@ -363,11 +364,11 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
         if (INCR) {
           const Real xv = xc[r] + acc;
           pn = p0 + xv;
-          plane_store(X + kp, plane_bytes, soff, xv);
+          plane_store<NTS>(X + kp, plane_bytes, soff, xv);
         } else {
           pn = p0 + (p0 - xc[r]) + acc;
         }
-        plane_store(Pn + kp, plane_bytes, soff, pn);
+        plane_store<NTS>(Pn + kp, plane_bytes, soff, pn);
       }
       // (4) plane k+1 into the other buffer
       if (more) {
