@@ -247,9 +247,16 @@ __device__ __forceinline__ void flux_fine_block(const FluxArgs<Real>& a, int blk
   __shared__ Real sR[kWaves][2][MQ * 8];
   __shared__ Real sC[kWaves][2][MQ * 16];
   __shared__ Real sA[kWaves][2][64];
+  // the interpolation and weight tables shared by every face, staged once
+  __shared__ Real sL[MQ * MQ], sW[MQ * MQ];
+  // per face: coarse element row and coarse basis of each Gauss row
+  __shared__ int sCY[kWaves][MQ];
+  __shared__ Real sY[kWaves][MQ * MQ];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int Nq = a.Nq, N0 = a.N0, N1 = a.N1, n0 = N0 + 1, n1 = N1 + 1;
   const int nfine = a.nex0 * a.ney0;
+  for (int i = threadIdx.x; i < Nq * n0; i += 64 * kWaves) sL[i] = a.Lq[i];
+  for (int i = threadIdx.x; i < Nq * Nq; i += 64 * kWaves) sW[i] = a.wJ[i];
   const int item = blk * kWaves + w;
   const bool valid = item < a.S * nfine;
   const int s = valid ? item / nfine : 0, f = valid ? item - s * nfine : 0;
@@ -257,12 +264,19 @@ __device__ __forceinline__ void flux_fine_block(const FluxArgs<Real>& a, int blk
   const long nf0 = (long)a.nn0x * (a.ney0 * N0 + 1), nf1 = (long)a.nn1x * (a.ney1 * N1 + 1);
   const Real* T0 = a.tr0 + (long)s * nf0 * 2;
   const Real* T1 = a.tr1 + (long)s * nf1 * 2;
-  // coarse node rows touched by this face
+  // coarse node rows touched by this face (one lane per Gauss row, reduced
+  // across the wave)
   int cy_lo = 1 << 30, cy_hi = -1;
-  for (int qb = 0; qb < Nq; ++qb) {
-    const int c = a.ycx[ey * Nq + qb];
-    cy_lo = min(cy_lo, c);
-    cy_hi = max(cy_hi, c);
+  if (lane < Nq) {
+    const int c = a.ycx[ey * Nq + lane];
+    sCY[w][lane] = c;
+    cy_lo = cy_hi = c;
+  }
+  if (lane < Nq * n1) sY[w][lane] = a.yw[(long)(ey * Nq) * n1 + lane];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    cy_lo = min(cy_lo, __shfl_xor(cy_lo, o, 64));
+    cy_hi = max(cy_hi, __shfl_xor(cy_hi, o, 64));
   }
   const int ry0 = N1 * cy_lo, nrow = N1 * (cy_hi - cy_lo) + n1;
   // (1) fine traces into LDS; coarse traces contracted along x
@@ -291,7 +305,7 @@ __device__ __forceinline__ void flux_fine_block(const FluxArgs<Real>& a, int blk
     const int qa = lane % Nq, b = lane / Nq;
     Real rv = 0, rd = 0;
     for (int aa = 0; aa < n0; ++aa) {
-      const Real l = a.Lq[qa * n0 + aa];
+      const Real l = sL[qa * n0 + aa];
       rv += l * sT[w][0][aa + n0 * b];
       rd += l * sT[w][1][aa + n0 * b];
     }
@@ -304,12 +318,12 @@ __device__ __forceinline__ void flux_fine_block(const FluxArgs<Real>& a, int blk
     const int qa = lane % Nq, qb = lane / Nq;
     Real pP = 0, dP = 0, pM = 0, dM = 0;
     for (int b = 0; b < n0; ++b) {
-      const Real l = a.Lq[qb * n0 + b];
+      const Real l = sL[qb * n0 + b];
       pP += l * sR[w][0][qa + Nq * b];
       dP += l * sR[w][1][qa + Nq * b];
     }
-    const int cy = a.ycx[ey * Nq + qb];
-    const Real* wy = a.yw + (long)(ey * Nq + qb) * n1;
+    const int cy = sCY[w][qb];
+    const Real* wy = &sY[w][qb * n1];
     for (int b = 0; b < n1; ++b) {
       const int li = qa + Nq * (N1 * cy + b - ry0);
       pM += wy[b] * sC[w][0][li];
@@ -317,7 +331,7 @@ __device__ __forceinline__ void flux_fine_block(const FluxArgs<Real>& a, int blk
     }
     const Real jump = pP - pM;
     const Real avg = Real(0.5) * (a.cf2 * dP + a.cc2 * dM);
-    const Real wj = a.wJ[qb * Nq + qa];
+    const Real wj = sW[qb * Nq + qa];
     const Real A = wj * (a.gamma * jump - avg), B = Real(-0.5) * wj * jump;
     sA[w][0][lane] = A;
     sA[w][1][lane] = B;
@@ -333,7 +347,7 @@ __device__ __forceinline__ void flux_fine_block(const FluxArgs<Real>& a, int blk
     const int qa = lane % Nq, b = lane / Nq;
     Real ta = 0, tb = 0;
     for (int qb = 0; qb < Nq; ++qb) {
-      const Real l = a.Lq[qb * n0 + b];
+      const Real l = sL[qb * n0 + b];
       ta += l * sA[w][0][qa + Nq * qb];
       tb += l * sA[w][1][qa + Nq * qb];
     }
@@ -345,7 +359,7 @@ __device__ __forceinline__ void flux_fine_block(const FluxArgs<Real>& a, int blk
     const int aa = lane % n0, b = lane / n0;
     Real RA = 0, RB = 0;
     for (int qa = 0; qa < Nq; ++qa) {
-      const Real l = a.Lq[qa * n0 + aa];
+      const Real l = sL[qa * n0 + aa];
       RA += l * sR[w][0][qa + Nq * b];
       RB += l * sR[w][1][qa + Nq * b];
     }
