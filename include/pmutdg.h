@@ -265,6 +265,14 @@ pmdg_status pmdg_mlp_bind(pmdg_mlp* m, void* dev_ptr, size_t bytes, void* stream
  * n_0, identity, amp_col = -1, out_scale = 1. */
 pmdg_status pmdg_mlp_set_io_map(pmdg_mlp* m, int n_u, int ncols, const int* src, const int* op, const float* shift,
                                 const float* scale, int amp_col, float out_scale, void* stream);
+/* Optional second factor per input column (host arrays of ncols = n_0):
+ * column c becomes g(u[src[c]]) * g2(u[src2[c]]) with g2 given by op2,
+ * shift2, scale2 as above; src2[c] = -1 keeps the column a single factor.
+ * pmdg_mlp_set_io_map clears every second factor, so call this after it.
+ * PMDG_EINVAL on a bad index, op or non-finite value; PMDG_ESTATE before
+ * the input map is set. */
+pmdg_status pmdg_mlp_set_io_factors(pmdg_mlp* m, int ncols, const int* src2, const int* op2, const float* shift2,
+                                    const float* scale2, void* stream);
 /* Host parameters, per layer W_l [n_{l+1}][n_l] row-major then b_l; resets Adam. */
 pmdg_status pmdg_mlp_set_params(pmdg_mlp* m, const float* host, void* stream);
 pmdg_status pmdg_mlp_get_params(pmdg_mlp* m, float* host, void* stream);

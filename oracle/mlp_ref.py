@@ -59,22 +59,29 @@ def unflatten(vec, widths):
     return params
 
 
+def _factor(v, op, shift, scale):
+    if op == 0:
+        return (v - shift) * scale
+    if op == 1:
+        return np.cos(scale * v + shift)
+    return np.sin(scale * v + shift)
+
+
 def embed(u, columns=None):
     """Network input x_0 from raw features u [B, n_u]; columns: one (src, op,
     shift, scale) per input, op 0 = (u_src - shift) * scale, 1 = cos(scale
-    u_src + shift), 2 = sin(scale u_src + shift).  None: u itself."""
+    u_src + shift), 2 = sin(scale u_src + shift); or (src, op, shift, scale,
+    src2, op2, shift2, scale2), the product of two such factors (src2 = -1:
+    the first alone).  None: u itself."""
     u = np.asarray(u, dtype=np.float64)
     if columns is None:
         return u.copy()
     cols = []
-    for src, op, shift, scale in columns:
-        v = u[:, src]
-        if op == 0:
-            cols.append((v - shift) * scale)
-        elif op == 1:
-            cols.append(np.cos(scale * v + shift))
-        else:
-            cols.append(np.sin(scale * v + shift))
+    for c in columns:
+        v = _factor(u[:, c[0]], c[1], c[2], c[3])
+        if len(c) > 4 and c[4] >= 0:
+            v = v * _factor(u[:, c[4]], c[5], c[6], c[7])
+        cols.append(v)
     return np.stack(cols, axis=1)
 
 

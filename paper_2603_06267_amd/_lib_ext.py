@@ -20,6 +20,8 @@ SIGS = {
     "pmdg_mlp_bind": [_vp, _vp, ctypes.c_size_t, _vp],
     "pmdg_mlp_set_io_map": [_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                             _fp, _fp, ctypes.c_int, ctypes.c_float, _vp],
+    "pmdg_mlp_set_io_factors": [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                _fp, _fp, _vp],
     "pmdg_mlp_set_params": [_vp, _fp, _vp],
     "pmdg_mlp_get_params": [_vp, _fp, _vp],
     "pmdg_mlp_get_grads": [_vp, _fp, _vp],

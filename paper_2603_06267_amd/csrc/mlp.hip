@@ -227,10 +227,19 @@ __global__ void k_splitk_reduce(const GemmArgs g) {
 
 // One network input column: raw feature src (-1: zero padding) and how it
 // enters (0: (u - shift) * scale, 1: cos(scale u + shift), 2: sin(scale u + shift)).
+// Input column: g(u[src]; op, shift, scale), times a second such factor of
+// u[src2] when src2 >= 0 (op 0: (x - shift) scale, 1: cos(scale x + shift),
+// 2: sin(scale x + shift)).
 struct EmbCol {
   int src, op;
   float shift, scale;
+  int src2, op2;
+  float shift2, scale2;
 };
+
+__device__ __forceinline__ float emb_factor(float x, int op, float shift, float scale) {
+  return op == 0 ? (x - shift) * scale : (op == 1 ? cosf(scale * x + shift) : sinf(scale * x + shift));
+}
 
 // x_0[r][c] = bf16(embed column c of u[row r]), rowscale[r] = u[row r][amp]
 __global__ void k_pack_input(const float* __restrict__ u, const int* __restrict__ idx, int nrows, int B, int nu, int ld,
@@ -243,8 +252,8 @@ __global__ void k_pack_input(const float* __restrict__ u, const int* __restrict_
   const EmbCol e = emb[c];
   float v = 0.f;
   if (e.src >= 0) {
-    const float x = u[src * nu + e.src];
-    v = e.op == 0 ? (x - e.shift) * e.scale : (e.op == 1 ? cosf(e.scale * x + e.shift) : sinf(e.scale * x + e.shift));
+    v = emb_factor(u[src * nu + e.src], e.op, e.shift, e.scale);
+    if (e.src2 >= 0) v *= emb_factor(u[src * nu + e.src2], e.op2, e.shift2, e.scale2);
   }
   X[i] = f2bf(v);
   if (c == 0) rowscale[r] = amp >= 0 ? u[src * nu + amp] : 1.0f;
@@ -608,7 +617,7 @@ pmdg_status pmdg_mlp_create(int nlayers, const int* widths, pmdg_mlp** out) {
   for (int l = 0; l < nlayers; ++l) m->kin[l] = (m->width[l] + 31) / 32 * 32;
   for (int l = 0; l < nlayers; ++l) m->nparams += (long)m->width[l + 1] * (m->width[l] + 1);
   m->n_u = m->width[0];
-  m->emb.assign(m->kin[0], EmbCol{-1, 0, 0.f, 1.f});
+  m->emb.assign(m->kin[0], EmbCol{-1, 0, 0.f, 1.f, -1, 0, 0.f, 1.f});
   for (int c = 0; c < m->width[0]; ++c) m->emb[c].src = c;
   *out = m;
   return PMDG_OK;
@@ -655,17 +664,42 @@ pmdg_status pmdg_mlp_set_io_map(pmdg_mlp* m, int n_u, int ncols, const int* src,
   if (ncols != m->width[0]) return mfail(PMDG_EINVAL, "ncols must equal widths[0] = " + std::to_string(m->width[0]));
   if (!(out_scale > 0.f) || !std::isfinite(out_scale)) return mfail(PMDG_EINVAL, "out_scale must be finite and > 0");
   if (amp_col < -1 || amp_col >= n_u) return mfail(PMDG_EINVAL, "amp_col must be -1 or a feature index");
-  std::vector<EmbCol> emb(m->kin[0], EmbCol{-1, 0, 0.f, 1.f});
+  std::vector<EmbCol> emb(m->kin[0], EmbCol{-1, 0, 0.f, 1.f, -1, 0, 0.f, 1.f});
   for (int c = 0; c < ncols; ++c) {
     if (src[c] < 0 || src[c] >= n_u) return mfail(PMDG_EINVAL, "src must index a raw feature");
     if (op[c] < 0 || op[c] > 2) return mfail(PMDG_EINVAL, "op must be 0 (affine), 1 (cos) or 2 (sin)");
     if (!std::isfinite(shift[c]) || !std::isfinite(scale[c])) return mfail(PMDG_EINVAL, "non-finite input map");
-    emb[c] = EmbCol{src[c], op[c], shift[c], scale[c]};
+    emb[c] = EmbCol{src[c], op[c], shift[c], scale[c], -1, 0, 0.f, 1.f};
   }
   m->emb = emb;
   m->n_u = n_u;
   m->amp_col = amp_col;
   m->out_scale = out_scale;
+  if (m->bound) {
+    hipStream_t st = (hipStream_t)stream;
+    MCHK(hipMemcpyAsync(at<EmbCol>(m, m->oEmb), m->emb.data(), sizeof(EmbCol) * m->emb.size(),
+                        hipMemcpyHostToDevice, st));
+    MCHK(hipStreamSynchronize(st));
+  }
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_mlp_set_io_factors(pmdg_mlp* m, int ncols, const int* src2, const int* op2, const float* shift2,
+                                    const float* scale2, void* stream) {
+  if (!m || !src2 || !op2 || !shift2 || !scale2) return mfail(PMDG_EINVAL, "NULL argument");
+  if (ncols != m->width[0]) return mfail(PMDG_EINVAL, "ncols must equal widths[0] = " + std::to_string(m->width[0]));
+  if ((int)m->emb.size() != m->kin[0]) return mfail(PMDG_ESTATE, "set the input map first");
+  std::vector<EmbCol> emb = m->emb;
+  for (int c = 0; c < ncols; ++c) {
+    if (src2[c] < -1 || src2[c] >= m->n_u) return mfail(PMDG_EINVAL, "src2 must be -1 or index a raw feature");
+    if (op2[c] < 0 || op2[c] > 2) return mfail(PMDG_EINVAL, "op2 must be 0 (affine), 1 (cos) or 2 (sin)");
+    if (!std::isfinite(shift2[c]) || !std::isfinite(scale2[c])) return mfail(PMDG_EINVAL, "non-finite input map");
+    emb[c].src2 = src2[c];
+    emb[c].op2 = op2[c];
+    emb[c].shift2 = shift2[c];
+    emb[c].scale2 = scale2[c];
+  }
+  m->emb = emb;
   if (m->bound) {
     hipStream_t st = (hipStream_t)stream;
     MCHK(hipMemcpyAsync(at<EmbCol>(m, m->oEmb), m->emb.data(), sizeof(EmbCol) * m->emb.size(),

@@ -66,7 +66,9 @@ class MLP:
 
     def set_io_map(self, n_u, columns, out_scale=1.0, amp_col=-1, stream=None):
         """columns: one (src, op, shift, scale) per network input, op 0 affine
-        ((u - shift) * scale), 1 cos(scale u + shift), 2 sin(scale u + shift)."""
+        ((u - shift) * scale), 1 cos(scale u + shift), 2 sin(scale u + shift),
+        or (src, op, shift, scale, src2, op2, shift2, scale2) for the product
+        of two such factors (src2 = -1: the first alone)."""
         cols = list(columns)
         src = np.ascontiguousarray([c[0] for c in cols], dtype=np.int32)
         op = np.ascontiguousarray([c[1] for c in cols], dtype=np.int32)
@@ -77,6 +79,14 @@ class MLP:
                                          sh.ctypes.data_as(fp), sc.ctypes.data_as(fp), int(amp_col),
                                          float(out_scale), _stream_ptr(stream)))
         self.n_u = int(n_u)
+        if any(len(c) > 4 for c in cols):
+            c2 = [tuple(c[4:8]) if len(c) > 4 else (-1, 0, 0.0, 1.0) for c in cols]
+            s2 = np.ascontiguousarray([c[0] for c in c2], dtype=np.int32)
+            o2 = np.ascontiguousarray([c[1] for c in c2], dtype=np.int32)
+            h2 = np.ascontiguousarray([c[2] for c in c2], dtype=np.float32)
+            k2 = np.ascontiguousarray([c[3] for c in c2], dtype=np.float32)
+            check(self.L.pmdg_mlp_set_io_factors(self.h, len(cols), s2.ctypes.data_as(ip), o2.ctypes.data_as(ip),
+                                                 h2.ctypes.data_as(fp), k2.ctypes.data_as(fp), _stream_ptr(stream)))
 
     # ---- compute ----------------------------------------------------------
     def forward(self, u, y=None, idx=None, B=None, stream=None):

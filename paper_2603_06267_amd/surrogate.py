@@ -44,13 +44,17 @@ FREQ_COL = N_PMUT
 T_TRACE_US = 4.42
 
 
-def input_columns(n_fourier=0):
+def input_columns(n_fourier=0, n_product=0):
     """Embedding of the raw features [phase x16, frequency (MHz), amplitude]:
     each phase as (cos, sin) (phases are angles), frequency in [1.5, 3] and
     amplitude in [0.5, 1] mapped affinely onto [-1, 1], and optionally
     n_fourier pairs cos / sin(2 pi tau_j f), tau_j = j T / n_fourier, which give
     the network the oscillation of the traces with frequency at the sampled
-    times."""
+    times.  n_product > 0 adds, for every phase column and j = 1 .. n_product,
+    its products with cos / sin(2 pi tau_j f), tau_j = j T / n_product: the
+    traces are linear in each PMUT's drive (A cos theta_k, A sin theta_k), so
+    these products span their dependence on phase and frequency together,
+    which a network would otherwise have to form from separate columns."""
     cols = []
     for k in range(N_PMUT):
         cols += [(k, 1, 0.0, 1.0), (k, 2, 0.0, 1.0)]
@@ -58,6 +62,11 @@ def input_columns(n_fourier=0):
     for j in range(1, n_fourier + 1):
         w = 2.0 * math.pi * j * T_TRACE_US / n_fourier
         cols += [(FREQ_COL, 1, 0.0, w), (FREQ_COL, 2, 0.0, w)]
+    for k in range(N_PMUT):
+        for op in (1, 2):
+            for j in range(1, n_product + 1):
+                w = 2.0 * math.pi * j * T_TRACE_US / n_product
+                cols += [(k, op, 0.0, 1.0, FREQ_COL, 1, 0.0, w), (k, op, 0.0, 1.0, FREQ_COL, 2, 0.0, w)]
     return cols
 
 
@@ -87,8 +96,9 @@ def solve(F, steps=512, device="cuda", stream=None, max_scenarios=4096):
 
 
 class Surrogate:
-    def __init__(self, n_members=2, max_batch=1024, seed=0, device="cuda", n_fourier=0, hidden=None, n_out=N_OUT):
-        self.columns = input_columns(n_fourier)
+    def __init__(self, n_members=2, max_batch=1024, seed=0, device="cuda", n_fourier=0, hidden=None, n_out=N_OUT,
+                 n_product=0):
+        self.columns = input_columns(n_fourier, n_product)
         self.widths = [len(self.columns)] + list(hidden or HIDDEN) + [n_out]
         self.members = [_mlp.MLP(self.widths, max_batch=max_batch, device=device) for _ in range(n_members)]
         self.max_batch = max_batch

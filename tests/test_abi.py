@@ -133,5 +133,14 @@ def test_mlp_host_checks():
     assert L.pmdg_mlp_bind(h, ctypes.c_void_p(0x100001), sz.value, None) == _lib.PMDG_EINVAL
     assert L.pmdg_mlp_pair_combine(None, x, 8, 32, x, x, None) == _lib.PMDG_EINVAL
     assert L.pmdg_mlp_pair_combine(x, x, 8, 30, x, x, None) == _lib.PMDG_EINVAL
+    # second factors of the input columns (host only while unbound)
+    ints = lambda v: (ctypes.c_int * 18)(*([v] * 18))
+    flts = lambda v: (ctypes.c_float * 18)(*([v] * 18))
+    assert L.pmdg_mlp_set_io_factors(h, 17, ints(-1), ints(0), flts(0), flts(1), None) == _lib.PMDG_EINVAL
+    assert L.pmdg_mlp_set_io_factors(h, 18, ints(18), ints(0), flts(0), flts(1), None) == _lib.PMDG_EINVAL
+    assert L.pmdg_mlp_set_io_factors(h, 18, ints(2), ints(3), flts(0), flts(1), None) == _lib.PMDG_EINVAL
+    assert L.pmdg_mlp_set_io_factors(h, 18, ints(2), ints(1), flts(0), flts(float("inf")), None) == _lib.PMDG_EINVAL
+    assert L.pmdg_mlp_set_io_factors(h, 18, ints(2), ints(1), flts(0), flts(1), None) == _lib.PMDG_OK
+    assert L.pmdg_mlp_set_io_factors(h, 18, None, ints(1), flts(0), flts(1), None) == _lib.PMDG_EINVAL
     L.pmdg_mlp_destroy(h)
     L.pmdg_mlp_destroy(None)

@@ -146,6 +146,35 @@ def test_forward_full_size_inference_batch():
     assert err < 1e-2
 
 
+def test_product_columns_forward():
+    """Two-factor input columns (phase cos / sin times a Fourier column of
+    the frequency, as the surrogate uses) through the network against the
+    oracle's embedding and forward pass."""
+    import math
+    rng = np.random.default_rng(12)
+    F = np.concatenate([rng.uniform(0, 2 * math.pi, (256, 3)), rng.uniform(1.5, 3, (256, 1))],
+                       axis=1).astype(np.float32)
+    cols = []
+    for k in range(3):
+        for op in (1, 2):
+            cols.append((k, op, 0.0, 1.0))
+            for j in (1, 2):
+                cols += [(k, op, 0.0, 1.0, 3, 1, 0.0, 2.1 * j), (k, op, 0.0, 1.0, 3, 2, 0.0, 2.1 * j)]
+    cols.append((3, 0, 2.25, 1 / 0.75))
+    widths = [len(cols), 64, 64]
+    params, _, _ = _twin(widths, 8, 13)
+    m = _model(widths, 256)
+    m.set_params(R.flatten(params))
+    m.set_io_map(4, cols)
+    y = m.forward(_dev(F)).cpu().numpy()
+    x = R.embed(F.astype(np.float64), [tuple(float(np.float32(v)) if i in (2, 3, 6, 7) else v for i, v in enumerate(c))
+                                       for c in cols])
+    ref, _ = R.forward(params, x)
+    err = rel_l2(y, ref)
+    _say(f"  product columns: rel L2 {err:.2e}")
+    assert err < 1e-2
+
+
 def test_amplitude_factor_in_training_loss():
     """With amp_col set, the loss compares y with t / (out_scale a): targets
     that are exactly out_scale * a * y(params) give zero loss and gradient."""

@@ -91,6 +91,26 @@ def test_embedding():
     assert np.array_equal(M.embed(u), u)
 
 
+def test_embedding_products():
+    """Two-factor columns against the angle-addition identities
+    cos a cos b - sin a sin b = cos(a + b), sin a cos b + cos a sin b =
+    sin(a + b), the Pythagorean identity for a factor times itself, and an
+    affine factor times a cosine; src2 = -1 leaves a single factor."""
+    rng = np.random.default_rng(6)
+    u = np.concatenate([rng.uniform(0, 2 * math.pi, (7, 2)), rng.uniform(1.5, 3, (7, 1))], axis=1)
+    cols = [(0, 1, 0.0, 1.0, 1, 1, 0.0, 1.0), (0, 2, 0.0, 1.0, 1, 2, 0.0, 1.0),
+            (0, 2, 0.0, 1.0, 1, 1, 0.0, 1.0), (0, 1, 0.0, 1.0, 1, 2, 0.0, 1.0),
+            (0, 1, 0.0, 1.0, 0, 1, 0.0, 1.0), (0, 2, 0.0, 1.0, 0, 2, 0.0, 1.0),
+            (2, 0, 2.25, 1 / 0.75, 0, 1, 0.3, 2.0), (2, 0, 1.0, 2.0, -1, 0, 0.0, 1.0)]
+    x = M.embed(u, cols)
+    a, b, f = u[:, 0], u[:, 1], u[:, 2]
+    assert np.allclose(x[:, 0] - x[:, 1], np.cos(a + b), atol=1e-14)
+    assert np.allclose(x[:, 2] + x[:, 3], np.sin(a + b), atol=1e-14)
+    assert np.allclose(x[:, 4] + x[:, 5], 1.0, atol=1e-14)
+    assert np.allclose(x[:, 6], (f - 2.25) / 0.75 * np.cos(2.0 * a + 0.3), atol=1e-14)
+    assert np.allclose(x[:, 7], (f - 1.0) * 2.0, atol=0)
+
+
 def test_adam_constant_gradient_closed_form():
     """With a constant gradient g the bias-corrected moments are exactly g and
     g^2 at every step, so each step moves by -lr g / (|g| + eps)."""
