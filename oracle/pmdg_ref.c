@@ -156,6 +156,7 @@ typedef struct {
   int literal;
   double sample_gain; /* 1 normally; 0 removes the sampling term (test hook) */
   double *mass;
+  double *cabs;      /* absorbing-boundary matrix C (diagonal), or NULL */
   double *p, *pd, *pdd;
   /* interface quadrature-point list (fine-face points mapped to coarse side) */
   int nq;
@@ -224,6 +225,42 @@ static void build_mass(rsolver *s) {
               for (int a = 0; a <= N; ++a)
                 s->mass[nidx(d, N * ex + a, N * ey + b, N * ez + c)] += d->wg[a] * d->wg[b] * d->wg[c] * J;
   }
+}
+
+/* First-order absorbing boundary (Sec. 2 and 3.1: the term int c pdot v ds
+ * on absorbing faces, in the acoustic solve as C pdot*): C_ii = sum over the
+ * element faces on an absorbing face of domain dd that contain i of
+ * c w_a w_b |J_f|, GLL collocation on the face, |J_f| the face's area / 4.
+ * faces: bit 2a + 0 for the face at the low end of axis a, 2a + 1 for the
+ * high end.  Calls accumulate (one per domain). */
+void pmdg_ref_set_absorbing(void *h, int dd, int faces) {
+  rsolver *s = (rsolver *)h;
+  if (!s->cabs) s->cabs = (double *)calloc(s->ntot, sizeof(double));
+  rdom *d = &s->d[dd];
+  int N = d->N;
+  for (int ax = 0; ax < 3; ++ax)
+    for (int side = 0; side < 2; ++side) {
+      if (!(faces & (1 << (2 * ax + side)))) continue;
+      int t1 = (ax + 1) % 3, t2 = (ax + 2) % 3;
+      double Jf = d->h[t1] * d->h[t2] / 4.0;
+      int fixed = side ? d->nn[ax] - 1 : 0;
+      for (int e2 = 0; e2 < d->ne[t2]; ++e2)
+        for (int e1 = 0; e1 < d->ne[t1]; ++e1)
+          for (int b = 0; b <= N; ++b)
+            for (int a = 0; a <= N; ++a) {
+              int g[3];
+              g[ax] = fixed;
+              g[t1] = N * e1 + a;
+              g[t2] = N * e2 + b;
+              s->cabs[nidx(d, g[0], g[1], g[2])] += d->c * d->wg[a] * d->wg[b] * Jf;
+            }
+    }
+}
+
+/* Copies C (zeros without absorbing faces) into out [ntot]. */
+void pmdg_ref_absorbing(void *h, double *out) {
+  rsolver *s = (rsolver *)h;
+  for (long i = 0; i < s->ntot; ++i) out[i] = s->cabs ? s->cabs[i] : 0.0;
 }
 
 /* ------------------------------------------------------------------ */
@@ -450,7 +487,7 @@ void pmdg_ref_destroy(void *h) {
   rsolver *s = (rsolver *)h;
   if (!s) return;
   free_pmuts(s);
-  free(s->mass); free(s->p); free(s->pd); free(s->pdd);
+  free(s->mass); free(s->cabs); free(s->p); free(s->pd); free(s->pdd);
   free(s->q_ce); free(s->q_xi); free(s->rcv);
   free(s);
 }
@@ -793,7 +830,8 @@ void pmdg_ref_step(void *h, int nsteps, double *traces) {
       s->pd[i] += 0.5 * dt * s->pdd[i];
     }
     if (!s->literal) pmut_block(s, s->p, tn1);
-    /* acoustic solve: pdd = M^{-1} (f(qdd) - K p); no absorbing term */
+    /* acoustic solve: pdd = M^{-1} (f(qdd) - K p - C pdot*), pdot* the
+     * predicted velocity (C = 0 without absorbing faces) */
     memset(f, 0, sizeof(double) * n);
     for (int k = 0; k < s->Np; ++k)
       for (int m = 0; m < s->Nm; ++m) {
@@ -803,7 +841,8 @@ void pmdg_ref_step(void *h, int nsteps, double *traces) {
       }
     pmdg_ref_apply_K(h, s->p, Kp, 3);
     for (long i = 0; i < n; ++i) {
-      s->pdd[i] = (f[i] - Kp[i]) / s->mass[i];
+      double damp = s->cabs ? s->cabs[i] * s->pd[i] : 0.0;
+      s->pdd[i] = (f[i] - Kp[i] - damp) / s->mass[i];
       s->pd[i] += 0.5 * dt * s->pdd[i];
     }
     s->nstep += 1;

@@ -78,6 +78,8 @@ def lib():
         L.pmdg_ref_lagrange.argtypes = [ctypes.c_int, _dp, ctypes.c_double, _dp, _dp]
         L.pmdg_ref_element_apply.argtypes = [ctypes.c_int, _dp, ctypes.c_double, _dp, _dp]
         L.pmdg_ref_num_threads.restype = ctypes.c_int
+        L.pmdg_ref_set_absorbing.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+        L.pmdg_ref_absorbing.argtypes = [vp, _dp]
         _lib = L
     return _lib
 
@@ -174,6 +176,17 @@ class RefSolver:
         x = np.zeros((self.n, 3))
         self.L.pmdg_ref_coords(self.h, _d(x))
         return x
+
+    def set_absorbing(self, dom, faces):
+        """First-order absorbing condition on the outer faces of domain dom
+        given by the bitmask faces (bit 2a: low end of axis a, 2a + 1: high
+        end)."""
+        self.L.pmdg_ref_set_absorbing(self.h, int(dom), int(faces))
+
+    def absorbing(self):
+        out = np.zeros(self.n)
+        self.L.pmdg_ref_absorbing(self.h, _d(out))
+        return out
 
     def mass(self):
         m = np.zeros(self.n)
@@ -286,6 +299,9 @@ def from_workload(wl, scenario=0, shape_fn=None):
     shape_fn(k, xyz) -> [Nm x n] mode-shape samples at the given face nodes
     (the workload's own mode-shape generator)."""
     s = RefSolver(wl["domains"], alpha=wl.get("alpha", 2.0), cfl=wl.get("cfl", 0.3))
+    for d, dom in enumerate(wl["domains"]):
+        if dom.get("absorbing", 0):
+            s.set_absorbing(d, dom["absorbing"])
     pm = wl.get("pmuts")
     if pm is not None and len(pm["radius"]):
         s.set_pmuts(pm["centers"], pm["radius"], pm["omega"], pm["zeta"], pm["eta"])
