@@ -228,7 +228,7 @@ static void build_mass(rsolver *s) {
 }
 
 /* First-order absorbing boundary (Sec. 2 and 3.1: the term int c pdot v ds
- * on absorbing faces, in the acoustic solve as C pdot*): C_ii = sum over the
+ * on absorbing faces, the damping matrix C of the acoustic solve): C_ii = sum over the
  * element faces on an absorbing face of domain dd that contain i of
  * c w_a w_b |J_f|, GLL collocation on the face, |J_f| the face's area / 4.
  * faces: bit 2a + 0 for the face at the low end of axis a, 2a + 1 for the
@@ -830,8 +830,13 @@ void pmdg_ref_step(void *h, int nsteps, double *traces) {
       s->pd[i] += 0.5 * dt * s->pdd[i];
     }
     if (!s->literal) pmut_block(s, s->p, tn1);
-    /* acoustic solve: pdd = M^{-1} (f(qdd) - K p - C pdot*), pdot* the
-     * predicted velocity (C = 0 without absorbing faces) */
+    /* acoustic solve: M pdd + C (pdot* + dt/2 pdd) = f(qdd) - K p, i.e. the
+     * damping acts on the corrected velocity of the gamma = 1/2 Newmark
+     * scheme: pdd = (f - K p - C pdot*) / (M + dt/2 C), with pdot* the
+     * predicted velocity (C = 0 without absorbing faces).  The printed
+     * solve takes C pdot* alone, which is stable only while
+     * dt (M^{-1} C)_ii <= 2; GLL end weights exceed that at edges and
+     * corners of absorbing faces at the configurations' CFL number. */
     memset(f, 0, sizeof(double) * n);
     for (int k = 0; k < s->Np; ++k)
       for (int m = 0; m < s->Nm; ++m) {
@@ -841,8 +846,8 @@ void pmdg_ref_step(void *h, int nsteps, double *traces) {
       }
     pmdg_ref_apply_K(h, s->p, Kp, 3);
     for (long i = 0; i < n; ++i) {
-      double damp = s->cabs ? s->cabs[i] * s->pd[i] : 0.0;
-      s->pdd[i] = (f[i] - Kp[i] - damp) / s->mass[i];
+      double ci = s->cabs ? s->cabs[i] : 0.0;
+      s->pdd[i] = (f[i] - Kp[i] - ci * s->pd[i]) / (s->mass[i] + 0.5 * dt * ci);
       s->pd[i] += 0.5 * dt * s->pdd[i];
     }
     s->nstep += 1;
