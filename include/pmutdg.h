@@ -111,6 +111,16 @@ pmdg_status pmdg_set_drive(pmdg_solver* h, const double* amp, const double* phas
  * (1/cap) sum_m eta q.  Default t_switch = +infinity (TX only). */
 pmdg_status pmdg_set_rx(pmdg_solver* h, double t_switch, double cap);
 
+/* First-order absorbing condition (the surface term int c pdot v ds of the
+ * weak form, Sec. 2 and 3.1; C pdot* in the acoustic solve of Algorithm 1)
+ * on the outer faces of brick dom given by the 6-bit mask faces: bit 2a for
+ * the face at the low end of axis a, bit 2a+1 for the high end.  The
+ * interface faces of two coupled bricks (primary top, secondary bottom)
+ * cannot be absorbing.  Before bind (PMDG_ESTATE after); PMDG_EINVAL on a
+ * bad domain or mask.  Bricks with absorbing faces keep single-step passes
+ * (PMDG_OPT_TIME_BLOCK has no effect on them). */
+pmdg_status pmdg_set_absorbing(pmdg_solver* h, int dom, int faces);
+
 /* Receiver points xyz[3*R]; each is located in the lowest-index element
  * containing it (primary first) and sampled by tensor Lagrange
  * interpolation, accumulated in FP64.  A point outside both bricks gives

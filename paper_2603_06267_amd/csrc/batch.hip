@@ -34,8 +34,8 @@ __global__ void __launch_bounds__(256) k_stiff_batch(const StiffArgs<float>* __r
 
 size_t batch_lds_bytes(int N, int rows) {
   switch (rows) {
-    case 1: return sizeof(float) * (2 * (64 + 2 * N) * (kWaves + 2 * N) + (N + 2) * (2 * N + 1));
-    case 2: return sizeof(float) * (2 * (64 + 2 * N) * (2 * kWaves + 2 * N) + (N + 2) * (2 * N + 1));
+    case 1: return sizeof(float) * stiff_lds_elems_rt(N, 1, kWaves);
+    case 2: return sizeof(float) * stiff_lds_elems_rt(N, 2, kWaves);
     default: return 0;
   }
 }

@@ -152,6 +152,7 @@ struct Brick {
   double lam1[3];               // largest eigenvalue of M_d^{-1} K_d
   std::vector<double> ctap[3];  // [N+2][2N] rows by node class (see StiffArgs)
   std::vector<double> cmin[3];  // [N+2]
+  int absorbing = 0;            // outer faces with the first-order absorbing condition (bit 2a / 2a+1: low / high end of axis a)
   double coord(int axis, int i) const {
     const int e = i / N, a = i % N;
     return x0[axis] + h[axis] * (e + 0.5 * ((double)rule.x[a] + 1.0));
@@ -460,6 +461,7 @@ static size_t layout(pmdg_solver* s) {
     }
     add(p + "taps", rb * 3 * (B.N + 3) * 2 * B.N);
     add(p + "mins", rb * 3 * (B.N + 3));
+    add(p + "absg", rb * 3 * (B.N + 3));
   }
   if (s->Np > 0) {
     add("force", rb * S * s->b[0].pplane);
@@ -587,6 +589,7 @@ static StiffArgs<Real> stiff_args(pmdg_solver* s, int d) {
     const std::string p = "d" + std::to_string(d) + ".";
     a.taps = dptr<Real>(s, p + "taps");
     a.mins = dptr<Real>(s, p + "mins");
+    a.absg = dptr<Real>(s, p + "absg");
   }
   const Brick& B = s->b[d];
   a.rows = (d == 1 && s->rows1 > 0) ? s->rows1 : s->rows;
@@ -822,7 +825,7 @@ static void completion_ranges(const pmdg_solver* s, int d, int r[4]) {
 
 // brick d advances two steps per stiffness pass
 static bool two_step(const pmdg_solver* s, int d) {
-  if (s->prec != 32) return false;
+  if (s->prec != 32 || s->b[d].absorbing) return false;
   const int tb = (d == 1 && s->tblock1 > 0) ? s->tblock1 : s->tblock;
   return tb == 2 && stiff2_tile_rows(s->b[d].N) > 0;
 }
@@ -930,15 +933,24 @@ static pmdg_status bind_tables(pmdg_solver* s, hipStream_t st) {
     const std::string p = "d" + std::to_string(d) + ".";
     const Brick& B = s->b[d];
     const int NT = 2 * B.N, NC = B.N + 3;
-    std::vector<double> taps((size_t)3 * NC * NT, 0.0), mins((size_t)3 * NC, 0.0);
+    std::vector<double> taps((size_t)3 * NC * NT, 0.0), mins((size_t)3 * NC, 0.0), absg((size_t)3 * NC, 0.0);
     const double sc = -s->dt * s->dt * B.c * B.c;
     for (int ax = 0; ax < 3; ++ax)
       for (int cls = 0; cls < B.N + 2; ++cls) {
         for (int t = 0; t < NT; ++t) taps[((size_t)ax * NC + cls) * NT + t] = sc * B.ctap[ax][(size_t)cls * NT + t];
         mins[(size_t)ax * NC + cls] = B.cmin[ax][cls];
       }
+    // first-order absorbing faces: the lumped boundary matrix of a face node
+    // is c times the node's face weight, i.e. the 3D lumped mass divided by
+    // the 1D mass m_d of the end node along the face normal, so dt M^{-1} C
+    // contributes dt c / m_d per absorbing face through the node
+    for (int ax = 0; ax < 3; ++ax) {
+      if (B.absorbing & (1 << (2 * ax))) absg[(size_t)ax * NC + B.N] = s->dt * B.c * B.cmin[ax][B.N];
+      if (B.absorbing & (1 << (2 * ax + 1))) absg[(size_t)ax * NC + B.N + 1] = s->dt * B.c * B.cmin[ax][B.N + 1];
+    }
     if ((r = upload_real<Real>(s, p + "taps", taps, st))) return r;
     if ((r = upload_real<Real>(s, p + "mins", mins, st))) return r;
+    if ((r = upload_real<Real>(s, p + "absg", absg, st))) return r;
   }
   if (s->ndom > 1) {
     if ((r = upload_real<Real>(s, "Lq", s->Lq, st))) return r;
@@ -1214,6 +1226,17 @@ pmdg_status pmdg_set_rx(pmdg_solver* s, double t_switch, double cap) {
   s->t_switch = t_switch;
   s->rx_cap = cap;
   drop_graphs(s);
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_set_absorbing(pmdg_solver* s, int dom, int faces) {
+  if (!s) return fail(PMDG_EINVAL, "NULL solver");
+  if (s->bound) return fail(PMDG_ESTATE, "set_absorbing must precede bind");
+  if (dom < 0 || dom >= s->ndom) return fail(PMDG_EINVAL, "no such domain");
+  if (faces < 0 || faces > 63) return fail(PMDG_EINVAL, "faces is a mask of 6 bits");
+  if (s->ndom > 1 && (faces & (dom == 0 ? 32 : 16)))
+    return fail(PMDG_EINVAL, "the interface face of a coupled brick cannot be absorbing");
+  s->b[dom].absorbing = faces;
   return PMDG_OK;
 }
 

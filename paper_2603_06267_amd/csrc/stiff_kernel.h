@@ -86,10 +86,15 @@ __device__ __forceinline__ int node_class(int i, int n) {
 }
 
 // LDS (in Real elements) of one stiffness workgroup: two plane buffers and
-// the z operator rows
+// the z rows by node class (2N taps, inverse mass, absorbing coefficient)
 template <int N, int RY, int WV>
 __host__ __device__ constexpr int stiff_lds_elems() {
-  return 2 * (64 + 2 * N) * (WV * RY + 2 * N) + (N + 2) * (2 * N + 1);
+  return 2 * (64 + 2 * N) * (WV * RY + 2 * N) + (N + 2) * (2 * N + 2);
+}
+
+// the same count for run-time arguments
+inline int stiff_lds_elems_rt(int N, int RY, int WV) {
+  return 2 * (64 + 2 * N) * (WV * RY + 2 * N) + (N + 2) * (2 * N + 2);
 }
 
 constexpr int ct_gcd(int a, int b) { return b == 0 ? a : ct_gcd(b, a % b); }
@@ -144,10 +149,19 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
 #pragma unroll
   for (int i = 0; i < NT; ++i) tx[i] = TP[cxl * NT + i];
   const Real mx = MI[cxl];
+  // absorbing faces: g = dt (M^{-1} C)_ii = gx + gy + gz, dt c / m_d of the
+  // end node of each absorbing face through the node (zero elsewhere).  The
+  // solve (M + dt/2 C) pdd = f - K p - C pdot* with pdot* = (p^n - p^{n-1})
+  // / dt turns the update into (acc - g (p^n - p^{n-1})) / (1 + g/2): 1 / (1
+  // + g/2) is prepared per row for the three z classes (interior, first,
+  // last plane); it is exactly 1 where no face absorbs.
+  const Real* __restrict__ AG = a.absg;
+  const Real gx = AG[cxl];
+  const Real gzl = AG[2 * NC + N], gzh = AG[2 * NC + N + 1];
   int cyr[RY];
   bool in[RY];
   unsigned roff[RY];
-  Real ty[RY][NT], my[RY];
+  Real ty[RY][NT], my[RY], gxy[RY], gi0[RY], gil[RY], gih[RY];
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
     const int y = ybase + r;
@@ -157,12 +171,16 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
 #pragma unroll
     for (int i = 0; i < NT; ++i) ty[r][i] = TP[(NC + cyr[r]) * NT + i];
     my[r] = MI[NC + cyr[r]];
+    gxy[r] = gx + AG[NC + cyr[r]];
+    gi0[r] = Real(1) / (Real(1) + Real(0.5) * gxy[r]);
+    gil[r] = Real(1) / (Real(1) + Real(0.5) * (gxy[r] + gzl));
+    gih[r] = Real(1) / (Real(1) + Real(0.5) * (gxy[r] + gzh));
   }
   // z operator rows by class, staged in LDS (read with uniform addresses)
   Real* ztab = lds + 2 * H * W;
-  for (int i = tid; i < (N + 2) * (NT + 1); i += 64 * WV) {
-    const int cls = i / (NT + 1), j = i % (NT + 1);
-    ztab[i] = j < NT ? TP[(2 * NC + cls) * NT + j] : MI[2 * NC + cls];
+  for (int i = tid; i < (N + 2) * (NT + 2); i += 64 * WV) {
+    const int cls = i / (NT + 2), j = i % (NT + 2);
+    ztab[i] = j < NT ? TP[(2 * NC + cls) * NT + j] : (j == NT ? MI[2 * NC + cls] : AG[2 * NC + cls]);
   }
   // x-halo slots of this thread: (row, column) pairs of the 2N x TY halo
   unsigned xh_off[NXH];
@@ -315,7 +333,7 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
       // every LDS operand of the plane is read up front, so that the reads
       // overlap one another rather than each being waited for at its use
       const Real* T = tile[b];
-      Real col[RY + NT], xl[RY][NT], tz[NT + 1];
+      Real col[RY + NT], xl[RY][NT], tz[NT + 2];
 #pragma unroll
       for (int j = 0; j < RY + NT; ++j) col[j] = T[(wave * RY + j) * W + N + lane];
 #pragma unroll
@@ -329,7 +347,7 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
       }
       const int cz = node_class<N>(k, nz);
 #pragma unroll
-      for (int i = 0; i <= NT; ++i) tz[i] = ztab[cz * (NT + 1) + i];
+      for (int i = 0; i < NT + 2; ++i) tz[i] = ztab[cz * (NT + 2) + i];
       __builtin_amdgcn_sched_barrier(0);
       const Real mz = tz[NT];
       const bool in_layer = (k >= lay0 && k <= lay1);
@@ -357,6 +375,10 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
           if (a.iface_side > 0) { if (cl == N) rif += RA[r]; }
           else { if (cl == 0) rif -= RA[r]; }
           acc -= a.dt2 * minv * rif;
+        }
+        {
+          const Real gi = cz == N ? gil[r] : (cz == N + 1 ? gih[r] : gi0[r]);
+          acc = (acc - (gxy[r] + tz[NT + 1]) * (INCR ? xc[r] : p0 - xc[r])) * gi;
         }
         const unsigned soff = in[r] ? roff[r] * (unsigned)sizeof(Real) : kDropOffset;
         const long kp = (long)k * plane;

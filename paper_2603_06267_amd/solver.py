@@ -126,6 +126,11 @@ class Solver:
     def set_rx(self, t_switch, cap):
         check(self.L.pmdg_set_rx(self.h, float(t_switch), float(cap)))
 
+    def set_absorbing(self, dom, faces):
+        """First-order absorbing condition on the outer faces of brick dom
+        (6-bit mask: bit 2a low end, 2a + 1 high end of axis a); before bind."""
+        check(self.L.pmdg_set_absorbing(self.h, int(dom), int(faces)))
+
     def set_receivers(self, xyz):
         xyz = _f64(xyz).reshape(-1, 3)
         self.R = xyz.shape[0]
@@ -202,6 +207,9 @@ def from_workload(wl, precision=32, n_steps=None, scenarios=None, shape_fn=None,
     steps = n_steps if n_steps is not None else wl["steps"]
     s = Solver(wl["domains"], cfl=wl.get("cfl", 0.3), alpha=wl.get("alpha", 2.0), precision=precision,
                n_scenarios=S, trace_capacity=max(steps, 1), device=device)
+    for d, dom in enumerate(wl["domains"]):
+        if dom.get("absorbing", 0):
+            s.set_absorbing(d, dom["absorbing"])
     pm = wl.get("pmuts")
     if pm is not None and len(pm["radius"]):
         s.set_pmuts(pm["centers"], pm["radius"], pm["omega"], pm["zeta"], pm["eta"])

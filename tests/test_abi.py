@@ -74,6 +74,15 @@ def test_setup_errors_and_state_errors():
     assert _err(s.set_pmut_shape, 0, np.full(n, 1e3)) == _lib.PMDG_EUNSTABLE
     assert _err(s.step, 1, 0) == _lib.PMDG_ESTATE
     assert _err(s.set_option, 2, 3) == _lib.PMDG_EINVAL
+    assert _err(s.set_absorbing, 1, 1) == _lib.PMDG_EINVAL      # one brick only
+    assert _err(s.set_absorbing, 0, 64) == _lib.PMDG_EINVAL
+    assert _err(s.set_absorbing, 0, -1) == _lib.PMDG_EINVAL
+    s.set_absorbing(0, 0b101111)
+    two = solver.Solver(W.config2()["domains"], trace_capacity=10)
+    assert _err(two.set_absorbing, 0, 1 << 5) == _lib.PMDG_EINVAL  # primary top: the interface
+    assert _err(two.set_absorbing, 1, 1 << 4) == _lib.PMDG_EINVAL  # secondary bottom: the interface
+    two.set_absorbing(0, 0b011111)
+    two.set_absorbing(1, 0b101111)
     assert _err(s.set_option, _lib.OPT_PREFETCH, 1) == _lib.PMDG_EINVAL
     assert _err(s.set_option, _lib.OPT_OVERLAP, 3) == _lib.PMDG_EINVAL
     assert _err(s.set_option, _lib.OPT_PREFETCH, 5) == _lib.PMDG_EINVAL

@@ -47,6 +47,26 @@ def test_batch_vs_oracle_highest_order_mesh():
         assert err <= 1e-5, (i, sc, err)
 
 
+def test_batch_with_absorbing_faces():
+    """Meshes with first-order absorbing faces in a batch: bitwise the
+    individual solvers, and the oracle to 1e-5."""
+    steps = 120
+    wls = _workloads(steps, nscen=4, mesh_ids=(2, 9))
+    wls[1] = dict(wls[1], domains=[dict(wls[1]["domains"][0], absorbing=0b111111)])
+    wls[2] = dict(wls[2], domains=[dict(wls[2]["domains"][0], absorbing=0b100011)])
+    sfs = [W.shape_fn(w) for w in wls]
+    b = B.build_batch(wls, shape_fns=sfs, n_steps=steps)
+    b.step(steps)
+    for wl, sf, sb in zip(wls, sfs, b.solvers):
+        s1 = solver.from_workload(wl, precision=32, n_steps=steps, shape_fn=sf)
+        s1.step(steps)
+        np.testing.assert_array_equal(sb.read_traces(), s1.read_traces())
+    o = ref.from_workload(wls[1], scenario=0, shape_fn=sfs[1])
+    to = o.step(steps)
+    tg = b.solvers[1].read_traces()[0]
+    assert np.linalg.norm(tg - to) / np.linalg.norm(to) <= 1e-5
+
+
 def test_tuner_choice_valid_and_cached(tmp_path):
     t = B.TileTuner(path=str(tmp_path / "tiles.json"), candidates=[(1, 9), (2, 17)], steps=3)
     dom = W.config4()["meshes"][6]["domains"]

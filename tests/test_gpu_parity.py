@@ -76,6 +76,35 @@ def test_config2_two_domain_array(precision):
     assert err <= TOL[precision]
 
 
+@pytest.mark.parametrize("precision", [32, 64])
+def test_absorbing_faces_cube(precision):
+    """First-order absorbing condition on every face of the config-1 cube
+    but the PMUT face, 400 steps (the wave has crossed the cube twice):
+    traces against the oracle; it cannot be switched on after bind."""
+    wl = W.config1()
+    wl = dict(wl, domains=[dict(wl["domains"][0], absorbing=0b101111)], steps=400)
+    _say(f"absorbing cube precision={precision}")
+    tg, to, g, o = run_pair(wl, precision)
+    err = rel_l2(tg, to)
+    _say(f"  rel L2 {err:.3e}")
+    assert err <= TOL[precision]
+    with pytest.raises(Exception):
+        g.set_absorbing(0, 1)
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_absorbing_faces_two_domain(precision):
+    """Absorbing side walls on both bricks and an absorbing top on the
+    secondary, non-nested 4:3 interface, 400 steps, against the oracle."""
+    wl = W.small_two_domain(False, steps=400)
+    prim, sec = wl["domains"]
+    wl = dict(wl, domains=[dict(prim, absorbing=0b001111), dict(sec, absorbing=0b101111)])
+    tg, to, g, o = run_pair(wl, precision)
+    err = rel_l2(tg, to)
+    _say(f"  absorbing two-domain precision={precision}: rel L2 {err:.3e}")
+    assert err <= TOL[precision]
+
+
 def test_graph_replay_equals_direct_launches():
     wl = W.small_two_domain(True, steps=150)
     sf = W.shape_fn(wl)
