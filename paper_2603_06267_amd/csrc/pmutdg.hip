@@ -590,6 +590,7 @@ static StiffArgs<Real> stiff_args(pmdg_solver* s, int d) {
     a.taps = dptr<Real>(s, p + "taps");
     a.mins = dptr<Real>(s, p + "mins");
     a.absg = dptr<Real>(s, p + "absg");
+    a.absorb = s->b[d].absorbing != 0;
   }
   const Brick& B = s->b[d];
   a.rows = (d == 1 && s->rows1 > 0) ? s->rows1 : s->rows;

@@ -58,6 +58,7 @@ struct StiffArgs {
   const Real* taps;         // [3][N+3][2N]: -dt^2 c^2 (M_d^{-1} K_d) off-centre entries
   const Real* mins;         // [3][N+3]: inverse assembled 1D lumped mass
   const Real* absg;         // [3][N+3]: dt c / m_d on the end classes of absorbing faces, else 0
+  int absorb;               // the brick has absorbing faces (absg not all zero)
   // tiling
   int nbx, nby, nbz, zchunk, rows, waves;
   int depth;                // prefetch distance in planes (2, or 3 / 4 where built)

@@ -152,16 +152,15 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
   // absorbing faces: g = dt (M^{-1} C)_ii = gx + gy + gz, dt c / m_d of the
   // end node of each absorbing face through the node (zero elsewhere).  The
   // solve (M + dt/2 C) pdd = f - K p - C pdot* with pdot* = (p^n - p^{n-1})
-  // / dt turns the update into (acc - g (p^n - p^{n-1})) / (1 + g/2): 1 / (1
-  // + g/2) is prepared per row for the three z classes (interior, first,
-  // last plane); it is exactly 1 where no face absorbs.
+  // / dt turns the update into (acc - g (p^n - p^{n-1})) / (1 + g/2), which
+  // is acc itself wherever g = 0; bricks without absorbing faces skip it.
+  const bool absorb = a.absorb;
   const Real* __restrict__ AG = a.absg;
   const Real gx = AG[cxl];
-  const Real gzl = AG[2 * NC + N], gzh = AG[2 * NC + N + 1];
   int cyr[RY];
   bool in[RY];
   unsigned roff[RY];
-  Real ty[RY][NT], my[RY], gxy[RY], gi0[RY], gil[RY], gih[RY];
+  Real ty[RY][NT], my[RY], gxy[RY];
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
     const int y = ybase + r;
@@ -172,9 +171,6 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
     for (int i = 0; i < NT; ++i) ty[r][i] = TP[(NC + cyr[r]) * NT + i];
     my[r] = MI[NC + cyr[r]];
     gxy[r] = gx + AG[NC + cyr[r]];
-    gi0[r] = Real(1) / (Real(1) + Real(0.5) * gxy[r]);
-    gil[r] = Real(1) / (Real(1) + Real(0.5) * (gxy[r] + gzl));
-    gih[r] = Real(1) / (Real(1) + Real(0.5) * (gxy[r] + gzh));
   }
   // z operator rows by class, staged in LDS (read with uniform addresses)
   Real* ztab = lds + 2 * H * W;
@@ -376,9 +372,9 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
           else { if (cl == 0) rif -= RA[r]; }
           acc -= a.dt2 * minv * rif;
         }
-        {
-          const Real gi = cz == N ? gil[r] : (cz == N + 1 ? gih[r] : gi0[r]);
-          acc = (acc - (gxy[r] + tz[NT + 1]) * (INCR ? xc[r] : p0 - xc[r])) * gi;
+        if (absorb) {
+          const Real g = gxy[r] + tz[NT + 1];
+          acc = (acc - g * (INCR ? xc[r] : p0 - xc[r])) / (Real(1) + Real(0.5) * g);
         }
         const unsigned soff = in[r] ? roff[r] * (unsigned)sizeof(Real) : kDropOffset;
         const long kp = (long)k * plane;
