@@ -71,11 +71,9 @@ __device__ void face_block(const FaceArgs<Real>& a, int b) {
   const long lev = a.prime ? cnt : cnt + 1;  // time level of the pressure to sample
   const int buf = (int)(lev % a.d0.nbuf);
 
-  if (b < a.nb_tr0) {
-    face_traces(a, 0, b * 256 + tid, buf);
-  } else if ((b -= a.nb_tr0) < a.nb_tr1) {
-    face_traces(a, 1, b * 256 + tid, buf);
-  } else if ((b -= a.nb_tr1) < a.nb_pm) {
+  // PMUT blocks come first: they carry the longest chains of dependent
+  // loads, so they should all be resident from the start of the launch
+  if (b < a.nb_pm) {
     // One PMUT.  Every load the update needs is issued up front (state,
     // ODE coefficients and drive value by the first threads, the sampled
     // pressures by all), so the block waits for memory once for the gather
@@ -180,8 +178,12 @@ __device__ void face_block(const FaceArgs<Real>& a, int b) {
         if (m < Nm) f += qdd_s[m] * bm[m];
       F[a.pm_node[n]] = (Real)(-a.kappa * f);
     }
+  } else if ((b -= a.nb_pm) < a.nb_tr0) {
+    face_traces(a, 0, b * 256 + tid, buf);
+  } else if ((b -= a.nb_tr0) < a.nb_tr1) {
+    face_traces(a, 1, b * 256 + tid, buf);
   } else if (!a.prime) {
-    b -= a.nb_pm;
+    b -= a.nb_tr1;
     const int item = b * kWaves + wave;
     if (item < a.S * a.R) {
       const int s = item / a.R, r = item - s * a.R;
