@@ -106,6 +106,43 @@ def run_gpu(wl, precision, steps, warmup, graphs, rows, zchunk, tblock=1):
     return el, el_graph, kt, finite
 
 
+def scenarios_leg(steps, warmup, rows, zchunk, S=4):
+    """The large-array workload with S drive scenarios in one solver (beam
+    steered to 20, 0, -20 and 40 degrees): S times the working set, well
+    beyond the 256 MB last-level cache, so its rate cannot lean on that
+    cache.  Same FP32 kernels, one launch per brick per step for all S."""
+    import math
+    from paper_2603_06267_amd import workloads as W
+    wl = W.config3(steps=steps + warmup)
+    ctr = np.asarray(wl["pmuts"]["centers"], dtype=np.float64)
+    f = float(np.asarray(wl["drive"]["freq"]).reshape(-1)[0])
+    angles = [20.0, 0.0, -20.0, 40.0][:S]
+    phase = np.stack([2 * math.pi * f * ctr[:, 0] * math.sin(math.radians(a)) / W.C_WATER for a in angles])
+    wl["drive"] = dict(wl["drive"], amp=np.ones((S, len(ctr))), phase=phase, freq=np.full(S, f))
+    el, el_graph, kt, finite = run_gpu(wl, 32, steps, warmup, True, rows, zchunk)
+    dofs = W.unique_dofs(wl)
+    return {"scenarios": S, "value": S * dofs * steps / min(el, el_graph), "unit": "DOF-updates/s",
+            "ms_per_step": min(el, el_graph) * 1e3 / steps, "stiff_ms": kt[0],
+            "achieved_GBs": 12.0 * S * dofs / (kt[0] * 1e-3) / 1e9,
+            "frac": 12.0 * S * dofs / (kt[0] * 1e-3) / 1e9 / PEAK_HBM_GBS, "finite": finite}
+
+
+def small_configs_leg(steps=400, warmup=20):
+    """DOF-updates/s of the small workloads (the config-1 cube and the
+    config-2 two-domain array), FP32 and FP64, hipGraph replay: latency-bound
+    launches, reported as rates only."""
+    from paper_2603_06267_amd import workloads as W
+    out = {}
+    for name, wl in (("config1", W.config1()), ("config2", W.config2())):
+        wl = dict(wl, steps=steps + warmup)
+        dofs = W.unique_dofs(wl)
+        for prec in (32, 64):
+            el, el_graph, kt, finite = run_gpu(wl, prec, steps, warmup, True, 2, -1)  # automatic z chunks
+            out[f"{name}_fp{prec}"] = {"unique_dofs": dofs, "value": dofs * steps / min(el, el_graph),
+                                       "ms_per_step": min(el, el_graph) * 1e3 / steps, "finite": finite}
+    return out
+
+
 def batched_leg(steps=512):
     """Batched form on the batch workload (64 drive scenarios of the cube with
     a 4x4 PMUT array + 16 uneven single-brick meshes, orders 3..6): one
@@ -232,6 +269,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 instantiation")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form leg")
+    ap.add_argument("--no-scenarios", action="store_true",
+                    help="skip the large-array leg with 4 drive scenarios in one solver")
+    ap.add_argument("--no-small", action="store_true", help="skip the small-workload rates")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-form leg")
     ap.add_argument("--surrogate-runs", type=int, default=4096)
     ap.add_argument("--surrogate-steps", type=int, default=3000)
@@ -299,6 +339,12 @@ def main():
         out["fp64"] = {"value": dofs * args.steps / min(el64, elg64), "unit": "DOF-updates/s",
                        "stiff_ms": kt64[0], "achieved_GBs": 24.0 * (n0 + n1) / (kt64[0] * 1e-3) / 1e9,
                        "frac": 24.0 * (n0 + n1) / (kt64[0] * 1e-3) / 1e9 / PEAK_HBM_GBS}
+    if not args.no_scenarios:
+        log("large array x 4 scenarios ...")
+        out["scenarios4"] = scenarios_leg(min(args.steps, 200), args.warmup, args.rows, args.zchunk)
+    if not args.no_small:
+        log("small workloads ...")
+        out["small"] = small_configs_leg()
     if not args.no_batched:
         log("batched form ...")
         out["batched"] = batched_leg()

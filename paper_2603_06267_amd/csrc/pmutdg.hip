@@ -196,7 +196,7 @@ struct pmdg_solver {
   std::map<std::string, Seg> seg;
   long steps_done = 0;
   // options
-  int use_graph = 1, rows = 2, zchunk = 73, graph_chunk = 64, timing = 0;
+  int use_graph = 1, rows = 2, zchunk = -1, graph_chunk = 64, timing = 0;  // zchunk -1: automatic
   int rows1 = 0, zchunk1 = -1;  // secondary brick's tile (0 / -1: as the primary's)
   int waves = 4;                // waves per stiffness workgroup
   int depth = 2;                // stiffness prefetch distance in planes
@@ -567,6 +567,21 @@ static DomView<Real> view(pmdg_solver* s, int d) {
   return v;
 }
 
+// Planes per stiffness workgroup along z for brick d, whose plane layer
+// has layer_tiles workgroup tiles (all scenarios): an explicit chunk, the
+// whole brick (0), or automatically (-1) 73 planes unless that leaves fewer
+// than 512 workgroups (two per CU), then fewer planes, at least 4.  Each
+// workgroup's plane loop is a chain of dependent memory round trips, so a
+// small brick needs short chunks to finish quickly.
+static int brick_zchunk(const pmdg_solver* s, int d, long layer_tiles) {
+  const int zc = (d == 1 && s->zchunk1 >= 0) ? s->zchunk1 : s->zchunk;
+  const int nz = s->b[d].nn[2];
+  if (zc > 0) return std::min(zc, nz);
+  if (zc == 0) return nz;
+  const long fit = (long)nz * layer_tiles / 512;
+  return (int)std::min<long>(nz, std::max(4L, std::min(73L, fit)));
+}
+
 template <typename Real>
 static StiffArgs<Real> stiff_args(pmdg_solver* s, int d) {
   StiffArgs<Real> a;
@@ -594,7 +609,6 @@ static StiffArgs<Real> stiff_args(pmdg_solver* s, int d) {
   }
   const Brick& B = s->b[d];
   a.rows = (d == 1 && s->rows1 > 0) ? s->rows1 : s->rows;
-  const int zc = (d == 1 && s->zchunk1 >= 0) ? s->zchunk1 : s->zchunk;
   a.waves = s->waves;
   a.depth = deep_prefetch_built(B.N, a.rows, a.waves) ? s->depth : 2;
   a.nbx = B.px / 64;
@@ -602,7 +616,7 @@ static StiffArgs<Real> stiff_args(pmdg_solver* s, int d) {
   a.nby = (B.nn[1] + TY - 1) / TY;
   a.zlo = 0;
   a.zhi = B.nn[2] - 1;
-  a.zchunk = (zc > 0) ? std::min(zc, B.nn[2]) : B.nn[2];
+  a.zchunk = brick_zchunk(s, d, (long)a.nbx * a.nby * s->S);
   a.nbz = (B.nn[2] + a.zchunk - 1) / a.zchunk;
   a.nblocks = a.nbx * a.nby * a.nbz * s->S;
   return a;
@@ -841,12 +855,11 @@ static StiffArgs<float> stiff2_args(pmdg_solver* s, int d) {
   StiffArgs<float> a = stiff_args<float>(s, d);
   const Brick& B = s->b[d];
   const int TYO = stiff2_tile_rows(B.N), TXO = 64 - 2 * B.N;
-  const int zc = (d == 1 && s->zchunk1 >= 0) ? s->zchunk1 : s->zchunk;
   a.nbx = (B.nn[0] + TXO - 1) / TXO;
   a.nby = (B.nn[1] + TYO - 1) / TYO;
   a.zlo = 0;
   a.zhi = B.nn[2] - 1;
-  a.zchunk = (zc > 0) ? std::min(zc, B.nn[2]) : B.nn[2];
+  a.zchunk = brick_zchunk(s, d, (long)a.nbx * a.nby * s->S);
   a.nbz = (B.nn[2] + a.zchunk - 1) / a.zchunk;
   a.nblocks = a.nbx * a.nby * a.nbz * s->S;
   int r[4];
@@ -1360,7 +1373,7 @@ pmdg_status pmdg_set_option(pmdg_solver* s, int option, long value) {
       s->rows = (int)value;
       break;
     case PMDG_OPT_TILE_ZCHUNK:
-      if (value < 0) return fail(PMDG_EINVAL, "zchunk must be >= 0");
+      if (value < -1) return fail(PMDG_EINVAL, "zchunk must be >= -1");
       s->zchunk = (int)value;
       break;
     case PMDG_OPT_OVERLAP:
