@@ -75,8 +75,9 @@ __device__ __forceinline__ T wave_sum(T v) {
 // copy of the current plane with an N-node halo.  Everything a plane needs
 // (lead plane, halos, the increment or previous level) is fetched D planes
 // ahead (two by default) so that memory latency overlaps the arithmetic of
-// the planes in between, with one barrier per plane.  Operator rows come by node class (x per lane, y per
-// wave row, z per plane, all uniform where the class is).
+// the planes in between, with one barrier per plane.  Operator rows come by
+// node class (x per lane, y per wave row, z per plane, all uniform where the
+// class is), as do the absorbing-face coefficients.
 // Increment form (FP32): X holds p^n - p^{n-1}, X += a, p^{n+1} = p^n + X.
 // Two-level form (FP64): p^{n+1} = p^n + (p^n - p^{n-1}) + a over p^{n-1}.
 // ------------------------------------------------------------------------
@@ -87,14 +88,12 @@ __device__ __forceinline__ int node_class(int i, int n) {
 
 // LDS (in Real elements) of one stiffness workgroup: two plane buffers and
 // the z rows by node class (2N taps, inverse mass, absorbing coefficient)
-template <int N, int RY, int WV>
-__host__ __device__ constexpr int stiff_lds_elems() {
+__host__ __device__ constexpr int stiff_lds_elems_rt(int N, int RY, int WV) {
   return 2 * (64 + 2 * N) * (WV * RY + 2 * N) + (N + 2) * (2 * N + 2);
 }
-
-// the same count for run-time arguments
-inline int stiff_lds_elems_rt(int N, int RY, int WV) {
-  return 2 * (64 + 2 * N) * (WV * RY + 2 * N) + (N + 2) * (2 * N + 2);
+template <int N, int RY, int WV>
+__host__ __device__ constexpr int stiff_lds_elems() {
+  return stiff_lds_elems_rt(N, RY, WV);
 }
 
 constexpr int ct_gcd(int a, int b) { return b == 0 ? a : ct_gcd(b, a % b); }
