@@ -174,7 +174,8 @@ pmdg_status pmdg_status_flags(pmdg_solver* h, int* nonfinite, void* stream);
 
 /* Options: PMDG_OPT_GRAPH (1 = replay hipGraphs, 0 = direct launches),
  * PMDG_OPT_TILE_ROWS (rows per wave of the stiffness tile: 1, 2 or 4; a
- * workgroup covers 64 x (4 rows) nodes per plane),
+ * workgroup covers 64 x (4 rows) nodes per plane; 0 = automatic (default):
+ * 1 for a brick whose whole z extent is one chunk at 2 rows, else 2),
  * PMDG_OPT_TILE_ZCHUNK (planes per workgroup along z, 0 = whole brick,
  * -1 = automatic (default): 73 unless a brick would then have fewer than
  * 512 workgroups, then fewer, at least 4),

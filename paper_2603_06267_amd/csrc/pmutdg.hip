@@ -196,7 +196,7 @@ struct pmdg_solver {
   std::map<std::string, Seg> seg;
   long steps_done = 0;
   // options
-  int use_graph = 1, rows = 2, zchunk = -1, graph_chunk = 64, timing = 0;  // zchunk -1: automatic
+  int use_graph = 1, rows = 0, zchunk = -1, graph_chunk = 64, timing = 0;  // rows 0, zchunk -1: automatic
   int rows1 = 0, zchunk1 = -1;  // secondary brick's tile (0 / -1: as the primary's)
   int waves = 4;                // waves per stiffness workgroup
   int depth = 2;                // stiffness prefetch distance in planes
@@ -582,6 +582,20 @@ static int brick_zchunk(const pmdg_solver* s, int d, long layer_tiles) {
   return (int)std::min<long>(nz, std::max(4L, std::min(73L, fit)));
 }
 
+// Rows per wave of brick d's stiffness tile: an explicit choice, or
+// automatically (0) 1 for a brick whose whole z extent is one chunk at 2
+// rows, else 2.  Such a brick cannot gain workgroups along z without
+// reloading 2N halo planes per extra chunk; halving the rows doubles its
+// workgroups at the cost of y-halo rows, which mostly hit in L2.
+static int brick_rows(const pmdg_solver* s, int d) {
+  const int r = (d == 1 && s->rows1 > 0) ? s->rows1 : s->rows;
+  if (r > 0) return r;
+  const Brick& B = s->b[d];
+  const long ty = 2L * s->waves;
+  const long layer = (long)(B.px / 64) * ((B.nn[1] + ty - 1) / ty) * s->S;
+  return brick_zchunk(s, d, layer) >= B.nn[2] ? 1 : 2;
+}
+
 template <typename Real>
 static StiffArgs<Real> stiff_args(pmdg_solver* s, int d) {
   StiffArgs<Real> a;
@@ -608,7 +622,7 @@ static StiffArgs<Real> stiff_args(pmdg_solver* s, int d) {
     a.absorb = s->b[d].absorbing != 0;
   }
   const Brick& B = s->b[d];
-  a.rows = (d == 1 && s->rows1 > 0) ? s->rows1 : s->rows;
+  a.rows = brick_rows(s, d);
   a.waves = s->waves;
   a.depth = deep_prefetch_built(B.N, a.rows, a.waves) ? s->depth : 2;
   a.nbx = B.px / 64;
@@ -1369,7 +1383,8 @@ pmdg_status pmdg_set_option(pmdg_solver* s, int option, long value) {
   switch (option) {
     case PMDG_OPT_GRAPH: s->use_graph = value ? 1 : 0; break;
     case PMDG_OPT_TILE_ROWS:
-      if (!(value == 1 || value == 2 || value == 4)) return fail(PMDG_EINVAL, "tile rows per wave must be 1, 2 or 4");
+      if (!(value == 0 || value == 1 || value == 2 || value == 4))
+        return fail(PMDG_EINVAL, "tile rows per wave must be 0 (automatic), 1, 2 or 4");
       s->rows = (int)value;
       break;
     case PMDG_OPT_TILE_ZCHUNK:
@@ -1605,12 +1620,13 @@ pmdg_status pmdg_batch_create(int n, pmdg_solver* const* solvers, pmdg_batch** o
     pmdg_solver* s = solvers[i];
     if (!s || !s->bound) { delete b; return fail(PMDG_ESTATE, "every solver must be bound"); }
     if (s->ndom != 1 || s->prec != 32) { delete b; return fail(PMDG_EINVAL, "batches take single-brick FP32 solvers"); }
-    if (s->rows != 1 && s->rows != 2) { delete b; return fail(PMDG_EINVAL, "batched tiles use 1 or 2 rows per wave"); }
+    const int rows = brick_rows(s, 0);
+    if (rows != 1 && rows != 2) { delete b; return fail(PMDG_EINVAL, "batched tiles use 1 or 2 rows per wave"); }
     if (s->waves != kWaves) { delete b; return fail(PMDG_EINVAL, "batched tiles use 4 waves per workgroup"); }
     b->sv.push_back(s);
     b->nmax = std::max(b->nmax, s->b[0].N);
     b->nm_max = std::max(b->nm_max, s->Nm);
-    b->lds = std::max(b->lds, batch_lds_bytes(s->b[0].N, s->rows));
+    b->lds = std::max(b->lds, batch_lds_bytes(s->b[0].N, rows));
     b->n_stiff += stiff_args<float>(s, 0).nblocks;
     b->n_face += face_args<float>(s, 0).nblocks;
   }

@@ -138,9 +138,12 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
   const Real* __restrict__ TP = a.taps;
   const Real* __restrict__ MI = a.mins;
   const unsigned px = (unsigned)a.d.px;
-  // rows are padded to a multiple of 64 nodes: every lane's x is inside the row
+  // rows are padded to a multiple of 64 nodes: every lane's x is inside the
+  // row.  Lanes past the last node load from the last node's address, so a
+  // tile that holds the row's tail touches no cache line of padding alone.
   const int x = bx * TX + lane;
   const bool xin = x < nx;
+  const unsigned xl = (unsigned)min(x, nx - 1);
   const int ybase = by * TY + wave * RY;
 
   Real tx[NT];
@@ -165,7 +168,7 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
     const int y = ybase + r;
     cyr[r] = y < ny ? node_class<N>(y, ny) : N + 2;
     in[r] = xin && y < ny;
-    roff[r] = (unsigned)x + px * (unsigned)min(y, ny - 1);
+    roff[r] = xl + px * (unsigned)min(y, ny - 1);
 #pragma unroll
     for (int i = 0; i < NT; ++i) ty[r][i] = TP[(NC + cyr[r]) * NT + i];
     my[r] = MI[NC + cyr[r]];
@@ -204,7 +207,7 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
     const int trow = hr < N ? hr : (TY + hr);
     const int y = by * TY - N + trow;
     yh_ok[j] = hr < NT && xin && y >= 0 && y < ny;
-    yh_off[j] = yh_ok[j] ? (unsigned)x + px * (unsigned)y : roff[0];
+    yh_off[j] = yh_ok[j] ? xl + px * (unsigned)y : roff[0];
     yh_dst[j] = hr < NT ? trow * W + N + lane : -1;
   }
 

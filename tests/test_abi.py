@@ -74,6 +74,8 @@ def test_setup_errors_and_state_errors():
     assert _err(s.set_pmut_shape, 0, np.full(n, 1e3)) == _lib.PMDG_EUNSTABLE
     assert _err(s.step, 1, 0) == _lib.PMDG_ESTATE
     assert _err(s.set_option, 2, 3) == _lib.PMDG_EINVAL
+    assert _err(s.set_option, 2, -1) == _lib.PMDG_EINVAL
+    s.set_option(2, 0)                                             # automatic rows per wave
     assert _err(s.set_option, 3, -2) == _lib.PMDG_EINVAL
     s.set_option(3, -1)
     assert _err(s.set_absorbing, 1, 1) == _lib.PMDG_EINVAL      # one brick only
