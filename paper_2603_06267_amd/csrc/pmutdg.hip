@@ -171,6 +171,7 @@ struct pmdg_solver {
   Brick b[2];
   // interface
   int Nq = 0;
+  int xl_max = 0;  // most fine Gauss points inside one coarse element along x
   std::vector<double> Lq, wJ, xw, yw;
   std::vector<int> xcx, ycx, xl_off, xl, yl_off, yl;
   double gamma = 0, dz0[kMaxOrder + 1] = {0}, dz1[kMaxOrder + 1] = {0};
@@ -385,8 +386,10 @@ static int setup_interface(pmdg_solver* s, std::string& err) {
       lst.insert(lst.end(), buckets[k].begin(), buckets[k].end());
     }
     off[nec] = (int)lst.size();
-    for (int k = 0; k < nec; ++k)
+    for (int k = 0; k < nec; ++k) {
       if (off[k + 1] - off[k] > 64) { err = "more than 64 fine Gauss points per coarse element along an axis"; return -1; }
+      if (axis == 0) s->xl_max = std::max(s->xl_max, off[k + 1] - off[k]);
+    }
   }
   const double cbar = 2.0 * F.c * C.c / (F.c + C.c);
   const int nmax = std::max(N0, N1);
@@ -728,8 +731,9 @@ static FluxArgs<Real> flux_args(pmdg_solver* s, int tick) {
   a.tick = tick;
   a.xsel = (int*)(dptr<char>(s, "ctl") + 8);
   a.toggle = 0;  // bit d: swap brick d's live increment copy
-  a.nb_fine = (s->S * nfine(s) + kWaves - 1) / kWaves;
-  a.nb_coarse = (s->S * ncoarse(s) + kWaves - 1) / kWaves;
+  a.nb_fine = (s->S * nfine(s) + 2 * kWaves - 1) / (2 * kWaves);
+  a.nb_coarse = (s->S * ncoarse(s) + 2 * kWaves - 1) / (2 * kWaves);
+  a.tcap = s->xl_max * (a.N1 + 1);
   return a;
 }
 

@@ -143,7 +143,8 @@ struct FluxArgs {
   int tick;
   int* xsel;                // [2] live increment copy per brick; with the
   int toggle;               // tick, bit d of toggle swaps brick d's
-  int nb_fine, nb_coarse;   // blocks (4 faces each)
+  int nb_fine, nb_coarse;   // blocks (8 faces each: two per wave)
+  int tcap;                 // LDS entries per component and coarse face (x points x (N1+1))
 };
 
 // Launchers (defined in pmutdg_kernels.hip).

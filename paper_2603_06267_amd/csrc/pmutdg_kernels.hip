@@ -231,35 +231,52 @@ __global__ void k_tick_batch(long* const* __restrict__ counters, int n) {
 
 // ------------------------------------------------------------------------
 // Interface flux, in two passes over Gamma_I.
-//   k_flux_fine: one wave per fine face.  The face's value / normal-derivative
+//   k_flux_fine: one half-wave per fine face.  The face's value / normal-derivative
 //     traces are staged in LDS and interpolated to its Nq x Nq Gauss points by
 //     two 1D contractions; the coarse traces are interpolated the same way
 //     (x first, over the at most 2 N1 + 1 coarse node rows the face touches,
 //     then y).  At each point the SIPG integrand gives
 //       A_q = w J (gamma [p] - {c^2 d_n p}),  B_q = -w J [p] / 2,
 //     stored for the coarse pass and reduced onto the fine face's nodes.
-//   k_flux_coarse: one wave per coarse face: reduces the A_q, B_q of the
+//   k_flux_coarse: one half-wave per coarse face: reduces the A_q, B_q of the
 //     points mapped into it onto its nodes (two 1D contractions), and, in the
 //     last launch of a step, advances the step counter.
 // ------------------------------------------------------------------------
+// LDS of a fine-pass workgroup, in Real entries: the two tables, then per
+// face slot the fine traces, the x-contracted rows, the x-contracted coarse
+// rows (a fine face meets at most two coarse element rows: 2 N1 + 1 node
+// rows), the SIPG terms and the coarse y basis; the slots' coarse element
+// rows (ints) follow.
+__host__ __device__ inline int flux_fine_slot(int Nq, int N0, int N1) {
+  const int n0 = N0 + 1, n1 = N1 + 1;
+  return 2 * n0 * n0 + 2 * Nq * n0 + 2 * Nq * (2 * N1 + 1) + 2 * Nq * Nq + Nq * n1;
+}
+
 template <typename Real>
-__device__ __forceinline__ void flux_fine_block(const FluxArgs<Real>& a, int blk) {
-  constexpr int MQ = kMaxNq - 1;  // Nq <= 8 on Gamma_I (orders <= 7)
-  __shared__ Real sT[kWaves][2][64];
-  __shared__ Real sR[kWaves][2][MQ * 8];
-  __shared__ Real sC[kWaves][2][MQ * 16];
-  __shared__ Real sA[kWaves][2][64];
-  // the interpolation and weight tables shared by every face, staged once
-  __shared__ Real sL[MQ * MQ], sW[MQ * MQ];
-  // per face: coarse element row and coarse basis of each Gauss row
-  __shared__ int sCY[kWaves][MQ];
-  __shared__ Real sY[kWaves][MQ * MQ];
+__device__ __forceinline__ void flux_fine_block(const FluxArgs<Real>& a, int blk, unsigned char* raw) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // two fine faces per wave, one per half-wave, so that a launch over the
+  // interface fits the machine's wave slots in one round
+  const int hl = lane & 31, slot = 2 * w + (lane >> 5);
   const int Nq = a.Nq, N0 = a.N0, N1 = a.N1, n0 = N0 + 1, n1 = N1 + 1;
+  const int crow = 2 * N1 + 1, fs = flux_fine_slot(Nq, N0, N1);
+  Real* sL = reinterpret_cast<Real*>(raw);
+  Real* sW = sL + Nq * n0;
+  Real* base = sW + Nq * Nq + slot * fs;
+  Real* T0v = base;                  // fine traces: value, normal derivative
+  Real* T0d = T0v + n0 * n0;
+  Real* Rv = T0d + n0 * n0;          // x-contracted rows
+  Real* Rd = Rv + Nq * n0;
+  Real* Cv = Rd + Nq * n0;           // x-contracted coarse rows
+  Real* Cd = Cv + Nq * crow;
+  Real* Av = Cd + Nq * crow;         // SIPG terms at the Gauss points
+  Real* Ad = Av + Nq * Nq;
+  Real* Yw = Ad + Nq * Nq;           // coarse y basis of each Gauss row
+  int* CY = reinterpret_cast<int*>(sW + Nq * Nq + 2 * kWaves * fs) + slot * Nq;
   const int nfine = a.nex0 * a.ney0;
   for (int i = threadIdx.x; i < Nq * n0; i += 64 * kWaves) sL[i] = a.Lq[i];
   for (int i = threadIdx.x; i < Nq * Nq; i += 64 * kWaves) sW[i] = a.wJ[i];
-  const int item = blk * kWaves + w;
+  const int item = blk * (2 * kWaves) + slot;
   const bool valid = item < a.S * nfine;
   const int s = valid ? item / nfine : 0, f = valid ? item - s * nfine : 0;
   const int ex = f % a.nex0, ey = f / a.nex0;
@@ -267,27 +284,28 @@ __device__ __forceinline__ void flux_fine_block(const FluxArgs<Real>& a, int blk
   const Real* T0 = a.tr0 + (long)s * nf0 * 2;
   const Real* T1 = a.tr1 + (long)s * nf1 * 2;
   // coarse node rows touched by this face (one lane per Gauss row, reduced
-  // across the wave)
+  // across the half-wave)
   int cy_lo = 1 << 30, cy_hi = -1;
-  if (lane < Nq) {
-    const int c = a.ycx[ey * Nq + lane];
-    sCY[w][lane] = c;
+  if (hl < Nq) {
+    const int c = a.ycx[ey * Nq + hl];
+    CY[hl] = c;
     cy_lo = cy_hi = c;
   }
-  if (lane < Nq * n1) sY[w][lane] = a.yw[(long)(ey * Nq) * n1 + lane];
+  for (int l = hl; l < Nq * n1; l += 32) Yw[l] = a.yw[(long)(ey * Nq) * n1 + l];
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
+  for (int o = 16; o > 0; o >>= 1) {
     cy_lo = min(cy_lo, __shfl_xor(cy_lo, o, 64));
     cy_hi = max(cy_hi, __shfl_xor(cy_hi, o, 64));
   }
   const int ry0 = N1 * cy_lo, nrow = N1 * (cy_hi - cy_lo) + n1;
   // (1) fine traces into LDS; coarse traces contracted along x
-  if (valid && lane < n0 * n0) {
-    const long node = (long)(N0 * ex + lane % n0) + (long)a.nn0x * (N0 * ey + lane / n0);
-    sT[w][0][lane] = T0[node * 2];
-    sT[w][1][lane] = T0[node * 2 + 1];
-  }
-  for (int l = lane; l < Nq * nrow; l += 64) {
+  if (valid)
+    for (int l = hl; l < n0 * n0; l += 32) {
+      const long node = (long)(N0 * ex + l % n0) + (long)a.nn0x * (N0 * ey + l / n0);
+      T0v[l] = T0[node * 2];
+      T0d[l] = T0[node * 2 + 1];
+    }
+  for (int l = hl; l < Nq * nrow; l += 32) {
     const int qa = l % Nq, row = ry0 + l / Nq;
     const int cx = a.xcx[ex * Nq + qa];
     const Real* wx = a.xw + (long)(ex * Nq + qa) * n1;
@@ -298,99 +316,106 @@ __device__ __forceinline__ void flux_fine_block(const FluxArgs<Real>& a, int blk
         cv += wx[aa] * T1[node * 2];
         cd += wx[aa] * T1[node * 2 + 1];
       }
-    sC[w][0][l] = cv;
-    sC[w][1][l] = cd;
+    Cv[l] = cv;
+    Cd[l] = cd;
   }
   __syncthreads();
-  // (2) fine traces contracted along x: sR[qa + Nq b]
-  if (lane < Nq * n0) {
-    const int qa = lane % Nq, b = lane / Nq;
+  // (2) fine traces contracted along x: R[qa + Nq b]
+  for (int l = hl; l < Nq * n0; l += 32) {
+    const int qa = l % Nq, b = l / Nq;
     Real rv = 0, rd = 0;
     for (int aa = 0; aa < n0; ++aa) {
-      const Real l = sL[qa * n0 + aa];
-      rv += l * sT[w][0][aa + n0 * b];
-      rd += l * sT[w][1][aa + n0 * b];
+      const Real lq = sL[qa * n0 + aa];
+      rv += lq * T0v[aa + n0 * b];
+      rd += lq * T0d[aa + n0 * b];
     }
-    sR[w][0][lane] = rv;
-    sR[w][1][lane] = rd;
+    Rv[l] = rv;
+    Rd[l] = rd;
   }
   __syncthreads();
   // (3) SIPG integrand at the Gauss points
-  if (lane < Nq * Nq) {
-    const int qa = lane % Nq, qb = lane / Nq;
+  for (int l = hl; l < Nq * Nq; l += 32) {
+    const int qa = l % Nq, qb = l / Nq;
     Real pP = 0, dP = 0, pM = 0, dM = 0;
     for (int b = 0; b < n0; ++b) {
-      const Real l = sL[qb * n0 + b];
-      pP += l * sR[w][0][qa + Nq * b];
-      dP += l * sR[w][1][qa + Nq * b];
+      const Real lq = sL[qb * n0 + b];
+      pP += lq * Rv[qa + Nq * b];
+      dP += lq * Rd[qa + Nq * b];
     }
-    const int cy = sCY[w][qb];
-    const Real* wy = &sY[w][qb * n1];
+    const int cy = CY[qb];
+    const Real* wy = &Yw[qb * n1];
     for (int b = 0; b < n1; ++b) {
       const int li = qa + Nq * (N1 * cy + b - ry0);
-      pM += wy[b] * sC[w][0][li];
-      dM += wy[b] * sC[w][1][li];
+      pM += wy[b] * Cv[li];
+      dM += wy[b] * Cd[li];
     }
     const Real jump = pP - pM;
     const Real avg = Real(0.5) * (a.cf2 * dP + a.cc2 * dM);
     const Real wj = sW[qb * Nq + qa];
     const Real A = wj * (a.gamma * jump - avg), B = Real(-0.5) * wj * jump;
-    sA[w][0][lane] = A;
-    sA[w][1][lane] = B;
+    Av[l] = A;
+    Ad[l] = B;
     if (valid) {
-      Real* o = a.Aq + (((long)s * nfine + f) * Nq * Nq + lane) * 2;
+      Real* o = a.Aq + (((long)s * nfine + f) * Nq * Nq + l) * 2;
       o[0] = A;
       o[1] = B;
     }
   }
   __syncthreads();
   // (4) reduce onto the fine nodes: contract along qb, then along qa
-  if (lane < Nq * n0) {
-    const int qa = lane % Nq, b = lane / Nq;
+  for (int l = hl; l < Nq * n0; l += 32) {
+    const int qa = l % Nq, b = l / Nq;
     Real ta = 0, tb = 0;
     for (int qb = 0; qb < Nq; ++qb) {
-      const Real l = sL[qb * n0 + b];
-      ta += l * sA[w][0][qa + Nq * qb];
-      tb += l * sA[w][1][qa + Nq * qb];
+      const Real lq = sL[qb * n0 + b];
+      ta += lq * Av[qa + Nq * qb];
+      tb += lq * Ad[qa + Nq * qb];
     }
-    sR[w][0][lane] = ta;
-    sR[w][1][lane] = tb;
+    Rv[l] = ta;
+    Rd[l] = tb;
   }
   __syncthreads();
-  if (valid && lane < n0 * n0) {
-    const int aa = lane % n0, b = lane / n0;
-    Real RA = 0, RB = 0;
-    for (int qa = 0; qa < Nq; ++qa) {
-      const Real l = sL[qa * n0 + aa];
-      RA += l * sR[w][0][qa + Nq * b];
-      RB += l * sR[w][1][qa + Nq * b];
+  if (valid)
+    for (int l = hl; l < n0 * n0; l += 32) {
+      const int aa = l % n0, b = l / n0;
+      Real RA = 0, RB = 0;
+      for (int qa = 0; qa < Nq; ++qa) {
+        const Real lq = sL[qa * n0 + aa];
+        RA += lq * Rv[qa + Nq * b];
+        RB += lq * Rd[qa + Nq * b];
+      }
+      Real* R = a.R0 + (((long)s * nfine + f) * n0 * n0 + l) * 2;
+      R[0] = RA;
+      R[1] = RB;
     }
-    Real* R = a.R0 + (((long)s * nfine + f) * n0 * n0 + lane) * 2;
-    R[0] = RA;
-    R[1] = RB;
-  }
 }
 
 template <typename Real>
 __global__ void __launch_bounds__(256) k_flux_fine(const FluxArgs<Real> a) {
-  flux_fine_block(a, blockIdx.x);
+  extern __shared__ __align__(16) unsigned char flux_lds[];
+  flux_fine_block(a, blockIdx.x, flux_lds);
 }
 
 template <typename Real>
 __global__ void __launch_bounds__(256) k_flux_coarse(const FluxArgs<Real> a) {
-  constexpr int ML = 64;  // fine Gauss points per coarse element along one axis
-  __shared__ Real sT[kWaves][2][ML * 8];
+  // Two coarse faces per wave, one per half-wave, so that a launch over the
+  // interface fits the machine's wave slots in one round.  Each face keeps
+  // its y-contracted sums (tcap entries per component) in dynamic LDS.
+  extern __shared__ __align__(16) unsigned char flux_lds[];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int Nq = a.Nq, N1 = a.N1, n1 = N1 + 1;
+  const int hl = lane & 31, slot = 2 * w + (lane >> 5);
+  const int Nq = a.Nq, N1 = a.N1, n1 = N1 + 1, tc = a.tcap;
   const int nfine = a.nex0 * a.ney0, ncoarse = a.nex1 * a.ney1;
-  const int item = blockIdx.x * kWaves + w;
+  const int item = blockIdx.x * (2 * kWaves) + slot;
   const bool valid = item < a.S * ncoarse;
   const int s = valid ? item / ncoarse : 0, f = valid ? item - s * ncoarse : 0;
   const int cx = f % a.nex1, cy = f / a.nex1;
   const int xo0 = a.xl_off[cx], nxl = a.xl_off[cx + 1] - xo0;
   const int yo0 = a.yl_off[cy], nyl = a.yl_off[cy + 1] - yo0;
-  // (1) contract along y: sT[ix + ML b] = sum_iy wy(iy)[b] A(ix, iy)
-  for (int l = lane; l < nxl * n1; l += 64) {
+  Real* TA = reinterpret_cast<Real*>(flux_lds) + 2 * slot * tc;
+  Real* TB = TA + tc;
+  // (1) contract along y: T[ix + nxl b] = sum_iy wy(iy)[b] A(ix, iy)
+  for (int l = hl; l < nxl * n1; l += 32) {
     const int ix = l % nxl, b = l / nxl;
     const int ex_qa = a.xl[xo0 + ix];
     const int ex = ex_qa / Nq, qa = ex_qa % Nq;
@@ -407,23 +432,24 @@ __global__ void __launch_bounds__(256) k_flux_coarse(const FluxArgs<Real> a) {
         ta += wy * A[0];
         tb += wy * A[1];
       }
-    sT[w][0][ix + ML * b] = ta;
-    sT[w][1][ix + ML * b] = tb;
+    TA[l] = ta;
+    TB[l] = tb;
   }
   __syncthreads();
   // (2) contract along x onto the coarse face's nodes
-  if (valid && lane < n1 * n1) {
-    const int aa = lane % n1, b = lane / n1;
-    Real RA = 0, RB = 0;
-    for (int ix = 0; ix < nxl; ++ix) {
-      const Real wx = a.xw[(long)a.xl[xo0 + ix] * n1 + aa];
-      RA += wx * sT[w][0][ix + ML * b];
-      RB += wx * sT[w][1][ix + ML * b];
+  if (valid)
+    for (int l = hl; l < n1 * n1; l += 32) {
+      const int aa = l % n1, b = l / n1;
+      Real RA = 0, RB = 0;
+      for (int ix = 0; ix < nxl; ++ix) {
+        const Real wx = a.xw[(long)a.xl[xo0 + ix] * n1 + aa];
+        RA += wx * TA[ix + nxl * b];
+        RB += wx * TB[ix + nxl * b];
+      }
+      Real* R = a.R1 + (((long)s * ncoarse + f) * n1 * n1 + l) * 2;
+      R[0] = RA;  // the stiffness kernel applies the coarse side's minus sign
+      R[1] = RB;
     }
-    Real* R = a.R1 + (((long)s * ncoarse + f) * n1 * n1 + lane) * 2;
-    R[0] = RA;  // the stiffness kernel applies the coarse side's minus sign
-    R[1] = RB;
-  }
   if (a.tick && blockIdx.x == 0 && threadIdx.x == 0) {
     atomicAdd((unsigned long long*)a.counter, 1ull);
     for (int d = 0; d < 2; ++d)
@@ -483,10 +509,14 @@ hipError_t launch_face(const FaceArgs<Real>& a, hipStream_t st) {
 template <typename Real>
 hipError_t launch_flux(const FluxArgs<Real>& a, hipStream_t st) {
   if (a.nb_fine == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_flux_fine<Real>, dim3(a.nb_fine), dim3(256), 0, st, a);
+  const size_t fine_lds = sizeof(Real) * ((size_t)a.Nq * (a.N0 + 1) + (size_t)a.Nq * a.Nq +
+                                          2 * kWaves * (size_t)flux_fine_slot(a.Nq, a.N0, a.N1)) +
+                          sizeof(int) * 2 * kWaves * (size_t)a.Nq;
+  hipLaunchKernelGGL(k_flux_fine<Real>, dim3(a.nb_fine), dim3(256), fine_lds, st, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_flux_coarse<Real>, dim3(a.nb_coarse), dim3(256), 0, st, a);
+  const size_t lds = sizeof(Real) * 2 * (2 * kWaves) * (size_t)a.tcap;
+  hipLaunchKernelGGL(k_flux_coarse<Real>, dim3(a.nb_coarse), dim3(256), lds, st, a);
   return hipGetLastError();
 }
 
