@@ -60,12 +60,16 @@ __device__ void face_traces(const FaceArgs<Real>& a, int side, int item, int buf
 }
 
 // One workgroup-sized unit b of the face work of one problem.
-// MM bounds the mode loops (a multiple of 4, >= the problem's Nm).
-template <typename Real, int MM>
+// MM bounds the mode loops (a multiple of 4, >= the problem's Nm).  KEEP
+// holds each PMUT node's projection row in LDS between the sampling and the
+// force scatter (the batch kernel, whose persistent loop needs more
+// registers, reloads it instead).
+template <typename Real, int MM, bool KEEP>
 __device__ void face_block(const FaceArgs<Real>& a, int b) {
   __shared__ double red[kWaves][kMaxModes];
   __shared__ double qp_s[kMaxModes], qds_s[kMaxModes], qdd_s[kMaxModes];
   __shared__ double phi_s;
+  __shared__ double sB[KEEP ? MM : 1][256];  // PMUT blocks: each thread's projection row
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const long cnt = *a.counter;
   const long lev = a.prime ? cnt : cnt + 1;  // time level of the pressure to sample
@@ -83,6 +87,14 @@ __device__ void face_block(const FaceArgs<Real>& a, int b) {
     const long qo = ((long)s * a.Np + k) * Nm;
     const int n0 = a.pm_off[k], n1 = a.pm_off[k + 1];
     const double dt = a.dt;
+    // The block's first 256 face nodes (every node of a disc of up to 256):
+    // the node index stays in a register and the projection row in the
+    // thread's own LDS column from the sampling to the force scatter, which
+    // then loads nothing from memory but the new accelerations.
+    const int nf = n0 + tid;
+    const bool mine = KEEP && nf < n1;
+    const int nrest = KEEP ? nf + 256 : nf;  // nodes past the first 256
+    const int node0 = mine ? a.pm_node[nf] : 0;
     if (!a.prime) {
       double q = 0, qd = 0, qdd = 0, w = 0, ze = 0, et = 0;
       const long pi = (long)k * Nm + tid;
@@ -111,9 +123,22 @@ __device__ void face_block(const FaceArgs<Real>& a, int b) {
       for (int m = 0; m < MM; ++m) acc[m] = 0.0;
       const Real* P0 = a.d0.P[buf] + (long)s * a.d0.nnodes;
       bool bad = false;
+      if (mine) {
+        const double p = (double)P0[node0];
+        bad |= !__builtin_isfinite(p);
+        const double* B = a.pm_B + (long)nf * Nm;
+        double bm[MM];
+#pragma unroll
+        for (int m = 0; m < MM; ++m) bm[m] = B[min(m, Nm - 1)];
+#pragma unroll
+        for (int m = 0; m < MM; ++m) {
+          if (KEEP) sB[m][tid] = bm[m];
+          if (m < Nm) acc[m] += bm[m] * p;
+        }
+      }
       // mode loops run over MM with clamped, unconditional loads: a
       // load under a per-mode condition would be waited for one mode at a time
-      for (int n = n0 + tid; n < n1; n += 256) {
+      for (int n = nrest; n < n1; n += 256) {
         const double p = (double)P0[a.pm_node[n]];
         bad |= !__builtin_isfinite(p);
         const double* B = a.pm_B + (long)n * Nm;
@@ -164,10 +189,23 @@ __device__ void face_block(const FaceArgs<Real>& a, int b) {
       }
     } else {
       if (tid < Nm) qdd_s[tid] = a.qdd[qo + tid];
+      if (mine) {
+        const double* B = a.pm_B + (long)nf * Nm;
+#pragma unroll
+        for (int m = 0; m < MM; ++m)
+          if (KEEP) sB[m][tid] = B[min(m, Nm - 1)];
+      }
     }
     __syncthreads();
     Real* F = a.force + (long)s * a.d0.plane;  // padded bottom plane
-    for (int n = n0 + tid; n < n1; n += 256) {
+    if (mine) {
+      double f = 0.0;
+#pragma unroll
+      for (int m = 0; m < MM; ++m)
+        if (m < Nm && KEEP) f += qdd_s[m] * sB[m][tid];
+      F[node0] = (Real)(-a.kappa * f);
+    }
+    for (int n = nrest; n < n1; n += 256) {
       const double* B = a.pm_B + (long)n * Nm;
       double bm[MM];
 #pragma unroll
@@ -209,7 +247,7 @@ __device__ void face_block(const FaceArgs<Real>& a, int b) {
 
 template <typename Real, int MM>
 __global__ void __launch_bounds__(256) k_face(const FaceArgs<Real> a) {
-  face_block<Real, MM>(a, blockIdx.x);
+  face_block<Real, MM, true>(a, blockIdx.x);
 }
 
 // Persistent face kernel over the (problem, unit) work list of a batch.
@@ -219,7 +257,7 @@ __global__ void __launch_bounds__(256) k_face_batch(const FaceArgs<Real>* __rest
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int2 w = items[it];
     __syncthreads();
-    face_block<Real, MM>(probs[w.x], w.y);
+    face_block<Real, MM, false>(probs[w.x], w.y);
   }
 }
 
