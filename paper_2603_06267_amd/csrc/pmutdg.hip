@@ -599,6 +599,26 @@ static int brick_rows(const pmdg_solver* s, int d) {
   return brick_zchunk(s, d, layer) >= B.nn[2] ? 1 : 2;
 }
 
+// Planes per workgroup of brick d's single-step stiffness launch.
+static int launch_zchunk(const pmdg_solver* s, int d) {
+  const Brick& B = s->b[d];
+  const int ty = s->waves * brick_rows(s, d);
+  return brick_zchunk(s, d, (long)(B.px / 64) * ((B.nn[1] + ty - 1) / ty) * s->S);
+}
+
+static bool two_step(const pmdg_solver* s, int d);
+
+// Brick d's stiffness launch writes its own value / normal-derivative
+// traces on Gamma_I, so the face kernel skips its trace blocks: two bricks,
+// brick d on the single-step pass, and the interface element layer inside
+// one z chunk of that launch.
+static bool fused_traces(const pmdg_solver* s, int d) {
+  if (s->ndom < 2 || two_step(s, d)) return false;
+  const int nz = s->b[d].nn[2], N = s->b[d].N, zc = launch_zchunk(s, d);
+  const int l0 = d == 0 ? nz - 1 - N : 0, l1 = d == 0 ? nz - 1 : N;
+  return l0 / zc == l1 / zc;
+}
+
 template <typename Real>
 static StiffArgs<Real> stiff_args(pmdg_solver* s, int d) {
   StiffArgs<Real> a;
@@ -636,6 +656,10 @@ static StiffArgs<Real> stiff_args(pmdg_solver* s, int d) {
   a.zchunk = brick_zchunk(s, d, (long)a.nbx * a.nby * s->S);
   a.nbz = (B.nn[2] + a.zchunk - 1) / a.zchunk;
   a.nblocks = a.nbx * a.nby * a.nbz * s->S;
+  if (fused_traces(s, d)) {
+    a.trace = dptr<Real>(s, d == 0 ? "tr0" : "tr1");
+    for (int c = 0; c <= B.N; ++c) a.trd[c] = (Real)(d == 0 ? s->dz0[c] : s->dz1[c]);
+  }
   return a;
 }
 
@@ -656,8 +680,8 @@ static FaceArgs<Real> face_args(pmdg_solver* s, int prime) {
     a.tr1 = dptr<Real>(s, "tr1");
     for (int c = 0; c <= s->b[0].N; ++c) a.dz0[c] = (Real)s->dz0[c];
     for (int c = 0; c <= s->b[1].N; ++c) a.dz1[c] = (Real)s->dz1[c];
-    a.nb_tr0 = (int)((s->S * face0(s) + 255) / 256);
-    a.nb_tr1 = (int)((s->S * face1(s) + 255) / 256);
+    a.nb_tr0 = prime || !fused_traces(s, 0) ? (int)((s->S * face0(s) + 255) / 256) : 0;
+    a.nb_tr1 = prime || !fused_traces(s, 1) ? (int)((s->S * face1(s) + 255) / 256) : 0;
   }
   if (s->Np > 0) {
     a.Np = s->Np;

@@ -59,6 +59,11 @@ struct StiffArgs {
   const Real* mins;         // [3][N+3]: inverse assembled 1D lumped mass
   const Real* absg;         // [3][N+3]: dt c / m_d on the end classes of absorbing faces, else 0
   int absorb;               // the brick has absorbing faces (absg not all zero)
+  // value / normal-derivative traces of p^{n+1} on Gamma_I written by this
+  // launch ([S][nn0*nn1][2], compact face grid), or null (the face kernel
+  // writes them); trd: the normal-derivative weights of the layer's planes
+  Real* trace;
+  Real trd[kMaxOrder + 1];
   // tiling
   int nbx, nby, nbz, zchunk, rows, waves;
   int depth;                // prefetch distance in planes (2, or 3 / 4 where built)

@@ -310,6 +310,14 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
     constexpr int i = decltype(ic)::value + 1;
     fetch(i, k0 + i);
   });
+  // value and normal derivative of p^{n+1} on Gamma_I, accumulated over the
+  // interface element layer as its planes are updated (when the launch
+  // writes the traces itself; the layer then lies inside one z chunk)
+  Real tv[RY], td[RY];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) tv[r] = td[r] = Real(0);
+  const bool traces = a.trace != nullptr;
+  const int tval = a.iface_side > 0 ? N : 0;  // layer index of the interface plane
 
   for (int kb = k0; kb < k1; kb += U) {
     static_for<U>([&](auto uc) {
@@ -389,6 +397,10 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
           pn = p0 + (p0 - xc[r]) + acc;
         }
         plane_store<NTS>(Pn + kp, plane_bytes, soff, pn);
+        if (traces && in_layer) {
+          td[r] += a.trd[cl] * pn;
+          if (cl == tval) tv[r] = pn;
+        }
       }
       // (4) plane k+1 into the other buffer
       if (more) {
@@ -410,6 +422,16 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
         xc[r] = (in[r] && more) ? fx[cs][r] : Real(0);
       }
     });
+  }
+  if (traces && k0 <= lay0 && lay1 < k1) {
+    Real* TR = a.trace + (long)s * nx * ny * 2;
+#pragma unroll
+    for (int r = 0; r < RY; ++r)
+      if (in[r]) {
+        const long f = x + (long)nx * (ybase + r);
+        TR[f * 2] = tv[r];
+        TR[f * 2 + 1] = td[r];
+      }
   }
 }
 
