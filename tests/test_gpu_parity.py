@@ -121,7 +121,11 @@ def test_graph_replay_equals_direct_launches():
 
 @pytest.mark.parametrize("rows,zchunk", [(1, 0), (2, 5), (4, 3), (1, 11)])
 def test_tilings_agree(rows, zchunk):
-    """Every tile shape gives the same arithmetic per node (bitwise)."""
+    """Every tile shape gives the same arithmetic per node (bitwise).  With
+    3- and 5-plane z chunks an interface element layer spans two chunks, so
+    the face kernel writes that brick's interface traces, which the
+    17-plane reference's stiffness launches write themselves: both paths
+    agree bitwise."""
     wl = W.small_two_domain(False, steps=80)
     sf = W.shape_fn(wl)
     ref_tr = None
