@@ -11,7 +11,8 @@ namespace pmdg {
 template <int N, int RY>
 __device__ __forceinline__ bool run_tile(const StiffArgs<float>& a, int key, int tile, float* lds) {
   if (key != N * 4 + RY) return false;
-  stiff_tile<float, N, true, RY, kWaves, 2, false>(a, tile, lds);
+  // single-brick problems: no interface traces, and none of their registers
+  stiff_tile<float, N, true, RY, kWaves, 2, false, false>(a, tile, lds);
   return true;
 }
 

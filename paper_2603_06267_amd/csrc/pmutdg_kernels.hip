@@ -59,6 +59,38 @@ __device__ void face_traces(const FaceArgs<Real>& a, int side, int item, int buf
   }
 }
 
+// Sums v[0..MM) over the 64 lanes of a wave by recursive halving.  At the
+// step with lane offset o, a lane whose o bit is clear keeps the lower half
+// of its values and one whose bit is set the upper half, and each adds its
+// partner's copy of the half it keeps; after log2(MM) such steps every lane
+// holds one value and plain butterfly steps over the remaining lane bits
+// finish the sums.  Returns the sum held by this lane; *m is its index, and
+// the lanes whose low 6 - log2(MM) bits are zero hold the MM sums once each.
+// 6 dependent exchange rounds for all MM values, instead of 6 per value.
+template <int MM>
+__device__ __forceinline__ double wave_sum_many(double (&v)[MM], int lane, int* m) {
+  static_assert(MM == 4 || MM == 8 || MM == 16, "MM must be 4, 8 or 16");
+  constexpr int LG = MM == 4 ? 2 : (MM == 8 ? 3 : 4);
+  int idx = 0;
+  static_for<LG>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    constexpr int o = 32 >> i, h = MM >> (i + 1);
+    const bool up = (lane & o) != 0;
+#pragma unroll
+    for (int j = 0; j < h; ++j) {
+      const double send = up ? v[j] : v[j + h];
+      const double keep = up ? v[j + h] : v[j];
+      v[j] = keep + __shfl_xor(send, o, 64);
+    }
+    if (up) idx += h;
+  });
+  double r = v[0];
+#pragma unroll
+  for (int o = 32 >> LG; o > 0; o >>= 1) r += __shfl_xor(r, o, 64);
+  *m = idx;
+  return r;
+}
+
 // One workgroup-sized unit b of the face work of one problem.
 // MM bounds the mode loops (a multiple of 4, >= the problem's Nm).  KEEP
 // holds each PMUT node's projection row in LDS between the sampling and the
@@ -154,12 +186,10 @@ __device__ void face_block(const FaceArgs<Real>& a, int b) {
         qp_s[tid] = q + dt * qd + 0.5 * dt * dt * qdd;
         qds_s[tid] = qd + 0.5 * dt * qdd;
       }
-#pragma unroll
-      for (int m = 0; m < MM; ++m) {
-        if (m < Nm) {
-          const double v = wave_sum(acc[m]);
-          if (lane == 0) red[wave][m] = v;
-        }
+      {
+        int m;
+        const double v = wave_sum_many<MM>(acc, lane, &m);
+        if ((lane & ((64 / MM) - 1)) == 0 && m < Nm) red[wave][m] = v;
       }
       __syncthreads();
       if (tid == 0) {

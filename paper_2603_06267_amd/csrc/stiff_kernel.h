@@ -101,8 +101,9 @@ constexpr int ct_gcd(int a, int b) { return b == 0 ? a : ct_gcd(b, a % b); }
 // One tile of the stiffness update (tile = linear tile index of the brick
 // and scenario); lds holds stiff_lds_elems<N, RY, WV>() elements.  D is the
 // prefetch distance in planes (the loads for plane k + D are issued while
-// plane k is updated); NTS selects non-temporal stores.
-template <typename Real, int N, bool INCR, int RY, int WV, int D = 2, bool NTS = true>
+// plane k is updated); NTS selects non-temporal stores; IFT builds in the
+// interface traces (off for the batch kernel, whose problems have none).
+template <typename Real, int N, bool INCR, int RY, int WV, int D = 2, bool NTS = true, bool IFT = true>
 __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id, Real* __restrict__ lds) {
   constexpr int TX = 64, TY = WV * RY, W = TX + 2 * N, H = TY + 2 * N, NT = 2 * N, NQ = NT + 1;
   static_assert(D >= 2, "prefetch distance of at least two planes");
@@ -316,7 +317,7 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
   Real tv[RY], td[RY];
 #pragma unroll
   for (int r = 0; r < RY; ++r) tv[r] = td[r] = Real(0);
-  const bool traces = a.trace != nullptr;
+  const bool traces = IFT && a.trace != nullptr;
   const int tval = a.iface_side > 0 ? N : 0;  // layer index of the interface plane
 
   for (int kb = k0; kb < k1; kb += U) {
