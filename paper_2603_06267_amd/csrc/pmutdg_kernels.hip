@@ -373,19 +373,32 @@ __device__ __forceinline__ void flux_fine_block(const FluxArgs<Real>& a, int blk
       T0v[l] = T0[node * 2];
       T0d[l] = T0[node * 2 + 1];
     }
-  for (int l = hl; l < Nq * nrow; l += 32) {
-    const int qa = l % Nq, row = ry0 + l / Nq;
-    const int cx = a.xcx[ex * Nq + qa];
+  // two items per lane and trip (a face meeting two coarse element rows has
+  // up to Nq (2 N1 + 1) of them, more than 32 at N1 = 3), gathered in one
+  // loop so that both items' loads are in flight together
+  const int ncl = Nq * nrow;
+  for (int l = hl; l < ncl; l += 64) {
+    const int m = min(l + 32, ncl - 1);  // second item, or the first again
+    const int qa = l % Nq, row = ry0 + l / Nq, qm = m % Nq, rowm = ry0 + m / Nq;
+    const int cx = a.xcx[ex * Nq + qa], cxm = a.xcx[ex * Nq + qm];
     const Real* wx = a.xw + (long)(ex * Nq + qa) * n1;
-    Real cv = 0, cd = 0;
+    const Real* wm = a.xw + (long)(ex * Nq + qm) * n1;
+    Real cv = 0, cd = 0, cvm = 0, cdm = 0;
     if (valid)
       for (int aa = 0; aa < n1; ++aa) {
         const long node = (long)(N1 * cx + aa) + (long)a.nn1x * row;
+        const long nodm = (long)(N1 * cxm + aa) + (long)a.nn1x * rowm;
         cv += wx[aa] * T1[node * 2];
         cd += wx[aa] * T1[node * 2 + 1];
+        cvm += wm[aa] * T1[nodm * 2];
+        cdm += wm[aa] * T1[nodm * 2 + 1];
       }
     Cv[l] = cv;
     Cd[l] = cd;
+    if (l + 32 < ncl) {
+      Cv[m] = cvm;
+      Cd[m] = cdm;
+    }
   }
   __syncthreads();
   // (2) fine traces contracted along x: R[qa + Nq b]
