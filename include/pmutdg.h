@@ -202,7 +202,8 @@ pmdg_status pmdg_set_option(pmdg_solver* h, int option, long value);
  * after the coupling of the first).  Same arithmetic per node either way. */
 #define PMDG_OPT_TIME_BLOCK 9
 /* Two bricks: 1 runs the face work that needs only the primary (PMUT
- * sampling, modal ODE, force, primary interface traces) on a side stream
+ * sampling, modal ODE, force, and the primary's interface traces where the
+ * face kernel rather than the stiffness launch writes them) on a side stream
  * alongside the secondary's stiffness launch; 2 also runs the primary's
  * stiffness launch on that side stream, concurrently with the secondary's;
  * 0 (default) runs every kernel of a step in sequence.  Same results in
