@@ -4,11 +4,13 @@
 // Per step, in stream order:
 //   k_stiff (one launch per brick)  p^{n+1} from p^n with the volume
 //       stiffness, the interface residual of p^n and the PMUT face force of
-//       qddot^n (Sec. 3.1, Algorithm 1 acoustic block, explicit form);
+//       qddot^n (Sec. 3.1, Algorithm 1 acoustic block, explicit form); where
+//       a brick's interface element layer lies in one z chunk, also the
+//       value / normal-derivative traces of p^{n+1} on Gamma_I;
 //   k_face   PMUT sampling of p^{n+1}, modal ODE to level n+1 and the new
 //       face force (Algorithm 1 PMUT block, synchronised with p^{n+1};
-//       eqs. g_m, f_i); receiver traces of p^{n+1}; value / normal-derivative
-//       traces of p^{n+1} on Gamma_I; advances the device step counter;
+//       eqs. g_m, f_i); receiver traces of p^{n+1}; the Gamma_I traces the
+//       stiffness launches do not write;
 //   k_flux   SIPG terms (eq. Wf_2, interface sums) at the Gauss points of the
 //       fine faces (Sec. 5), reduced onto the faces of both sides for the
 //       next k_stiff.
