@@ -77,8 +77,9 @@ typedef struct {
  * operators, the interface quadrature-point list (fine-face Gauss points
  * mapped into the coarse elements, Sec. 5) and dt.  Rejects geometry where
  * the secondary's bottom face is not the primary's top face (EINVAL) and a
- * dt beyond the explicit stability bound of the volume operator
- * (EUNSTABLE).  *out receives the handle (NULL on error). */
+ * dt beyond the explicit stability bound of the volume operator or of the
+ * coupled operator with the interface penalty (EUNSTABLE; see
+ * pmdg_lambda_max).  *out receives the handle (NULL on error). */
 pmdg_status pmdg_create(const pmdg_problem* pr, pmdg_solver** out);
 
 /* PMUTs on the primary's bottom face (Sec. 2, eq. pmut_problem): Np discs
@@ -137,6 +138,19 @@ pmdg_status pmdg_bind(pmdg_solver* h, void* dev_ptr, size_t bytes, void* stream)
 
 /* The time step in use. */
 pmdg_status pmdg_get_dt(pmdg_solver* h, double* dt);
+
+/* Largest eigenvalue of M^{-1} K that pmdg_create checked dt against
+ * (Sec. 3.1: the leapfrog is stable for dt^2 lambda_max < 4).  One brick:
+ * c^2 times the sum of the three 1D operators' largest eigenvalues (exact
+ * for the Kronecker-sum operator).  Two bricks: the larger of that and the
+ * largest eigenvalue of the coupled operator with the interface penalty
+ * gamma_F of Sec. 3, computed by Lanczos iteration on a patch of both bricks
+ * around Gamma_I with the same element sizes, orders, materials and penalty
+ * (laterally the shortest run of coarse elements ending on a fine element
+ * edge, at least three coarse elements where the brick has them; up to three
+ * element layers per side).  pmdg_create rejects dt^2 lambda_max >= 4 / 1.02
+ * for the coupled estimate with PMDG_EUNSTABLE. */
+pmdg_status pmdg_lambda_max(pmdg_solver* h, double* lam);
 
 /* Enqueues n time steps on stream and returns without waiting.  Steps run
  * as captured hipGraphs (replayed in chunks) unless graphs are disabled with

@@ -67,6 +67,7 @@ _SIGS = {
     "pmdg_workspace_size": [_vp, ctypes.POINTER(ctypes.c_size_t)],
     "pmdg_bind": [_vp, _vp, ctypes.c_size_t, _vp],
     "pmdg_get_dt": [_vp, _dp],
+    "pmdg_lambda_max": [_vp, _dp],
     "pmdg_step": [_vp, ctypes.c_int, _vp],
     "pmdg_steps_done": [_vp, ctypes.POINTER(ctypes.c_long)],
     "pmdg_read_traces": [_vp, _dp, _vp],

@@ -168,6 +168,7 @@ struct pmdg_solver {
   int ndom = 1, S = 1, prec = 32;
   long cap = 1;
   double dt = 0;
+  double lam_max = 0;  // largest eigenvalue of M^{-1} K (coupled operator for two bricks)
   Brick b[2];
   // interface
   int Nq = 0;
@@ -397,6 +398,208 @@ static int setup_interface(pmdg_solver* s, std::string& err) {
   for (int c = 0; c < n0; ++c) s->dz0[c] = (double)(2.0L / F.h[2] * F.rule.D[N0 * n0 + c]);
   for (int c = 0; c < n1; ++c) s->dz1[c] = (double)(2.0L / C.h[2] * C.rule.D[0 * n1 + c]);
   return 0;
+}
+
+// ------------------------------------------------------------------------
+// Explicit stability of the coupled operator (Sec. 3.1: the leapfrog needs
+// dt^2 lambda_max(M^{-1} K) < 4).  The SIPG penalty gamma_F of Sec. 3 lifts
+// the largest eigenvalue well above that of either brick's volume operator
+// (a factor of about 1.7 at alpha = 2 and 7 at alpha = 10 for the orders
+// used here).  Those modes live at the element scale next to Gamma_I, so the
+// eigenvalue is computed on a patch of the two bricks with the same element
+// sizes, orders, materials and penalty: laterally the shortest run of coarse
+// elements that ends on a fine element edge, repeated to at least three
+// coarse elements where the brick has them, and up to three element layers
+// on each side of Gamma_I (rigid patch walls).  Lanczos iteration in the
+// M-inner product on the patch operator (volume stiffness by the assembled
+// 1D rows, interface terms of eq. Wf_2 at the fine-face Gauss points).
+// ------------------------------------------------------------------------
+static long bnode(const Brick& B, int i, int j, int k) { return ((long)k * B.nn[1] + j) * B.nn[0] + i; }
+
+// y = M^{-1} K v on the two bricks of s (host tables of setup_brick and
+// setup_interface); v and y hold the primary's nodes, then the secondary's.
+static void coupled_apply(const pmdg_solver* s, const std::vector<double>& v, std::vector<double>& y) {
+  const long off1 = s->b[0].nnodes;
+  std::fill(y.begin(), y.end(), 0.0);
+  std::vector<double> r(y.size(), 0.0);
+  for (int d = 0; d < s->ndom; ++d) {
+    const Brick& B = s->b[d];
+    const int N = B.N, NT = 2 * N;
+    const double c2 = B.c * B.c;
+    const long o = d ? off1 : 0;
+    for (int k = 0; k < B.nn[2]; ++k)
+      for (int j = 0; j < B.nn[1]; ++j)
+        for (int i = 0; i < B.nn[0]; ++i) {
+          const int ix[3] = {i, j, k};
+          const long me = o + bnode(B, i, j, k);
+          double acc = 0;
+          for (int a = 0; a < 3; ++a)
+            for (int t = -N; t <= N; ++t) {
+              if (t == 0 || ix[a] + t < 0 || ix[a] + t >= B.nn[a]) continue;
+              int jx[3] = {i, j, k};
+              jx[a] += t;
+              const int slot = t < 0 ? (t + N) : (N + t - 1);
+              acc += B.tap[a][(size_t)ix[a] * NT + slot] * (v[o + bnode(B, jx[0], jx[1], jx[2])] - v[me]);
+            }
+          y[me] = c2 * acc;
+        }
+  }
+  if (s->ndom < 2) return;
+  const Brick &F = s->b[0], &C = s->b[1];
+  const int N0 = F.N, N1 = C.N, n0 = N0 + 1, n1 = N1 + 1, Nq = s->Nq;
+  const double c0 = F.c * F.c, c1 = C.c * C.c, g = s->gamma;
+  const int kt0 = F.nn[2] - 1;
+  for (int ey = 0; ey < F.ne[1]; ++ey)
+    for (int ex = 0; ex < F.ne[0]; ++ex)
+      for (int qb = 0; qb < Nq; ++qb)
+        for (int qa = 0; qa < Nq; ++qa) {
+          const int px = ex * Nq + qa, py = ey * Nq + qb;
+          const int kx = s->xcx[px], ky = s->ycx[py];
+          const double* wx = &s->xw[(size_t)px * n1];
+          const double* wy = &s->yw[(size_t)py * n1];
+          const double* lx = &s->Lq[qa * n0];
+          const double* ly = &s->Lq[qb * n0];
+          double pp = 0, dp = 0, pm = 0, dm = 0;
+          for (int b = 0; b < n0; ++b)
+            for (int a = 0; a < n0; ++a) {
+              const double w = lx[a] * ly[b];
+              const int i = N0 * ex + a, j = N0 * ey + b;
+              pp += w * v[bnode(F, i, j, kt0)];
+              for (int c = 0; c < n0; ++c) dp += w * s->dz0[c] * v[bnode(F, i, j, kt0 - N0 + c)];
+            }
+          for (int b = 0; b < n1; ++b)
+            for (int a = 0; a < n1; ++a) {
+              const double w = wx[a] * wy[b];
+              const int i = N1 * kx + a, j = N1 * ky + b;
+              pm += w * v[off1 + bnode(C, i, j, 0)];
+              for (int c = 0; c < n1; ++c) dm += w * s->dz1[c] * v[off1 + bnode(C, i, j, c)];
+            }
+          const double W = s->wJ[qb * Nq + qa];
+          const double jump = pp - pm, avg = 0.5 * (c0 * dp + c1 * dm);
+          for (int b = 0; b < n0; ++b)
+            for (int a = 0; a < n0; ++a) {
+              const double w = W * lx[a] * ly[b];
+              const int i = N0 * ex + a, j = N0 * ey + b;
+              r[bnode(F, i, j, kt0)] += w * (g * jump - avg);
+              for (int c = 0; c < n0; ++c) r[bnode(F, i, j, kt0 - N0 + c)] -= w * 0.5 * c0 * jump * s->dz0[c];
+            }
+          for (int b = 0; b < n1; ++b)
+            for (int a = 0; a < n1; ++a) {
+              const double w = W * wx[a] * wy[b];
+              const int i = N1 * kx + a, j = N1 * ky + b;
+              r[off1 + bnode(C, i, j, 0)] += w * (avg - g * jump);
+              for (int c = 0; c < n1; ++c) r[off1 + bnode(C, i, j, c)] -= w * 0.5 * c1 * jump * s->dz1[c];
+            }
+        }
+  for (int d = 0; d < 2; ++d) {
+    const Brick& B = s->b[d];
+    const long o = d ? off1 : 0;
+    for (int k = 0; k < B.nn[2]; ++k)
+      for (int j = 0; j < B.nn[1]; ++j)
+        for (int i = 0; i < B.nn[0]; ++i) {
+          const long me = o + bnode(B, i, j, k);
+          y[me] += r[me] / (B.mass1[0][i] * B.mass1[1][j] * B.mass1[2][k]);
+        }
+  }
+}
+
+// Largest eigenvalue of the symmetric tridiagonal matrix with diagonal al and
+// off-diagonal be, by Sturm-sequence bisection.
+static double tridiag_max_eig(const std::vector<double>& al, const std::vector<double>& be) {
+  const int m = (int)al.size();
+  double lo = INFINITY, hi = -INFINITY;
+  for (int i = 0; i < m; ++i) {
+    const double r = (i > 0 ? std::fabs(be[i - 1]) : 0) + (i + 1 < m ? std::fabs(be[i]) : 0);
+    lo = std::min(lo, al[i] - r);
+    hi = std::max(hi, al[i] + r);
+  }
+  auto count_above = [&](double x) {  // eigenvalues > x
+    int n = 0;
+    double q = 1;
+    for (int i = 0; i < m; ++i) {
+      q = al[i] - x - (i > 0 ? be[i - 1] * be[i - 1] / q : 0.0);
+      if (q == 0) q = -1e-300;
+      if (q > 0) ++n;
+    }
+    return n;
+  };
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * std::fabs(hi); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (count_above(mid) > 0) lo = mid; else hi = mid;
+  }
+  return hi;
+}
+
+static double patch_lambda_max(const pmdg_solver* s, std::string& err) {
+  const Brick &F = s->b[0], &C = s->b[1];
+  pmdg_solver P;
+  P.pr = s->pr;
+  P.ndom = 2;
+  pmdg_brick pf = s->pr.dom[0], pc = s->pr.dom[1];
+  for (int a = 0; a < 2; ++a) {
+    const int nec = C.ne[a];
+    int kc = nec;
+    for (int k = 1; k <= nec; ++k) {
+      const double r = k * C.h[a] / F.h[a];
+      if (std::fabs(r - std::round(r)) <= 1e-9 * r) { kc = k; break; }
+    }
+    const int rep = std::max(1, std::min((3 + kc - 1) / kc, nec / kc));
+    kc *= rep;
+    const int kf = kc == nec ? F.ne[a] : (int)std::lround(kc * C.h[a] / F.h[a]);
+    pf.ne[a] = kf;
+    pf.x1[a] = F.x0[a] + kf * F.h[a];
+    pc.ne[a] = kc;
+    pc.x1[a] = C.x0[a] + kc * C.h[a];
+  }
+  const double ztop = F.x0[2] + F.ne[2] * F.h[2];
+  pf.ne[2] = std::min(F.ne[2], 3);
+  pf.x0[2] = ztop - pf.ne[2] * F.h[2];
+  pf.x1[2] = ztop;
+  pc.ne[2] = std::min(C.ne[2], 3);
+  pc.x0[2] = ztop;
+  pc.x1[2] = ztop + pc.ne[2] * C.h[2];
+  if (setup_brick(P.b[0], pf, err) || setup_brick(P.b[1], pc, err) || setup_interface(&P, err)) return -1;
+  const long n = P.b[0].nnodes + P.b[1].nnodes;
+  std::vector<double> mass(n);
+  for (int d = 0; d < 2; ++d) {
+    const Brick& B = P.b[d];
+    const long o = d ? P.b[0].nnodes : 0;
+    for (int k = 0; k < B.nn[2]; ++k)
+      for (int j = 0; j < B.nn[1]; ++j)
+        for (int i = 0; i < B.nn[0]; ++i) mass[o + bnode(B, i, j, k)] = B.mass1[0][i] * B.mass1[1][j] * B.mass1[2][k];
+  }
+  auto dotm = [&](const std::vector<double>& a, const std::vector<double>& b) {
+    double acc = 0;
+    for (long i = 0; i < n; ++i) acc += mass[i] * a[i] * b[i];
+    return acc;
+  };
+  const int m = (int)std::min<long>(60, n);
+  std::vector<std::vector<double>> Q;
+  std::vector<double> al, be, w(n), q(n);
+  uint64_t st = 0x9E3779B97F4A7C15ull;
+  for (long i = 0; i < n; ++i) {
+    st = st * 6364136223846793005ull + 1442695040888963407ull;
+    q[i] = (double)(st >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+  }
+  double nq = std::sqrt(dotm(q, q));
+  for (long i = 0; i < n; ++i) q[i] /= nq;
+  Q.push_back(q);
+  for (int j = 0; j < m; ++j) {
+    coupled_apply(&P, Q[j], w);
+    al.push_back(dotm(w, Q[j]));
+    for (int pass = 0; pass < 2; ++pass)  // full reorthogonalisation, twice
+      for (const auto& qi : Q) {
+        const double h = dotm(w, qi);
+        for (long i = 0; i < n; ++i) w[i] -= h * qi[i];
+      }
+    const double b = std::sqrt(dotm(w, w));
+    if (j + 1 == m || !(b > 1e-12 * std::fabs(al.back()))) break;
+    be.push_back(b);
+    for (long i = 0; i < n; ++i) w[i] /= b;
+    Q.push_back(w);
+  }
+  be.resize(al.size() > 0 ? al.size() - 1 : 0);
+  return tridiag_max_eig(al, be);
 }
 
 // ------------------------------------------------------------------------
@@ -1153,13 +1356,31 @@ pmdg_status pmdg_create(const pmdg_problem* pr, pmdg_solver** out) {
     }
     s->dt = best;
   }
-  // explicit stability of the volume operator: dt^2 lambda_max < 4
+  // explicit stability, dt^2 lambda_max < 4: the volume operator of each
+  // brick (exact: the Kronecker sum of the 1D operators), then the coupled
+  // operator with the interface penalty (patch estimate, with a 2% margin for
+  // the difference between the patch and the whole bricks)
   for (int d = 0; d < s->ndom; ++d) {
     const Brick& B = s->b[d];
     const double lam = B.c * B.c * (B.lam1[0] + B.lam1[1] + B.lam1[2]);
+    s->lam_max = std::max(s->lam_max, lam);
     if (s->dt * s->dt * lam >= 4.0) {
       delete s;
       return fail(PMDG_EUNSTABLE, "dt exceeds the explicit stability bound of brick " + std::to_string(d));
+    }
+  }
+  if (s->ndom == 2) {
+    const double lam = patch_lambda_max(s, err);
+    if (!(lam > 0)) {
+      delete s;
+      return fail(PMDG_EINVAL, "coupled stability estimate failed: " + err);
+    }
+    s->lam_max = std::max(s->lam_max, lam);
+    if (s->dt * s->dt * lam * 1.02 >= 4.0) {
+      const double r = s->dt * s->dt * lam;
+      delete s;
+      return fail(PMDG_EUNSTABLE, "dt^2 lambda_max of the coupled operator is " + std::to_string(r) +
+                                      " (>= 4 / 1.02): reduce cfl or penalty_alpha");
     }
   }
   s->amp.assign(s->S, 0.0);
@@ -1381,6 +1602,12 @@ pmdg_status pmdg_bind(pmdg_solver* s, void* dev_ptr, size_t bytes, void* stream)
 pmdg_status pmdg_get_dt(pmdg_solver* s, double* dt) {
   if (!s || !dt) return fail(PMDG_EINVAL, "NULL argument");
   *dt = s->dt;
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_lambda_max(pmdg_solver* s, double* lam) {
+  if (!s || !lam) return fail(PMDG_EINVAL, "NULL argument");
+  *lam = s->lam_max;
   return PMDG_OK;
 }
 

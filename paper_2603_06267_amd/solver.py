@@ -89,6 +89,11 @@ class Solver:
         check(self.L.pmdg_get_dt(self.h, ctypes.byref(v)))
         return v.value
 
+    def lambda_max(self):
+        v = ctypes.c_double()
+        check(self.L.pmdg_lambda_max(self.h, ctypes.byref(v)))
+        return v.value
+
     def num_nodes(self):
         n = ctypes.c_long()
         check(self.L.pmdg_num_nodes(self.h, ctypes.byref(n)))

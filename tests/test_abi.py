@@ -110,6 +110,35 @@ def test_dt_and_pmut_nodes_match_oracle():
         assert np.abs(xyz - o.coords()).max() < 1e-13
 
 
+@pytest.mark.parametrize("nested", [True, False])
+def test_coupled_stability_check(nested):
+    """The interface penalty gamma_F (Sec. 3) raises lambda_max(M^-1 K) above
+    either brick's volume operator: pmdg_create checks dt^2 lambda_max < 4
+    (Sec. 3.1) on the coupled operator.  The library's patch estimate agrees
+    with the oracle's power iteration over the whole coupled operator of the
+    small two-domain mesh (nested 2:1 and non-nested 4:3), alpha = 2 is
+    accepted at CFL 0.3 and alpha = 10 (dt^2 lambda_max about 11) rejected."""
+    doms = W.small_two_domain(nested=nested)["domains"]
+    s = solver.Solver(doms, 0.3, 0.0, 2.0)
+    o = ref.RefSolver(doms, alpha=2.0)
+    lo = o.lambda_max(iters=1500)
+    lam = s.lambda_max()
+    # power iteration approaches from below; the estimate is the patch's
+    assert lo * 0.999 <= lam <= lo * 1.003, (lam, lo)
+    # the penalty matters: well above either brick's volume operator alone
+    vol = max(ref.RefSolver([d]).lambda_max(iters=400) for d in doms)
+    assert lam > 1.5 * vol
+    assert s.dt ** 2 * lam < 4.0
+    assert _err(solver.Solver, doms, 0.3, 0.0, 10.0) == _lib.PMDG_EUNSTABLE
+    assert _err(solver.Solver, doms, 0.3, 0.0, 5.0) == _lib.PMDG_EUNSTABLE
+    # the same penalty with a time step inside the bound is accepted
+    big = solver.Solver(doms, 0.1, 0.0, 10.0)
+    assert big.dt ** 2 * big.lambda_max() < 4.0
+    # one brick: the Kronecker sum of the 1D operators
+    one = solver.Solver([doms[0]])
+    assert abs(one.lambda_max() - ref.RefSolver([doms[0]]).lambda_max(iters=2000)) <= 1e-3 * one.lambda_max()
+
+
 def test_workspace_grows_with_scenarios():
     wl = W.config1()
     a = solver.Solver(wl["domains"], n_scenarios=1, trace_capacity=8)
