@@ -52,6 +52,57 @@ def measured_traffic(rows, zchunk):
     return float(fields["traffic_bytes_per_step"])
 
 
+GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
+
+
+def golden_traces(config, wl):
+    """FP64 oracle traces of a workload stored by tests/golden/make_traces.py
+    (written by the oracle on the host), or None when absent or when they
+    belong to other inputs."""
+    from paper_2603_06267_amd import workloads as W
+    path = os.path.join(GOLDEN_DIR, f"config{config}_traces.npz")
+    if not os.path.exists(path):
+        return None
+    z = np.load(path)
+    if str(z["key"]) != W.workload_key(wl):
+        return None
+    return z["traces"]
+
+
+def trace_error(tg, to):
+    """Relative L2 of GPU traces [R x n] against the oracle's over their
+    common steps: all receivers together, and the largest receiver by
+    receiver (each against max(its norm, 1% of the loudest))."""
+    if to is None:
+        return None
+    n = min(tg.shape[-1], to.shape[-1])
+    a, b = tg[:, :n], to[:, :n]
+    nr = np.linalg.norm(b, axis=1)
+    per = np.linalg.norm(a - b, axis=1) / np.maximum(nr, 0.01 * nr.max())
+    return {"rel_l2": float(np.linalg.norm(a - b) / np.linalg.norm(b)), "per_receiver_max": float(per.max()),
+            "steps": int(n)}
+
+
+def trace_leg():
+    """The large-array workload over its full 5,000 steps in the benchmark's
+    launch configuration, FP32 and FP64, against the stored oracle traces."""
+    import torch
+    from paper_2603_06267_amd import solver, workloads as W
+    wl = W.config3()
+    to = golden_traces(3, wl)
+    if to is None:
+        return None
+    out = {"reference": "FP64 CPU oracle, tests/golden/config3_traces.npz", "steps": int(to.shape[1])}
+    for prec in (32, 64):
+        g = solver.from_workload(wl, precision=prec, n_steps=to.shape[1], shape_fn=W.shape_fn(wl),
+                                 device="cuda:0")
+        g.step(to.shape[1])
+        torch.cuda.synchronize()
+        out[f"fp{prec}"] = trace_error(g.read_traces()[0], to)
+        g.close()
+    return out
+
+
 def cpu_baseline(wl, steps):
     """The FP64 oracle, as it stands, on a bounded sample of the same workload
     (the first `steps` steps of config 3), on all host cores."""
@@ -104,6 +155,7 @@ def run_gpu(wl, precision, steps, warmup, graphs, rows, zchunk, tblock=1):
     el_graph = time.perf_counter() - t1
     tr = gg.read_traces()
     finite = bool(np.isfinite(tr).all()) and not gg.nonfinite()
+    run_gpu.traces = tr
     return el, el_graph, kt, finite
 
 
@@ -121,8 +173,10 @@ def scenarios_leg(steps, warmup, rows, zchunk, S=4):
     phase = np.stack([2 * math.pi * f * ctr[:, 0] * math.sin(math.radians(a)) / W.C_WATER for a in angles])
     wl["drive"] = dict(wl["drive"], amp=np.ones((S, len(ctr))), phase=phase, freq=np.full(S, f))
     el, el_graph, kt, finite = run_gpu(wl, 32, steps, warmup, True, rows, zchunk)
+    err = trace_error(run_gpu.traces[0], golden_traces(3, W.config3()))
     dofs = W.unique_dofs(wl)
-    return {"scenarios": S, "value": S * dofs * steps / min(el, el_graph), "unit": "DOF-updates/s",
+    return {"scenarios": S, "trace_error_scenario0": err,
+            "value": S * dofs * steps / min(el, el_graph), "unit": "DOF-updates/s",
             "ms_per_step": min(el, el_graph) * 1e3 / steps, "stiff_ms": kt[0],
             "achieved_GBs": 12.0 * S * dofs / (kt[0] * 1e-3) / 1e9,
             "frac": 12.0 * S * dofs / (kt[0] * 1e-3) / 1e9 / PEAK_HBM_GBS, "finite": finite}
@@ -134,13 +188,15 @@ def small_configs_leg(steps=400, warmup=20):
     launches, reported as rates only."""
     from paper_2603_06267_amd import workloads as W
     out = {}
-    for name, wl in (("config1", W.config1()), ("config2", W.config2())):
+    for cfg, name, wl in ((1, "config1", W.config1()), (2, "config2", W.config2())):
         wl = dict(wl, steps=steps + warmup)
         dofs = W.unique_dofs(wl)
+        to = golden_traces(cfg, wl)
         for prec in (32, 64):
             el, el_graph, kt, finite = run_gpu(wl, prec, steps, warmup, True, 2, -1)  # automatic z chunks
             out[f"{name}_fp{prec}"] = {"unique_dofs": dofs, "value": dofs * steps / min(el, el_graph),
-                                       "ms_per_step": min(el, el_graph) * 1e3 / steps, "finite": finite}
+                                       "ms_per_step": min(el, el_graph) * 1e3 / steps, "finite": finite,
+                                       "trace_error": trace_error(run_gpu.traces[0], to)}
     return out
 
 
@@ -164,6 +220,8 @@ def batched_leg(steps=512):
     b.step(steps - 8)
     torch.cuda.synchronize()
     el = time.perf_counter() - t
+    err = {"scenario0": trace_error(b.solvers[0].read_traces()[0], golden_traces("4base", wls[0])),
+           "mesh15": trace_error(b.solvers[16].read_traces()[0], golden_traces("4mesh15", wls[16]))}
     nsc = sum(len(w["drive"]["amp"]) for w in wls)
     singles = []
     for w, sf in zip(wls, sfs):
@@ -180,7 +238,7 @@ def batched_leg(steps=512):
     frac = (steps - 8) / steps
     return {"workload": "64 scenarios (cube, 4x4 PMUTs, 3 modes) + 16 meshes 8x8x4..24x24x8 N=3..6, 512 steps",
             "scenarios": nsc, "batched_scenarios_per_s": nsc * frac / el, "loop_scenarios_per_s": nsc * frac / el2,
-            "speedup": el2 / el, "setup_and_tuning_s": setup, "tiles": {k: v["best"] for k, v in tuner.cache.items()}}
+            "speedup": el2 / el, "trace_error": err, "setup_and_tuning_s": setup, "tiles": {k: v["best"] for k, v in tuner.cache.items()}}
 
 
 def surrogate_leg(runs, steps, log, batch=256, lr=1e-3):
@@ -273,6 +331,8 @@ def main():
     ap.add_argument("--no-scenarios", action="store_true",
                     help="skip the large-array leg with 4 drive scenarios in one solver")
     ap.add_argument("--no-small", action="store_true", help="skip the small-workload rates")
+    ap.add_argument("--no-trace", action="store_true",
+                    help="skip the full 5,000-step large-array runs compared with the oracle's traces")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-form leg")
     ap.add_argument("--surrogate-runs", type=int, default=4096)
     ap.add_argument("--surrogate-steps", type=int, default=3000)
@@ -300,6 +360,7 @@ def main():
                                        args.tblock)
     log(f"  timed (events): {el * 1e3 / args.steps:.4f} ms/step; graph replay: {el_graph * 1e3 / args.steps:.4f} "
         f"ms/step; kernels ms: stiff {kt[0]:.4f} face {kt[1]:.4f} flux {kt[2]:.4f}")
+    main_err = trace_error(run_gpu.traces[0], golden_traces(3, W.config3()))
     best = min(el, el_graph)
     value = dofs * args.steps / best
     # algorithmic bytes per step of the stiffness launches (both bricks): read
@@ -333,13 +394,18 @@ def main():
                      "moved_GBs": None if traffic is None else traffic / (kt[0] * 1e-3) / 1e9},
         "kernel_ms": {"stiff": kt[0], "face": kt[1], "flux": kt[2]},
         "finite": finite,
+        "trace_error": main_err,
     }
     if not args.no_fp64:
         log("FP64 instantiation ...")
         el64, elg64, kt64, fin64 = run_gpu(wl, 64, args.steps, args.warmup, not args.direct, 1, args.zchunk)
         out["fp64"] = {"value": dofs * args.steps / min(el64, elg64), "unit": "DOF-updates/s",
+                       "trace_error": trace_error(run_gpu.traces[0], golden_traces(3, W.config3())),
                        "stiff_ms": kt64[0], "achieved_GBs": 24.0 * (n0 + n1) / (kt64[0] * 1e-3) / 1e9,
                        "frac": 24.0 * (n0 + n1) / (kt64[0] * 1e-3) / 1e9 / PEAK_HBM_GBS}
+    if not args.no_trace:
+        log("large array, full run against the oracle's traces ...")
+        out["trace_rel_l2"] = trace_leg()
     if not args.no_scenarios:
         log("large array x 4 scenarios ...")
         out["scenarios4"] = scenarios_leg(min(args.steps, 200), args.warmup, args.rows, args.zchunk)

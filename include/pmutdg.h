@@ -172,7 +172,10 @@ pmdg_status pmdg_read_modal(pmdg_solver* h, int s, double* q, double* qd, double
 /* Field state of scenario s: pressure at the current and the previous time
  * level, [n_nodes] each, nodes of the primary then of the secondary, x
  * fastest.  set_state also sets the modal state (NULL: zero) and the step
- * counter, and recomputes the face force and interface terms. */
+ * counter, and recomputes the face force and interface terms.  The
+ * scenarios of a solver share the step counter: with S > 1, nstep must equal
+ * the steps done (PMDG_ESTATE otherwise), so the other scenarios keep their
+ * state and traces. */
 pmdg_status pmdg_num_nodes(pmdg_solver* h, long* n);
 pmdg_status pmdg_get_state(pmdg_solver* h, int s, double* p, double* p_prev, void* stream);
 pmdg_status pmdg_set_state(pmdg_solver* h, int s, const double* p, const double* p_prev, const double* q,
@@ -245,7 +248,11 @@ void pmdg_destroy(pmdg_solver* h);
 typedef struct pmdg_batch pmdg_batch;
 
 /* solvers[n]: bound, ndom == 1, precision 32, tile rows 1 or 2; the batch
- * does not own them and they must outlive it.  EINVAL / ESTATE otherwise. */
+ * does not own them and they must outlive it.  EINVAL / ESTATE otherwise.
+ * The batch fixes each solver's tile and kernel arguments here: until
+ * pmdg_batch_destroy, pmdg_set_option on a member solver accepts only
+ * PMDG_OPT_GRAPH, PMDG_OPT_GRAPH_CHUNK and PMDG_OPT_TIMING (PMDG_ESTATE for
+ * the others). */
 pmdg_status pmdg_batch_create(int n, pmdg_solver* const* solvers, pmdg_batch** out);
 /* Device bytes for the work lists and argument blocks. */
 pmdg_status pmdg_batch_workspace_size(pmdg_batch* b, size_t* bytes);

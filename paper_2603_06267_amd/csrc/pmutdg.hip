@@ -205,6 +205,7 @@ struct pmdg_solver {
   int tblock = 1;               // steps per stiffness pass of the primary (1, or 2 for FP32)
   int tblock1 = 0;              // same for the secondary (0: as the primary)
   int overlap = 0;              // PMUT face work alongside the secondary's stiffness
+  int batches = 0;              // batches holding this solver (their tile layout is fixed)
   std::map<int, hipGraphExec_t> graphs;
   hipStream_t cap_stream = nullptr;
   // side stream and events for running the PMUT part of the face kernel
@@ -1635,6 +1636,8 @@ pmdg_status pmdg_node_coords(pmdg_solver* s, double* xyz) {
 
 pmdg_status pmdg_set_option(pmdg_solver* s, int option, long value) {
   if (!s) return fail(PMDG_EINVAL, "NULL solver");
+  if (s->batches > 0 && option != PMDG_OPT_GRAPH && option != PMDG_OPT_GRAPH_CHUNK && option != PMDG_OPT_TIMING)
+    return fail(PMDG_ESTATE, "the solver is held by a batch, whose tile layout was fixed at pmdg_batch_create");
   switch (option) {
     case PMDG_OPT_GRAPH: s->use_graph = value ? 1 : 0; break;
     case PMDG_OPT_TILE_ROWS:
@@ -1799,6 +1802,11 @@ pmdg_status pmdg_set_state(pmdg_solver* s, int sc, const double* p, const double
   if (!s->bound) return fail(PMDG_ESTATE, "not bound");
   if (sc < 0 || sc >= s->S) return fail(PMDG_EINVAL, "scenario out of range");
   if (nstep < 0 || (s->R > 0 && nstep > s->cap)) return fail(PMDG_EINVAL, "nstep out of range");
+  // the S scenarios share one step counter, which also selects their state
+  // buffers: with several scenarios only the current step can be set
+  if (s->S > 1 && nstep != s->steps_done)
+    return fail(PMDG_ESTATE, "with several scenarios nstep must equal the steps done (" +
+                                 std::to_string(s->steps_done) + ")");
   return s->prec == 64 ? set_state_t<double>(s, sc, p, p_prev, q, qd, qdd, nstep, (hipStream_t)stream)
                        : set_state_t<float>(s, sc, p, p_prev, q, qd, qdd, nstep, (hipStream_t)stream);
 }
@@ -1839,6 +1847,10 @@ struct pmdg_batch {
   int use_graph = 1, graph_chunk = 64;
   std::map<int, hipGraphExec_t> graphs;
   hipStream_t cap_stream = nullptr;
+  // kernel arguments of every solver, fixed at create together with the
+  // layout, item counts and LDS size they imply
+  std::vector<StiffArgs<float>> sa;
+  std::vector<FaceArgs<float>> fa;
 };
 
 static size_t al256(size_t x) { return (x + 255) / 256 * 256; }
@@ -1882,10 +1894,13 @@ pmdg_status pmdg_batch_create(int n, pmdg_solver* const* solvers, pmdg_batch** o
     b->nmax = std::max(b->nmax, s->b[0].N);
     b->nm_max = std::max(b->nm_max, s->Nm);
     b->lds = std::max(b->lds, batch_lds_bytes(s->b[0].N, rows));
-    b->n_stiff += stiff_args<float>(s, 0).nblocks;
-    b->n_face += face_args<float>(s, 0).nblocks;
+    b->sa.push_back(stiff_args<float>(s, 0));
+    b->fa.push_back(face_args<float>(s, 0));
+    b->n_stiff += b->sa.back().nblocks;
+    b->n_face += b->fa.back().nblocks;
   }
   batch_layout(b);
+  for (pmdg_solver* s : b->sv) ++s->batches;
   *out = b;
   return PMDG_OK;
 }
@@ -1903,18 +1918,18 @@ pmdg_status pmdg_batch_bind(pmdg_batch* b, void* dev_ptr, size_t bytes, void* st
   if (bytes < b->bytes) return fail(PMDG_ENOMEM, "batch workspace too small: need " + std::to_string(b->bytes));
   hipStream_t st = (hipStream_t)stream;
   b->ws = (char*)dev_ptr;
-  std::vector<StiffArgs<float>> sa;
-  std::vector<FaceArgs<float>> fa;
+  const std::vector<StiffArgs<float>>& sa = b->sa;
+  const std::vector<FaceArgs<float>>& fa = b->fa;
   std::vector<int2> si, fi;
   std::vector<long*> ctr;
   for (size_t p = 0; p < b->sv.size(); ++p) {
     pmdg_solver* s = b->sv[p];
-    sa.push_back(stiff_args<float>(s, 0));
-    fa.push_back(face_args<float>(s, 0));
-    for (int t = 0; t < sa.back().nblocks; ++t) si.push_back(make_int2((int)p, t));
-    for (int t = 0; t < fa.back().nblocks; ++t) fi.push_back(make_int2((int)p, t));
+    for (int t = 0; t < sa[p].nblocks; ++t) si.push_back(make_int2((int)p, t));
+    for (int t = 0; t < fa[p].nblocks; ++t) fi.push_back(make_int2((int)p, t));
     ctr.push_back(dptr<long>(s, "ctl"));
   }
+  if ((int)si.size() != b->n_stiff || (int)fi.size() != b->n_face)
+    return fail(PMDG_EINVAL, "internal: batch item counts differ from the layout");
   HIPCHK(hipMemcpyAsync(b->ws + b->off_sargs, sa.data(), sa.size() * sizeof(sa[0]), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(b->ws + b->off_fargs, fa.data(), fa.size() * sizeof(fa[0]), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(b->ws + b->off_sitems, si.data(), si.size() * sizeof(int2), hipMemcpyHostToDevice, st));
@@ -1984,6 +1999,7 @@ pmdg_status pmdg_batch_step(pmdg_batch* b, int n, void* stream) {
 
 void pmdg_batch_destroy(pmdg_batch* b) {
   if (!b) return;
+  for (pmdg_solver* s : b->sv) --s->batches;
   for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   delete b;

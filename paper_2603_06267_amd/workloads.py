@@ -13,6 +13,8 @@ amplitudes are in arbitrary consistent units (the problem is linear).
 
 Seeds: NumPy PCG64 `default_rng(20260306 + index)`.
 """
+import hashlib
+import json
 import math
 
 import numpy as np
@@ -244,3 +246,20 @@ def element_local_dofs(wl):
     for d in wl["domains"]:
         n += int(np.prod(d["ne"])) * (d["N"] + 1) ** 3
     return n
+
+
+def workload_key(wl):
+    """SHA-256 over every input array of a single-mesh workload description
+    (bricks, PMUT data, drive, receivers): stored results computed from a
+    workload carry it, so a changed generator is noticed."""
+    h = hashlib.sha256()
+    h.update(json.dumps(wl["domains"], sort_keys=True).encode())
+    h.update(json.dumps([wl.get("cfl"), wl.get("alpha")]).encode())
+    for k in ("centers", "radius", "omega", "zeta", "eta", "scale"):
+        h.update(np.ascontiguousarray(wl["pmuts"][k], dtype=np.float64).tobytes())
+    dr = wl["drive"]
+    for k in ("amp", "phase", "freq"):
+        h.update(np.ascontiguousarray(dr[k], dtype=np.float64).tobytes())
+    h.update(json.dumps([dr["ncyc"], dr.get("envelope", 0)]).encode())
+    h.update(np.ascontiguousarray(wl["receivers"], dtype=np.float64).tobytes())
+    return h.hexdigest()

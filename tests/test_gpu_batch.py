@@ -74,3 +74,26 @@ def test_tuner_choice_valid_and_cached(tmp_path):
     assert best in [(1, 9), (2, 17)]
     t2 = B.TileTuner(path=str(tmp_path / "tiles.json"))
     assert t2.tune(dom, S=1) == best
+
+
+def test_batch_fixes_member_tile_options():
+    """A batch fixes its solvers' tiles and kernel arguments when it is
+    created: tile options of a member are refused until the batch is
+    destroyed; graph and timing options stay open."""
+    from paper_2603_06267_amd import _lib
+    steps = 20
+    wls = _workloads(steps, nscen=2, mesh_ids=(1,))
+    sfs = [W.shape_fn(w) for w in wls]
+    b = B.build_batch(wls, shape_fns=sfs, n_steps=steps)
+    s0 = b.solvers[0]
+    for opt, val in ((_lib.OPT_TILE_ROWS, 2), (_lib.OPT_TILE_ZCHUNK, 5), (_lib.OPT_TILE_WAVES, 8),
+                     (_lib.OPT_PREFETCH, 3), (_lib.OPT_TIME_BLOCK, 2)):
+        with pytest.raises(_lib.PmdgError) as e:
+            s0.set_option(opt, val)
+        assert e.value.code == _lib.PMDG_ESTATE
+    s0.set_option(_lib.OPT_TIMING, 0)
+    b.step(steps)
+    tr = s0.read_traces()
+    assert np.isfinite(tr).all()
+    b.close()
+    s0.set_option(_lib.OPT_TILE_ROWS, 2)

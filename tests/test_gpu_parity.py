@@ -20,6 +20,25 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def per_receiver_max(tg, to, floor=0.01):
+    """Largest relative L2 over receivers, each receiver's error measured
+    against max(its own trace norm, floor x the loudest receiver's norm)."""
+    tg = np.asarray(tg).reshape(-1, tg.shape[-1])
+    to = np.asarray(to).reshape(-1, to.shape[-1])
+    nr = np.linalg.norm(to, axis=1)
+    return float((np.linalg.norm(tg - to, axis=1) / np.maximum(nr, floor * nr.max())).max())
+
+
+def check_traces(tg, to, precision, label):
+    """Global and receiver-by-receiver relative L2 within the tolerance."""
+    err = rel_l2(tg, to)
+    pr = per_receiver_max(tg, to)
+    _say(f"  {label}: rel L2 {err:.3e}, per receiver max {pr:.3e}")
+    assert err <= TOL[precision]
+    assert pr <= TOL[precision]
+    return err
+
+
 def _say(msg):
     print(msg, flush=True)
     sys.stdout.flush()
@@ -44,9 +63,7 @@ def test_config1_cube_single_pmut(precision):
     tg, to, g, o = run_pair(wl, precision)
     assert abs(g.dt - o.dt) < 1e-15 * o.dt
     assert np.abs(to).max() > 0
-    err = rel_l2(tg, to)
-    _say(f"  rel L2 {err:.3e}")
-    assert err <= TOL[precision]
+    check_traces(tg, to, precision, "config1")
     # modal state agrees as well
     q, qd, qdd = g.read_modal()
     st = o.get_state()
@@ -61,9 +78,7 @@ def test_small_two_domain(precision, nested):
     _say(f"small two-domain nested={nested} precision={precision}")
     wl = W.small_two_domain(nested, steps=400)
     tg, to, g, o = run_pair(wl, precision)
-    err = rel_l2(tg, to)
-    _say(f"  rel L2 {err:.3e}")
-    assert err <= TOL[precision]
+    check_traces(tg, to, precision, "small two-domain")
 
 
 @pytest.mark.parametrize("precision", [32, 64])
@@ -71,9 +86,7 @@ def test_config2_two_domain_array(precision):
     _say(f"config2 precision={precision} (2000 steps)")
     wl = W.config2()
     tg, to, g, o = run_pair(wl, precision)
-    err = rel_l2(tg, to)
-    _say(f"  rel L2 {err:.3e}")
-    assert err <= TOL[precision]
+    check_traces(tg, to, precision, "config2")
 
 
 @pytest.mark.parametrize("precision", [32, 64])
@@ -85,9 +98,7 @@ def test_absorbing_faces_cube(precision):
     wl = dict(wl, domains=[dict(wl["domains"][0], absorbing=0b101111)], steps=400)
     _say(f"absorbing cube precision={precision}")
     tg, to, g, o = run_pair(wl, precision)
-    err = rel_l2(tg, to)
-    _say(f"  rel L2 {err:.3e}")
-    assert err <= TOL[precision]
+    check_traces(tg, to, precision, "absorbing cube")
     with pytest.raises(Exception):
         g.set_absorbing(0, 1)
 
@@ -100,9 +111,7 @@ def test_absorbing_faces_two_domain(precision):
     prim, sec = wl["domains"]
     wl = dict(wl, domains=[dict(prim, absorbing=0b001111), dict(sec, absorbing=0b101111)])
     tg, to, g, o = run_pair(wl, precision)
-    err = rel_l2(tg, to)
-    _say(f"  absorbing two-domain precision={precision}: rel L2 {err:.3e}")
-    assert err <= TOL[precision]
+    check_traces(tg, to, precision, f"absorbing two-domain precision={precision}")
 
 
 def test_graph_replay_equals_direct_launches():
@@ -240,15 +249,15 @@ def _smooth_field(xyz, seed):
 @pytest.mark.parametrize("precision", [32, 64])
 def test_config3_full_size_one_step(precision):
     """Full-size config 3 (32.8M nodes, 1024 PMUTs, 4:3 interface) in the
-    launch configuration the benchmark times: one step from a smooth state
-    with non-zero modal accelerations, against the oracle's explicit update
-    p^{n+1} = 2 p^n - p^{n-1} + dt^2 M^{-1} (f(qdd^n) - K p^n) at every node."""
+    launch configuration the benchmark times (automatic tile rows and z
+    chunks, hipGraph replay): one step from a smooth state with non-zero
+    modal accelerations, against the oracle's explicit update
+    p^{n+1} = 2 p^n - p^{n-1} + dt^2 M^{-1} (f(qdd^n) - K p^n) at every node,
+    relative to the largest change of p over the step."""
     _say(f"config3 one step precision={precision}")
     wl = W.config3(steps=4)
     sf = W.shape_fn(wl)
-    g = solver.from_workload(wl, precision=precision, n_steps=4, shape_fn=sf, bind=False)
-    g.set_option(2, 2)
-    g.bind()
+    g = solver.from_workload(wl, precision=precision, n_steps=4, shape_fn=sf)
     xyz = g.node_coords()
     p = _smooth_field(xyz, 1)
     pp = p - 0.05 * _smooth_field(xyz, 2)
@@ -256,7 +265,6 @@ def test_config3_full_size_one_step(precision):
     nm = g.Np * g.Nm
     qdd = rng.standard_normal(nm)
     g.set_state(0, p, pp, np.zeros(nm), np.zeros(nm), qdd, nstep=0)
-    g.set_option(1, 0)
     g.step(1)
     pn, _ = g.get_state(0)
     del xyz
@@ -274,7 +282,7 @@ def test_config3_full_size_one_step(precision):
     scale = np.abs(expect - p).max()
     err = np.abs(d).max() / scale
     _say(f"  max |diff| / max |p^(n+1) - p^n| = {err:.3e}")
-    assert err < (2e-4 if precision == 32 else 1e-10)
+    assert err < (1e-5 if precision == 32 else 1e-10)
 
 
 @pytest.mark.parametrize("case", ["cube", "nested", "4to3"])
