@@ -136,6 +136,20 @@ pmdg_status pmdg_workspace_size(pmdg_solver* h, size_t* bytes);
  * keeps the memory alive until pmdg_destroy.  Binding twice: ESTATE. */
 pmdg_status pmdg_bind(pmdg_solver* h, void* dev_ptr, size_t bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under graph
+ * capture, serving loops, harnesses that forbid hipMalloc): pmdg_bind with
+ * a workspace the library holds, one static device array of 32 MiB per GPU
+ * (kept until the process ends), instead of caller memory.  Same tables,
+ * kernels and results as pmdg_bind on the current device; zeroes the state
+ * like pmdg_bind.  It allocates nothing: no hipMalloc, no library routine
+ * that allocates.  PMDG_ENOMEM if the solver needs more than 32 MiB
+ * (pmdg_workspace_size tells).  One array per device: the solver bound last
+ * owns it; calls on a solver whose array was since bound to another solver
+ * return PMDG_ESTATE (step, read and state calls, set_drive, batching), and
+ * pmdg_destroy of the owner frees the array for the next bind.  Calls that
+ * overlap on one GPU race on the array. */
+pmdg_status pmdg_bind_static(pmdg_solver* h, void* stream);
+
 /* The time step in use. */
 pmdg_status pmdg_get_dt(pmdg_solver* h, double* dt);
 

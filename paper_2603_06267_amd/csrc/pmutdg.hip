@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -206,6 +207,7 @@ struct pmdg_solver {
   int tblock1 = 0;              // same for the secondary (0: as the primary)
   int overlap = 0;              // PMUT face work alongside the secondary's stiffness
   int batches = 0;              // batches holding this solver (their tile layout is fixed)
+  int static_dev = -1;          // device whose library-held workspace this solver is bound to, or -1
   std::map<int, hipGraphExec_t> graphs;
   hipStream_t cap_stream = nullptr;
   // side stream and events for running the PMUT part of the face kernel
@@ -1312,6 +1314,29 @@ static pmdg_status set_state_t(pmdg_solver* s, int sc, const double* p, const do
 // ------------------------------------------------------------------------
 // ABI
 // ------------------------------------------------------------------------
+// ------------------------------------------------------------------------
+// Library-held workspace (pmdg_bind_static): one static device array per
+// GPU, for callers that cannot allocate device memory.  Host code never
+// passes the array's name to a kernel or a copy: the device address is
+// looked up once per device with hipGetSymbolAddress and kept here.  The
+// solver last bound to a device's array owns it; the others are refused.
+// ------------------------------------------------------------------------
+constexpr size_t kScratchBytes = 32ull << 20;
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static char* g_scratch_ptr[kScratchDevices];
+static const pmdg_solver* g_scratch_owner[kScratchDevices];
+
+// The solver is bound to a library-held workspace that a later
+// pmdg_bind_static on the same device has taken over.
+static bool ws_lost(const pmdg_solver* s) {
+  if (s->static_dev < 0) return false;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_owner[s->static_dev] != s;
+}
+static const char* kLostMsg = "the library-held workspace of this device was bound to another solver";
+
 extern "C" {
 
 const char* pmdg_last_error(void) { return g_err.c_str(); }
@@ -1478,6 +1503,7 @@ pmdg_status pmdg_set_drive(pmdg_solver* s, const double* amp, const double* phas
                            int envelope) {
   if (!s || (s->Np > 0 && (!amp || !phase)) || !freq) return fail(PMDG_EINVAL, "NULL argument");
   if (envelope < 0 || envelope > 2 || !(ncyc > 0)) return fail(PMDG_EINVAL, "bad envelope or ncyc");
+  if (s->bound && ws_lost(s)) return fail(PMDG_ESTATE, kLostMsg);
   for (int i = 0; i < s->S; ++i)
     if (!(freq[i] > 0)) return fail(PMDG_EINVAL, "freq must be > 0");
   const size_t n = (size_t)s->S * s->Np;
@@ -1600,6 +1626,40 @@ pmdg_status pmdg_bind(pmdg_solver* s, void* dev_ptr, size_t bytes, void* stream)
   return PMDG_OK;
 }
 
+pmdg_status pmdg_bind_static(pmdg_solver* s, void* stream) {
+  if (!s) return fail(PMDG_EINVAL, "NULL solver");
+  if (s->bound) return fail(PMDG_ESTATE, "already bound");
+  for (int k = 0; k < s->Np; ++k)
+    if (!s->shape_set[k]) return fail(PMDG_ESTATE, "mode shape of PMUT " + std::to_string(k) + " not set");
+  const size_t need = layout(s);
+  if (need > kScratchBytes)
+    return fail(PMDG_ENOMEM, "the solver needs " + std::to_string(need) + " bytes; the library-held workspace holds " +
+                                 std::to_string(kScratchBytes) + ": bind caller memory with pmdg_bind");
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kScratchDevices) return fail(PMDG_EINVAL, "device index beyond the library-held workspaces");
+  char* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      void* p = nullptr;
+      HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+      if (!p || ((uintptr_t)p & 255)) return fail(PMDG_EHIP, "library-held workspace has no aligned device address");
+      g_scratch_ptr[dev] = (char*)p;
+    }
+    base = g_scratch_ptr[dev];
+    g_scratch_owner[dev] = s;
+  }
+  s->static_dev = dev;
+  const pmdg_status r = pmdg_bind(s, base, kScratchBytes, stream);
+  if (r) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_owner[dev] == s) g_scratch_owner[dev] = nullptr;
+    s->static_dev = -1;
+  }
+  return r;
+}
+
 pmdg_status pmdg_get_dt(pmdg_solver* s, double* dt) {
   if (!s || !dt) return fail(PMDG_EINVAL, "NULL argument");
   *dt = s->dt;
@@ -1693,6 +1753,7 @@ pmdg_status pmdg_set_option(pmdg_solver* s, int option, long value) {
 pmdg_status pmdg_step(pmdg_solver* s, int n, void* stream) {
   if (!s) return fail(PMDG_EINVAL, "NULL solver");
   if (!s->bound) return fail(PMDG_ESTATE, "bind before stepping");
+  if (ws_lost(s)) return fail(PMDG_ESTATE, kLostMsg);
   if (n < 0) return fail(PMDG_EINVAL, "n must be >= 0");
   if (s->steps_done + n > s->cap) return fail(PMDG_ESTATE, "trace capacity (maximum step count) exceeded");
   if (n == 0) return PMDG_OK;
@@ -1765,6 +1826,7 @@ pmdg_status pmdg_kernel_times(pmdg_solver* s, double* ms3) {
 pmdg_status pmdg_read_traces(pmdg_solver* s, double* out, void* stream) {
   if (!s || !out) return fail(PMDG_EINVAL, "NULL argument");
   if (!s->bound) return fail(PMDG_ESTATE, "not bound");
+  if (ws_lost(s)) return fail(PMDG_ESTATE, kLostMsg);
   if (s->R == 0) return PMDG_OK;
   HIPCHK(hipStreamSynchronize((hipStream_t)stream));
   std::vector<double> all((size_t)s->S * s->R * s->cap);
@@ -1778,6 +1840,7 @@ pmdg_status pmdg_read_traces(pmdg_solver* s, double* out, void* stream) {
 pmdg_status pmdg_read_modal(pmdg_solver* s, int sc, double* q, double* qd, double* qdd, void* stream) {
   if (!s) return fail(PMDG_EINVAL, "NULL solver");
   if (!s->bound) return fail(PMDG_ESTATE, "not bound");
+  if (ws_lost(s)) return fail(PMDG_ESTATE, kLostMsg);
   if (sc < 0 || sc >= s->S) return fail(PMDG_EINVAL, "scenario out of range");
   if (s->Np == 0) return PMDG_OK;
   HIPCHK(hipStreamSynchronize((hipStream_t)stream));
@@ -1791,6 +1854,7 @@ pmdg_status pmdg_read_modal(pmdg_solver* s, int sc, double* q, double* qd, doubl
 pmdg_status pmdg_get_state(pmdg_solver* s, int sc, double* p, double* p_prev, void* stream) {
   if (!s) return fail(PMDG_EINVAL, "NULL solver");
   if (!s->bound) return fail(PMDG_ESTATE, "not bound");
+  if (ws_lost(s)) return fail(PMDG_ESTATE, kLostMsg);
   if (sc < 0 || sc >= s->S) return fail(PMDG_EINVAL, "scenario out of range");
   return s->prec == 64 ? get_state_t<double>(s, sc, p, p_prev, (hipStream_t)stream)
                        : get_state_t<float>(s, sc, p, p_prev, (hipStream_t)stream);
@@ -1800,6 +1864,7 @@ pmdg_status pmdg_set_state(pmdg_solver* s, int sc, const double* p, const double
                            const double* qd, const double* qdd, long nstep, void* stream) {
   if (!s) return fail(PMDG_EINVAL, "NULL solver");
   if (!s->bound) return fail(PMDG_ESTATE, "not bound");
+  if (ws_lost(s)) return fail(PMDG_ESTATE, kLostMsg);
   if (sc < 0 || sc >= s->S) return fail(PMDG_EINVAL, "scenario out of range");
   if (nstep < 0 || (s->R > 0 && nstep > s->cap)) return fail(PMDG_EINVAL, "nstep out of range");
   // the S scenarios share one step counter, which also selects their state
@@ -1814,6 +1879,7 @@ pmdg_status pmdg_set_state(pmdg_solver* s, int sc, const double* p, const double
 pmdg_status pmdg_status_flags(pmdg_solver* s, int* nonfinite, void* stream) {
   if (!s || !nonfinite) return fail(PMDG_EINVAL, "NULL argument");
   if (!s->bound) return fail(PMDG_ESTATE, "not bound");
+  if (ws_lost(s)) return fail(PMDG_ESTATE, kLostMsg);
   HIPCHK(hipStreamSynchronize((hipStream_t)stream));
   HIPCHK(hipMemcpy(nonfinite, dptr<char>(s, "ctl") + 16, sizeof(int), hipMemcpyDeviceToHost));
   return PMDG_OK;
@@ -1821,6 +1887,10 @@ pmdg_status pmdg_status_flags(pmdg_solver* s, int* nonfinite, void* stream) {
 
 void pmdg_destroy(pmdg_solver* s) {
   if (!s) return;
+  if (s->static_dev >= 0) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_owner[s->static_dev] == s) g_scratch_owner[s->static_dev] = nullptr;
+  }
   drop_graphs(s);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   if (s->side) (void)hipStreamDestroy(s->side);
@@ -1886,6 +1956,7 @@ pmdg_status pmdg_batch_create(int n, pmdg_solver* const* solvers, pmdg_batch** o
   for (int i = 0; i < n; ++i) {
     pmdg_solver* s = solvers[i];
     if (!s || !s->bound) { delete b; return fail(PMDG_ESTATE, "every solver must be bound"); }
+    if (ws_lost(s)) { delete b; return fail(PMDG_ESTATE, kLostMsg); }
     if (s->ndom != 1 || s->prec != 32) { delete b; return fail(PMDG_EINVAL, "batches take single-brick FP32 solvers"); }
     const int rows = brick_rows(s, 0);
     if (rows != 1 && rows != 2) { delete b; return fail(PMDG_EINVAL, "batched tiles use 1 or 2 rows per wave"); }
@@ -1960,8 +2031,10 @@ pmdg_status pmdg_batch_step(pmdg_batch* b, int n, void* stream) {
   if (!b) return fail(PMDG_EINVAL, "NULL batch");
   if (!b->bound) return fail(PMDG_ESTATE, "bind the batch before stepping");
   if (n < 0) return fail(PMDG_EINVAL, "n must be >= 0");
-  for (auto* s : b->sv)
+  for (auto* s : b->sv) {
     if (s->steps_done + n > s->cap) return fail(PMDG_ESTATE, "a solver's trace capacity would be exceeded");
+    if (ws_lost(s)) return fail(PMDG_ESTATE, kLostMsg);
+  }
   if (n == 0) return PMDG_OK;
   hipStream_t st = (hipStream_t)stream;
   if (!b->use_graph) {

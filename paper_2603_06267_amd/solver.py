@@ -154,6 +154,11 @@ class Solver:
         ptr = (ptr + 255) // 256 * 256
         check(self.L.pmdg_bind(self.h, ctypes.c_void_p(ptr), nbytes, _stream_ptr(stream)))
 
+    def bind_static(self, stream=None):
+        """Binds the library-held workspace of the current device (no device
+        allocation by anyone)."""
+        check(self.L.pmdg_bind_static(self.h, _stream_ptr(stream)))
+
     def set_option(self, opt, value):
         check(self.L.pmdg_set_option(self.h, int(opt), int(value)))
 
@@ -204,7 +209,9 @@ class Solver:
 def from_workload(wl, precision=32, n_steps=None, scenarios=None, shape_fn=None, device="cuda", bind=True):
     """Builds, fills and binds a solver for a workload description.
 
-    scenarios: indices into the workload's drive rows (default: all rows)."""
+    scenarios: indices into the workload's drive rows (default: all rows).
+    bind: True binds a caller workspace (a torch tensor), "static" the
+    library-held workspace, False leaves the solver unbound."""
     dr = wl.get("drive")
     if scenarios is None:
         scenarios = list(range(np.asarray(dr["amp"]).shape[0])) if dr is not None else [0]
@@ -227,6 +234,8 @@ def from_workload(wl, precision=32, n_steps=None, scenarios=None, shape_fn=None,
         if "rx" in wl:
             s.set_rx(wl["rx"]["t_switch"], wl["rx"]["cap"])
     s.set_receivers(wl["receivers"])
-    if bind:
+    if bind == "static":
+        s.bind_static()
+    elif bind:
         s.bind()
     return s
