@@ -154,6 +154,7 @@ typedef struct {
   long ntot;
   double dt, alpha, gammaF;
   int literal;
+  int abs_literal;    /* absorbing damping on the predicted velocity alone, as printed (test switch) */
   double sample_gain; /* 1 normally; 0 removes the sampling term (test hook) */
   double *mass;
   double *cabs;      /* absorbing-boundary matrix C (diagonal), or NULL */
@@ -496,6 +497,9 @@ long pmdg_ref_num_nodes(void *h) { return ((rsolver *)h)->ntot; }
 long pmdg_ref_dom_nodes(void *h, int d) { return ((rsolver *)h)->d[d].nnodes; }
 double pmdg_ref_gamma(void *h) { return ((rsolver *)h)->gammaF; }
 void pmdg_ref_set_literal(void *h, int lit) { ((rsolver *)h)->literal = lit; }
+/* Test switch: the acoustic solve takes the absorbing term as printed in
+ * Algorithm 1, M pdd = f - K p - C pdot* with the predicted velocity alone. */
+void pmdg_ref_set_absorbing_literal(void *h, int on) { ((rsolver *)h)->abs_literal = on; }
 void pmdg_ref_set_sample_gain(void *h, double g) { ((rsolver *)h)->sample_gain = g; }
 void pmdg_ref_set_dt(void *h, double dt) { ((rsolver *)h)->dt = dt; }
 
@@ -847,7 +851,8 @@ void pmdg_ref_step(void *h, int nsteps, double *traces) {
     pmdg_ref_apply_K(h, s->p, Kp, 3);
     for (long i = 0; i < n; ++i) {
       double ci = s->cabs ? s->cabs[i] : 0.0;
-      s->pdd[i] = (f[i] - Kp[i] - ci * s->pd[i]) / (s->mass[i] + 0.5 * dt * ci);
+      double mi = s->abs_literal ? s->mass[i] : s->mass[i] + 0.5 * dt * ci;
+      s->pdd[i] = (f[i] - Kp[i] - ci * s->pd[i]) / mi;
       s->pd[i] += 0.5 * dt * s->pdd[i];
     }
     s->nstep += 1;

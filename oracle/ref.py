@@ -40,6 +40,7 @@ def lib():
         L.pmdg_ref_gamma.restype = ctypes.c_double
         L.pmdg_ref_gamma.argtypes = [vp]
         L.pmdg_ref_set_literal.argtypes = [vp, ctypes.c_int]
+        L.pmdg_ref_set_absorbing_literal.argtypes = [vp, ctypes.c_int]
         L.pmdg_ref_set_sample_gain.argtypes = [vp, ctypes.c_double]
         L.pmdg_ref_set_dt.argtypes = [vp, ctypes.c_double]
         L.pmdg_ref_cfl_dt.restype = ctypes.c_double
@@ -216,6 +217,11 @@ class RefSolver:
 
     def set_literal(self, on):
         self.L.pmdg_ref_set_literal(self.h, 1 if on else 0)
+
+    def set_absorbing_literal(self, on):
+        """Test switch: absorbing damping on the predicted velocity alone,
+        M pdd = f - K p - C pdot* (the acoustic solve as printed)."""
+        self.L.pmdg_ref_set_absorbing_literal(self.h, 1 if on else 0)
 
     def set_sample_gain(self, g):
         self.L.pmdg_ref_set_sample_gain(self.h, float(g))

@@ -93,3 +93,47 @@ def test_energy_leaves_a_cube_with_absorbing_faces():
         out.append(energy() / e0)
     assert abs(out[0] - 1.0) < 1e-2
     assert out[1] < 1e-3
+
+
+def _cube_five_absorbing(cfl, literal, steps):
+    """Config-1 cube with absorbing faces everywhere but the bottom: the
+    largest energy ratio over the run (with a smooth initial field)."""
+    dom = W.brick([0, 0, 0], [1, 1, 1], [4, 4, 4], 4, c=1.5)
+    s = R.RefSolver([dom], cfl=cfl)
+    s.set_absorbing(0, 0b111110)
+    s.set_absorbing_literal(literal)
+    xyz = s.coords()
+    p0 = np.cos(2.1 * xyz[:, 0] + 0.3) * np.cos(1.3 * xyz[:, 1]) * np.cos(2.7 * xyz[:, 2] + 0.5)
+    s.set_state(p=p0, pd=np.zeros_like(p0), pdd=np.zeros_like(p0))
+    M = s.mass()
+    C = s.absorbing()
+
+    def energy():
+        st = s.get_state()
+        return 0.5 * st["pd"] @ (M * st["pd"]) + 0.5 * st["p"] @ s.apply_K(st["p"])
+
+    e0, worst = energy(), 0.0
+    for _ in range(steps // 50):
+        s.step(50)
+        e = energy()
+        worst = max(worst, e / e0)
+        if not np.isfinite(e) or e > 1e12 * e0:
+            break
+    return worst, energy() / e0, float((s.dt * C / M).max())
+
+
+def test_printed_absorbing_solve_is_unstable_at_the_cfl_used():
+    """The acoustic solve as printed, M pdd = f - K p - C pdot*, is the
+    explicit damped central difference: stable only while dt (M^-1 C)_ii
+    <= 2.  At CFL 0.3 the GLL end weights give about 3.1 at the cube's
+    corners and the energy grows without bound; at CFL 0.15 every node is
+    below 2 and it decays like the damping on the corrected velocity, which
+    stays bounded at CFL 0.3."""
+    worst, last, g = _cube_five_absorbing(0.3, True, 400)
+    assert g > 2.0
+    assert worst > 1e6
+    worst, last, g = _cube_five_absorbing(0.15, True, 800)
+    assert g < 2.0
+    assert worst < 1.05 and last < 0.2
+    worst, last, g = _cube_five_absorbing(0.3, False, 400)
+    assert worst < 1.05 and last < 0.2

@@ -304,3 +304,69 @@ def test_window_values():
     assert abs(ref.window(0.05 * Td, Td) - 0.5806560846) < 1e-9
     assert abs(ref.window(0.1 * Td, Td) - 0.9631987356) < 1e-9
     assert ref.window(-0.1, Td) == 0.0 and ref.window(Td * 1.01, Td) == 0.0
+
+
+def _coupled_energy_run(cfl, kappa_factor=1.0, steps=100_000, every=50):
+    """A rigid cube (2^3 elements, N = 2) with one PMUT of two modes, zeta = 0,
+    no drive, energy starting in the membrane (q^0 = (1, 0.7)).  Returns the
+    coupled energy of Sec. 3.1 (eqs. semi_SEM, semi_PMUT),
+    E = 1/2 pdot.M pdot + 1/2 p.K p + kappa/2 sum_m (omega_m^2 qdot_m^2 + qdd_m^2),
+    every `every` steps: the continuous system conserves it exactly
+    (d/dt of the modal part is kappa qdd.B^T pdot, which cancels the
+    acoustic work of the face force).  The coupling matrix is scaled so that
+    the coupling number kappa dt^2 b.M^-1 b is 0.5 at CFL 0.3 and kept
+    physically fixed at other CFL numbers."""
+    dom = W.brick([0, 0, 0], [1, 1, 1], [2, 2, 2], 2)
+    dt03 = ref.RefSolver([dom], cfl=0.3).dt
+    s = ref.RefSolver([dom], cfl=cfl)
+    om = 2 * math.pi * np.array([[0.35, 0.6]])
+    s.set_pmuts([[0.5, 0.5]], [0.4], om, np.zeros((1, 2)), np.ones((1, 2)))
+    xyz = s.pmut_nodes(0)
+    r = np.hypot(xyz[:, 0] - 0.5, xyz[:, 1] - 0.5)
+    shape = np.stack([np.cos(0.5 * math.pi * r / 0.4), np.cos(1.5 * math.pi * r / 0.4)])
+    M = s.mass()
+    kappa = dom["rho"] * dom["c"] ** 2
+    s.set_shape(0, shape)
+    nd, b = s.coupling(0, 0)
+    X03 = kappa * dt03 ** 2 * np.sum(b * b / M[nd])
+    s.set_shape(0, shape * math.sqrt(0.5 / X03))
+    s.set_receivers([[0.5, 0.5, 0.5]])
+    s.set_drive([0.0], [0.0], 1.0, 3.0, 0)
+    B = np.zeros((s.n, 2))
+    for m in range(2):
+        nd, v = s.coupling(0, m)
+        B[nd, m] = v
+    q0 = np.array([1.0, 0.7])
+    qdd0 = -om.reshape(-1) ** 2 * q0
+    s.set_state(p=np.zeros(s.n), pd=np.zeros(s.n), pdd=-kappa * (B @ qdd0) / M, q=q0, qd=np.zeros(2), qdd=qdd0)
+    om2 = om.reshape(-1) ** 2
+    E = []
+    for _ in range(steps // every):
+        s.step(every)
+        st = s.get_state()
+        acoustic = 0.5 * st["pd"] @ (M * st["pd"]) + 0.5 * st["p"] @ s.apply_K(st["p"])
+        modal = 0.5 * kappa * kappa_factor * np.sum(om2 * st["qd"] ** 2 + st["qdd"] ** 2)
+        E.append(acoustic + modal)
+    return np.array(E)
+
+
+def test_coupled_energy_bounded_without_drift():
+    """Pin P11: with coupling, zeta = 0 and no drive, the synchronised scheme
+    keeps the coupled energy bounded over 1e5 steps with no secular drift,
+    and its oscillation is the O(dt^2) error of the scheme (about 11x
+    smaller from CFL 0.1 to 0.03).  A face force or sampled pressure with a
+    wrong factor (kappa off by 20%) leaves an O(1) oscillation of the same
+    energy; a wrong sign makes it grow."""
+    res = {}
+    for cfl in (0.1, 0.03):
+        E = _coupled_energy_run(cfl)
+        n = len(E) // 10
+        res[cfl] = (E.max() - E.min()) / E.mean()
+        assert np.isfinite(E).all()
+        assert abs(E[-n:].mean() - E[:n].mean()) < 1e-4 * E.mean()
+    assert res[0.03] < 5e-3
+    ratio = res[0.1] / res[0.03]
+    assert 7.0 < ratio < 16.0, ratio
+    # the energy with kappa weighted wrongly is not an invariant
+    E = _coupled_energy_run(0.03, kappa_factor=1.2)
+    assert (E.max() - E.min()) / E.mean() > 0.05
