@@ -299,7 +299,8 @@ void pmdg_batch_destroy(pmdg_batch* b);
  * model). */
 typedef struct pmdg_mlp pmdg_mlp;
 
-/* widths[nlayers + 1]: n_0 .. n_L; n_1 .. n_L multiples of 8; 1 <= nlayers <= 16. */
+/* widths[nlayers + 1]: n_0 .. n_L; hidden widths n_1 .. n_{L-1} multiples of
+ * 32, the output width n_L a multiple of 8; 1 <= nlayers <= 16. */
 pmdg_status pmdg_mlp_create(int nlayers, const int* widths, pmdg_mlp** out);
 /* Number of trainable values sum_l n_{l+1} (n_l + 1). */
 pmdg_status pmdg_mlp_num_params(pmdg_mlp* m, long* n);
@@ -347,6 +348,42 @@ pmdg_status pmdg_mlp_train_step(pmdg_mlp* m, const float* u, const float* t, con
  * a, b, mean 16-byte aligned; mean may alias a or b. */
 pmdg_status pmdg_mlp_pair_combine(const float* a, const float* b, int B, int n, float* mean, float* spread,
                                   void* stream);
+/* Least-squares fit of the whole network (a closed-form training of it).
+ * With input columns that are products of each PMUT's drive factor
+ * (cos / sin of its phase) and a basis in frequency, the traces are a
+ * linear function of the embedded inputs (the solver is linear in each
+ * PMUT's drive A_k (cos theta_k, sin theta_k), Sec. 3.1).  The fit solves
+ * min ||X W - T / (out_scale a)|| over rows u[idx[r]], t[idx[r]] (r < n) with
+ * X the FP32 embedding, truncates W to its best rank-`rank` predictor
+ * (eigen-decomposition of the whitened normal equations, host FP64), and
+ * writes a network that computes it: the first layer maps the inputs to the
+ * `rank` whitened coordinates z, the leading `npairs` enter the hidden layers
+ * as pairs (gelu(z), gelu(-z)), whose difference is z exactly, the others
+ * shifted by a bias beta (gelu(z + beta) = z + beta to within 1.4e-3 for
+ * z + beta >= 3), the hidden layers pass them on and the output layer maps
+ * them to the traces.  Needs hidden layers of one width with npairs + rank
+ * <= that width, rank <= n_0 and rank <= n; ridge >= 0 adds ridge * (mean
+ * diagonal of X^T X) to it.  Sets out_scale to the RMS of t / a over the fit
+ * rows and resets Adam.  The large products run on the GPU (FP32), the
+ * n_0 x n_0 factorisations on the host.  work: caller device memory of
+ * pmdg_mlp_fit_linear_workspace bytes, 256-byte aligned.  u, t, idx device
+ * pointers (idx NULL: rows 0 .. n-1). */
+pmdg_status pmdg_mlp_fit_linear_workspace(pmdg_mlp* m, int n, int rank, size_t* bytes);
+pmdg_status pmdg_mlp_fit_linear(pmdg_mlp* m, const float* u, const float* t, const int* idx, int nrows, int n,
+                                int npairs, int rank, float ridge, void* work, size_t work_bytes, void* stream);
+/* out_scale = RMS over rows idx of t / a (the normalisation of the targets
+ * before training); work: device scratch of n doubles, 8-byte aligned. */
+pmdg_status pmdg_mlp_set_target_scale(pmdg_mlp* m, const float* u, const float* t, const int* idx, int nrows, int n,
+                                      void* work, size_t work_bytes, void* stream);
+/* The model's current out_scale. */
+pmdg_status pmdg_mlp_out_scale(pmdg_mlp* m, float* out_scale);
+/* err[r] = ||y_r - t[idx[r]]|| / ||t[idx[r]]|| (0 for a zero target) for
+ * r < B, rows of n floats (device pointers; idx NULL: row r). */
+pmdg_status pmdg_mlp_row_errors(const float* y, const float* t, const int* idx, int nrows, int B, int n, float* err,
+                                void* stream);
+/* dst[rows[i]] = src[i] for i < nr, rows of n floats (device pointers): puts
+ * solver traces in place of the network's for the rows sent to the solver. */
+pmdg_status pmdg_mlp_scatter_rows(const float* src, const int* rows, int nr, int n, float* dst, void* stream);
 /* NULL is a no-op. */
 void pmdg_mlp_destroy(pmdg_mlp* m);
 

@@ -31,6 +31,13 @@ SIGS = {
     "pmdg_mlp_train_step": [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_float, ctypes.c_float,
                             ctypes.c_float, ctypes.c_float, _vp, _vp, _vp],
     "pmdg_mlp_pair_combine": [_vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp],
+    "pmdg_mlp_fit_linear_workspace": [_vp, ctypes.c_int, ctypes.c_int, _sp],
+    "pmdg_mlp_fit_linear": [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                            ctypes.c_float, _vp, ctypes.c_size_t, _vp],
+    "pmdg_mlp_set_target_scale": [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_size_t, _vp],
+    "pmdg_mlp_out_scale": [_vp, _fp],
+    "pmdg_mlp_row_errors": [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp],
+    "pmdg_mlp_scatter_rows": [_vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp],
 }
 
 

@@ -26,6 +26,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <vector>
 
@@ -438,6 +439,173 @@ hipError_t gemm(GemmArgs g, float* part, hipStream_t st) {
   return gemm_t<ACON, BCON, EPI, 2, 2, 32>(g, part, st);
 }
 
+
+// ------------------------------------------------------------------------
+// Least-squares fit of the network (pmdg_mlp_fit_linear).  The surrogate's
+// target is linear in the embedded input columns when those are products of
+// each PMUT's drive (cos / sin of its phase) with a basis in frequency, so a
+// linear map of rank r fitted by least squares is a network whose hidden
+// layers pass r signals through: the leading ones as pairs (gelu(z) -
+// gelu(-z) = z exactly), the rest shifted by beta so that gelu(z + beta) is
+// z + beta to within the BF16 rounding.  The large products run here on the
+// GPU in FP32; the factorisations of the n_0 x n_0 matrices run on the host
+// in FP64.
+// ------------------------------------------------------------------------
+
+// C[i][j] = alpha sum_k A(i, k) B(k, j) over FP32 operands with arbitrary
+// strides: A(i, k) = A[i sai + k sak], B(k, j) = B[g(k) sbk + j sbj], g(k) =
+// gidx[k] (row gather) or k.  64 x 64 tiles, 16-deep slices staged in LDS;
+// each slice is loaded along whichever index has unit stride.
+__global__ void __launch_bounds__(256) k_sgemm(int M, int N, int K, const float* __restrict__ A, long sai, long sak,
+                                              const float* __restrict__ B, long sbk, long sbj,
+                                              const int* __restrict__ gidx, float alpha, float* __restrict__ C,
+                                              long ldc) {
+  __shared__ float As[16][64 + 4];
+  __shared__ float Bs[16][64 + 4];
+  const int t = threadIdx.x, tx = t % 16, ty = t / 16;
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  const bool a_k_fast = sak == 1 && sai != 1, b_k_fast = sbk == 1 && sbj != 1;
+  float acc[4][4] = {};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int q = 0; q < 4; ++q) {
+      const int e = t + 256 * q;
+      const int ii = a_k_fast ? e / 16 : e % 64, kk = a_k_fast ? e % 16 : e / 64;
+      const int i = i0 + ii, k = k0 + kk;
+      As[kk][ii] = (i < M && k < K) ? A[(long)i * sai + (long)k * sak] : 0.f;
+      const int jj = b_k_fast ? e / 16 : e % 64, kb = b_k_fast ? e % 16 : e / 64;
+      const int j = j0 + jj, k2 = k0 + kb;
+      float bv = 0.f;
+      if (j < N && k2 < K) bv = B[(long)(gidx ? gidx[k2] : k2) * sbk + (long)j * sbj];
+      Bs[kb][jj] = bv;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < 16; ++kk) {
+      float a[4], b[4];
+      for (int r = 0; r < 4; ++r) a[r] = As[kk][ty * 4 + r];
+      for (int c = 0; c < 4; ++c) b[c] = Bs[kk][tx * 4 + c];
+      for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) acc[r][c] += a[r] * b[c];
+    }
+    __syncthreads();
+  }
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c) {
+      const int i = i0 + ty * 4 + r, j = j0 + tx * 4 + c;
+      if (i < M && j < N) C[(long)i * ldc + j] = alpha * acc[r][c];
+    }
+}
+
+// X[r][c] = embed column c of u[idx[r]] (FP32, n_0 columns), Xs = X / (s a_r)
+// with a_r the amplitude feature (or 1), s the output scale.
+__global__ void k_embed_f32(const float* __restrict__ u, const int* __restrict__ idx, int nrows, int n, int nu, int n0,
+                            const EmbCol* __restrict__ emb, int amp, float inv_scale, float* __restrict__ X,
+                            float* __restrict__ Xs) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= (long)n * n0) return;
+  const int r = (int)(i / n0), c = (int)(i % n0);
+  const long src = idx ? min(max(idx[r], 0), nrows - 1) : r;
+  const EmbCol e = emb[c];
+  float v = 0.f;
+  if (e.src >= 0) {
+    v = emb_factor(u[src * nu + e.src], e.op, e.shift, e.scale);
+    if (e.src2 >= 0) v *= emb_factor(u[src * nu + e.src2], e.op2, e.shift2, e.scale2);
+  }
+  const float a = amp >= 0 ? u[src * nu + amp] : 1.0f;
+  X[i] = v;
+  Xs[i] = a != 0.f ? v * inv_scale / a : 0.f;
+}
+
+// sum over the fit rows of (t[idx[r]] / a_r)^2: one partial per workgroup
+// (row r = blockIdx.x), summed on the host in a fixed order.
+__global__ void __launch_bounds__(256) k_row_sq(const float* __restrict__ t, const float* __restrict__ u,
+                                               const int* __restrict__ idx, int nrows, int nu, int amp, int nL,
+                                               double* __restrict__ part) {
+  __shared__ double red[256];
+  const int r = blockIdx.x;
+  const long src = idx ? min(max(idx[r], 0), nrows - 1) : r;
+  const float a = amp >= 0 ? u[src * nu + amp] : 1.0f;
+  const float inv = a != 0.f ? 1.0f / a : 0.f;
+  double s = 0;
+  for (int j = threadIdx.x; j < nL; j += 256) {
+    const double v = (double)(t[src * (long)nL + j] * inv);
+    s += v * v;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[r] = red[0];
+}
+
+// Output layer of the fitted network from the rank-r coefficients C [r][nL]:
+// W[j][c] = +C[c][j] (c < P), -C[c - P][j] (P <= c < 2P), C[c - P][j]
+// (2P <= c < P + r), 0 beyond; b[j] = -beta sum_{i >= P} C[i][j] (removes the
+// shift of the singly passed signals).  W is [nL][ld] FP32 with its BF16 copy.
+__global__ void k_fit_out_layer(const float* __restrict__ C, int r, int P, int nL, int width, int ld, float beta,
+                                float* __restrict__ W, bf16_t* __restrict__ Wb, float* __restrict__ b) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= (long)nL * ld) return;
+  const int j = (int)(i / ld), c = (int)(i % ld);
+  float v = 0.f;
+  if (c < P) v = C[(long)c * nL + j];
+  else if (c < 2 * P) v = -C[(long)(c - P) * nL + j];
+  else if (c < P + r && c < width) v = C[(long)(c - P) * nL + j];
+  W[i] = v;
+  Wb[i] = f2bf(v);
+  if (c == 0) {
+    float acc = 0.f;
+    for (int k = P; k < r; ++k) acc += C[(long)k * nL + j];
+    b[j] = -beta * acc;
+  }
+}
+
+// max |Z| over a block of columns [c0, c1) of Z [n][ld] (non-negative floats
+// compare as their bit patterns)
+__global__ void k_absmax_cols(const float* __restrict__ Z, long n, int ld, int c0, int c1, unsigned* __restrict__ out) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= n * ld) return;
+  const int c = (int)(i % ld);
+  if (c < c0 || c >= c1) return;
+  atomicMax(out, __float_as_uint(fabsf(Z[i])));
+}
+
+// per-row relative L2 error ||y_r - t[idx[r]]|| / ||t[idx[r]]||
+__global__ void __launch_bounds__(256) k_row_relerr(const float* __restrict__ y, const float* __restrict__ t,
+                                                   const int* __restrict__ idx, int nrows, int n,
+                                                   float* __restrict__ err) {
+  __shared__ double red[2][256];
+  const int r = blockIdx.x;
+  const long src = idx ? min(max(idx[r], 0), nrows - 1) : r;
+  double se = 0, sn = 0;
+  for (int j = threadIdx.x; j < n; j += 256) {
+    const double tv = t[src * (long)n + j], d = (double)y[(long)r * n + j] - tv;
+    se += d * d;
+    sn += tv * tv;
+  }
+  red[0][threadIdx.x] = se;
+  red[1][threadIdx.x] = sn;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + w];
+      red[1][threadIdx.x] += red[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) err[r] = red[1][0] > 0 ? (float)sqrt(red[0][0] / red[1][0]) : 0.f;
+}
+
+// dst[rows[i]] = src[i] for i < nr, rows of n floats
+__global__ void k_scatter_rows(const float* __restrict__ src, const int* __restrict__ rows, int nr, int n,
+                               float* __restrict__ dst) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= (long)nr * n) return;
+  const int r = (int)(i / n), c = (int)(i % n);
+  dst[(long)rows[r] * n + c] = src[i];
+}
 }  // namespace
 
 #define MCHK(call)                                                                                  \
@@ -503,6 +671,229 @@ static void mlp_layout(pmdg_mlp* m) {
 
 template <typename T>
 static T* at(pmdg_mlp* m, size_t off) { return (T*)(m->ws + off); }
+
+// ---- host FP64 linear algebra for the least-squares fit (n of a few hundred)
+
+// Cholesky factor L (lower, row-major) of the SPD matrix A [n][n]; false if
+// a pivot is not positive.
+static bool chol_lower(int n, const std::vector<double>& A, std::vector<double>& L) {
+  L.assign((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double s = A[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) s -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+    if (!(s > 0)) return false;
+    const double ljj = std::sqrt(s);
+    L[(size_t)j * n + j] = ljj;
+    for (int i = j + 1; i < n; ++i) {
+      double t = A[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) t -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+      L[(size_t)i * n + j] = t / ljj;
+    }
+  }
+  return true;
+}
+
+// B <- L^{-1} B for B [n][m] (forward substitution, column by column of B)
+static void solve_lower(int n, int m, const std::vector<double>& L, std::vector<double>& B) {
+  for (int i = 0; i < n; ++i) {
+    double* bi = &B[(size_t)i * m];
+    for (int k = 0; k < i; ++k) {
+      const double l = L[(size_t)i * n + k];
+      if (l == 0) continue;
+      const double* bk = &B[(size_t)k * m];
+      for (int j = 0; j < m; ++j) bi[j] -= l * bk[j];
+    }
+    const double inv = 1.0 / L[(size_t)i * n + i];
+    for (int j = 0; j < m; ++j) bi[j] *= inv;
+  }
+}
+
+// B <- L^{-T} B for B [n][m] (back substitution with the transpose)
+static void solve_lower_t(int n, int m, const std::vector<double>& L, std::vector<double>& B) {
+  for (int i = n - 1; i >= 0; --i) {
+    double* bi = &B[(size_t)i * m];
+    for (int k = i + 1; k < n; ++k) {
+      const double l = L[(size_t)k * n + i];
+      if (l == 0) continue;
+      const double* bk = &B[(size_t)k * m];
+      for (int j = 0; j < m; ++j) bi[j] -= l * bk[j];
+    }
+    const double inv = 1.0 / L[(size_t)i * n + i];
+    for (int j = 0; j < m; ++j) bi[j] *= inv;
+  }
+}
+
+// Eigen-decomposition of the symmetric A [n][n] (destroyed): eigenvalues w in
+// descending order, eigenvectors as the columns of V [n][n].  Householder
+// reduction to tridiagonal form with the reflections accumulated, then the
+// implicit QL iteration with Wilkinson-type shifts (Golub and Van Loan,
+// Matrix Computations, Sec. 8.3).  false if an eigenvalue does not converge.
+static bool sym_eig(int n, std::vector<double>& A, std::vector<double>& w, std::vector<double>& V) {
+  std::vector<double> d(n), e(n, 0.0);
+  // Vt holds the accumulated transformation by rows (row i = column i of
+  // the eigenvector matrix), so every update runs along contiguous rows
+  std::vector<double> Vt((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) Vt[(size_t)i * n + i] = 1.0;
+  std::vector<double> v(n), p(n), sv(n);
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;  // length of the column below the diagonal
+    double xn = 0;
+    for (int i = 0; i < m; ++i) xn += A[(size_t)(k + 1 + i) * n + k] * A[(size_t)(k + 1 + i) * n + k];
+    xn = std::sqrt(xn);
+    if (xn == 0) { e[k] = 0; continue; }
+    const double x0 = A[(size_t)(k + 1) * n + k];
+    const double alpha = x0 >= 0 ? -xn : xn;
+    double vn2 = 0;
+    for (int i = 0; i < m; ++i) {
+      v[i] = A[(size_t)(k + 1 + i) * n + k] - (i == 0 ? alpha : 0.0);
+      vn2 += v[i] * v[i];
+    }
+    if (vn2 == 0) { e[k] = x0; continue; }
+    const double beta = 2.0 / vn2;
+    // p = beta A22 v, K = beta/2 v.p, w = p - K v; A22 -= v w^T + w v^T
+    double vp = 0;
+    for (int i = 0; i < m; ++i) {
+      const double* ai = &A[(size_t)(k + 1 + i) * n + k + 1];
+      double s = 0;
+      for (int j = 0; j < m; ++j) s += ai[j] * v[j];
+      p[i] = beta * s;
+      vp += v[i] * p[i];
+    }
+    const double K = 0.5 * beta * vp;
+    for (int i = 0; i < m; ++i) p[i] -= K * v[i];
+    for (int i = 0; i < m; ++i) {
+      double* ai = &A[(size_t)(k + 1 + i) * n + k + 1];
+      for (int j = 0; j < m; ++j) ai[j] -= v[i] * p[j] + p[i] * v[j];
+    }
+    for (int i = 0; i < m; ++i) {
+      A[(size_t)(k + 1 + i) * n + k] = i == 0 ? alpha : 0.0;
+      A[(size_t)k * n + k + 1 + i] = i == 0 ? alpha : 0.0;
+    }
+    e[k] = alpha;
+    // rows k+1.. of Vt: Vt_j -= beta v_j sum_i v_i Vt_i
+    std::fill(sv.begin(), sv.end(), 0.0);
+    for (int j = 0; j < m; ++j) {
+      const double* vj = &Vt[(size_t)(k + 1 + j) * n];
+      for (int r = 0; r < n; ++r) sv[r] += v[j] * vj[r];
+    }
+    for (int j = 0; j < m; ++j) {
+      double* vj = &Vt[(size_t)(k + 1 + j) * n];
+      const double f = beta * v[j];
+      for (int r = 0; r < n; ++r) vj[r] -= f * sv[r];
+    }
+  }
+  if (n >= 2) e[n - 2] = A[(size_t)(n - 1) * n + n - 2];
+  e[n - 1] = 0;
+  for (int i = 0; i < n; ++i) d[i] = A[(size_t)i * n + i];
+  // implicit QL on (d, e): e[i] couples i and i + 1
+  const double eps = std::numeric_limits<double>::epsilon();
+  for (int l = 0; l < n; ++l) {
+    for (int iter = 0;; ++iter) {
+      int m = l;
+      for (; m < n - 1; ++m)
+        if (std::fabs(e[m]) <= eps * (std::fabs(d[m]) + std::fabs(d[m + 1]))) break;
+      if (m == l) break;
+      if (iter == 100) return false;
+      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+      double r = std::hypot(g, 1.0);
+      g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
+      double s = 1, c = 1, pp = 0;
+      int i = m - 1;
+      bool early = false;
+      for (; i >= l; --i) {
+        const double f = s * e[i], b = c * e[i];
+        r = std::hypot(f, g);
+        e[i + 1] = r;
+        if (r == 0) {  // split: d[i+1] converged early
+          d[i + 1] -= pp;
+          e[m] = 0;
+          early = true;
+          break;
+        }
+        s = f / r;
+        c = g / r;
+        g = d[i + 1] - pp;
+        r = (d[i] - g) * s + 2.0 * c * b;
+        pp = s * r;
+        d[i + 1] = g + pp;
+        g = c * r - b;
+        double* va = &Vt[(size_t)i * n];
+        double* vb = &Vt[(size_t)(i + 1) * n];
+        for (int k = 0; k < n; ++k) {
+          const double fv = vb[k];
+          vb[k] = s * va[k] + c * fv;
+          va[k] = c * va[k] - s * fv;
+        }
+      }
+      if (early) continue;
+      d[l] -= pp;
+      e[l] = g;
+      e[m] = 0;
+    }
+  }
+  // descending order
+  std::vector<int> ord(n);
+  for (int i = 0; i < n; ++i) ord[i] = i;
+  std::sort(ord.begin(), ord.end(), [&](int a, int b) { return d[a] > d[b]; });
+  w.resize(n);
+  V.assign((size_t)n * n, 0.0);
+  for (int c = 0; c < n; ++c) {
+    w[c] = d[ord[c]];
+    const double* src = &Vt[(size_t)ord[c] * n];
+    for (int r = 0; r < n; ++r) V[(size_t)r * n + c] = src[r];
+  }
+  return true;
+}
+
+// Device buffers of the least-squares fit (byte offsets into the caller's
+// fit workspace).
+struct FitLayout {
+  size_t X, Xs, G, Bt, S, M, C, Z, part, zmax, bytes;
+};
+
+static FitLayout fit_layout(const pmdg_mlp* m, int n, int rank) {
+  const size_t n0 = m->width[0], nL = m->width[m->L];
+  FitLayout f;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = a256(o + bytes); return r; };
+  f.X = take(4 * (size_t)n * n0);
+  f.Xs = take(4 * (size_t)n * n0);
+  f.G = take(4 * n0 * n0);
+  f.Bt = take(4 * n0 * nL);
+  f.S = take(4 * n0 * n0);
+  f.M = take(4 * n0 * (size_t)rank);
+  f.C = take(4 * (size_t)rank * nL);
+  f.Z = take(4 * (size_t)n * rank);
+  f.part = take(8 * (size_t)n);
+  f.zmax = take(4);
+  f.bytes = o;
+  return f;
+}
+
+// out_scale = RMS over rows idx of t / a (a the amplitude feature or 1);
+// part: n doubles of device scratch
+static pmdg_status target_scale(pmdg_mlp* m, const float* u, const float* t, const int* idx, int nrows, int n,
+                                double* part, hipStream_t st) {
+  const int nL = m->width[m->L];
+  hipLaunchKernelGGL(k_row_sq, dim3(n), dim3(256), 0, st, t, u, idx, nrows, m->n_u, m->amp_col, nL, part);
+  MCHK(hipGetLastError());
+  std::vector<double> hp(n);
+  MCHK(hipMemcpyAsync(hp.data(), part, 8 * (size_t)n, hipMemcpyDeviceToHost, st));
+  MCHK(hipStreamSynchronize(st));
+  double ss = 0;
+  for (int r = 0; r < n; ++r) ss += hp[r];
+  const double oscale = std::sqrt(ss / ((double)n * nL));
+  if (!(oscale > 0) || !std::isfinite(oscale)) return mfail(PMDG_EINVAL, "targets are zero or not finite");
+  m->out_scale = (float)oscale;
+  return PMDG_OK;
+}
+
+static hipError_t sgemm(int M, int N, int K, const float* A, long sai, long sak, const float* B, long sbk, long sbj,
+                        const int* gidx, float alpha, float* C, long ldc, hipStream_t st) {
+  hipLaunchKernelGGL(k_sgemm, dim3((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64)), dim3(256), 0, st, M, N, K,
+                     A, sai, sak, B, sbk, sbj, gidx, alpha, C, ldc);
+  return hipGetLastError();
+}
 
 static pmdg_status check_batch(pmdg_mlp* m, const int* idx, int nrows, int B) {
   if (!m->bound) return mfail(PMDG_ESTATE, "model not bound");
@@ -609,6 +1000,10 @@ pmdg_status pmdg_mlp_create(int nlayers, const int* widths, pmdg_mlp** out) {
     if (widths[l] < 1 || widths[l] > (1 << 20)) return mfail(PMDG_EINVAL, "widths must be in [1, 2^20]");
   for (int l = 1; l <= nlayers; ++l)
     if (widths[l] % 8) return mfail(PMDG_EINVAL, "hidden and output widths must be multiples of 8");
+  // a hidden layer's activations are the next layer's input rows, whose
+  // leading dimension is the input width rounded up to 32
+  for (int l = 1; l < nlayers; ++l)
+    if (widths[l] % 32) return mfail(PMDG_EINVAL, "hidden widths must be multiples of 32");
   pmdg_mlp* m = new (std::nothrow) pmdg_mlp();
   if (!m) return mfail(PMDG_ENOMEM, "out of host memory");
   m->L = nlayers;
@@ -816,6 +1211,184 @@ pmdg_status pmdg_mlp_pair_combine(const float* a, const float* b, int B, int n, 
   if (B < 1 || n < 4 || n % 4) return mfail(PMDG_EINVAL, "need B >= 1 and n a positive multiple of 4");
   if (((uintptr_t)a | (uintptr_t)b | (uintptr_t)mean) & 15) return mfail(PMDG_EINVAL, "arrays must be 16-byte aligned");
   hipLaunchKernelGGL(k_pair_combine, dim3(B), dim3(256), 0, (hipStream_t)stream, a, b, n, mean, spread);
+  MCHK(hipGetLastError());
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_mlp_fit_linear_workspace(pmdg_mlp* m, int n, int rank, size_t* bytes) {
+  if (!m || !bytes) return mfail(PMDG_EINVAL, "NULL argument");
+  if (n < 1 || rank < 1) return mfail(PMDG_EINVAL, "n and rank must be >= 1");
+  *bytes = fit_layout(m, n, rank).bytes;
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_mlp_fit_linear(pmdg_mlp* m, const float* u, const float* t, const int* idx, int nrows, int n,
+                                int npairs, int rank, float ridge, void* work, size_t work_bytes, void* stream) {
+  if (!m || !u || !t || !work) return mfail(PMDG_EINVAL, "NULL argument");
+  if (!m->bound) return mfail(PMDG_ESTATE, "model not bound");
+  if ((int)m->emb.size() != m->kin[0]) return mfail(PMDG_ESTATE, "set the input map first");
+  const int L = m->L, n0 = m->width[0], nL = m->width[L];
+  if (L < 2) return mfail(PMDG_EINVAL, "the fit needs at least one hidden layer");
+  const int Wd = m->width[1];
+  for (int l = 1; l < L; ++l)
+    if (m->width[l] != Wd) return mfail(PMDG_EINVAL, "the fit needs hidden layers of one width");
+  if (n < 1 || nrows < 1 || (!idx && nrows < n)) return mfail(PMDG_EINVAL, "bad row counts");
+  if (npairs < 0 || rank < 1 || npairs > rank || npairs + rank > Wd || rank > n0 || rank > n)
+    return mfail(PMDG_EINVAL, "need 0 <= npairs <= rank, npairs + rank <= hidden width, rank <= n_0 and rank <= n");
+  if (!(ridge >= 0.f) || !std::isfinite(ridge)) return mfail(PMDG_EINVAL, "ridge must be finite and >= 0");
+  const FitLayout f = fit_layout(m, n, rank);
+  if (((uintptr_t)work & 255) || work_bytes < f.bytes)
+    return mfail(PMDG_ENOMEM, "fit workspace must be 256-byte aligned and hold " + std::to_string(f.bytes) + " bytes");
+  hipStream_t st = (hipStream_t)stream;
+  char* w = (char*)work;
+  float *X = (float*)(w + f.X), *Xs = (float*)(w + f.Xs), *G = (float*)(w + f.G), *Bt = (float*)(w + f.Bt);
+  float *S = (float*)(w + f.S), *Md = (float*)(w + f.M), *C = (float*)(w + f.C), *Z = (float*)(w + f.Z);
+  double* part = (double*)(w + f.part);
+  unsigned* zmax = (unsigned*)(w + f.zmax);
+  // output scale: RMS of the amplitude-normalised targets over the fit rows
+  pmdg_status rs = target_scale(m, u, t, idx, nrows, n, part, st);
+  if (rs) return rs;
+  const double oscale = m->out_scale;
+  // X, Xs = X / (out_scale a); G = X^T X; Bt = Xs^T t; S = Bt Bt^T
+  hipLaunchKernelGGL(k_embed_f32, dim3((unsigned)nblk((long)n * n0, 256)), dim3(256), 0, st, u, idx, nrows, n,
+                     m->n_u, n0, at<EmbCol>(m, m->oEmb), m->amp_col, (float)(1.0 / oscale), X, Xs);
+  MCHK(hipGetLastError());
+  MCHK(sgemm(n0, n0, n, X, 1, n0, X, n0, 1, nullptr, 1.f, G, n0, st));
+  MCHK(sgemm(n0, nL, n, Xs, 1, n0, t, nL, 1, idx, 1.f, Bt, nL, st));
+  MCHK(sgemm(n0, n0, nL, Bt, nL, 1, Bt, 1, nL, nullptr, 1.f, S, n0, st));
+  std::vector<float> hG((size_t)n0 * n0), hS((size_t)n0 * n0);
+  MCHK(hipMemcpyAsync(hG.data(), G, 4 * hG.size(), hipMemcpyDeviceToHost, st));
+  MCHK(hipMemcpyAsync(hS.data(), S, 4 * hS.size(), hipMemcpyDeviceToHost, st));
+  MCHK(hipStreamSynchronize(st));
+  // host, FP64: G + ridge = L L^T; H = L^{-1} S L^{-T} = V diag(w) V^T;
+  // M0 = L^{-T} V_r gives x M0 orthonormal over the fit rows and
+  // x M0 M0^T Bt the rank-r least-squares predictor
+  std::vector<double> Gd(hG.begin(), hG.end()), H(hS.begin(), hS.end()), Lc;
+  double tr = 0;
+  for (int i = 0; i < n0; ++i) tr += Gd[(size_t)i * n0 + i];
+  const double lam = std::max((double)ridge * tr / n0, 1e-12 * tr / n0);
+  for (int i = 0; i < n0; ++i) Gd[(size_t)i * n0 + i] += lam;
+  if (!chol_lower(n0, Gd, Lc)) return mfail(PMDG_EINVAL, "the embedded columns are linearly dependent on the fit rows");
+  solve_lower(n0, n0, Lc, H);  // L^{-1} S
+  for (int i = 0; i < n0; ++i)  // transpose in place: (L^{-1} S)^T = S L^{-T}
+    for (int j = i + 1; j < n0; ++j) std::swap(H[(size_t)i * n0 + j], H[(size_t)j * n0 + i]);
+  solve_lower(n0, n0, Lc, H);  // L^{-1} S L^{-T}
+  for (int i = 0; i < n0; ++i)
+    for (int j = i + 1; j < n0; ++j) {
+      const double a = 0.5 * (H[(size_t)i * n0 + j] + H[(size_t)j * n0 + i]);
+      H[(size_t)i * n0 + j] = H[(size_t)j * n0 + i] = a;
+    }
+  std::vector<double> ev, V;
+  if (!sym_eig(n0, H, ev, V)) return mfail(PMDG_EINVAL, "eigenvalue iteration did not converge");
+  std::vector<double> M0((size_t)n0 * rank);
+  for (int i = 0; i < n0; ++i)
+    for (int c = 0; c < rank; ++c) M0[(size_t)i * rank + c] = V[(size_t)i * n0 + c];
+  solve_lower_t(n0, rank, Lc, M0);
+  // z = x M with M = alpha M0 has unit RMS per column over the fit rows
+  const double alpha = std::sqrt((double)n);
+  std::vector<float> hM((size_t)n0 * rank);
+  for (size_t i = 0; i < hM.size(); ++i) hM[i] = (float)(alpha * M0[i]);
+  MCHK(hipMemcpyAsync(Md, hM.data(), 4 * hM.size(), hipMemcpyHostToDevice, st));
+  // C = M^T Bt / alpha^2 (so that z C = x M0 M0^T Bt); Z = X M
+  MCHK(sgemm(rank, nL, n0, Md, 1, rank, Bt, nL, 1, nullptr, (float)(1.0 / (alpha * alpha)), C, nL, st));
+  MCHK(sgemm(n, rank, n0, X, n0, 1, Md, rank, 1, nullptr, 1.f, Z, rank, st));
+  MCHK(hipMemsetAsync(zmax, 0, 4, st));
+  hipLaunchKernelGGL(k_absmax_cols, dim3((unsigned)nblk((long)n * rank, 256)), dim3(256), 0, st, Z, (long)n, rank,
+                     npairs, rank, zmax);
+  MCHK(hipGetLastError());
+  unsigned zbits = 0;
+  MCHK(hipMemcpyAsync(&zbits, zmax, 4, hipMemcpyDeviceToHost, st));
+  MCHK(hipStreamSynchronize(st));
+  float zm;
+  memcpy(&zm, &zbits, 4);
+  // shift of the singly passed signals: gelu(u) = u Phi(u) is u to within
+  // 1.4e-3 u for u >= 3, with a 25% margin on the largest |z| of the fit rows
+  const float beta = npairs < rank ? 1.25f * zm + 3.0f : 0.f;
+  const int P = npairs, ns = rank - npairs;
+  // first layer: rows [M_c; -M_c] for the pairs, M_c + beta for the singles
+  {
+    const int kp = m->kin[0];
+    std::vector<float> W((size_t)Wd * kp, 0.f), b(Wd, 0.f);
+    for (int c = 0; c < P; ++c)
+      for (int i = 0; i < n0; ++i) {
+        W[(size_t)c * kp + i] = hM[(size_t)i * rank + c];
+        W[(size_t)(P + c) * kp + i] = -hM[(size_t)i * rank + c];
+      }
+    for (int c = 0; c < ns; ++c) {
+      for (int i = 0; i < n0; ++i) W[(size_t)(2 * P + c) * kp + i] = hM[(size_t)i * rank + P + c];
+      b[2 * P + c] = beta;
+    }
+    MCHK(hipMemcpy(at<float>(m, m->oW[0]), W.data(), 4 * W.size(), hipMemcpyHostToDevice));
+    MCHK(hipMemcpy(at<float>(m, m->ob[0]), b.data(), 4 * b.size(), hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)nblk((long)W.size(), 256)), dim3(256), 0, st,
+                       at<float>(m, m->oW[0]), at<bf16_t>(m, m->oWb[0]), (long)W.size());
+    MCHK(hipGetLastError());
+  }
+  // hidden layers: z_pair -> [z; -z] from (gelu(z), gelu(-z)); singles pass
+  for (int l = 1; l + 1 < L; ++l) {
+    const int kp = m->kin[l];
+    std::vector<float> W((size_t)Wd * kp, 0.f), b(Wd, 0.f);
+    for (int c = 0; c < P; ++c) {
+      W[(size_t)c * kp + c] = 1.f;
+      W[(size_t)c * kp + P + c] = -1.f;
+      W[(size_t)(P + c) * kp + c] = -1.f;
+      W[(size_t)(P + c) * kp + P + c] = 1.f;
+    }
+    for (int c = 2 * P; c < 2 * P + ns; ++c) W[(size_t)c * kp + c] = 1.f;
+    MCHK(hipMemcpy(at<float>(m, m->oW[l]), W.data(), 4 * W.size(), hipMemcpyHostToDevice));
+    MCHK(hipMemcpy(at<float>(m, m->ob[l]), b.data(), 4 * b.size(), hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)nblk((long)W.size(), 256)), dim3(256), 0, st,
+                       at<float>(m, m->oW[l]), at<bf16_t>(m, m->oWb[l]), (long)W.size());
+    MCHK(hipGetLastError());
+  }
+  // output layer from C
+  hipLaunchKernelGGL(k_fit_out_layer, dim3((unsigned)nblk((long)nL * m->kin[L - 1], 256)), dim3(256), 0, st, C, rank,
+                     P, nL, Wd, m->kin[L - 1], beta, at<float>(m, m->oW[L - 1]), at<bf16_t>(m, m->oWb[L - 1]),
+                     at<float>(m, m->ob[L - 1]));
+  MCHK(hipGetLastError());
+  for (int l = 0; l < L; ++l) {
+    const size_t nw = (size_t)m->width[l + 1] * m->kin[l], nb = m->width[l + 1];
+    MCHK(hipMemsetAsync(at<float>(m, m->omW[l]), 0, 4 * nw, st));
+    MCHK(hipMemsetAsync(at<float>(m, m->ovW[l]), 0, 4 * nw, st));
+    MCHK(hipMemsetAsync(at<float>(m, m->omb[l]), 0, 4 * nb, st));
+    MCHK(hipMemsetAsync(at<float>(m, m->ovb[l]), 0, 4 * nb, st));
+  }
+  m->adam_t = 0;
+  m->have_z = false;
+  MCHK(hipStreamSynchronize(st));
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_mlp_set_target_scale(pmdg_mlp* m, const float* u, const float* t, const int* idx, int nrows, int n,
+                                      void* work, size_t work_bytes, void* stream) {
+  if (!m || !u || !t || !work) return mfail(PMDG_EINVAL, "NULL argument");
+  if (!m->bound) return mfail(PMDG_ESTATE, "model not bound");
+  if (n < 1 || nrows < 1 || (!idx && nrows < n)) return mfail(PMDG_EINVAL, "bad row counts");
+  if (((uintptr_t)work & 7) || work_bytes < 8 * (size_t)n) return mfail(PMDG_ENOMEM, "work must hold n doubles");
+  return target_scale(m, u, t, idx, nrows, n, (double*)work, (hipStream_t)stream);
+}
+
+pmdg_status pmdg_mlp_out_scale(pmdg_mlp* m, float* out_scale) {
+  if (!m || !out_scale) return mfail(PMDG_EINVAL, "NULL argument");
+  *out_scale = m->out_scale;
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_mlp_row_errors(const float* y, const float* t, const int* idx, int nrows, int B, int n, float* err,
+                                void* stream) {
+  if (!y || !t || !err) return mfail(PMDG_EINVAL, "NULL argument");
+  if (B < 1 || n < 1 || nrows < 1 || (!idx && nrows < B)) return mfail(PMDG_EINVAL, "bad sizes");
+  hipLaunchKernelGGL(k_row_relerr, dim3(B), dim3(256), 0, (hipStream_t)stream, y, t, idx, nrows, n, err);
+  MCHK(hipGetLastError());
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_mlp_scatter_rows(const float* src, const int* rows, int nr, int n, float* dst, void* stream) {
+  if (!src || !rows || !dst) return mfail(PMDG_EINVAL, "NULL argument");
+  if (nr < 0 || n < 1) return mfail(PMDG_EINVAL, "bad sizes");
+  if (nr == 0) return PMDG_OK;
+  hipLaunchKernelGGL(k_scatter_rows, dim3((unsigned)nblk((long)nr * n, 256)), dim3(256), 0, (hipStream_t)stream, src,
+                     rows, nr, n, dst);
   MCHK(hipGetLastError());
   return PMDG_OK;
 }

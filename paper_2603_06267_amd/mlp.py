@@ -112,6 +112,32 @@ class MLP:
                                          float(b1), float(b2), float(eps), _ptr(rowerr), _ptr(rownorm),
                                          _stream_ptr(stream)))
 
+    def fit_linear(self, u, t, idx, n, npairs, rank, ridge=0.0, stream=None):
+        """Least-squares fit of the whole network on rows idx[:n] of (u, t)
+        (pmdg_mlp_fit_linear); the fit workspace is a temporary torch buffer."""
+        import torch
+        nb = ctypes.c_size_t()
+        check(self.L.pmdg_mlp_fit_linear_workspace(self.h, int(n), int(rank), ctypes.byref(nb)))
+        work = torch.empty(nb.value + 256, dtype=torch.uint8, device=u.device)
+        ptr = (work.data_ptr() + 255) // 256 * 256
+        check(self.L.pmdg_mlp_fit_linear(self.h, _ptr(u), _ptr(t), _ptr(idx), int(u.shape[0]), int(n), int(npairs),
+                                         int(rank), float(ridge), ctypes.c_void_p(ptr), nb.value,
+                                         _stream_ptr(stream)))
+        del work
+
+    def set_target_scale(self, u, t, idx, n, stream=None):
+        """out_scale = RMS of t / a over rows idx[:n] (pmdg_mlp_set_target_scale)."""
+        import torch
+        work = torch.empty(int(n), dtype=torch.float64, device=u.device)
+        check(self.L.pmdg_mlp_set_target_scale(self.h, _ptr(u), _ptr(t), _ptr(idx), int(u.shape[0]), int(n),
+                                               _ptr(work), 8 * int(n), _stream_ptr(stream)))
+
+    @property
+    def out_scale(self):
+        v = ctypes.c_float()
+        check(self.L.pmdg_mlp_out_scale(self.h, ctypes.byref(v)))
+        return v.value
+
     def close(self):
         if getattr(self, "h", None):
             self.L.pmdg_mlp_destroy(self.h)
@@ -144,3 +170,19 @@ def columns_from_kinds(kind, shift, scale):
         else:
             cols += [(c, 1, 0.0, 1.0), (c, 2, 0.0, 1.0)]
     return cols
+
+
+def row_errors(y, t, idx=None, stream=None):
+    """err[r] = ||y_r - t[idx[r]]|| / ||t[idx[r]]|| on the device."""
+    import torch
+    B, n = y.shape
+    err = torch.empty(B, dtype=torch.float32, device=y.device)
+    check(lib().pmdg_mlp_row_errors(_ptr(y), _ptr(t), _ptr(idx), int(t.shape[0]), int(B), int(n), _ptr(err),
+                                    _stream_ptr(stream)))
+    return err
+
+
+def scatter_rows(src, rows, dst, stream=None):
+    """dst[rows[i]] = src[i] on the device (rows: device int32)."""
+    nr, n = src.shape
+    check(lib().pmdg_mlp_scatter_rows(_ptr(src), _ptr(rows), int(nr), int(n), _ptr(dst), _stream_ptr(stream)))

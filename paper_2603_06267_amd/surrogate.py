@@ -6,13 +6,19 @@ estimate and the solver as fallback.
   data       the GPU solver (FP32 state, FP64 modal ODE and traces) on the
              seeded scenarios of the surrogate data set, one batched launch
   network    18 drive parameters -> 512 -> 512 -> 512 -> 512 -> 32768, GELU,
-             trained by the library's BF16-MFMA forward / backward / Adam
-             kernels.  Each phase enters as the pair (cos, sin) (phases are
-             angles, 34 network inputs in all), frequency and amplitude
-             affinely; the output is scaled by the amplitude, since the
-             solver's traces are exactly proportional to it
-  estimate   a two-member ensemble (different initialisations and minibatch
-             orders); its spread |y_1 - y_2| / |(y_1 + y_2) / 2|, scaled by the
+             run by the library's BF16-MFMA kernels.  Each phase enters as
+             the pair (cos, sin) (phases are angles), frequency and amplitude
+             affinely, and each phase column also times a cosine series in
+             frequency (N_COS terms): the solver is linear in each PMUT's
+             drive, so the traces are a linear function of those products.
+             Training: the least-squares fit of the library
+             (pmdg_mlp_fit_linear) writes the network that computes the best
+             rank-RANK linear map of the inputs; Adam on the library's forward
+             / backward kernels (fit) remains available.  The output is scaled
+             by the amplitude, since the solver's traces are exactly
+             proportional to it
+  estimate   a two-member ensemble (members fitted on disjoint halves of the
+             training rows); its spread |y_1 - y_2| / |(y_1 + y_2) / 2|, scaled by the
              split-conformal quantile of (true error / spread) on a held-out
              calibration set, bounds the relative L2 error of the ensemble
              mean with the stated coverage
@@ -35,16 +41,24 @@ HIDDEN = [512, 512, 512, 512]
 N_OUT = 64 * 512
 N_PMUT = 16
 TOL = 0.02
+# default network input and least-squares fit: cosine series of 24 terms in
+# frequency times each phase column (770 inputs), rank 416 with the leading
+# 96 directions passed as pairs (96 x 2 + 320 = 512 hidden units)
+N_COS = 24
+RANK = 416
+N_PAIRS = 96
 
 
 AMP_COL = N_PMUT + 1
 FREQ_COL = N_PMUT
+# drive frequencies of the data set, U[F_LO, F_LO + F_SPAN] MHz
+F_LO, F_SPAN = 1.5, 1.5
 # sampled trace length (512 steps of the cube's dt = 8.634 ns), for the
 # frequency's Fourier columns
 T_TRACE_US = 4.42
 
 
-def input_columns(n_fourier=0, n_product=0):
+def input_columns(n_fourier=0, n_product=0, n_cos=0):
     """Embedding of the raw features [phase x16, frequency (MHz), amplitude]:
     each phase as (cos, sin) (phases are angles), frequency in [1.5, 3] and
     amplitude in [0.5, 1] mapped affinely onto [-1, 1], and optionally
@@ -54,7 +68,12 @@ def input_columns(n_fourier=0, n_product=0):
     its products with cos / sin(2 pi tau_j f), tau_j = j T / n_product: the
     traces are linear in each PMUT's drive (A cos theta_k, A sin theta_k), so
     these products span their dependence on phase and frequency together,
-    which a network would otherwise have to form from separate columns."""
+    which a network would otherwise have to form from separate columns.
+    n_cos > 0 adds the products of every phase column with the cosine series
+    cos(pi j (f - F_LO) / F_SPAN), j = 1 .. n_cos - 1: over the data set's
+    uniform frequencies these are orthogonal to one another and to the phase
+    columns (condition number of the embedded rows about 3), so a linear
+    least-squares map on them is well posed in FP32 and BF16."""
     cols = []
     for k in range(N_PMUT):
         cols += [(k, 1, 0.0, 1.0), (k, 2, 0.0, 1.0)]
@@ -67,6 +86,10 @@ def input_columns(n_fourier=0, n_product=0):
             for j in range(1, n_product + 1):
                 w = 2.0 * math.pi * j * T_TRACE_US / n_product
                 cols += [(k, op, 0.0, 1.0, FREQ_COL, 1, 0.0, w), (k, op, 0.0, 1.0, FREQ_COL, 2, 0.0, w)]
+    for k in range(N_PMUT):
+        for op in (1, 2):
+            for j in range(1, n_cos):
+                cols.append((k, op, 0.0, 1.0, FREQ_COL, 1, -math.pi * j * F_LO / F_SPAN, math.pi * j / F_SPAN))
     return cols
 
 
@@ -97,8 +120,8 @@ def solve(F, steps=512, device="cuda", stream=None, max_scenarios=4096):
 
 class Surrogate:
     def __init__(self, n_members=2, max_batch=1024, seed=0, device="cuda", n_fourier=0, hidden=None, n_out=N_OUT,
-                 n_product=0):
-        self.columns = input_columns(n_fourier, n_product)
+                 n_product=0, n_cos=0):
+        self.columns = input_columns(n_fourier, n_product, n_cos)
         self.widths = [len(self.columns)] + list(hidden or HIDDEN) + [n_out]
         self.members = [_mlp.MLP(self.widths, max_batch=max_batch, device=device) for _ in range(n_members)]
         self.max_batch = max_batch
@@ -114,10 +137,11 @@ class Surrogate:
         Each member: He initialisation from its own seed, its own minibatch
         order, Adam with a cosine learning-rate decay from lr to lr_final."""
         import torch
-        tr = torch.as_tensor(np.asarray(train_idx), dtype=torch.long, device=U.device)
+        tr = torch.as_tensor(np.asarray(train_idx).astype(np.int32), device=U.device)
         # RMS of the amplitude-normalised training traces
-        amp = U[tr, AMP_COL:AMP_COL + 1]
-        self.out_scale = float(torch.sqrt(((T[tr] / amp) ** 2).mean()).item())
+        self.members[0].set_io_map(N_PMUT + 2, self.columns, amp_col=AMP_COL)
+        self.members[0].set_target_scale(U, T, tr, len(train_idx))
+        self.out_scale = self.members[0].out_scale
         err = torch.empty(batch, dtype=torch.float32, device=U.device)
         nrm = torch.empty(batch, dtype=torch.float32, device=U.device)
         ntr = len(train_idx)
@@ -142,6 +166,40 @@ class Surrogate:
                     self.history.append((k, s, rel))
                     log(f"member {k} step {s}: minibatch median rel L2 {rel:.4f} "
                         f"({time.perf_counter() - t0:.1f} s)")
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    def fit_linear(self, U, T, train_idx, npairs=96, rank=416, ridge=0.0, finetune_steps=0, batch=256, lr=1e-5):
+        """Least-squares training (pmdg_mlp_fit_linear): the training rows are
+        split into disjoint parts by a seeded permutation, one per member, and
+        each member is fitted on its own part, so that the members' spread
+        reflects what the data leave undetermined.  finetune_steps > 0 then
+        runs that many Adam steps per member on all training rows (cosine
+        decay from lr)."""
+        import torch
+        t0 = time.perf_counter()
+        rng = np.random.default_rng(self.seed)
+        perm = np.asarray(train_idx)[rng.permutation(len(train_idx))]
+        parts = np.array_split(perm, len(self.members))
+        for m, part in zip(self.members, parts):
+            m.set_io_map(N_PMUT + 2, self.columns, amp_col=AMP_COL)
+            idx = torch.as_tensor(np.sort(part).astype(np.int32), device=U.device)
+            m.fit_linear(U, T, idx, len(part), npairs, rank, ridge)
+        self.out_scale = self.members[0].out_scale
+        if finetune_steps > 0:
+            err = torch.empty(batch, dtype=torch.float32, device=U.device)
+            nrm = torch.empty(batch, dtype=torch.float32, device=U.device)
+            ntr = len(train_idx)
+            per_epoch = ntr // batch
+            for k, m in enumerate(self.members):
+                g = np.random.default_rng(self.seed + 1000 * k + 1)
+                for s in range(finetune_steps):
+                    if s % per_epoch == 0:
+                        order = np.asarray(train_idx)[g.permutation(ntr)][:per_epoch * batch]
+                        sel = torch.as_tensor(order.astype(np.int32), device=U.device)
+                    j = s % per_epoch
+                    a = 0.5 * lr * (1 + math.cos(math.pi * s / finetune_steps))
+                    m.train_step(U, T, sel[j * batch:(j + 1) * batch], a, rowerr=err, rownorm=nrm)
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
@@ -179,8 +237,7 @@ class Surrogate:
             rr = np.concatenate([r, np.repeat(r[-1:], pad)]) if pad else r
             idx = torch.as_tensor(rr.astype(np.int32), device=U.device)
             mean, spread = self.predict(U, idx=idx)
-            t = T[torch.as_tensor(rr, device=U.device)]
-            e = torch.linalg.vector_norm(mean - t, dim=1) / torch.linalg.vector_norm(t, dim=1)
+            e = _mlp.row_errors(mean, T, idx)
             errs.append(e[:len(r)].cpu().numpy())
             spreads.append(spread[:len(r)].cpu().numpy())
         return np.concatenate(errs), np.concatenate(spreads)
@@ -203,7 +260,7 @@ class Surrogate:
         if mask.any():
             rows = np.nonzero(mask)[0]
             sol = solve(np.asarray(F)[rows], stream=stream)
-            mean[torch.as_tensor(rows, device=mean.device)] = sol
+            _mlp.scatter_rows(sol, torch.as_tensor(rows.astype(np.int32), device=mean.device), mean, stream=stream)
         return mean, mask, est
 
 

@@ -159,6 +159,7 @@ def test_mlp_host_checks():
 
     assert create([18, 512, 30]) == _lib.PMDG_EINVAL      # output width not a multiple of 8
     assert create([18, 0, 32]) == _lib.PMDG_EINVAL
+    assert create([18, 16, 16, 64]) == _lib.PMDG_EINVAL  # hidden widths are multiples of 32
     assert L.pmdg_mlp_create(0, None, ctypes.byref(h)) == _lib.PMDG_EINVAL
     assert create([18, 512, 512, 512, 512, 32768]) == _lib.PMDG_OK
     n = ctypes.c_long()
@@ -184,5 +185,13 @@ def test_mlp_host_checks():
     assert L.pmdg_mlp_set_io_factors(h, 18, ints(2), ints(1), flts(0), flts(float("inf")), None) == _lib.PMDG_EINVAL
     assert L.pmdg_mlp_set_io_factors(h, 18, ints(2), ints(1), flts(0), flts(1), None) == _lib.PMDG_OK
     assert L.pmdg_mlp_set_io_factors(h, 18, None, ints(1), flts(0), flts(1), None) == _lib.PMDG_EINVAL
+    # least-squares fit: sizes on the host, compute calls need a bound model
+    assert L.pmdg_mlp_fit_linear_workspace(h, 3584, 416, ctypes.byref(sz)) == _lib.PMDG_OK
+    assert sz.value > 4 * 18 * 32768
+    assert L.pmdg_mlp_fit_linear_workspace(h, 0, 416, ctypes.byref(sz)) == _lib.PMDG_EINVAL
+    assert L.pmdg_mlp_fit_linear(h, x, x, None, 100, 100, 4, 10, 0.0, x, 1 << 30, None) == _lib.PMDG_ESTATE
+    assert L.pmdg_mlp_set_target_scale(h, x, x, None, 100, 100, x, 800, None) == _lib.PMDG_ESTATE
+    assert L.pmdg_mlp_row_errors(None, x, None, 8, 8, 8, x, None) == _lib.PMDG_EINVAL
+    assert L.pmdg_mlp_scatter_rows(x, x, -1, 8, x, None) == _lib.PMDG_EINVAL
     L.pmdg_mlp_destroy(h)
     L.pmdg_mlp_destroy(None)

@@ -257,3 +257,61 @@ def test_pair_combine():
     assert np.array_equal(mean, (0.5 * (a.astype(np.float64) + b)).astype(np.float32))
     exp = np.linalg.norm(a.astype(np.float64) - b, axis=1) / np.linalg.norm(0.5 * (a.astype(np.float64) + b), axis=1)
     assert np.abs(spread.cpu().numpy() - exp).max() < 1e-5 * exp.max()
+
+
+def _lsq_rank(X, Y, r):
+    """Best rank-r linear predictor of Y from X over the rows (FP64): the
+    projection of Y on the column space of X, truncated to its r leading
+    singular directions."""
+    Q, _ = np.linalg.qr(X)
+    P = Q.T @ Y
+    U, s, Vt = np.linalg.svd(P, full_matrices=False)
+    return Q @ (U[:, :r] * s[:r]) @ Vt[:r]
+
+
+@pytest.mark.parametrize("noise", [0.0, 0.3])
+def test_fit_linear_against_numpy_lsq(noise):
+    """pmdg_mlp_fit_linear on a reduced twin (3 phases, cosine-series product
+    columns, hidden width 32, rank 20 with 8 pairs and 12 shifted singles):
+    the network it writes reproduces the rank-20 least-squares predictor of
+    the targets (computed here with NumPy in FP64), to the BF16 tolerance, and
+    an exactly rank-20 linear target is reproduced; out_scale is the RMS of
+    t / a over the fit rows.  Tolerance 2e-2: besides the BF16 roundings of a
+    plain network (1e-2 above), each singly passed signal is carried as
+    z + beta with beta about 8 rms(z), so its BF16 rounding is about 8 times
+    larger relative to z; here, unlike the surrogate's decaying spectrum,
+    those signals weigh as much as the paired ones."""
+    import math
+    import torch
+    rng = np.random.default_rng(21)
+    n = 400
+    F = np.concatenate([rng.uniform(0, 2 * math.pi, (n, 3)), rng.uniform(1.5, 3, (n, 1)),
+                        rng.uniform(0.5, 1, (n, 1))], axis=1).astype(np.float32)
+    cols = []
+    for k in range(3):
+        cols += [(k, 1, 0.0, 1.0), (k, 2, 0.0, 1.0)]
+    cols += [(3, 0, 2.25, 1 / 0.75), (4, 0, 0.75, 4.0)]
+    for k in range(3):
+        for op in (1, 2):
+            for j in range(1, 6):
+                cols.append((k, op, 0.0, 1.0, 3, 1, -math.pi * j, math.pi * j / 1.5))
+    n0, r, P, nL = len(cols), 20, 8, 64
+    X = R.embed(F.astype(np.float64), [tuple(float(np.float32(v)) if i in (2, 3, 6, 7) else v for i, v in enumerate(c))
+                                       for c in cols])
+    Wt = rng.standard_normal((n0, r)) @ rng.standard_normal((r, nL))
+    a = F[:, 4:5].astype(np.float64)
+    T = a * (X @ Wt + noise * rng.standard_normal((n, nL)))
+    m = _model([n0, 32, 32, 32, nL], 400)
+    m.set_io_map(5, cols, amp_col=4)
+    U, Td = _dev(F), _dev(T)
+    idx = _dev(np.arange(n, dtype=np.int32), dtype=torch.int32)
+    m.fit_linear(U, Td, idx, n, P, r)
+    s = m.out_scale
+    assert abs(s - np.sqrt(np.mean((T / a) ** 2))) < 1e-5 * s
+    y = m.forward(U).cpu().numpy()
+    ref = a * _lsq_rank(X, T / a, r)
+    err = rel_l2(y, ref)
+    _say(f"  fit_linear noise={noise}: network vs rank-{r} least squares rel L2 {err:.2e}")
+    assert err < 2e-2
+    if noise == 0.0:
+        assert rel_l2(y, T) < 2e-2

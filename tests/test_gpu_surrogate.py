@@ -1,8 +1,9 @@
 """Surrogate form end to end on the GPU: training data from the GPU solver
-(checked against the oracle), two-member BF16-MFMA training, split-conformal
-calibration of the error estimate, inference with solver fallback at the 2%
-relative-L2 tolerance, and the throughput of that pipeline against the plain
-solver.
+(checked against the oracle), two members fitted by least squares (each on
+its own half of the training rows) and run by the BF16-MFMA kernels,
+split-conformal calibration of the error estimate, inference with solver
+fallback at the 2% relative-L2 tolerance, and the throughput of that pipeline
+against the plain solver, one scenario at a time and batched.
 
 The data set is the surrogate workload (4096 seeded scenarios of the cube with
 a 4x4 PMUT array; 3584 train, 256 calibration, 256 test)."""
@@ -43,9 +44,9 @@ def data():
 @pytest.fixture(scope="module")
 def trained(data):
     F, U, T = data
-    sur = S.Surrogate(n_members=2, seed=3)
-    el = sur.fit(U, T, TRAIN, steps=3000, log=_say, log_every=1000)
-    _say(f"trained 2 members x 3000 steps in {el:.1f} s")
+    sur = S.Surrogate(n_members=2, seed=3, n_cos=S.N_COS)
+    el = sur.fit_linear(U, T, TRAIN, npairs=S.N_PAIRS, rank=S.RANK)
+    _say(f"fitted 2 members ({len(sur.columns)} input columns, rank {S.RANK}) in {el:.1f} s")
     scale = sur.calibrate(U, T, CAL)
     _say(f"calibration scale (95% split-conformal) {scale:.3f}")
     return sur
@@ -65,26 +66,34 @@ def test_training_data_matches_oracle(data):
         assert err < 1e-5
 
 
-def test_calibrated_estimate_covers(data, trained):
-    """On held-out test rows the calibrated estimate bounds the true error of
-    the ensemble mean for about 95% of them (split-conformal; 256 rows)."""
+def test_held_out_error_and_coverage(data, trained):
+    """On the 256 held-out test rows the ensemble mean is within 2% relative
+    L2 of the solver at the median, and the calibrated estimate bounds the
+    true error for about 95% of them (split-conformal; 256 rows, so at least
+    90% here)."""
     F, U, T = data
     err, spread = trained.errors(U, T, TEST)
     est = trained.estimate(spread)
     cover = float(np.mean(err <= est))
     _say(f"  test rows: network rel L2 median {np.median(err):.4f}, p90 {np.quantile(err, 0.9):.4f}; "
-         f"coverage {cover:.3f}")
-    assert cover >= 0.88
+         f"coverage {cover:.3f}; estimate <= 2% for {np.mean(est <= S.TOL):.3f}")
+    assert np.median(err) <= S.TOL
+    assert cover >= 0.90
+    # the estimate separates: most rows are certified at 2%
+    assert np.mean(est <= S.TOL) >= 0.5
 
 
 def test_fallback_delivers_tolerance_and_gain(data, trained):
     """Inference with fallback on the 256 test scenarios: rows whose estimate
     exceeds 2% carry the solver's traces, bitwise; the delivered traces meet
     2% except for the estimate's non-covered share; the pipeline's
-    scenarios/s is above the plain single-scenario solver's."""
+    scenarios/s is above the plain solver's, one scenario at a time and in one
+    batched launch for all 256 (the method without the network)."""
     import torch
     F, U, T = data
     rows = TEST
+    trained.infer(F[rows])  # warm
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     out, mask, est = trained.infer(F[rows])
     torch.cuda.synchronize()
@@ -96,12 +105,23 @@ def test_fallback_delivers_tolerance_and_gain(data, trained):
     if mask.any():
         assert torch.equal(out[torch.as_tensor(np.nonzero(mask)[0], device="cuda")],
                            t[torch.as_tensor(np.nonzero(mask)[0], device="cuda")])
-    assert (err > S.TOL).mean() <= 0.12
+    assert (err > S.TOL).mean() <= 0.08
+    assert mask.mean() < 0.5
     # the plain solver one scenario at a time (8 of them, timed)
     t0 = time.perf_counter()
     for r in rows[:8]:
         S.solve(F[r:r + 1])
     torch.cuda.synchronize()
     single = 8 / (time.perf_counter() - t0)
-    _say(f"  plain single-scenario solver: {single:.1f} scenarios/s; pipeline gain {len(rows) / el / single:.1f}x")
-    assert len(rows) / el > single
+    # and batched: all 256 test scenarios in one launch
+    S.solve(F[rows[:8]])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.solve(F[rows])
+    torch.cuda.synchronize()
+    batched = len(rows) / (time.perf_counter() - t0)
+    pipe = len(rows) / el
+    _say(f"  plain solver: {single:.1f} scenarios/s one at a time, {batched:.1f} batched; pipeline gain "
+         f"{pipe / single:.1f}x and {pipe / batched:.2f}x")
+    assert pipe > single
+    assert pipe > batched
