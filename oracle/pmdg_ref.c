@@ -22,6 +22,9 @@
  *     synchronised ordering (the ODE samples the predicted pressure at the new
  *     time level); the printed ordering is kept behind a switch for tests.
  *   - The smooth drive window g(t) (Sec. 6.1, eq. voltage).
+ *   - First-order absorbing faces and the perfectly matched layer (Sec. 2,
+ *     eq. full_problem: the damping alpha p_t + beta p, the auxiliary fields
+ *     Phi and psi, the profile zeta_i and its constant).
  *
  * Written for clarity, not speed: element loops, explicit Lagrange products,
  * no blocking.  OpenMP is used only over element colours so that no two
@@ -159,6 +162,13 @@ typedef struct {
   double *mass;
   double *cabs;      /* absorbing-boundary matrix C (diagonal), or NULL */
   double *p, *pd, *pdd;
+  /* perfectly matched layer, per domain (Sec. 2, eq. full_problem) */
+  int pml_on[2];
+  double *pzeta[2][3];  /* zeta_i of the layer at the node coordinates of axis i, [nn[i]] */
+  long *eslot[2];       /* element -> slot of its Phi values, or -1 */
+  long nel[2];          /* elements with zeta > 0 at one of their nodes */
+  double *Phi[2];       /* [nel][3][(N+1)^3], element-wise at the GLL nodes */
+  double *psi;          /* [ntot], psi_t = p */
   /* interface quadrature-point list (fine-face points mapped to coarse side) */
   int nq;
   double gq[RMAXQ], gw[RMAXQ];
@@ -490,6 +500,11 @@ void pmdg_ref_destroy(void *h) {
   free_pmuts(s);
   free(s->mass); free(s->cabs); free(s->p); free(s->pd); free(s->pdd);
   free(s->q_ce); free(s->q_xi); free(s->rcv);
+  for (int d = 0; d < 2; ++d) {
+    for (int a = 0; a < 3; ++a) free(s->pzeta[d][a]);
+    free(s->eslot[d]); free(s->Phi[d]);
+  }
+  free(s->psi);
   free(s);
 }
 
@@ -753,6 +768,175 @@ static double receiver_value(const rsolver *s, int r, const double *p) {
 }
 
 /* ------------------------------------------------------------------ */
+/* Perfectly matched layer (Sec. 2, eq. full_problem)                  */
+/* ------------------------------------------------------------------ */
+
+/* The damping profile of Sec. 2 at distance d into a layer of thickness ell:
+ * zeta = zt (d / ell - sin(2 pi d / ell) / (2 pi)) on [0, ell], zero outside,
+ * with zt = (c / ell) log(1 / R). */
+static double pml_profile(double d, double ell, double c, double R) {
+  if (!(ell > 0) || d <= 0) return 0.0;
+  if (d > ell) d = ell;
+  double zt = c / ell * log(1.0 / R);
+  return zt * (d / ell - sin(2.0 * M_PI * d / ell) / (2.0 * M_PI));
+}
+
+/* Layers of thickness ell[2a] (low end of axis a) and ell[2a + 1] (high end)
+ * inside domain dd, with reflection coefficient R: zeta_a at every node
+ * coordinate of axis a is the profile of the layer the node lies in (the
+ * distance counted from the layer's inner face), 0 elsewhere.  The interface
+ * faces of two coupled domains (primary top, secondary bottom) carry no
+ * layer.  Elements with zeta > 0 at one of their nodes hold the auxiliary
+ * field Phi; psi is kept at every node.  Returns 0, or -1 on bad input. */
+int pmdg_ref_set_pml(void *h, int dd, const double *ell, double R) {
+  rsolver *s = (rsolver *)h;
+  if (dd < 0 || dd >= s->ndom || !(R > 0 && R < 1)) return -1;
+  rdom *d = &s->d[dd];
+  for (int a = 0; a < 3; ++a) {
+    double L = d->h[a] * d->ne[a];
+    if (ell[2 * a] < 0 || ell[2 * a + 1] < 0 || ell[2 * a] + ell[2 * a + 1] > L) return -1;
+  }
+  if (s->ndom == 2 && ((dd == 0 && ell[5] > 0) || (dd == 1 && ell[4] > 0))) return -1;
+  for (int a = 0; a < 3; ++a) {
+    free(s->pzeta[dd][a]);
+    s->pzeta[dd][a] = (double *)calloc(d->nn[a], sizeof(double));
+    double lo = d->x0[a] + ell[2 * a], hi = d->x0[a] + d->h[a] * d->ne[a] - ell[2 * a + 1];
+    for (int i = 0; i < d->nn[a]; ++i) {
+      double x = node_coord(d, a, i);
+      double z = 0.0;
+      if (ell[2 * a] > 0 && x < lo) z = pml_profile(lo - x, ell[2 * a], d->c, R);
+      if (ell[2 * a + 1] > 0 && x > hi) z = pml_profile(x - hi, ell[2 * a + 1], d->c, R);
+      s->pzeta[dd][a][i] = z;
+    }
+  }
+  int N = d->N, n3 = (N + 1) * (N + 1) * (N + 1);
+  long ne = (long)d->ne[0] * d->ne[1] * d->ne[2];
+  free(s->eslot[dd]);
+  s->eslot[dd] = (long *)malloc(sizeof(long) * ne);
+  long nel = 0;
+  for (int ez = 0; ez < d->ne[2]; ++ez)
+    for (int ey = 0; ey < d->ne[1]; ++ey)
+      for (int ex = 0; ex < d->ne[0]; ++ex) {
+        int any = 0;
+        for (int m = 0; m <= N; ++m)
+          any |= s->pzeta[dd][0][N * ex + m] > 0 || s->pzeta[dd][1][N * ey + m] > 0 || s->pzeta[dd][2][N * ez + m] > 0;
+        s->eslot[dd][ex + (long)d->ne[0] * (ey + (long)d->ne[1] * ez)] = any ? nel++ : -1;
+      }
+  s->nel[dd] = nel;
+  free(s->Phi[dd]);
+  s->Phi[dd] = (double *)calloc((size_t)(nel > 0 ? nel : 1) * 3 * n3, sizeof(double));
+  if (!s->psi) s->psi = (double *)calloc(s->ntot, sizeof(double));
+  s->pml_on[dd] = nel > 0;
+  return 0;
+}
+
+/* zeta of axis a of domain dd at that axis's node coordinates (zeros without
+ * a layer), out[nn[a]]. */
+void pmdg_ref_pml_profile(void *h, int dd, int a, double *out) {
+  rsolver *s = (rsolver *)h;
+  for (int i = 0; i < s->d[dd].nn[a]; ++i) out[i] = s->pzeta[dd][a] ? s->pzeta[dd][a][i] : 0.0;
+}
+
+/* Element-local gradient (d/dx, d/dy, d/dz) of the nodal field u at the GLL
+ * node (a, b, c) of element (ex, ey, ez): the derivative of the element's
+ * polynomial, D by the metric 2 / h per axis. */
+static void elem_grad(const rdom *d, const double *u, int ex, int ey, int ez, int a, int b, int c, double g[3]) {
+  int N = d->N;
+  g[0] = g[1] = g[2] = 0.0;
+  for (int m = 0; m <= N; ++m) {
+    g[0] += d->D[a][m] * u[nidx(d, N * ex + m, N * ey + b, N * ez + c)];
+    g[1] += d->D[b][m] * u[nidx(d, N * ex + a, N * ey + m, N * ez + c)];
+    g[2] += d->D[c][m] * u[nidx(d, N * ex + a, N * ey + b, N * ez + m)];
+  }
+  for (int k = 0; k < 3; ++k) g[k] *= 2.0 / d->h[k];
+}
+
+/* Phi_t = Z1 Phi + c^2 Z2 grad p + c^2 Z3 grad psi at every GLL node of every
+ * layer element, Z1 = diag(-zeta_i), Z2 = diag(alpha - 2 zeta_i), Z3 =
+ * diag(zeta_j zeta_k), by the trapezoidal rule over one step: p and psi
+ * enter as the averages of their old and new values, so that
+ * (1 + dt/2 zeta_i) Phi_i^{n+1} = (1 - dt/2 zeta_i) Phi_i^n
+ *   + dt c^2 ((alpha - 2 zeta_i) d_i pbar + zeta_j zeta_k d_i psibar). */
+static void pml_update_phi(rsolver *s, const double *pold, const double *pnew, const double *psiold,
+                           const double *psinew) {
+  double dt = s->dt;
+  for (int dd = 0; dd < s->ndom; ++dd) {
+    if (!s->pml_on[dd]) continue;
+    rdom *d = &s->d[dd];
+    int N = d->N, n1 = N + 1, n3 = n1 * n1 * n1;
+    double c2 = d->c * d->c;
+#pragma omp parallel for schedule(static)
+    for (long e = 0; e < (long)d->ne[0] * d->ne[1] * d->ne[2]; ++e) {
+      long slot = s->eslot[dd][e];
+      if (slot < 0) continue;
+      int ex = (int)(e % d->ne[0]), ey = (int)((e / d->ne[0]) % d->ne[1]), ez = (int)(e / ((long)d->ne[0] * d->ne[1]));
+      double *Ph = s->Phi[dd] + (size_t)slot * 3 * n3;
+      for (int c = 0; c <= N; ++c)
+        for (int b = 0; b <= N; ++b)
+          for (int a = 0; a <= N; ++a) {
+            double z[3] = {s->pzeta[dd][0][N * ex + a], s->pzeta[dd][1][N * ey + b], s->pzeta[dd][2][N * ez + c]};
+            double al = z[0] + z[1] + z[2];
+            double g0[3], g1[3], s0[3], s1[3];
+            elem_grad(d, pold, ex, ey, ez, a, b, c, g0);
+            elem_grad(d, pnew, ex, ey, ez, a, b, c, g1);
+            elem_grad(d, psiold, ex, ey, ez, a, b, c, s0);
+            elem_grad(d, psinew, ex, ey, ez, a, b, c, s1);
+            int q = a + n1 * (b + n1 * c);
+            for (int i = 0; i < 3; ++i) {
+              double zjk = z[(i + 1) % 3] * z[(i + 2) % 3];
+              double rhs = c2 * ((al - 2.0 * z[i]) * 0.5 * (g0[i] + g1[i]) + zjk * 0.5 * (s0[i] + s1[i]));
+              double *ph = &Ph[i * n3 + q];
+              *ph = ((1.0 - 0.5 * dt * z[i]) * *ph + dt * rhs) / (1.0 + 0.5 * dt * z[i]);
+            }
+          }
+    }
+  }
+}
+
+/* r += (Phi, grad v_i) over the layer elements (the weak form of
+ * -div Phi with Phi.n = 0 on the outer boundary), GLL quadrature at the
+ * element's nodes, where Phi is stored. */
+static void pml_weak_div(const rsolver *s, double *r) {
+  for (int dd = 0; dd < s->ndom; ++dd) {
+    if (!s->pml_on[dd]) continue;
+    const rdom *d = &s->d[dd];
+    int N = d->N, n1 = N + 1, n3 = n1 * n1 * n1;
+    double J = d->h[0] * d->h[1] * d->h[2] / 8.0;
+    for (int colour = 0; colour < 8; ++colour) {
+      int cx = colour & 1, cy = (colour >> 1) & 1, cz = (colour >> 2) & 1;
+      int nx = (d->ne[0] - cx + 1) / 2, ny = (d->ne[1] - cy + 1) / 2, nz = (d->ne[2] - cz + 1) / 2;
+      long tot = (long)nx * ny * nz;
+#pragma omp parallel for schedule(static)
+      for (long t = 0; t < tot; ++t) {
+        int ex = cx + 2 * (int)(t % nx), ey = cy + 2 * (int)((t / nx) % ny), ez = cz + 2 * (int)(t / ((long)nx * ny));
+        long slot = s->eslot[dd][ex + (long)d->ne[0] * (ey + (long)d->ne[1] * ez)];
+        if (slot < 0) continue;
+        const double *Ph = s->Phi[dd] + (size_t)slot * 3 * n3;
+        for (int c = 0; c <= N; ++c)
+          for (int b = 0; b <= N; ++b)
+            for (int a = 0; a <= N; ++a) {
+              int q = a + n1 * (b + n1 * c);
+              double wq = d->wg[a] * d->wg[b] * d->wg[c] * J;
+              for (int m = 0; m <= N; ++m) {
+                r[nidx(d, N * ex + m, N * ey + b, N * ez + c)] += wq * (2.0 / d->h[0]) * d->D[a][m] * Ph[q];
+                r[nidx(d, N * ex + a, N * ey + m, N * ez + c)] += wq * (2.0 / d->h[1]) * d->D[b][m] * Ph[n3 + q];
+                r[nidx(d, N * ex + a, N * ey + b, N * ez + m)] += wq * (2.0 / d->h[2]) * d->D[c][m] * Ph[2 * n3 + q];
+              }
+            }
+      }
+    }
+  }
+}
+
+/* alpha, beta, gamma of Sec. 2 at node (i, j, k) of domain dd. */
+static void pml_coeffs(const rsolver *s, int dd, int i, int j, int k, double *al, double *be, double *ga) {
+  double z0 = s->pzeta[dd][0][i], z1 = s->pzeta[dd][1][j], z2 = s->pzeta[dd][2][k];
+  *al = z0 + z1 + z2;
+  *be = z0 * z1 + z1 * z2 + z2 * z0;
+  *ga = z0 * z1 * z2;
+}
+
+/* ------------------------------------------------------------------ */
 /* State and time stepping (Sec. 3.1, Algorithm 1)                     */
 /* ------------------------------------------------------------------ */
 
@@ -823,24 +1007,37 @@ void pmdg_ref_step(void *h, int nsteps, double *traces) {
   rsolver *s = (rsolver *)h;
   long n = s->ntot;
   double dt = s->dt;
+  int pml = s->psi && (s->pml_on[0] || s->pml_on[1]);
   double *f = (double *)malloc(sizeof(double) * n);
   double *Kp = (double *)malloc(sizeof(double) * n);
+  double *pold = pml ? (double *)malloc(sizeof(double) * n) : NULL;
+  double *psinew = pml ? (double *)malloc(sizeof(double) * n) : NULL;
   for (int it = 0; it < nsteps; ++it) {
     double tn = s->nstep * dt, tn1 = (s->nstep + 1) * dt;
     if (s->literal) pmut_block(s, s->p, tn);
+    if (pml) memcpy(pold, s->p, sizeof(double) * n);
     /* acoustic predictor */
     for (long i = 0; i < n; ++i) {
       s->p[i] += dt * s->pd[i] + 0.5 * dt * dt * s->pdd[i];
       s->pd[i] += 0.5 * dt * s->pdd[i];
     }
     if (!s->literal) pmut_block(s, s->p, tn1);
+    /* layer fields: psi_t = p by the trapezoidal rule, then Phi from the
+     * averaged gradients of p and psi (Sec. 2, eq. full_problem, rows 2-3) */
+    if (pml) {
+      for (long i = 0; i < n; ++i) psinew[i] = s->psi[i] + 0.5 * dt * (pold[i] + s->p[i]);
+      pml_update_phi(s, pold, s->p, s->psi, psinew);
+      memcpy(s->psi, psinew, sizeof(double) * n);
+    }
     /* acoustic solve: M pdd + C (pdot* + dt/2 pdd) = f(qdd) - K p, i.e. the
      * damping acts on the corrected velocity of the gamma = 1/2 Newmark
      * scheme: pdd = (f - K p - C pdot*) / (M + dt/2 C), with pdot* the
      * predicted velocity (C = 0 without absorbing faces).  The printed
      * solve takes C pdot* alone, which is stable only while
      * dt (M^{-1} C)_ii <= 2; GLL end weights exceed that at edges and
-     * corners of absorbing faces at the configurations' CFL number. */
+     * corners of absorbing faces at the configurations' CFL number.  In a
+     * layer, the first row of eq. full_problem adds alpha M to C and
+     * (Phi, grad v) + M (beta p + gamma psi) to K p. */
     memset(f, 0, sizeof(double) * n);
     for (int k = 0; k < s->Np; ++k)
       for (int m = 0; m < s->Nm; ++m) {
@@ -849,17 +1046,31 @@ void pmdg_ref_step(void *h, int nsteps, double *traces) {
           f[s->fn_node[k][nn]] += -s->kappa * qdd * s->fn_wf[k][nn] * s->fn_shape[k][(long)m * s->fn_cnt[k] + nn];
       }
     pmdg_ref_apply_K(h, s->p, Kp, 3);
-    for (long i = 0; i < n; ++i) {
-      double ci = s->cabs ? s->cabs[i] : 0.0;
-      double mi = s->abs_literal ? s->mass[i] : s->mass[i] + 0.5 * dt * ci;
-      s->pdd[i] = (f[i] - Kp[i] - ci * s->pd[i]) / mi;
-      s->pd[i] += 0.5 * dt * s->pdd[i];
+    if (pml) pml_weak_div(s, Kp);
+    for (int dd = 0; dd < s->ndom; ++dd) {
+      const rdom *d = &s->d[dd];
+      int lay = pml && s->pml_on[dd];
+      for (int k = 0; k < d->nn[2]; ++k)
+        for (int j = 0; j < d->nn[1]; ++j)
+          for (int i0 = 0; i0 < d->nn[0]; ++i0) {
+            long i = nidx(d, i0, j, k);
+            double ci = s->cabs ? s->cabs[i] : 0.0, kp = Kp[i];
+            if (lay) {
+              double al, be, ga;
+              pml_coeffs(s, dd, i0, j, k, &al, &be, &ga);
+              ci += s->mass[i] * al;
+              kp += s->mass[i] * (be * s->p[i] + ga * s->psi[i]);
+            }
+            double mi = s->abs_literal ? s->mass[i] : s->mass[i] + 0.5 * dt * ci;
+            s->pdd[i] = (f[i] - kp - ci * s->pd[i]) / mi;
+            s->pd[i] += 0.5 * dt * s->pdd[i];
+          }
     }
     s->nstep += 1;
     if (traces)
       for (int r = 0; r < s->R; ++r) traces[(long)r * nsteps + it] = receiver_value(s, r, s->p);
   }
-  free(f); free(Kp);
+  free(f); free(Kp); free(pold); free(psinew);
 }
 
 /* Interpolated pressure at the receivers for an arbitrary field p. */

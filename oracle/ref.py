@@ -81,6 +81,9 @@ def lib():
         L.pmdg_ref_num_threads.restype = ctypes.c_int
         L.pmdg_ref_set_absorbing.argtypes = [vp, ctypes.c_int, ctypes.c_int]
         L.pmdg_ref_absorbing.argtypes = [vp, _dp]
+        L.pmdg_ref_set_pml.restype = ctypes.c_int
+        L.pmdg_ref_set_pml.argtypes = [vp, ctypes.c_int, _dp, ctypes.c_double]
+        L.pmdg_ref_pml_profile.argtypes = [vp, ctypes.c_int, ctypes.c_int, _dp]
         _lib = L
     return _lib
 
@@ -154,6 +157,7 @@ class RefSolver:
         if not self.h:
             raise ValueError("oracle: invalid mesh description")
         self.ndom = len(domains)
+        self.domains = [dict(d) for d in domains]
         self.n = self.L.pmdg_ref_num_nodes(self.h)
         self.dt = float(dt) if dt is not None else self.L.pmdg_ref_cfl_dt(self.h, float(cfl))
         self.L.pmdg_ref_set_dt(self.h, self.dt)
@@ -183,6 +187,21 @@ class RefSolver:
         given by the bitmask faces (bit 2a: low end of axis a, 2a + 1: high
         end)."""
         self.L.pmdg_ref_set_absorbing(self.h, int(dom), int(faces))
+
+    def set_pml(self, dom, ell, R=1e-4):
+        """Perfectly matched layer inside domain dom: thickness ell[2a] at the
+        low end and ell[2a + 1] at the high end of axis a (0: none),
+        reflection coefficient R."""
+        ell = np.ascontiguousarray(ell, dtype=np.float64).reshape(6)
+        if self.L.pmdg_ref_set_pml(self.h, int(dom), _d(ell), float(R)):
+            raise ValueError("oracle: bad layer description")
+
+    def pml_profile(self, dom, axis):
+        """zeta of the given axis at that axis's node coordinates of domain dom."""
+        d = self.domains[dom]
+        out = np.zeros(d["N"] * d["ne"][axis] + 1)
+        self.L.pmdg_ref_pml_profile(self.h, int(dom), int(axis), _d(out))
+        return out
 
     def absorbing(self):
         out = np.zeros(self.n)
@@ -308,6 +327,8 @@ def from_workload(wl, scenario=0, shape_fn=None):
     for d, dom in enumerate(wl["domains"]):
         if dom.get("absorbing", 0):
             s.set_absorbing(d, dom["absorbing"])
+        if dom.get("pml"):
+            s.set_pml(d, dom["pml"]["ell"], dom["pml"].get("R", 1e-4))
     pm = wl.get("pmuts")
     if pm is not None and len(pm["radius"]):
         s.set_pmuts(pm["centers"], pm["radius"], pm["omega"], pm["zeta"], pm["eta"])
