@@ -122,6 +122,23 @@ pmdg_status pmdg_set_rx(pmdg_solver* h, double t_switch, double cap);
  * (PMDG_OPT_TIME_BLOCK has no effect on them). */
 pmdg_status pmdg_set_absorbing(pmdg_solver* h, int dom, int faces);
 
+/* Perfectly matched layer (Sec. 2, eq. full_problem: the damping
+ * alpha p_t + beta p, the auxiliary fields Phi and psi with
+ * Phi_t = Z1 Phi + c^2 Z2 grad p + c^2 Z3 grad psi, psi_t = p, and the
+ * profile zeta_i of that section with constant (c / ell) log(1 / R)) inside
+ * brick dom: layers of thickness ell[2a] at the low end and ell[2a+1] at the
+ * high end of axis a (0: none), the outermost part of the brick; R in (0, 1)
+ * is the design reflection coefficient of a layer (a plane wave through it
+ * and back is attenuated by R).  Phi is held at the GLL nodes of every
+ * element with zeta > 0 at one of its nodes, psi at their nodes.  Combine
+ * with pmdg_set_absorbing on the outer faces, as in the paper.  Interface
+ * faces of two coupled bricks carry no layer; orders up to 6; before bind
+ * (PMDG_ESTATE after); PMDG_EINVAL on bad input.  A brick with a layer keeps
+ * single-step passes on 4-wave tiles of 1 or 2 rows, sequential launches
+ * (PMDG_OPT_TIME_BLOCK and PMDG_OPT_OVERLAP have no effect) and cannot join
+ * a batch; pmdg_set_state starts Phi and psi at rest. */
+pmdg_status pmdg_set_pml(pmdg_solver* h, int dom, const double* ell, double R);
+
 /* Receiver points xyz[3*R]; each is located in the lowest-index element
  * containing it (primary first) and sampled by tensor Lagrange
  * interpolation, accumulated in FP64.  A point outside both bricks gives

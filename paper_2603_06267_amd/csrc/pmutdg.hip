@@ -154,6 +154,11 @@ struct Brick {
   std::vector<double> ctap[3];  // [N+2][2N] rows by node class (see StiffArgs)
   std::vector<double> cmin[3];  // [N+2]
   int absorbing = 0;            // outer faces with the first-order absorbing condition (bit 2a / 2a+1: low / high end of axis a)
+  // perfectly matched layer: zeta per axis at the node coordinates, the
+  // layer's elements (slot per element, -1 outside) and their nodes
+  bool pml = false;
+  std::vector<double> pzeta[3];
+  std::vector<int> eslot, pel, pnode;
   double coord(int axis, int i) const {
     const int e = i / N, a = i % N;
     return x0[axis] + h[axis] * (e + 0.5 * ((double)rule.x[a] + 1.0));
@@ -671,6 +676,19 @@ static size_t layout(pmdg_solver* s) {
     add(p + "taps", rb * 3 * (B.N + 3) * 2 * B.N);
     add(p + "mins", rb * 3 * (B.N + 3));
     add(p + "absg", rb * 3 * (B.N + 3));
+    if (B.pml) {
+      const size_t n3 = (size_t)(B.N + 1) * (B.N + 1) * (B.N + 1), nel = B.pel.size() / 3;
+      for (int a = 0; a < 3; ++a) {
+        add(p + "pz" + std::to_string(a), rb * B.nn[a]);
+        add(p + "pmi" + std::to_string(a), rb * B.nn[a]);
+      }
+      add(p + "eslot", sizeof(int) * B.eslot.size());
+      add(p + "pel", sizeof(int) * B.pel.size());
+      add(p + "pnode", sizeof(int) * B.pnode.size());
+      add(p + "phi", rb * S * nel * 3 * n3);
+      add(p + "psi", rb * S * B.pnodes);
+      add(p + "pacc", rb * S * B.pnodes);
+    }
   }
   if (s->Np > 0) {
     add("force", rb * S * s->b[0].pplane);
@@ -854,6 +872,18 @@ static StiffArgs<Real> stiff_args(pmdg_solver* s, int d) {
   a.rows = brick_rows(s, d);
   a.waves = s->waves;
   a.depth = deep_prefetch_built(B.N, a.rows, a.waves) ? s->depth : 2;
+  if (B.pml) {
+    // the layer's build: 4-wave tiles of 1 or 2 rows, 2-plane prefetch
+    const std::string p = "d" + std::to_string(d) + ".";
+    a.rows = std::min(a.rows, 2);
+    a.waves = 4;
+    a.depth = 2;
+    a.pml_acc = dptr<Real>(s, p + "pacc");
+    a.pml_zx = dptr<Real>(s, p + "pz0");
+    a.pml_zy = dptr<Real>(s, p + "pz1");
+    a.pml_zz = dptr<Real>(s, p + "pz2");
+    a.dt = (Real)s->dt;
+  }
   a.nbx = B.px / 64;
   const int TY = a.waves * a.rows;
   a.nby = (B.nn[1] + TY - 1) / TY;
@@ -1057,14 +1087,58 @@ static pmdg_status enqueue_step_split(pmdg_solver* s, hipStream_t st, int toggle
   return PMDG_OK;
 }
 
+static bool any_pml(const pmdg_solver* s) { return s->b[0].pml || (s->ndom > 1 && s->b[1].pml); }
+
+// Arguments of the layer kernels of brick d (prime: the acceleration of the
+// current level only).
+template <typename Real>
+static PmlArgs<Real> pml_args(pmdg_solver* s, int d, int prime) {
+  PmlArgs<Real> a;
+  memset(&a, 0, sizeof(a));
+  const Brick& B = s->b[d];
+  const std::string p = "d" + std::to_string(d) + ".";
+  a.d = view<Real>(s, d);
+  a.S = s->S;
+  a.counter = dptr<long>(s, "ctl");
+  a.prime = prime;
+  a.dt = (Real)s->dt;
+  a.c2 = (Real)(B.c * B.c);
+  for (int k = 0; k < 3; ++k) {
+    a.gh[k] = (Real)(2.0 / B.h[k]);
+    a.ne[k] = B.ne[k];
+  }
+  a.J = (Real)(B.h[0] * B.h[1] * B.h[2] / 8.0);
+  a.zx = dptr<Real>(s, p + "pz0");
+  a.zy = dptr<Real>(s, p + "pz1");
+  a.zz = dptr<Real>(s, p + "pz2");
+  a.mix = dptr<Real>(s, p + "pmi0");
+  a.miy = dptr<Real>(s, p + "pmi1");
+  a.miz = dptr<Real>(s, p + "pmi2");
+  a.eslot = dptr<int>(s, p + "eslot");
+  a.pel = dptr<int>(s, p + "pel");
+  a.nel = (int)(B.pel.size() / 3);
+  a.pnode = dptr<int>(s, p + "pnode");
+  a.npn = (int)(B.pnode.size() / 3);
+  a.phi = dptr<Real>(s, p + "phi");
+  a.psi = dptr<Real>(s, p + "psi");
+  a.acc = dptr<Real>(s, p + "pacc");
+  const int n1 = B.N + 1;
+  for (int q = 0; q < n1; ++q) {
+    a.w[q] = (Real)B.rule.w[q];
+    for (int m = 0; m < n1; ++m) a.D[q * n1 + m] = (Real)B.rule.D[q * n1 + m];
+  }
+  return a;
+}
+
 template <typename Real>
 static pmdg_status enqueue_step(pmdg_solver* s, hipStream_t st, Timer* tm) {
-  if (!tm && s->ndom == 2 && s->overlap) return enqueue_step_split<Real>(s, st, 0);
+  if (!tm && s->ndom == 2 && s->overlap && !any_pml(s)) return enqueue_step_split<Real>(s, st, 0);
   const bool incr = s->prec == 32;
   for (int d = 0; d < s->ndom; ++d) {
     StiffArgs<Real> a = stiff_args<Real>(s, d);
     TBEGIN(0);
     HIPCHK(launch_stiff<Real>(a, incr, st));
+    if (s->b[d].pml) HIPCHK(launch_pml<Real>(pml_args<Real>(s, d, 0), st));
     TEND();
   }
   return enqueue_coupling<Real>(s, st, tm, 0);
@@ -1088,7 +1162,7 @@ static void completion_ranges(const pmdg_solver* s, int d, int r[4]) {
 
 // brick d advances two steps per stiffness pass
 static bool two_step(const pmdg_solver* s, int d) {
-  if (s->prec != 32 || s->b[d].absorbing) return false;
+  if (s->prec != 32 || s->b[d].absorbing || s->b[0].pml || (s->ndom > 1 && s->b[1].pml)) return false;
   const int tb = (d == 1 && s->tblock1 > 0) ? s->tblock1 : s->tblock;
   return tb == 2 && stiff2_tile_rows(s->b[d].N) > 0;
 }
@@ -1166,6 +1240,8 @@ template <typename Real>
 static pmdg_status prime(pmdg_solver* s, hipStream_t st) {
   FaceArgs<Real> a = face_args<Real>(s, 1);
   HIPCHK(launch_face<Real>(a, st));
+  for (int d = 0; d < s->ndom; ++d)
+    if (s->b[d].pml) HIPCHK(launch_pml<Real>(pml_args<Real>(s, d, 1), st));
   if (s->ndom > 1) {
     FluxArgs<Real> f = flux_args<Real>(s, 0);
     HIPCHK(launch_flux<Real>(f, st));
@@ -1213,6 +1289,15 @@ static pmdg_status bind_tables(pmdg_solver* s, hipStream_t st) {
     if ((r = upload_real<Real>(s, p + "taps", taps, st))) return r;
     if ((r = upload_real<Real>(s, p + "mins", mins, st))) return r;
     if ((r = upload_real<Real>(s, p + "absg", absg, st))) return r;
+    if (B.pml) {
+      for (int a = 0; a < 3; ++a) {
+        if ((r = upload_real<Real>(s, p + "pz" + std::to_string(a), B.pzeta[a], st))) return r;
+        if ((r = upload_real<Real>(s, p + "pmi" + std::to_string(a), B.minv[a], st))) return r;
+      }
+      if ((r = upload_vec(s, p + "eslot", B.eslot, st))) return r;
+      if ((r = upload_vec(s, p + "pel", B.pel, st))) return r;
+      if ((r = upload_vec(s, p + "pnode", B.pnode, st))) return r;
+    }
   }
   if (s->ndom > 1) {
     if ((r = upload_real<Real>(s, "Lq", s->Lq, st))) return r;
@@ -1302,6 +1387,16 @@ static pmdg_status set_state_t(pmdg_solver* s, int sc, const double* p, const do
     HIPCHK(hipMemcpy(dptr<double>(s, "q") + off, q ? q : z.data(), nm * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(dptr<double>(s, "qd") + off, qd ? qd : z.data(), nm * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(dptr<double>(s, "qdd") + off, qdd ? qdd : z.data(), nm * 8, hipMemcpyHostToDevice));
+  }
+  // layer fields start at rest (psi = 0, Phi = 0); the layer's acceleration
+  // of the set level is formed by prime
+  for (int d = 0; d < s->ndom; ++d) {
+    const Brick& B = s->b[d];
+    if (!B.pml) continue;
+    const std::string pf = "d" + std::to_string(d) + ".";
+    const long n3 = (long)(B.N + 1) * (B.N + 1) * (B.N + 1), nel = (long)(B.pel.size() / 3);
+    HIPCHK(launch_fill<Real>(dptr<Real>(s, pf + "psi") + (size_t)sc * B.pnodes, B.pnodes, Real(0), st));
+    HIPCHK(launch_fill<Real>(dptr<Real>(s, pf + "phi") + (size_t)sc * nel * 3 * n3, nel * 3 * n3, Real(0), st));
   }
   HIPCHK(hipMemcpy(dptr<long>(s, "ctl"), &nstep, sizeof(long), hipMemcpyHostToDevice));
   pmdg_status r = prime<Real>(s, st);
@@ -1541,6 +1636,64 @@ pmdg_status pmdg_set_absorbing(pmdg_solver* s, int dom, int faces) {
   if (s->ndom > 1 && (faces & (dom == 0 ? 32 : 16)))
     return fail(PMDG_EINVAL, "the interface face of a coupled brick cannot be absorbing");
   s->b[dom].absorbing = faces;
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_set_pml(pmdg_solver* s, int dom, const double* ell, double R) {
+  if (!s || !ell) return fail(PMDG_EINVAL, "NULL argument");
+  if (s->bound) return fail(PMDG_ESTATE, "set_pml must precede bind");
+  if (dom < 0 || dom >= s->ndom) return fail(PMDG_EINVAL, "domain out of range");
+  if (!(R > 0 && R < 1)) return fail(PMDG_EINVAL, "the reflection coefficient R must be in (0, 1)");
+  Brick& B = s->b[dom];
+  for (int a = 0; a < 3; ++a) {
+    const double L = B.h[a] * B.ne[a];
+    if (!(ell[2 * a] >= 0) || !(ell[2 * a + 1] >= 0) || ell[2 * a] + ell[2 * a + 1] > L * (1 + 1e-12))
+      return fail(PMDG_EINVAL, "layer thicknesses must be >= 0 and fit in the brick");
+  }
+  if (s->ndom == 2 && ((dom == 0 && ell[5] > 0) || (dom == 1 && ell[4] > 0)))
+    return fail(PMDG_EINVAL, "the interface faces of two coupled bricks carry no layer");
+  if (B.N > kPmlMaxOrder) return fail(PMDG_EINVAL, "layers are built for orders up to 6");
+  // the profile of Sec. 2 at distance d into a layer of thickness l
+  auto prof = [&](double d, double l) {
+    if (!(l > 0) || d <= 0) return 0.0;
+    d = std::min(d, l);
+    return B.c / l * std::log(1.0 / R) * (d / l - std::sin(2.0 * M_PI * d / l) / (2.0 * M_PI));
+  };
+  for (int a = 0; a < 3; ++a) {
+    B.pzeta[a].assign(B.nn[a], 0.0);
+    const double lo = B.x0[a] + ell[2 * a], hi = B.x0[a] + B.h[a] * B.ne[a] - ell[2 * a + 1];
+    for (int i = 0; i < B.nn[a]; ++i) {
+      const double x = B.coord(a, i);
+      double z = 0.0;
+      if (ell[2 * a] > 0 && x < lo) z = prof(lo - x, ell[2 * a]);
+      if (ell[2 * a + 1] > 0 && x > hi) z = prof(x - hi, ell[2 * a + 1]);
+      B.pzeta[a][i] = z;
+    }
+  }
+  const int N = B.N;
+  B.eslot.assign((size_t)B.ne[0] * B.ne[1] * B.ne[2], -1);
+  B.pel.clear();
+  std::vector<char> mark(B.nnodes, 0);
+  for (int ez = 0; ez < B.ne[2]; ++ez)
+    for (int ey = 0; ey < B.ne[1]; ++ey)
+      for (int ex = 0; ex < B.ne[0]; ++ex) {
+        bool any = false;
+        for (int m = 0; m <= N; ++m)
+          any = any || B.pzeta[0][N * ex + m] > 0 || B.pzeta[1][N * ey + m] > 0 || B.pzeta[2][N * ez + m] > 0;
+        if (!any) continue;
+        B.eslot[ex + (size_t)B.ne[0] * (ey + (size_t)B.ne[1] * ez)] = (int)(B.pel.size() / 3);
+        B.pel.insert(B.pel.end(), {ex, ey, ez});
+        for (int c = 0; c <= N; ++c)
+          for (int b = 0; b <= N; ++b)
+            for (int aa = 0; aa <= N; ++aa)
+              mark[(N * ex + aa) + (long)B.nn[0] * ((N * ey + b) + (long)B.nn[1] * (N * ez + c))] = 1;
+      }
+  B.pnode.clear();
+  for (int k = 0; k < B.nn[2]; ++k)
+    for (int j = 0; j < B.nn[1]; ++j)
+      for (int i = 0; i < B.nn[0]; ++i)
+        if (mark[i + (long)B.nn[0] * (j + (long)B.nn[1] * k)]) B.pnode.insert(B.pnode.end(), {i, j, k});
+  B.pml = !B.pel.empty();
   return PMDG_OK;
 }
 
@@ -1958,6 +2111,7 @@ pmdg_status pmdg_batch_create(int n, pmdg_solver* const* solvers, pmdg_batch** o
     if (!s || !s->bound) { delete b; return fail(PMDG_ESTATE, "every solver must be bound"); }
     if (ws_lost(s)) { delete b; return fail(PMDG_ESTATE, kLostMsg); }
     if (s->ndom != 1 || s->prec != 32) { delete b; return fail(PMDG_EINVAL, "batches take single-brick FP32 solvers"); }
+    if (s->b[0].pml) { delete b; return fail(PMDG_EINVAL, "batches take solvers without a matched layer"); }
     const int rows = brick_rows(s, 0);
     if (rows != 1 && rows != 2) { delete b; return fail(PMDG_EINVAL, "batched tiles use 1 or 2 rows per wave"); }
     if (s->waves != kWaves) { delete b; return fail(PMDG_EINVAL, "batched tiles use 4 waves per workgroup"); }

@@ -59,6 +59,15 @@ struct StiffArgs {
   const Real* mins;         // [3][N+3]: inverse assembled 1D lumped mass
   const Real* absg;         // [3][N+3]: dt c / m_d on the end classes of absorbing faces, else 0
   int absorb;               // the brick has absorbing faces (absg not all zero)
+  // perfectly matched layer: the layer's acceleration
+  // -(M^{-1} (Phi, grad v) + beta p + gamma psi) at every node ([S][nnodes],
+  // zero outside the layer), and zeta per axis at the node coordinates; the
+  // damping alpha = zeta_x + zeta_y + zeta_z joins the absorbing term
+  const Real* pml_acc;      // null: no layer (the kernel built without it is used)
+  const Real* pml_zx;
+  const Real* pml_zy;
+  const Real* pml_zz;
+  Real dt;
   // value / normal-derivative traces of p^{n+1} on Gamma_I written by this
   // launch ([S][nn0*nn1][2], compact face grid), or null (the face kernel
   // writes them); trd: the normal-derivative weights of the layer's planes
@@ -152,6 +161,36 @@ struct FluxArgs {
   int tcap;                 // LDS entries per component and coarse face (x points x (N1+1))
 };
 
+// Perfectly matched layer of one brick: auxiliary fields and the layer's
+// acceleration, advanced after the brick's stiffness update.
+template <typename Real>
+struct PmlArgs {
+  DomView<Real> d;
+  int S;
+  const long* counter;
+  int prime;                // 1: acceleration of the current level only (psi, Phi kept)
+  Real dt, c2;
+  Real gh[3];               // 2 / h per axis
+  Real J;                   // h_x h_y h_z / 8
+  int ne[3];
+  const Real* zx;           // zeta per axis at the node coordinates
+  const Real* zy;
+  const Real* zz;
+  const Real* mix;          // inverse assembled 1D lumped mass per axis
+  const Real* miy;
+  const Real* miz;
+  const int* eslot;         // [ne0*ne1*ne2]: slot of the element's Phi, or -1
+  const int* pel;           // [nel][3]: element coordinates of each slot
+  int nel;
+  const int* pnode;         // [npn][3]: nodes of the layer's elements
+  int npn;
+  Real* phi;                // [S][nel][3][(N+1)^3]
+  Real* psi;                // [S][nnodes]
+  Real* acc;                // [S][nnodes]
+  Real w[kMaxOrder + 1];    // GLL weights
+  Real D[(kMaxOrder + 1) * (kMaxOrder + 1)];  // D[q][m] = l_m'(x_q)
+};
+
 // Launchers (defined in pmutdg_kernels.hip).
 template <typename Real>
 hipError_t launch_stiff(const StiffArgs<Real>& a, bool incr, hipStream_t st);
@@ -167,6 +206,13 @@ int stiff2_tile_rows(int N);  // owned rows per two-step tile (0: order not supp
 hipError_t launch_stiff2_lo(const StiffArgs<float>& a, hipStream_t st);
 hipError_t launch_fill_bytes(void* p, size_t n, hipStream_t st);
 hipError_t launch_tick(long* counter, int* xsel, int toggle, hipStream_t st);
+// perfectly matched layer (pml_kernels.hip): the stiffness update with the
+// layer's terms, and the auxiliary-field kernels run after it
+template <typename Real>
+hipError_t launch_stiff_pml(const StiffArgs<Real>& a, bool incr, hipStream_t st);
+template <typename Real>
+hipError_t launch_pml(const PmlArgs<Real>& a, hipStream_t st);
+constexpr int kPmlMaxOrder = 6;
 // batched form
 size_t batch_lds_bytes(int N, int rows);
 hipError_t batch_occupancy(int nmax, size_t lds, int* blocks_per_cu);

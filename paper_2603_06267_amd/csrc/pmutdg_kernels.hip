@@ -560,12 +560,14 @@ __global__ void k_fill(Real* p, long n, Real v) {
 template <>
 hipError_t launch_stiff<float>(const StiffArgs<float>& a, bool incr, hipStream_t st) {
   if (!incr) return hipErrorInvalidValue;  // FP32 state always uses the increment form
+  if (a.pml_acc) return launch_stiff_pml<float>(a, incr, st);
   return a.d.N <= 4 ? launch_stiff_f32_lo(a, st) : launch_stiff_f32_hi(a, st);
 }
 
 template <>
 hipError_t launch_stiff<double>(const StiffArgs<double>& a, bool incr, hipStream_t st) {
   if (incr) return hipErrorInvalidValue;  // FP64 state uses the two-level form
+  if (a.pml_acc) return launch_stiff_pml<double>(a, incr, st);
   return a.d.N <= 4 ? launch_stiff_f64_lo(a, st) : launch_stiff_f64_hi(a, st);
 }
 

@@ -103,7 +103,8 @@ constexpr int ct_gcd(int a, int b) { return b == 0 ? a : ct_gcd(b, a % b); }
 // prefetch distance in planes (the loads for plane k + D are issued while
 // plane k is updated); NTS selects non-temporal stores; IFT builds in the
 // interface traces (off for the batch kernel, whose problems have none).
-template <typename Real, int N, bool INCR, int RY, int WV, int D = 2, bool NTS = true, bool IFT = true>
+template <typename Real, int N, bool INCR, int RY, int WV, int D = 2, bool NTS = true, bool IFT = true,
+          bool PML = false>
 __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id, Real* __restrict__ lds) {
   constexpr int TX = 64, TY = WV * RY, W = TX + 2 * N, H = TY + 2 * N, NT = 2 * N, NQ = NT + 1;
   static_assert(D >= 2, "prefetch distance of at least two planes");
@@ -160,6 +161,10 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
   const bool absorb = a.absorb;
   const Real* __restrict__ AG = a.absg;
   const Real gx = AG[cxl];
+  // layer damping per axis (PML build): dt zeta at the lane's x, row's y
+  Real pzx = Real(0), pzy[RY];
+  const Real* __restrict__ PA = PML ? a.pml_acc + (long)s * a.d.nnodes : nullptr;
+  if constexpr (PML) pzx = a.dt * a.pml_zx[xl];
   int cyr[RY];
   bool in[RY];
   unsigned roff[RY];
@@ -174,6 +179,7 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
     for (int i = 0; i < NT; ++i) ty[r][i] = TP[(NC + cyr[r]) * NT + i];
     my[r] = MI[NC + cyr[r]];
     gxy[r] = gx + AG[NC + cyr[r]];
+    pzy[r] = PML ? a.dt * a.pml_zy[min(y, ny - 1)] : Real(0);
   }
   // z operator rows by class, staged in LDS (read with uniform addresses)
   Real* ztab = lds + 2 * H * W;
@@ -216,7 +222,7 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
   const int k1 = min(a.zhi + 1, k0 + a.zchunk);
 
   Real q[RY][NQ];
-  Real xc[RY];
+  Real xc[RY], ac[RY];
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
 #pragma unroll
@@ -227,6 +233,11 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
     }
     const Real v = X[roff[r] + (unsigned)k0 * plane];
     xc[r] = in[r] ? v : Real(0);
+    ac[r] = Real(0);
+    if constexpr (PML) {
+      const Real va = PA[roff[r] + (unsigned)k0 * plane];
+      ac[r] = in[r] ? va : Real(0);
+    }
   }
   {
     Real* T = tile[0];
@@ -291,7 +302,7 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
   // has D-1 plane updates of work to hide behind.  Slot (j - k0) mod D holds
   // the data for plane j: the queue's lead plane j+N, the increment (or
   // p^{n-1}) of plane j and the x/y halos of plane j.
-  Real fq[D][RY], fx[D][RY], fhx[D][NXH], fhy[D][HYR];
+  Real fq[D][RY], fx[D][RY], fa[D][RY], fhx[D][NXH], fhy[D][HYR];
   auto fetch = [&](int slot, int j) {
     const unsigned kl_off = (unsigned)min(j + N, nz - 1) * plane;
     const unsigned kn_off = (unsigned)min(j, nz - 1) * plane;
@@ -299,6 +310,7 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
     for (int r = 0; r < RY; ++r) {
       fq[slot][r] = P[roff[r] + kl_off];
       fx[slot][r] = X[roff[r] + kn_off];
+      if constexpr (PML) fa[slot][r] = PA[roff[r] + kn_off];
     }
     // unused halo slots read the lead-plane line of the lane's first row,
     // which the fetch has just requested: no further L2 request
@@ -357,6 +369,7 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
       for (int i = 0; i < NT + 2; ++i) tz[i] = ztab[cz * (NT + 2) + i];
       __builtin_amdgcn_sched_barrier(0);
       const Real mz = tz[NT];
+      const Real pzz = PML ? a.dt * a.pml_zz[k] : Real(0);
       const bool in_layer = (k >= lay0 && k <= lay1);
       const int cl = k - lay0;
       // (3) update the nodes of plane k
@@ -383,7 +396,13 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
           else { if (cl == 0) rif -= RA[r]; }
           acc -= a.dt2 * minv * rif;
         }
-        if (absorb) {
+        if constexpr (PML) {
+          // layer terms of the first row of eq. full_problem: the layer's
+          // acceleration, and the damping alpha on the corrected velocity
+          acc += a.dt2 * ac[r];
+          const Real g = (absorb ? gxy[r] + tz[NT + 1] : Real(0)) + pzx + pzy[r] + pzz;
+          acc = (acc - g * (INCR ? xc[r] : p0 - xc[r])) / (Real(1) + Real(0.5) * g);
+        } else if (absorb) {
           const Real g = gxy[r] + tz[NT + 1];
           acc = (acc - g * (INCR ? xc[r] : p0 - xc[r])) / (Real(1) + Real(0.5) * g);
         }
@@ -421,6 +440,7 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
       for (int r = 0; r < RY; ++r) {
         q[r][uq] = (in[r] && kl < nz) ? fq[cs][r] : Real(0);
         xc[r] = (in[r] && more) ? fx[cs][r] : Real(0);
+        if constexpr (PML) ac[r] = (in[r] && more) ? fa[cs][r] : Real(0);
       }
     });
   }

@@ -136,6 +136,11 @@ class Solver:
         (6-bit mask: bit 2a low end, 2a + 1 high end of axis a); before bind."""
         check(self.L.pmdg_set_absorbing(self.h, int(dom), int(faces)))
 
+    def set_pml(self, dom, ell, R=1e-4):
+        """Perfectly matched layer inside brick dom: thickness ell[2a] at the
+        low end and ell[2a + 1] at the high end of axis a; before bind."""
+        check(self.L.pmdg_set_pml(self.h, int(dom), _d(_f64(ell).reshape(6)), float(R)))
+
     def set_receivers(self, xyz):
         xyz = _f64(xyz).reshape(-1, 3)
         self.R = xyz.shape[0]
@@ -222,6 +227,8 @@ def from_workload(wl, precision=32, n_steps=None, scenarios=None, shape_fn=None,
     for d, dom in enumerate(wl["domains"]):
         if dom.get("absorbing", 0):
             s.set_absorbing(d, dom["absorbing"])
+        if dom.get("pml"):
+            s.set_pml(d, dom["pml"]["ell"], dom["pml"].get("R", 1e-4))
     pm = wl.get("pmuts")
     if pm is not None and len(pm["radius"]):
         s.set_pmuts(pm["centers"], pm["radius"], pm["omega"], pm["zeta"], pm["eta"])

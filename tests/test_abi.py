@@ -87,6 +87,14 @@ def test_setup_errors_and_state_errors():
     assert _err(two.set_absorbing, 1, 1 << 4) == _lib.PMDG_EINVAL  # secondary bottom: the interface
     two.set_absorbing(0, 0b011111)
     two.set_absorbing(1, 0b101111)
+    # matched layers: fit in the brick, not on Gamma_I, R in (0, 1)
+    assert _err(two.set_pml, 0, [0, 0, 0, 0, 0, 0.25], 1e-4) == _lib.PMDG_EINVAL
+    assert _err(two.set_pml, 1, [0, 0, 0, 0, 0.5, 0], 1e-4) == _lib.PMDG_EINVAL
+    assert _err(two.set_pml, 1, [3.0, 1.5, 0, 0, 0, 0], 1e-4) == _lib.PMDG_EINVAL
+    assert _err(two.set_pml, 1, [0.5] * 4 + [0, 0.5], 1.0) == _lib.PMDG_EINVAL
+    two.set_pml(1, [0.5] * 4 + [0, 0.5], 1e-4)
+    two.set_pml(0, [0.25] * 4 + [0, 0], 1e-4)
+    assert two.workspace_size() > 0
     assert _err(s.set_option, _lib.OPT_PREFETCH, 1) == _lib.PMDG_EINVAL
     assert _err(s.set_option, _lib.OPT_OVERLAP, 3) == _lib.PMDG_EINVAL
     assert _err(s.set_option, _lib.OPT_PREFETCH, 5) == _lib.PMDG_EINVAL
