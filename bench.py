@@ -182,6 +182,42 @@ def scenarios_leg(steps, warmup, rows, zchunk, S=4):
             "frac": 12.0 * S * dofs / (kt[0] * 1e-3) / 1e9 / PEAK_HBM_GBS, "finite": finite}
 
 
+def pml_workload(steps):
+    """The large-array workload with perfectly matched layers in front of
+    absorbing faces: 1 mm (3 coarse elements) on the secondary's side walls
+    and top, 0.5 mm (2 fine elements) on the primary's side walls."""
+    from paper_2603_06267_amd import workloads as W
+    wl = W.config3(steps=steps)
+    prim, sec = wl["domains"]
+    prim = dict(prim, absorbing=0b001111, pml={"ell": [0.5, 0.5, 0.5, 0.5, 0.0, 0.0], "R": 1e-4})
+    sec = dict(sec, absorbing=0b101111, pml={"ell": [1.0, 1.0, 1.0, 1.0, 0.0, 1.0], "R": 1e-4})
+    return dict(wl, domains=[prim, sec])
+
+
+def pml_leg(steps=200, warmup=10):
+    """Rate of the large-array workload with matched layers (graph replay),
+    the stiffness-plus-layer time per step, and the share of DOFs inside the
+    layers' elements."""
+    from paper_2603_06267_amd import workloads as W
+    wl = pml_workload(steps + warmup)
+    dofs = W.unique_dofs(wl)
+    el, el_graph, kt, finite = run_gpu(wl, 32, steps, warmup, True, 0, 73)
+    layer = 0
+    for d in wl["domains"]:
+        N, ne = d["N"], d["ne"]
+        h = [(d["x1"][a] - d["x0"][a]) / ne[a] for a in range(3)]
+        ell = d["pml"]["ell"]
+        # nodes outside the layers' elements, per axis: the nodes of the
+        # elements between the layers, less the face node shared with a layer
+        free = [N * (ne[a] - round(ell[2 * a] / h[a]) - round(ell[2 * a + 1] / h[a])) + 1
+                - (ell[2 * a] > 0) - (ell[2 * a + 1] > 0) for a in range(3)]
+        layer += int(np.prod([N * e + 1 for e in ne])) - int(np.prod([max(v, 0) for v in free]))
+    return {"workload": "config3 with matched layers: secondary side walls and top 1 mm, primary side walls "
+                        "0.5 mm, absorbing outer faces", "unique_dofs": dofs, "layer_dofs": layer,
+            "value": dofs * steps / min(el, el_graph), "unit": "DOF-updates/s",
+            "ms_per_step": min(el, el_graph) * 1e3 / steps, "stiff_and_layer_ms": kt[0], "finite": finite}
+
+
 def small_configs_leg(steps=400, warmup=20):
     """DOF-updates/s of the small workloads (the config-1 cube and the
     config-2 two-domain array), FP32 and FP64, hipGraph replay: latency-bound
@@ -363,6 +399,9 @@ def main():
     ap.add_argument("--no-scenarios", action="store_true",
                     help="skip the large-array leg with 4 drive scenarios in one solver")
     ap.add_argument("--no-small", action="store_true", help="skip the small-workload rates")
+    ap.add_argument("--no-pml", action="store_true", help="skip the large array with matched layers")
+    ap.add_argument("--pml-only", action="store_true",
+                    help="run only the large array with matched layers (direct launches, for counters)")
     ap.add_argument("--no-trace", action="store_true",
                     help="skip the full 5,000-step large-array runs compared with the oracle's traces")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-form leg")
@@ -383,6 +422,12 @@ def main():
         sys.exit(2)
 
     from paper_2603_06267_amd import workloads as W
+    if args.pml_only:
+        wl = pml_workload(args.steps + args.warmup)
+        el, el_graph, kt, finite = run_gpu(wl, 32, args.steps, args.warmup, not args.direct, 0, 73)
+        print(json.dumps({"pml_only": True, "ms_per_step": min(el, el_graph) * 1e3 / args.steps,
+                          "stiff_and_layer_ms": kt[0], "finite": finite}), flush=True)
+        return
     wl = W.config3(steps=args.steps + args.warmup)
     dofs = W.unique_dofs(wl)
     n0 = int(np.prod([wl["domains"][0]["N"] * e + 1 for e in wl["domains"][0]["ne"]]))
@@ -443,6 +488,9 @@ def main():
     if not args.no_scenarios:
         log("large array x 4 scenarios ...")
         out["scenarios4"] = scenarios_leg(min(args.steps, 200), args.warmup, args.rows, args.zchunk)
+    if not args.no_pml:
+        log("large array with matched layers ...")
+        out["pml"] = pml_leg()
     if not args.no_small:
         log("small workloads ...")
         out["small"] = small_configs_leg()

@@ -11,12 +11,13 @@
 // auxiliary fields to the new level and form the next acceleration:
 //   k_pml_phi   per layer element: Phi at its GLL nodes by the trapezoidal
 //               rule, from the element-local gradients of the averaged p and
-//               psi of the two levels (Phi is discontinuous across elements);
+//               psi of the two levels (Phi is discontinuous across elements),
+//               then the element's share of the weak divergence (Phi, grad v)
+//               at each of its nodes;
 //   k_pml_node  per node of the layer's elements: psi by the trapezoidal
-//               rule, the weak divergence (Phi, grad v) gathered from the (up
-//               to eight) layer elements sharing the node, and the new
-//               acceleration.  No atomics: every node sums its own terms in a
-//               fixed order.
+//               rule, the shares of the (up to eight) layer elements sharing
+//               the node, and the new acceleration.  No atomics: every node
+//               sums its own terms in a fixed order.
 #include "stiff_kernel.h"
 
 namespace pmdg {
@@ -59,51 +60,83 @@ __device__ __forceinline__ long pml_dev(const DomView<Real>& d, int i, int j, in
   return (long)i + (long)d.px * j + d.plane * k;
 }
 
-// One workgroup per (layer element, scenario), one thread per GLL node.
+// Layer elements in groups of EPB per workgroup (one thread per GLL node).
 // Levels: p^n = P[cnt % nbuf], p^{n+1} = P[(cnt + 1) % nbuf] (the step
 // counter advances at the end of the step); psi still holds psi^n, so the
-// average of psi over the step is psi^n + dt/4 (p^n + p^{n+1}).
+// average of psi over the step is psi^n + dt/4 (p^n + p^{n+1}).  After Phi,
+// the element's share of the weak divergence at each of its nodes,
+// r_E(i) = sum_q w_q J Phi(q) . grad v_i(q), which depends on this
+// element's Phi only, is written per element node for k_pml_node to gather.
+template <int N>
+constexpr int pml_epb() {
+  return (N + 1) * (N + 1) * (N + 1) <= 256 ? 256 / ((N + 1) * (N + 1) * (N + 1)) : 1;
+}
+
 template <typename Real, int N>
 __global__ void __launch_bounds__(256) k_pml_phi(const PmlArgs<Real> a) {
-  constexpr int n1 = N + 1, n3 = n1 * n1 * n1;
-  __shared__ Real pb[n3], sb[n3];
-  const int e = blockIdx.x, s = blockIdx.y;
-  const int ex = a.pel[3 * e], ey = a.pel[3 * e + 1], ez = a.pel[3 * e + 2];
+  constexpr int n1 = N + 1, n3 = n1 * n1 * n1, EPB = pml_epb<N>();
+  __shared__ Real pb[EPB * n3], sb[EPB * n3], pf[EPB * 3 * n3];
+  const int s = blockIdx.y;
   const long cnt = *a.counter;
   const Real* P0 = a.d.P[cnt % a.d.nbuf] + (long)s * a.d.nnodes;
   const Real* P1 = a.d.P[(cnt + 1) % a.d.nbuf] + (long)s * a.d.nnodes;
   const Real* PS = a.psi + (long)s * a.d.nnodes;
-  for (int t = threadIdx.x; t < n3; t += blockDim.x) {
-    const int ia = t % n1, ib = (t / n1) % n1, ic = t / (n1 * n1);
-    const long g = pml_dev(a.d, N * ex + ia, N * ey + ib, N * ez + ic);
+  for (int t = threadIdx.x; t < EPB * n3; t += blockDim.x) {
+    const int el = t / n3, q = t % n3, e = blockIdx.x * EPB + el;
+    if (e >= a.nel) continue;
+    const int ia = q % n1, ib = (q / n1) % n1, ic = q / (n1 * n1);
+    const long g = pml_dev(a.d, N * a.pel[3 * e] + ia, N * a.pel[3 * e + 1] + ib, N * a.pel[3 * e + 2] + ic);
     const Real p0 = P0[g], p1 = P1[g];
     pb[t] = Real(0.5) * (p0 + p1);
     sb[t] = PS[g] + Real(0.25) * a.dt * (p0 + p1);
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < n3; t += blockDim.x) {
-    const int ia = t % n1, ib = (t / n1) % n1, ic = t / (n1 * n1);
+  for (int t = threadIdx.x; t < EPB * n3; t += blockDim.x) {
+    const int el = t / n3, q = t % n3, e = blockIdx.x * EPB + el;
+    if (e >= a.nel) continue;
+    const int ia = q % n1, ib = (q / n1) % n1, ic = q / (n1 * n1);
+    const Real* PB = pb + el * n3;
+    const Real* SB = sb + el * n3;
     Real gp[3] = {0, 0, 0}, gs[3] = {0, 0, 0};
 #pragma unroll
     for (int m = 0; m < n1; ++m) {
       const Real dx = a.D[ia * n1 + m], dy = a.D[ib * n1 + m], dz = a.D[ic * n1 + m];
-      gp[0] += dx * pb[m + n1 * (ib + n1 * ic)];
-      gp[1] += dy * pb[ia + n1 * (m + n1 * ic)];
-      gp[2] += dz * pb[ia + n1 * (ib + n1 * m)];
-      gs[0] += dx * sb[m + n1 * (ib + n1 * ic)];
-      gs[1] += dy * sb[ia + n1 * (m + n1 * ic)];
-      gs[2] += dz * sb[ia + n1 * (ib + n1 * m)];
+      gp[0] += dx * PB[m + n1 * (ib + n1 * ic)];
+      gp[1] += dy * PB[ia + n1 * (m + n1 * ic)];
+      gp[2] += dz * PB[ia + n1 * (ib + n1 * m)];
+      gs[0] += dx * SB[m + n1 * (ib + n1 * ic)];
+      gs[1] += dy * SB[ia + n1 * (m + n1 * ic)];
+      gs[2] += dz * SB[ia + n1 * (ib + n1 * m)];
     }
+    const int ex = a.pel[3 * e], ey = a.pel[3 * e + 1], ez = a.pel[3 * e + 2];
     const Real z[3] = {a.zx[N * ex + ia], a.zy[N * ey + ib], a.zz[N * ez + ic]};
     const Real al = z[0] + z[1] + z[2];
-    Real* ph = a.phi + ((long)s * a.nel + e) * 3 * n3 + t;
+    Real* ph = a.phi + ((long)s * a.nel + e) * 3 * n3 + q;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const Real zjk = z[(i + 1) % 3] * z[(i + 2) % 3];
       const Real rhs = a.c2 * a.gh[i] * ((al - Real(2) * z[i]) * gp[i] + zjk * gs[i]);
       const Real hz = Real(0.5) * a.dt * z[i];
-      ph[i * n3] = ((Real(1) - hz) * ph[i * n3] + a.dt * rhs) / (Real(1) + hz);
+      const Real v = ((Real(1) - hz) * ph[i * n3] + a.dt * rhs) / (Real(1) + hz);
+      ph[i * n3] = v;
+      pf[(el * 3 + i) * n3 + q] = v;
     }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < EPB * n3; t += blockDim.x) {
+    const int el = t / n3, q = t % n3, e = blockIdx.x * EPB + el;
+    if (e >= a.nel) continue;
+    const int la = q % n1, lb = (q / n1) % n1, lc = q / (n1 * n1);
+    const Real* F = pf + el * 3 * n3;
+    Real gx = 0, gy = 0, gz = 0;
+#pragma unroll
+    for (int m = 0; m < n1; ++m) {
+      gx += a.w[m] * a.D[m * n1 + la] * F[m + n1 * (lb + n1 * lc)];
+      gy += a.w[m] * a.D[m * n1 + lb] * F[n3 + la + n1 * (m + n1 * lc)];
+      gz += a.w[m] * a.D[m * n1 + lc] * F[2 * n3 + la + n1 * (lb + n1 * m)];
+    }
+    a.rel[((long)s * a.nel + e) * n3 + q] =
+        a.J * (a.gh[0] * a.w[lb] * a.w[lc] * gx + a.gh[1] * a.w[la] * a.w[lc] * gy + a.gh[2] * a.w[la] * a.w[lb] * gz);
   }
 }
 
@@ -125,8 +158,7 @@ __global__ void __launch_bounds__(256) k_pml_node(const PmlArgs<Real> a) {
     ps += Real(0.5) * a.dt * (pc + pn);
     a.psi[so + g] = ps;
   }
-  // (Phi, grad v) at this node: for each layer element containing it, the
-  // three GLL lines through the node inside that element
+  // (Phi, grad v) at this node: the shares of the layer elements containing it
   Real G = 0;
   const int exs[2] = {I / N - ((I % N == 0 && I > 0) ? 1 : 0), I / N};
   const int eys[2] = {J / N - ((J % N == 0 && J > 0) ? 1 : 0), J / N};
@@ -143,16 +175,7 @@ __global__ void __launch_bounds__(256) k_pml_node(const PmlArgs<Real> a) {
         const int slot = a.eslot[ex + a.ne[0] * (ey + a.ne[1] * ez)];
         if (slot < 0) continue;
         const int la = I - N * ex, lb = J - N * ey, lc = K - N * ez;
-        const Real* ph = a.phi + ((long)s * a.nel + slot) * 3 * n3;
-        Real gx = 0, gy = 0, gz = 0;
-#pragma unroll
-        for (int q = 0; q < n1; ++q) {
-          gx += a.w[q] * a.D[q * n1 + la] * ph[q + n1 * (lb + n1 * lc)];
-          gy += a.w[q] * a.D[q * n1 + lb] * ph[n3 + la + n1 * (q + n1 * lc)];
-          gz += a.w[q] * a.D[q * n1 + lc] * ph[2 * n3 + la + n1 * (lb + n1 * q)];
-        }
-        G += a.J * (a.gh[0] * a.w[lb] * a.w[lc] * gx + a.gh[1] * a.w[la] * a.w[lc] * gy +
-                    a.gh[2] * a.w[la] * a.w[lb] * gz);
+        G += a.rel[((long)s * a.nel + slot) * n3 + la + n1 * (lb + n1 * lc)];
       }
     }
   }
@@ -165,7 +188,8 @@ __global__ void __launch_bounds__(256) k_pml_node(const PmlArgs<Real> a) {
 template <typename Real, int N>
 static hipError_t pml_order(const PmlArgs<Real>& a, hipStream_t st) {
   if (!a.prime && a.nel > 0)
-    hipLaunchKernelGGL((k_pml_phi<Real, N>), dim3(a.nel, a.S), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_pml_phi<Real, N>), dim3((a.nel + pml_epb<N>() - 1) / pml_epb<N>(), a.S), dim3(256), 0, st,
+                       a);
   const long nt = (long)a.npn * a.S;
   if (nt > 0) hipLaunchKernelGGL((k_pml_node<Real, N>), dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, a);
   return hipGetLastError();

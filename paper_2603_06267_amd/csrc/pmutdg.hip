@@ -686,6 +686,7 @@ static size_t layout(pmdg_solver* s) {
       add(p + "pel", sizeof(int) * B.pel.size());
       add(p + "pnode", sizeof(int) * B.pnode.size());
       add(p + "phi", rb * S * nel * 3 * n3);
+      add(p + "prel", rb * S * nel * n3);
       add(p + "psi", rb * S * B.pnodes);
       add(p + "pacc", rb * S * B.pnodes);
     }
@@ -1120,6 +1121,7 @@ static PmlArgs<Real> pml_args(pmdg_solver* s, int d, int prime) {
   a.pnode = dptr<int>(s, p + "pnode");
   a.npn = (int)(B.pnode.size() / 3);
   a.phi = dptr<Real>(s, p + "phi");
+  a.rel = dptr<Real>(s, p + "prel");
   a.psi = dptr<Real>(s, p + "psi");
   a.acc = dptr<Real>(s, p + "pacc");
   const int n1 = B.N + 1;
@@ -1397,6 +1399,7 @@ static pmdg_status set_state_t(pmdg_solver* s, int sc, const double* p, const do
     const long n3 = (long)(B.N + 1) * (B.N + 1) * (B.N + 1), nel = (long)(B.pel.size() / 3);
     HIPCHK(launch_fill<Real>(dptr<Real>(s, pf + "psi") + (size_t)sc * B.pnodes, B.pnodes, Real(0), st));
     HIPCHK(launch_fill<Real>(dptr<Real>(s, pf + "phi") + (size_t)sc * nel * 3 * n3, nel * 3 * n3, Real(0), st));
+    HIPCHK(launch_fill<Real>(dptr<Real>(s, pf + "prel") + (size_t)sc * nel * n3, nel * n3, Real(0), st));
   }
   HIPCHK(hipMemcpy(dptr<long>(s, "ctl"), &nstep, sizeof(long), hipMemcpyHostToDevice));
   pmdg_status r = prime<Real>(s, st);

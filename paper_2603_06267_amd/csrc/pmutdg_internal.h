@@ -185,6 +185,7 @@ struct PmlArgs {
   const int* pnode;         // [npn][3]: nodes of the layer's elements
   int npn;
   Real* phi;                // [S][nel][3][(N+1)^3]
+  Real* rel;                // [S][nel][(N+1)^3]: each element's share of (Phi, grad v) at its nodes
   Real* psi;                // [S][nnodes]
   Real* acc;                // [S][nnodes]
   Real w[kMaxOrder + 1];    // GLL weights
