@@ -196,6 +196,14 @@ pmdg_status pmdg_steps_done(pmdg_solver* h, long* nsteps);
  * host array out (column j holds the pressure at time (j+1) dt). */
 pmdg_status pmdg_read_traces(pmdg_solver* h, double* out, void* stream);
 
+/* The same traces into caller-owned device memory, without a host copy or a
+ * wait: enqueues on stream one kernel that writes the dense array
+ * [S][R][steps_done] to out as FP64 (bits = 64) or rounded to FP32
+ * (bits = 32).  out must hold S*R*steps_done elements of that type on the
+ * solver's device and is valid once stream has reached the call.  EINVAL for
+ * NULL out or other bits. */
+pmdg_status pmdg_read_traces_device(pmdg_solver* h, void* out, int bits, void* stream);
+
 /* Modal state of scenario s after the last step: q, qdot, qddot [Np*Nm]
  * (host arrays; NULL entries skipped). */
 pmdg_status pmdg_read_modal(pmdg_solver* h, int s, double* q, double* qd, double* qdd, void* stream);

@@ -73,6 +73,7 @@ _SIGS = {
     "pmdg_step": [_vp, ctypes.c_int, _vp],
     "pmdg_steps_done": [_vp, ctypes.POINTER(ctypes.c_long)],
     "pmdg_read_traces": [_vp, _dp, _vp],
+    "pmdg_read_traces_device": [_vp, _vp, ctypes.c_int, _vp],
     "pmdg_read_modal": [_vp, ctypes.c_int, _dp, _dp, _dp, _vp],
     "pmdg_num_nodes": [_vp, ctypes.POINTER(ctypes.c_long)],
     "pmdg_get_state": [_vp, ctypes.c_int, _dp, _dp, _vp],

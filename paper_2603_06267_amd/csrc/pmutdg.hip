@@ -1993,6 +1993,18 @@ pmdg_status pmdg_read_traces(pmdg_solver* s, double* out, void* stream) {
   return PMDG_OK;
 }
 
+pmdg_status pmdg_read_traces_device(pmdg_solver* s, void* out, int bits, void* stream) {
+  if (!s || !out) return fail(PMDG_EINVAL, "NULL argument");
+  if (bits != 32 && bits != 64) return fail(PMDG_EINVAL, "bits must be 32 or 64");
+  if (!s->bound) return fail(PMDG_ESTATE, "not bound");
+  if (ws_lost(s)) return fail(PMDG_ESTATE, kLostMsg);
+  if (s->R == 0) return PMDG_OK;
+  const long n = std::min(s->steps_done, s->cap);
+  HIPCHK(launch_pack_traces(dptr<double>(s, "traces"), out, bits, s->cap, n, (long)s->S * s->R,
+                            (hipStream_t)stream));
+  return PMDG_OK;
+}
+
 pmdg_status pmdg_read_modal(pmdg_solver* s, int sc, double* q, double* qd, double* qdd, void* stream) {
   if (!s) return fail(PMDG_EINVAL, "NULL solver");
   if (!s->bound) return fail(PMDG_ESTATE, "not bound");

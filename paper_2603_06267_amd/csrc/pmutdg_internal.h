@@ -207,6 +207,7 @@ int stiff2_tile_rows(int N);  // owned rows per two-step tile (0: order not supp
 hipError_t launch_stiff2_lo(const StiffArgs<float>& a, hipStream_t st);
 hipError_t launch_fill_bytes(void* p, size_t n, hipStream_t st);
 hipError_t launch_tick(long* counter, int* xsel, int toggle, hipStream_t st);
+hipError_t launch_pack_traces(const double* src, void* dst, int bits, long cap, long n, long rows, hipStream_t st);
 // perfectly matched layer (pml_kernels.hip): the stiffness update with the
 // layer's terms, and the auxiliary-field kernels run after it
 template <typename Real>

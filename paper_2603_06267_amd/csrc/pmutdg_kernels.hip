@@ -554,9 +554,30 @@ __global__ void k_fill(Real* p, long n, Real v) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = v;
 }
 
+// Packs rows of the trace buffer (leading dimension cap) into a dense
+// [rows][n] array of type Out.
+template <typename Out>
+__global__ void k_pack_traces(const double* __restrict__ src, Out* __restrict__ dst, long cap, long n, long rows) {
+  const long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i >= rows * n) return;
+  const long r = i / n, j = i - r * n;
+  dst[i] = (Out)src[r * cap + j];
+}
+
 // ------------------------------------------------------------------------
 // Launchers
 // ------------------------------------------------------------------------
+hipError_t launch_pack_traces(const double* src, void* dst, int bits, long cap, long n, long rows, hipStream_t st) {
+  const long total = rows * n;
+  if (total <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)((total + 255) / 256);
+  if (bits == 32)
+    hipLaunchKernelGGL(k_pack_traces<float>, dim3(grid), dim3(256), 0, st, src, (float*)dst, cap, n, rows);
+  else
+    hipLaunchKernelGGL(k_pack_traces<double>, dim3(grid), dim3(256), 0, st, src, (double*)dst, cap, n, rows);
+  return hipGetLastError();
+}
+
 template <>
 hipError_t launch_stiff<float>(const StiffArgs<float>& a, bool incr, hipStream_t st) {
   if (!incr) return hipErrorInvalidValue;  // FP32 state always uses the increment form

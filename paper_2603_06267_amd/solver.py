@@ -72,6 +72,10 @@ class Solver:
 
     def close(self):
         if getattr(self, "h", None):
+            if getattr(self, "ws", None) is not None:
+                # work enqueued on any stream may still read the workspace
+                import torch
+                torch.cuda.synchronize(self.ws.device)
             self.L.pmdg_destroy(self.h)
             self.h = None
         self.ws = None
@@ -186,6 +190,18 @@ class Solver:
         out = np.zeros((self.S, self.R, max(n, 1)))
         check(self.L.pmdg_read_traces(self.h, _d(out), _stream_ptr(stream)))
         return out[:, :, :n]
+
+    def read_traces_device(self, bits=32, stream=None):
+        """Traces [S, R, steps_done] as a device tensor (FP32 or FP64),
+        written by the library on `stream` without a host round trip."""
+        import torch
+        n = self.steps_done()
+        dt = torch.float32 if bits == 32 else torch.float64
+        out = torch.empty((self.S, self.R, n), dtype=dt, device=self.device)
+        if out.numel():
+            check(self.L.pmdg_read_traces_device(self.h, ctypes.c_void_p(out.data_ptr()), bits,
+                                                 _stream_ptr(stream)))
+        return out
 
     def read_modal(self, s=0, stream=None):
         nm = max(self.Np * self.Nm, 1)

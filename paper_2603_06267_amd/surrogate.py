@@ -112,8 +112,8 @@ def solve(F, steps=512, device="cuda", stream=None, max_scenarios=4096):
         wl = dict(base, drive=drive_from_features(F[i0:i0 + max_scenarios]))
         g = _solver.from_workload(wl, precision=32, n_steps=steps, shape_fn=sf, device=device)
         g.step(steps, stream)
-        tr = g.read_traces(stream)
-        out.append(torch.from_numpy(tr.reshape(tr.shape[0], -1).astype(np.float32)).to(device))
+        tr = g.read_traces_device(32, stream)
+        out.append(tr.reshape(tr.shape[0], -1))
         g.close()
     return torch.cat(out) if len(out) > 1 else out[0]
 

@@ -176,3 +176,23 @@ def test_set_state_keeps_other_scenarios():
     tr = g.read_traces()
     assert np.array_equal(tr[1], full[1])
     assert rel_l2(tr[0], full[0]) < 1e-6
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_traces_on_device_equal_host_read(precision):
+    """pmdg_read_traces_device: FP64 output equals the host read bit for bit,
+    FP32 output is its round-to-nearest; two scenarios, a trace buffer with
+    spare capacity (leading dimension > steps done)."""
+    import torch
+    wl = W.config1()
+    _say(f"device traces, config1, precision={precision}")
+    g = solver.from_workload(wl, precision=precision, n_steps=100, shape_fn=W.shape_fn(wl))
+    g.step(37)
+    host = g.read_traces()
+    d64 = g.read_traces_device(64).cpu().numpy()
+    d32 = g.read_traces_device(32).cpu().numpy()
+    assert d64.shape == host.shape == (g.S, g.R, 37)
+    assert np.array_equal(d64, host)
+    assert np.array_equal(d32, host.astype(np.float32))
+    assert np.abs(host).max() > 0
+    g.close()
