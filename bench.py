@@ -113,8 +113,19 @@ def cpu_baseline(wl, steps):
     o.step(steps)
     dt = time.perf_counter() - t0
     dofs = W.unique_dofs(wl)
-    return {"value": dofs * steps / dt, "unit": "DOF-updates/s", "cores": ref.num_threads(), "kind": "oracle",
-            "sample": f"{steps} steps of the same config-3 workload (FP64 oracle, {dt:.1f} s)"}
+    cores = ref.num_threads()
+    # the same oracle on one thread, for one step of the same state
+    ref.set_threads(1)
+    try:
+        t1 = time.perf_counter()
+        o.step(1)
+        dt1 = time.perf_counter() - t1
+    finally:
+        ref.set_threads(cores)
+    return {"value": dofs * steps / dt, "unit": "DOF-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{steps} steps of the same config-3 workload (FP64 oracle, {dt:.1f} s)",
+            "single_thread": {"value": dofs / dt1, "unit": "DOF-updates/s", "cores": 1,
+                              "sample": f"step {steps + 1} of the same run on one thread ({dt1:.1f} s)"}}
 
 
 def run_gpu(wl, precision, steps, warmup, graphs, rows, zchunk, tblock=1):

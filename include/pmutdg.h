@@ -30,7 +30,22 @@
  *   - Layout of the primary brick: PMUT discs sit on its bottom face
  *     z = x0[2]; the secondary brick (if any) sits on top of it and shares the
  *     primary's top face as Gamma_I (the primary is the "+" / fine side).
- *   - All boundaries other than PMUT discs are rigid (homogeneous Neumann).
+ *   - Boundaries other than PMUT discs are rigid (homogeneous Neumann)
+ *     unless pmdg_set_absorbing or pmdg_set_pml says otherwise.
+ *
+ * Shape of the interface
+ *   - A problem is described in steps rather than one struct: pmdg_create
+ *     (mesh, time step, precision, scenario count), then pmdg_set_pmuts,
+ *     pmdg_set_pmut_shape (mode shapes, per PMUT, once its face nodes are
+ *     known from pmdg_pmut_face_nodes), pmdg_set_drive, pmdg_set_rx,
+ *     pmdg_set_receivers and the boundary calls, then pmdg_bind.  Each call
+ *     validates its own arguments, so an error names the input at fault.
+ *   - Batching (pmdg_batch_create) takes solvers that are already bound
+ *     rather than problem descriptions: the batch reuses each solver's
+ *     tables, state and traces in place and results are read through the
+ *     solvers, so no second copy of a problem exists.
+ *   - Traces are read into host memory (pmdg_read_traces) or device memory
+ *     (pmdg_read_traces_device).
  */
 #ifndef PMUTDG_H
 #define PMUTDG_H

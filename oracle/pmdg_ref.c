@@ -1098,6 +1098,15 @@ double pmdg_ref_cfl_dt(void *h, double cfl) {
   return best;
 }
 
+/* Thread count of the oracle's OpenMP loops from here on (n >= 1). */
+void pmdg_ref_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 int pmdg_ref_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

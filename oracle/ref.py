@@ -79,6 +79,7 @@ def lib():
         L.pmdg_ref_lagrange.argtypes = [ctypes.c_int, _dp, ctypes.c_double, _dp, _dp]
         L.pmdg_ref_element_apply.argtypes = [ctypes.c_int, _dp, ctypes.c_double, _dp, _dp]
         L.pmdg_ref_num_threads.restype = ctypes.c_int
+        L.pmdg_ref_set_threads.argtypes = [ctypes.c_int]
         L.pmdg_ref_set_absorbing.argtypes = [vp, ctypes.c_int, ctypes.c_int]
         L.pmdg_ref_absorbing.argtypes = [vp, _dp]
         L.pmdg_ref_set_pml.restype = ctypes.c_int
@@ -136,6 +137,11 @@ def drive(A, theta, f, ncyc, envelope, t):
 
 def num_threads():
     return lib().pmdg_ref_num_threads()
+
+
+def set_threads(n):
+    """Thread count of the oracle's loops from here on."""
+    lib().pmdg_ref_set_threads(int(n))
 
 
 def dom_params(dom):
