@@ -21,6 +21,11 @@
  *   - Newmark beta=0, gamma=1/2 time stepping (Sec. 3.1, Algorithm 1), in the
  *     synchronised ordering (the ODE samples the predicted pressure at the new
  *     time level); the printed ordering is kept behind a switch for tests.
+ *   - Trilinear hexahedra (Sec. 3: every element the image of the reference
+ *     cube under a trilinear map X_K with positive Jacobian): node
+ *     coordinates, lumped mass, element stiffness with the metric terms,
+ *     PMUT face weights with the surface Jacobian, receivers located by a
+ *     Newton inverse map; and the face matching of Sec. 5, Algorithm 3.
  *   - The smooth drive window g(t) (Sec. 6.1, eq. voltage).
  *   - First-order absorbing faces and the perfectly matched layer (Sec. 2,
  *     eq. full_problem: the damping alpha p_t + beta p, the auxiliary fields
@@ -144,6 +149,9 @@ typedef struct {
   long nnodes, off;
   double xg[RMAXN], wg[RMAXN];
   double D[RMAXN][RMAXN];
+  /* trilinear hexahedra (Sec. 3, maps X_K): vertex coordinates
+   * [(ne0+1)(ne1+1)(ne2+1)][3], x fastest; NULL for an axis-aligned brick */
+  double *V;
 } rdom;
 
 typedef struct {
@@ -202,6 +210,151 @@ static double node_coord(const rdom *d, int axis, int i) {
   return d->x0[axis] + d->h[axis] * (e + 0.5 * (d->xg[a] + 1.0));
 }
 
+/* ------------------------------------------------------------------ */
+/* Trilinear hexahedra (Sec. 3, maps X_K)                              */
+/* ------------------------------------------------------------------ */
+
+/* Corner c = cx + 2 cy + 4 cz of the reference cube sits at
+ * ((-1)^(cx+1), (-1)^(cy+1), (-1)^(cz+1)).  X(xi) = sum_c N_c(xi) V_c with
+ * N_c = prod_a (1 + s_a xi_a) / 2; J[i][j] = d x_i / d xi_j. */
+static void tri_map(const double V8[8][3], const double xi[3], double x[3], double J[3][3]) {
+  for (int i = 0; i < 3; ++i) {
+    x[i] = 0;
+    for (int j = 0; j < 3; ++j) J[i][j] = 0;
+  }
+  for (int c = 0; c < 8; ++c) {
+    double sg[3], f[3];
+    for (int a = 0; a < 3; ++a) {
+      sg[a] = ((c >> a) & 1) ? 1.0 : -1.0;
+      f[a] = 0.5 * (1.0 + sg[a] * xi[a]);
+    }
+    double Nc = f[0] * f[1] * f[2];
+    double dN[3] = {0.5 * sg[0] * f[1] * f[2], 0.5 * sg[1] * f[0] * f[2], 0.5 * sg[2] * f[0] * f[1]};
+    for (int i = 0; i < 3; ++i) {
+      x[i] += Nc * V8[c][i];
+      for (int j = 0; j < 3; ++j) J[i][j] += dN[j] * V8[c][i];
+    }
+  }
+}
+
+static double det3(const double J[3][3]) {
+  return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+         J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+}
+
+/* Inverse of a 3x3 matrix by its adjugate; returns the determinant. */
+static double inv3(const double J[3][3], double Ji[3][3]) {
+  double dt = det3(J);
+  Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / dt;
+  Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / dt;
+  Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / dt;
+  Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / dt;
+  Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / dt;
+  Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / dt;
+  Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / dt;
+  Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / dt;
+  Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / dt;
+  return dt;
+}
+
+static long vidx(const rdom *d, int i, int j, int k) {
+  return i + (long)(d->ne[0] + 1) * (j + (long)(d->ne[1] + 1) * k);
+}
+
+/* The eight vertices of element (ex, ey, ez) in corner order. */
+static void elem_vertices(const rdom *d, int ex, int ey, int ez, double V8[8][3]) {
+  for (int c = 0; c < 8; ++c) {
+    long v = vidx(d, ex + (c & 1), ey + ((c >> 1) & 1), ez + ((c >> 2) & 1));
+    for (int a = 0; a < 3; ++a) V8[c][a] = d->V[3 * v + a];
+  }
+}
+
+/* Element and local index along one axis of global node index i: the lower
+ * element owns a shared node, except at the last node of the line. */
+static void node_elem(const rdom *d, int axis, int i, int *e, int *a) {
+  *e = i / d->N;
+  *a = i % d->N;
+  if (*e == d->ne[axis]) { *e -= 1; *a = d->N; }
+}
+
+/* Coordinates of node (i, j, k): on a brick the tensor grid, on trilinear
+ * hexahedra the map of the lowest element containing it at its GLL point. */
+static void node_xyz(const rdom *d, int i, int j, int k, double x[3]) {
+  if (!d->V) {
+    x[0] = node_coord(d, 0, i); x[1] = node_coord(d, 1, j); x[2] = node_coord(d, 2, k);
+    return;
+  }
+  int e[3], a[3], g[3] = {i, j, k};
+  for (int t = 0; t < 3; ++t) node_elem(d, t, g[t], &e[t], &a[t]);
+  double V8[8][3], J[3][3], xi[3] = {d->xg[a[0]], d->xg[a[1]], d->xg[a[2]]};
+  elem_vertices(d, e[0], e[1], e[2], V8);
+  tri_map(V8, xi, x, J);
+}
+
+/* Element residual r = K_e u of the volume term of a on a trilinear
+ * hexahedron with vertices V24 (corner order): the integral of
+ * c^2 grad u . grad v over K = X_K(K^), by GLL collocation on the
+ * reference cube.  At each node grad_x u = J^{-T} grad_xi u, so the
+ * reference flux is w |J| c^2 J^{-1} J^{-T} grad_xi u, tested with
+ * grad_xi l_m (Sec. 3, eq. Wf_2, first sum, with the change of variables
+ * x = X_K(xi)).  u, r are [(N+1)^3] with a fastest. */
+void pmdg_ref_hex_apply(int N, const double *V24, double c, const double *u, double *r) {
+  double xg[RMAXN], w[RMAXN], D[RMAXN * RMAXN], V8[8][3];
+  pmdg_ref_gll(N, xg, w);
+  pmdg_ref_dmat(N, D);
+  for (int q = 0; q < 8; ++q)
+    for (int a = 0; a < 3; ++a) V8[q][a] = V24[3 * q + a];
+  int n1 = N + 1;
+#define U(a, b, cc) u[(a) + n1 * ((b) + n1 * (cc))]
+  for (int i = 0; i < n1 * n1 * n1; ++i) r[i] = 0.0;
+  for (int cc = 0; cc <= N; ++cc)
+    for (int b = 0; b <= N; ++b)
+      for (int a = 0; a <= N; ++a) {
+        double gr[3] = {0, 0, 0};
+        for (int m = 0; m <= N; ++m) {
+          gr[0] += D[a * n1 + m] * U(m, b, cc);
+          gr[1] += D[b * n1 + m] * U(a, m, cc);
+          gr[2] += D[cc * n1 + m] * U(a, b, m);
+        }
+        double xi[3] = {xg[a], xg[b], xg[cc]}, x[3], J[3][3], Ji[3][3];
+        tri_map(V8, xi, x, J);
+        double dJ = inv3(J, Ji);
+        /* physical gradient, then the reference flux J^{-1} (grad_x u) */
+        double gx[3], F[3];
+        for (int i = 0; i < 3; ++i) gx[i] = Ji[0][i] * gr[0] + Ji[1][i] * gr[1] + Ji[2][i] * gr[2];
+        double wq = w[a] * w[b] * w[cc] * dJ * c * c;
+        for (int i = 0; i < 3; ++i) F[i] = wq * (Ji[i][0] * gx[0] + Ji[i][1] * gx[1] + Ji[i][2] * gx[2]);
+        for (int m = 0; m <= N; ++m) {
+          r[m + n1 * (b + n1 * cc)] += D[a * n1 + m] * F[0];
+          r[a + n1 * (m + n1 * cc)] += D[b * n1 + m] * F[1];
+          r[a + n1 * (b + n1 * m)] += D[cc * n1 + m] * F[2];
+        }
+      }
+#undef U
+}
+
+/* Newton's method for the reference point xi of x in the element with
+ * vertices V8, from xi = 0; returns 0 when it converged (|dxi| < 1e-14),
+ * -1 otherwise. */
+static int tri_inverse(const double V8[8][3], const double x[3], double xi[3]) {
+  xi[0] = xi[1] = xi[2] = 0.0;
+  for (int it = 0; it < 60; ++it) {
+    double y[3], J[3][3], Ji[3][3], dx[3], st = 0;
+    tri_map(V8, xi, y, J);
+    if (!(fabs(det3(J)) > 0)) return -1;
+    inv3(J, Ji);
+    for (int i = 0; i < 3; ++i) dx[i] = x[i] - y[i];
+    for (int i = 0; i < 3; ++i) {
+      double d = Ji[i][0] * dx[0] + Ji[i][1] * dx[1] + Ji[i][2] * dx[2];
+      xi[i] += d;
+      st += fabs(d);
+    }
+    if (!(fabs(xi[0]) < 10 && fabs(xi[1]) < 10 && fabs(xi[2]) < 10)) return -1;
+    if (st < 1e-14) return 0;
+  }
+  return -1;
+}
+
 static int setup_dom(rdom *d, const double *prm) {
   /* prm: x0[3], h[3], ne[3], N, c, rho */
   for (int a = 0; a < 3; ++a) { d->x0[a] = prm[a]; d->h[a] = prm[3 + a]; d->ne[a] = (int)prm[6 + a]; }
@@ -230,11 +383,21 @@ static void build_mass(rsolver *s) {
     double J = d->h[0] * d->h[1] * d->h[2] / 8.0;
     for (int ez = 0; ez < d->ne[2]; ++ez)
       for (int ey = 0; ey < d->ne[1]; ++ey)
-        for (int ex = 0; ex < d->ne[0]; ++ex)
+        for (int ex = 0; ex < d->ne[0]; ++ex) {
+          double V8[8][3];
+          if (d->V) elem_vertices(d, ex, ey, ez, V8);
           for (int c = 0; c <= N; ++c)
             for (int b = 0; b <= N; ++b)
-              for (int a = 0; a <= N; ++a)
-                s->mass[nidx(d, N * ex + a, N * ey + b, N * ez + c)] += d->wg[a] * d->wg[b] * d->wg[c] * J;
+              for (int a = 0; a <= N; ++a) {
+                double Jq = J;
+                if (d->V) {
+                  double xi[3] = {d->xg[a], d->xg[b], d->xg[c]}, x[3], Jm[3][3];
+                  tri_map(V8, xi, x, Jm);
+                  Jq = det3(Jm);
+                }
+                s->mass[nidx(d, N * ex + a, N * ey + b, N * ez + c)] += d->wg[a] * d->wg[b] * d->wg[c] * Jq;
+              }
+        }
   }
 }
 
@@ -246,6 +409,7 @@ static void build_mass(rsolver *s) {
  * high end.  Calls accumulate (one per domain). */
 void pmdg_ref_set_absorbing(void *h, int dd, int faces) {
   rsolver *s = (rsolver *)h;
+  if (s->d[dd].V) return; /* absorbing faces on trilinear hexahedra are not built */
   if (!s->cabs) s->cabs = (double *)calloc(s->ntot, sizeof(double));
   rdom *d = &s->d[dd];
   int N = d->N;
@@ -266,6 +430,139 @@ void pmdg_ref_set_absorbing(void *h, int dd, int faces) {
               s->cabs[nidx(d, g[0], g[1], g[2])] += d->c * d->wg[a] * d->wg[b] * Jf;
             }
     }
+}
+
+/* Trilinear hexahedra for the domain of a single-domain solver: V holds
+ * the (ne0+1)(ne1+1)(ne2+1) vertices [.. x 3], x fastest (Sec. 3: element
+ * (ex, ey, ez) is the trilinear image of the reference cube on its eight
+ * vertices).  Returns 0; -1 for a two-domain solver or one with absorbing
+ * faces or a layer; -2 when the Jacobian determinant is not positive at a
+ * GLL node of some element.  Rebuilds the lumped mass; PMUTs and receivers
+ * are set afterwards. */
+int pmdg_ref_set_vertices(void *h, int dd, const double *V) {
+  rsolver *s = (rsolver *)h;
+  if (s->ndom != 1 || dd != 0 || s->cabs || s->pml_on[0]) return -1;
+  rdom *d = &s->d[dd];
+  long nv = (long)(d->ne[0] + 1) * (d->ne[1] + 1) * (d->ne[2] + 1);
+  double *Vc = (double *)malloc(sizeof(double) * 3 * nv);
+  memcpy(Vc, V, sizeof(double) * 3 * nv);
+  double *old = d->V;
+  d->V = Vc;
+  int N = d->N;
+  for (int ez = 0; ez < d->ne[2]; ++ez)
+    for (int ey = 0; ey < d->ne[1]; ++ey)
+      for (int ex = 0; ex < d->ne[0]; ++ex) {
+        double V8[8][3];
+        elem_vertices(d, ex, ey, ez, V8);
+        for (int c = 0; c <= N; ++c)
+          for (int b = 0; b <= N; ++b)
+            for (int a = 0; a <= N; ++a) {
+              double xi[3] = {d->xg[a], d->xg[b], d->xg[c]}, x[3], J[3][3];
+              tri_map(V8, xi, x, J);
+              if (!(det3(J) > 0)) {
+                d->V = old;
+                free(Vc);
+                return -2;
+              }
+            }
+      }
+  free(old);
+  build_mass(s);
+  return 0;
+}
+
+/* Outward unit normal at the centre of face f = 2 axis + side of the
+ * element with vertices V8, the face's first corner and its diameter (the
+ * longer diagonal). */
+static void face_geometry(const double V8[8][3], int f, double n[3], double v0[3], double *diam) {
+  int ax = f / 2, side = f % 2, t1 = (ax + 1) % 3, t2 = (ax + 2) % 3;
+  double xi[3] = {0, 0, 0}, x[3], J[3][3];
+  xi[ax] = side ? 1.0 : -1.0;
+  tri_map(V8, xi, x, J);
+  double a[3] = {J[0][t1], J[1][t1], J[2][t1]}, b[3] = {J[0][t2], J[1][t2], J[2][t2]};
+  double c[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+  double l = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]), sg = side ? 1.0 : -1.0;
+  for (int i = 0; i < 3; ++i) n[i] = sg * c[i] / l;
+  /* corners of the face: bit ax fixed to side; k00, k10, k01, k11 in (t1, t2) */
+  int k[4];
+  for (int q = 0; q < 4; ++q) k[q] = (side << ax) | ((q & 1) << t1) | (((q >> 1) & 1) << t2);
+  for (int i = 0; i < 3; ++i) v0[i] = V8[k[0]][i];
+  double d1 = 0, d2 = 0;
+  for (int i = 0; i < 3; ++i) {
+    d1 += (V8[k[3]][i] - V8[k[0]][i]) * (V8[k[3]][i] - V8[k[0]][i]);
+    d2 += (V8[k[2]][i] - V8[k[1]][i]) * (V8[k[2]][i] - V8[k[1]][i]);
+  }
+  *diam = sqrt(d1 > d2 ? d1 : d2);
+}
+
+/* Face matching on Gamma_I (Sec. 5, Algorithm 3).  Fine side: nf
+ * hexahedra fine_hex [nf][8][3] (corner order) and the local face of each
+ * on Gamma_I, fine_face[nf] = 2 axis + side (side 0: xi_axis = -1, side 1:
+ * +1); coarse side likewise (nc, coarse_hex, coarse_face).  For every
+ * Gauss-Legendre point (nq per direction) of every fine face, x_q =
+ * X_{K+}(xi), the coarse faces are taken in index order; one is a candidate
+ * when its outward normal at its centre is opposite to the fine face's,
+ * |n+ + n-| < tol, and its first corner lies within
+ * r = max(diam F-, diam F+) + eps of x_q; the first candidate whose
+ * element's inverse map (Newton) puts x_q in [-1, 1]^3, up to 1e-10, is the
+ * match.  Points are ordered (fine face, j, i) with i along the face's
+ * first tangential axis (axis + 1) mod 3.  Writes elem[nf nq^2] (coarse
+ * index, or -1) and xi[nf nq^2][3]; returns the number of unmatched points,
+ * or -1 for bad arguments. */
+int pmdg_ref_match_faces(int nq, int nf, const double *fine_hex, const int *fine_face, int nc,
+                         const double *coarse_hex, const int *coarse_face, double tol, double eps,
+                         int *elem, double *xi) {
+  if (nq < 1 || nq > RMAXQ || nf < 0 || nc < 0) return -1;
+  double gq[RMAXQ], gw[RMAXQ];
+  pmdg_ref_gl(nq, gq, gw);
+  double *cn = (double *)malloc(sizeof(double) * 3 * (nc ? nc : 1));
+  double *cv = (double *)malloc(sizeof(double) * 3 * (nc ? nc : 1));
+  double *cd = (double *)malloc(sizeof(double) * (nc ? nc : 1));
+  for (int c = 0; c < nc; ++c) {
+    double V8[8][3];
+    memcpy(V8, coarse_hex + 24L * c, sizeof(V8));
+    if (coarse_face[c] < 0 || coarse_face[c] > 5) { free(cn); free(cv); free(cd); return -1; }
+    face_geometry(V8, coarse_face[c], cn + 3 * c, cv + 3 * c, cd + c);
+  }
+  int unmatched = 0;
+  for (int f = 0; f < nf; ++f) {
+    double V8[8][3], nf3[3], vf[3], df;
+    memcpy(V8, fine_hex + 24L * f, sizeof(V8));
+    if (fine_face[f] < 0 || fine_face[f] > 5) { unmatched = -1; break; }
+    face_geometry(V8, fine_face[f], nf3, vf, &df);
+    int ax = fine_face[f] / 2, t1 = (ax + 1) % 3, t2 = (ax + 2) % 3;
+    for (int j = 0; j < nq; ++j)
+      for (int i = 0; i < nq; ++i) {
+        long q = ((long)f * nq + j) * nq + i;
+        double r[3], x[3], J[3][3];
+        r[ax] = (fine_face[f] % 2) ? 1.0 : -1.0;
+        r[t1] = gq[i];
+        r[t2] = gq[j];
+        tri_map(V8, r, x, J);
+        elem[q] = -1;
+        xi[3 * q] = xi[3 * q + 1] = xi[3 * q + 2] = 0.0;
+        for (int c = 0; c < nc; ++c) {
+          double sn = 0, dv = 0;
+          for (int k = 0; k < 3; ++k) {
+            sn += (nf3[k] + cn[3 * c + k]) * (nf3[k] + cn[3 * c + k]);
+            dv += (cv[3 * c + k] - x[k]) * (cv[3 * c + k] - x[k]);
+          }
+          double rad = (cd[c] > df ? cd[c] : df) + eps;
+          if (!(sqrt(sn) < tol && sqrt(dv) < rad)) continue;
+          double W8[8][3], t[3];
+          memcpy(W8, coarse_hex + 24L * c, sizeof(W8));
+          if (tri_inverse(W8, x, t)) continue;
+          if (fabs(t[0]) <= 1 + 1e-10 && fabs(t[1]) <= 1 + 1e-10 && fabs(t[2]) <= 1 + 1e-10) {
+            elem[q] = c;
+            for (int k = 0; k < 3; ++k) xi[3 * q + k] = t[k];
+            break;
+          }
+        }
+        if (elem[q] < 0) ++unmatched;
+      }
+  }
+  free(cn); free(cv); free(cd);
+  return unmatched;
 }
 
 /* Copies C (zeros without absorbing faces) into out [ntot]. */
@@ -328,7 +625,13 @@ static void volume_apply(const rsolver *s, const double *p, double *Kp) {
           for (int b = 0; b <= N; ++b)
             for (int a = 0; a <= N; ++a)
               u[a + n1 * (b + n1 * c)] = p[nidx(d, N * ex + a, N * ey + b, N * ez + c)];
-        pmdg_ref_element_apply(N, d->h, d->c, u, r);
+        if (d->V) {
+          double V8[8][3];
+          elem_vertices(d, ex, ey, ez, V8);
+          pmdg_ref_hex_apply(N, &V8[0][0], d->c, u, r);
+        } else {
+          pmdg_ref_element_apply(N, d->h, d->c, u, r);
+        }
         for (int c = 0; c <= N; ++c)
           for (int b = 0; b <= N; ++b)
             for (int a = 0; a <= N; ++a)
@@ -390,6 +693,19 @@ static int build_interface(rsolver *s) {
       }
   }
   return 0;
+}
+
+/* The interface quadrature-point list: coarse element (ex, ey) and
+ * reference coordinates (xi, eta) of every Gauss-Legendre point of every
+ * fine face, [npts][2] each, points ordered (fine face, eta, xi) with the
+ * fine face ex + ne0 ey.  Returns npts (0 without an interface). */
+long pmdg_ref_interface_points(void *h, int *ce, double *xi) {
+  rsolver *s = (rsolver *)h;
+  if (s->ndom < 2) return 0;
+  long npts = s->nfine * s->nq * s->nq;
+  if (ce) memcpy(ce, s->q_ce, sizeof(int) * 2 * npts);
+  if (xi) memcpy(xi, s->q_xi, sizeof(double) * 2 * npts);
+  return npts;
 }
 
 /* Adds the three interface sums of a (Sec. 3, eq. Wf_2) for all test
@@ -501,6 +817,7 @@ void pmdg_ref_destroy(void *h) {
   free(s->mass); free(s->cabs); free(s->p); free(s->pd); free(s->pdd);
   free(s->q_ce); free(s->q_xi); free(s->rcv);
   for (int d = 0; d < 2; ++d) {
+    free(s->d[d].V);
     for (int a = 0; a < 3; ++a) free(s->pzeta[d][a]);
     free(s->eslot[d]); free(s->Phi[d]);
   }
@@ -526,10 +843,7 @@ void pmdg_ref_coords(void *h, double *xyz) {
     for (int k = 0; k < d->nn[2]; ++k)
       for (int j = 0; j < d->nn[1]; ++j)
         for (int i = 0; i < d->nn[0]; ++i) {
-          long n = nidx(d, i, j, k);
-          xyz[3 * n] = node_coord(d, 0, i);
-          xyz[3 * n + 1] = node_coord(d, 1, j);
-          xyz[3 * n + 2] = node_coord(d, 2, k);
+          node_xyz(d, i, j, k, xyz + 3 * nidx(d, i, j, k));
         }
   }
 }
@@ -612,16 +926,33 @@ int pmdg_ref_set_pmuts(void *h, int Np, const double *ctr, const double *rad, in
   double *wf = (double *)calloc((size_t)nx * ny, sizeof(double));
   double Jf = 0.25 * d->h[0] * d->h[1];
   for (int ey = 0; ey < d->ne[1]; ++ey)
-    for (int ex = 0; ex < d->ne[0]; ++ex)
+    for (int ex = 0; ex < d->ne[0]; ++ex) {
+      double V8[8][3];
+      if (d->V) elem_vertices(d, ex, ey, 0, V8);
       for (int b = 0; b <= N; ++b)
-        for (int a = 0; a <= N; ++a) wf[(N * ex + a) + (long)nx * (N * ey + b)] += d->wg[a] * d->wg[b] * Jf;
+        for (int a = 0; a <= N; ++a) {
+          double Jq = Jf;
+          if (d->V) {
+            /* surface Jacobian |dX/dxi x dX/deta| on the face zeta = -1 */
+            double xi[3] = {d->xg[a], d->xg[b], -1.0}, x[3], J[3][3];
+            tri_map(V8, xi, x, J);
+            double cx = J[1][0] * J[2][1] - J[2][0] * J[1][1];
+            double cy = J[2][0] * J[0][1] - J[0][0] * J[2][1];
+            double cz = J[0][0] * J[1][1] - J[1][0] * J[0][1];
+            Jq = sqrt(cx * cx + cy * cy + cz * cz);
+          }
+          wf[(N * ex + a) + (long)nx * (N * ey + b)] += d->wg[a] * d->wg[b] * Jq;
+        }
+    }
   for (int k = 0; k < Np; ++k) {
     int cnt = 0;
     for (int pass = 0; pass < 2; ++pass) {
       cnt = 0;
       for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
-          double dx = node_coord(d, 0, i) - ctr[2 * k], dy = node_coord(d, 1, j) - ctr[2 * k + 1];
+          double xn[3];
+          node_xyz(d, i, j, 0, xn);
+          double dx = xn[0] - ctr[2 * k], dy = xn[1] - ctr[2 * k + 1];
           if (sqrt(dx * dx + dy * dy) <= rad[k]) {
             if (pass == 1) {
               s->fn_node[k][cnt] = nidx(d, i, j, 0);
@@ -652,9 +983,7 @@ int pmdg_ref_pmut_nodes(void *h, int k, double *xyz) {
     for (int n = 0; n < s->fn_cnt[k]; ++n) {
       long g = s->fn_node[k][n] - d->off;
       int i = (int)(g % d->nn[0]), j = (int)((g / d->nn[0]) % d->nn[1]);
-      xyz[3 * n] = node_coord(d, 0, i);
-      xyz[3 * n + 1] = node_coord(d, 1, j);
-      xyz[3 * n + 2] = node_coord(d, 2, 0);
+      node_xyz(d, i, j, 0, xyz + 3 * n);
     }
   }
   return s->fn_cnt[k];
@@ -731,7 +1060,23 @@ int pmdg_ref_set_receivers(void *h, int R, const double *xyz) {
       int e[3];
       double xi[3];
       int inside = 1;
-      for (int a = 0; a < 3 && inside; ++a) {
+      if (d->V) {
+        /* lowest element whose inverse map puts the point in [-1, 1]^3 */
+        inside = 0;
+        for (int ez = 0; ez < d->ne[2] && !inside; ++ez)
+          for (int ey = 0; ey < d->ne[1] && !inside; ++ey)
+            for (int ex = 0; ex < d->ne[0] && !inside; ++ex) {
+              double V8[8][3], t[3];
+              elem_vertices(d, ex, ey, ez, V8);
+              if (tri_inverse(V8, xyz + 3 * r, t)) continue;
+              if (fabs(t[0]) <= 1 + 1e-10 && fabs(t[1]) <= 1 + 1e-10 && fabs(t[2]) <= 1 + 1e-10) {
+                inside = 1;
+                e[0] = ex; e[1] = ey; e[2] = ez;
+                xi[0] = t[0]; xi[1] = t[1]; xi[2] = t[2];
+              }
+            }
+      }
+      for (int a = 0; a < 3 && inside && !d->V; ++a) {
         int found = -1;
         for (int k = 0; k < d->ne[a]; ++k) {
           double t = 2.0 * (xyz[3 * r + a] - (d->x0[a] + k * d->h[a])) / d->h[a] - 1.0;
@@ -791,6 +1136,7 @@ static double pml_profile(double d, double ell, double c, double R) {
 int pmdg_ref_set_pml(void *h, int dd, const double *ell, double R) {
   rsolver *s = (rsolver *)h;
   if (dd < 0 || dd >= s->ndom || !(R > 0 && R < 1)) return -1;
+  if (s->d[dd].V) return -1; /* layers on trilinear hexahedra are not built */
   rdom *d = &s->d[dd];
   for (int a = 0; a < 3; ++a) {
     double L = d->h[a] * d->ne[a];
@@ -1091,7 +1437,26 @@ double pmdg_ref_cfl_dt(void *h, double cfl) {
     const rdom *d = &s->d[dd];
     double gap = INFINITY, hm = INFINITY;
     for (int i = 0; i < d->N; ++i) if (d->xg[i + 1] - d->xg[i] < gap) gap = d->xg[i + 1] - d->xg[i];
-    for (int a = 0; a < 3; ++a) if (d->h[a] < hm) hm = d->h[a];
+    if (!d->V) {
+      for (int a = 0; a < 3; ++a) if (d->h[a] < hm) hm = d->h[a];
+    } else {
+      /* shortest edge of any element */
+      for (int ez = 0; ez < d->ne[2]; ++ez)
+        for (int ey = 0; ey < d->ne[1]; ++ey)
+          for (int ex = 0; ex < d->ne[0]; ++ex) {
+            double V8[8][3];
+            elem_vertices(d, ex, ey, ez, V8);
+            for (int c = 0; c < 8; ++c)
+              for (int a = 0; a < 3; ++a) {
+                if ((c >> a) & 1) continue;
+                int c2 = c | (1 << a);
+                double l = sqrt((V8[c2][0] - V8[c][0]) * (V8[c2][0] - V8[c][0]) +
+                                (V8[c2][1] - V8[c][1]) * (V8[c2][1] - V8[c][1]) +
+                                (V8[c2][2] - V8[c][2]) * (V8[c2][2] - V8[c][2]));
+                if (l < hm) hm = l;
+              }
+          }
+    }
     double v = cfl * hm * gap * 0.5 / d->c;
     if (v < best) best = v;
   }

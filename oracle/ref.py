@@ -80,6 +80,15 @@ def lib():
         L.pmdg_ref_element_apply.argtypes = [ctypes.c_int, _dp, ctypes.c_double, _dp, _dp]
         L.pmdg_ref_num_threads.restype = ctypes.c_int
         L.pmdg_ref_set_threads.argtypes = [ctypes.c_int]
+        L.pmdg_ref_set_vertices.restype = ctypes.c_int
+        L.pmdg_ref_set_vertices.argtypes = [vp, ctypes.c_int, _dp]
+        L.pmdg_ref_hex_apply.argtypes = [ctypes.c_int, _dp, ctypes.c_double, _dp, _dp]
+        _ip = ctypes.POINTER(ctypes.c_int)
+        L.pmdg_ref_match_faces.restype = ctypes.c_int
+        L.pmdg_ref_match_faces.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _ip, ctypes.c_int, _dp, _ip,
+                                           ctypes.c_double, ctypes.c_double, _ip, _dp]
+        L.pmdg_ref_interface_points.restype = ctypes.c_long
+        L.pmdg_ref_interface_points.argtypes = [vp, _ip, _dp]
         L.pmdg_ref_set_absorbing.argtypes = [vp, ctypes.c_int, ctypes.c_int]
         L.pmdg_ref_absorbing.argtypes = [vp, _dp]
         L.pmdg_ref_set_pml.restype = ctypes.c_int
@@ -144,6 +153,37 @@ def set_threads(n):
     lib().pmdg_ref_set_threads(int(n))
 
 
+def hex_apply(N, V8, c, u):
+    """K_e u on one trilinear hexahedron with vertices V8 [8 x 3] (corner
+    c = cx + 2 cy + 4 cz), u [(N+1)^3] with the first index fastest."""
+    V8 = np.ascontiguousarray(V8, dtype=np.float64).reshape(24)
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1)
+    r = np.zeros_like(u)
+    lib().pmdg_ref_hex_apply(int(N), _d(V8), float(c), _d(u), _d(r))
+    return r
+
+
+def match_faces(nq, fine_hex, fine_face, coarse_hex, coarse_face, tol=1e-6, eps=1e-9):
+    """Face matching of Sec. 5, Algorithm 3 (see pmdg_ref_match_faces):
+    returns (elem [nf*nq*nq], xi [nf*nq*nq, 3], unmatched count)."""
+    fh = np.ascontiguousarray(fine_hex, dtype=np.float64).reshape(-1, 24)
+    ch = np.ascontiguousarray(coarse_hex, dtype=np.float64).reshape(-1, 24)
+    ff = np.ascontiguousarray(fine_face, dtype=np.int32).reshape(-1)
+    cf = np.ascontiguousarray(coarse_face, dtype=np.int32).reshape(-1)
+    nf, nc = len(fh), len(ch)
+    assert len(ff) == nf and len(cf) == nc
+    elem = np.zeros(max(nf * nq * nq, 1), dtype=np.int32)
+    xi = np.zeros((max(nf * nq * nq, 1), 3))
+    _ip = ctypes.POINTER(ctypes.c_int)
+    n = lib().pmdg_ref_match_faces(int(nq), nf, _d(fh), ff.ctypes.data_as(_ip), nc, _d(ch),
+                                   cf.ctypes.data_as(_ip), float(tol), float(eps),
+                                   elem.ctypes.data_as(_ip), _d(xi))
+    if n < 0:
+        raise ValueError("oracle: bad face-matching arguments")
+    m = nf * nq * nq
+    return elem[:m], xi[:m], n
+
+
 def dom_params(dom):
     """12 doubles {x0[3], h[3], ne[3], N, c, rho} from a brick description."""
     x0 = np.asarray(dom["x0"], dtype=np.float64)
@@ -165,6 +205,7 @@ class RefSolver:
         self.ndom = len(domains)
         self.domains = [dict(d) for d in domains]
         self.n = self.L.pmdg_ref_num_nodes(self.h)
+        self._cfl = None if dt is not None else float(cfl)
         self.dt = float(dt) if dt is not None else self.L.pmdg_ref_cfl_dt(self.h, float(cfl))
         self.L.pmdg_ref_set_dt(self.h, self.dt)
         self.Np = 0
@@ -188,10 +229,39 @@ class RefSolver:
         self.L.pmdg_ref_coords(self.h, _d(x))
         return x
 
+    def set_vertices(self, dom, V):
+        """Trilinear hexahedra: vertex coordinates [(ne0+1)(ne1+1)(ne2+1), 3]
+        of the single domain, x fastest.  A CFL-chosen time step is chosen
+        again from the shortest element edge."""
+        d = self.domains[dom]
+        nv = int(np.prod(np.asarray(d["ne"]) + 1))
+        V = np.ascontiguousarray(V, dtype=np.float64).reshape(nv, 3)
+        r = self.L.pmdg_ref_set_vertices(self.h, int(dom), _d(V))
+        if r == -2:
+            raise ValueError("oracle: an element's Jacobian is not positive")
+        if r:
+            raise ValueError("oracle: trilinear hexahedra need a single domain without absorbing faces or layers")
+        self.domains[dom]["_mapped"] = True
+        if self._cfl is not None:
+            self.dt = self.L.pmdg_ref_cfl_dt(self.h, self._cfl)
+            self.L.pmdg_ref_set_dt(self.h, self.dt)
+
+    def interface_points(self):
+        """(coarse element (ex, ey) [npts, 2], reference (xi, eta) [npts, 2])
+        of every fine-face Gauss-Legendre point, ordered (fine face, eta, xi)."""
+        _ip = ctypes.POINTER(ctypes.c_int)
+        n = self.L.pmdg_ref_interface_points(self.h, None, None)
+        ce = np.zeros((max(n, 1), 2), dtype=np.int32)
+        xi = np.zeros((max(n, 1), 2))
+        self.L.pmdg_ref_interface_points(self.h, ce.ctypes.data_as(_ip), _d(xi))
+        return ce[:n], xi[:n]
+
     def set_absorbing(self, dom, faces):
         """First-order absorbing condition on the outer faces of domain dom
         given by the bitmask faces (bit 2a: low end of axis a, 2a + 1: high
         end)."""
+        if self.domains[dom].get("_mapped"):
+            raise ValueError("oracle: absorbing faces on trilinear hexahedra are not built")
         self.L.pmdg_ref_set_absorbing(self.h, int(dom), int(faces))
 
     def set_pml(self, dom, ell, R=1e-4):
@@ -330,6 +400,9 @@ def from_workload(wl, scenario=0, shape_fn=None):
     shape_fn(k, xyz) -> [Nm x n] mode-shape samples at the given face nodes
     (the workload's own mode-shape generator)."""
     s = RefSolver(wl["domains"], alpha=wl.get("alpha", 2.0), cfl=wl.get("cfl", 0.3))
+    for d, dom in enumerate(wl["domains"]):
+        if dom.get("vertices") is not None:
+            s.set_vertices(d, dom["vertices"])
     for d, dom in enumerate(wl["domains"]):
         if dom.get("absorbing", 0):
             s.set_absorbing(d, dom["absorbing"])

@@ -44,6 +44,82 @@ def brick(x0, x1, ne, N, c=C_WATER, rho=RHO):
             "ne": [int(v) for v in ne], "N": int(N), "c": float(c), "rho": float(rho)}
 
 
+def brick_vertices(dom):
+    """Element vertices of a brick, [(ne0+1)(ne1+1)(ne2+1), 3], x fastest."""
+    x0 = np.asarray(dom["x0"], dtype=np.float64)
+    x1 = np.asarray(dom["x1"], dtype=np.float64)
+    ne = np.asarray(dom["ne"])
+    ax = [x0[a] + (x1[a] - x0[a]) * np.arange(ne[a] + 1) / ne[a] for a in range(3)]
+    Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    return np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+
+
+def warped_vertices(dom, amp=0.15, jitter=0.0, seed=0):
+    """Brick vertices moved by a smooth seeded displacement that keeps every
+    boundary face planar (the component normal to a face vanishes on it),
+    plus an optional seeded jitter of the interior vertices; amp and jitter
+    are in units of the element size.  The elements stay trilinear
+    hexahedra filling the same brick."""
+    rng = np.random.default_rng(SEED0 + 100 + seed)
+    x0 = np.asarray(dom["x0"], dtype=np.float64)
+    x1 = np.asarray(dom["x1"], dtype=np.float64)
+    ne = np.asarray(dom["ne"])
+    h = (x1 - x0) / ne
+    V = brick_vertices(dom)
+    u = (V - x0) / (x1 - x0)
+    ph = rng.uniform(0.0, 2 * math.pi, size=(3, 2))
+    W = V.copy()
+    for a in range(3):
+        b, c = (a + 1) % 3, (a + 2) % 3
+        W[:, a] += amp * h[a] * (np.sin(math.pi * u[:, a]) * np.sin(2 * math.pi * u[:, b] + ph[a, 0])
+                                 * np.sin(2 * math.pi * u[:, c] + ph[a, 1]))
+    if jitter > 0:
+        inner = np.all((u > 1e-12) & (u < 1 - 1e-12), axis=1)
+        W[inner] += jitter * h * rng.uniform(-1.0, 1.0, size=(int(inner.sum()), 3))
+    return W
+
+
+def disc_conforming_vertices(dom, centres, radius, pitch, shrink=1e-9):
+    """Brick vertices moved in x-y so that element edges follow each PMUT
+    disc: in the square cell of side `pitch` around a disc centre (a vertex,
+    with pitch / h an even number of elements), the vertex ring at
+    Chebyshev distance m_d = floor(radius / h) elements lands on the circle
+    of radius radius (1 - shrink), inner rings on concentric circles, and the
+    rings between the circle and the cell boundary are blended linearly
+    towards the unchanged cell boundary.  The same map applies at every
+    height.  `shrink` keeps the ring's nodes strictly inside the disc."""
+    x0 = np.asarray(dom["x0"], dtype=np.float64)
+    x1 = np.asarray(dom["x1"], dtype=np.float64)
+    ne = np.asarray(dom["ne"])
+    h = (x1 - x0) / ne
+    k = pitch / h[0]
+    if abs(h[0] - h[1]) > 1e-12 * h[0] or abs(k - round(k)) > 1e-9 or int(round(k)) % 2:
+        raise ValueError("the pitch must be an even number of equal x-y elements")
+    half = int(round(k)) // 2
+    md = int(math.floor(radius / h[0] + 1e-12))
+    if not 1 <= md < half:
+        raise ValueError("the disc must span at least one element ring inside its cell")
+    V = brick_vertices(dom)
+    out = V.copy()
+    ctr = np.asarray(centres, dtype=np.float64).reshape(-1, 2)
+    rc = radius * (1.0 - shrink)
+    for cx, cy in ctr:
+        u = np.rint((V[:, 0] - cx) / h[0])
+        v = np.rint((V[:, 1] - cy) / h[1])
+        m = np.maximum(np.abs(u), np.abs(v))
+        sel = (m > 0) & (m < half)
+        if not sel.any():
+            continue
+        us, vs, ms = u[sel], v[sel], m[sel]
+        nrm = np.hypot(us, vs)
+        pcx, pcy = rc * us / nrm, rc * vs / nrm
+        t = np.where(ms <= md, 0.0, (ms - md) / (half - md))
+        sc = np.where(ms <= md, ms / md, 1.0)
+        out[sel, 0] = cx + (1 - t) * sc * pcx + t * us * h[0]
+        out[sel, 1] = cy + (1 - t) * sc * pcy + t * vs * h[1]
+    return out
+
+
 def _grid_centres(nx, ny, pitch, offset):
     return np.array([[offset + pitch * i, offset + pitch * j] for j in range(ny) for i in range(nx)],
                     dtype=np.float64)
@@ -253,7 +329,11 @@ def workload_key(wl):
     (bricks, PMUT data, drive, receivers): stored results computed from a
     workload carry it, so a changed generator is noticed."""
     h = hashlib.sha256()
-    h.update(json.dumps(wl["domains"], sort_keys=True).encode())
+    h.update(json.dumps([{k: v for k, v in d.items() if k != "vertices"} for d in wl["domains"]],
+                        sort_keys=True).encode())
+    for d in wl["domains"]:
+        if d.get("vertices") is not None:
+            h.update(np.ascontiguousarray(d["vertices"], dtype=np.float64).tobytes())
     h.update(json.dumps([wl.get("cfl"), wl.get("alpha")]).encode())
     for k in ("centers", "radius", "omega", "zeta", "eta", "scale"):
         h.update(np.ascontiguousarray(wl["pmuts"][k], dtype=np.float64).tobytes())

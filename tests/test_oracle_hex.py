@@ -1,0 +1,289 @@
+"""Pins of the oracle's trilinear hexahedra (Sec. 3: every element is the
+image of the reference cube under a trilinear map X_K with positive
+Jacobian; the spaces are Q_N on the reference cube composed with X_K^{-1})
+and of its face matching (Sec. 5, Algorithm 3).
+
+- Vertices of an axis-aligned brick reproduce the brick solver: mass, node
+  coordinates, K p and traces.
+- The mass sums to the volume of the domain: meshes that warp a brick keep
+  its boundary planes, so that volume is the brick's, and GLL quadrature of
+  order N >= 2 integrates a trilinear map's Jacobian exactly.
+- Patch test: for a field linear in x, K p vanishes at every interior node
+  of any trilinear mesh once N >= 3 (the integrand cof(J) grad_xi l is then a
+  polynomial GLL integrates exactly, and the discrete divergence theorem
+  holds); K 1 = 0.
+- Rigid motions of the mesh leave K and the mass unchanged.
+- The first nonzero Neumann eigenvalues of a warped unit cube converge to
+  (pi c)^2 under p-refinement.
+- The nodal interpolant of a linear field is exact at receivers anywhere in
+  a jittered mesh (the inverse map finds the right element and point).
+- The bottom face weights sum to the face's area.
+- A standing wave on a warped cube follows cos(pi c t).
+- Algorithm 3 reproduces the brick oracle's interface list; on warped
+  interface meshes every fine point is matched to the lowest-index coarse
+  element containing it (checked by a point-in-quadrilateral test) and the
+  coarse map at the returned reference point gives the point back; coarse
+  faces whose normal is not opposite are skipped.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import ref as R
+from paper_2603_06267_amd import workloads as W
+
+
+def _solver(dom, V=None, cfl=0.3):
+    s = R.RefSolver([dom], cfl=cfl)
+    if V is not None:
+        s.set_vertices(0, V)
+    return s
+
+
+def _interior_mask(dom, coords):
+    x0 = np.asarray(dom["x0"]); x1 = np.asarray(dom["x1"])
+    tol = 1e-9 * np.max(x1 - x0)
+    return np.all((coords > x0 + tol) & (coords < x1 - tol), axis=1)
+
+
+def test_affine_vertices_reproduce_the_brick():
+    dom = W.brick([0.2, -0.1, 0.5], [1.7, 0.9, 2.5], [3, 2, 4], 3)
+    a = _solver(dom)
+    b = _solver(dom, W.brick_vertices(dom))
+    assert abs(a.dt - b.dt) <= 1e-14 * a.dt
+    assert np.abs(a.coords() - b.coords()).max() < 1e-13
+    assert np.abs(a.mass() - b.mass()).max() < 1e-13 * a.mass().max()
+    p = np.random.default_rng(5).standard_normal(a.n)
+    ka, kb = a.apply_K(p, 1), b.apply_K(p, 1)
+    assert np.abs(ka - kb).max() < 1e-11 * np.abs(ka).max()
+    # the coupled time loop of config 1 with its brick given as vertices
+    wl = W.config1()
+    wv = dict(wl, domains=[dict(wl["domains"][0], vertices=W.brick_vertices(wl["domains"][0]))])
+    ta = R.from_workload(wl, shape_fn=W.shape_fn(wl)).step(120)
+    tb = R.from_workload(wv, shape_fn=W.shape_fn(wv)).step(120)
+    assert np.linalg.norm(ta - tb) <= 1e-11 * np.linalg.norm(ta)
+
+
+@pytest.mark.parametrize("N", [2, 3, 5])
+def test_mass_is_the_volume(N):
+    dom = W.brick([0, 0, 0], [2.0, 1.0, 1.5], [3, 3, 2], N)
+    s = _solver(dom, W.warped_vertices(dom, amp=0.2, jitter=0.2, seed=1))
+    assert abs(s.mass().sum() - 3.0) < 1e-13 * 3.0
+    # the mapped mesh differs from the brick: masses are not the brick's
+    b = _solver(dom)
+    assert np.abs(s.mass() - b.mass()).max() > 1e-3 * b.mass().max()
+
+
+@pytest.mark.parametrize("N", [3, 4, 6])
+def test_patch_linear_fields(N):
+    dom = W.brick([0, 0, 0], [1.0, 1.2, 0.8], [3, 2, 3], N)
+    s = _solver(dom, W.warped_vertices(dom, amp=0.25, jitter=0.25, seed=2))
+    x = s.coords()
+    inner = _interior_mask(dom, x)
+    assert inner.sum() > 10
+    for a in ([1.0, 0, 0], [0, 1.0, 0], [0.3, -0.7, 1.1]):
+        p = x @ np.asarray(a) + 0.4
+        kp = s.apply_K(p, 1)
+        scale = np.abs(s.apply_K(np.random.default_rng(1).standard_normal(s.n), 1)).max()
+        assert np.abs(kp[inner]).max() < 1e-11 * scale
+        assert np.abs(kp).max() > 1e-6 * scale   # boundary rows carry the flux
+    assert np.abs(s.apply_K(np.ones(s.n), 1)).max() < 1e-11 * scale
+
+
+def test_rigid_motion_leaves_K_unchanged():
+    dom = W.brick([0, 0, 0], [1.0, 1.0, 1.0], [2, 3, 2], 4)
+    V = W.warped_vertices(dom, amp=0.2, jitter=0.2, seed=3)
+    q, _ = np.linalg.qr(np.random.default_rng(7).standard_normal((3, 3)))
+    if np.linalg.det(q) < 0:
+        q[:, 0] *= -1
+    Vr = V @ q.T + np.array([3.0, -2.0, 0.5])
+    a, b = _solver(dom, V), _solver(dom, Vr)
+    assert np.abs(a.coords() @ q.T + np.array([3.0, -2.0, 0.5]) - b.coords()).max() < 1e-12
+    assert np.abs(a.mass() - b.mass()).max() < 1e-13 * a.mass().max()
+    p = np.random.default_rng(8).standard_normal(a.n)
+    ka, kb = a.apply_K(p, 1), b.apply_K(p, 1)
+    assert np.abs(ka - kb).max() < 1e-11 * np.abs(ka).max()
+
+
+def test_neumann_eigenvalues_converge_on_a_warped_cube():
+    """Unit cube, c = 1.5, meshed by 2^3 smoothly warped trilinear
+    hexahedra: the three smallest nonzero eigenvalues of M^{-1} K tend to
+    (pi c)^2 as N grows."""
+    import scipy.linalg as sl
+    c = 1.5
+    exact = (math.pi * c) ** 2
+    errs = []
+    for N in (2, 3, 4, 5, 6):
+        dom = W.brick([0, 0, 0], [1, 1, 1], [2, 2, 2], N, c=c)
+        s = _solver(dom, W.warped_vertices(dom, amp=0.3, seed=4))
+        K = s.dense_K(1)
+        m = s.mass()
+        dm = 1.0 / np.sqrt(m)
+        ev = sl.eigh(K * dm[:, None] * dm[None, :], eigvals_only=True, subset_by_index=[0, 3])
+        assert abs(ev[0]) < 1e-9 * exact
+        errs.append(np.abs(ev[1:4] - exact).max() / exact)
+    errs = np.array(errs)
+    assert (np.diff(errs) < 0).all(), errs
+    assert errs[-1] < 1e-6 and errs[0] > 1e3 * errs[-1], errs
+
+
+def test_receivers_interpolate_linear_fields_exactly():
+    dom = W.brick([0, 0, 0], [1.0, 1.0, 1.0], [3, 3, 3], 3)
+    s = _solver(dom, W.warped_vertices(dom, amp=0.2, jitter=0.3, seed=5))
+    rng = np.random.default_rng(9)
+    pts = rng.uniform(0.02, 0.98, size=(40, 3))
+    # points on the warped boundary plane and on element vertices too
+    V = W.warped_vertices(dom, amp=0.2, jitter=0.3, seed=5)
+    pts = np.vstack([pts, V[[0, 13, 21, 37, 63]], [[0.5, 0.5, 0.0], [1.0, 0.3, 0.7]]])
+    s.set_receivers(pts)
+    a = np.array([0.7, -1.3, 2.1])
+    p = s.coords() @ a - 0.25
+    got = s.sample(p)
+    assert np.abs(got - (pts @ a - 0.25)).max() < 1e-12
+
+
+def test_bottom_face_weights_sum_to_its_area():
+    dom = W.brick([0, 0, 0], [2.0, 1.0, 1.0], [8, 4, 2], 4)
+    V = W.disc_conforming_vertices(dom, W._grid_centres(2, 1, 1.0, 0.5), 0.3, 1.0)
+    s = _solver(dom, V)
+    # one "PMUT" covering the whole face, unit shape
+    s.set_pmuts(np.array([[1.0, 0.5]]), np.array([5.0]), np.array([[1.0]]), np.array([[0.0]]),
+                np.array([[1.0]]))
+    n = s.pmut_nodes(0).shape[0]
+    s.set_shape(0, np.ones((1, n)))
+    node, val = s.coupling(0, 0)
+    assert abs(val.sum() - 2.0) < 1e-13
+    # the conforming map puts element edges on the circle: the ring of
+    # vertices around each centre is at the disc radius
+    xyz = s.coords()
+    bottom = xyz[np.abs(xyz[:, 2]) < 1e-12]
+    r = np.hypot(bottom[:, 0] - 0.5, bottom[:, 1] - 0.5)
+    assert np.sum(np.abs(r - 0.3) < 1e-6) >= 8
+
+
+def test_standing_wave_on_a_warped_cube():
+    c = 1.5
+    dom = W.brick([0, 0, 0], [1, 1, 1], [3, 3, 3], 5, c=c)
+    s = _solver(dom, W.warped_vertices(dom, amp=0.2, seed=6), cfl=0.2)
+    x = s.coords()
+    p0 = np.cos(math.pi * x[:, 0])
+    s.set_state(p=p0, pd=np.zeros_like(p0), pdd=-s.apply_K(p0) / s.mass())
+    n = int(round(0.5 / s.dt))
+    s.step(n)
+    t = n * s.dt
+    err = np.abs(s.get_state()["p"] - p0 * math.cos(math.pi * c * t)).max()
+    assert err < 2e-4, err
+
+
+# ---------------------------------------------------------------- Algorithm 3
+
+def _layer_hexes(V, ne, ez):
+    """Hexahedra [n, 8, 3] (corner order) of element layer ez, ordered
+    ex + ne0 ey."""
+    nx, ny = ne[0] + 1, ne[1] + 1
+    out = []
+    for ey in range(ne[1]):
+        for ex in range(ne[0]):
+            cs = []
+            for c in range(8):
+                i, j, k = ex + (c & 1), ey + ((c >> 1) & 1), ez + ((c >> 2) & 1)
+                cs.append(V[i + nx * (j + ny * k)])
+            out.append(cs)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("nested", [True, False])
+def test_matching_reproduces_the_brick_interface(nested):
+    wl = W.small_two_domain(nested=nested)
+    prim, sec = wl["domains"]
+    s = R.RefSolver([prim, sec])
+    ce, xi = s.interface_points()
+    nq = max(prim["N"], sec["N"]) + 1
+    fine = _layer_hexes(W.brick_vertices(prim), prim["ne"], prim["ne"][2] - 1)
+    coarse = _layer_hexes(W.brick_vertices(sec), sec["ne"], 0)
+    elem, rx, un = R.match_faces(nq, fine, np.full(len(fine), 5), coarse, np.full(len(coarse), 4))
+    assert un == 0
+    assert np.array_equal(elem, ce[:, 0] + sec["ne"][0] * ce[:, 1])
+    assert np.abs(rx[:, :2] - xi).max() < 1e-12
+    assert np.abs(rx[:, 2] + 1).max() < 1e-12
+
+
+def _point_in_quad(p, q):
+    """p inside or on the convex quadrilateral q [4, 2] (counter-clockwise)."""
+    for i in range(4):
+        a, b = q[i], q[(i + 1) % 4]
+        if (b[0] - a[0]) * (p[1] - a[1]) - (b[1] - a[1]) * (p[0] - a[0]) < -1e-12:
+            return False
+    return True
+
+
+def _warp_interface(dom, seed, amp=0.25):
+    """Brick vertices with a seeded in-plane jitter of every vertex not on
+    the side walls (the bottom and top planes stay planar)."""
+    rng = np.random.default_rng(1000 + seed)
+    V = W.brick_vertices(dom)
+    x0 = np.asarray(dom["x0"]); x1 = np.asarray(dom["x1"])
+    h = (x1 - x0) / np.asarray(dom["ne"])
+    side = np.any(np.abs(V[:, :2] - x0[:2]) < 1e-12, axis=1) | np.any(np.abs(V[:, :2] - x1[:2]) < 1e-12, axis=1)
+    V[~side, 0] += amp * h[0] * rng.uniform(-1, 1, size=(~side).sum())
+    V[~side, 1] += amp * h[1] * rng.uniform(-1, 1, size=(~side).sum())
+    return V
+
+
+def test_matching_on_warped_interfaces():
+    prim = W.brick([0, 0, 0], [3, 3, 1], [8, 8, 2], 3)
+    sec = W.brick([0, 0, 1], [3, 3, 4], [6, 6, 3], 3)
+    Vf, Vc = _warp_interface(prim, 1), _warp_interface(sec, 2)
+    fine = _layer_hexes(Vf, prim["ne"], 1)
+    coarse = _layer_hexes(Vc, sec["ne"], 0)
+    nq = 4
+    elem, xi, un = R.match_faces(nq, fine, np.full(len(fine), 5), coarse, np.full(len(coarse), 4))
+    assert un == 0
+    gq = np.polynomial.legendre.leggauss(nq)[0]
+    for f in range(len(fine)):
+        for j in range(nq):
+            for i in range(nq):
+                q = (f * nq + j) * nq + i
+                # the fine point by the bilinear top face of the fine element
+                ref = np.array([gq[i], gq[j], 1.0])
+                x = _trilinear(fine[f], ref)
+                assert abs(x[2] - 1.0) < 1e-13
+                # lowest-index coarse bottom face containing it
+                want = -1
+                for c in range(len(coarse)):
+                    quad = coarse[c][[0, 1, 3, 2], :2]
+                    if _point_in_quad(x[:2], quad):
+                        want = c
+                        break
+                assert elem[q] == want
+                assert np.abs(_trilinear(coarse[want], xi[q]) - x).max() < 1e-12
+                assert np.abs(xi[q]).max() <= 1 + 1e-10
+
+
+def test_matching_skips_faces_with_the_wrong_normal():
+    """Each coarse element listed twice, first with its top face (normal +z,
+    the same as the fine faces'): the normal filter must skip those.  The
+    coarse elements are flat, so their top faces also pass the radius test
+    and only the normal filter can reject them."""
+    prim = W.brick([0, 0, 0], [2, 2, 1], [4, 4, 1], 2)
+    sec = W.brick([0, 0, 1], [2, 2, 1.3], [3, 3, 1], 2)
+    fine = _layer_hexes(W.brick_vertices(prim), prim["ne"], 0)
+    coarse = _layer_hexes(W.brick_vertices(sec), sec["ne"], 0)
+    both = np.concatenate([coarse, coarse])
+    faces = np.concatenate([np.full(len(coarse), 5), np.full(len(coarse), 4)])
+    elem, xi, un = R.match_faces(3, fine, np.full(len(fine), 5), both, faces)
+    assert un == 0
+    assert (elem >= len(coarse)).all()
+
+
+def _trilinear(V8, xi):
+    """X(xi) of one hexahedron, written from the corner-weight definition."""
+    x = np.zeros(3)
+    for c in range(8):
+        w = 1.0
+        for a in range(3):
+            s = 1.0 if (c >> a) & 1 else -1.0
+            w *= 0.5 * (1 + s * xi[a])
+        x += w * V8[c]
+    return x
