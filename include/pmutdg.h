@@ -154,6 +154,26 @@ pmdg_status pmdg_set_absorbing(pmdg_solver* h, int dom, int faces);
  * a batch; pmdg_set_state starts Phi and psi at rest. */
 pmdg_status pmdg_set_pml(pmdg_solver* h, int dom, const double* ell, double R);
 
+/* Trilinear hexahedra (Sec. 3: each element is the image of the reference
+ * cube under a trilinear map X_K with positive Jacobian).  Gives the
+ * single brick of a one-domain solver its element vertices:
+ * V[(ne0+1)(ne1+1)(ne2+1)][3] (host array, x fastest; element (ex, ey, ez)
+ * is the trilinear image of the reference cube on the eight vertices
+ * (ex + cx, ey + cy, ez + cz)).  The brick's x0 / x1 then only name its
+ * topology; node coordinates, the lumped mass, the stiffness (with the
+ * metric terms, evaluated per element from its corners on the GPU), the
+ * PMUT face weights (with the surface Jacobian of the bottom face) and the
+ * receiver lookup (Newton inverse map, lowest element first) follow the
+ * vertices.  A CFL-chosen time step is chosen again from the shortest
+ * element edge; the stability check uses the element-wise bound
+ * lambda_max(M^{-1} K) <= max_e lambda_max(M_e^{-1} K_e) (PMDG_EUNSTABLE).
+ * Must precede pmdg_set_pmuts, pmdg_set_receivers and pmdg_bind (ESTATE).
+ * EINVAL: two-brick solvers, absorbing faces or layers (neither is built on
+ * trilinear hexahedra), non-finite coordinates, or an element whose
+ * Jacobian determinant is not positive at one of its GLL nodes.  Not
+ * accepted by pmdg_batch_create. */
+pmdg_status pmdg_set_vertices(pmdg_solver* h, int dom, const double* V);
+
 /* Receiver points xyz[3*R]; each is located in the lowest-index element
  * containing it (primary first) and sampled by tensor Lagrange
  * interpolation, accumulated in FP64.  A point outside both bricks gives

@@ -334,9 +334,14 @@ void pmdg_ref_hex_apply(int N, const double *V24, double c, const double *u, dou
 }
 
 /* Newton's method for the reference point xi of x in the element with
- * vertices V8, from xi = 0; returns 0 when it converged (|dxi| < 1e-14),
- * -1 otherwise. */
-static int tri_inverse(const double V8[8][3], const double x[3], double xi[3]) {
+ * vertices V8g, from xi = 0; returns 0 when it converged (|dxi| < 1e-14),
+ * -1 otherwise.  Coordinates are taken relative to the first vertex, so the
+ * residual's rounding is that of the element's size. */
+static int tri_inverse(const double V8g[8][3], const double xg[3], double xi[3]) {
+  double V8[8][3], x[3];
+  for (int c = 0; c < 8; ++c)
+    for (int a = 0; a < 3; ++a) V8[c][a] = V8g[c][a] - V8g[0][a];
+  for (int a = 0; a < 3; ++a) x[a] = xg[a] - V8g[0][a];
   xi[0] = xi[1] = xi[2] = 0.0;
   for (int it = 0; it < 60; ++it) {
     double y[3], J[3][3], Ji[3][3], dx[3], st = 0;

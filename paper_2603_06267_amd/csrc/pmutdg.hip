@@ -159,6 +159,11 @@ struct Brick {
   bool pml = false;
   std::vector<double> pzeta[3];
   std::vector<int> eslot, pel, pnode;
+  // trilinear hexahedra: element vertices [(ne0+1)(ne1+1)(ne2+1)][3] (empty
+  // for an axis-aligned brick), the inverse assembled lumped mass in the
+  // padded device layout, and each element's corner offsets from corner 0
+  std::vector<double> V, hminv, hvert;
+  bool mapped() const { return !V.empty(); }
   double coord(int axis, int i) const {
     const int e = i / N, a = i % N;
     return x0[axis] + h[axis] * (e + 0.5 * ((double)rule.x[a] + 1.0));
@@ -673,6 +678,12 @@ static size_t layout(pmdg_solver* s) {
       add(p + "P2", rb * S * B.pnodes);
       add(p + "X", rb * 2 * S * B.pnodes);
     }
+    if (B.mapped()) {
+      const size_t nel = (size_t)B.ne[0] * B.ne[1] * B.ne[2], n3 = (size_t)(B.N + 1) * (B.N + 1) * (B.N + 1);
+      add(p + "hminv", rb * B.pnodes);
+      add(p + "hvert", rb * nel * 24);
+      add(p + "hy", rb * S * nel * n3);
+    }
     add(p + "taps", rb * 3 * (B.N + 3) * 2 * B.N);
     add(p + "mins", rb * 3 * (B.N + 3));
     add(p + "absg", rb * 3 * (B.N + 3));
@@ -1132,11 +1143,46 @@ static PmlArgs<Real> pml_args(pmdg_solver* s, int d, int prime) {
   return a;
 }
 
+// Kernel arguments of a brick given as trilinear hexahedra.
+template <typename Real>
+static HexArgs<Real> hex_args(pmdg_solver* s, int d) {
+  HexArgs<Real> a;
+  memset(&a, 0, sizeof(a));
+  const Brick& B = s->b[d];
+  const std::string p = "d" + std::to_string(d) + ".";
+  a.d = view<Real>(s, d);
+  a.S = s->S;
+  for (int k = 0; k < 3; ++k) a.ne[k] = B.ne[k];
+  a.nel = B.ne[0] * B.ne[1] * B.ne[2];
+  const int epb = hex_elems_per_block<Real>(B.N);
+  a.eblocks = (int)(((long)s->S * a.nel + epb - 1) / epb);
+  a.dt2 = (Real)(s->dt * s->dt);
+  a.c2 = (Real)(B.c * B.c);
+  a.counter = dptr<long>(s, "ctl");
+  a.force = (d == 0 && s->Np > 0) ? dptr<Real>(s, "force") : nullptr;
+  a.minv = dptr<Real>(s, p + "hminv");
+  a.vert = dptr<Real>(s, p + "hvert");
+  a.y = dptr<Real>(s, p + "hy");
+  const int n1 = B.N + 1;
+  for (int i = 0; i < n1; ++i) {
+    a.w[i] = (Real)B.rule.w[i];
+    a.xg[i] = (Real)B.rule.x[i];
+    for (int j = 0; j < n1; ++j) a.D[i * n1 + j] = (Real)B.rule.D[i * n1 + j];
+  }
+  return a;
+}
+
 template <typename Real>
 static pmdg_status enqueue_step(pmdg_solver* s, hipStream_t st, Timer* tm) {
   if (!tm && s->ndom == 2 && s->overlap && !any_pml(s)) return enqueue_step_split<Real>(s, st, 0);
   const bool incr = s->prec == 32;
   for (int d = 0; d < s->ndom; ++d) {
+    if (s->b[d].mapped()) {
+      TBEGIN(0);
+      HIPCHK(launch_hex<Real>(hex_args<Real>(s, d), incr, st));
+      TEND();
+      continue;
+    }
     StiffArgs<Real> a = stiff_args<Real>(s, d);
     TBEGIN(0);
     HIPCHK(launch_stiff<Real>(a, incr, st));
@@ -1164,7 +1210,8 @@ static void completion_ranges(const pmdg_solver* s, int d, int r[4]) {
 
 // brick d advances two steps per stiffness pass
 static bool two_step(const pmdg_solver* s, int d) {
-  if (s->prec != 32 || s->b[d].absorbing || s->b[0].pml || (s->ndom > 1 && s->b[1].pml)) return false;
+  if (s->prec != 32 || s->b[d].absorbing || s->b[0].pml || (s->ndom > 1 && s->b[1].pml) || s->b[d].mapped())
+    return false;
   const int tb = (d == 1 && s->tblock1 > 0) ? s->tblock1 : s->tblock;
   return tb == 2 && stiff2_tile_rows(s->b[d].N) > 0;
 }
@@ -1287,6 +1334,10 @@ static pmdg_status bind_tables(pmdg_solver* s, hipStream_t st) {
     for (int ax = 0; ax < 3; ++ax) {
       if (B.absorbing & (1 << (2 * ax))) absg[(size_t)ax * NC + B.N] = s->dt * B.c * B.cmin[ax][B.N];
       if (B.absorbing & (1 << (2 * ax + 1))) absg[(size_t)ax * NC + B.N + 1] = s->dt * B.c * B.cmin[ax][B.N + 1];
+    }
+    if (B.mapped()) {
+      if ((r = upload_real<Real>(s, p + "hminv", B.hminv, st))) return r;
+      if ((r = upload_real<Real>(s, p + "hvert", B.hvert, st))) return r;
     }
     if ((r = upload_real<Real>(s, p + "taps", taps, st))) return r;
     if ((r = upload_real<Real>(s, p + "mins", mins, st))) return r;
@@ -1413,6 +1464,225 @@ static pmdg_status set_state_t(pmdg_solver* s, int sc, const double* p, const do
 // ABI
 // ------------------------------------------------------------------------
 // ------------------------------------------------------------------------
+// ------------------------------------------------------------------------
+// Trilinear hexahedra (host setup)
+// ------------------------------------------------------------------------
+// Corner c = cx + 2 cy + 4 cz of the reference cube [-1, 1]^3; the map is
+// x(xi) = sum_c prod_a (1 + s_a xi_a) / 2 V_c with s_a = +-1 by the bits of c.
+static void hex_corners(const Brick& B, int ex, int ey, int ez, double V8[8][3]) {
+  const long nx = B.ne[0] + 1, ny = B.ne[1] + 1;
+  for (int c = 0; c < 8; ++c) {
+    const long v = (ex + (c & 1)) + nx * ((ey + ((c >> 1) & 1)) + ny * (long)(ez + ((c >> 2) & 1)));
+    for (int a = 0; a < 3; ++a) V8[c][a] = B.V[3 * v + a];
+  }
+}
+
+static void hex_map(const double V8[8][3], const double xi[3], double x[3], double J[3][3]) {
+  for (int r = 0; r < 3; ++r) {
+    x[r] = 0;
+    J[r][0] = J[r][1] = J[r][2] = 0;
+  }
+  for (int c = 0; c < 8; ++c) {
+    double f[3], sg[3];
+    for (int a = 0; a < 3; ++a) {
+      sg[a] = ((c >> a) & 1) ? 1.0 : -1.0;
+      f[a] = 0.5 * (1 + sg[a] * xi[a]);
+    }
+    const double d[3] = {0.5 * sg[0] * f[1] * f[2], 0.5 * sg[1] * f[0] * f[2], 0.5 * sg[2] * f[0] * f[1]};
+    for (int r = 0; r < 3; ++r) {
+      x[r] += f[0] * f[1] * f[2] * V8[c][r];
+      for (int k = 0; k < 3; ++k) J[r][k] += d[k] * V8[c][r];
+    }
+  }
+}
+
+// adj(J) (= det J times J^{-1}); returns det J
+static double hex_adj(const double J[3][3], double A[3][3]) {
+  A[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+  A[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+  A[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+  A[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+  A[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+  A[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+  A[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+  A[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+  A[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  return J[0][0] * A[0][0] + J[0][1] * A[1][0] + J[0][2] * A[2][0];
+}
+
+// Coordinates of node (i, j, k): the lowest element holding it, at its GLL point.
+static void hex_node_xyz(const Brick& B, int i, int j, int k, double x[3]) {
+  const int g[3] = {i, j, k};
+  int e[3];
+  double xi[3], J[3][3], V8[8][3];
+  for (int a = 0; a < 3; ++a) {
+    e[a] = std::min(g[a] / B.N, B.ne[a] - 1);
+    xi[a] = (double)B.rule.x[g[a] - B.N * e[a]];
+  }
+  hex_corners(B, e[0], e[1], e[2], V8);
+  hex_map(V8, xi, x, J);
+}
+
+// Newton's method for the reference point of x in the element with corners
+// V8, from the centre; false if it does not converge.  It works in
+// coordinates relative to corner 0, so its residual carries rounding of
+// the element's size, not of the distance from the origin.
+static bool hex_inverse(const double V8g[8][3], const double xg[3], double xi[3]) {
+  double V8[8][3], x[3];
+  for (int c = 0; c < 8; ++c)
+    for (int a = 0; a < 3; ++a) V8[c][a] = V8g[c][a] - V8g[0][a];
+  for (int a = 0; a < 3; ++a) x[a] = xg[a] - V8g[0][a];
+  xi[0] = xi[1] = xi[2] = 0;
+  for (int it = 0; it < 60; ++it) {
+    double y[3], J[3][3], A[3][3];
+    hex_map(V8, xi, y, J);
+    const double det = hex_adj(J, A);
+    if (!(std::fabs(det) > 0)) return false;
+    const double r[3] = {x[0] - y[0], x[1] - y[1], x[2] - y[2]};
+    double step = 0;
+    for (int a = 0; a < 3; ++a) {
+      const double dxi = (A[a][0] * r[0] + A[a][1] * r[1] + A[a][2] * r[2]) / det;
+      xi[a] += dxi;
+      step += std::fabs(dxi);
+    }
+    if (!(std::fabs(xi[0]) < 10 && std::fabs(xi[1]) < 10 && std::fabs(xi[2]) < 10)) return false;
+    if (step < 1e-14) return true;
+  }
+  return false;
+}
+
+// K_e u on one element with corners V8 (without c^2): GLL collocation of
+// grad u . grad v |J| on the reference cube, by sum factorisation.
+static void hex_apply_host(const Rule1D& R, const double V8[8][3], const double* u, double* r) {
+  const int N = R.N, n1 = N + 1, n3 = n1 * n1 * n1;
+  std::vector<double> F(3 * (size_t)n3);
+  for (int i = 0; i < n3; ++i) {
+    const int a = i % n1, b = (i / n1) % n1, c = i / (n1 * n1);
+    double g[3] = {0, 0, 0};
+    for (int m = 0; m < n1; ++m) {
+      g[0] += (double)R.D[a * n1 + m] * u[m + n1 * (b + n1 * c)];
+      g[1] += (double)R.D[b * n1 + m] * u[a + n1 * (m + n1 * c)];
+      g[2] += (double)R.D[c * n1 + m] * u[a + n1 * (b + n1 * m)];
+    }
+    const double xi[3] = {(double)R.x[a], (double)R.x[b], (double)R.x[c]};
+    double x[3], J[3][3], A[3][3];
+    hex_map(V8, xi, x, J);
+    const double det = hex_adj(J, A);
+    double h[3];
+    for (int k = 0; k < 3; ++k) h[k] = A[0][k] * g[0] + A[1][k] * g[1] + A[2][k] * g[2];
+    const double sc = (double)(R.w[a] * R.w[b] * R.w[c]) / det;
+    for (int k = 0; k < 3; ++k) F[k * (size_t)n3 + i] = sc * (A[k][0] * h[0] + A[k][1] * h[1] + A[k][2] * h[2]);
+  }
+  for (int i = 0; i < n3; ++i) {
+    const int a = i % n1, b = (i / n1) % n1, c = i / (n1 * n1);
+    double v = 0;
+    for (int m = 0; m < n1; ++m) {
+      v += (double)R.D[m * n1 + a] * F[m + n1 * (b + n1 * c)];
+      v += (double)R.D[m * n1 + b] * F[n3 + a + n1 * (m + n1 * c)];
+      v += (double)R.D[m * n1 + c] * F[2 * (size_t)n3 + a + n1 * (b + n1 * m)];
+    }
+    r[i] = v;
+  }
+}
+
+// Largest eigenvalue of Mt^{-1} K_e for one element, Mt the diagonal of
+// element-node masses mt: Lanczos with full reorthogonalisation on the
+// symmetric form Mt^{-1/2} K_e Mt^{-1/2}.
+static double hex_elem_lambda(const Rule1D& R, const double V8[8][3], const double* mt) {
+  const int N = R.N, n1 = N + 1, n3 = n1 * n1 * n1;
+  std::vector<double> ms(n3);
+  for (int i = 0; i < n3; ++i) ms[i] = 1.0 / std::sqrt(mt[i]);
+  const int m = std::min(n3, 40);
+  std::vector<std::vector<double>> Q;
+  std::vector<double> al, be, q(n3), w(n3), t(n3), y(n3);
+  unsigned long long st = 0x9e3779b97f4a7c15ULL;
+  double nr = 0;
+  for (int i = 0; i < n3; ++i) {
+    st = st * 6364136223846793005ULL + 1442695040888963407ULL;
+    q[i] = (double)(st >> 11) / 9007199254740992.0 - 0.5;
+    nr += q[i] * q[i];
+  }
+  for (int i = 0; i < n3; ++i) q[i] /= std::sqrt(nr);
+  for (int k = 0; k < m; ++k) {
+    Q.push_back(q);
+    for (int i = 0; i < n3; ++i) t[i] = ms[i] * q[i];
+    hex_apply_host(R, V8, t.data(), y.data());
+    for (int i = 0; i < n3; ++i) w[i] = ms[i] * y[i];
+    double a = 0;
+    for (int i = 0; i < n3; ++i) a += w[i] * q[i];
+    al.push_back(a);
+    for (const auto& v : Q) {
+      double d = 0;
+      for (int i = 0; i < n3; ++i) d += w[i] * v[i];
+      for (int i = 0; i < n3; ++i) w[i] -= d * v[i];
+    }
+    double b = 0;
+    for (int i = 0; i < n3; ++i) b += w[i] * w[i];
+    b = std::sqrt(b);
+    if (k + 1 == m || b < 1e-12 * std::fabs(a)) break;
+    be.push_back(b);
+    for (int i = 0; i < n3; ++i) q[i] = w[i] / b;
+  }
+  return tridiag_max_eig(al, be);
+}
+
+// Largest eigenvalue of M^{-1} K on a whole trilinear brick (mass: the
+// assembled lumped mass, compact layout): Lanczos in the M inner product
+// with full reorthogonalisation, as for the coupled operator.
+static double hex_mesh_lambda(const Brick& B, const std::vector<double>& mass) {
+  const int N = B.N, n1 = N + 1, n3 = n1 * n1 * n1;
+  const long n = B.nnodes;
+  auto idx = [&](int ex, int ey, int ez, int i) {
+    return (N * ex + i % n1) + (long)B.nn[0] * ((N * ey + (i / n1) % n1) + (long)B.nn[1] * (N * ez + i / (n1 * n1)));
+  };
+  auto apply = [&](const std::vector<double>& u, std::vector<double>& w) {
+    std::fill(w.begin(), w.end(), 0.0);
+    std::vector<double> ue(n3), re(n3);
+    for (int ez = 0; ez < B.ne[2]; ++ez)
+      for (int ey = 0; ey < B.ne[1]; ++ey)
+        for (int ex = 0; ex < B.ne[0]; ++ex) {
+          double V8[8][3];
+          hex_corners(B, ex, ey, ez, V8);
+          for (int i = 0; i < n3; ++i) ue[i] = u[idx(ex, ey, ez, i)];
+          hex_apply_host(B.rule, V8, ue.data(), re.data());
+          for (int i = 0; i < n3; ++i) w[idx(ex, ey, ez, i)] += re[i];
+        }
+    for (long i = 0; i < n; ++i) w[i] *= B.c * B.c / mass[i];
+  };
+  auto dotm = [&](const std::vector<double>& a, const std::vector<double>& b) {
+    double acc = 0;
+    for (long i = 0; i < n; ++i) acc += mass[i] * a[i] * b[i];
+    return acc;
+  };
+  const int m = (int)std::min<long>(60, n);
+  std::vector<std::vector<double>> Q;
+  std::vector<double> al, be, w(n), q(n);
+  uint64_t st = 0x9E3779B97F4A7C15ull;
+  for (long i = 0; i < n; ++i) {
+    st = st * 6364136223846793005ull + 1442695040888963407ull;
+    q[i] = (double)(st >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+  }
+  const double nq = std::sqrt(dotm(q, q));
+  for (long i = 0; i < n; ++i) q[i] /= nq;
+  Q.push_back(q);
+  for (int j = 0; j < m; ++j) {
+    apply(Q[j], w);
+    al.push_back(dotm(w, Q[j]));
+    for (int pass = 0; pass < 2; ++pass)
+      for (const auto& qi : Q) {
+        const double h = dotm(w, qi);
+        for (long i = 0; i < n; ++i) w[i] -= h * qi[i];
+      }
+    const double b = std::sqrt(dotm(w, w));
+    if (j + 1 == m || !(b > 1e-12 * std::fabs(al.back()))) break;
+    be.push_back(b);
+    for (long i = 0; i < n; ++i) w[i] /= b;
+    Q.push_back(w);
+  }
+  be.resize(al.size() > 0 ? al.size() - 1 : 0);
+  return tridiag_max_eig(al, be);
+}
+
 // Library-held workspace (pmdg_bind_static): one static device array per
 // GPU, for callers that cannot allocate device memory.  Host code never
 // passes the array's name to a kernel or a copy: the device address is
@@ -1532,18 +1802,51 @@ pmdg_status pmdg_set_pmuts(pmdg_solver* s, int Np, const double* ctr, const doub
   s->pm_off.assign(Np + 1, 0);
   s->pm_node.clear();
   s->pm_wf.clear();
+  // trilinear hexahedra: bottom-face node coordinates and the assembled face
+  // weights w_a w_b |dX/dxi x dX/deta| of the face zeta = -1
+  std::vector<double> hx, hy, hw;
+  if (B.mapped()) {
+    const long nf = face0(s);
+    hx.assign(nf, 0.0);
+    hy.assign(nf, 0.0);
+    hw.assign(nf, 0.0);
+    for (int j = 0; j < B.nn[1]; ++j)
+      for (int i = 0; i < B.nn[0]; ++i) {
+        double x[3];
+        hex_node_xyz(B, i, j, 0, x);
+        hx[i + (long)B.nn[0] * j] = x[0];
+        hy[i + (long)B.nn[0] * j] = x[1];
+      }
+    for (int ey = 0; ey < B.ne[1]; ++ey)
+      for (int ex = 0; ex < B.ne[0]; ++ex) {
+        double V8[8][3];
+        hex_corners(B, ex, ey, 0, V8);
+        for (int b = 0; b <= B.N; ++b)
+          for (int a = 0; a <= B.N; ++a) {
+            const double xi[3] = {(double)B.rule.x[a], (double)B.rule.x[b], -1.0};
+            double x[3], J[3][3];
+            hex_map(V8, xi, x, J);
+            const double n0 = J[1][0] * J[2][1] - J[2][0] * J[1][1], n1 = J[2][0] * J[0][1] - J[0][0] * J[2][1],
+                         n2 = J[0][0] * J[1][1] - J[1][0] * J[0][1];
+            hw[(B.N * ex + a) + (long)B.nn[0] * (B.N * ey + b)] +=
+                (double)(B.rule.w[a] * B.rule.w[b]) * std::sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+          }
+      }
+  }
   for (int k = 0; k < Np; ++k) {
     s->pm_off[k] = (int)s->pm_node.size();
     for (int j = 0; j < B.nn[1]; ++j)
       for (int i = 0; i < B.nn[0]; ++i) {
-        const double dx = B.coord(0, i) - ctr[2 * k], dy = B.coord(1, j) - ctr[2 * k + 1];
+        const long f = i + (long)B.nn[0] * j;
+        const double xn = B.mapped() ? hx[f] : B.coord(0, i), yn = B.mapped() ? hy[f] : B.coord(1, j);
+        const double dx = xn - ctr[2 * k], dy = yn - ctr[2 * k + 1];
         if (std::sqrt(dx * dx + dy * dy) <= radius[k]) {
-          const long f = i + (long)B.nn[0] * j;
           if (owner[f] >= 0) return fail(PMDG_EINVAL, "PMUT discs overlap");
           owner[f] = k;
           s->pm_node.push_back(i + B.px * j);  // device (padded) face index
-          // face quadrature weight: product of the assembled 1D lumped masses
-          s->pm_wf.push_back(B.mass1[0][i] * B.mass1[1][j]);
+          // face quadrature weight: on bricks the product of the assembled
+          // 1D lumped masses
+          s->pm_wf.push_back(B.mapped() ? hw[f] : B.mass1[0][i] * B.mass1[1][j]);
         }
       }
   }
@@ -1564,6 +1867,10 @@ pmdg_status pmdg_pmut_face_nodes(pmdg_solver* s, int k, int* n, double* xyz) {
     const Brick& B = s->b[0];
     for (int m = 0; m < cnt; ++m) {
       const int f = s->pm_node[o + m];
+      if (B.mapped()) {
+        hex_node_xyz(B, f % B.px, f / B.px, 0, xyz + 3 * m);
+        continue;
+      }
       xyz[3 * m] = B.coord(0, f % B.px);
       xyz[3 * m + 1] = B.coord(1, f / B.px);
       xyz[3 * m + 2] = B.x0[2];
@@ -1636,6 +1943,7 @@ pmdg_status pmdg_set_absorbing(pmdg_solver* s, int dom, int faces) {
   if (s->bound) return fail(PMDG_ESTATE, "set_absorbing must precede bind");
   if (dom < 0 || dom >= s->ndom) return fail(PMDG_EINVAL, "no such domain");
   if (faces < 0 || faces > 63) return fail(PMDG_EINVAL, "faces is a mask of 6 bits");
+  if (faces && s->b[dom].mapped()) return fail(PMDG_EINVAL, "absorbing faces are not built on trilinear hexahedra");
   if (s->ndom > 1 && (faces & (dom == 0 ? 32 : 16)))
     return fail(PMDG_EINVAL, "the interface face of a coupled brick cannot be absorbing");
   s->b[dom].absorbing = faces;
@@ -1648,6 +1956,7 @@ pmdg_status pmdg_set_pml(pmdg_solver* s, int dom, const double* ell, double R) {
   if (dom < 0 || dom >= s->ndom) return fail(PMDG_EINVAL, "domain out of range");
   if (!(R > 0 && R < 1)) return fail(PMDG_EINVAL, "the reflection coefficient R must be in (0, 1)");
   Brick& B = s->b[dom];
+  if (B.mapped()) return fail(PMDG_EINVAL, "layers are not built on trilinear hexahedra");
   for (int a = 0; a < 3; ++a) {
     const double L = B.h[a] * B.ne[a];
     if (!(ell[2 * a] >= 0) || !(ell[2 * a + 1] >= 0) || ell[2 * a] + ell[2 * a + 1] > L * (1 + 1e-12))
@@ -1700,6 +2009,131 @@ pmdg_status pmdg_set_pml(pmdg_solver* s, int dom, const double* ell, double R) {
   return PMDG_OK;
 }
 
+pmdg_status pmdg_set_vertices(pmdg_solver* s, int dom, const double* V) {
+  if (!s || !V) return fail(PMDG_EINVAL, "NULL argument");
+  if (s->bound) return fail(PMDG_ESTATE, "set_vertices must precede bind");
+  if (s->ndom != 1 || dom != 0) return fail(PMDG_EINVAL, "trilinear hexahedra are built for single-brick solvers");
+  Brick& B = s->b[0];
+  if (B.absorbing || B.pml)
+    return fail(PMDG_EINVAL, "absorbing faces and layers are not built on trilinear hexahedra");
+  if (s->Np > 0 || s->R > 0) return fail(PMDG_ESTATE, "set_vertices must precede set_pmuts and set_receivers");
+  const long nv = (long)(B.ne[0] + 1) * (B.ne[1] + 1) * (B.ne[2] + 1);
+  for (long i = 0; i < 3 * nv; ++i)
+    if (!std::isfinite(V[i])) return fail(PMDG_EINVAL, "vertex coordinates must be finite");
+  std::vector<double> old;
+  old.swap(B.V);
+  B.V.assign(V, V + 3 * nv);
+  const int N = B.N, n1 = N + 1;
+  const long nel = (long)B.ne[0] * B.ne[1] * B.ne[2];
+  std::vector<double> mass(B.nnodes, 0.0), hvert((size_t)nel * 24, 0.0);
+  double hm = INFINITY, lam = 0;
+  for (int ez = 0; ez < B.ne[2]; ++ez)
+    for (int ey = 0; ey < B.ne[1]; ++ey)
+      for (int ex = 0; ex < B.ne[0]; ++ex) {
+        const long e = ex + (long)B.ne[0] * (ey + (long)B.ne[1] * ez);
+        double V8[8][3];
+        hex_corners(B, ex, ey, ez, V8);
+        for (int c = 0; c < 8; ++c)
+          for (int a = 0; a < 3; ++a) hvert[e * 24 + 3 * c + a] = V8[c][a] - V8[0][a];
+        for (int c = 0; c < 8; ++c)
+          for (int a = 0; a < 3; ++a) {
+            if ((c >> a) & 1) continue;
+            const int c2 = c | (1 << a);
+            const double d0 = V8[c2][0] - V8[c][0], d1 = V8[c2][1] - V8[c][1], d2 = V8[c2][2] - V8[c][2];
+            hm = std::min(hm, std::sqrt(d0 * d0 + d1 * d1 + d2 * d2));
+          }
+        for (int c = 0; c <= N; ++c)
+          for (int b = 0; b <= N; ++b)
+            for (int a = 0; a <= N; ++a) {
+              const double xi[3] = {(double)B.rule.x[a], (double)B.rule.x[b], (double)B.rule.x[c]};
+              double x[3], J[3][3], A[3][3];
+              hex_map(V8, xi, x, J);
+              const double det = hex_adj(J, A);
+              if (!(det > 0)) {
+                B.V.swap(old);
+                return fail(PMDG_EINVAL, "the Jacobian of element " + std::to_string(e) + " is not positive");
+              }
+              mass[(N * ex + a) + (long)B.nn[0] * ((N * ey + b) + (long)B.nn[1] * (N * ez + c))] +=
+                  (double)(B.rule.w[a] * B.rule.w[b] * B.rule.w[c]) * det;
+            }
+      }
+  // Stability.  Meshes of up to kHexLanczosNodes nodes: Lanczos on the
+  // whole operator, with a 2% margin for its estimate from below.  Larger
+  // ones: with Mt_e the assembled lumped mass of each node divided by the
+  // number of elements holding it, p.M p = sum_e p_e.Mt_e p_e and
+  // p.K p = sum_e p_e.K_e p_e, so lambda_max(M^{-1} K) <= max_e
+  // lambda_max(Mt_e^{-1} K_e), an upper bound needing no margin.  The
+  // element value depends on the element's shape and Mt_e up to translation
+  // and scale (lambda ~ 1 / L^2): it is cached by the normalised corner
+  // offsets and masses.
+  constexpr long kHexLanczosNodes = 150000;
+  double margin = 1.0;
+  if (B.nnodes <= kHexLanczosNodes) {
+    lam = hex_mesh_lambda(B, mass);
+    margin = 1.02;
+  } else {
+    const int n3 = n1 * n1 * n1;
+    std::map<std::vector<long long>, double> cache;
+    std::vector<double> mt(n3);
+    std::vector<long long> key(21 + n3);
+    for (int ez = 0; ez < B.ne[2]; ++ez)
+      for (int ey = 0; ey < B.ne[1]; ++ey)
+        for (int ex = 0; ex < B.ne[0]; ++ex) {
+          double V8[8][3], W8[8][3], L = 0;
+          hex_corners(B, ex, ey, ez, V8);
+          for (int c = 1; c < 8; ++c)
+            for (int a = 0; a < 3; ++a) L = std::max(L, std::fabs(V8[c][a] - V8[0][a]));
+          for (int c = 0; c < 8; ++c)
+            for (int a = 0; a < 3; ++a) {
+              W8[c][a] = (V8[c][a] - V8[0][a]) / L;
+              if (c > 0) key[3 * (c - 1) + a] = std::llround(W8[c][a] * 1e9);
+            }
+          const int g0[3] = {N * ex, N * ey, N * ez};
+          for (int i = 0; i < n3; ++i) {
+            const int l[3] = {i % n1, (i / n1) % n1, i / (n1 * n1)};
+            int mult = 1;
+            for (int a = 0; a < 3; ++a) {
+              const int gi = g0[a] + l[a];
+              if (gi % N == 0 && gi > 0 && gi < N * B.ne[a]) mult *= 2;
+            }
+            mt[i] = mass[(g0[0] + l[0]) + (long)B.nn[0] * ((g0[1] + l[1]) + (long)B.nn[1] * (g0[2] + l[2]))] /
+                    mult / (L * L * L);
+            key[21 + i] = std::llround(mt[i] * 1e9);
+          }
+          auto it = cache.find(key);
+          double ln;
+          if (it != cache.end()) {
+            ln = it->second;
+          } else {
+            ln = hex_elem_lambda(B.rule, W8, mt.data());
+            cache.emplace(key, ln);
+          }
+          lam = std::max(lam, B.c * B.c * ln / (L * L));
+        }
+  }
+  double dt = s->dt;
+  if (!(s->pr.dt > 0)) {
+    double gap = INFINITY;
+    for (int i = 0; i < N; ++i) gap = std::min(gap, (double)(B.rule.x[i + 1] - B.rule.x[i]));
+    dt = s->pr.cfl * hm * gap * 0.5 / B.c;
+  }
+  if (dt * dt * lam * margin >= 4.0) {
+    B.V.swap(old);
+    return fail(PMDG_EUNSTABLE, "dt^2 lambda_max of the trilinear mesh is " + std::to_string(dt * dt * lam) +
+                                    " (>= 4): reduce cfl");
+  }
+  B.hminv.assign((size_t)B.pnodes, 0.0);
+  for (int k = 0; k < B.nn[2]; ++k)
+    for (int j = 0; j < B.nn[1]; ++j)
+      for (int i = 0; i < B.nn[0]; ++i)
+        B.hminv[i + (size_t)B.px * (j + (size_t)B.nn[1] * k)] =
+            1.0 / mass[i + (size_t)B.nn[0] * (j + (size_t)B.nn[1] * k)];
+  B.hvert.swap(hvert);
+  s->dt = dt;
+  s->lam_max = lam;
+  return PMDG_OK;
+}
+
 pmdg_status pmdg_set_receivers(pmdg_solver* s, int R, const double* xyz) {
   if (!s || R < 0 || (R > 0 && !xyz)) return fail(PMDG_EINVAL, "bad receiver arguments");
   if (s->bound) return fail(PMDG_ESTATE, "set_receivers must precede bind");
@@ -1714,7 +2148,24 @@ pmdg_status pmdg_set_receivers(pmdg_solver* s, int R, const double* xyz) {
       int e[3];
       ld xi[3];
       bool in = true;
-      for (int a = 0; a < 3 && in; ++a) {
+      if (B.mapped()) {
+        // lowest element (x fastest) whose inverse map puts the point in
+        // [-1, 1]^3 up to 1e-10
+        in = false;
+        for (int ez = 0; ez < B.ne[2] && !in; ++ez)
+          for (int ey = 0; ey < B.ne[1] && !in; ++ey)
+            for (int ex = 0; ex < B.ne[0] && !in; ++ex) {
+              double V8[8][3], t[3];
+              hex_corners(B, ex, ey, ez, V8);
+              if (!hex_inverse(V8, xyz + 3 * r, t)) continue;
+              if (std::fabs(t[0]) <= 1 + 1e-10 && std::fabs(t[1]) <= 1 + 1e-10 && std::fabs(t[2]) <= 1 + 1e-10) {
+                in = true;
+                e[0] = ex; e[1] = ey; e[2] = ez;
+                for (int a = 0; a < 3; ++a) xi[a] = t[a];
+              }
+            }
+      }
+      for (int a = 0; a < 3 && in && !B.mapped(); ++a) {
         int found = -1;
         for (int k = 0; k < B.ne[a]; ++k) {
           const ld t = 2 * (xyz[3 * r + a] - (B.x0[a] + k * (ld)B.h[a])) / B.h[a] - 1;
@@ -1842,6 +2293,10 @@ pmdg_status pmdg_node_coords(pmdg_solver* s, double* xyz) {
     for (int k = 0; k < B.nn[2]; ++k)
       for (int j = 0; j < B.nn[1]; ++j)
         for (int i = 0; i < B.nn[0]; ++i, ++o) {
+          if (B.mapped()) {
+            hex_node_xyz(B, i, j, k, xyz + 3 * o);
+            continue;
+          }
           xyz[3 * o] = B.coord(0, i);
           xyz[3 * o + 1] = B.coord(1, j);
           xyz[3 * o + 2] = B.coord(2, k);
@@ -2127,6 +2582,7 @@ pmdg_status pmdg_batch_create(int n, pmdg_solver* const* solvers, pmdg_batch** o
     if (ws_lost(s)) { delete b; return fail(PMDG_ESTATE, kLostMsg); }
     if (s->ndom != 1 || s->prec != 32) { delete b; return fail(PMDG_EINVAL, "batches take single-brick FP32 solvers"); }
     if (s->b[0].pml) { delete b; return fail(PMDG_EINVAL, "batches take solvers without a matched layer"); }
+    if (s->b[0].mapped()) { delete b; return fail(PMDG_EINVAL, "batches take axis-aligned bricks"); }
     const int rows = brick_rows(s, 0);
     if (rows != 1 && rows != 2) { delete b; return fail(PMDG_EINVAL, "batched tiles use 1 or 2 rows per wave"); }
     if (s->waves != kWaves) { delete b; return fail(PMDG_EINVAL, "batched tiles use 4 waves per workgroup"); }

@@ -192,6 +192,32 @@ struct PmlArgs {
   Real D[(kMaxOrder + 1) * (kMaxOrder + 1)];  // D[q][m] = l_m'(x_q)
 };
 
+// Trilinear hexahedra (a brick given by its element vertices): the
+// element kernel writes each element's residual K_e p at its own nodes, the
+// node kernel gathers those, adds the PMUT force and advances the state.
+template <typename Real>
+struct HexArgs {
+  DomView<Real> d;
+  int S;
+  int ne[3];
+  int nel;                  // ne0 ne1 ne2
+  int eblocks;              // workgroups of the element kernel
+  Real dt2, c2;
+  const long* counter;
+  const Real* force;        // PMUT face force [S][plane] on the bottom plane, or null
+  const Real* minv;         // [pnodes] inverse assembled lumped mass
+  const Real* vert;         // [nel][24] corner offsets from corner 0 (corner c = cx + 2 cy + 4 cz)
+  Real* y;                  // [S][nel][(N+1)^3] element residuals
+  Real w[kMaxOrder + 1];    // GLL weights
+  Real xg[kMaxOrder + 1];   // GLL nodes
+  Real D[(kMaxOrder + 1) * (kMaxOrder + 1)];  // D[q][m] = l_m'(x_q)
+};
+
+template <typename Real>
+hipError_t launch_hex(const HexArgs<Real>& a, bool incr, hipStream_t st);
+template <typename Real>
+int hex_elems_per_block(int N);
+
 // Launchers (defined in pmutdg_kernels.hip).
 template <typename Real>
 hipError_t launch_stiff(const StiffArgs<Real>& a, bool incr, hipStream_t st);

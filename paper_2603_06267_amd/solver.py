@@ -135,6 +135,12 @@ class Solver:
     def set_rx(self, t_switch, cap):
         check(self.L.pmdg_set_rx(self.h, float(t_switch), float(cap)))
 
+    def set_vertices(self, dom, V):
+        """Trilinear hexahedra: element vertices [(ne0+1)(ne1+1)(ne2+1), 3]
+        of the single brick, x fastest; before set_pmuts, set_receivers and
+        bind."""
+        check(self.L.pmdg_set_vertices(self.h, int(dom), _d(_f64(V).reshape(-1, 3))))
+
     def set_absorbing(self, dom, faces):
         """First-order absorbing condition on the outer faces of brick dom
         (6-bit mask: bit 2a low end, 2a + 1 high end of axis a); before bind."""
@@ -240,6 +246,9 @@ def from_workload(wl, precision=32, n_steps=None, scenarios=None, shape_fn=None,
     steps = n_steps if n_steps is not None else wl["steps"]
     s = Solver(wl["domains"], cfl=wl.get("cfl", 0.3), alpha=wl.get("alpha", 2.0), precision=precision,
                n_scenarios=S, trace_capacity=max(steps, 1), device=device)
+    for d, dom in enumerate(wl["domains"]):
+        if dom.get("vertices") is not None:
+            s.set_vertices(d, dom["vertices"])
     for d, dom in enumerate(wl["domains"]):
         if dom.get("absorbing", 0):
             s.set_absorbing(d, dom["absorbing"])

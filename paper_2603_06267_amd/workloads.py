@@ -307,6 +307,49 @@ def small_two_domain(nested=True, steps=60):
             "receivers": rec, "steps": steps}
 
 
+def mapped_cube(kind="conforming", N=4, ne=(4, 4, 4), steps=400, seed=0):
+    """The config-1 cube (one disc of radius 0.433 mm at the centre of the
+    bottom face) meshed by trilinear hexahedra: "conforming" puts element
+    edges on the disc's circle, "warped" moves the vertices by a smooth
+    seeded field, "jittered" adds a seeded jitter of the interior vertices
+    to that; the boundary planes stay where they are."""
+    wl = config1()
+    dom = brick([0, 0, 0], [1, 1, 1], list(ne), N)
+    if kind == "conforming":
+        V = disc_conforming_vertices(dom, np.array([[0.5, 0.5]]), 0.433, 1.0)
+    elif kind == "warped":
+        V = warped_vertices(dom, amp=0.2, seed=seed)
+    elif kind == "jittered":
+        V = warped_vertices(dom, amp=0.2, jitter=0.25, seed=seed)
+    else:
+        raise ValueError(kind)
+    dom["vertices"] = V
+    return dict(wl, name=f"cube-{kind}-{ne[0]}x{ne[1]}x{ne[2]}N{N}-1pmut", domains=[dom], steps=steps)
+
+
+def mapped_array(steps=300):
+    """The large array's PMUT brick on its own, meshed so that element edges
+    follow every disc: 32x32 = 1024 discs (r = 0.433 mm) at 1 mm pitch,
+    10 modes each, 128x128x8 trilinear hexahedra of order N = 4 over
+    [0,32]^2 x [0,2] mm (8.68M unique DOFs); the beam steered 20 degrees
+    along x; 64 receivers in the brick's upper half."""
+    rng = np.random.default_rng(SEED0 + 6)
+    dom = brick([0, 0, 0], [32, 32, 2], [128, 128, 8], 4)
+    ctr = _grid_centres(32, 32, 1.0, 0.5)
+    dom["vertices"] = disc_conforming_vertices(dom, ctr, 0.433, 1.0)
+    freqs = rng.uniform(2.375, 2.625, size=(1024, 10))
+    pm = _pmut_block(ctr, 0.433, freqs)
+    f = 2.5
+    phase = (2 * math.pi * f * ctr[:, 0] * math.sin(math.radians(20.0)) / C_WATER).reshape(1, -1)
+    rec = np.column_stack([rng.uniform(1.0, 31.0, size=64), rng.uniform(1.0, 31.0, size=64),
+                           rng.uniform(1.0, 1.95, size=64)])
+    return {"name": "array-1024pmut-conforming-128x128x8N4", "domains": [dom], "cfl": 0.3,
+            "alpha": 2.0, "pmuts": pm,
+            "drive": {"amp": np.ones((1, 1024)), "phase": phase, "freq": np.array([f]),
+                      "ncyc": 3.0, "envelope": 0},
+            "receivers": rec, "steps": steps}
+
+
 CONFIGS = {1: config1, 2: config2, 3: config3}
 
 

@@ -203,3 +203,75 @@ def test_mlp_host_checks():
     assert L.pmdg_mlp_scatter_rows(x, x, -1, 8, x, None) == _lib.PMDG_EINVAL
     L.pmdg_mlp_destroy(h)
     L.pmdg_mlp_destroy(None)
+
+
+def test_trilinear_host_setup_matches_oracle():
+    """pmdg_set_vertices (Sec. 3, trilinear maps X_K): the re-chosen time
+    step, the stability estimate (whole-mesh Lanczos on small meshes, the
+    element-wise bound above 150,000 nodes), the node coordinates and the
+    PMUT face nodes agree with the oracle on the same vertices."""
+    for kind in ("conforming", "jittered"):
+        wl = W.mapped_cube(kind)
+        dom = wl["domains"][0]
+        s = solver.Solver([dom])
+        s.set_vertices(0, dom["vertices"])
+        o = ref.RefSolver([dom])
+        o.set_vertices(0, dom["vertices"])
+        assert abs(s.dt - o.dt) <= 1e-14 * o.dt
+        lo = o.lambda_max(iters=800)
+        assert lo * 0.999 <= s.lambda_max() <= lo * 1.003
+        assert np.abs(s.node_coords() - o.coords()).max() < 1e-13
+        pm = wl["pmuts"]
+        s.set_pmuts(pm["centers"], pm["radius"], pm["omega"], pm["zeta"], pm["eta"])
+        o.set_pmuts(pm["centers"], pm["radius"], pm["omega"], pm["zeta"], pm["eta"])
+        a, b = s.pmut_face_nodes(0), o.pmut_nodes(0)
+        assert a.shape == b.shape and np.abs(a - b).max() < 1e-14
+
+
+def test_trilinear_element_bound_is_above_the_eigenvalue():
+    """Above the Lanczos size the stability check takes
+    max_e lambda_max(Mt_e^{-1} K_e), Mt_e the assembled mass over the node's
+    multiplicity: an upper bound of lambda_max(M^{-1} K)."""
+    dom = W.brick([0, 0, 0], [6.0, 6.0, 2.0], [24, 24, 8], 4)   # 157,609 nodes
+    V = W.warped_vertices(dom, amp=0.2, jitter=0.15, seed=3)
+    s = solver.Solver([dom])
+    s.set_vertices(0, V)
+    small = W.brick([0, 0, 0], [1.5, 1.5, 1.0], [6, 6, 4], 4)
+    Vs = W.warped_vertices(small, amp=0.2, jitter=0.15, seed=3)
+    o = ref.RefSolver([small])
+    o.set_vertices(0, Vs)
+    # same element sizes and distortion: the bound sits above the smaller
+    # mesh's eigenvalue and within 3x of it
+    lam_small = o.lambda_max(iters=600)
+    assert lam_small < s.lambda_max() < 3 * lam_small
+    assert s.dt ** 2 * s.lambda_max() < 4
+
+
+def test_trilinear_errors():
+    wl = W.mapped_cube("warped")
+    dom = wl["domains"][0]
+    V = dom["vertices"]
+    two = W.small_two_domain()["domains"]
+    assert _err(solver.Solver(two).set_vertices, 0, np.zeros((10, 3))) == _lib.PMDG_EINVAL
+    s = solver.Solver([dom])
+    bad = V.copy()
+    bad[0] = np.nan
+    assert _err(s.set_vertices, 0, bad) == _lib.PMDG_EINVAL
+    # fold one element inside out: swap two vertices of the top layer
+    fold = V.copy()
+    nx = dom["ne"][0] + 1
+    fold[[1, 1 + nx * (dom["ne"][1] + 1)]] = fold[[1 + nx * (dom["ne"][1] + 1), 1]]
+    assert _err(s.set_vertices, 0, fold) == _lib.PMDG_EINVAL
+    s.set_vertices(0, V)
+    assert _err(s.set_absorbing, 0, 1) == _lib.PMDG_EINVAL
+    assert _err(s.set_pml, 0, [0.25, 0, 0, 0, 0, 0]) == _lib.PMDG_EINVAL
+    # a time step stable on the brick but not on the warped mesh
+    lb = solver.Solver([dom]).lambda_max()
+    assert s.lambda_max() > 1.1 * lb
+    t = solver.Solver([dom], cfl=0.0, dt=0.98 * 2 / np.sqrt(lb))
+    assert _err(t.set_vertices, 0, V) == _lib.PMDG_EUNSTABLE
+    # geometry must come before the PMUTs and receivers
+    u = solver.Solver([dom])
+    pm = wl["pmuts"]
+    u.set_pmuts(pm["centers"], pm["radius"], pm["omega"], pm["zeta"], pm["eta"])
+    assert _err(u.set_vertices, 0, V) == _lib.PMDG_ESTATE
