@@ -174,6 +174,29 @@ pmdg_status pmdg_set_pml(pmdg_solver* h, int dom, const double* ell, double R);
  * accepted by pmdg_batch_create. */
 pmdg_status pmdg_set_vertices(pmdg_solver* h, int dom, const double* V);
 
+/* Face matching on Gamma_I (Sec. 5, Algorithm 3), on the GPU.  Fine side:
+ * nf hexahedra fine_hex[nf][8][3] (corner c = cx + 2 cy + 4 cz) and the local
+ * face of each on Gamma_I, fine_face[nf] = 2 axis + side (side 0: the face
+ * xi_axis = -1, side 1: +1); coarse side likewise (nc, coarse_hex,
+ * coarse_face).  For every Gauss-Legendre point (nq per direction) of every
+ * fine face, x_q = X_{K+}(xi), the coarse faces are taken in index order;
+ * one is a candidate when its outward unit normal at its centre is opposite
+ * to the fine face's, |n+ + n-| < tol, and its first corner (lowest corner
+ * index on the face) lies within r = max(diam F-, diam F+) + eps of x_q
+ * (diam: the largest distance between two corners of the face); the
+ * first candidate whose element's inverse
+ * map (Newton) puts x_q in [-1, 1]^3 up to 1e-10 is the match.  Points are
+ * ordered (fine face, j, i), i along the face's first tangential axis
+ * (axis + 1) mod 3.  Writes elem[nf nq^2] (coarse index, or -1),
+ * xi[nf nq^2][3] (reference point in that element, 0 if unmatched) and
+ * *unmatched (the count of -1 entries).  Every array is device memory; the
+ * call enqueues two kernels on stream and returns (no allocation, no wait).
+ * Faces with an index outside 0..5 match nothing.  EINVAL: nq outside
+ * 1..9, negative counts, tol <= 0, eps < 0, NULL arrays. */
+pmdg_status pmdg_match_faces(int nq, int nf, const double* fine_hex, const int* fine_face, int nc,
+                             const double* coarse_hex, const int* coarse_face, double tol, double eps, int* elem,
+                             double* xi, int* unmatched, void* stream);
+
 /* Receiver points xyz[3*R]; each is located in the lowest-index element
  * containing it (primary first) and sampled by tensor Lagrange
  * interpolation, accumulated in FP64.  A point outside both bricks gives

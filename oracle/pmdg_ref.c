@@ -478,7 +478,8 @@ int pmdg_ref_set_vertices(void *h, int dd, const double *V) {
 
 /* Outward unit normal at the centre of face f = 2 axis + side of the
  * element with vertices V8, the face's first corner and its diameter (the
- * longer diagonal). */
+ * largest distance between two of its corners, which bounds the distance
+ * from a corner to any point of the face). */
 static void face_geometry(const double V8[8][3], int f, double n[3], double v0[3], double *diam) {
   int ax = f / 2, side = f % 2, t1 = (ax + 1) % 3, t2 = (ax + 2) % 3;
   double xi[3] = {0, 0, 0}, x[3], J[3][3];
@@ -492,12 +493,14 @@ static void face_geometry(const double V8[8][3], int f, double n[3], double v0[3
   int k[4];
   for (int q = 0; q < 4; ++q) k[q] = (side << ax) | ((q & 1) << t1) | (((q >> 1) & 1) << t2);
   for (int i = 0; i < 3; ++i) v0[i] = V8[k[0]][i];
-  double d1 = 0, d2 = 0;
-  for (int i = 0; i < 3; ++i) {
-    d1 += (V8[k[3]][i] - V8[k[0]][i]) * (V8[k[3]][i] - V8[k[0]][i]);
-    d2 += (V8[k[2]][i] - V8[k[1]][i]) * (V8[k[2]][i] - V8[k[1]][i]);
-  }
-  *diam = sqrt(d1 > d2 ? d1 : d2);
+  double dmax = 0;
+  for (int p = 0; p < 4; ++p)
+    for (int q = p + 1; q < 4; ++q) {
+      double d = 0;
+      for (int i = 0; i < 3; ++i) d += (V8[k[q]][i] - V8[k[p]][i]) * (V8[k[q]][i] - V8[k[p]][i]);
+      if (d > dmax) dmax = d;
+    }
+  *diam = sqrt(dmax);
 }
 
 /* Face matching on Gamma_I (Sec. 5, Algorithm 3).  Fine side: nf
@@ -508,7 +511,8 @@ static void face_geometry(const double V8[8][3], int f, double n[3], double v0[3
  * X_{K+}(xi), the coarse faces are taken in index order; one is a candidate
  * when its outward normal at its centre is opposite to the fine face's,
  * |n+ + n-| < tol, and its first corner lies within
- * r = max(diam F-, diam F+) + eps of x_q; the first candidate whose
+ * r = max(diam F-, diam F+) + eps of x_q (diam: the largest distance
+ * between two corners of the face); the first candidate whose
  * element's inverse map (Newton) puts x_q in [-1, 1]^3, up to 1e-10, is the
  * match.  Points are ordered (fine face, j, i) with i along the face's
  * first tangential axis (axis + 1) mod 3.  Writes elem[nf nq^2] (coarse

@@ -65,6 +65,8 @@ _SIGS = {
     "pmdg_set_absorbing": [_vp, ctypes.c_int, ctypes.c_int],
     "pmdg_set_pml": [_vp, ctypes.c_int, _dp, ctypes.c_double],
     "pmdg_set_vertices": [_vp, ctypes.c_int, _dp],
+    "pmdg_match_faces": [ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp, _vp, ctypes.c_double,
+                         ctypes.c_double, _vp, _vp, _vp, _vp],
     "pmdg_set_receivers": [_vp, ctypes.c_int, _dp],
     "pmdg_workspace_size": [_vp, ctypes.POINTER(ctypes.c_size_t)],
     "pmdg_bind": [_vp, _vp, ctypes.c_size_t, _vp],

@@ -2009,6 +2009,36 @@ pmdg_status pmdg_set_pml(pmdg_solver* s, int dom, const double* ell, double R) {
   return PMDG_OK;
 }
 
+pmdg_status pmdg_match_faces(int nq, int nf, const double* fine_hex, const int* fine_face, int nc,
+                             const double* coarse_hex, const int* coarse_face, double tol, double eps, int* elem,
+                             double* xi, int* unmatched, void* stream) {
+  if (nq < 1 || nq > kMaxNq) return fail(PMDG_EINVAL, "nq must be in 1..9");
+  if (nf < 0 || nc < 0) return fail(PMDG_EINVAL, "face counts must be >= 0");
+  if (!(tol > 0) || !(eps >= 0)) return fail(PMDG_EINVAL, "tol must be > 0 and eps >= 0");
+  if (!unmatched || (nf > 0 && (!fine_hex || !fine_face || !elem || !xi)) || (nc > 0 && (!coarse_hex || !coarse_face)))
+    return fail(PMDG_EINVAL, "NULL array");
+  if ((long)nf * nq * nq > (1L << 31) - 1) return fail(PMDG_EINVAL, "too many points");
+  MatchArgs a;
+  memset(&a, 0, sizeof(a));
+  a.nq = nq;
+  a.nf = nf;
+  a.nc = nc;
+  a.fine_hex = fine_hex;
+  a.fine_face = fine_face;
+  a.coarse_hex = coarse_hex;
+  a.coarse_face = coarse_face;
+  a.tol = tol;
+  a.eps = eps;
+  a.elem = elem;
+  a.xi = xi;
+  a.unmatched = unmatched;
+  std::vector<ld> gx, gw;
+  gl_rule(nq, gx, gw);
+  for (int i = 0; i < nq; ++i) a.gq[i] = (double)gx[i];
+  HIPCHK(launch_match(a, (hipStream_t)stream));
+  return PMDG_OK;
+}
+
 pmdg_status pmdg_set_vertices(pmdg_solver* s, int dom, const double* V) {
   if (!s || !V) return fail(PMDG_EINVAL, "NULL argument");
   if (s->bound) return fail(PMDG_ESTATE, "set_vertices must precede bind");

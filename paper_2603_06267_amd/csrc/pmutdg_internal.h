@@ -218,6 +218,22 @@ hipError_t launch_hex(const HexArgs<Real>& a, bool incr, hipStream_t st);
 template <typename Real>
 int hex_elems_per_block(int N);
 
+// Face matching on Gamma_I (Sec. 5, Algorithm 3) of hexahedra given by
+// their corners; device arrays.
+struct MatchArgs {
+  int nq, nf, nc;
+  const double* fine_hex;   // [nf][8][3]
+  const int* fine_face;     // [nf] 2 axis + side
+  const double* coarse_hex; // [nc][8][3]
+  const int* coarse_face;   // [nc]
+  double tol, eps;
+  int* elem;                // [nf nq^2]
+  double* xi;               // [nf nq^2][3]
+  int* unmatched;           // one int
+  double gq[kMaxNq + 1];    // Gauss-Legendre nodes
+};
+hipError_t launch_match(const MatchArgs& a, hipStream_t st);
+
 // Launchers (defined in pmutdg_kernels.hip).
 template <typename Real>
 hipError_t launch_stiff(const StiffArgs<Real>& a, bool incr, hipStream_t st);

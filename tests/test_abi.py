@@ -275,3 +275,17 @@ def test_trilinear_errors():
     pm = wl["pmuts"]
     u.set_pmuts(pm["centers"], pm["radius"], pm["omega"], pm["zeta"], pm["eta"])
     assert _err(u.set_vertices, 0, V) == _lib.PMDG_ESTATE
+
+
+def test_match_faces_argument_errors():
+    """pmdg_match_faces checks its sizes, tolerances and pointers on the host
+    before enqueueing anything."""
+    L = _lib.lib()
+    vp = ctypes.c_void_p
+    one = vp(1)
+    ok = (4, 1, one, one, 1, one, one, 1e-6, 1e-9, one, one, one, None)
+    for i, bad in ((0, 0), (0, 10), (1, -1), (4, -1), (7, 0.0), (8, -1e-9), (2, None), (5, None), (9, None),
+                   (11, None)):
+        a = list(ok)
+        a[i] = bad
+        assert L.pmdg_match_faces(*a) == _lib.PMDG_EINVAL, (i, bad)

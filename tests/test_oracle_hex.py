@@ -287,3 +287,25 @@ def _trilinear(V8, xi):
             w *= 0.5 * (1 + s * xi[a])
         x += w * V8[c]
     return x
+
+
+def _trapezoid_case():
+    """A coarse element whose interface face is a thin trapezoid with one
+    edge (10) longer than both diagonals (about 5.1), and a small fine face
+    near that edge's far end: the point lies 9.85 from the coarse face's
+    first corner."""
+    bot = np.array([[0, 0], [10, 0], [4.9, 0.1], [5.1, 0.1]])
+    coarse = np.array([[*bot[c & 3], 0.0 if c < 4 else 1.0] for c in range(8)])[None]
+    fx, fy = (9.80, 9.90), (0.0002, 0.0008)
+    fine = np.array([[fx[c & 1], fy[(c >> 1) & 1], -1.0 if c < 4 else 0.0] for c in range(8)])[None]
+    return fine, np.array([5]), coarse, np.array([4])
+
+
+def test_matching_radius_is_the_face_diameter():
+    """r = max(diam F-, diam F+) + eps with diam the largest distance between
+    two corners: a point of the face can be farther from the first corner
+    than either diagonal."""
+    fine, ff, coarse, cf = _trapezoid_case()
+    elem, xi, un = R.match_faces(2, fine, ff, coarse, cf)
+    assert un == 0 and (elem == 0).all()
+    assert np.abs(xi[:, 2] + 1).max() < 1e-12
