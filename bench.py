@@ -229,6 +229,91 @@ def pml_leg(steps=200, warmup=10):
             "ms_per_step": min(el, el_graph) * 1e3 / steps, "stiff_and_layer_ms": kt[0], "finite": finite}
 
 
+def mapped_leg(steps=200, warmup=10):
+    """The large array's PMUT brick meshed by trilinear hexahedra whose edges
+    follow every disc (128x128x8 hexes, N = 4, 1024 PMUTs): rate with graph
+    replay, the time of the two element-path launches per step against the
+    bytes an update must move (read p, the increment X and the inverse mass,
+    write p and X: 20 B per DOF, plus 96 B of corner offsets per element),
+    and the trace error of a 1,000-step run against the oracle's stored
+    traces."""
+    from paper_2603_06267_amd import solver, workloads as W
+    wl = W.mapped_array(steps=steps + warmup)
+    dofs = W.unique_dofs(wl)
+    d = wl["domains"][0]
+    nel = int(np.prod(d["ne"]))
+    n3 = (d["N"] + 1) ** 3
+    el, el_graph, kt, finite = run_gpu(wl, 32, steps, warmup, True, 0, 73)
+    alg = 20.0 * dofs + 96.0 * nel
+    # the element residuals go through HBM once each way
+    design = alg + 4.0 * dofs + 2 * 4.0 * nel * n3
+    full = W.mapped_array()
+    to = golden_traces("mapped", full)
+    terr = None
+    if to is not None:
+        g = solver.from_workload(full, precision=32, shape_fn=W.shape_fn(full), device="cuda:0")
+        g.step(full["steps"])
+        terr = trace_error(g.read_traces()[0], to)
+        g.close()
+    return {"workload": "large-array PMUT brick, 128x128x8 trilinear hexes N=4 with edges on every disc, "
+                        "1024 PMUTs", "unique_dofs": dofs, "elements": nel,
+            "value": dofs * steps / min(el, el_graph), "unit": "DOF-updates/s",
+            "ms_per_step": min(el, el_graph) * 1e3 / steps, "element_path_ms": kt[0],
+            "roofline": {"bound": "hbm", "algorithmic_bytes": alg, "design_bytes": design,
+                         "achieved": alg / (kt[0] * 1e-3) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": alg / (kt[0] * 1e-3) / 1e9 / PEAK_HBM_GBS},
+            "finite": finite, "trace_error": terr}
+
+
+def matching_leg(repeats=5):
+    """Face matching of Sec. 5, Algorithm 3, on the large array's interface
+    (16,384 fine faces, 5 x 5 Gauss points each, against 9,216 coarse faces),
+    as bricks and with both sides warped: GPU time per call (HIP events) and
+    the oracle's single-thread rate on a sample of 64 fine faces."""
+    import torch
+    from oracle import ref
+    from paper_2603_06267_amd import matching as M, workloads as W
+    wl = W.config3(steps=1)
+    prim, sec = wl["domains"]
+    out = {"fine_faces": prim["ne"][0] * prim["ne"][1], "coarse_faces": sec["ne"][0] * sec["ne"][1], "nq": 5}
+    rng = np.random.default_rng(5)
+
+    def warp(dom, amp=0.25):
+        V = W.brick_vertices(dom)
+        x0, x1 = np.asarray(dom["x0"]), np.asarray(dom["x1"])
+        h = (x1 - x0) / np.asarray(dom["ne"])
+        side = np.any(np.abs(V[:, :2] - x0[:2]) < 1e-12, axis=1) | np.any(np.abs(V[:, :2] - x1[:2]) < 1e-12, axis=1)
+        V[~side, :2] += amp * h[:2] * rng.uniform(-1, 1, size=((~side).sum(), 2))
+        return V
+
+    for name, Vf, Vc in (("bricks", W.brick_vertices(prim), W.brick_vertices(sec)),
+                         ("warped", warp(prim), warp(sec))):
+        fine = M.layer_hexes(Vf, prim["ne"], prim["ne"][2] - 1)
+        coarse = M.layer_hexes(Vc, sec["ne"], 0)
+        ff, cf = np.full(len(fine), 5), np.full(len(coarse), 4)
+        e, x, u = M.match_faces(5, fine, ff, coarse, cf)
+        torch.cuda.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(repeats):
+            e, x, u = M.match_faces(5, fine, ff, coarse, cf)
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / repeats
+        npts = len(fine) * 25
+        sample = np.sort(rng.choice(len(fine), size=64, replace=False))
+        c0 = time.perf_counter()
+        eo, xo, uo = ref.match_faces(5, fine[sample], ff[sample], coarse, cf)
+        cpu = time.perf_counter() - c0
+        pts = (sample[:, None] * 25 + np.arange(25)[None, :]).ravel()
+        en = e.cpu().numpy()
+        out[name] = {"points": npts, "gpu_ms": ms, "gpu_points_per_s": npts / (ms * 1e-3),
+                     "unmatched": int(u.cpu().numpy()[0]),
+                     "oracle_points_per_s": len(pts) / cpu, "oracle_threads": 1,
+                     "sample_agrees": bool(np.array_equal(en[pts], eo))}
+    return out
+
+
 def small_configs_leg(steps=400, warmup=20):
     """DOF-updates/s of the small workloads (the config-1 cube and the
     config-2 two-domain array), FP32 and FP64, hipGraph replay: latency-bound
@@ -413,6 +498,10 @@ def main():
     ap.add_argument("--no-pml", action="store_true", help="skip the large array with matched layers")
     ap.add_argument("--pml-only", action="store_true",
                     help="run only the large array with matched layers (direct launches, for counters)")
+    ap.add_argument("--no-mapped", action="store_true",
+                    help="skip the PMUT brick meshed by trilinear hexahedra and the face matching")
+    ap.add_argument("--mapped-only", action="store_true",
+                    help="run only the trilinear-hexahedron brick (direct launches with --direct, for counters)")
     ap.add_argument("--no-trace", action="store_true",
                     help="skip the full 5,000-step large-array runs compared with the oracle's traces")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-form leg")
@@ -438,6 +527,12 @@ def main():
         el, el_graph, kt, finite = run_gpu(wl, 32, args.steps, args.warmup, not args.direct, 0, 73)
         print(json.dumps({"pml_only": True, "ms_per_step": min(el, el_graph) * 1e3 / args.steps,
                           "stiff_and_layer_ms": kt[0], "finite": finite}), flush=True)
+        return
+    if args.mapped_only:
+        wl = W.mapped_array(steps=args.steps + args.warmup)
+        el, el_graph, kt, finite = run_gpu(wl, 32, args.steps, args.warmup, not args.direct, 0, 73)
+        print(json.dumps({"mapped_only": True, "ms_per_step": min(el, el_graph) * 1e3 / args.steps,
+                          "element_path_ms": kt[0], "finite": finite}), flush=True)
         return
     wl = W.config3(steps=args.steps + args.warmup)
     dofs = W.unique_dofs(wl)
@@ -502,6 +597,11 @@ def main():
     if not args.no_pml:
         log("large array with matched layers ...")
         out["pml"] = pml_leg()
+    if not args.no_mapped:
+        log("trilinear-hexahedron PMUT brick ...")
+        out["mapped"] = mapped_leg()
+        log("face matching (Algorithm 3) ...")
+        out["matching"] = matching_leg()
     if not args.no_small:
         log("small workloads ...")
         out["small"] = small_configs_leg()

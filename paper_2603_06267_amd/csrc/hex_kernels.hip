@@ -5,12 +5,16 @@
 // c^2 (J^{-T} grad_xi p) . (J^{-T} grad_xi v) |J|, taken by GLL collocation).
 //
 // Two launches per step:
-//   k_hex_elem: per element, the reference gradient of p by the 1D
+//   k_hex_elem: per strip of elements along x (p staged in LDS row by row,
+//     shared nodes loaded once), one thread per (element, a, b) column of
+//     nodes marching along c: the reference gradient of p by the 1D
 //     derivative matrix along each axis (sum factorisation), the metric
-//     G = w |J| c^2 J^{-1} J^{-T} from the trilinear map at each node
-//     (computed from the element's eight corners, nothing stored per node),
-//     and the transposed contraction; each element writes its residual at
-//     its own (N+1)^3 nodes, so no two workgroups add into one address.
+//     G = w |J| c^2 J^{-1} J^{-T} at each node (the Jacobian's column d is
+//     the bilinear interpolation of the element's four half edges along d;
+//     nothing is stored per node), and the transposed contraction, whose
+//     component along c stays in the thread's registers; each element
+//     writes its residual at its own (N+1)^3 nodes, so no two workgroups add
+//     into one address.
 //   k_hex_node: per node, the sum of the residuals of the (up to eight)
 //     elements holding it, the PMUT face force, the inverse lumped mass and
 //     the explicit Newmark update (increment form in FP32, two-level form in
@@ -19,118 +23,168 @@
 
 namespace pmdg {
 
+// Elements per workgroup: a strip of SX consecutive elements along x, one
+// thread per (element, a, b) column of nodes.
 template <int N>
-__host__ __device__ constexpr int hex_epb() {
-  return (N + 1) * (N + 1) * (N + 1) <= 256 ? 256 / ((N + 1) * (N + 1) * (N + 1)) : 1;
+__host__ __device__ constexpr int hex_sx() {
+  return 256 / ((N + 1) * (N + 1));
+}
+
+// Residual layout (x-contiguous): for element row (ey, ez) and local row
+// (b, c), the entries of all elements of the row follow each other along x,
+// element ex at ex (N+1) + a; so a wave writing one strip and a wave
+// gathering one node row both touch consecutive addresses.
+template <int N, typename Real>
+__device__ __forceinline__ long hex_yidx(const HexArgs<Real>& a, int ex, int ey, int ez, int la, int lb, int lc) {
+  constexpr int n1 = N + 1;
+  return (((long)(ez * a.ne[1] + ey) * n1 + lc) * n1 + lb) * ((long)a.ne[0] * n1) + (long)ex * n1 + la;
 }
 
 template <typename Real, int N>
 __global__ void __launch_bounds__(256) k_hex_elem(const HexArgs<Real> a) {
-  constexpr int n1 = N + 1, n3 = n1 * n1 * n1, EPB = hex_epb<N>();
-  __shared__ Real u[EPB][n3];
-  __shared__ Real F[EPB][3][n3];
-  __shared__ Real V[EPB][24];
-  __shared__ Real Dm[n1 * n1];
+  constexpr int n1 = N + 1, n2 = n1 * n1, n3 = n2 * n1, SX = hex_sx<N>(), UX = SX * N + 1;
+  __shared__ Real u[n2 * UX];      // p on the strip's nodes, [c][b][x]
+  __shared__ Real F0[SX * n3];     // reference flux components 0 and 1,
+  __shared__ Real F1[SX * n3];     //   [element][c][b][a]
+  __shared__ Real E[SX][12][3];    // half edge vectors: 4 along each axis
+  __shared__ Real Dm[n2], Wq[n1], Xq[n1];
   const int tid = threadIdx.x;
-  const long total = (long)a.S * a.nel;
-  const long g0 = (long)blockIdx.x * EPB;
+  const int nsx = (a.ne[0] + SX - 1) / SX;
+  long t = blockIdx.x;
+  const int sx = (int)(t % nsx); t /= nsx;
+  const int ey = (int)(t % a.ne[1]); t /= a.ne[1];
+  const int ez = (int)(t % a.ne[2]);
+  const int s = (int)(t / a.ne[2]);
+  const int ex0 = sx * SX, nsx_here = min(SX, a.ne[0] - ex0);
   const long cnt = *a.counter;
-  const Real* __restrict__ P = a.d.P[(int)(cnt % a.d.nbuf)];
-  if (tid < n1 * n1) Dm[tid] = a.D[tid];
-  for (int t = tid; t < EPB * 24; t += 256) {
-    const int es = t / 24, j = t - es * 24;
-    const long ge = g0 + es;
-    V[es][j] = ge < total ? a.vert[(ge % a.nel) * 24 + j] : Real(0);
+  const Real* __restrict__ P = a.d.P[(int)(cnt % a.d.nbuf)] + (long)s * a.d.nnodes;
+  if (tid < n2) Dm[tid] = a.D[tid];
+  if (tid < n1) {
+    Wq[tid] = a.w[tid];
+    Xq[tid] = a.xg[tid];
   }
-  for (int t = tid; t < EPB * n3; t += 256) {
-    const int es = t / n3, i = t - es * n3;
-    const long ge = g0 + es;
-    Real v = Real(0);
-    if (ge < total) {
-      const int s = (int)(ge / a.nel), e = (int)(ge % a.nel);
-      const int ex = e % a.ne[0], ey = (e / a.ne[0]) % a.ne[1], ez = e / (a.ne[0] * a.ne[1]);
-      const int ia = i % n1, ib = (i / n1) % n1, ic = i / (n1 * n1);
-      const long node = (long)(N * ex + ia) + (long)a.d.px * (N * ey + ib) + a.d.plane * (N * ez + ic);
-      v = P[(long)s * a.d.nnodes + node];
+  // p on the strip: rows of nsx_here N + 1 consecutive nodes
+  const int ux = nsx_here * N + 1;
+  for (int w = tid; w < n2 * ux; w += 256) {
+    const int row = w / ux, xl = w - row * ux, lb = row % n1, lc = row / n1;
+    const long node = (long)(ex0 * N + xl) + (long)a.d.px * (ey * N + lb) + a.d.plane * (ez * N + lc);
+    u[row * UX + xl] = P[node];
+  }
+  // half edge vectors: edges along axis d join corners c and c | (1 << d)
+  // for the four c with bit d clear, in increasing order of c
+  for (int w = tid; w < SX * 36; w += 256) {
+    const int el = w / 36, r = w - el * 36, q = r / 3, k = r - 3 * q, d = q / 4, m = q % 4;
+    Real v = 0;
+    if (el < nsx_here) {
+      const int lo = m & ((1 << d) - 1), c0 = lo | ((m >> d) << (d + 1));
+      const long e = (long)(ex0 + el) + (long)a.ne[0] * (ey + (long)a.ne[1] * ez);
+      const Real* V = a.vert + e * 24;
+      v = Real(0.5) * (V[3 * (c0 | (1 << d)) + k] - V[3 * c0 + k]);
     }
-    u[es][i] = v;
+    E[el][q][k] = v;
   }
   __syncthreads();
-  // reference flux G grad_xi (p - p_0) at every node (p_0: the element's
-  // first nodal value; grad_xi of a constant is zero, so subtracting it only
-  // removes rounding from the sums)
-  for (int t = tid; t < EPB * n3; t += 256) {
-    const int es = t / n3, i = t - es * n3;
-    const int ia = i % n1, ib = (i / n1) % n1, ic = i / (n1 * n1);
-    const Real u0 = u[es][0];
-    Real g0r = 0, g1r = 0, g2r = 0;
+  // thread -> (a fastest, element, b): consecutive threads write consecutive
+  // residual addresses
+  const int ia = tid % n1, el = (tid / n1) % SX, ib = tid / (n1 * SX);
+  const bool active = tid < SX * n2 && el < nsx_here;
+  Real f2[n1];
+  if (active) {
+    // Jacobian column d at a node is the bilinear interpolation of the four
+    // half edges along d in the other two reference coordinates: column 2
+    // depends on (a, b) only; columns 0 and 1 are blended along c below
+    const Real xa = Xq[ia], xb = Xq[ib];
+    Real c2[3], A0[3], A1[3], B0[3], B1[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      // axis 2 edges: bits (0, 1) = (a, b)
+      const Real lo = Real(0.5) * ((1 - xa) * E[el][8][k] + (1 + xa) * E[el][9][k]);
+      const Real hi = Real(0.5) * ((1 - xa) * E[el][10][k] + (1 + xa) * E[el][11][k]);
+      c2[k] = Real(0.5) * ((1 - xb) * lo + (1 + xb) * hi);
+      // axis 0 edges: bits (1, 2) = (b, c); blend along b now, along c later
+      A0[k] = Real(0.5) * ((1 - xb) * E[el][0][k] + (1 + xb) * E[el][1][k]);
+      A1[k] = Real(0.5) * ((1 - xb) * E[el][2][k] + (1 + xb) * E[el][3][k]);
+      // axis 1 edges: bits (0, 2) = (a, c)
+      B0[k] = Real(0.5) * ((1 - xa) * E[el][4][k] + (1 + xa) * E[el][5][k]);
+      B1[k] = Real(0.5) * ((1 - xa) * E[el][6][k] + (1 + xa) * E[el][7][k]);
+    }
+    const Real* ue = u + el * N;
+    Real da[n1], db[n1], ucol[n1];
 #pragma unroll
     for (int m = 0; m < n1; ++m) {
-      g0r += Dm[ia * n1 + m] * (u[es][m + n1 * (ib + n1 * ic)] - u0);
-      g1r += Dm[ib * n1 + m] * (u[es][ia + n1 * (m + n1 * ic)] - u0);
-      g2r += Dm[ic * n1 + m] * (u[es][ia + n1 * (ib + n1 * m)] - u0);
+      da[m] = Dm[ia * n1 + m];
+      db[m] = Dm[ib * n1 + m];
+      ucol[m] = ue[(m * n1 + ib) * UX + ia];
     }
-    // J[r][c] = d x_r / d xi_c of the trilinear map at this node
-    const Real xi[3] = {a.xg[ia], a.xg[ib], a.xg[ic]};
-    Real J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    const Real wab = Wq[ia] * Wq[ib] * a.c2;
 #pragma unroll
-    for (int c = 1; c < 8; ++c) {
-      const Real s0 = (c & 1) ? Real(1) : Real(-1), s1 = (c & 2) ? Real(1) : Real(-1), s2 = (c & 4) ? Real(1) : Real(-1);
-      const Real f0 = Real(0.5) * (Real(1) + s0 * xi[0]), f1 = Real(0.5) * (Real(1) + s1 * xi[1]),
-                 f2 = Real(0.5) * (Real(1) + s2 * xi[2]);
-      const Real d0 = Real(0.5) * s0 * f1 * f2, d1 = Real(0.5) * s1 * f0 * f2, d2 = Real(0.5) * s2 * f0 * f1;
+    for (int ic = 0; ic < n1; ++ic) {
+      Real g0 = 0, g1 = 0, g2 = 0;
 #pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        const Real vc = V[es][3 * c + r];
-        J[r][0] += d0 * vc;
-        J[r][1] += d1 * vc;
-        J[r][2] += d2 * vc;
+      for (int m = 0; m < n1; ++m) {
+        g0 += da[m] * ue[(ic * n1 + ib) * UX + m];
+        g1 += db[m] * ue[(ic * n1 + m) * UX + ia];
+        g2 += Dm[ic * n1 + m] * ucol[m];
       }
+      const Real zc = Xq[ic];
+      const Real J00 = Real(0.5) * ((1 - zc) * A0[0] + (1 + zc) * A1[0]);
+      const Real J10 = Real(0.5) * ((1 - zc) * A0[1] + (1 + zc) * A1[1]);
+      const Real J20 = Real(0.5) * ((1 - zc) * A0[2] + (1 + zc) * A1[2]);
+      const Real J01 = Real(0.5) * ((1 - zc) * B0[0] + (1 + zc) * B1[0]);
+      const Real J11 = Real(0.5) * ((1 - zc) * B0[1] + (1 + zc) * B1[1]);
+      const Real J21 = Real(0.5) * ((1 - zc) * B0[2] + (1 + zc) * B1[2]);
+      const Real J02 = c2[0], J12 = c2[1], J22 = c2[2];
+      const Real A00 = J11 * J22 - J12 * J21, A01 = J02 * J21 - J01 * J22, A02 = J01 * J12 - J02 * J11;
+      const Real A10 = J12 * J20 - J10 * J22, A11 = J00 * J22 - J02 * J20, A12 = J02 * J10 - J00 * J12;
+      const Real A20 = J10 * J21 - J11 * J20, A21 = J01 * J20 - J00 * J21, A22 = J00 * J11 - J01 * J10;
+      const Real det = J00 * A00 + J01 * A10 + J02 * A20;
+      // flux = w |J| c^2 J^{-1} J^{-T} grad_xi p = w c^2 adj (adj^T g) / det
+      const Real hx = A00 * g0 + A10 * g1 + A20 * g2;
+      const Real hy = A01 * g0 + A11 * g1 + A21 * g2;
+      const Real hz = A02 * g0 + A12 * g1 + A22 * g2;
+      const Real sc = wab * Wq[ic] / det;
+      const int o = el * n3 + (ic * n1 + ib) * n1 + ia;
+      F0[o] = sc * (A00 * hx + A01 * hy + A02 * hz);
+      F1[o] = sc * (A10 * hx + A11 * hy + A12 * hz);
+      f2[ic] = sc * (A20 * hx + A21 * hy + A22 * hz);
     }
-    // cofactors: adj(J) = det(J) J^{-1}
-    const Real A00 = J[1][1] * J[2][2] - J[1][2] * J[2][1], A01 = J[0][2] * J[2][1] - J[0][1] * J[2][2],
-               A02 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
-    const Real A10 = J[1][2] * J[2][0] - J[1][0] * J[2][2], A11 = J[0][0] * J[2][2] - J[0][2] * J[2][0],
-               A12 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
-    const Real A20 = J[1][0] * J[2][1] - J[1][1] * J[2][0], A21 = J[0][1] * J[2][0] - J[0][0] * J[2][1],
-               A22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-    const Real det = J[0][0] * A00 + J[0][1] * A10 + J[0][2] * A20;
-    // grad_x p = J^{-T} grad_xi p = adj^T g / det; flux = w |J| c^2 J^{-1} grad_x p
-    //          = w c^2 adj (adj^T g) / det
-    const Real hx = A00 * g0r + A10 * g1r + A20 * g2r;
-    const Real hy = A01 * g0r + A11 * g1r + A21 * g2r;
-    const Real hz = A02 * g0r + A12 * g1r + A22 * g2r;
-    const Real sc = a.w[ia] * a.w[ib] * a.w[ic] * a.c2 / det;
-    F[es][0][i] = sc * (A00 * hx + A01 * hy + A02 * hz);
-    F[es][1][i] = sc * (A10 * hx + A11 * hy + A12 * hz);
-    F[es][2][i] = sc * (A20 * hx + A21 * hy + A22 * hz);
   }
   __syncthreads();
-  for (int t = tid; t < EPB * n3; t += 256) {
-    const int es = t / n3, i = t - es * n3;
-    const long ge = g0 + es;
-    if (ge >= total) continue;
-    const int ia = i % n1, ib = (i / n1) % n1, ic = i / (n1 * n1);
-    Real r = 0;
+  if (!active) return;
+  // transposed contraction: the test function's reference gradient at each
+  // node; component 2 runs along this thread's own column
+  Real* __restrict__ Y = a.y + (long)s * a.nel * n3;
+  const Real* f0 = F0 + el * n3;
+  const Real* f1 = F1 + el * n3;
+#pragma unroll
+  for (int ic = 0; ic < n1; ++ic) {
+    Real v = 0;
 #pragma unroll
     for (int m = 0; m < n1; ++m) {
-      r += Dm[m * n1 + ia] * F[es][0][m + n1 * (ib + n1 * ic)];
-      r += Dm[m * n1 + ib] * F[es][1][ia + n1 * (m + n1 * ic)];
-      r += Dm[m * n1 + ic] * F[es][2][ia + n1 * (ib + n1 * m)];
+      v += Dm[m * n1 + ia] * f0[(ic * n1 + ib) * n1 + m];
+      v += Dm[m * n1 + ib] * f1[(ic * n1 + m) * n1 + ia];
+      v += Dm[m * n1 + ic] * f2[m];
     }
-    a.y[ge * n3 + i] = r;
+    Y[hex_yidx<N>(a, ex0 + el, ey, ez, ia, ib, ic)] = v;
   }
 }
 
-// Elements along one axis holding node index i (at most two) and the
-// node's local index in each.
+// Elements along one axis holding node index i: element q = i / N at local
+// index r = i - q N when q < ne, and element q - 1 at local index N when
+// r = 0 and q > 0.
+struct HexOwners {
+  int q, r;
+  bool lo, hi;  // element q holds the node; element q - 1 holds it
+};
+
 template <int N>
-__device__ __forceinline__ int hex_owners(int i, int ne, int e[2], int l[2]) {
-  int n = 0;
-  const int q = i / N, r = i - q * N;
-  if (q < ne) { e[n] = q; l[n] = r; ++n; }
-  if (r == 0 && q > 0) { e[n] = q - 1; l[n] = N; ++n; }
-  return n;
+__device__ __forceinline__ HexOwners hex_owners(int i, int ne) {
+  HexOwners o;
+  o.q = i / N;
+  o.r = i - o.q * N;
+  o.lo = o.q < ne;
+  o.hi = o.r == 0 && o.q > 0;
+  return o;
 }
 
 template <typename Real, int N, bool INCR>
@@ -145,18 +199,28 @@ __global__ void __launch_bounds__(256) k_hex_node(const HexArgs<Real> a) {
   const long jk = node / a.d.px;
   const int j = (int)(jk % a.d.nn[1]), k = (int)(jk / a.d.nn[1]);
   if (i >= a.d.nn[0]) return;  // row padding
-  int ex[2], lx[2], ey[2], ly[2], ez[2], lz[2];
-  const int cx = hex_owners<N>(i, a.ne[0], ex, lx);
-  const int cy = hex_owners<N>(j, a.ne[1], ey, ly);
-  const int cz = hex_owners<N>(k, a.ne[2], ez, lz);
+  const HexOwners ox = hex_owners<N>(i, a.ne[0]), oy = hex_owners<N>(j, a.ne[1]), oz = hex_owners<N>(k, a.ne[2]);
   const Real* __restrict__ Y = a.y + (long)s * a.nel * n3;
+  // the residual of (ex, ey, ez) at local (la, lb, lc) sits at
+  // ((ez ne1 + ey) n1 + lc) n1 + lb) rows of ne0 n1 entries, then ex n1 + la
+  const long rowlen = (long)a.ne[0] * n1;
   Real kp = 0;
-  for (int z = 0; z < cz; ++z)
-    for (int yy = 0; yy < cy; ++yy)
-      for (int x = 0; x < cx; ++x) {
-        const long e = ex[x] + (long)a.ne[0] * (ey[yy] + (long)a.ne[1] * ez[z]);
-        kp += Y[e * n3 + lx[x] + n1 * (ly[yy] + n1 * lz[z])];
+#pragma unroll
+  for (int z = 0; z < 2; ++z) {
+    if (!(z ? oz.hi : oz.lo)) continue;
+    const int ez = oz.q - z, lc = z ? N : oz.r;
+#pragma unroll
+    for (int yy = 0; yy < 2; ++yy) {
+      if (!(yy ? oy.hi : oy.lo)) continue;
+      const int ey = oy.q - yy, lb = yy ? N : oy.r;
+      const Real* row = Y + ((((long)ez * a.ne[1] + ey) * n1 + lc) * n1 + lb) * rowlen;
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        if (!(x ? ox.hi : ox.lo)) continue;
+        kp += row[(long)(ox.q - x) * n1 + (x ? N : ox.r)];
       }
+    }
+  }
   const long cnt = *a.counter;
   const int cur = (int)(cnt % a.d.nbuf), nxt = (int)((cnt + 1) % a.d.nbuf);
   const long o = (long)s * per + node;
@@ -178,6 +242,8 @@ __global__ void __launch_bounds__(256) k_hex_node(const HexArgs<Real> a) {
 
 template <typename Real, int N>
 static hipError_t hex_launch_n(const HexArgs<Real>& a, bool incr, hipStream_t st) {
+  const long strips = (long)(a.ne[0] + hex_sx<N>() - 1) / hex_sx<N>() * a.ne[1] * a.ne[2] * a.S;
+  if (strips != a.eblocks) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_hex_elem<Real, N>), dim3(a.eblocks), dim3(256), 0, st, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -193,14 +259,14 @@ static hipError_t hex_launch_n(const HexArgs<Real>& a, bool incr, hipStream_t st
 template <typename Real>
 int hex_elems_per_block(int N) {
   switch (N) {
-    case 1: return hex_epb<1>();
-    case 2: return hex_epb<2>();
-    case 3: return hex_epb<3>();
-    case 4: return hex_epb<4>();
-    case 5: return hex_epb<5>();
-    case 6: return hex_epb<6>();
-    case 7: return hex_epb<7>();
-    case 8: return hex_epb<8>();
+    case 1: return hex_sx<1>();
+    case 2: return hex_sx<2>();
+    case 3: return hex_sx<3>();
+    case 4: return hex_sx<4>();
+    case 5: return hex_sx<5>();
+    case 6: return hex_sx<6>();
+    case 7: return hex_sx<7>();
+    case 8: return hex_sx<8>();
   }
   return 0;
 }

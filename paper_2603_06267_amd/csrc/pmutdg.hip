@@ -1154,8 +1154,9 @@ static HexArgs<Real> hex_args(pmdg_solver* s, int d) {
   a.S = s->S;
   for (int k = 0; k < 3; ++k) a.ne[k] = B.ne[k];
   a.nel = B.ne[0] * B.ne[1] * B.ne[2];
-  const int epb = hex_elems_per_block<Real>(B.N);
-  a.eblocks = (int)(((long)s->S * a.nel + epb - 1) / epb);
+  // one workgroup per strip of sx elements along x, per element row and scenario
+  const int sx = hex_elems_per_block<Real>(B.N);
+  a.eblocks = (int)((long)(B.ne[0] + sx - 1) / sx * B.ne[1] * B.ne[2] * s->S);
   a.dt2 = (Real)(s->dt * s->dt);
   a.c2 = (Real)(B.c * B.c);
   a.counter = dptr<long>(s, "ctl");

@@ -201,13 +201,13 @@ struct HexArgs {
   int S;
   int ne[3];
   int nel;                  // ne0 ne1 ne2
-  int eblocks;              // workgroups of the element kernel
+  int eblocks;              // workgroups of the element kernel (one per strip of elements along x)
   Real dt2, c2;
   const long* counter;
   const Real* force;        // PMUT face force [S][plane] on the bottom plane, or null
   const Real* minv;         // [pnodes] inverse assembled lumped mass
   const Real* vert;         // [nel][24] corner offsets from corner 0 (corner c = cx + 2 cy + 4 cz)
-  Real* y;                  // [S][nel][(N+1)^3] element residuals
+  Real* y;                  // [S][nel (N+1)^3] element residuals, x-contiguous rows
   Real w[kMaxOrder + 1];    // GLL weights
   Real xg[kMaxOrder + 1];   // GLL nodes
   Real D[(kMaxOrder + 1) * (kMaxOrder + 1)];  // D[q][m] = l_m'(x_q)

@@ -327,7 +327,7 @@ def mapped_cube(kind="conforming", N=4, ne=(4, 4, 4), steps=400, seed=0):
     return dict(wl, name=f"cube-{kind}-{ne[0]}x{ne[1]}x{ne[2]}N{N}-1pmut", domains=[dom], steps=steps)
 
 
-def mapped_array(steps=300):
+def mapped_array(steps=1000):
     """The large array's PMUT brick on its own, meshed so that element edges
     follow every disc: 32x32 = 1024 discs (r = 0.433 mm) at 1 mm pitch,
     10 modes each, 128x128x8 trilinear hexahedra of order N = 4 over

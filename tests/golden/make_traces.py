@@ -9,7 +9,10 @@ tests/golden/config<N>_traces.npz:
   degrees, 64 receivers), 5,000 steps; about two hours on seven host cores;
 - config 4 (batched workload): scenario 0 of the cube with a 4x4 PMUT array
   and the highest-order uneven mesh (24x24x8 hexes, N = 6), 512 steps each,
-  as config4base_traces.npz and config4mesh15_traces.npz.
+  as config4base_traces.npz and config4mesh15_traces.npz;
+- mapped: the large array's PMUT brick meshed by trilinear hexahedra whose
+  edges follow every disc (128x128x8 hexes, N = 4, 1024 PMUTs), 1,000
+  steps, as configmapped_traces.npz; about ten minutes on eight cores.
 
 Only the oracle (oracle/ref.py, oracle/pmdg_ref.c) and the seeded input
 generators (paper_2603_06267_amd/workloads.py) are used.  The run is the time
@@ -17,7 +20,7 @@ loop of Algorithm 1 in its synchronised reading, Sec. 3.1.  It is done in
 chunks; with --ckpt-dir each chunk is followed by a checkpoint of the whole
 oracle state there, so an interrupted run resumes where it stopped.
 
-    python tests/golden/make_traces.py --config 3 [--steps 5000] [--chunk 250]
+    python tests/golden/make_traces.py --config {1,2,3,4,mapped} [--steps 5000] [--chunk 250]
         [--ckpt-dir DIR]
 
 Each stored file holds the traces [R x steps] (trace column n is time
@@ -39,7 +42,7 @@ if ROOT not in sys.path:
 from oracle import ref  # noqa: E402
 from paper_2603_06267_amd import workloads as W  # noqa: E402
 
-STEPS = {1: 1000, 2: 2000, 3: 5000, 4: 512}
+STEPS = {"1": 1000, "2": 2000, "3": 5000, "4": 512, "mapped": 1000}
 
 
 def golden_path(config):
@@ -81,19 +84,21 @@ def run(wl, steps, chunk, ckpt, tag):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--config", type=int, choices=(1, 2, 3, 4), default=3)
+    ap.add_argument("--config", choices=tuple(STEPS), default="3")
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--chunk", type=int, default=250)
     ap.add_argument("--ckpt-dir", default=None)
     a = ap.parse_args()
     steps = a.steps or STEPS[a.config]
-    if a.config == 4:
+    if a.config == "4":
         # the batched workload: scenario 0 of the 4x4-PMUT cube and the
         # highest-order uneven mesh (24x24x8 hexes, N = 6)
         c4 = W.config4()
         jobs = [("4base", dict(c4["scenarios"], steps=steps)), ("4mesh15", dict(c4["meshes"][15], steps=steps))]
+    elif a.config == "mapped":
+        jobs = [("mapped", W.mapped_array(steps=steps))]
     else:
-        jobs = [(str(a.config), dict(W.CONFIGS[a.config](), steps=steps))]
+        jobs = [(a.config, dict(W.CONFIGS[int(a.config)](), steps=steps))]
     for tag, wl in jobs:
         key = W.workload_key(wl)
         ck = None

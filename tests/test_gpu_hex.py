@@ -133,3 +133,28 @@ def test_brick_as_vertices_and_graph_replay():
         out.append(g.read_traces())
     assert np.array_equal(out[0], out[1])
     assert rel_l2(out[1], a.read_traces()) <= 2e-6
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_mapped_array_traces(precision):
+    """The large array's PMUT brick meshed by trilinear hexahedra whose edges
+    follow every disc (8.68M DOFs, 1024 PMUTs), 1,000 steps with graph
+    replay as the benchmark runs it, against the oracle's stored traces
+    (tests/golden/make_traces.py --config mapped)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "configmapped_traces.npz")
+    if not os.path.exists(path):
+        pytest.skip("oracle traces of the trilinear PMUT brick not generated")
+    z = np.load(path)
+    wl = W.mapped_array(steps=int(z["steps"]))
+    assert str(z["key"]) == W.workload_key(wl), "stored traces belong to another workload"
+    _say(f"mapped array precision={precision}")
+    g = solver.from_workload(wl, precision=precision, shape_fn=W.shape_fn(wl))
+    assert abs(g.dt - float(z["dt"])) <= 1e-14 * g.dt
+    g.step(wl["steps"])
+    tg = g.read_traces()[0]
+    to = z["traces"]
+    err, pr = rel_l2(tg, to), per_receiver_max(tg, to)
+    _say(f"  rel L2 {err:.3e}, per receiver max {pr:.3e}")
+    assert err <= TOL[precision] and pr <= TOL[precision]
+    g.close()
