@@ -190,7 +190,8 @@ pmdg_status pmdg_set_vertices(pmdg_solver* h, int dom, const double* V);
  * (axis + 1) mod 3.  Writes elem[nf nq^2] (coarse index, or -1),
  * xi[nf nq^2][3] (reference point in that element, 0 if unmatched) and
  * *unmatched (the count of -1 entries).  Every array is device memory; the
- * call enqueues two kernels on stream and returns (no allocation, no wait).
+ * call enqueues two kernels on stream and returns (no allocation, no wait;
+ * *unmatched is cleared by the first).
  * Faces with an index outside 0..5 match nothing.  EINVAL: nq outside
  * 1..9, negative counts, tol <= 0, eps < 0, NULL arrays. */
 pmdg_status pmdg_match_faces(int nq, int nf, const double* fine_hex, const int* fine_face, int nc,

@@ -557,7 +557,8 @@ int pmdg_ref_match_faces(int nq, int nf, const double *fine_hex, const int *fine
             dv += (cv[3 * c + k] - x[k]) * (cv[3 * c + k] - x[k]);
           }
           double rad = (cd[c] > df ? cd[c] : df) + eps;
-          if (!(sqrt(sn) < tol && sqrt(dv) < rad)) continue;
+          /* |n+ + n-| < tol and |V - x_q| < r, compared as squares */
+          if (!(sn < tol * tol && dv < rad * rad)) continue;
           double W8[8][3], t[3];
           memcpy(W8, coarse_hex + 24L * c, sizeof(W8));
           if (tri_inverse(W8, x, t)) continue;

@@ -8,9 +8,10 @@
 // the coarse element's corners.  A coarse face is a candidate when |n+ + n-| < tol and its first
 // corner lies within r = max(diam F-, diam F+) + eps of x_q; the first
 // candidate whose element's inverse map (Newton, in coordinates relative to
-// its first corner) puts x_q inside [-1, 1]^3 up to 1e-10 is the match.  A
-// second launch counts the points left unmatched.  FP64 throughout; nothing
-// is allocated.
+// its first corner) puts x_q inside [-1, 1]^3 up to 1e-10 is the match.
+// The unmatched points are counted by one atomic per wave into a counter
+// that a one-thread launch clears first.  FP64 throughout; nothing is
+// allocated.
 #include "pmutdg_internal.h"
 
 namespace pmdg {
@@ -158,7 +159,8 @@ __global__ void __launch_bounds__(kMatchThreads) k_match(const MatchArgs a) {
       const double s0 = nf[0] + cn[t][0], s1 = nf[1] + cn[t][1], s2 = nf[2] + cn[t][2];
       const double e0 = cv[t][0] - x[0], e1 = cv[t][1] - x[1], e2 = cv[t][2] - x[2];
       const double rad = (cd[t] > df ? cd[t] : df) + a.eps;
-      if (!(sqrt(s0 * s0 + s1 * s1 + s2 * s2) < a.tol && sqrt(e0 * e0 + e1 * e1 + e2 * e2) < rad)) continue;
+      // |n+ + n-| < tol and |V - x_q| < r, compared as squares
+      if (!(s0 * s0 + s1 * s1 + s2 * s2 < a.tol * a.tol && e0 * e0 + e1 * e1 + e2 * e2 < rad * rad)) continue;
       double t3[3];
       if (!tri_inverse_d(a.coarse_hex + (long)(c0 + t) * 24, x, t3)) continue;
       if (fabs(t3[0]) <= 1 + 1e-10 && fabs(t3[1]) <= 1 + 1e-10 && fabs(t3[2]) <= 1 + 1e-10) {
@@ -177,33 +179,24 @@ __global__ void __launch_bounds__(kMatchThreads) k_match(const MatchArgs a) {
     a.xi[3 * q + 1] = fxi[1];
     a.xi[3 * q + 2] = fxi[2];
   }
+  // unmatched points: one integer atomic per wave (an exact sum in any order)
+  const unsigned long long miss = __ballot(live && found < 0);
+  if ((tid & 63) == 0 && miss) atomicAdd(a.unmatched, (int)__popcll(miss));
 }
 
-// One workgroup counts the unmatched points (fixed order, no atomics).
-__global__ void __launch_bounds__(256) k_match_count(const int* __restrict__ elem, long npts, int* out) {
-  __shared__ int part[256];
-  int c = 0;
-  for (long i = threadIdx.x; i < npts; i += 256) c += elem[i] < 0 ? 1 : 0;
-  part[threadIdx.x] = c;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *out = part[0];
+__global__ void k_match_zero(int* out) {
+  if (threadIdx.x == 0) *out = 0;
 }
 
 }  // namespace
 
 hipError_t launch_match(const MatchArgs& a, hipStream_t st) {
   const long npts = (long)a.nf * a.nq * a.nq;
-  if (npts > 0) {
-    hipLaunchKernelGGL(k_match, dim3((unsigned)((npts + kMatchThreads - 1) / kMatchThreads)), dim3(kMatchThreads), 0,
-                       st, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(k_match_count, dim3(1), dim3(256), 0, st, a.elem, npts, a.unmatched);
+  hipLaunchKernelGGL(k_match_zero, dim3(1), dim3(64), 0, st, a.unmatched);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || npts == 0) return e;
+  hipLaunchKernelGGL(k_match, dim3((unsigned)((npts + kMatchThreads - 1) / kMatchThreads)), dim3(kMatchThreads), 0, st,
+                     a);
   return hipGetLastError();
 }
 
