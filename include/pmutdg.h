@@ -4,8 +4,9 @@
  *
  * One step advances, on the GPU:
  *   - the matrix-free stiffness action of the continuous GLL spectral
- *     elements inside each of (up to) two axis-aligned bricks (Sec. 3,
- *     bilinear form a, eq. Wf_2, volume sum),
+ *     elements inside each of (up to) two axis-aligned bricks, or inside one
+ *     brick of trilinear hexahedra (Sec. 3, bilinear form a, eq. Wf_2,
+ *     volume sum; maps X_K),
  *   - the symmetric interior-penalty terms across the non-conforming,
  *     mixed-order interface Gamma_I between the bricks (eq. Wf_2, interface
  *     sums; penalty gamma_F; interface quadrature on the finer face, Sec. 5),
@@ -15,6 +16,8 @@
  *     pressure it samples on its face, and the face force it returns
  *     (Sec. 2, eq. pmut_problem; Sec. 3.1, eqs. f_i, g_m, semi_PMUT),
  *   - pressure traces at receiver points.
+ * At setup, pmdg_match_faces runs the face matching of Sec. 5, Algorithm 3,
+ * on the GPU.
  *
  * Conventions
  *   - Every call returns a pmdg_status (0 = OK, negative = error).  No
