@@ -167,6 +167,7 @@ def run_gpu(wl, precision, steps, warmup, graphs, rows, zchunk, tblock=1):
     tr = gg.read_traces()
     finite = bool(np.isfinite(tr).all()) and not gg.nonfinite()
     run_gpu.traces = tr
+    run_gpu.resident = gg.resident()
     return el, el_graph, kt, finite
 
 
@@ -314,6 +315,44 @@ def matching_leg(repeats=5):
     return out
 
 
+def resident_leg(steps=512):
+    """Many drive scenarios of the batch cube (4x4 PMUTs, 4,913 nodes, N = 4)
+    in one solver: the LDS-resident path (one workgroup per scenario, whole
+    steps per launch) against the tiled path replayed as hipGraphs, for the
+    64 scenarios of the batched workload and the 4,096 of the surrogate's
+    data set; scenarios per second over `steps` steps each, and the trace
+    error of scenario 0 of the 64 against the oracle's stored traces."""
+    import torch
+    from paper_2603_06267_amd import _lib, solver, workloads as W
+    out = {}
+    for name, wl in (("scenarios64", W.config4()["scenarios"]), ("scenarios4096", W.config5()["scenarios"])):
+        S = np.asarray(wl["drive"]["amp"]).shape[0]
+        wl = dict(wl, steps=steps)
+        rates = {}
+        for mode in (1, 0):
+            g = solver.from_workload(wl, precision=32, n_steps=steps + 8, shape_fn=W.shape_fn(wl), device="cuda:0",
+                                     bind=False)
+            g.set_option(_lib.OPT_RESIDENT, mode)
+            g.bind()
+            g.step(8)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.step(steps)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            rates["resident" if mode else "tiled"] = {"scenarios_per_s": S / el, "ms_per_step": el * 1e3 / steps,
+                                                      "path_resident": g.resident()}
+            if mode and name == "scenarios64":
+                to = golden_traces("4base", dict(W.config4()["scenarios"], steps=512))
+                rates["resident"]["trace_error"] = trace_error(g.read_traces()[0], to)
+            g.close()
+        rates["scenarios"] = S
+        rates["unique_dofs"] = W.unique_dofs(wl)
+        rates["speedup"] = rates["resident"]["scenarios_per_s"] / rates["tiled"]["scenarios_per_s"]
+        out[name] = rates
+    return out
+
+
 def small_configs_leg(steps=400, warmup=20):
     """DOF-updates/s of the small workloads (the config-1 cube and the
     config-2 two-domain array), FP32 and FP64, hipGraph replay: latency-bound
@@ -325,9 +364,11 @@ def small_configs_leg(steps=400, warmup=20):
         dofs = W.unique_dofs(wl)
         to = golden_traces(cfg, wl)
         for prec in (32, 64):
-            el, el_graph, kt, finite = run_gpu(wl, prec, steps, warmup, True, 2, -1)  # automatic z chunks
+            # automatic tiles; config 1 in FP32 fits the LDS-resident path
+            el, el_graph, kt, finite = run_gpu(wl, prec, steps, warmup, True, 0, -1)
             out[f"{name}_fp{prec}"] = {"unique_dofs": dofs, "value": dofs * steps / min(el, el_graph),
                                        "ms_per_step": min(el, el_graph) * 1e3 / steps, "finite": finite,
+                                       "resident": run_gpu.resident,
                                        "trace_error": trace_error(run_gpu.traces[0], to)}
     return out
 
@@ -605,6 +646,8 @@ def main():
     if not args.no_small:
         log("small workloads ...")
         out["small"] = small_configs_leg()
+        log("LDS-resident scenarios ...")
+        out["resident"] = resident_leg()
     if not args.no_batched:
         log("batched form ...")
         out["batched"] = batched_leg()

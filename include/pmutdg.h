@@ -333,6 +333,19 @@ pmdg_status pmdg_set_option(pmdg_solver* h, int option, long value);
  * (default), 3 or 4.  Distances above 2 apply to bricks of order <= 4 with
  * 4-wave tiles of 1 or 2 rows; other bricks keep 2.  Same results. */
 #define PMDG_OPT_PREFETCH 12
+/* LDS-resident steps (1 = automatic, the default; 0 = never).  A
+ * single-brick FP32 solver without absorbing faces, layers or trilinear
+ * vertices, with every tile option at its default, whose pressure,
+ * increment, face force and PMUT tables fit one workgroup's LDS,
+ * runs pmdg_step as launches of up to 2,048 whole steps each, one 1024-thread
+ * workgroup per scenario (stiffness and update, PMUT sampling, modal ODE and
+ * force, receivers), without graphs.  The arithmetic per node is the same as
+ * the tiled path's; PMUT and receiver sums are taken in another order. */
+#define PMDG_OPT_RESIDENT 13
+
+/* *on = 1 when pmdg_step on this bound solver takes the LDS-resident path
+ * (PMDG_OPT_RESIDENT), else 0. */
+pmdg_status pmdg_resident(pmdg_solver* h, int* on);
 pmdg_status pmdg_kernel_times(pmdg_solver* h, double* ms3);
 
 /* Frees host resources (device memory is the caller's).  NULL is a no-op. */

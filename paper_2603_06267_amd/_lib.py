@@ -28,6 +28,7 @@ OPT_TIME_BLOCK = 9
 OPT_OVERLAP = 10
 OPT_TIME_BLOCK_SECONDARY = 11
 OPT_PREFETCH = 12
+OPT_RESIDENT = 13
 
 ERRNAMES = {PMDG_EINVAL: "EINVAL", PMDG_ENOMEM: "ENOMEM", PMDG_EHIP: "EHIP",
             PMDG_EUNSTABLE: "EUNSTABLE", PMDG_ESTATE: "ESTATE"}
@@ -75,6 +76,7 @@ _SIGS = {
     "pmdg_lambda_max": [_vp, _dp],
     "pmdg_step": [_vp, ctypes.c_int, _vp],
     "pmdg_steps_done": [_vp, ctypes.POINTER(ctypes.c_long)],
+    "pmdg_resident": [_vp, ctypes.POINTER(ctypes.c_int)],
     "pmdg_read_traces": [_vp, _dp, _vp],
     "pmdg_read_traces_device": [_vp, _vp, ctypes.c_int, _vp],
     "pmdg_read_modal": [_vp, ctypes.c_int, _dp, _dp, _dp, _vp],

@@ -9,7 +9,7 @@ LIB = os.path.join(HERE, "libpmutdg.so")
 SOURCES = ["pmutdg.hip", "pmutdg_kernels.hip", "stiff_f32_lo.hip", "stiff_f32_hi.hip", "stiff_f64_lo.hip",
            "stiff_f64_hi.hip", "batch.hip", "mlp.hip",
            "stiff2_lo.hip", "pml_kernels.hip", "hex_kernels.hip",
-           "match_kernels.hip"]
+           "match_kernels.hip", "resident_kernels.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

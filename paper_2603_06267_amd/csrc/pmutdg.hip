@@ -216,6 +216,7 @@ struct pmdg_solver {
   int tblock = 1;               // steps per stiffness pass of the primary (1, or 2 for FP32)
   int tblock1 = 0;              // same for the secondary (0: as the primary)
   int overlap = 0;              // PMUT face work alongside the secondary's stiffness
+  int resident = 1;             // small single-brick FP32 solvers: whole steps with p in LDS (0: never)
   int batches = 0;              // batches holding this solver (their tile layout is fixed)
   int static_dev = -1;          // device whose library-held workspace this solver is bound to, or -1
   std::map<int, hipGraphExec_t> graphs;
@@ -1300,8 +1301,100 @@ static pmdg_status prime(pmdg_solver* s, hipStream_t st) {
 }
 
 // n steps: pairs of two-step passes where enabled, single steps otherwise
+// The LDS-resident path (one workgroup per scenario, whole steps per
+// launch): single-brick FP32 solvers without absorbing faces, layers or
+// trilinear vertices, with the default tile options, whose pressure, increment,
+// face force and PMUT tables fit one workgroup's LDS.
+static bool resident_args(pmdg_solver* s, ResidentArgs* out) {
+  if (!s->resident || s->ndom != 1 || s->prec != 32) return false;
+  const Brick& B = s->b[0];
+  if (B.absorbing || B.pml || B.mapped()) return false;
+  if (s->rows != 0 || s->zchunk != -1 || s->waves != 4 || s->depth != 2 || s->tblock != 1 || s->overlap != 0)
+    return false;
+  if (s->Nm > kMaxModes || B.nnodes > resident_max_nodes() || B.pnodes > (1L << 30)) return false;
+  ResidentArgs a;
+  memset(&a, 0, sizeof(a));
+  const int NT = 2 * B.N, NC = B.N + 3;
+  const long nc = B.nnodes, nface = (long)s->pm_node.size();
+  auto al = [](long v) { return (v + 15) / 16 * 16; };
+  long off = al(2 * 4 * nc);
+  a.off_force = (int)off;
+  off = al(off + 4L * B.nn[0] * B.nn[1]);
+  a.off_taps = (int)off;
+  off = al(off + 4L * 3 * NC * NT);
+  a.off_mins = (int)off;
+  off = al(off + 4L * 3 * NC);
+  a.off_B = (int)off;
+  off = al(off + 8L * nface * s->Nm);
+  a.off_fn = (int)off;
+  off = al(off + 4L * nface);
+  a.off_q = (int)off;
+  off += 8L * 3 * s->Np * s->Nm;
+  int dev = 0, lim = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return false;
+  if (off > lim) return false;
+  a.lds_bytes = (int)off;
+  a.d = view<float>(s, 0);
+  a.S = s->S;
+  a.nc = (int)nc;
+  a.inv_nn0 = 1.0f / B.nn[0];
+  a.inv_nn1 = 1.0f / B.nn[1];
+  a.counter = dptr<long>(s, "ctl");
+  a.dt2 = (float)(s->dt * s->dt);
+  a.taps = dptr<float>(s, "d0.taps");
+  a.mins = dptr<float>(s, "d0.mins");
+  a.nonfinite = (int*)(dptr<char>(s, "ctl") + 16);
+  FaceArgs<float> f = face_args<float>(s, 0);
+  a.force = s->Np > 0 ? dptr<float>(s, "force") : nullptr;
+  a.Np = s->Np;
+  a.Nm = s->Nm;
+  a.nface = (int)nface;
+  a.pm_off = f.pm_off;
+  a.pm_node = f.pm_node;
+  a.pm_B = f.pm_B;
+  a.omega = f.omega;
+  a.zeta = f.zeta;
+  a.eta = f.eta;
+  a.kappa = f.kappa;
+  a.dt = f.dt;
+  a.dA = f.dA;
+  a.car = f.car;
+  a.ncar = f.ncar;
+  a.t_switch = f.t_switch;
+  a.cap = f.cap;
+  a.q = f.q;
+  a.qd = f.qd;
+  a.qdd = f.qdd;
+  a.R = s->R;
+  a.r_base = f.r_base;
+  a.r_w = f.r_w;
+  a.traces = f.traces;
+  a.tcap = f.tcap;
+  *out = a;
+  return true;
+}
+
+static pmdg_status enqueue_resident(pmdg_solver* s, const ResidentArgs& base, hipStream_t st, int n, Timer* tm) {
+  for (int i = 0; i < n;) {
+    ResidentArgs a = base;
+    a.nsteps = std::min(n - i, 2048);
+    if (tm) HIPCHK(tm->begin(0, st));
+    HIPCHK(launch_resident(a, st));
+    HIPCHK(launch_tick_n(const_cast<long*>(a.counter), a.nsteps, st));
+    if (tm) HIPCHK(tm->end(st));
+    i += a.nsteps;
+  }
+  return PMDG_OK;
+}
+
 static pmdg_status enqueue(pmdg_solver* s, hipStream_t st, int n, Timer* tm) {
   pmdg_status r = PMDG_OK;
+  {
+    ResidentArgs ra;
+    if (resident_args(s, &ra)) return enqueue_resident(s, ra, st, n, tm);
+  }
   int i = 0;
   if (two_step_any(s))
     for (; i + 1 < n && !r; i += 2) r = enqueue_pair(s, st, tm);
@@ -2386,6 +2479,10 @@ pmdg_status pmdg_set_option(pmdg_solver* s, int option, long value) {
       s->graph_chunk = (int)value;
       break;
     case PMDG_OPT_TIMING: s->timing = value ? 1 : 0; break;
+    case PMDG_OPT_RESIDENT:
+      if (!(value == 0 || value == 1)) return fail(PMDG_EINVAL, "resident mode must be 0 (never) or 1 (automatic)");
+      s->resident = (int)value;
+      break;
     default: return fail(PMDG_EINVAL, "unknown option");
   }
   drop_graphs(s);
@@ -2419,7 +2516,9 @@ pmdg_status pmdg_step(pmdg_solver* s, int n, void* stream) {
     s->steps_done += n;
     return PMDG_OK;
   }
-  if (!s->use_graph) {
+  ResidentArgs ra;
+  if (!s->use_graph || resident_args(s, &ra)) {
+    // (the LDS-resident path runs many steps per launch: no graphs needed)
     pmdg_status r = enqueue(s, st, n, nullptr);
     if (r) return r;
     s->steps_done += n;
@@ -2450,6 +2549,14 @@ pmdg_status pmdg_step(pmdg_solver* s, int n, void* stream) {
     left -= len;
   }
   s->steps_done += n;
+  return PMDG_OK;
+}
+
+pmdg_status pmdg_resident(pmdg_solver* s, int* on) {
+  if (!s || !on) return fail(PMDG_EINVAL, "NULL argument");
+  if (!s->bound) return fail(PMDG_ESTATE, "not bound");
+  ResidentArgs ra;
+  *on = resident_args(s, &ra) ? 1 : 0;
   return PMDG_OK;
 }
 

@@ -234,6 +234,50 @@ struct MatchArgs {
 };
 hipError_t launch_match(const MatchArgs& a, hipStream_t st);
 
+// A single-brick FP32 solver small enough to keep its pressure in LDS:
+// one workgroup per scenario runs many whole steps (stiffness and update,
+// PMUT sampling, modal ODE and force, receivers) in one launch.
+struct ResidentArgs {
+  DomView<float> d;
+  int S, nsteps;
+  int nc;                   // nodes (compact)
+  float inv_nn0, inv_nn1;   // 1 / nn[0], 1 / nn[1] (index decomposition)
+  const long* counter;
+  float dt2;
+  const float* taps;        // [3][N+3][2N]
+  const float* mins;        // [3][N+3]
+  float* force;             // [S][plane] PMUT face force on the bottom plane, or null
+  int* nonfinite;
+  // PMUTs
+  int Np, Nm, nface;
+  const int* pm_off;        // [Np+1]
+  const int* pm_node;       // padded bottom-face index
+  const double* pm_B;       // [nface][Nm]
+  const double* omega;
+  const double* zeta;
+  const double* eta;
+  double kappa, dt;
+  const double* dA;         // [S*Np][2]
+  const double* car;        // [S][ncar][2]
+  long ncar;
+  double t_switch, cap;
+  double* q;                // [S*Np*Nm]
+  double* qd;
+  double* qdd;
+  // receivers
+  int R;
+  const long* r_base;       // padded index of the element's first node
+  const double* r_w;        // [R][3][kMaxOrder+1]
+  double* traces;           // [S][R][tcap]
+  long tcap;
+  // dynamic LDS layout (bytes)
+  int off_force, off_taps, off_mins, off_B, off_fn, off_q;
+  int lds_bytes;
+};
+hipError_t launch_resident(const ResidentArgs& a, hipStream_t st);
+int resident_max_nodes();
+hipError_t launch_tick_n(long* counter, long n, hipStream_t st);
+
 // Launchers (defined in pmutdg_kernels.hip).
 template <typename Real>
 hipError_t launch_stiff(const StiffArgs<Real>& a, bool incr, hipStream_t st);

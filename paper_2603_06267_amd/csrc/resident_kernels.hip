@@ -1,0 +1,270 @@
+// Steps of a small single-brick FP32 solver with the pressure held in LDS.
+//
+// One workgroup (1024 threads) per scenario keeps p on every node in LDS
+// together with the increment X = p^n - p^{n-1}, and runs whole steps (Sec. 3.1, Algorithm 1 in its synchronised
+// reading) back to back inside one launch:
+//   1. stiffness and update at every node: the difference-form Kronecker
+//      stencil of the tiled kernel, in the same operation order, and the
+//      PMUT face force on the bottom plane; X += a is formed from p^n for
+//      every node first, then p += X in place after a barrier;
+//   2. PMUT sampling of p^{n+1} (FP64), the modal Newmark update with its
+//      drive (or the receive-mode feedback), and the new face force, one
+//      wave per PMUT (Sec. 2, eq. pmut_problem; Sec. 3.1, eqs. f_i, g_m);
+//   3. receiver traces of p^{n+1} (FP64), one wave per receiver.
+// HBM is touched only to read the state at the start, to write the traces
+// of each step and to write the state back at the end.  A one-thread launch
+// then advances the device step counter by the number of steps.
+#include "pmutdg_internal.h"
+
+namespace pmdg {
+
+namespace {
+
+constexpr int kResThreads = 1024;
+constexpr int kResMaxPer = 32;  // nodes per thread (the LDS bound comes first)
+
+template <int N>
+__device__ __forceinline__ int res_class(int i, int n) {
+  return i == 0 ? N : (i == n - 1 ? N + 1 : i % N);
+}
+
+// floor(n / d) for 0 <= n < 2^20 from a float reciprocal, corrected by one
+__device__ __forceinline__ int res_div(int n, int d, float inv) {
+  int q = (int)((float)n * inv);
+  const int r = n - q * d;
+  if (r < 0) --q;
+  else if (r >= d) ++q;
+  return q;
+}
+
+__device__ __forceinline__ double res_wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int N, int MM>
+__global__ void __launch_bounds__(kResThreads) k_resident(const ResidentArgs a) {
+  constexpr int NT = 2 * N, NC = N + 3, n1 = N + 1;
+  extern __shared__ __align__(16) unsigned char lds[];
+  float* P = reinterpret_cast<float*>(lds);
+  float* XS = P + a.nc;
+  float* FZ = reinterpret_cast<float*>(lds + a.off_force);
+  float* TP = reinterpret_cast<float*>(lds + a.off_taps);
+  float* MI = reinterpret_cast<float*>(lds + a.off_mins);
+  double* BB = reinterpret_cast<double*>(lds + a.off_B);
+  int* FN = reinterpret_cast<int*>(lds + a.off_fn);
+  double* QS = reinterpret_cast<double*>(lds + a.off_q);  // q, qd, qdd: [3][Np Nm]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int s = blockIdx.x;
+  const int nx = a.d.nn[0], ny = a.d.nn[1], nz = a.d.nn[2], nc = a.nc, px = a.d.px;
+  const long cnt0 = *a.counter;
+  const float* Pg = a.d.P[(int)(cnt0 % 3)] + (long)s * a.d.nnodes;
+  float* Xg = a.d.X + (long)(*a.d.xsel) * a.d.xstride + (long)s * a.d.nnodes;
+  const int nfz = nx * ny, Nm = a.Nm, npm = a.Np * Nm;
+
+  for (int n = tid; n < nc; n += kResThreads) {
+    const int jk = res_div(n, nx, a.inv_nn0), i = n - jk * nx;
+    const int k = res_div(jk, ny, a.inv_nn1), j = jk - k * ny;
+    const long g = i + (long)px * (j + (long)ny * k);
+    P[n] = Pg[g];
+    XS[n] = Xg[g];
+  }
+  for (int f = tid; f < nfz; f += kResThreads) {
+    const int j = res_div(f, nx, a.inv_nn0), i = f - j * nx;
+    FZ[f] = a.force ? a.force[(long)s * a.d.plane + i + (long)px * j] : 0.f;
+  }
+  for (int t = tid; t < 3 * NC * NT; t += kResThreads) TP[t] = a.taps[t];
+  for (int t = tid; t < 3 * NC; t += kResThreads) MI[t] = a.mins[t];
+  for (int t = tid; t < a.nface * Nm; t += kResThreads) BB[t] = a.pm_B[t];
+  for (int t = tid; t < a.nface; t += kResThreads) {
+    const int f = a.pm_node[t];
+    FN[t] = f % px + nx * (f / px);
+  }
+  for (int t = tid; t < npm; t += kResThreads) {
+    const long o = (long)s * npm + t;
+    QS[t] = a.q[o];
+    QS[npm + t] = a.qd[o];
+    QS[2 * npm + t] = a.qdd[o];
+  }
+  __syncthreads();
+
+  const double dt = a.dt;
+  for (int st = 0; st < a.nsteps; ++st) {
+    const long cnt = cnt0 + st;
+    // (1) stiffness and update: X += a from p^n at every node, then p += X
+    for (int n = tid; n < nc; n += kResThreads) {
+      {
+        const int jk = res_div(n, nx, a.inv_nn0), i = n - jk * nx;
+        const int k = res_div(jk, ny, a.inv_nn1), j = jk - k * ny;
+        const int cx = res_class<N>(i, nx), cy = res_class<N>(j, ny), cz = res_class<N>(k, nz);
+        const float* tx = TP + cx * NT;
+        const float* ty = TP + (NC + cy) * NT;
+        const float* tz = TP + (2 * NC + cz) * NT;
+        const float p0 = P[n];
+        const int sy = nx, sz = nx * ny;
+        float ac = 0.f;
+#pragma unroll
+        for (int t = 0; t < N; ++t) {
+          // neighbours outside the brick carry zero taps and read as zero
+          const float xa = i - N + t >= 0 ? P[n - N + t] : 0.f;
+          const float xb = i + 1 + t < nx ? P[n + 1 + t] : 0.f;
+          const float ya = j - N + t >= 0 ? P[n + (t - N) * sy] : 0.f;
+          const float yb = j + 1 + t < ny ? P[n + (1 + t) * sy] : 0.f;
+          const float za = k - N + t >= 0 ? P[n + (t - N) * sz] : 0.f;
+          const float zb = k + 1 + t < nz ? P[n + (1 + t) * sz] : 0.f;
+          ac += tx[t] * (xa - p0);
+          ac += tx[N + t] * (xb - p0);
+          ac += ty[t] * (ya - p0);
+          ac += ty[N + t] * (yb - p0);
+          ac += tz[t] * (za - p0);
+          ac += tz[N + t] * (zb - p0);
+        }
+        const float minv = MI[cx] * MI[NC + cy] * MI[2 * NC + cz];
+        if (k == 0) ac += a.dt2 * minv * FZ[i + nx * j];
+        XS[n] = XS[n] + ac;
+      }
+    }
+    __syncthreads();
+    for (int n = tid; n < nc; n += kResThreads) P[n] = P[n] + XS[n];
+    __syncthreads();
+    // (2) PMUTs: sample p^{n+1}, modal update, face force
+    const long lev = cnt + 1;
+    const bool driven = !(lev * dt > a.t_switch);
+    for (int k = wave; k < a.Np; k += kResThreads / 64) {
+      const int f0 = a.pm_off[k], f1 = a.pm_off[k + 1], po = k * Nm;
+      double g[MM];
+#pragma unroll
+      for (int m = 0; m < MM; ++m) g[m] = 0.0;
+      bool bad = false;
+      for (int f = f0 + lane; f < f1; f += 64) {
+        const double p = (double)P[FN[f]];
+        bad |= !__builtin_isfinite(p);
+#pragma unroll
+        for (int m = 0; m < MM; ++m)
+          if (m < Nm) g[m] += BB[f * Nm + m] * p;
+      }
+      if (bad) atomicOr(a.nonfinite, 1);
+#pragma unroll
+      for (int m = 0; m < MM; ++m)
+        if (m < Nm) g[m] = res_wave_sum(g[m]);
+      double qp = 0.0, qds = 0.0;
+      if (lane < Nm) {
+        const double q = QS[po + lane], qd = QS[npm + po + lane], qdd = QS[2 * npm + po + lane];
+        qp = q + dt * qd + 0.5 * dt * dt * qdd;
+        qds = qd + 0.5 * dt * qdd;
+      }
+      double phi;
+      if (driven) {
+        const double* c2 = a.car + ((long)s * a.ncar + min(lev, a.ncar - 1)) * 2;
+        const double* d2 = a.dA + ((long)s * a.Np + k) * 2;
+        phi = d2[0] * c2[0] - d2[1] * c2[1];
+      } else {
+        phi = res_wave_sum(lane < Nm ? a.eta[po + lane] * qp : 0.0) / a.cap;
+      }
+      double qa = 0.0;
+      if (lane < Nm) {
+        double gm = 0.0;
+#pragma unroll
+        for (int m = 0; m < MM; ++m)
+          if (m == lane) gm = g[m];
+        const double w = a.omega[po + lane], ze = a.zeta[po + lane], et = a.eta[po + lane];
+        qa = -w * w * qp - 2.0 * ze * w * qds + gm + et * phi;
+        QS[po + lane] = qp;
+        QS[npm + po + lane] = qds + 0.5 * dt * qa;
+        QS[2 * npm + po + lane] = qa;
+      }
+      double qm[MM];
+#pragma unroll
+      for (int m = 0; m < MM; ++m) qm[m] = __shfl(qa, m, 64);
+      for (int f = f0 + lane; f < f1; f += 64) {
+        double fv = 0.0;
+#pragma unroll
+        for (int m = 0; m < MM; ++m)
+          if (m < Nm) fv += qm[m] * BB[f * Nm + m];
+        FZ[FN[f]] = (float)(-a.kappa * fv);
+      }
+    }
+    // (3) receivers
+    for (int r = wave; r < a.R; r += kResThreads / 64) {
+      // padded node index of the element's first node (small brick: 32-bit)
+      const int b = (int)a.r_base[r];
+      const int i0 = b % px, jk = b / px;
+      const int j0 = jk % ny, k0 = jk / ny;
+      const int cb = i0 + nx * (j0 + ny * k0);
+      const double* w = a.r_w + (long)r * 3 * (kMaxOrder + 1);
+      double v = 0.0;
+      for (int idx = lane; idx < n1 * n1 * n1; idx += 64) {
+        const int i = idx % n1, j = (idx / n1) % n1, c = idx / (n1 * n1);
+        v += w[i] * w[kMaxOrder + 1 + j] * w[2 * (kMaxOrder + 1) + c] * (double)P[cb + i + nx * (j + ny * c)];
+      }
+      v = res_wave_sum(v);
+      if (lane == 0 && cnt < a.tcap) a.traces[((long)s * a.R + r) * a.tcap + cnt] = v;
+      if (lane == 0 && !__builtin_isfinite(v)) atomicOr(a.nonfinite, 1);
+    }
+    __syncthreads();
+  }
+
+  // state out: the level cnt0 + nsteps, its increment, the face force and
+  // the modal state
+  float* PgE = a.d.P[(int)((cnt0 + a.nsteps) % 3)] + (long)s * a.d.nnodes;
+  for (int n = tid; n < nc; n += kResThreads) {
+    const int jk = res_div(n, nx, a.inv_nn0), i = n - jk * nx;
+    const int k = res_div(jk, ny, a.inv_nn1), j = jk - k * ny;
+    const long g = i + (long)px * (j + (long)ny * k);
+    PgE[g] = P[n];
+    Xg[g] = XS[n];
+  }
+  if (a.force)
+    for (int f = tid; f < nfz; f += kResThreads) {
+      const int j = res_div(f, nx, a.inv_nn0), i = f - j * nx;
+      a.force[(long)s * a.d.plane + i + (long)px * j] = FZ[f];
+    }
+  for (int t = tid; t < npm; t += kResThreads) {
+    const long o = (long)s * npm + t;
+    a.q[o] = QS[t];
+    a.qd[o] = QS[npm + t];
+    a.qdd[o] = QS[2 * npm + t];
+  }
+}
+
+__global__ void k_tick_n(long* counter, long n) {
+  if (threadIdx.x == 0) *counter += n;
+}
+
+template <int N, int MM>
+hipError_t res_launch_nm(const ResidentArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL((k_resident<N, MM>), dim3(a.S), dim3(kResThreads), a.lds_bytes, st, a);
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t res_launch_n(const ResidentArgs& a, hipStream_t st) {
+  return a.Nm <= 4 ? res_launch_nm<N, 4>(a, st) : res_launch_nm<N, kMaxModes>(a, st);
+}
+
+}  // namespace
+
+int resident_max_nodes() { return kResMaxPer * kResThreads; }
+
+hipError_t launch_resident(const ResidentArgs& a, hipStream_t st) {
+  if (a.nc > resident_max_nodes() || a.Nm > kMaxModes || a.nsteps < 1) return hipErrorInvalidValue;
+  switch (a.d.N) {
+    case 1: return res_launch_n<1>(a, st);
+    case 2: return res_launch_n<2>(a, st);
+    case 3: return res_launch_n<3>(a, st);
+    case 4: return res_launch_n<4>(a, st);
+    case 5: return res_launch_n<5>(a, st);
+    case 6: return res_launch_n<6>(a, st);
+    case 7: return res_launch_n<7>(a, st);
+    case 8: return res_launch_n<8>(a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_tick_n(long* counter, long n, hipStream_t st) {
+  hipLaunchKernelGGL(k_tick_n, dim3(1), dim3(64), 0, st, counter, n);
+  return hipGetLastError();
+}
+
+}  // namespace pmdg

@@ -186,6 +186,12 @@ class Solver:
         check(self.L.pmdg_steps_done(self.h, ctypes.byref(n)))
         return n.value
 
+    def resident(self):
+        """True when step() takes the LDS-resident path."""
+        v = ctypes.c_int()
+        check(self.L.pmdg_resident(self.h, ctypes.byref(v)))
+        return bool(v.value)
+
     def kernel_times(self):
         t = np.zeros(3)
         check(self.L.pmdg_kernel_times(self.h, _d(t)))
