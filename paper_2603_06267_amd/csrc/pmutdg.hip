@@ -1329,7 +1329,17 @@ static bool resident_args(pmdg_solver* s, ResidentArgs* out) {
   a.off_fn = (int)off;
   off = al(off + 4L * nface);
   a.off_q = (int)off;
-  off += 8L * 3 * s->Np * s->Nm;
+  off = al(off + 8L * 3 * s->Np * s->Nm);
+  a.off_coef = (int)off;
+  off = al(off + 8L * 3 * s->Np * s->Nm);
+  a.off_da = (int)off;
+  off = al(off + 8L * 2 * s->Np);
+  a.off_rw = (int)off;
+  off = al(off + 8L * 3 * (B.N + 1) * s->R);
+  a.off_poff = (int)off;
+  off = al(off + 4L * (s->Np + 1));
+  a.off_rb = (int)off;
+  off += 4L * s->R;
   int dev = 0, lim = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)

@@ -272,6 +272,7 @@ struct ResidentArgs {
   long tcap;
   // dynamic LDS layout (bytes)
   int off_force, off_taps, off_mins, off_B, off_fn, off_q;
+  int off_coef, off_da, off_rw, off_poff, off_rb;  // ODE coefficients, drive, receiver weights, PMUT offsets, receiver bases
   int lds_bytes;
 };
 hipError_t launch_resident(const ResidentArgs& a, hipStream_t st);

@@ -55,6 +55,11 @@ __global__ void __launch_bounds__(kResThreads) k_resident(const ResidentArgs a) 
   double* BB = reinterpret_cast<double*>(lds + a.off_B);
   int* FN = reinterpret_cast<int*>(lds + a.off_fn);
   double* QS = reinterpret_cast<double*>(lds + a.off_q);  // q, qd, qdd: [3][Np Nm]
+  double* CF = reinterpret_cast<double*>(lds + a.off_coef);  // omega, zeta, eta: [3][Np Nm]
+  double* DA = reinterpret_cast<double*>(lds + a.off_da);    // [Np][2]: A cos theta, A sin theta
+  double* RW = reinterpret_cast<double*>(lds + a.off_rw);    // [R][3][N+1]
+  int* PO = reinterpret_cast<int*>(lds + a.off_poff);        // [Np+1]
+  int* RB = reinterpret_cast<int*>(lds + a.off_rb);          // [R] compact first node
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int s = blockIdx.x;
   const int nx = a.d.nn[0], ny = a.d.nn[1], nz = a.d.nn[2], nc = a.nc, px = a.d.px;
@@ -86,12 +91,31 @@ __global__ void __launch_bounds__(kResThreads) k_resident(const ResidentArgs a) 
     QS[t] = a.q[o];
     QS[npm + t] = a.qd[o];
     QS[2 * npm + t] = a.qdd[o];
+    CF[t] = a.omega[t];
+    CF[npm + t] = a.zeta[t];
+    CF[2 * npm + t] = a.eta[t];
+  }
+  for (int t = tid; t < 2 * a.Np; t += kResThreads) DA[t] = a.dA[(long)s * a.Np * 2 + t];
+  for (int t = tid; t <= a.Np; t += kResThreads) PO[t] = a.pm_off[t];
+  for (int t = tid; t < a.R * 3 * n1; t += kResThreads) {
+    const int r = t / (3 * n1), q = t - r * 3 * n1, ax = q / n1, i = q - ax * n1;
+    RW[t] = a.r_w[(long)r * 3 * (kMaxOrder + 1) + ax * (kMaxOrder + 1) + i];
+  }
+  for (int r = tid; r < a.R; r += kResThreads) {
+    // padded node index of the element's first node (small brick: 32-bit)
+    const int b = (int)a.r_base[r];
+    const int i0 = b % px, jk = b / px;
+    RB[r] = i0 + nx * jk;
   }
   __syncthreads();
 
   const double dt = a.dt;
   for (int st = 0; st < a.nsteps; ++st) {
     const long cnt = cnt0 + st;
+    // this step's drive carrier, loaded ahead of the stiffness phase
+    const long lev = cnt + 1;
+    const double* c2 = a.car + ((long)s * a.ncar + min(lev, a.ncar - 1)) * 2;
+    const double car0 = a.Np > 0 ? c2[0] : 0.0, car1 = a.Np > 0 ? c2[1] : 0.0;
     // (1) stiffness and update: X += a from p^n at every node, then p += X
     for (int n = tid; n < nc; n += kResThreads) {
       {
@@ -129,10 +153,9 @@ __global__ void __launch_bounds__(kResThreads) k_resident(const ResidentArgs a) 
     for (int n = tid; n < nc; n += kResThreads) P[n] = P[n] + XS[n];
     __syncthreads();
     // (2) PMUTs: sample p^{n+1}, modal update, face force
-    const long lev = cnt + 1;
     const bool driven = !(lev * dt > a.t_switch);
     for (int k = wave; k < a.Np; k += kResThreads / 64) {
-      const int f0 = a.pm_off[k], f1 = a.pm_off[k + 1], po = k * Nm;
+      const int f0 = PO[k], f1 = PO[k + 1], po = k * Nm;
       double g[MM];
 #pragma unroll
       for (int m = 0; m < MM; ++m) g[m] = 0.0;
@@ -156,11 +179,9 @@ __global__ void __launch_bounds__(kResThreads) k_resident(const ResidentArgs a) 
       }
       double phi;
       if (driven) {
-        const double* c2 = a.car + ((long)s * a.ncar + min(lev, a.ncar - 1)) * 2;
-        const double* d2 = a.dA + ((long)s * a.Np + k) * 2;
-        phi = d2[0] * c2[0] - d2[1] * c2[1];
+        phi = DA[2 * k] * car0 - DA[2 * k + 1] * car1;
       } else {
-        phi = res_wave_sum(lane < Nm ? a.eta[po + lane] * qp : 0.0) / a.cap;
+        phi = res_wave_sum(lane < Nm ? CF[2 * npm + po + lane] * qp : 0.0) / a.cap;
       }
       double qa = 0.0;
       if (lane < Nm) {
@@ -168,7 +189,7 @@ __global__ void __launch_bounds__(kResThreads) k_resident(const ResidentArgs a) 
 #pragma unroll
         for (int m = 0; m < MM; ++m)
           if (m == lane) gm = g[m];
-        const double w = a.omega[po + lane], ze = a.zeta[po + lane], et = a.eta[po + lane];
+        const double w = CF[po + lane], ze = CF[npm + po + lane], et = CF[2 * npm + po + lane];
         qa = -w * w * qp - 2.0 * ze * w * qds + gm + et * phi;
         QS[po + lane] = qp;
         QS[npm + po + lane] = qds + 0.5 * dt * qa;
@@ -187,16 +208,12 @@ __global__ void __launch_bounds__(kResThreads) k_resident(const ResidentArgs a) 
     }
     // (3) receivers
     for (int r = wave; r < a.R; r += kResThreads / 64) {
-      // padded node index of the element's first node (small brick: 32-bit)
-      const int b = (int)a.r_base[r];
-      const int i0 = b % px, jk = b / px;
-      const int j0 = jk % ny, k0 = jk / ny;
-      const int cb = i0 + nx * (j0 + ny * k0);
-      const double* w = a.r_w + (long)r * 3 * (kMaxOrder + 1);
+      const int cb = RB[r];
+      const double* w = RW + r * 3 * n1;
       double v = 0.0;
       for (int idx = lane; idx < n1 * n1 * n1; idx += 64) {
         const int i = idx % n1, j = (idx / n1) % n1, c = idx / (n1 * n1);
-        v += w[i] * w[kMaxOrder + 1 + j] * w[2 * (kMaxOrder + 1) + c] * (double)P[cb + i + nx * (j + ny * c)];
+        v += w[i] * w[n1 + j] * w[2 * n1 + c] * (double)P[cb + i + nx * (j + ny * c)];
       }
       v = res_wave_sum(v);
       if (lane == 0 && cnt < a.tcap) a.traces[((long)s * a.R + r) * a.tcap + cnt] = v;
