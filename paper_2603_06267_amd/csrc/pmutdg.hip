@@ -1312,6 +1312,11 @@ static bool resident_args(pmdg_solver* s, ResidentArgs* out) {
   if (s->rows != 0 || s->zchunk != -1 || s->waves != 4 || s->depth != 2 || s->tblock != 1 || s->overlap != 0)
     return false;
   if (s->Nm > kMaxModes || B.nnodes > resident_max_nodes() || B.pnodes > (1L << 30)) return false;
+  // every table the kernel reads must exist: PMUT tables when there are
+  // PMUTs, receiver tables when there are receivers
+  if ((s->Np > 0 && !(dptr<int>(s, "pm_off") && dptr<double>(s, "pm_B") && dptr<double>(s, "car"))) ||
+      (s->R > 0 && !(dptr<long>(s, "r_base") && dptr<double>(s, "r_w") && dptr<double>(s, "traces"))))
+    return false;
   ResidentArgs a;
   memset(&a, 0, sizeof(a));
   const int NT = 2 * B.N, NC = B.N + 3;

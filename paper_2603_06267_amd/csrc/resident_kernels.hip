@@ -96,7 +96,9 @@ __global__ void __launch_bounds__(kResThreads) k_resident(const ResidentArgs a) 
     CF[2 * npm + t] = a.eta[t];
   }
   for (int t = tid; t < 2 * a.Np; t += kResThreads) DA[t] = a.dA[(long)s * a.Np * 2 + t];
-  for (int t = tid; t <= a.Np; t += kResThreads) PO[t] = a.pm_off[t];
+  // (a solver without PMUTs has no PMUT tables at all)
+  if (a.Np > 0)
+    for (int t = tid; t <= a.Np; t += kResThreads) PO[t] = a.pm_off[t];
   for (int t = tid; t < a.R * 3 * n1; t += kResThreads) {
     const int r = t / (3 * n1), q = t - r * 3 * n1, ax = q / n1, i = q - ax * n1;
     RW[t] = a.r_w[(long)r * 3 * (kMaxOrder + 1) + ax * (kMaxOrder + 1) + i];

@@ -123,3 +123,26 @@ def test_long_run_and_path_switch():
     pa, _ = a.get_state(0)
     pb, _ = b.get_state(0)
     assert rel_l2(pa, pb) <= 1e-6
+
+
+@pytest.mark.parametrize("receivers", [0, 1])
+def test_without_pmuts(receivers):
+    """A brick without PMUTs (no PMUT tables at all), with and without a
+    receiver: the resident path from a smooth state against the tiled path."""
+    dom = W.brick([0, 0, 0], [1, 1, 1], [3, 3, 3], 4)
+    out = []
+    for mode in (1, 0):
+        g = solver.Solver([dom], precision=32, trace_capacity=200)
+        if receivers:
+            g.set_receivers([[0.3, 0.6, 0.2]])
+        g.set_option(_lib.OPT_RESIDENT, mode)
+        g.bind()
+        assert g.resident() == bool(mode)
+        x = g.node_coords()
+        p = np.cos(np.pi * x[:, 0]) * np.cos(2 * np.pi * x[:, 2])
+        g.set_state(0, p, 0.999 * p)
+        g.step(150)
+        out.append((g.get_state(0)[0], g.read_traces() if receivers else None))
+    assert rel_l2(out[0][0], out[1][0]) <= 1e-6
+    if receivers:
+        assert rel_l2(out[0][1], out[1][1]) <= 1e-6
