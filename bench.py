@@ -128,7 +128,7 @@ def cpu_baseline(wl, steps):
                               "sample": f"step {steps + 1} of the same run on one thread ({dt1:.1f} s)"}}
 
 
-def run_gpu(wl, precision, steps, warmup, graphs, rows, zchunk, tblock=1):
+def run_gpu(wl, precision, steps, warmup, graphs, rows, zchunk, tblock=1, overlap=None):
     import torch
     from paper_2603_06267_amd import solver, workloads as W
     g = solver.from_workload(wl, precision=precision, n_steps=steps + warmup, shape_fn=W.shape_fn(wl),
@@ -136,6 +136,8 @@ def run_gpu(wl, precision, steps, warmup, graphs, rows, zchunk, tblock=1):
     g.set_option(2, rows)
     g.set_option(3, zchunk)
     g.set_option(9, tblock)
+    if overlap is not None:
+        g.set_option(10, overlap)
     g.bind()
     stream = torch.cuda.current_stream()
     g.set_option(1, 1 if graphs else 0)
@@ -156,6 +158,8 @@ def run_gpu(wl, precision, steps, warmup, graphs, rows, zchunk, tblock=1):
     gg.set_option(2, rows)
     gg.set_option(3, zchunk)
     gg.set_option(9, tblock)
+    if overlap is not None:
+        gg.set_option(10, overlap)
     gg.bind()
     gg.set_option(1, 1 if graphs else 0)
     gg.step(warmup)
@@ -527,6 +531,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--rows", type=int, default=0, help="rows per wave of the stiffness tile (0: automatic)")
     ap.add_argument("--zchunk", type=int, default=73)
+    ap.add_argument("--overlap", type=int, default=None, choices=(0, 1, 2, 3),
+                    help="PMDG_OPT_OVERLAP for the large-array run (default: the library's)")
     ap.add_argument("--tblock", type=int, default=1, choices=(1, 2),
                     help="steps per stiffness pass (2: the fused two-step pass)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -583,7 +589,7 @@ def main():
     log(f"config 3: {dofs} unique DOFs ({W.element_local_dofs(wl)} element-local); FP32 run, "
         f"{args.warmup} warmup + {args.steps} timed steps")
     el, el_graph, kt, finite = run_gpu(wl, 32, args.steps, args.warmup, not args.direct, args.rows, args.zchunk,
-                                       args.tblock)
+                                       args.tblock, args.overlap)
     log(f"  timed (events): {el * 1e3 / args.steps:.4f} ms/step; graph replay: {el_graph * 1e3 / args.steps:.4f} "
         f"ms/step; kernels ms: stiff {kt[0]:.4f} face {kt[1]:.4f} flux {kt[2]:.4f}")
     main_err = trace_error(run_gpu.traces[0], golden_traces(3, W.config3()))

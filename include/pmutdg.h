@@ -324,8 +324,12 @@ pmdg_status pmdg_set_option(pmdg_solver* h, int option, long value);
  * face kernel rather than the stiffness launch writes them) on a side stream
  * alongside the secondary's stiffness launch; 2 also runs the primary's
  * stiffness launch on that side stream, concurrently with the secondary's;
- * 0 (default) runs every kernel of a step in sequence.  Same results in
- * every mode; other values are rejected (PMDG_EINVAL). */
+ * 3 runs the face kernel's PMUT and receiver work on a side stream
+ * alongside the interface kernels (it reads a copy of the step counter
+ * that the primary's stiffness launch writes, since the last interface
+ * kernel advances the counter); 0 (default) runs every kernel of a step in
+ * sequence.  Same results in every mode; other values are rejected
+ * (PMDG_EINVAL). */
 #define PMDG_OPT_OVERLAP 10
 /* PMDG_OPT_TIME_BLOCK for the secondary brick alone (0 = as the primary). */
 #define PMDG_OPT_TIME_BLOCK_SECONDARY 11

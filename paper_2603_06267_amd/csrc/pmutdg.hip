@@ -1102,6 +1102,52 @@ static pmdg_status enqueue_step_split(pmdg_solver* s, hipStream_t st, int toggle
 
 static bool any_pml(const pmdg_solver* s) { return s->b[0].pml || (s->ndom > 1 && s->b[1].pml); }
 
+// Two bricks, untimed, overlap mode 3: both stiffness launches in sequence
+// (and any interface traces they do not write themselves), then the PMUT
+// and receiver blocks of the face kernel on a side stream alongside the two
+// interface kernels, both short and bound by latency rather than bandwidth.  The last interface kernel advances the
+// step counter, so the face kernel reads a copy of it that the primary's
+// stiffness launch writes.
+template <typename Real>
+static pmdg_status enqueue_step_faceflux(pmdg_solver* s, hipStream_t st, int toggle) {
+  if (!s->side) {
+    HIPCHK(hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming));
+  }
+  const bool incr = s->prec == 32;
+  long* snap = (long*)(dptr<char>(s, "ctl") + 32);
+  StiffArgs<Real> a0 = stiff_args<Real>(s, 0);
+  a0.cnt_snap = snap;
+  HIPCHK(launch_stiff<Real>(a0, incr, st));
+  HIPCHK(launch_stiff<Real>(stiff_args<Real>(s, 1), incr, st));
+  FaceArgs<Real> f = face_args<Real>(s, 0);
+  f.counter = snap;
+  // interface traces the stiffness launches did not write go first: the
+  // interface kernels read them
+  if (f.nb_tr0 + f.nb_tr1 > 0) {
+    FaceArgs<Real> ft = f;
+    ft.nb_pm = 0;
+    ft.nb_rc = 0;
+    ft.R = 0;
+    ft.nblocks = f.nb_tr0 + f.nb_tr1;
+    HIPCHK(launch_face<Real>(ft, st));
+  }
+  HIPCHK(hipEventRecord(s->ev_fork, st));
+  HIPCHK(hipStreamWaitEvent(s->side, s->ev_fork, 0));
+  FaceArgs<Real> fp = f;
+  fp.nb_tr0 = 0;
+  fp.nb_tr1 = 0;
+  fp.nblocks = std::max(1, f.nb_pm + f.nb_rc);
+  HIPCHK(launch_face<Real>(fp, s->side));
+  HIPCHK(hipEventRecord(s->ev_join, s->side));
+  FluxArgs<Real> a = flux_args<Real>(s, 1);
+  a.toggle = toggle;
+  HIPCHK(launch_flux<Real>(a, st));
+  HIPCHK(hipStreamWaitEvent(st, s->ev_join, 0));
+  return PMDG_OK;
+}
+
 // Arguments of the layer kernels of brick d (prime: the acceleration of the
 // current level only).
 template <typename Real>
@@ -1176,6 +1222,8 @@ static HexArgs<Real> hex_args(pmdg_solver* s, int d) {
 
 template <typename Real>
 static pmdg_status enqueue_step(pmdg_solver* s, hipStream_t st, Timer* tm) {
+  if (!tm && s->ndom == 2 && s->overlap == 3 && !any_pml(s) && !s->b[0].mapped())
+    return enqueue_step_faceflux<Real>(s, st, 0);
   if (!tm && s->ndom == 2 && s->overlap && !any_pml(s)) return enqueue_step_split<Real>(s, st, 0);
   const bool incr = s->prec == 32;
   for (int d = 0; d < s->ndom; ++d) {
@@ -2460,7 +2508,7 @@ pmdg_status pmdg_set_option(pmdg_solver* s, int option, long value) {
       s->zchunk = (int)value;
       break;
     case PMDG_OPT_OVERLAP:
-      if (!(value >= 0 && value <= 2)) return fail(PMDG_EINVAL, "overlap mode must be 0, 1 or 2");
+      if (!(value >= 0 && value <= 3)) return fail(PMDG_EINVAL, "overlap mode must be 0, 1, 2 or 3");
       s->overlap = (int)value;
       break;
     case PMDG_OPT_TIME_BLOCK:

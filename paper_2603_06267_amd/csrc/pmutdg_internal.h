@@ -45,6 +45,8 @@ struct StiffArgs {
   int S;
   Real dt2;                 // dt^2
   const long* counter;      // steps completed (read only here)
+  long* cnt_snap;           // or null: tile 0 copies the step counter here (read by a face kernel
+                            // that runs alongside the interface kernel, which advances the counter)
   // PMUT face force on the primary's bottom plane: [S][nn0*nn1], or null
   const Real* force;
   // interface residual per face of Gamma_I: [S][nface][(N+1)^2][2] or null

@@ -128,6 +128,7 @@ __device__ __forceinline__ void stiff_tile(const StiffArgs<Real>& a, int tile_id
   const unsigned plane = (unsigned)a.d.plane;
   const unsigned plane_bytes = plane * (unsigned)sizeof(Real);
   const long cnt = *a.counter;
+  if (a.cnt_snap && tile_id == 0 && tid == 0) *a.cnt_snap = cnt;
   const int cur = (int)(cnt % a.d.nbuf), nxt = (int)((cnt + 1) % a.d.nbuf);
   const Real* __restrict__ P = a.d.P[cur] + (long)s * a.d.nnodes;
   Real* __restrict__ Pn = a.d.P[nxt] + (long)s * a.d.nnodes;

@@ -372,13 +372,15 @@ def test_config3_two_step_pass_full_size(precision):
     assert d < 1e-5
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 @pytest.mark.parametrize("graph", [0, 1])
 def test_overlapped_face_work_equals_sequential(graph, mode):
     """Running the PMUT face work (mode 1), or the primary's whole chain of
     stiffness and face work (mode 2), on a side stream alongside the
-    secondary's stiffness launch gives bitwise the traces and modal state of
-    running every kernel in sequence."""
+    secondary's stiffness launch, or the face kernel alongside the interface
+    kernels (mode 3, the face kernel reading the step counter's copy), gives
+    bitwise the traces and modal state of running every kernel in
+    sequence."""
     wl = W.small_two_domain(False, steps=90)
     sf = W.shape_fn(wl)
     res = []
