@@ -47,8 +47,11 @@ template <int N, int MM>
 __global__ void __launch_bounds__(kResThreads) k_resident(const ResidentArgs a) {
   constexpr int NT = 2 * N, NC = N + 3, n1 = N + 1;
   extern __shared__ __align__(16) unsigned char lds[];
-  float* P = reinterpret_cast<float*>(lds);
-  float* XS = P + a.nc;
+  // p with N planes of zeros before and after: every neighbour of the
+  // stencil is a valid address, and those outside the brick carry zero taps
+  const int pad = N * a.d.nn[0] * a.d.nn[1];
+  float* P = reinterpret_cast<float*>(lds) + pad;
+  float* XS = P + a.nc + pad;
   float* FZ = reinterpret_cast<float*>(lds + a.off_force);
   float* TP = reinterpret_cast<float*>(lds + a.off_taps);
   float* MI = reinterpret_cast<float*>(lds + a.off_mins);
@@ -74,6 +77,10 @@ __global__ void __launch_bounds__(kResThreads) k_resident(const ResidentArgs a) 
     const long g = i + (long)px * (j + (long)ny * k);
     P[n] = Pg[g];
     XS[n] = Xg[g];
+  }
+  for (int t = tid; t < pad; t += kResThreads) {
+    P[-pad + t] = 0.f;
+    P[nc + t] = 0.f;
   }
   for (int f = tid; f < nfz; f += kResThreads) {
     const int j = res_div(f, nx, a.inv_nn0), i = f - j * nx;
@@ -132,13 +139,15 @@ __global__ void __launch_bounds__(kResThreads) k_resident(const ResidentArgs a) 
         float ac = 0.f;
 #pragma unroll
         for (int t = 0; t < N; ++t) {
-          // neighbours outside the brick carry zero taps and read as zero
-          const float xa = i - N + t >= 0 ? P[n - N + t] : 0.f;
-          const float xb = i + 1 + t < nx ? P[n + 1 + t] : 0.f;
-          const float ya = j - N + t >= 0 ? P[n + (t - N) * sy] : 0.f;
-          const float yb = j + 1 + t < ny ? P[n + (1 + t) * sy] : 0.f;
-          const float za = k - N + t >= 0 ? P[n + (t - N) * sz] : 0.f;
-          const float zb = k + 1 + t < nz ? P[n + (1 + t) * sz] : 0.f;
+          // a neighbour outside the brick has a zero tap; its address (the
+          // zero padding, or a node of the next or previous row or plane)
+          // holds a finite value
+          const float xa = P[n - N + t];
+          const float xb = P[n + 1 + t];
+          const float ya = P[n + (t - N) * sy];
+          const float yb = P[n + (1 + t) * sy];
+          const float za = P[n + (t - N) * sz];
+          const float zb = P[n + (1 + t) * sz];
           ac += tx[t] * (xa - p0);
           ac += tx[N + t] * (xb - p0);
           ac += ty[t] * (ya - p0);
@@ -253,6 +262,11 @@ __global__ void k_tick_n(long* counter, long n) {
 
 template <int N, int MM>
 hipError_t res_launch_nm(const ResidentArgs& a, hipStream_t st) {
+  if (a.lds_bytes > 65536) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_resident<N, MM>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, a.lds_bytes);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL((k_resident<N, MM>), dim3(a.S), dim3(kResThreads), a.lds_bytes, st, a);
   return hipGetLastError();
 }
