@@ -1371,7 +1371,7 @@ static bool resident_args(pmdg_solver* s, ResidentArgs* out) {
   const long nc = B.nnodes, nface = (long)s->pm_node.size();
   auto al = [](long v) { return (v + 15) / 16 * 16; };
   // p with N planes of zero padding on each side, then the increment
-  long off = al(4 * (nc + 2L * B.N * B.nn[0] * B.nn[1]) + 4 * nc);
+  long off = al(4 * (nc + 2L * resident_pad(B.N, B.nn[0], B.nn[1])) + 4 * nc);
   a.off_force = (int)off;
   off = al(off + 4L * B.nn[0] * B.nn[1]);
   a.off_taps = (int)off;

@@ -279,6 +279,7 @@ struct ResidentArgs {
 };
 hipError_t launch_resident(const ResidentArgs& a, hipStream_t st);
 int resident_max_nodes();
+__host__ __device__ int resident_pad(int N, int nx, int ny);  // zero padding around p in LDS (nodes)
 hipError_t launch_tick_n(long* counter, long n, hipStream_t st);
 
 // Launchers (defined in pmutdg_kernels.hip).

@@ -18,9 +18,14 @@
 
 namespace pmdg {
 
+// Zero padding before and after p in LDS: N planes for the z neighbours, and
+// room for the last x window of the last row.
+__host__ __device__ int resident_pad(int N, int nx, int ny) { return N * nx * ny + 8 + N; }
+
 namespace {
 
 constexpr int kResThreads = 1024;
+constexpr int kResRun = 8;  // nodes per x run of the stiffness phase (room for it in resident_pad)
 constexpr int kResMaxPer = 32;  // nodes per thread (the LDS bound comes first)
 
 template <int N>
@@ -49,7 +54,7 @@ __global__ void __launch_bounds__(kResThreads) k_resident(const ResidentArgs a) 
   extern __shared__ __align__(16) unsigned char lds[];
   // p with N planes of zeros before and after: every neighbour of the
   // stencil is a valid address, and those outside the brick carry zero taps
-  const int pad = N * a.d.nn[0] * a.d.nn[1];
+  const int pad = resident_pad(N, a.d.nn[0], a.d.nn[1]);
   float* P = reinterpret_cast<float*>(lds) + pad;
   float* XS = P + a.nc + pad;
   float* FZ = reinterpret_cast<float*>(lds + a.off_force);
@@ -119,45 +124,66 @@ __global__ void __launch_bounds__(kResThreads) k_resident(const ResidentArgs a) 
   __syncthreads();
 
   const double dt = a.dt;
+  // runs along x: each row split into nseg runs of at most kResRun nodes
+  const int nseg = (nx + kResRun - 1) / kResRun, seglen = (nx + nseg - 1) / nseg;
+  const int nseg_all = nseg * ny * nz;
   for (int st = 0; st < a.nsteps; ++st) {
     const long cnt = cnt0 + st;
     // this step's drive carrier, loaded ahead of the stiffness phase
     const long lev = cnt + 1;
     const double* c2 = a.car + ((long)s * a.ncar + min(lev, a.ncar - 1)) * 2;
     const double car0 = a.Np > 0 ? c2[0] : 0.0, car1 = a.Np > 0 ? c2[1] : 0.0;
-    // (1) stiffness and update: X += a from p^n at every node, then p += X
-    for (int n = tid; n < nc; n += kResThreads) {
-      {
-        const int jk = res_div(n, nx, a.inv_nn0), i = n - jk * nx;
-        const int k = res_div(jk, ny, a.inv_nn1), j = jk - k * ny;
-        const int cx = res_class<N>(i, nx), cy = res_class<N>(j, ny), cz = res_class<N>(k, nz);
-        const float* tx = TP + cx * NT;
-        const float* ty = TP + (NC + cy) * NT;
-        const float* tz = TP + (2 * NC + cz) * NT;
-        const float p0 = P[n];
-        const int sy = nx, sz = nx * ny;
-        float ac = 0.f;
+    // (1) stiffness and update: X += a from p^n at every node, then p += X.
+    // A thread takes a run of up to kResRun nodes along x: the x line comes
+    // from one window of registers, the y and z rows of the operator once
+    // per run.
+    for (int sgi = tid; sgi < nseg_all; sgi += kResThreads) {
+      const int row = sgi / nseg, sg = sgi - row * nseg;
+      const int k = res_div(row, ny, a.inv_nn1), j = row - k * ny;
+      const int i0 = sg * seglen, len = min(seglen, nx - i0);
+      const int base = row * nx + i0;
+      const int cy = res_class<N>(j, ny), cz = res_class<N>(k, nz);
+      float ty[NT], tz[NT];
 #pragma unroll
-        for (int t = 0; t < N; ++t) {
-          // a neighbour outside the brick has a zero tap; its address (the
-          // zero padding, or a node of the next or previous row or plane)
-          // holds a finite value
-          const float xa = P[n - N + t];
-          const float xb = P[n + 1 + t];
-          const float ya = P[n + (t - N) * sy];
-          const float yb = P[n + (1 + t) * sy];
-          const float za = P[n + (t - N) * sz];
-          const float zb = P[n + (1 + t) * sz];
-          ac += tx[t] * (xa - p0);
-          ac += tx[N + t] * (xb - p0);
-          ac += ty[t] * (ya - p0);
-          ac += ty[N + t] * (yb - p0);
-          ac += tz[t] * (za - p0);
-          ac += tz[N + t] * (zb - p0);
+      for (int t = 0; t < NT; ++t) {
+        ty[t] = TP[(NC + cy) * NT + t];
+        tz[t] = TP[(2 * NC + cz) * NT + t];
+      }
+      const float myz = MI[NC + cy], mz = MI[2 * NC + cz];
+      // the x window: nodes i0 - N .. i0 + kResRun + N - 1 of this row (the
+      // padding keeps every address valid)
+      float w[kResRun + 2 * N];
+#pragma unroll
+      for (int q = 0; q < kResRun + 2 * N; ++q) w[q] = P[base - N + q];
+      const int sy = nx, sz = nx * ny;
+#pragma unroll
+      for (int u = 0; u < kResRun; ++u) {
+        if (u < len) {
+          const int n = base + u, i = i0 + u;
+          const int cx = res_class<N>(i, nx);
+          const float* tx = TP + cx * NT;
+          const float p0 = w[u + N];
+          float ac = 0.f;
+#pragma unroll
+          for (int t = 0; t < N; ++t) {
+            // a neighbour outside the brick has a zero tap; its address (the
+            // zero padding, or a node of the next or previous row or plane)
+            // holds a finite value
+            const float ya = P[n + (t - N) * sy];
+            const float yb = P[n + (1 + t) * sy];
+            const float za = P[n + (t - N) * sz];
+            const float zb = P[n + (1 + t) * sz];
+            ac += tx[t] * (w[u + t] - p0);
+            ac += tx[N + t] * (w[u + N + 1 + t] - p0);
+            ac += ty[t] * (ya - p0);
+            ac += ty[N + t] * (yb - p0);
+            ac += tz[t] * (za - p0);
+            ac += tz[N + t] * (zb - p0);
+          }
+          const float minv = MI[cx] * myz * mz;
+          if (k == 0) ac += a.dt2 * minv * FZ[i + nx * j];
+          XS[n] = XS[n] + ac;
         }
-        const float minv = MI[cx] * MI[NC + cy] * MI[2 * NC + cz];
-        if (k == 0) ac += a.dt2 * minv * FZ[i + nx * j];
-        XS[n] = XS[n] + ac;
       }
     }
     __syncthreads();
