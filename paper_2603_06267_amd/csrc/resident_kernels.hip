@@ -1,8 +1,9 @@
 // Steps of a small single-brick FP32 solver with the pressure held in LDS.
 //
 // One workgroup (1024 threads) per scenario keeps p on every node in LDS
-// together with the increment X = p^n - p^{n-1}, and runs whole steps (Sec. 3.1, Algorithm 1 in its synchronised
-// reading) back to back inside one launch:
+// together with the increment X = p^n - p^{n-1}, and runs whole steps
+// (Sec. 3.1, Algorithm 1 in its synchronised reading) back to back inside
+// one launch:
 //   1. stiffness and update at every node: the difference-form Kronecker
 //      stencil of the tiled kernel, in the same operation order, and the
 //      PMUT face force on the bottom plane; X += a is formed from p^n for
@@ -10,7 +11,7 @@
 //   2. PMUT sampling of p^{n+1} (FP64), the modal Newmark update with its
 //      drive (or the receive-mode feedback), and the new face force, one
 //      wave per PMUT (Sec. 2, eq. pmut_problem; Sec. 3.1, eqs. f_i, g_m);
-//   3. receiver traces of p^{n+1} (FP64), one wave per receiver.
+//   3. receiver traces of p^{n+1} (FP64), 16 lanes per receiver.
 // HBM is touched only to read the state at the start, to write the traces
 // of each step and to write the state back at the end.  A one-thread launch
 // then advances the device step counter by the number of steps.
@@ -243,18 +244,28 @@ __global__ void __launch_bounds__(kResThreads) k_resident(const ResidentArgs a) 
         FZ[FN[f]] = (float)(-a.kappa * fv);
       }
     }
-    // (3) receivers
-    for (int r = wave; r < a.R; r += kResThreads / 64) {
-      const int cb = RB[r];
-      const double* w = RW + r * 3 * n1;
-      double v = 0.0;
-      for (int idx = lane; idx < n1 * n1 * n1; idx += 64) {
-        const int i = idx % n1, j = (idx / n1) % n1, c = idx / (n1 * n1);
-        v += w[i] * w[n1 + j] * w[2 * n1 + c] * (double)P[cb + i + nx * (j + ny * c)];
+    // (3) receivers: 16 lanes per receiver, all 64 groups of the workgroup
+    // at once
+    {
+      const int grp = tid >> 4, l16 = tid & 15;
+      for (int r0 = 0; r0 < a.R; r0 += kResThreads / 16) {
+        const int r = r0 + grp;
+        double v = 0.0;
+        if (r < a.R) {
+          const int cb = RB[r];
+          const double* w = RW + r * 3 * n1;
+          for (int idx = l16; idx < n1 * n1 * n1; idx += 16) {
+            const int i = idx % n1, j = (idx / n1) % n1, c = idx / (n1 * n1);
+            v += w[i] * w[n1 + j] * w[2 * n1 + c] * (double)P[cb + i + nx * (j + ny * c)];
+          }
+        }
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
+        if (r < a.R && l16 == 0) {
+          if (cnt < a.tcap) a.traces[((long)s * a.R + r) * a.tcap + cnt] = v;
+          if (!__builtin_isfinite(v)) atomicOr(a.nonfinite, 1);
+        }
       }
-      v = res_wave_sum(v);
-      if (lane == 0 && cnt < a.tcap) a.traces[((long)s * a.R + r) * a.tcap + cnt] = v;
-      if (lane == 0 && !__builtin_isfinite(v)) atomicOr(a.nonfinite, 1);
     }
     __syncthreads();
   }
