@@ -1415,6 +1415,8 @@ static bool resident_args(pmdg_solver* s, ResidentArgs* out) {
   a.Np = s->Np;
   a.Nm = s->Nm;
   a.nface = (int)nface;
+  for (int k = 0; k < s->Np; ++k)
+    if (s->pm_off[k + 1] - s->pm_off[k] > 48) a.pm_wide = 1;
   a.pm_off = f.pm_off;
   a.pm_node = f.pm_node;
   a.pm_B = f.pm_B;

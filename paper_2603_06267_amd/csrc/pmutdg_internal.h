@@ -252,6 +252,7 @@ struct ResidentArgs {
   int* nonfinite;
   // PMUTs
   int Np, Nm, nface;
+  int pm_wide;              // some PMUT has more than 48 face nodes: 64 lanes per PMUT, else 16
   const int* pm_off;        // [Np+1]
   const int* pm_node;       // padded bottom-face index
   const double* pm_B;       // [nface][Nm]

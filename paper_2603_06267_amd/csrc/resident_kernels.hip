@@ -9,8 +9,8 @@
 //      PMUT face force on the bottom plane; X += a is formed from p^n for
 //      every node first, then p += X in place after a barrier;
 //   2. PMUT sampling of p^{n+1} (FP64), the modal Newmark update with its
-//      drive (or the receive-mode feedback), and the new face force, one
-//      wave per PMUT (Sec. 2, eq. pmut_problem; Sec. 3.1, eqs. f_i, g_m);
+//      drive (or the receive-mode feedback), and the new face force, 16
+//      lanes per PMUT (Sec. 2, eq. pmut_problem; Sec. 3.1, eqs. f_i, g_m);
 //   3. receiver traces of p^{n+1} (FP64), 16 lanes per receiver.
 // HBM is touched only to read the state at the start, to write the traces
 // of each step and to write the state back at the end.  A one-thread launch
@@ -43,13 +43,15 @@ __device__ __forceinline__ int res_div(int n, int d, float inv) {
   return q;
 }
 
-__device__ __forceinline__ double res_wave_sum(double v) {
+// sum over the G lanes of a lane group
+template <int G>
+__device__ __forceinline__ double res_group_sum(double v) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
   return v;
 }
 
-template <int N, int MM>
+template <int N, int MM, int G>
 __global__ void __launch_bounds__(kResThreads) k_resident(const ResidentArgs a) {
   constexpr int NT = 2 * N, NC = N + 3, n1 = N + 1;
   extern __shared__ __align__(16) unsigned char lds[];
@@ -69,7 +71,7 @@ __global__ void __launch_bounds__(kResThreads) k_resident(const ResidentArgs a) 
   double* RW = reinterpret_cast<double*>(lds + a.off_rw);    // [R][3][N+1]
   int* PO = reinterpret_cast<int*>(lds + a.off_poff);        // [Np+1]
   int* RB = reinterpret_cast<int*>(lds + a.off_rb);          // [R] compact first node
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x;
   const int s = blockIdx.x;
   const int nx = a.d.nn[0], ny = a.d.nn[1], nz = a.d.nn[2], nc = a.nc, px = a.d.px;
   const long cnt0 = *a.counter;
@@ -190,58 +192,65 @@ __global__ void __launch_bounds__(kResThreads) k_resident(const ResidentArgs a) 
     __syncthreads();
     for (int n = tid; n < nc; n += kResThreads) P[n] = P[n] + XS[n];
     __syncthreads();
-    // (2) PMUTs: sample p^{n+1}, modal update, face force
+    // (2) PMUTs: sample p^{n+1}, modal update, face force; G lanes per PMUT
+    // (16, or 64 for PMUTs of more than 48 face nodes; lane m of the group
+    // also carries mode m)
     const bool driven = !(lev * dt > a.t_switch);
-    for (int k = wave; k < a.Np; k += kResThreads / 64) {
-      const int f0 = PO[k], f1 = PO[k + 1], po = k * Nm;
-      double g[MM];
+    {
+      const int grp = tid / G, l16 = tid % G;
+      for (int k0 = 0; k0 < a.Np; k0 += kResThreads / G) {
+        const int k = k0 + grp;
+        if (k >= a.Np) continue;
+        const int f0 = PO[k], f1 = PO[k + 1], po = k * Nm;
+        double g[MM];
 #pragma unroll
-      for (int m = 0; m < MM; ++m) g[m] = 0.0;
-      bool bad = false;
-      for (int f = f0 + lane; f < f1; f += 64) {
-        const double p = (double)P[FN[f]];
-        bad |= !__builtin_isfinite(p);
+        for (int m = 0; m < MM; ++m) g[m] = 0.0;
+        bool bad = false;
+        for (int f = f0 + l16; f < f1; f += G) {
+          const double p = (double)P[FN[f]];
+          bad |= !__builtin_isfinite(p);
 #pragma unroll
-        for (int m = 0; m < MM; ++m)
-          if (m < Nm) g[m] += BB[f * Nm + m] * p;
-      }
-      if (bad) atomicOr(a.nonfinite, 1);
-#pragma unroll
-      for (int m = 0; m < MM; ++m)
-        if (m < Nm) g[m] = res_wave_sum(g[m]);
-      double qp = 0.0, qds = 0.0;
-      if (lane < Nm) {
-        const double q = QS[po + lane], qd = QS[npm + po + lane], qdd = QS[2 * npm + po + lane];
-        qp = q + dt * qd + 0.5 * dt * dt * qdd;
-        qds = qd + 0.5 * dt * qdd;
-      }
-      double phi;
-      if (driven) {
-        phi = DA[2 * k] * car0 - DA[2 * k + 1] * car1;
-      } else {
-        phi = res_wave_sum(lane < Nm ? CF[2 * npm + po + lane] * qp : 0.0) / a.cap;
-      }
-      double qa = 0.0;
-      if (lane < Nm) {
-        double gm = 0.0;
+          for (int m = 0; m < MM; ++m)
+            if (m < Nm) g[m] += BB[f * Nm + m] * p;
+        }
+        if (bad) atomicOr(a.nonfinite, 1);
 #pragma unroll
         for (int m = 0; m < MM; ++m)
-          if (m == lane) gm = g[m];
-        const double w = CF[po + lane], ze = CF[npm + po + lane], et = CF[2 * npm + po + lane];
-        qa = -w * w * qp - 2.0 * ze * w * qds + gm + et * phi;
-        QS[po + lane] = qp;
-        QS[npm + po + lane] = qds + 0.5 * dt * qa;
-        QS[2 * npm + po + lane] = qa;
-      }
-      double qm[MM];
+          if (m < Nm) g[m] = res_group_sum<G>(g[m]);
+        double qp = 0.0, qds = 0.0;
+        if (l16 < Nm) {
+          const double q = QS[po + l16], qd = QS[npm + po + l16], qdd = QS[2 * npm + po + l16];
+          qp = q + dt * qd + 0.5 * dt * dt * qdd;
+          qds = qd + 0.5 * dt * qdd;
+        }
+        double phi;
+        if (driven) {
+          phi = DA[2 * k] * car0 - DA[2 * k + 1] * car1;
+        } else {
+          phi = res_group_sum<G>(l16 < Nm ? CF[2 * npm + po + l16] * qp : 0.0) / a.cap;
+        }
+        double qa = 0.0;
+        if (l16 < Nm) {
+          double gm = 0.0;
 #pragma unroll
-      for (int m = 0; m < MM; ++m) qm[m] = __shfl(qa, m, 64);
-      for (int f = f0 + lane; f < f1; f += 64) {
-        double fv = 0.0;
+          for (int m = 0; m < MM; ++m)
+            if (m == l16) gm = g[m];
+          const double w = CF[po + l16], ze = CF[npm + po + l16], et = CF[2 * npm + po + l16];
+          qa = -w * w * qp - 2.0 * ze * w * qds + gm + et * phi;
+          QS[po + l16] = qp;
+          QS[npm + po + l16] = qds + 0.5 * dt * qa;
+          QS[2 * npm + po + l16] = qa;
+        }
+        double qm[MM];
 #pragma unroll
-        for (int m = 0; m < MM; ++m)
-          if (m < Nm) fv += qm[m] * BB[f * Nm + m];
-        FZ[FN[f]] = (float)(-a.kappa * fv);
+        for (int m = 0; m < MM; ++m) qm[m] = __shfl(qa, m, G);
+        for (int f = f0 + l16; f < f1; f += G) {
+          double fv = 0.0;
+#pragma unroll
+          for (int m = 0; m < MM; ++m)
+            if (m < Nm) fv += qm[m] * BB[f * Nm + m];
+          FZ[FN[f]] = (float)(-a.kappa * fv);
+        }
       }
     }
     // (3) receivers: 16 lanes per receiver, all 64 groups of the workgroup
@@ -259,8 +268,7 @@ __global__ void __launch_bounds__(kResThreads) k_resident(const ResidentArgs a) 
             v += w[i] * w[n1 + j] * w[2 * n1 + c] * (double)P[cb + i + nx * (j + ny * c)];
           }
         }
-#pragma unroll
-        for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
+        v = res_group_sum<16>(v);
         if (r < a.R && l16 == 0) {
           if (cnt < a.tcap) a.traces[((long)s * a.R + r) * a.tcap + cnt] = v;
           if (!__builtin_isfinite(v)) atomicOr(a.nonfinite, 1);
@@ -297,15 +305,20 @@ __global__ void k_tick_n(long* counter, long n) {
   if (threadIdx.x == 0) *counter += n;
 }
 
-template <int N, int MM>
-hipError_t res_launch_nm(const ResidentArgs& a, hipStream_t st) {
+template <int N, int MM, int G>
+hipError_t res_launch_nmg(const ResidentArgs& a, hipStream_t st) {
   if (a.lds_bytes > 65536) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_resident<N, MM>),
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_resident<N, MM, G>),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, a.lds_bytes);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_resident<N, MM>), dim3(a.S), dim3(kResThreads), a.lds_bytes, st, a);
+  hipLaunchKernelGGL((k_resident<N, MM, G>), dim3(a.S), dim3(kResThreads), a.lds_bytes, st, a);
   return hipGetLastError();
+}
+
+template <int N, int MM>
+hipError_t res_launch_nm(const ResidentArgs& a, hipStream_t st) {
+  return a.pm_wide ? res_launch_nmg<N, MM, 64>(a, st) : res_launch_nmg<N, MM, 16>(a, st);
 }
 
 template <int N>
