@@ -106,14 +106,19 @@ struct Tile {
 // consecutive tiles that share the same B (weight) tile, which then stays in
 // that XCD's L2.  Operand rows are staged in LDS padded by 8 elements, so
 // the 16-byte fragment reads of 32 consecutive rows hit distinct banks.
+// The next slice is fetched into registers before the MFMAs of the current
+// one and written to the other LDS buffer after them, so its memory latency
+// overlaps the arithmetic; one barrier per slice.  LDS is dynamic:
+// 2 (BM + BN) LDK elements.
 template <bool ACON, bool BCON, int EPI, int TM, int TN, int BK>
 __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
   using TL = Tile<TM, TN, BK>;
   constexpr int BM = TL::BM, BN = TL::BN, LDK = TL::LDK;
   constexpr int CA = BM * BK / 8 / 256, CB = BN * BK / 8 / 256;  // 8-element chunks per thread
   static_assert(CA * 256 * 8 == BM * BK && CB * 256 * 8 == BN * BK, "tile must split into chunks");
-  __shared__ __attribute__((aligned(16))) bf16_t As[2][BM * LDK];
-  __shared__ __attribute__((aligned(16))) bf16_t Bs[2][BN * LDK];
+  extern __shared__ __attribute__((aligned(16))) bf16_t gemm_lds[];
+  bf16_t* const As0 = gemm_lds;
+  bf16_t* const Bs0 = gemm_lds + 2 * BM * LDK;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
 
@@ -127,22 +132,47 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
 
   // contiguous operand: chunk c covers row c / (BK/8), reduction 8 (c % (BK/8));
   // strided operand: chunk c covers reduction c / (B?/8), rows 8 (c % (B?/8))
-  auto load_tile = [&](int buf, int k0) {
+  uint4 ra[CA], rb[CB];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int c2 = 0; c2 < CA; ++c2) {
+      const int c = tid + 256 * c2;
+      ra[c2] = make_uint4(0, 0, 0, 0);
+      if (ACON) {
+        const int row = c / (BK / 8), kc = (c % (BK / 8)) * 8;
+        if (m0 + row < g.M && k0 + kc < kend) ra[c2] = *(const uint4*)(g.A + (long)(m0 + row) * g.lda + k0 + kc);
+      } else {
+        const int r = c / (BM / 8), ic = (c % (BM / 8)) * 8;
+        if (k0 + r < kend && m0 + ic < g.M) ra[c2] = *(const uint4*)(g.A + (long)(k0 + r) * g.lda + m0 + ic);
+      }
+    }
+#pragma unroll
+    for (int c2 = 0; c2 < CB; ++c2) {
+      const int c = tid + 256 * c2;
+      rb[c2] = make_uint4(0, 0, 0, 0);
+      if (BCON) {
+        const int col = c / (BK / 8), kc = (c % (BK / 8)) * 8;
+        if (n0 + col < g.N && k0 + kc < kend) rb[c2] = *(const uint4*)(g.B + (long)(n0 + col) * g.ldb + k0 + kc);
+      } else {
+        const int r = c / (BN / 8), jc = (c % (BN / 8)) * 8;
+        if (k0 + r < kend && n0 + jc < g.N) rb[c2] = *(const uint4*)(g.B + (long)(k0 + r) * g.ldb + n0 + jc);
+      }
+    }
+  };
+  auto stash = [&](int buf) {
+    bf16_t* As = As0 + buf * BM * LDK;
+    bf16_t* Bs = Bs0 + buf * BN * LDK;
 #pragma unroll
     for (int c2 = 0; c2 < CA; ++c2) {
       const int c = tid + 256 * c2;
       if (ACON) {
         const int row = c / (BK / 8), kc = (c % (BK / 8)) * 8;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (m0 + row < g.M && k0 + kc < kend) v = *(const uint4*)(g.A + (long)(m0 + row) * g.lda + k0 + kc);
-        *(uint4*)&As[buf][row * LDK + kc] = v;
+        *(uint4*)&As[row * LDK + kc] = ra[c2];
       } else {
         const int r = c / (BM / 8), ic = (c % (BM / 8)) * 8;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (k0 + r < kend && m0 + ic < g.M) v = *(const uint4*)(g.A + (long)(k0 + r) * g.lda + m0 + ic);
-        const bf16_t* e = (const bf16_t*)&v;
+        const bf16_t* e = (const bf16_t*)&ra[c2];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) As[buf][(ic + q) * LDK + r] = e[q];
+        for (int q = 0; q < 8; ++q) As[(ic + q) * LDK + r] = e[q];
       }
     }
 #pragma unroll
@@ -150,16 +180,12 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
       const int c = tid + 256 * c2;
       if (BCON) {
         const int col = c / (BK / 8), kc = (c % (BK / 8)) * 8;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (n0 + col < g.N && k0 + kc < kend) v = *(const uint4*)(g.B + (long)(n0 + col) * g.ldb + k0 + kc);
-        *(uint4*)&Bs[buf][col * LDK + kc] = v;
+        *(uint4*)&Bs[col * LDK + kc] = rb[c2];
       } else {
         const int r = c / (BN / 8), jc = (c % (BN / 8)) * 8;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (k0 + r < kend && n0 + jc < g.N) v = *(const uint4*)(g.B + (long)(k0 + r) * g.ldb + n0 + jc);
-        const bf16_t* e = (const bf16_t*)&v;
+        const bf16_t* e = (const bf16_t*)&rb[c2];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) Bs[buf][(jc + q) * LDK + r] = e[q];
+        for (int q = 0; q < 8; ++q) Bs[(jc + q) * LDK + r] = e[q];
       }
     }
   };
@@ -173,23 +199,29 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
   const int nk = (kend - kbeg + BK - 1) / BK;
-  if (nk > 0) load_tile(0, kbeg);
+  if (nk > 0) {
+    fetch(kbeg);
+    stash(0);
+  }
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
-    if (kt + 1 < nk) load_tile(buf ^ 1, kbeg + (kt + 1) * BK);
+    const bool more = kt + 1 < nk;
+    if (more) fetch(kbeg + (kt + 1) * BK);
+    const bf16_t* As = As0 + buf * BM * LDK;
+    const bf16_t* Bs = Bs0 + buf * BN * LDK;
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 16) {
       bf16x8 af[TM], bfr[TN];
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
         const int row = wm * 32 * TM + i * 32 + (lane & 31);
-        af[i] = *(const bf16x8*)&As[buf][row * LDK + kk + (lane >> 5) * 8];
+        af[i] = *(const bf16x8*)&As[row * LDK + kk + (lane >> 5) * 8];
       }
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
         const int col = wn * 32 * TN + j * 32 + (lane & 31);
-        bfr[j] = *(const bf16x8*)&Bs[buf][col * LDK + kk + (lane >> 5) * 8];
+        bfr[j] = *(const bf16x8*)&Bs[col * LDK + kk + (lane >> 5) * 8];
       }
 #pragma unroll
       for (int i = 0; i < TM; ++i)
@@ -197,21 +229,83 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
         for (int j = 0; j < TN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
     }
+    // buffer buf ^ 1 was last read in the previous slice, before its barrier
+    if (more) stash(buf ^ 1);
     __syncthreads();
   }
 
-  float* part = g.ks > 1 ? g.part + (long)z * g.M * g.N : nullptr;
+  auto row_of = [&](int i, int r) { return m0 + wm * 32 * TM + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3); };
+  auto col_of = [&](int j) { return n0 + wn * 32 * TN + j * 32 + (lane & 31); };
+  if (g.ks > 1) {
+    float* part = g.part + (long)z * g.M * g.N;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = row_of(i, r), col = col_of(j);
+          if (row < g.M && col < g.N) part[(long)row * g.N + col] = acc[i][j][r];
+        }
+    return;
+  }
+  // The epilogue's operands (bias, row factors, pre-activations) are all
+  // loaded before the first store, unconditionally from clamped indices:
+  // the stores may alias them as far as the compiler knows, and a load
+  // under a branch, or after a store, waits for its own result there, once
+  // per element.
+  float bj[TN], rs[TM][16];
+  const bool scaled = EPI == EPI_FWD_LIN && g.Y != nullptr;
+  if (EPI == EPI_FWD_GELU || EPI == EPI_FWD_LIN) {
+#pragma unroll
+    for (int j = 0; j < TN; ++j) bj[j] = g.bias[min(col_of(j), g.N - 1)];
+  }
+  if (scaled) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) rs[i][r] = g.out_scale * g.rowscale[min(row_of(i, r), g.M - 1)];
+  }
+  if (EPI == EPI_DX_GELU) {
+    float zp[TM][TN][16];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          zp[i][j][r] = g.Zprev[(long)min(row_of(i, r), g.M - 1) * g.ldc + min(col_of(j), g.N - 1)];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[i][j][r] *= gelu_d(zp[i][j][r]);
+  }
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
     for (int j = 0; j < TN; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int row = m0 + wm * 32 * TM + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-        const int col = n0 + wn * 32 * TN + j * 32 + (lane & 31);
+        const int row = row_of(i, r), col = col_of(j);
         if (row >= g.M || col >= g.N) continue;
-        if (part) part[(long)row * g.N + col] = acc[i][j][r];
-        else epilogue<EPI>(g, row, col, acc[i][j][r]);
+        const long o = (long)row * g.ldc + col;
+        const float v = acc[i][j][r];
+        if (EPI == EPI_FWD_GELU) {
+          const float zz = v + bj[j];
+          g.Cf[o] = zz;
+          g.Cb[o] = f2bf(gelu(zz));
+        } else if (EPI == EPI_FWD_LIN) {
+          const float zz = v + bj[j];
+          if (scaled) g.Y[o] = rs[i][r] * zz;
+          else g.Cf[o] = zz;
+        } else if (EPI == EPI_DX_GELU) {
+          g.Cf[o] = v;
+          g.Cb[o] = f2bf(v);
+        } else {
+          g.Cf[o] = v;
+        }
       }
 }
 
@@ -421,7 +515,13 @@ hipError_t gemm_t(GemmArgs g, float* part, hipStream_t st) {
     g.kchunk = ((g.K + 31) / 32) * 32;
     g.ks = 1;
   }
-  hipLaunchKernelGGL((k_gemm<ACON, BCON, EPI, TM, TN, BK>), dim3(g.mt * g.nt * g.ks), dim3(256), 0, st, g);
+  const size_t lds = sizeof(bf16_t) * 2 * (TL::BM + TL::BN) * TL::LDK;
+  if (lds > 65536) {
+    const hipError_t attr = hipFuncSetAttribute((const void*)k_gemm<ACON, BCON, EPI, TM, TN, BK>,
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (attr != hipSuccess) return attr;
+  }
+  hipLaunchKernelGGL((k_gemm<ACON, BCON, EPI, TM, TN, BK>), dim3(g.mt * g.nt * g.ks), dim3(256), lds, st, g);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || g.ks == 1) return e;
   hipLaunchKernelGGL((k_splitk_reduce<EPI>), dim3((unsigned)nblk((long)g.M * g.N, 256)), dim3(256), 0, st, g);
@@ -430,13 +530,16 @@ hipError_t gemm_t(GemmArgs g, float* part, hipStream_t st) {
 
 // Tile choice: 64 x 64 tiles where 128 x 128 tiles would leave most CUs
 // idle and the reduction is short (the hidden and first layers), else
-// 128 x 128 with split-K.  (Wider 2 x 4 blocks per wave measured slower: at
-// 268 registers one wave per SIMD cannot hide the LDS and memory latency.)
+// 128 x 128 with split-K, over 64-deep slices (32-deep when both operands
+// are strided: their LDS scatter then measured faster).  (Wider 2 x 4 blocks
+// per wave measured slower: at 268 registers one wave per SIMD cannot hide
+// the LDS and memory latency.)
 template <bool ACON, bool BCON, int EPI>
 hipError_t gemm(GemmArgs g, float* part, hipStream_t st) {
   const long mid = (long)((g.M + 127) / 128) * ((g.N + 127) / 128);
   if (mid < kTargetBlocks / 4 && g.K <= 2048) return gemm_t<ACON, BCON, EPI, 1, 1, 32>(g, part, st);
-  return gemm_t<ACON, BCON, EPI, 2, 2, 32>(g, part, st);
+  if (!ACON && !BCON) return gemm_t<ACON, BCON, EPI, 2, 2, 32>(g, part, st);
+  return gemm_t<ACON, BCON, EPI, 2, 2, 64>(g, part, st);
 }
 
 
