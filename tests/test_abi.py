@@ -96,7 +96,7 @@ def test_setup_errors_and_state_errors():
     two.set_pml(0, [0.25] * 4 + [0, 0], 1e-4)
     assert two.workspace_size() > 0
     assert _err(s.set_option, _lib.OPT_PREFETCH, 1) == _lib.PMDG_EINVAL
-    assert _err(s.set_option, _lib.OPT_OVERLAP, 3) == _lib.PMDG_EINVAL
+    assert _err(s.set_option, _lib.OPT_OVERLAP, 4) == _lib.PMDG_EINVAL
     assert _err(s.set_option, _lib.OPT_PREFETCH, 5) == _lib.PMDG_EINVAL
     s.set_option(_lib.OPT_PREFETCH, 4)
     s.set_option(_lib.OPT_PREFETCH, 2)
