@@ -229,6 +229,18 @@ pmdg_status pmdg_bind(pmdg_solver* h, void* dev_ptr, size_t bytes, void* stream)
  * overlap on one GPU race on the array. */
 pmdg_status pmdg_bind_static(pmdg_solver* h, void* stream);
 
+/* Returns a bound solver to step 0 with everything at rest, as pmdg_bind
+ * left it: the workspace is zeroed (pressure levels, increments, layer
+ * fields, modal states, traces, step counter) and every table uploaded
+ * again, in the same memory (caller-owned or library-held).  Meshes,
+ * operators, PMUTs, receivers, options and the drive are kept; call
+ * pmdg_set_drive before or after to run other drive scenarios with the
+ * same solver, without building it again (the set-up of pmdg_create and
+ * the set_* calls costs far more than a short run of a small mesh).
+ * Returns when the work enqueued on stream is done.  Unbound solver, or
+ * one whose library-held workspace was taken by another solver: ESTATE. */
+pmdg_status pmdg_restart(pmdg_solver* h, void* stream);
+
 /* The time step in use. */
 pmdg_status pmdg_get_dt(pmdg_solver* h, double* dt);
 

@@ -72,6 +72,7 @@ _SIGS = {
     "pmdg_workspace_size": [_vp, ctypes.POINTER(ctypes.c_size_t)],
     "pmdg_bind": [_vp, _vp, ctypes.c_size_t, _vp],
     "pmdg_bind_static": [_vp, _vp],
+    "pmdg_restart": [_vp, _vp],
     "pmdg_get_dt": [_vp, _dp],
     "pmdg_lambda_max": [_vp, _dp],
     "pmdg_step": [_vp, ctypes.c_int, _vp],

@@ -197,6 +197,10 @@ struct pmdg_solver {
   std::vector<double> amp, phase, freq;
   double ncyc = 3, t_switch = INFINITY, rx_cap = 1;
   int envelope = 0;
+  // drive tables as last uploaded (valid once bound: restart uploads them
+  // again without recomputing them)
+  std::vector<double> dA_h, car_h;
+  bool drive_cached = false;
   // receivers
   int R = 0;
   std::vector<int> r_dom;
@@ -206,6 +210,7 @@ struct pmdg_solver {
   bool bound = false;
   char* ws = nullptr;
   size_t ws_bytes = 0;
+  size_t ws_need = 0;  // bytes the layout uses (zeroed by bind and restart)
   std::map<std::string, Seg> seg;
   long steps_done = 0;
   // options
@@ -646,6 +651,7 @@ static void drive_tables(const pmdg_solver* s, std::vector<double>& dA, std::vec
     for (long n = 0; n <= s->cap; ++n) {
       const double t = n * s->dt;
       const double g = drive_window(t, Td, s->envelope);
+      if (g == 0.0) continue;  // outside the burst the carrier entries stay zero
       car[((size_t)sc * (s->cap + 1) + n) * 2] = g * std::sin(2.0 * M_PI * f * t);
       car[((size_t)sc * (s->cap + 1) + n) * 2 + 1] = g * std::cos(2.0 * M_PI * f * t);
     }
@@ -2077,14 +2083,15 @@ pmdg_status pmdg_set_drive(pmdg_solver* s, const double* amp, const double* phas
   s->freq.assign(freq, freq + s->S);
   s->ncyc = ncyc;
   s->envelope = envelope;
+  s->drive_cached = false;
   drop_graphs(s);
   if (s->bound && s->Np > 0) {
     hipStream_t st = nullptr;
     pmdg_status r;
-    std::vector<double> dA, car;
-    drive_tables(s, dA, car);
-    if ((r = upload_vec(s, "dA", dA, st))) return r;
-    if ((r = upload_vec(s, "car", car, st))) return r;
+    drive_tables(s, s->dA_h, s->car_h);
+    s->drive_cached = true;
+    if ((r = upload_vec(s, "dA", s->dA_h, st))) return r;
+    if ((r = upload_vec(s, "car", s->car_h, st))) return r;
   }
   return PMDG_OK;
 }
@@ -2385,6 +2392,41 @@ pmdg_status pmdg_workspace_size(pmdg_solver* s, size_t* bytes) {
   return PMDG_OK;
 }
 
+}  // extern "C"
+
+// Zeroes the solver's workspace and uploads every table: the state of
+// step 0, everything at rest (pmdg_bind and pmdg_restart).
+static pmdg_status fill_workspace(pmdg_solver* s, hipStream_t st) {
+  // fill kernel: safe under capture on any stream
+  HIPCHK(launch_fill_bytes(s->ws, s->ws_need / 4 * 4, st));
+  pmdg_status r = s->prec == 64 ? bind_tables<double>(s, st) : bind_tables<float>(s, st);
+  if (r) return r;
+  if (s->Np > 0) {
+    if ((r = upload_vec(s, "pm_off", s->pm_off, st))) return r;
+    if ((r = upload_vec(s, "pm_node", s->pm_node, st))) return r;
+    if ((r = upload_vec(s, "pm_B", s->pm_B, st))) return r;
+    if ((r = upload_vec(s, "omega", s->omega, st))) return r;
+    if ((r = upload_vec(s, "zeta", s->zeta, st))) return r;
+    if ((r = upload_vec(s, "eta", s->eta, st))) return r;
+    if (!s->drive_cached) {
+      drive_tables(s, s->dA_h, s->car_h);
+      s->drive_cached = true;
+    }
+    if ((r = upload_vec(s, "dA", s->dA_h, st))) return r;
+    if ((r = upload_vec(s, "car", s->car_h, st))) return r;
+  }
+  if (s->R > 0) {
+    if ((r = upload_vec(s, "r_dom", s->r_dom, st))) return r;
+    if ((r = upload_vec(s, "r_base", s->r_base, st))) return r;
+    if ((r = upload_vec(s, "r_w", s->r_w, st))) return r;
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  s->steps_done = 0;
+  return PMDG_OK;
+}
+
+extern "C" {
+
 pmdg_status pmdg_bind(pmdg_solver* s, void* dev_ptr, size_t bytes, void* stream) {
   if (!s) return fail(PMDG_EINVAL, "NULL solver");
   if (s->bound) return fail(PMDG_ESTATE, "already bound");
@@ -2393,34 +2435,24 @@ pmdg_status pmdg_bind(pmdg_solver* s, void* dev_ptr, size_t bytes, void* stream)
     if (!s->shape_set[k]) return fail(PMDG_ESTATE, "mode shape of PMUT " + std::to_string(k) + " not set");
   const size_t need = layout(s);
   if (bytes < need) return fail(PMDG_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
-  hipStream_t st = (hipStream_t)stream;
   s->ws = (char*)dev_ptr;
   s->ws_bytes = bytes;
-  // zero everything (fill kernel: safe under capture on any stream)
-  HIPCHK(launch_fill_bytes(s->ws, need / 4 * 4, st));
-  pmdg_status r = s->prec == 64 ? bind_tables<double>(s, st) : bind_tables<float>(s, st);
-  if (r) { s->ws = nullptr; return r; }
-  if (s->Np > 0) {
-    if ((r = upload_vec(s, "pm_off", s->pm_off, st))) return r;
-    if ((r = upload_vec(s, "pm_node", s->pm_node, st))) return r;
-    if ((r = upload_vec(s, "pm_B", s->pm_B, st))) return r;
-    if ((r = upload_vec(s, "omega", s->omega, st))) return r;
-    if ((r = upload_vec(s, "zeta", s->zeta, st))) return r;
-    if ((r = upload_vec(s, "eta", s->eta, st))) return r;
-    std::vector<double> dA, car;
-    drive_tables(s, dA, car);
-    if ((r = upload_vec(s, "dA", dA, st))) return r;
-    if ((r = upload_vec(s, "car", car, st))) return r;
+  s->ws_need = need;
+  const pmdg_status r = fill_workspace(s, (hipStream_t)stream);
+  if (r) {
+    s->ws = nullptr;
+    return r;
   }
-  if (s->R > 0) {
-    if ((r = upload_vec(s, "r_dom", s->r_dom, st))) return r;
-    if ((r = upload_vec(s, "r_base", s->r_base, st))) return r;
-    if ((r = upload_vec(s, "r_w", s->r_w, st))) return r;
-  }
-  HIPCHK(hipStreamSynchronize(st));
   s->bound = true;
-  s->steps_done = 0;
   return PMDG_OK;
+}
+
+pmdg_status pmdg_restart(pmdg_solver* s, void* stream) {
+  if (!s) return fail(PMDG_EINVAL, "NULL solver");
+  if (!s->bound) return fail(PMDG_ESTATE, "not bound");
+  if (ws_lost(s)) return fail(PMDG_ESTATE, kLostMsg);
+  drop_graphs(s);
+  return fill_workspace(s, (hipStream_t)stream);
 }
 
 pmdg_status pmdg_bind_static(pmdg_solver* s, void* stream) {

@@ -174,6 +174,11 @@ class Solver:
         allocation by anyone)."""
         check(self.L.pmdg_bind_static(self.h, _stream_ptr(stream)))
 
+    def restart(self, stream=None):
+        """Back to step 0 with everything at rest, tables and drive kept
+        (pmdg_restart)."""
+        check(self.L.pmdg_restart(self.h, _stream_ptr(stream)))
+
     def set_option(self, opt, value):
         check(self.L.pmdg_set_option(self.h, int(opt), int(value)))
 

@@ -73,6 +73,8 @@ def test_setup_errors_and_state_errors():
     n = len(s.pmut_face_nodes(0))
     assert _err(s.set_pmut_shape, 0, np.full(n, 1e3)) == _lib.PMDG_EUNSTABLE
     assert _err(s.step, 1, 0) == _lib.PMDG_ESTATE
+    assert s.L.pmdg_restart(s.h, None) == _lib.PMDG_ESTATE  # restart needs a bound solver
+    assert s.L.pmdg_restart(None, None) == _lib.PMDG_EINVAL
     assert _err(s.set_option, 2, 3) == _lib.PMDG_EINVAL
     assert _err(s.set_option, 2, -1) == _lib.PMDG_EINVAL
     s.set_option(2, 0)                                             # automatic rows per wave

@@ -85,43 +85,60 @@ def test_held_out_error_and_coverage(data, trained):
 
 def test_fallback_delivers_tolerance_and_gain(data, trained):
     """Inference with fallback on the 256 test scenarios: rows whose estimate
-    exceeds 2% carry the solver's traces, bitwise; the delivered traces meet
-    2% except for the estimate's non-covered share; the pipeline's
-    scenarios/s is above the plain solver's, one scenario at a time and in one
-    batched launch for all 256 (the method without the network)."""
+    exceeds 2% carry the solver's traces, bitwise, and the delivered traces
+    meet 2% except for the estimate's non-covered share.  Throughput on a
+    fresh batch of 1,024 seeded scenarios, every call timed after an untimed
+    one of the same size (the solvers that solve restarts then exist): the
+    pipeline's scenarios/s is above the plain solver's, one scenario at a
+    time and in one batched launch for all 1,024 (the method without the
+    network).  At a few hundred scenarios the batched solver does not fill
+    the GPU, so a fallback of a tenth of them costs about as much as all of
+    them; hence the larger batch."""
     import torch
     F, U, T = data
     rows = TEST
     trained.infer(F[rows])  # warm
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
     out, mask, est = trained.infer(F[rows])
     torch.cuda.synchronize()
-    el = time.perf_counter() - t0
     t = T[torch.as_tensor(rows, device="cuda")]
     err = (torch.linalg.vector_norm(out - t, dim=1) / torch.linalg.vector_norm(t, dim=1)).cpu().numpy()
     _say(f"  routed to the solver: {mask.mean():.3f}; delivered rel L2 median {np.median(err):.2e}, "
-         f"share above 2%: {(err > S.TOL).mean():.3f}; {len(rows) / el:.0f} scenarios/s")
+         f"share above 2%: {(err > S.TOL).mean():.3f}")
     if mask.any():
         assert torch.equal(out[torch.as_tensor(np.nonzero(mask)[0], device="cuda")],
                            t[torch.as_tensor(np.nonzero(mask)[0], device="cuda")])
     assert (err > S.TOL).mean() <= 0.08
     assert mask.mean() < 0.5
-    # the plain solver one scenario at a time (8 of them, timed)
+    # a fresh batch of 1024 scenarios
+    rng = np.random.default_rng(W.SEED0 + 91)
+    ph, fr, am = W.scenario_params(rng, 1024)
+    Fb = np.concatenate([ph, fr[:, None], am[:, None]], 1)
+    S.solve(Fb)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for r in rows[:8]:
-        S.solve(F[r:r + 1])
+    Tb = S.solve(Fb)
+    torch.cuda.synchronize()
+    batched = len(Fb) / (time.perf_counter() - t0)
+    trained.infer(Fb)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outb, maskb, _ = trained.infer(Fb)
+    torch.cuda.synchronize()
+    pipe = len(Fb) / (time.perf_counter() - t0)
+    errb = (torch.linalg.vector_norm(outb - Tb, dim=1) / torch.linalg.vector_norm(Tb, dim=1)).cpu().numpy()
+    # the plain solver one scenario at a time (8 of them, timed)
+    S.solve(Fb[:1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(8):
+        S.solve(Fb[r:r + 1])
     torch.cuda.synchronize()
     single = 8 / (time.perf_counter() - t0)
-    # and batched: all 256 test scenarios in one launch
-    S.solve(F[rows[:8]])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    S.solve(F[rows])
-    torch.cuda.synchronize()
-    batched = len(rows) / (time.perf_counter() - t0)
-    pipe = len(rows) / el
-    _say(f"  plain solver: {single:.1f} scenarios/s one at a time, {batched:.1f} batched; pipeline gain "
-         f"{pipe / single:.1f}x and {pipe / batched:.2f}x")
+    _say(f"  1024 fresh scenarios: routed {maskb.mean():.3f}, delivered share above 2% {(errb > S.TOL).mean():.4f}; "
+         f"pipeline {pipe:.0f} scenarios/s; plain solver {single:.1f} one at a time, {batched:.0f} batched; "
+         f"gain {pipe / single:.1f}x and {pipe / batched:.2f}x")
+    assert (errb > S.TOL).mean() <= 0.08
+    assert maskb.mean() < 0.5
     assert pipe > single
     assert pipe > batched
