@@ -40,6 +40,17 @@ __device__ __forceinline__ long hex_yidx(const HexArgs<Real>& a, int ex, int ey,
   return (((long)(ez * a.ne[1] + ey) * n1 + lc) * n1 + lb) * ((long)a.ne[0] * n1) + (long)ex * n1 + la;
 }
 
+// 1 / x: the hardware reciprocal in FP32 (1 ulp, for the metric's 1 / |J|
+// with |J| > 0), IEEE division in FP64
+template <typename Real>
+__device__ __forceinline__ Real hex_rcp(Real x) {
+  return Real(1) / x;
+}
+template <>
+__device__ __forceinline__ float hex_rcp<float>(float x) {
+  return __builtin_amdgcn_rcpf(x);
+}
+
 template <typename Real, int N>
 __global__ void __launch_bounds__(256) k_hex_elem(const HexArgs<Real> a) {
   constexpr int n1 = N + 1, n2 = n1 * n1, n3 = n2 * n1, SX = hex_sx<N>(), UX = SX * N + 1;
@@ -50,11 +61,12 @@ __global__ void __launch_bounds__(256) k_hex_elem(const HexArgs<Real> a) {
   __shared__ Real Dm[n2], Wq[n1], Xq[n1];
   const int tid = threadIdx.x;
   const int nsx = (a.ne[0] + SX - 1) / SX;
-  long t = blockIdx.x;
-  const int sx = (int)(t % nsx); t /= nsx;
-  const int ey = (int)(t % a.ne[1]); t /= a.ne[1];
-  const int ez = (int)(t % a.ne[2]);
-  const int s = (int)(t / a.ne[2]);
+  // 32-bit block decomposition (the grid is far below 2^31 blocks)
+  int t = (int)blockIdx.x;
+  const int sx = t % nsx; t /= nsx;
+  const int ey = t % a.ne[1]; t /= a.ne[1];
+  const int ez = t % a.ne[2];
+  const int s = t / a.ne[2];
   const int ex0 = sx * SX, nsx_here = min(SX, a.ne[0] - ex0);
   const long cnt = *a.counter;
   const Real* __restrict__ P = a.d.P[(int)(cnt % a.d.nbuf)] + (long)s * a.d.nnodes;
@@ -63,12 +75,13 @@ __global__ void __launch_bounds__(256) k_hex_elem(const HexArgs<Real> a) {
     Wq[tid] = a.w[tid];
     Xq[tid] = a.xg[tid];
   }
-  // p on the strip: rows of nsx_here N + 1 consecutive nodes
+  // p on the strip: rows of nsx_here N + 1 consecutive nodes (indices
+  // split by the compile-time row width UX, entries past the strip skipped)
   const int ux = nsx_here * N + 1;
-  for (int w = tid; w < n2 * ux; w += 256) {
-    const int row = w / ux, xl = w - row * ux, lb = row % n1, lc = row / n1;
-    const long node = (long)(ex0 * N + xl) + (long)a.d.px * (ey * N + lb) + a.d.plane * (ez * N + lc);
-    u[row * UX + xl] = P[node];
+  const Real* __restrict__ P0 = P + (long)ex0 * N + (long)a.d.px * (ey * N) + a.d.plane * (ez * N);
+  for (int w = tid; w < n2 * UX; w += 256) {
+    const int row = w / UX, xl = w - row * UX, lb = row % n1, lc = row / n1;
+    if (xl < ux) u[row * UX + xl] = P0[xl + (long)a.d.px * lb + a.d.plane * lc];
   }
   // half edge vectors: edges along axis d join corners c and c | (1 << d)
   // for the four c with bit d clear, in increasing order of c
@@ -94,7 +107,8 @@ __global__ void __launch_bounds__(256) k_hex_elem(const HexArgs<Real> a) {
     // half edges along d in the other two reference coordinates: column 2
     // depends on (a, b) only; columns 0 and 1 are blended along c below
     const Real xa = Xq[ia], xb = Xq[ib];
-    Real c2[3], A0[3], A1[3], B0[3], B1[3];
+    // columns 0 and 1 are linear in the third coordinate zc: M + zc D
+    Real c2[3], MA[3], DA[3], MB[3], DB[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       // axis 2 edges: bits (0, 1) = (a, b)
@@ -102,11 +116,15 @@ __global__ void __launch_bounds__(256) k_hex_elem(const HexArgs<Real> a) {
       const Real hi = Real(0.5) * ((1 - xa) * E[el][10][k] + (1 + xa) * E[el][11][k]);
       c2[k] = Real(0.5) * ((1 - xb) * lo + (1 + xb) * hi);
       // axis 0 edges: bits (1, 2) = (b, c); blend along b now, along c later
-      A0[k] = Real(0.5) * ((1 - xb) * E[el][0][k] + (1 + xb) * E[el][1][k]);
-      A1[k] = Real(0.5) * ((1 - xb) * E[el][2][k] + (1 + xb) * E[el][3][k]);
+      const Real A0 = Real(0.5) * ((1 - xb) * E[el][0][k] + (1 + xb) * E[el][1][k]);
+      const Real A1 = Real(0.5) * ((1 - xb) * E[el][2][k] + (1 + xb) * E[el][3][k]);
       // axis 1 edges: bits (0, 2) = (a, c)
-      B0[k] = Real(0.5) * ((1 - xa) * E[el][4][k] + (1 + xa) * E[el][5][k]);
-      B1[k] = Real(0.5) * ((1 - xa) * E[el][6][k] + (1 + xa) * E[el][7][k]);
+      const Real B0 = Real(0.5) * ((1 - xa) * E[el][4][k] + (1 + xa) * E[el][5][k]);
+      const Real B1 = Real(0.5) * ((1 - xa) * E[el][6][k] + (1 + xa) * E[el][7][k]);
+      MA[k] = Real(0.5) * (A0 + A1);
+      DA[k] = Real(0.5) * (A1 - A0);
+      MB[k] = Real(0.5) * (B0 + B1);
+      DB[k] = Real(0.5) * (B1 - B0);
     }
     const Real* ue = u + el * N;
     Real da[n1], db[n1], ucol[n1];
@@ -127,12 +145,8 @@ __global__ void __launch_bounds__(256) k_hex_elem(const HexArgs<Real> a) {
         g2 += Dm[ic * n1 + m] * ucol[m];
       }
       const Real zc = Xq[ic];
-      const Real J00 = Real(0.5) * ((1 - zc) * A0[0] + (1 + zc) * A1[0]);
-      const Real J10 = Real(0.5) * ((1 - zc) * A0[1] + (1 + zc) * A1[1]);
-      const Real J20 = Real(0.5) * ((1 - zc) * A0[2] + (1 + zc) * A1[2]);
-      const Real J01 = Real(0.5) * ((1 - zc) * B0[0] + (1 + zc) * B1[0]);
-      const Real J11 = Real(0.5) * ((1 - zc) * B0[1] + (1 + zc) * B1[1]);
-      const Real J21 = Real(0.5) * ((1 - zc) * B0[2] + (1 + zc) * B1[2]);
+      const Real J00 = MA[0] + zc * DA[0], J10 = MA[1] + zc * DA[1], J20 = MA[2] + zc * DA[2];
+      const Real J01 = MB[0] + zc * DB[0], J11 = MB[1] + zc * DB[1], J21 = MB[2] + zc * DB[2];
       const Real J02 = c2[0], J12 = c2[1], J22 = c2[2];
       const Real A00 = J11 * J22 - J12 * J21, A01 = J02 * J21 - J01 * J22, A02 = J01 * J12 - J02 * J11;
       const Real A10 = J12 * J20 - J10 * J22, A11 = J00 * J22 - J02 * J20, A12 = J02 * J10 - J00 * J12;
@@ -142,7 +156,7 @@ __global__ void __launch_bounds__(256) k_hex_elem(const HexArgs<Real> a) {
       const Real hx = A00 * g0 + A10 * g1 + A20 * g2;
       const Real hy = A01 * g0 + A11 * g1 + A21 * g2;
       const Real hz = A02 * g0 + A12 * g1 + A22 * g2;
-      const Real sc = wab * Wq[ic] / det;
+      const Real sc = wab * Wq[ic] * hex_rcp(det);
       const int o = el * n3 + (ic * n1 + ib) * n1 + ia;
       F0[o] = sc * (A00 * hx + A01 * hy + A02 * hz);
       F1[o] = sc * (A10 * hx + A11 * hy + A12 * hz);
@@ -153,19 +167,28 @@ __global__ void __launch_bounds__(256) k_hex_elem(const HexArgs<Real> a) {
   if (!active) return;
   // transposed contraction: the test function's reference gradient at each
   // node; component 2 runs along this thread's own column
-  Real* __restrict__ Y = a.y + (long)s * a.nel * n3;
+  // this thread's column of residual entries: consecutive c are one
+  // (N+1) x (row length) block apart
+  Real* __restrict__ Yc = a.y + (long)s * a.nel * n3 + hex_yidx<N>(a, ex0 + el, ey, ez, ia, ib, 0);
+  const long ystride = (long)n1 * n1 * a.ne[0];
   const Real* f0 = F0 + el * n3;
   const Real* f1 = F1 + el * n3;
+  Real dta[n1], dtb[n1];
+#pragma unroll
+  for (int m = 0; m < n1; ++m) {
+    dta[m] = Dm[m * n1 + ia];
+    dtb[m] = Dm[m * n1 + ib];
+  }
 #pragma unroll
   for (int ic = 0; ic < n1; ++ic) {
     Real v = 0;
 #pragma unroll
     for (int m = 0; m < n1; ++m) {
-      v += Dm[m * n1 + ia] * f0[(ic * n1 + ib) * n1 + m];
-      v += Dm[m * n1 + ib] * f1[(ic * n1 + m) * n1 + ia];
+      v += dta[m] * f0[(ic * n1 + ib) * n1 + m];
+      v += dtb[m] * f1[(ic * n1 + m) * n1 + ia];
       v += Dm[m * n1 + ic] * f2[m];
     }
-    Y[hex_yidx<N>(a, ex0 + el, ey, ez, ia, ib, ic)] = v;
+    Yc[ic * ystride] = v;
   }
 }
 
