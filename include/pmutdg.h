@@ -49,6 +49,9 @@
  *     solvers, so no second copy of a problem exists.
  *   - Traces are read into host memory (pmdg_read_traces) or device memory
  *     (pmdg_read_traces_device).
+ *   - A bound solver runs other drives after pmdg_restart (back to step 0,
+ *     everything at rest) and pmdg_set_drive, without the set-up of
+ *     pmdg_create and the set_* calls again.
  */
 #ifndef PMUTDG_H
 #define PMUTDG_H
