@@ -16,11 +16,18 @@ __device__ __forceinline__ bool run_tile(const StiffArgs<float>& a, int key, int
   return true;
 }
 
+// Workgroup b takes the items woff[b] .. woff[b+1]-1 of the work list (the
+// host balances the lists by each item's plane count), or, without woff,
+// every gridDim.x-th item from b.
 template <int NMAX>
 __global__ void __launch_bounds__(256) k_stiff_batch(const StiffArgs<float>* __restrict__ probs,
-                                                     const int2* __restrict__ items, int nitems) {
+                                                     const int2* __restrict__ items, int nitems,
+                                                     const int* __restrict__ woff) {
   extern __shared__ float lds[];
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+  const int beg = woff ? woff[blockIdx.x] : (int)blockIdx.x;
+  const int end = woff ? woff[blockIdx.x + 1] : nitems;
+  const int inc = woff ? 1 : (int)gridDim.x;
+  for (int it = beg; it < end; it += inc) {
     const int2 w = items[it];
     const StiffArgs<float>& a = probs[w.x];
     const int key = a.d.N * 4 + a.rows;
@@ -51,13 +58,13 @@ hipError_t batch_occupancy(int nmax, size_t lds, int* blocks_per_cu) {
   }
 }
 
-hipError_t launch_stiff_batch(const StiffArgs<float>* probs, const int2* items, int nitems, int nmax, int grid,
-                              size_t lds, hipStream_t st) {
+hipError_t launch_stiff_batch(const StiffArgs<float>* probs, const int2* items, int nitems, const int* woff,
+                              int nmax, int grid, size_t lds, hipStream_t st) {
   if (nitems == 0) return hipSuccess;
   switch (nmax_of(nmax)) {
-    case 4: hipLaunchKernelGGL(k_stiff_batch<4>, dim3(grid), dim3(256), lds, st, probs, items, nitems); break;
-    case 6: hipLaunchKernelGGL(k_stiff_batch<6>, dim3(grid), dim3(256), lds, st, probs, items, nitems); break;
-    default: hipLaunchKernelGGL(k_stiff_batch<8>, dim3(grid), dim3(256), lds, st, probs, items, nitems); break;
+    case 4: hipLaunchKernelGGL(k_stiff_batch<4>, dim3(grid), dim3(256), lds, st, probs, items, nitems, woff); break;
+    case 6: hipLaunchKernelGGL(k_stiff_batch<6>, dim3(grid), dim3(256), lds, st, probs, items, nitems, woff); break;
+    default: hipLaunchKernelGGL(k_stiff_batch<8>, dim3(grid), dim3(256), lds, st, probs, items, nitems, woff); break;
   }
   return hipGetLastError();
 }

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <queue>
 #include <string>
 #include <vector>
 
@@ -2771,7 +2772,7 @@ struct pmdg_batch {
   size_t lds = 0;
   int n_stiff = 0, n_face = 0, grid_stiff = 1, grid_face = 1;
   char* ws = nullptr;
-  size_t off_sargs = 0, off_fargs = 0, off_sitems = 0, off_fitems = 0, off_ctr = 0, bytes = 0;
+  size_t off_sargs = 0, off_fargs = 0, off_sitems = 0, off_fitems = 0, off_ctr = 0, off_woff = 0, bytes = 0;
   bool bound = false;
   int use_graph = 1, graph_chunk = 64;
   std::map<int, hipGraphExec_t> graphs;
@@ -2792,12 +2793,53 @@ static void batch_layout(pmdg_batch* b) {
   b->off_sitems = o; o = al256(o + (size_t)b->n_stiff * sizeof(int2));
   b->off_fitems = o; o = al256(o + (size_t)b->n_face * sizeof(int2));
   b->off_ctr = o; o = al256(o + n * sizeof(long*));
+  // per-workgroup item ranges: at most one workgroup per item
+  b->off_woff = o; o = al256(o + ((size_t)b->n_stiff + 1) * sizeof(int));
   b->bytes = o;
+}
+
+// Splits the stiffness items of a batch into `grid` per-workgroup lists of
+// about equal cost: an item's cost is the plane iterations of its z-march
+// (the planes of its chunk plus the 2N that fill the register queue) plus
+// two for its set-up.  Longest items first, each to the least loaded list
+// (ties to the lower index), so the launch ends with the longest list
+// rather than with whichever workgroup a round robin gave the most long
+// items.  Every item is computed the same way whichever workgroup takes it.
+static void balance_items(const std::vector<StiffArgs<float>>& sa, int grid, std::vector<int2>& items,
+                          std::vector<int>& woff) {
+  const int n = (int)items.size();
+  std::vector<int> cost(n), order(n);
+  for (int i = 0; i < n; ++i) {
+    const StiffArgs<float>& a = sa[items[i].x];
+    const int bz = (items[i].y / (a.nbx * a.nby)) % a.nbz;
+    const int k0 = a.zlo + bz * a.zchunk, k1 = std::min(a.zhi + 1, k0 + a.zchunk);
+    cost[i] = (k1 - k0) + 2 * a.d.N + 2;
+    order[i] = i;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  typedef std::pair<long, int> Load;  // (cost so far, list)
+  std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+  for (int g = 0; g < grid; ++g) heap.push(Load(0, g));
+  std::vector<std::vector<int>> lists(grid);
+  for (int i : order) {
+    Load l = heap.top();
+    heap.pop();
+    lists[l.second].push_back(i);
+    heap.push(Load(l.first + cost[i], l.second));
+  }
+  std::vector<int2> out;
+  out.reserve(n);
+  woff.assign(grid + 1, 0);
+  for (int g = 0; g < grid; ++g) {
+    for (int i : lists[g]) out.push_back(items[i]);
+    woff[g + 1] = (int)out.size();
+  }
+  items.swap(out);
 }
 
 static pmdg_status batch_enqueue(pmdg_batch* b, hipStream_t st) {
   HIPCHK(launch_stiff_batch((const StiffArgs<float>*)(b->ws + b->off_sargs), (const int2*)(b->ws + b->off_sitems),
-                            b->n_stiff, b->nmax, b->grid_stiff, b->lds, st));
+                            b->n_stiff, (const int*)(b->ws + b->off_woff), b->nmax, b->grid_stiff, b->lds, st));
   HIPCHK(launch_face_batch((const FaceArgs<float>*)(b->ws + b->off_fargs), (const int2*)(b->ws + b->off_fitems),
                            b->n_face, b->grid_face, b->nm_max, st));
   HIPCHK(launch_tick_batch((long* const*)(b->ws + b->off_ctr), (int)b->sv.size(), st));
@@ -2862,18 +2904,21 @@ pmdg_status pmdg_batch_bind(pmdg_batch* b, void* dev_ptr, size_t bytes, void* st
   }
   if ((int)si.size() != b->n_stiff || (int)fi.size() != b->n_face)
     return fail(PMDG_EINVAL, "internal: batch item counts differ from the layout");
-  HIPCHK(hipMemcpyAsync(b->ws + b->off_sargs, sa.data(), sa.size() * sizeof(sa[0]), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(b->ws + b->off_fargs, fa.data(), fa.size() * sizeof(fa[0]), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(b->ws + b->off_sitems, si.data(), si.size() * sizeof(int2), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(b->ws + b->off_fitems, fi.data(), fi.size() * sizeof(int2), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(b->ws + b->off_ctr, ctr.data(), ctr.size() * sizeof(long*), hipMemcpyHostToDevice, st));
-  HIPCHK(hipStreamSynchronize(st));
   int dev = 0, cus = 256, occ = 1;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   HIPCHK(batch_occupancy(b->nmax, b->lds, &occ));
   b->grid_stiff = std::max(1, std::min(b->n_stiff, cus * std::max(occ, 1)));
   b->grid_face = std::max(1, std::min(b->n_face, cus * 4));
+  std::vector<int> woff;
+  balance_items(sa, b->grid_stiff, si, woff);
+  HIPCHK(hipMemcpyAsync(b->ws + b->off_sargs, sa.data(), sa.size() * sizeof(sa[0]), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(b->ws + b->off_fargs, fa.data(), fa.size() * sizeof(fa[0]), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(b->ws + b->off_sitems, si.data(), si.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(b->ws + b->off_woff, woff.data(), woff.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(b->ws + b->off_fitems, fi.data(), fi.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(b->ws + b->off_ctr, ctr.data(), ctr.size() * sizeof(long*), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
   b->bound = true;
   return PMDG_OK;
 }

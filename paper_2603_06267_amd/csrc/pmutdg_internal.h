@@ -309,8 +309,9 @@ constexpr int kPmlMaxOrder = 6;
 // batched form
 size_t batch_lds_bytes(int N, int rows);
 hipError_t batch_occupancy(int nmax, size_t lds, int* blocks_per_cu);
-hipError_t launch_stiff_batch(const StiffArgs<float>* probs, const int2* items, int nitems, int nmax, int grid,
-                              size_t lds, hipStream_t st);
+// woff: per-workgroup item ranges [grid + 1] (nullptr: round robin)
+hipError_t launch_stiff_batch(const StiffArgs<float>* probs, const int2* items, int nitems, const int* woff,
+                              int nmax, int grid, size_t lds, hipStream_t st);
 hipError_t launch_face_batch(const FaceArgs<float>* probs, const int2* items, int nitems, int grid, int nm_max,
                              hipStream_t st);
 hipError_t launch_tick_batch(long* const* counters, int n, hipStream_t st);
