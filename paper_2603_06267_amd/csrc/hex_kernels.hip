@@ -325,14 +325,23 @@ template <typename Real, int N>
 static hipError_t hex_launch_n(const HexArgs<Real>& a, bool incr, hipStream_t st) {
   const long strips = (long)(a.ne[0] + hex_sx<N>() - 1) / hex_sx<N>() * a.ne[1] * a.ne[2] * a.S;
   if (strips != a.eblocks) return hipErrorInvalidValue;
-  // persistent: as many workgroups as fit the chip at once, at most one per strip
-  int dev = 0, cus = 0, per_cu = 0;
+  // persistent: as many workgroups as fit the chip at once, at most one per
+  // strip (the count is queried once per device and kept)
+  constexpr int kDevices = 64;
+  static int slots[kDevices] = {0};
+  int dev = 0;
   hipError_t e0 = hipGetDevice(&dev);
-  if (e0 == hipSuccess) e0 = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e0 == hipSuccess)
-    e0 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_hex_elem<Real, N>, 256, 0);
   if (e0 != hipSuccess) return e0;
-  const long grid = std::max(1L, std::min(strips, (long)cus * std::max(per_cu, 1)));
+  int fit = (dev >= 0 && dev < kDevices) ? slots[dev] : 0;
+  if (fit <= 0) {
+    int cus = 0, per_cu = 0;
+    e0 = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e0 == hipSuccess) e0 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_hex_elem<Real, N>, 256, 0);
+    if (e0 != hipSuccess) return e0;
+    fit = std::max(1, cus * std::max(per_cu, 1));
+    if (dev >= 0 && dev < kDevices) slots[dev] = fit;
+  }
+  const long grid = std::max(1L, std::min(strips, (long)fit));
   hipLaunchKernelGGL((k_hex_elem<Real, N>), dim3((unsigned)grid), dim3(256), 0, st, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
