@@ -13,6 +13,7 @@
 #include <mutex>
 #include <queue>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "pmutdg_internal.h"
@@ -642,21 +643,35 @@ static double drive_window(double t, double Td, int envelope) {
 static void drive_tables(const pmdg_solver* s, std::vector<double>& dA, std::vector<double>& car) {
   dA.assign((size_t)s->S * s->Np * 2, 0.0);
   car.assign((size_t)s->S * (s->cap + 1) * 2, 0.0);
-  for (int sc = 0; sc < s->S; ++sc) {
-    for (int k = 0; k < s->Np; ++k) {
-      const size_t i = (size_t)sc * s->Np + k;
-      dA[2 * i] = s->amp[i] * std::cos(s->phase[i]);
-      dA[2 * i + 1] = s->amp[i] * std::sin(s->phase[i]);
+  // scenarios [sc0, sc1): disjoint entries, so several host threads can
+  // share the work (the FP64 window and carrier values of a few thousand
+  // scenarios take milliseconds on one thread)
+  auto fill = [s, &dA, &car](int sc0, int sc1) {
+    for (int sc = sc0; sc < sc1; ++sc) {
+      for (int k = 0; k < s->Np; ++k) {
+        const size_t i = (size_t)sc * s->Np + k;
+        dA[2 * i] = s->amp[i] * std::cos(s->phase[i]);
+        dA[2 * i + 1] = s->amp[i] * std::sin(s->phase[i]);
+      }
+      const double f = s->freq[sc], Td = s->ncyc / f;
+      for (long n = 0; n <= s->cap; ++n) {
+        const double t = n * s->dt;
+        const double g = drive_window(t, Td, s->envelope);
+        if (g == 0.0) continue;  // outside the burst the carrier entries stay zero
+        car[((size_t)sc * (s->cap + 1) + n) * 2] = g * std::sin(2.0 * M_PI * f * t);
+        car[((size_t)sc * (s->cap + 1) + n) * 2 + 1] = g * std::cos(2.0 * M_PI * f * t);
+      }
     }
-    const double f = s->freq[sc], Td = s->ncyc / f;
-    for (long n = 0; n <= s->cap; ++n) {
-      const double t = n * s->dt;
-      const double g = drive_window(t, Td, s->envelope);
-      if (g == 0.0) continue;  // outside the burst the carrier entries stay zero
-      car[((size_t)sc * (s->cap + 1) + n) * 2] = g * std::sin(2.0 * M_PI * f * t);
-      car[((size_t)sc * (s->cap + 1) + n) * 2 + 1] = g * std::cos(2.0 * M_PI * f * t);
-    }
+  };
+  const long work = (long)s->S * (s->cap + 1);
+  const int nt = (int)std::min<long>(std::min<long>(std::max(1u, std::thread::hardware_concurrency()), 16L), s->S);
+  if (nt <= 1 || work < (1L << 16)) {
+    fill(0, s->S);
+    return;
   }
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nt; ++t) pool.emplace_back(fill, (int)((long)s->S * t / nt), (int)((long)s->S * (t + 1) / nt));
+  for (std::thread& th : pool) th.join();
 }
 
 // ------------------------------------------------------------------------
