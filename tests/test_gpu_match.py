@@ -55,6 +55,24 @@ def _sides(prim, sec, Vf=None, Vc=None):
     return fine, np.full(len(fine), 5), coarse, np.full(len(coarse), 4)
 
 
+def test_degenerate_face_sets():
+    """No coarse faces: every point is unmatched (element -1) and counted, as
+    the oracle has it; no fine faces: nothing to match and a count of 0,
+    whatever the unmatched counter held before."""
+    prim = W.brick([0, 0, 0], [2, 2, 1], [4, 4, 1], 2)
+    sec = W.brick([0, 0, 1], [2, 2, 2], [3, 3, 1], 2)
+    fine, ff, coarse, cf = _sides(prim, sec)
+    e, x, u = _gpu(3, fine, ff, coarse[:0], cf[:0])
+    eo, xo, uo = ref.match_faces(3, fine, ff, coarse[:0], cf[:0])
+    assert u == uo == len(fine) * 9
+    assert (e == -1).all() and np.array_equal(e, eo)
+    e, x, u = _gpu(3, fine, ff, coarse, cf)  # leaves a count of 0 ...
+    e, x, u = _gpu(3, fine[:1], ff[:1], coarse[:0], cf[:0])  # ... then 9
+    assert u == 9
+    e, x, u = _gpu(3, fine[:0], ff[:0], coarse, cf)
+    assert u == 0 and len(e) == 0
+
+
 @pytest.mark.parametrize("nested", [True, False])
 def test_brick_interface_list(nested):
     wl = W.small_two_domain(nested=nested)
