@@ -93,6 +93,9 @@ def test_restart_repeats_the_run(case, precision):
     g = solver.from_workload(wl, precision=precision, n_steps=300, shape_fn=W.shape_fn(wl))
     g.step(200)
     a = g.read_traces()
+    g.step(0)  # no steps: nothing changes
+    assert g.steps_done() == 200
+    np.testing.assert_array_equal(g.read_traces(), a)
     g.step(50)
     g.restart()
     g.step(200)
