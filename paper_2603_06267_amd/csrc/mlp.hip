@@ -51,7 +51,9 @@ __device__ __forceinline__ float gelu_d(float z) {
   return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * __expf(-0.5f * z * z);
 }
 
-enum { EPI_FWD_GELU = 0, EPI_FWD_LIN = 1, EPI_DX_GELU = 2, EPI_DW = 3 };
+// EPI_FWD_LIN_STAGED: EPI_FWD_LIN for outputs with 16-byte aligned rows and
+// no split-K, stored through LDS as 16-byte row segments
+enum { EPI_FWD_GELU = 0, EPI_FWD_LIN = 1, EPI_DX_GELU = 2, EPI_DW = 3, EPI_FWD_LIN_STAGED = 4 };
 
 struct GemmArgs {
   int M, N, K;           // C[M][N] = sum_r A(i, r) B(r, j)
@@ -235,6 +237,58 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
   }
 
   auto row_of = [&](int i, int r) { return m0 + wm * 32 * TM + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3); };
+  // Linear outputs with 16-byte aligned rows: the tile goes through LDS (the
+  // operand buffers are free: the loop ended with a barrier), so that every
+  // thread then stores whole 16-byte row segments: a quarter of the store
+  // instructions, and no accumulator copies held for the epilogue.  Same
+  // arithmetic as the per-element epilogue below.
+  if constexpr (EPI == EPI_FWD_LIN_STAGED) {
+    float* out = g.Y ? g.Y : g.Cf;
+    {
+      constexpr int LDC = BN + 8, F4 = BN / 4, RPP = 256 / F4, PASSES = BM / RPP;
+      static_assert(BM * LDC * sizeof(float) <= 2 * (BM + BN) * LDK * sizeof(bf16_t), "tile fits the LDS");
+      static_assert(256 % F4 == 0 && BM % RPP == 0, "tile splits into passes");
+      float* T = reinterpret_cast<float*>(gemm_lds);
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+          for (int r = 0; r < 16; ++r)
+            T[(wm * 32 * TM + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3)) * LDC + wn * 32 * TN + j * 32 +
+              (lane & 31)] = acc[i][j][r];
+      const int cl = (tid % F4) * 4, rl0 = tid / F4, col = n0 + cl;
+      const bool scaled = g.Y != nullptr;
+      float b4[4], rsp[PASSES];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) b4[c] = g.bias[min(col + c, g.N - 1)];
+#pragma unroll
+      for (int k = 0; k < PASSES; ++k)
+        rsp[k] = scaled ? g.out_scale * g.rowscale[min(m0 + rl0 + k * RPP, g.M - 1)] : 0.0f;
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < PASSES; ++k) {
+        const int rl = rl0 + k * RPP, row = m0 + rl;
+        if (row >= g.M || col >= g.N) continue;
+        const float4 v = *reinterpret_cast<const float4*>(&T[rl * LDC + cl]);
+        const float vv[4] = {v.x, v.y, v.z, v.w};
+        float o[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const float zz = vv[c] + b4[c];
+          o[c] = scaled ? rsp[k] * zz : zz;
+        }
+        float* dst = out + (long)row * g.ldc + col;
+        if (col + 3 < g.N) {
+          *reinterpret_cast<float4*>(dst) = make_float4(o[0], o[1], o[2], o[3]);
+        } else {
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            if (col + c < g.N) dst[c] = o[c];
+        }
+      }
+    }
+  } else {
   auto col_of = [&](int j) { return n0 + wn * 32 * TN + j * 32 + (lane & 31); };
   if (g.ks > 1) {
     float* part = g.part + (long)z * g.M * g.N;
@@ -307,6 +361,7 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
           g.Cf[o] = v;
         }
       }
+  }
 }
 
 // split-K: sum the ks partial tiles in a fixed order, then the epilogue
@@ -507,14 +562,8 @@ void plan_split(GemmArgs& g, int BM, int BN) {
 }
 
 template <bool ACON, bool BCON, int EPI, int TM, int TN, int BK>
-hipError_t gemm_t(GemmArgs g, float* part, hipStream_t st) {
+hipError_t gemm_t_launch(const GemmArgs& g, hipStream_t st) {
   using TL = Tile<TM, TN, BK>;
-  plan_split(g, TL::BM, TL::BN);
-  g.part = part;
-  if (g.ks > 1 && (size_t)g.ks * g.M * g.N > kPartFloats) {
-    g.kchunk = ((g.K + 31) / 32) * 32;
-    g.ks = 1;
-  }
   const size_t lds = sizeof(bf16_t) * 2 * (TL::BM + TL::BN) * TL::LDK;
   if (lds > 65536) {
     const hipError_t attr = hipFuncSetAttribute((const void*)k_gemm<ACON, BCON, EPI, TM, TN, BK>,
@@ -526,6 +575,28 @@ hipError_t gemm_t(GemmArgs g, float* part, hipStream_t st) {
   if (e != hipSuccess || g.ks == 1) return e;
   hipLaunchKernelGGL((k_splitk_reduce<EPI>), dim3((unsigned)nblk((long)g.M * g.N, 256)), dim3(256), 0, st, g);
   return hipGetLastError();
+}
+
+template <bool ACON, bool BCON, int EPI, int TM, int TN, int BK>
+hipError_t gemm_t(GemmArgs g, float* part, hipStream_t st) {
+  using TL = Tile<TM, TN, BK>;
+  plan_split(g, TL::BM, TL::BN);
+  g.part = part;
+  if (g.ks > 1 && (size_t)g.ks * g.M * g.N > kPartFloats) {
+    g.kchunk = ((g.K + 31) / 32) * 32;
+    g.ks = 1;
+  }
+  if constexpr (EPI == EPI_FWD_LIN) {
+    // linear outputs staged through LDS where the tile fits the operand
+    // buffers and the rows are 16-byte aligned
+    constexpr bool fits = TL::BM * (TL::BN + 8) * sizeof(float) <= 2 * (TL::BM + TL::BN) * TL::LDK * sizeof(bf16_t);
+    const float* out = g.Y ? g.Y : g.Cf;
+    if constexpr (fits) {
+      if (g.ks == 1 && (g.ldc & 3) == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0)
+        return gemm_t_launch<ACON, BCON, EPI_FWD_LIN_STAGED, TM, TN, BK>(g, st);
+    }
+  }
+  return gemm_t_launch<ACON, BCON, EPI, TM, TN, BK>(g, st);
 }
 
 // Tile choice: 64 x 64 tiles where 128 x 128 tiles would leave most CUs
