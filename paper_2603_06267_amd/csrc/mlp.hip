@@ -243,32 +243,41 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
   // instructions, and no accumulator copies held for the epilogue.  Same
   // arithmetic as the per-element epilogue below.
   if constexpr (EPI == EPI_FWD_LIN_STAGED) {
+    // in one pass, or in two halves of rows (one per row of waves) when the
+    // whole tile does not fit the operand buffers
     float* out = g.Y ? g.Y : g.Cf;
-    {
-      constexpr int LDC = BN + 8, F4 = BN / 4, RPP = 256 / F4, PASSES = BM / RPP;
-      static_assert(BM * LDC * sizeof(float) <= 2 * (BM + BN) * LDK * sizeof(bf16_t), "tile fits the LDS");
-      static_assert(256 % F4 == 0 && BM % RPP == 0, "tile splits into passes");
-      float* T = reinterpret_cast<float*>(gemm_lds);
+    constexpr int LDC = BN + 8, F4 = BN / 4, RPP = 256 / F4;
+    constexpr size_t kLds = 2 * (BM + BN) * LDK * sizeof(bf16_t);
+    constexpr int HALVES = BM * LDC * sizeof(float) <= kLds ? 1 : 2, HR = BM / HALVES, PASSES = HR / RPP;
+    static_assert(HR * LDC * sizeof(float) <= kLds, "a half tile fits the LDS");
+    static_assert(256 % F4 == 0 && HR % RPP == 0 && (HALVES == 1 || HR == 32 * TM), "tile splits into passes");
+    float* T = reinterpret_cast<float*>(gemm_lds);
+    const int cl = (tid % F4) * 4, rl0 = tid / F4, col = n0 + cl;
+    const bool scaled = g.Y != nullptr;
+    float b4[4], rsp[HALVES][PASSES];
 #pragma unroll
-      for (int i = 0; i < TM; ++i)
+    for (int c = 0; c < 4; ++c) b4[c] = g.bias[min(col + c, g.N - 1)];
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
-#pragma unroll
-          for (int r = 0; r < 16; ++r)
-            T[(wm * 32 * TM + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3)) * LDC + wn * 32 * TN + j * 32 +
-              (lane & 31)] = acc[i][j][r];
-      const int cl = (tid % F4) * 4, rl0 = tid / F4, col = n0 + cl;
-      const bool scaled = g.Y != nullptr;
-      float b4[4], rsp[PASSES];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) b4[c] = g.bias[min(col + c, g.N - 1)];
+    for (int h = 0; h < HALVES; ++h)
 #pragma unroll
       for (int k = 0; k < PASSES; ++k)
-        rsp[k] = scaled ? g.out_scale * g.rowscale[min(m0 + rl0 + k * RPP, g.M - 1)] : 0.0f;
+        rsp[h][k] = scaled ? g.out_scale * g.rowscale[min(m0 + h * HR + rl0 + k * RPP, g.M - 1)] : 0.0f;
+#pragma unroll
+    for (int h = 0; h < HALVES; ++h) {
+      if (HALVES == 1 || wm == h) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+              T[(wm * 32 * TM - h * HR + i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3)) * LDC + wn * 32 * TN +
+                j * 32 + (lane & 31)] = acc[i][j][r];
+      }
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < PASSES; ++k) {
-        const int rl = rl0 + k * RPP, row = m0 + rl;
+        const int rl = rl0 + k * RPP, row = m0 + h * HR + rl;
         if (row >= g.M || col >= g.N) continue;
         const float4 v = *reinterpret_cast<const float4*>(&T[rl * LDC + cl]);
         const float vv[4] = {v.x, v.y, v.z, v.w};
@@ -276,7 +285,7 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const float zz = vv[c] + b4[c];
-          o[c] = scaled ? rsp[k] * zz : zz;
+          o[c] = scaled ? rsp[h][k] * zz : zz;
         }
         float* dst = out + (long)row * g.ldc + col;
         if (col + 3 < g.N) {
@@ -287,6 +296,7 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
             if (col + c < g.N) dst[c] = o[c];
         }
       }
+      if (HALVES > 1) __syncthreads();  // the next half reuses T
     }
   } else {
   auto col_of = [&](int j) { return n0 + wn * 32 * TN + j * 32 + (lane & 31); };
@@ -587,9 +597,10 @@ hipError_t gemm_t(GemmArgs g, float* part, hipStream_t st) {
     g.ks = 1;
   }
   if constexpr (EPI == EPI_FWD_LIN) {
-    // linear outputs staged through LDS where the tile fits the operand
+    // linear outputs staged through LDS where half the tile fits the operand
     // buffers and the rows are 16-byte aligned
-    constexpr bool fits = TL::BM * (TL::BN + 8) * sizeof(float) <= 2 * (TL::BM + TL::BN) * TL::LDK * sizeof(bf16_t);
+    constexpr bool fits =
+        TL::BM / 2 * (TL::BN + 8) * sizeof(float) <= 2 * (TL::BM + TL::BN) * TL::LDK * sizeof(bf16_t);
     const float* out = g.Y ? g.Y : g.Cf;
     if constexpr (fits) {
       if (g.ks == 1 && (g.ldc & 3) == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0)
@@ -610,6 +621,10 @@ hipError_t gemm(GemmArgs g, float* part, hipStream_t st) {
   const long mid = (long)((g.M + 127) / 128) * ((g.N + 127) / 128);
   if (mid < kTargetBlocks / 4 && g.K <= 2048) return gemm_t<ACON, BCON, EPI, 1, 1, 32>(g, part, st);
   if (!ACON && !BCON) return gemm_t<ACON, BCON, EPI, 2, 2, 32>(g, part, st);
+  // Linear outputs over many tiles: 32-deep slices, whose 40 KB of LDS and
+  // (staged epilogue) 64 VGPRs let four workgroups share a CU; with fewer
+  // tiles the deeper slices measured faster.
+  if (EPI == EPI_FWD_LIN && ACON && BCON && mid >= 1024) return gemm_t<ACON, BCON, EPI, 2, 2, 32>(g, part, st);
   return gemm_t<ACON, BCON, EPI, 2, 2, 64>(g, part, st);
 }
 
