@@ -289,7 +289,10 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g) {
         }
         float* dst = out + (long)row * g.ldc + col;
         if (col + 3 < g.N) {
-          *reinterpret_cast<float4*>(dst) = make_float4(o[0], o[1], o[2], o[3]);
+          // non-temporal: nothing in this launch reads the output back
+          typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f4v;
+          f4v ov = {o[0], o[1], o[2], o[3]};
+          __builtin_nontemporal_store(ov, reinterpret_cast<f4v*>(dst));
         } else {
 #pragma unroll
           for (int c = 0; c < 4; ++c)
